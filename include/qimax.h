@@ -1,0 +1,179 @@
+/* qimax.h -- C ABI of the MI355X (gfx950) generator-propagation library.
+ *
+ * The library propagates the n stabilizer generators of |0^n> through a circuit in
+ * the Heisenberg picture (paper, Sec. II-A, eq. (1)): every generator starts as
+ * Z_j (qubit j holds Z, the others I) and each operator U replaces a generator G by
+ * U G U^dagger. A generator is a real linear combination of Pauli strings (the
+ * paper's "simple form", Sec. II-A and III-B), stored on the device as a sorted
+ * list of (key, weight) terms per generator.
+ *
+ * Keys are the paper's base-4 Pauli index (Sec. III-B): digit d_j of qubit j in
+ * {I=0, X=1, Y=2, Z=3}, key = sum_j d_j 4^(n-1-j), qubit 0 the most significant digit.
+ * For n <= 32 a key is one uint64 word; for 32 < n <= 64 it is two words, word 0 the
+ * low 64 bits. (This release implements n <= 32.)
+ *
+ * Threading: a context is not thread-safe; distinct contexts are independent.
+ * Errors: every call returns a qimax_status; no exception crosses this boundary.
+ * qimax_last_error() describes the last failure of a context.
+ */
+#ifndef QIMAX_H
+#define QIMAX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qimax_ctx qimax_ctx;
+
+typedef enum {
+  QIMAX_OK = 0,
+  QIMAX_EINVAL = -1,    /* bad argument: qubit out of range, bad PTM, bad gate code  */
+  QIMAX_ENOMEM = -2,    /* device memory (or opts.mem_cap_bytes) exhausted           */
+  QIMAX_EDEVICE = -3,   /* a HIP call failed, or a kernel reported an inconsistency  */
+  QIMAX_ETOOLARGE = -4, /* request outside the implemented range (n, fan-out, ...)   */
+  QIMAX_ESTATE = -5     /* the context is unusable after an earlier device error     */
+} qimax_status;
+
+/* Gate codes of the instruction form {gate, wire, theta} (Sec. III-A). Rotations are
+ * R_s(theta) = exp(-i theta s / 2); T = R_z(pi/4) and SX = R_x(pi/2) up to a phase. */
+enum {
+  QIMAX_GATE_H = 0, QIMAX_GATE_S = 1, QIMAX_GATE_SDG = 2, QIMAX_GATE_T = 3, QIMAX_GATE_TDG = 4,
+  QIMAX_GATE_SX = 5, QIMAX_GATE_X = 6, QIMAX_GATE_Y = 7, QIMAX_GATE_Z = 8,
+  QIMAX_GATE_RX = 9, QIMAX_GATE_RY = 10, QIMAX_GATE_RZ = 11,
+  QIMAX_GATE_CX = 12, /* q0 = control, q1 = target */
+  QIMAX_GATE_CZ = 13
+};
+
+typedef struct {
+  int precision;        /* 64: FP64 weights; 32: FP32 weights                                */
+  int fp32_merge;       /* precision 32 only: 0 = compensated FP32 sums (TwoSum), 1 = sums
+                           accumulated in FP64 and rounded once                               */
+  double prune_eps;     /* at the end of each apply call, drop terms with |w| <= prune_eps;
+                           internal passes drop exact zeros only (Sec. III-B)                 */
+  size_t mem_cap_bytes; /* 0 = limited by the device only; otherwise a cap on the bytes the
+                           context may hold on the device                                     */
+  void* hip_stream;     /* hipStream_t to run on, or NULL for the context's own stream        */
+  int validate;         /* 1 (default): every PTM must be unital, trace-preserving and
+                           orthogonal within 1e-12; 0 admits any real matrix                  */
+  int device;           /* HIP device ordinal; -1 = the current device                        */
+} qimax_opts;
+
+/* Fills *o with the defaults: precision 64, fp32_merge 0, prune_eps 0, no memory cap,
+ * own stream, validate 1, current device. */
+void qimax_default_opts(qimax_opts* o);
+
+/* One grouped operator as its real Pauli transfer matrix (PTM), Sec. III-C:
+ * R[a][b] = (1/2^k) Tr(P_a U P_b U^dagger) over the Pauli basis (I, X, Y, Z), row-major
+ * R[out][in], 4x4 for arity 1 and 16x16 for arity 2. The two-qubit basis index is
+ * 4*p(q[0]) + p(q[1]). The image of a term whose local Pauli is b is
+ * sum_a R[a][b] * (the term with that local Pauli replaced by a). */
+typedef struct {
+  uint32_t arity;    /* 1 or 2                                                           */
+  uint32_t q[2];     /* wires; q[1] ignored for arity 1; q[0] != q[1] for arity 2         */
+  const double* ptm; /* host pointer, 16 or 256 doubles; copied before the call returns   */
+} qimax_op;
+
+/* Creates a context on the device holding the n generators Z_0 .. Z_{n-1} of |0^n>
+ * (Sec. II-A; the initial simple form of Sec. IV: weights all 1, every digit string a
+ * single Z). 1 <= n <= 32 in this release (QIMAX_ETOOLARGE beyond). opts may be NULL
+ * for the defaults. On success *out owns all device memory of the context. */
+qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out);
+
+/* Resets the generators to Z_0 .. Z_{n-1} (the state qimax_create leaves), keeping the
+ * context's device buffers and options. Counters (qimax_get_stats) keep accumulating. */
+qimax_status qimax_reset(qimax_ctx* ctx);
+
+/* Applies the operators in array order: each generator G becomes U G U^dagger with
+ * U = U_{n_ops-1} ... U_0. Every term expands into its nonzero images (the flatten of
+ * Sec. IV, eq. (3)); images with equal keys are summed and exact zeros dropped; at the
+ * end of the call terms with |w| <= prune_eps are dropped. Operators on disjoint wires
+ * may be fused into one pass; overlapping ones keep their order (Alg. 2).
+ * Inputs are host memory and are copied. On failure the generators are unchanged. */
+qimax_status qimax_apply_layer(qimax_ctx* ctx, const qimax_op* ops, size_t n_ops);
+
+/* Applies m instructions {gate[i], (q0[i], q1[i]), theta[i]} (host arrays, Sec. III-A)
+ * as one layer: the library splits them into the paper's alternating runs U_k (one-qubit
+ * gates only) and V_k (two-qubit gates only) (Sec. III-A, Alg. 2), composes the gates of
+ * every U_{k,j} into one transfer matrix on the device (Alg. 1), and applies the result as
+ * qimax_apply_layer does. theta is ignored for gates without a parameter.
+ * On failure the generators are unchanged. */
+qimax_status qimax_apply_circuit(qimax_ctx* ctx, const uint8_t* gate, const uint32_t* q0,
+                                 const uint32_t* q1, const double* theta, size_t m);
+
+/* The grouping of qimax_apply_circuit without applying it: writes up to `cap` grouped
+ * operators (ops[i].ptm points into ptm_buf, 16 or 256 doubles each, packed in order;
+ * ptm_buf must hold 256*cap doubles) and sets *n_ops to the total count; *n_u / *n_v
+ * receive K and K', the numbers of U and V runs. cap = 0 only counts. */
+qimax_status qimax_group_circuit(qimax_ctx* ctx, const uint8_t* gate, const uint32_t* q0,
+                                 const uint32_t* q1, const double* theta, size_t m,
+                                 qimax_op* ops, double* ptm_buf, size_t cap, size_t* n_ops,
+                                 size_t* n_u, size_t* n_v);
+
+/* Total number of terms held (all generators). Cheap; synchronises the stream. */
+qimax_status qimax_num_terms(qimax_ctx* ctx, uint64_t* T);
+
+/* Copies the generators to host memory (the paper's Lambda and index tensor, Alg. 2):
+ * gen_off[0..n] (n+1 words, generator j owns terms gen_off[j] .. gen_off[j+1]-1),
+ * keys (T*W words, W = 1 for n <= 32) and weights as FP64. Terms come out ascending by
+ * key within each generator. Two-call size query: with cap < T only *T is written
+ * (gen_off, keys and w may then be NULL) and QIMAX_OK is returned. */
+qimax_status qimax_get_generators(qimax_ctx* ctx, uint64_t* gen_off, uint64_t* keys, double* w,
+                                  size_t cap, size_t* T);
+
+/* <psi|P|psi> = Tr(rho P) for rho = 2^-n prod_j (I + G_j) (eq. (2)), P given as n letters
+ * of "IXYZ", qubit 0 first. For a single-qubit projector the paper's p_{k,0} is
+ * (1 + <Z_k>)/2 (Sec. II-B). Exact when every generator is a single term (GF(2)
+ * elimination); otherwise by projecting a random state for n <= 20 (QIMAX_ETOOLARGE
+ * beyond). Runs on the host after copying the generators; not part of propagation. */
+qimax_status qimax_expect(qimax_ctx* ctx, const char* pauli, double* out);
+
+/* Counters since qimax_create (host-side bookkeeping, no device work). */
+typedef struct {
+  uint64_t terms;          /* current number of terms                                     */
+  uint64_t passes;         /* expanding passes executed                                   */
+  uint64_t term_updates;   /* images produced, one per output image of every operator     */
+  uint64_t images;         /* images materialised by the expand kernel                    */
+  uint64_t sort_elems;     /* elements sorted                                             */
+  uint64_t peak_bytes;     /* peak device bytes held by the context                       */
+  uint64_t alloc_bytes;    /* device bytes currently held                                 */
+} qimax_stats;
+
+qimax_status qimax_get_stats(const qimax_ctx* ctx, qimax_stats* out);
+
+/* The term_updates counter split by generator: out[j] for j < n (host bookkeeping). */
+qimax_status qimax_get_generator_updates(const qimax_ctx* ctx, uint64_t* out, size_t n);
+
+/* Per-kernel timing with HIP events on the context's stream. qimax_profile(ctx, 1) clears
+ * the totals and starts recording every kernel launch; qimax_profile(ctx, 0) stops.
+ * qimax_profile_read synchronises, then writes up to `cap` entries (one per kernel kind that
+ * ran) and sets *n to the number of kinds. alg_bytes is the algorithmic traffic of those
+ * launches: the bytes the kernel's job has to read and write, not the bytes it moved.
+ * `name` points to a static string. */
+typedef struct {
+  const char* name;
+  uint64_t launches;
+  double total_ms;
+  double alg_bytes;
+} qimax_kernel_time;
+
+qimax_status qimax_profile(qimax_ctx* ctx, int enable);
+qimax_status qimax_profile_read(qimax_ctx* ctx, qimax_kernel_time* out, size_t cap, size_t* n);
+
+/* Blocks until all work of the context has finished. */
+qimax_status qimax_sync(qimax_ctx* ctx);
+
+/* Text of the last error of ctx (owned by ctx, valid until its next call); ctx may be
+ * NULL for errors of qimax_create. */
+const char* qimax_last_error(const qimax_ctx* ctx);
+
+/* Releases all device memory of the context. NULL is ignored. */
+void qimax_destroy(qimax_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QIMAX_H */

@@ -1,0 +1,848 @@
+// HIP kernels for gfx950 (wave64): generator init, fan-out count, scans, term expansion,
+// segmented LSD radix sort, segmented reduce + prune + compaction, grouping (PTM
+// composition). Every global write is bounds-checked against the size its launcher was
+// given; a violation raises an error bit instead of writing.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qimax_internal.h"
+
+namespace qimax {
+namespace {
+
+static_assert(kSortBlock == kRadix, "one thread per radix digit in the scatter kernel");
+
+// ------------------------------------------------------------------------------ keys
+// A key is the paper's base-4 Pauli index; qubit q's digit is at bit pos = 2(n-1-q).
+template <typename K>
+__device__ __forceinline__ uint32_t get_d(K k, uint32_t pos) {
+  return (uint32_t)(k >> pos) & 3u;
+}
+template <typename K>
+__device__ __forceinline__ K set_d(K k, uint32_t pos, uint32_t d) {
+  return (k & ~((K)3 << pos)) | ((K)d << pos);
+}
+
+template <typename K>
+__device__ __forceinline__ K apply_perm(K key, const PermDesc& p, uint32_t& neg) {
+  uint32_t in = get_d(key, p.pa);
+  if (p.arity == 2) in = (in << 2) | get_d(key, p.pb);
+  const uint64_t word = (in < 8) ? p.lo : p.hi;
+  const uint32_t e = (uint32_t)(word >> ((in & 7u) * 8u)) & 0xFFu;
+  neg ^= (e >> 4) & 1u;
+  const uint32_t o = e & 15u;
+  if (p.arity == 2) {
+    key = set_d(key, p.pa, o >> 2);
+    key = set_d(key, p.pb, o & 3u);
+  } else {
+    key = set_d(key, p.pa, o);
+  }
+  return key;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t local2(K key, uint32_t pa, uint32_t pb) {
+  return (get_d(key, pa) << 2) | get_d(key, pb);
+}
+
+template <int WP> struct WTraits;
+template <> struct WTraits<64> { using W = double; };
+template <> struct WTraits<32> { using W = float; };
+
+// ------------------------------------------------------------------------ block scans
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over a block of NT threads (NT a multiple of 64). sh: NT/64 words.
+template <int NT>
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t* sh, uint64_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t incl = wave_incl_scan(v);
+  if (lane == 63) sh[wid] = incl;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint64_t x = sh[w];
+    if (w < wid) pre += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + incl - v;
+}
+
+// ------------------------------------------------------------------------------ init
+template <typename K, typename W>
+__global__ void k_init(K* keys, W* w, uint64_t* seg_off, uint32_t n) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    keys[j] = (K)3 << (2u * (n - 1u - j));  // Z on qubit j
+    w[j] = (W)1;
+    seg_off[j] = j;
+  }
+  if (j == 0) seg_off[n] = n;
+}
+
+// ----------------------------------------------------------------------- fan-out count
+template <typename K>
+__global__ void __launch_bounds__(256) k_count(const K* __restrict__ keys, uint64_t T, PassArgs pa,
+                                               uint32_t* __restrict__ cnt, uint32_t* err) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  K key = keys[i];
+  uint32_t neg = 0;
+  for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+  uint64_t f = 1;
+  for (uint32_t e = 0; e < pa.nE1; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
+  for (uint32_t e = 0; e < pa.nE2; ++e) {
+    f *= pa.E2[e].cnt[local2(key, pa.E2[e].pa, pa.E2[e].pb)];
+    if (f > 0xFFFFFFFFull) break;
+  }
+  if (f > 0xFFFFFFFFull) {
+    atomicOr(err, kErrFanout);
+    f = 0;
+  }
+  cnt[i] = (uint32_t)f;
+}
+
+// ------------------------------------------------------------------------------ scans
+template <typename TI>
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const TI* __restrict__ in, uint64_t N,
+                                                            uint64_t* __restrict__ part) {
+  __shared__ uint64_t sh[kScanBlock / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + (uint64_t)k * kScanBlock + threadIdx.x;
+    if (i < N) s += (uint64_t)in[i];
+  }
+  uint64_t tot;
+  block_excl_scan<kScanBlock>(s, sh, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Exclusive scan of part[0..nb) in place by one block; part[nb] = total.
+__global__ void __launch_bounds__(kScanBlock) k_scan_partials(uint64_t* part, uint64_t nb) {
+  __shared__ uint64_t sh[kScanBlock / 64];
+  uint64_t carry = 0;
+  for (uint64_t base = 0; base < nb; base += kScanTile) {
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const uint64_t i = base + (uint64_t)threadIdx.x * kScanItems + k;
+      v[k] = (i < nb) ? part[i] : 0;
+      s += v[k];
+    }
+    uint64_t tot;
+    uint64_t pre = block_excl_scan<kScanBlock>(s, sh, &tot) + carry;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const uint64_t i = base + (uint64_t)threadIdx.x * kScanItems + k;
+      if (i < nb) part[i] = pre;
+      pre += v[k];
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[nb] = carry;
+}
+
+template <typename TI>
+__global__ void __launch_bounds__(kScanBlock) k_scan_down(const TI* __restrict__ in, uint64_t N,
+                                                          const uint64_t* __restrict__ part,
+                                                          uint64_t* __restrict__ out) {
+  __shared__ uint64_t sh[kScanBlock / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    v[k] = (i < N) ? (uint64_t)in[i] : 0;
+    s += v[k];
+  }
+  uint64_t tot;
+  uint64_t pre = block_excl_scan<kScanBlock>(s, sh, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    if (i < N) out[i] = pre;
+    pre += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[N] = part[gridDim.x];
+}
+
+__global__ void k_zero_one(uint64_t* out) { out[0] = 0; }
+
+__global__ void k_gather_u64(const uint64_t* __restrict__ src, const uint64_t* __restrict__ idx,
+                             uint64_t* __restrict__ dst, uint32_t S1) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S1) dst[s] = src[idx[s]];
+}
+
+__global__ void k_gather_u64_by_u32(const uint64_t* __restrict__ src, const uint32_t* __restrict__ idx,
+                                    uint64_t* __restrict__ dst, uint32_t S1) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S1) dst[s] = src[idx[s]];
+}
+
+// ----------------------------------------------------------------------------- expand
+// Block b produces images [b*kExpandTile, min((b+1)*kExpandTile, T_img)). The parents
+// covering that range are found by binary search on the image offsets `off`
+// (off[p] = first image of parent p, off[T_in] = T_img); image g of parent p is the
+// (g - off[p])-th entry of the Cartesian product over the pass's expanding operators
+// (mixed-radix over their per-term nonzero counts), i.e. one term of the flatten.
+__device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t* a, uint64_t lo, uint64_t hi,
+                                                    uint64_t x) {
+  // first index i in [lo, hi) with a[i] > x (hi if none)
+  while (lo < hi) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] > x) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+template <typename K, int WP>
+__global__ void __launch_bounds__(kExpandBlock)
+k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__ w, uint64_t T_in,
+         const uint64_t* __restrict__ off, uint64_t T_img, PassArgs pa, K* __restrict__ keys_out,
+         typename WTraits<WP>::W* __restrict__ w_out, uint32_t* err) {
+  using W = typename WTraits<WP>::W;
+  constexpr int kWin = kExpandTile + 1;
+  __shared__ uint64_t win[kWin];
+  __shared__ uint64_t bounds[2];
+  const uint64_t g0 = (uint64_t)blockIdx.x * kExpandTile;
+  if (g0 >= T_img) return;
+  const uint64_t g1 = min(g0 + (uint64_t)kExpandTile, T_img);
+  if (threadIdx.x == 0) {
+    const uint64_t plo = upper_bound_u64(off, 0, T_in + 1, g0) - 1;
+    const uint64_t phi = upper_bound_u64(off, plo, T_in + 1, g1 - 1) - 1;
+    bounds[0] = plo;
+    bounds[1] = phi;
+  }
+  __syncthreads();
+  const uint64_t plo = bounds[0], phi = bounds[1];
+  const uint64_t nwin = phi - plo + 2;  // off[plo .. phi+1]
+  const bool in_lds = nwin <= (uint64_t)kWin;
+  if (in_lds) {
+    for (uint64_t k = threadIdx.x; k < nwin; k += kExpandBlock) win[k] = off[plo + k];
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int it = 0; it < kExpandItems; ++it) {
+    const uint64_t g = g0 + (uint64_t)it * kExpandBlock + threadIdx.x;
+    if (g >= g1) break;
+    uint64_t p, start;
+    if (in_lds) {
+      uint32_t lo = 0, hi = (uint32_t)nwin;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (win[mid] > g) hi = mid; else lo = mid + 1;
+      }
+      p = plo + lo - 1;
+      start = win[lo - 1];
+    } else {
+      p = upper_bound_u64(off, plo, phi + 2, g) - 1;
+      start = off[p];
+    }
+    if (p >= T_in) {
+      atomicOr(err, kErrIndex);
+      continue;
+    }
+    K key = keys[p];
+    W wv = w[p];
+    uint32_t neg = 0;
+    for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+    uint32_t r = (uint32_t)(g - start);
+    for (uint32_t e = 0; e < pa.nE1; ++e) {
+      const Exp1Desc& E = pa.E1[e];
+      const uint32_t d = get_d(key, E.pos);
+      const uint32_t c = E.cnt[d];
+      if (c == 0) { atomicOr(err, kErrIndex); break; }
+      const uint32_t q = r / c;
+      const uint32_t k = r - q * c;
+      r = q;
+      key = set_d(key, E.pos, E.out[d][k]);
+      if constexpr (WP == 64) wv *= E.val[d][k]; else wv *= E.valf[d][k];
+    }
+    for (uint32_t e = 0; e < pa.nE2; ++e) {
+      const Exp2Desc& E = pa.E2[e];
+      const uint32_t in = local2(key, E.pa, E.pb);
+      const uint32_t c = E.cnt[in];
+      if (c == 0) { atomicOr(err, kErrIndex); break; }
+      const uint32_t q = r / c;
+      const uint32_t k = r - q * c;
+      r = q;
+      const uint32_t o = E.out[in][k];
+      key = set_d(key, E.pa, o >> 2);
+      key = set_d(key, E.pb, o & 3u);
+      if constexpr (WP == 64) wv *= E.val[in][k]; else wv *= E.valf[in][k];
+    }
+    for (uint32_t b = 0; b < pa.nB; ++b) key = apply_perm(key, pa.B[b], neg);
+    if (neg) wv = -wv;
+    keys_out[g] = key;
+    w_out[g] = wv;
+  }
+}
+
+// ----------------------------------------------------------------------- radix sort
+// Histogram position of (block b, digit d) in the flat array whose exclusive scan gives
+// the scatter bases: segment-major, then digit, then block within the segment. Since
+// segments are contiguous in the array being sorted, the scan value is
+// seg_begin + (count of smaller digits in the segment) + (count of d in earlier blocks).
+__device__ __forceinline__ uint64_t hist_pos(const Tiling& tl, uint32_t b, uint32_t d) {
+  const uint32_t s = tl.blk_seg[b];
+  const uint32_t f = tl.seg_blk[s];
+  const uint32_t nb = tl.seg_blk[s + 1] - f;
+  return (uint64_t)kRadix * f + (uint64_t)d * nb + (b - f);
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock) k_sort_hist(const K* __restrict__ keys, uint32_t shift,
+                                                          Tiling tl, uint64_t* __restrict__ hist,
+                                                          uint64_t hist_size, uint32_t* err) {
+  __shared__ uint32_t h[kSortBlock / 64][kRadix];
+  const uint32_t b = blockIdx.x;
+  const int wid = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < (kSortBlock / 64) * kRadix; k += kSortBlock) (&h[0][0])[k] = 0;
+  __syncthreads();
+  const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
+  for (uint64_t i = begin + threadIdx.x; i < end; i += kSortBlock) {
+    const uint32_t d = (uint32_t)(keys[i] >> shift) & (kRadix - 1);
+    atomicAdd(&h[wid][d], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kSortBlock) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kSortBlock / 64; ++w) c += h[w][d];
+    const uint64_t pos = hist_pos(tl, b, d);
+    if (pos < hist_size) hist[pos] = c; else atomicOr(err, kErrIndex);
+  }
+}
+
+template <typename K, typename W>
+__global__ void __launch_bounds__(kSortBlock)
+k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __restrict__ keys_out,
+               W* __restrict__ w_out, uint64_t T, uint32_t shift, Tiling tl,
+               const uint64_t* __restrict__ hist_off, uint32_t* err) {
+  constexpr int kWaves = kSortBlock / 64;
+  constexpr int kRounds = kSortItems;                 // rounds per wave
+  constexpr int kWaveSpan = 64 * kRounds;             // tile elements per wave
+  __shared__ uint64_t stage[kSortTile];               // keys, then weights (as raw 64-bit)
+  __shared__ uint32_t wrun[kWaves][kRadix];            // per-wave running digit counts
+  __shared__ uint32_t dstart[kRadix];                  // tile-local start of each digit
+  __shared__ uint64_t gbase[kRadix];                   // global destination of each digit
+  __shared__ uint64_t scan_sh[kSortBlock / 64];
+
+  const uint32_t b = blockIdx.x;
+  const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
+  const uint32_t n_tile = (uint32_t)(end - begin);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < kWaves * kRadix; k += kSortBlock) (&wrun[0][0])[k] = 0;
+  __syncthreads();
+
+  K key[kRounds];
+  W wv[kRounds];
+  uint32_t rank[kRounds];
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t li = wid * kWaveSpan + r * 64 + lane;  // tile-local index, stable order
+    const bool valid = li < n_tile;
+    key[r] = valid ? keys_in[begin + li] : (K)0;
+    wv[r] = valid ? w_in[begin + li] : (W)0;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t bb = __ballot(on);
+      m &= on ? bb : ~bb;
+    }
+    uint32_t base = 0;
+    const int leader = __ffsll((long long)m) - 1;  // lowest lane with this digit
+    if (valid && lane == leader) base = atomicAdd(&wrun[wid][d], (uint32_t)__popcll(m));
+    base = __shfl(base, leader < 0 ? 0 : leader, 64);
+    rank[r] = valid ? base + (uint32_t)__popcll(m & lt) : 0u;
+  }
+  __syncthreads();
+  // per-digit totals of the tile, wave prefixes, digit starts
+  uint32_t tile_cnt = 0;
+  {
+    const int d = threadIdx.x;  // kSortBlock == kRadix
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = wrun[w][d];
+      wrun[w][d] = tile_cnt;  // becomes the wave prefix
+      tile_cnt += c;
+    }
+  }
+  uint64_t tot;
+  const uint64_t ds = block_excl_scan<kSortBlock>(tile_cnt, scan_sh, &tot);
+  {
+    const int d = threadIdx.x;
+    dstart[d] = (uint32_t)ds;
+    gbase[d] = tile_cnt ? hist_off[hist_pos(tl, b, d)] : 0;
+  }
+  __syncthreads();
+  // stage keys at their tile-local sorted positions
+  uint32_t pos[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t li = wid * kWaveSpan + r * 64 + lane;
+    if (li < n_tile) {
+      const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+      pos[r] = dstart[d] + wrun[wid][d] + rank[r];
+      if (pos[r] < (uint32_t)kSortTile) stage[pos[r]] = (uint64_t)key[r];
+      else atomicOr(err, kErrIndex);
+    } else {
+      pos[r] = 0xFFFFFFFFu;
+    }
+  }
+  __syncthreads();
+  // write keys out in sorted tile order (coalesced within each digit run)
+  uint32_t outd[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t j = r * kSortBlock + threadIdx.x;
+    outd[r] = 0xFFFFFFFFu;
+    if (j < n_tile) {
+      const K k = (K)stage[j];
+      const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+      outd[r] = d;
+      const uint64_t dst = gbase[d] + (j - dstart[d]);
+      if (dst < T) keys_out[dst] = k; else atomicOr(err, kErrIndex);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    if (pos[r] < (uint32_t)kSortTile) {
+      if constexpr (sizeof(W) == 8) stage[pos[r]] = __double_as_longlong(wv[r]);
+      else stage[pos[r]] = (uint64_t)__float_as_uint(wv[r]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t j = r * kSortBlock + threadIdx.x;
+    if (j < n_tile) {
+      const uint32_t d = outd[r];
+      const uint64_t dst = gbase[d] + (j - dstart[d]);
+      W v;
+      if constexpr (sizeof(W) == 8) v = __longlong_as_double((long long)stage[j]);
+      else v = __uint_as_float((uint32_t)stage[j]);
+      if (dst < T) w_out[dst] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------ merge
+// Equal keys are adjacent inside a segment after the sort. The thread that owns the
+// first element of a run (its head) sums the run in array order (deterministic), then
+// keeps it when |sum| > thr. FP32 runs are summed with the TwoSum-compensated
+// (Kahan-Babuska) recurrence, or in FP64 and rounded once.
+template <typename W>
+struct RunSum {
+  W s = 0;
+  W c = 0;
+  __device__ __forceinline__ void add(W x) {
+    const W t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ W value() const { return s + c; }
+};
+
+template <typename K, typename W>
+__device__ __forceinline__ W run_sum(const K* __restrict__ keys, const W* __restrict__ w, uint64_t i,
+                                     uint64_t seg_end, K key, int fp64_acc) {
+  if constexpr (sizeof(W) == 8) {
+    double s = w[i];
+    for (uint64_t j = i + 1; j < seg_end && keys[j] == key; ++j) s += w[j];
+    return s;
+  } else {
+    if (fp64_acc) {
+      double s = (double)w[i];
+      for (uint64_t j = i + 1; j < seg_end && keys[j] == key; ++j) s += (double)w[j];
+      return (float)s;
+    }
+    RunSum<float> rs;
+    rs.add(w[i]);
+    for (uint64_t j = i + 1; j < seg_end && keys[j] == key; ++j) rs.add(w[j]);
+    return rs.value();
+  }
+}
+
+template <typename K, typename W, bool kWrite>
+__global__ void __launch_bounds__(kSortBlock)
+k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, double thr, int fp64_acc,
+        uint32_t* __restrict__ blk_cnt, const uint64_t* __restrict__ blk_off, K* __restrict__ keys_out,
+        W* __restrict__ w_out, uint64_t out_cap, uint32_t* err) {
+  __shared__ K sk[kSortTile + 1];
+  __shared__ uint64_t scan_sh[kSortBlock / 64];
+  const uint32_t b = blockIdx.x;
+  const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
+  const uint32_t s = tl.blk_seg[b];
+  const uint64_t seg_begin = tl.blk_begin[tl.seg_blk[s]];
+  const uint64_t seg_end = tl.blk_end[tl.seg_blk[s + 1] - 1];
+  const uint32_t n_tile = (uint32_t)(end - begin);
+  // sk[0] holds the key before the tile (if inside the segment), sk[1 + i] the tile
+  for (uint32_t i = threadIdx.x; i < n_tile; i += kSortBlock) sk[1 + i] = keys[begin + i];
+  if (threadIdx.x == 0 && begin > seg_begin) sk[0] = keys[begin - 1];
+  __syncthreads();
+  const uint32_t i0 = threadIdx.x * kSortItems;
+  uint32_t keep = 0;
+  uint32_t keep_mask = 0;
+  W sums[kSortItems];
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    sums[k] = 0;
+    const uint32_t li = i0 + k;
+    if (li >= n_tile) continue;
+    const uint64_t gi = begin + li;
+    const K key = sk[1 + li];
+    const bool head = (gi == seg_begin) || (sk[li] != key);
+    if (!head) continue;
+    const W v = run_sum(keys, w, gi, seg_end, key, fp64_acc);
+    if (fabs((double)v) > thr) {
+      sums[k] = v;
+      keep_mask |= 1u << k;
+      ++keep;
+    }
+  }
+  uint64_t tot;
+  const uint64_t pre = block_excl_scan<kSortBlock>(keep, scan_sh, &tot);
+  if constexpr (!kWrite) {
+    if (threadIdx.x == 0) blk_cnt[b] = (uint32_t)tot;
+  } else {
+    uint64_t o = blk_off[b] + pre;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+      if (!(keep_mask & (1u << k))) continue;
+      if (o < out_cap) {
+        keys_out[o] = sk[1 + i0 + k];
+        w_out[o] = sums[k];
+      } else {
+        atomicOr(err, kErrIndex);
+      }
+      ++o;
+    }
+  }
+}
+
+template <int WP>
+__global__ void k_weights_to_f64(const typename WTraits<WP>::W* __restrict__ w, double* __restrict__ out,
+                                 uint64_t T) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T) out[i] = (double)w[i];
+}
+
+// -------------------------------------------------------------------- grouping pass
+// The 4x4 transfer matrix R[out][in] of one gate (Pauli order I, X, Y, Z): the closed
+// form of (1/2) Tr(P_out U P_in U^dagger), i.e. diag(1, M) with M the SO(3) rotation of
+// the Bloch vector that U performs (Sec. II-C; Alg. 1 composes these per qubit).
+__device__ void gate_ptm(uint32_t code, double th, double R[4][4]) {
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) R[a][b] = (a == b) ? 1.0 : 0.0;
+  // rotation about axis ax in {1,2,3} by angle t: the two other axes (u, v) in cyclic
+  // order turn as u -> cos t u + sin t v, v -> cos t v - sin t u
+  auto rot = [&](int ax, double t) {
+    double sn, cs;
+    sincos(t, &sn, &cs);
+    const int u = ax % 3 + 1, v = u % 3 + 1;
+    R[u][u] = cs; R[v][v] = cs; R[v][u] = sn; R[u][v] = -sn;
+  };
+  switch (code) {
+    case 0:  // H: X <-> Z, Y -> -Y
+      R[1][1] = 0; R[3][3] = 0; R[3][1] = 1; R[1][3] = 1; R[2][2] = -1; break;
+    case 1:  // S: X -> Y, Y -> -X
+      R[1][1] = 0; R[2][2] = 0; R[2][1] = 1; R[1][2] = -1; break;
+    case 2:  // S^dagger: X -> -Y, Y -> X
+      R[1][1] = 0; R[2][2] = 0; R[2][1] = -1; R[1][2] = 1; break;
+    case 3: rot(3, M_PI / 4); break;   // T
+    case 4: rot(3, -M_PI / 4); break;  // T^dagger
+    case 5:  // SX: Y -> Z, Z -> -Y
+      R[2][2] = 0; R[3][3] = 0; R[3][2] = 1; R[2][3] = -1; break;
+    case 6: R[2][2] = -1; R[3][3] = -1; break;  // X
+    case 7: R[1][1] = -1; R[3][3] = -1; break;  // Y
+    case 8: R[1][1] = -1; R[2][2] = -1; break;  // Z
+    case 9: rot(1, th); break;   // RX
+    case 10: rot(2, th); break;  // RY
+    case 11: rot(3, th); break;  // RZ
+    default: break;
+  }
+}
+
+__global__ void k_compose_ptm(const uint8_t* __restrict__ gate, const double* __restrict__ theta,
+                              const uint32_t* __restrict__ idx, const uint32_t* __restrict__ chain_off,
+                              uint32_t n_chains, double* __restrict__ out) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_chains) return;
+  double R[4][4], G[4][4], P[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) R[a][b] = (a == b) ? 1.0 : 0.0;
+  for (uint32_t k = chain_off[c]; k < chain_off[c + 1]; ++k) {
+    const uint32_t gi = idx[k];
+    gate_ptm(gate[gi], theta[gi], G);
+    // later gate acts on the images of the earlier ones: R <- G R
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        double s = 0.0;
+        for (int t = 0; t < 4; ++t) s += G[a][t] * R[t][b];
+        P[a][b] = s;
+      }
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) R[a][b] = P[a][b];
+  }
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) out[(uint64_t)c * 16 + a * 4 + b] = R[a][b];
+}
+
+inline uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)((n + block - 1) / block); }
+
+}  // namespace
+
+// ============================================================================ launchers
+
+const char* kernel_kind_name(int k) {
+  static const char* names[kKNum] = {"init", "count", "scan", "expand", "sort_hist", "sort_scatter",
+                                     "merge_count", "merge_write", "compose_ptm"};
+  return (k >= 0 && k < kKNum) ? names[k] : "?";
+}
+
+hipEvent_t prof_begin(Prof* p, hipStream_t s) {
+  if (!p || !p->on) return nullptr;
+  hipEvent_t e = nullptr;
+  if (!p->pool.empty()) {
+    e = p->pool.back();
+    p->pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  if (hipEventRecord(e, s) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_end(Prof* p, hipStream_t s, hipEvent_t a, int kind, double bytes) {
+  if (!p || !p->on || !a) return;
+  hipEvent_t b = nullptr;
+  if (!p->pool.empty()) {
+    b = p->pool.back();
+    p->pool.pop_back();
+  } else if (hipEventCreate(&b) != hipSuccess) {
+    return;
+  }
+  if (hipEventRecord(b, s) != hipSuccess) return;
+  p->recs.push_back({kind, a, b, bytes});
+}
+
+void prof_resolve(Prof* p) {
+  if (!p) return;
+  for (auto& r : p->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      p->launches[r.kind] += 1;
+      p->ms[r.kind] += ms;
+      p->bytes[r.kind] += r.bytes;
+    }
+    p->pool.push_back(r.a);
+    p->pool.push_back(r.b);
+  }
+  p->recs.clear();
+}
+
+void prof_reset(Prof* p) {
+  if (!p) return;
+  for (int k = 0; k < kKNum; ++k) {
+    p->launches[k] = 0;
+    p->ms[k] = 0;
+    p->bytes[k] = 0;
+  }
+}
+
+void prof_destroy(Prof* p) {
+  if (!p) return;
+  for (auto& r : p->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : p->pool) (void)hipEventDestroy(e);
+  p->recs.clear();
+  p->pool.clear();
+}
+
+#define QIMAX_DISPATCH_K(KC, ...)                    \
+  do {                                               \
+    if ((KC) == 0) { using K = uint32_t; __VA_ARGS__; } \
+    else { using K = uint64_t; __VA_ARGS__; }        \
+  } while (0)
+
+hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, uint32_t n, hipStream_t s,
+                       Prof* prof) {
+  hipEvent_t ev = prof_begin(prof, s);
+  QIMAX_DISPATCH_K(KC, {
+    if (WP == 64) k_init<K, double><<<grid_for(n, 64), 64, 0, s>>>((K*)keys, (double*)w, seg_off, n);
+    else k_init<K, float><<<grid_for(n, 64), 64, 0, s>>>((K*)keys, (float*)w, seg_off, n);
+  });
+  prof_end(prof, s, ev, kKInit, 0.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(int KC, const void* keys, uint64_t T, const PassArgs& pa, uint32_t* cnt, uint32_t* err,
+                        hipStream_t s, Prof* prof) {
+  if (T == 0) return hipSuccess;
+  hipEvent_t ev = prof_begin(prof, s);
+  QIMAX_DISPATCH_K(KC, { k_count<K><<<grid_for(T, 256), 256, 0, s>>>((const K*)keys, T, pa, cnt, err); });
+  prof_end(prof, s, ev, kKCount, (double)T * ((KC == 0 ? 4 : 8) + 4));
+  return hipGetLastError();
+}
+
+size_t scan_tmp_words(uint64_t N) { return (size_t)((N + kScanTile - 1) / kScanTile) + 2; }
+
+template <typename TI>
+static hipError_t scan_impl(const TI* in, uint64_t* out, uint64_t N, uint64_t* tmp, hipStream_t s, Prof* prof) {
+  hipEvent_t ev = prof_begin(prof, s);
+  if (N == 0) {
+    k_zero_one<<<1, 1, 0, s>>>(out);
+  } else {
+    const uint64_t nb = (N + kScanTile - 1) / kScanTile;
+    k_scan_reduce<TI><<<(uint32_t)nb, kScanBlock, 0, s>>>(in, N, tmp);
+    k_scan_partials<<<1, kScanBlock, 0, s>>>(tmp, nb);
+    k_scan_down<TI><<<(uint32_t)nb, kScanBlock, 0, s>>>(in, N, tmp, out);
+  }
+  prof_end(prof, s, ev, kKScan, (double)N * sizeof(TI) + (double)(N + 1) * 8);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t N, uint64_t* tmp, hipStream_t s,
+                           Prof* prof) {
+  return scan_impl<uint32_t>(in, out, N, tmp, s, prof);
+}
+hipError_t launch_scan_u64(const uint64_t* in, uint64_t* out, uint64_t N, uint64_t* tmp, hipStream_t s,
+                           Prof* prof) {
+  return scan_impl<uint64_t>(in, out, N, tmp, s, prof);
+}
+
+hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint64_t* dst, uint32_t S1, hipStream_t s,
+                             Prof* prof) {
+  (void)prof;
+  k_gather_u64<<<grid_for(S1, 64), 64, 0, s>>>(src_off, idx, dst, S1);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const uint64_t* off,
+                         uint64_t T_img, const PassArgs& pa, void* keys_out, void* w_out, uint32_t* err,
+                         hipStream_t s, Prof* prof) {
+  if (T_img == 0) return hipSuccess;
+  const uint64_t nb = (T_img + kExpandTile - 1) / kExpandTile;
+  hipEvent_t ev = prof_begin(prof, s);
+  QIMAX_DISPATCH_K(KC, {
+    if (WP == 64)
+      k_expand<K, 64><<<(uint32_t)nb, kExpandBlock, 0, s>>>((const K*)keys, (const double*)w, T_in, off, T_img,
+                                                             pa, (K*)keys_out, (double*)w_out, err);
+    else
+      k_expand<K, 32><<<(uint32_t)nb, kExpandBlock, 0, s>>>((const K*)keys, (const float*)w, T_in, off, T_img,
+                                                             pa, (K*)keys_out, (float*)w_out, err);
+  });
+  const double per = (KC == 0 ? 4 : 8) + (WP == 64 ? 8 : 4);
+  prof_end(prof, s, ev, kKExpand, per * (double)(T_in + T_img) + 8.0 * (double)T_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_in, void* keys_out, void* w_out,
+                            uint64_t T, uint32_t shift, const Tiling& tl, uint64_t* hist, uint64_t* hist_off,
+                            uint64_t* tmp, uint32_t* err, hipStream_t s, Prof* prof) {
+  if (T == 0 || tl.n_blocks == 0) return hipSuccess;
+  const uint64_t hsize = (uint64_t)kRadix * tl.n_blocks;
+  const double kb = KC == 0 ? 4 : 8, wb = WP == 64 ? 8 : 4;
+  QIMAX_DISPATCH_K(KC, {
+    hipEvent_t ev = prof_begin(prof, s);
+    k_sort_hist<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys_in, shift, tl, hist, hsize, err);
+    prof_end(prof, s, ev, kKSortHist, kb * (double)T + 8.0 * (double)hsize);
+    hipError_t e = scan_impl<uint64_t>(hist, hist_off, hsize, tmp, s, prof);
+    if (e != hipSuccess) return e;
+    ev = prof_begin(prof, s);
+    if (WP == 64)
+      k_sort_scatter<K, double><<<tl.n_blocks, kSortBlock, 0, s>>>(
+          (const K*)keys_in, (const double*)w_in, (K*)keys_out, (double*)w_out, T, shift, tl, hist_off, err);
+    else
+      k_sort_scatter<K, float><<<tl.n_blocks, kSortBlock, 0, s>>>(
+          (const K*)keys_in, (const float*)w_in, (K*)keys_out, (float*)w_out, T, shift, tl, hist_off, err);
+    prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, uint64_t T,
+                        const Tiling& tl, double thr, void* keys_out, void* w_out, uint64_t* seg_off_out,
+                        uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp, uint32_t* err, hipStream_t s,
+                        Prof* prof) {
+  if (tl.n_blocks == 0) {
+    // no terms at all: every segment offset is zero
+    k_zero_one<<<1, 1, 0, s>>>(blk_off);
+    k_gather_u64_by_u32<<<grid_for(tl.n_segs + 1, 64), 64, 0, s>>>(blk_off, tl.seg_blk, seg_off_out,
+                                                                   tl.n_segs + 1);
+    return hipGetLastError();
+  }
+  const double kb = KC == 0 ? 4 : 8, wb = WP == 64 ? 8 : 4;
+  QIMAX_DISPATCH_K(KC, {
+    hipEvent_t ev = prof_begin(prof, s);
+    if (WP == 64) {
+      k_merge<K, double, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
+          (const K*)keys_in, (const double*)w_in, tl, thr, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0, err);
+    } else {
+      k_merge<K, float, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
+          (const K*)keys_in, (const float*)w_in, tl, thr, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0, err);
+    }
+    prof_end(prof, s, ev, kKMergeCount, (kb + wb) * (double)T);
+    hipError_t e = scan_impl<uint32_t>(blk_cnt, blk_off, tl.n_blocks, tmp, s, prof);
+    if (e != hipSuccess) return e;
+    ev = prof_begin(prof, s);
+    if (WP == 64) {
+      k_merge<K, double, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
+          (const K*)keys_in, (const double*)w_in, tl, thr, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
+          (double*)w_out, T, err);
+    } else {
+      k_merge<K, float, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
+          (const K*)keys_in, (const float*)w_in, tl, thr, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
+          (float*)w_out, T, err);
+    }
+    // output size is known only on the device; the read side is counted here and the
+    // written terms are added by the caller once the count is back on the host
+    prof_end(prof, s, ev, kKMergeWrite, (kb + wb) * (double)T);
+  });
+  k_gather_u64_by_u32<<<grid_for(tl.n_segs + 1, 64), 64, 0, s>>>(blk_off, tl.seg_blk, seg_off_out, tl.n_segs + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights_to_f64(int WP, const void* w, double* out, uint64_t T, hipStream_t s, Prof* prof) {
+  (void)prof;
+  if (T == 0) return hipSuccess;
+  if (WP == 64) k_weights_to_f64<64><<<grid_for(T, 256), 256, 0, s>>>((const double*)w, out, T);
+  else k_weights_to_f64<32><<<grid_for(T, 256), 256, 0, s>>>((const float*)w, out, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_ptm(const uint8_t* gate, const double* theta, const uint32_t* idx,
+                              const uint32_t* chain_off, uint32_t n_chains, double* ptm_out, hipStream_t s,
+                              Prof* prof) {
+  if (n_chains == 0) return hipSuccess;
+  hipEvent_t ev = prof_begin(prof, s);
+  k_compose_ptm<<<grid_for(n_chains, 64), 64, 0, s>>>(gate, theta, idx, chain_off, n_chains, ptm_out);
+  prof_end(prof, s, ev, kKCompose, 0.0);
+  return hipGetLastError();
+}
+
+}  // namespace qimax

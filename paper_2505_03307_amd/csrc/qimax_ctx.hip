@@ -1,0 +1,1130 @@
+// Host runtime behind the C ABI: context and device memory, operator validation and
+// classification, the pass planner, the grouping of instructions into the paper's U_k /
+// V_k operators, readout and expectation values.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/qimax.h"
+#include "qimax_internal.h"
+
+using namespace qimax;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// One operator on the host: PTM R[out][in] (dim 4 or 16), its wires and its operator
+// group (the index of the U_k / V_k run it belongs to).
+struct HostOp {
+  int arity = 1;
+  int q0 = 0, q1 = 0;
+  int dim = 4;
+  int group = 0;
+  bool perm = false;
+  uint64_t mask = 0;  // wires touched
+  std::vector<double> R;  // dim*dim
+};
+
+struct Pass {
+  std::vector<const HostOp*> A, E, B;
+  uint64_t emask = 0, bmask = 0;
+  int egroup = -1;
+  double fanout_bound = 1.0;
+};
+
+// The paper's CX look-up tables (Sec. III-C-2), indexed [p_c][p_t] with I=0, X=1, Y=2, Z=3:
+// new control digit, new target digit and sign.
+const int kLutC[4][4] = {{0, 0, 3, 3}, {1, 1, 2, 2}, {2, 2, 1, 1}, {3, 3, 0, 0}};
+const int kLutT[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {1, 0, 3, 2}, {0, 1, 2, 3}};
+const int kLutSign[4][4] = {{1, 1, 1, 1}, {1, 1, 1, -1}, {1, 1, -1, 1}, {1, 1, 1, 1}};
+
+void cx_ptm(double* R) {
+  std::fill(R, R + 256, 0.0);
+  for (int pc = 0; pc < 4; ++pc)
+    for (int pt = 0; pt < 4; ++pt) {
+      const int in = 4 * pc + pt, out = 4 * kLutC[pc][pt] + kLutT[pc][pt];
+      R[out * 16 + in] = (double)kLutSign[pc][pt];
+    }
+}
+
+// Hadamard's PTM on one digit: X <-> Z, Y -> -Y.
+void h_ptm(double* R) {
+  std::fill(R, R + 16, 0.0);
+  R[0 * 4 + 0] = 1;
+  R[3 * 4 + 1] = 1;
+  R[2 * 4 + 2] = -1;
+  R[1 * 4 + 3] = 1;
+}
+
+// CZ = (I x H) CX (I x H) on (q0, q1); the transfer matrices compose the same way.
+void cz_ptm(double* R) {
+  double cx[256], h[16], ih[256], tmp[256];
+  cx_ptm(cx);
+  h_ptm(h);
+  std::fill(ih, ih + 256, 0.0);
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < 4; ++c) ih[(4 * a + b) * 16 + (4 * a + c)] = h[b * 4 + c];
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) {
+      double s = 0;
+      for (int k = 0; k < 16; ++k) s += cx[i * 16 + k] * ih[k * 16 + j];
+      tmp[i * 16 + j] = s;
+    }
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) {
+      double s = 0;
+      for (int k = 0; k < 16; ++k) s += ih[i * 16 + k] * tmp[k * 16 + j];
+      R[i * 16 + j] = s;
+    }
+}
+
+bool is_signed_perm(const std::vector<double>& R, int dim) {
+  for (int c = 0; c < dim; ++c) {
+    int nz = 0;
+    for (int r = 0; r < dim; ++r) {
+      const double v = R[r * dim + c];
+      if (v == 0.0) continue;
+      if (v != 1.0 && v != -1.0) return false;
+      ++nz;
+    }
+    if (nz != 1) return false;
+  }
+  return true;
+}
+
+int max_col_nnz(const std::vector<double>& R, int dim) {
+  int m = 0;
+  for (int c = 0; c < dim; ++c) {
+    int nz = 0;
+    for (int r = 0; r < dim; ++r) nz += R[r * dim + c] != 0.0;
+    m = std::max(m, nz);
+  }
+  return m;
+}
+
+// Unital, trace preserving and orthogonal (R^T R = I) within tol.
+bool is_valid_ptm(const std::vector<double>& R, int dim, double tol) {
+  if (std::fabs(R[0] - 1.0) > tol) return false;
+  for (int a = 1; a < dim; ++a)
+    if (std::fabs(R[a * dim]) > tol || std::fabs(R[a]) > tol) return false;
+  for (int i = 0; i < dim; ++i)
+    for (int j = 0; j < dim; ++j) {
+      double s = 0;
+      for (int k = 0; k < dim; ++k) s += R[k * dim + i] * R[k * dim + j];
+      if (std::fabs(s - (i == j ? 1.0 : 0.0)) > tol) return false;
+    }
+  for (double v : R)
+    if (!std::isfinite(v)) return false;
+  return true;
+}
+
+constexpr int kMaxE1 = 64;
+constexpr int kMaxE2 = 8;
+constexpr double kMaxFanout = 2147483647.0;
+
+}  // namespace
+
+struct qimax_ctx {
+  uint32_t n = 0;
+  int KC = 1;
+  int WP = 64;
+  int fp64_acc = 0;
+  double eps = 0.0;
+  size_t cap = 0;
+  int validate = 1;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t kb = 8, wb = 8;  // bytes per key / weight
+
+  // committed state
+  DevBuf keys, w, seg;
+  uint64_t T = 0;
+  std::vector<uint64_t> h_seg;
+  std::vector<HostOp> pending;  // deferred Clifford operators (not yet applied)
+
+  // pass outputs (ping-pong) and their segment offsets
+  DevBuf pk[2], pw[2], pseg[2];
+  // images and sort ping-pong
+  DevBuf ik[2], iw[2];
+  DevBuf cnt, off, scan_tmp, hist, hist_off, blk_begin, blk_end, blk_seg, seg_blk, blk_cnt, blk_off, img_seg;
+  DevBuf desc, err, f64tmp;
+  DevBuf gr_gate, gr_theta, gr_idx, gr_off, gr_out;
+  uint64_t* pinned = nullptr;  // small pinned host scratch
+  size_t pinned_words = 0;
+
+  size_t alloc_bytes = 0, peak_bytes = 0;
+  std::string last_error;
+  bool broken = false;
+  qimax_stats st{};
+  Prof prof;
+  std::vector<uint64_t> gen_updates;
+  // host staging of asynchronous uploads; kept alive until the next stream synchronisation
+  std::vector<uint8_t> stage_desc;
+  std::vector<uint64_t> stage_begin, stage_end;
+  std::vector<uint32_t> stage_seg, stage_seg_blk;
+};
+
+namespace {
+
+
+thread_local std::string g_create_error;
+
+qimax_status fail(qimax_ctx* c, qimax_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+qimax_status hip_fail(qimax_ctx* c, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    return fail(c, QIMAX_ENOMEM, msg);
+  }
+  c->broken = true;
+  return fail(c, QIMAX_EDEVICE, msg);
+}
+
+#define HIPCHK(c, expr, what)                          \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return hip_fail((c), _e, (what)); \
+  } while (0)
+
+void dev_free(qimax_ctx* c, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    c->alloc_bytes -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// Grow-only device buffer with the context's memory cap.
+qimax_status ensure(qimax_ctx* c, DevBuf& b, size_t bytes, bool headroom = true) {
+  if (bytes <= b.bytes && b.p) return QIMAX_OK;
+  size_t want = bytes == 0 ? 256 : bytes;
+  if (headroom) want = want + want / 4;
+  want = (want + 255) & ~(size_t)255;
+  const size_t after = c->alloc_bytes - b.bytes + want;
+  if (c->cap && after > c->cap) {
+    if (bytes > 0 && c->alloc_bytes - b.bytes + bytes <= c->cap)
+      want = (bytes + 255) & ~(size_t)255;
+    if (c->alloc_bytes - b.bytes + want > c->cap)
+      return fail(c, QIMAX_ENOMEM, "memory cap exceeded (requested " + std::to_string(bytes) + " bytes)");
+  }
+  if (b.p) {
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    dev_free(c, b);
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, QIMAX_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  b.p = p;
+  b.bytes = want;
+  c->alloc_bytes += want;
+  c->peak_bytes = std::max(c->peak_bytes, c->alloc_bytes);
+  return QIMAX_OK;
+}
+
+#define QCHK(expr)                         \
+  do {                                     \
+    qimax_status _s = (expr);              \
+    if (_s != QIMAX_OK) return _s;         \
+  } while (0)
+
+__global__ void k_clear_u32(uint32_t* p) { *p = 0u; }
+
+uint32_t bitpos(const qimax_ctx* c, int q) { return 2u * (c->n - 1u - (uint32_t)q); }
+
+PermDesc make_perm(const qimax_ctx* c, const HostOp& op) {
+  PermDesc d{};
+  d.arity = (uint32_t)op.arity;
+  d.pa = bitpos(c, op.q0);
+  d.pb = op.arity == 2 ? bitpos(c, op.q1) : 0u;
+  for (int in = 0; in < op.dim; ++in) {
+    int out = 0;
+    bool neg = false;
+    for (int r = 0; r < op.dim; ++r) {
+      const double v = op.R[r * op.dim + in];
+      if (v != 0.0) {
+        out = r;
+        neg = v < 0;
+      }
+    }
+    const uint64_t e = (uint64_t)(out | (neg ? 16 : 0));
+    if (in < 8) d.lo |= e << (8 * in);
+    else d.hi |= e << (8 * (in - 8));
+  }
+  return d;
+}
+
+Exp1Desc make_exp1(const qimax_ctx* c, const HostOp& op) {
+  Exp1Desc d{};
+  d.pos = bitpos(c, op.q0);
+  for (int in = 0; in < 4; ++in) {
+    int k = 0;
+    for (int r = 0; r < 4; ++r) {
+      const double v = op.R[r * 4 + in];
+      if (v == 0.0) continue;
+      d.out[in][k] = (uint8_t)r;
+      d.val[in][k] = v;
+      d.valf[in][k] = (float)v;
+      ++k;
+    }
+    d.cnt[in] = (uint8_t)k;
+  }
+  return d;
+}
+
+Exp2Desc make_exp2(const qimax_ctx* c, const HostOp& op) {
+  Exp2Desc d{};
+  d.pa = bitpos(c, op.q0);
+  d.pb = bitpos(c, op.q1);
+  for (int in = 0; in < 16; ++in) {
+    int k = 0;
+    for (int r = 0; r < 16; ++r) {
+      const double v = op.R[r * 16 + in];
+      if (v == 0.0) continue;
+      d.out[in][k] = (uint8_t)r;
+      d.val[in][k] = v;
+      d.valf[in][k] = (float)v;
+      ++k;
+    }
+    d.cnt[in] = (uint8_t)k;
+  }
+  return d;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Upload the pass's operator descriptors; fills pa with device pointers.
+qimax_status upload_pass(qimax_ctx* c, const Pass& p, PassArgs& pa) {
+  std::vector<PermDesc> A, B;
+  std::vector<Exp1Desc> E1;
+  std::vector<Exp2Desc> E2;
+  for (auto* op : p.A) A.push_back(make_perm(c, *op));
+  for (auto* op : p.B) B.push_back(make_perm(c, *op));
+  for (auto* op : p.E) {
+    if (op->arity == 1) E1.push_back(make_exp1(c, *op));
+    else E2.push_back(make_exp2(c, *op));
+  }
+  const size_t oA = 0, oB = align256(oA + A.size() * sizeof(PermDesc));
+  const size_t o1 = align256(oB + B.size() * sizeof(PermDesc));
+  const size_t o2 = align256(o1 + E1.size() * sizeof(Exp1Desc));
+  const size_t total = align256(o2 + E2.size() * sizeof(Exp2Desc)) + 256;
+  QCHK(ensure(c, c->desc, total));
+  std::vector<uint8_t>& host = c->stage_desc;
+  host.assign(total, 0);
+  if (!A.empty()) std::memcpy(host.data() + oA, A.data(), A.size() * sizeof(PermDesc));
+  if (!B.empty()) std::memcpy(host.data() + oB, B.data(), B.size() * sizeof(PermDesc));
+  if (!E1.empty()) std::memcpy(host.data() + o1, E1.data(), E1.size() * sizeof(Exp1Desc));
+  if (!E2.empty()) std::memcpy(host.data() + o2, E2.data(), E2.size() * sizeof(Exp2Desc));
+  HIPCHK(c, hipMemcpyAsync(c->desc.p, host.data(), total, hipMemcpyHostToDevice, c->stream), "upload descriptors");
+  uint8_t* base = (uint8_t*)c->desc.p;
+  pa.A = (const PermDesc*)(base + oA);
+  pa.B = (const PermDesc*)(base + oB);
+  pa.E1 = (const Exp1Desc*)(base + o1);
+  pa.E2 = (const Exp2Desc*)(base + o2);
+  pa.nA = (uint32_t)A.size();
+  pa.nB = (uint32_t)B.size();
+  pa.nE1 = (uint32_t)E1.size();
+  pa.nE2 = (uint32_t)E2.size();
+  return QIMAX_OK;
+}
+
+// Segment-aligned tiles of at most kSortTile elements over segment offsets so[0..S].
+struct HostTiling {
+  std::vector<uint64_t> begin, end;
+  std::vector<uint32_t> seg, seg_blk;
+};
+
+void make_tiling(const std::vector<uint64_t>& so, HostTiling& t) {
+  const size_t S = so.size() - 1;
+  t.begin.clear(); t.end.clear(); t.seg.clear(); t.seg_blk.assign(S + 1, 0);
+  for (size_t s = 0; s < S; ++s) {
+    t.seg_blk[s] = (uint32_t)t.begin.size();
+    for (uint64_t b = so[s]; b < so[s + 1]; b += kSortTile) {
+      t.begin.push_back(b);
+      t.end.push_back(std::min(b + (uint64_t)kSortTile, so[s + 1]));
+      t.seg.push_back((uint32_t)s);
+    }
+  }
+  t.seg_blk[S] = (uint32_t)t.begin.size();
+}
+
+qimax_status upload_tiling(qimax_ctx* c, const HostTiling& hin, Tiling& tl) {
+  c->stage_begin = hin.begin;
+  c->stage_end = hin.end;
+  c->stage_seg = hin.seg;
+  c->stage_seg_blk = hin.seg_blk;
+  struct { std::vector<uint64_t>& begin; std::vector<uint64_t>& end; std::vector<uint32_t>& seg;
+           std::vector<uint32_t>& seg_blk; } h{c->stage_begin, c->stage_end, c->stage_seg, c->stage_seg_blk};
+  const size_t nb = h.begin.size();
+  QCHK(ensure(c, c->blk_begin, std::max<size_t>(nb, 1) * 8));
+  QCHK(ensure(c, c->blk_end, std::max<size_t>(nb, 1) * 8));
+  QCHK(ensure(c, c->blk_seg, std::max<size_t>(nb, 1) * 4));
+  QCHK(ensure(c, c->seg_blk, h.seg_blk.size() * 4));
+  if (nb) {
+    HIPCHK(c, hipMemcpyAsync(c->blk_begin.p, h.begin.data(), nb * 8, hipMemcpyHostToDevice, c->stream), "tiling");
+    HIPCHK(c, hipMemcpyAsync(c->blk_end.p, h.end.data(), nb * 8, hipMemcpyHostToDevice, c->stream), "tiling");
+    HIPCHK(c, hipMemcpyAsync(c->blk_seg.p, h.seg.data(), nb * 4, hipMemcpyHostToDevice, c->stream), "tiling");
+  }
+  HIPCHK(c, hipMemcpyAsync(c->seg_blk.p, h.seg_blk.data(), h.seg_blk.size() * 4, hipMemcpyHostToDevice, c->stream),
+         "tiling");
+  tl.blk_begin = (const uint64_t*)c->blk_begin.p;
+  tl.blk_end = (const uint64_t*)c->blk_end.p;
+  tl.blk_seg = (const uint32_t*)c->blk_seg.p;
+  tl.seg_blk = (const uint32_t*)c->seg_blk.p;
+  tl.n_blocks = (uint32_t)nb;
+  tl.n_segs = (uint32_t)(h.seg_blk.size() - 1);
+  return QIMAX_OK;
+}
+
+// Copy `words` uint64 from device to the pinned scratch (plus the error word) and wait.
+qimax_status readback(qimax_ctx* c, const void* dev, size_t words, uint32_t* err_out) {
+  if (words + 1 > c->pinned_words) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    size_t want = std::max<size_t>(words + 1, 4096);
+    HIPCHK(c, hipHostMalloc((void**)&c->pinned, want * 8, hipHostMallocDefault), "hipHostMalloc");
+    c->pinned_words = want;
+  }
+  if (words)
+    HIPCHK(c, hipMemcpyAsync(c->pinned, dev, words * 8, hipMemcpyDeviceToHost, c->stream), "readback");
+  HIPCHK(c, hipMemcpyAsync(c->pinned + words, c->err.p, 4, hipMemcpyDeviceToHost, c->stream), "readback err");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  prof_resolve(&c->prof);
+  *err_out = (uint32_t)(c->pinned[words] & 0xFFFFFFFFu);
+  return QIMAX_OK;
+}
+
+std::string err_text(uint32_t e) {
+  std::string s;
+  if (e & kErrIndex) s += " index-out-of-range";
+  if (e & kErrFanout) s += " fanout-overflow";
+  if (e & kErrOrder) s += " order";
+  return s;
+}
+
+// Runs one pass on terms (k_in, w_in, seg_in [device], so_in [host]) and writes the merged
+// result to pass buffer `slot`. On success fills so_out (host) and returns the count.
+qimax_status run_pass(qimax_ctx* c, const Pass& p, const void* k_in, const void* w_in, const uint64_t* seg_in,
+                      const std::vector<uint64_t>& so_in, int slot, double thr, std::vector<uint64_t>& so_out) {
+  const uint32_t S = c->n;
+  const uint64_t T_in = so_in[S];
+  PassArgs pa{};
+  QCHK(upload_pass(c, p, pa));
+  k_clear_u32<<<1, 1, 0, c->stream>>>((uint32_t*)c->err.p);
+  // fan-out count and scan -> image offsets
+  QCHK(ensure(c, c->cnt, std::max<uint64_t>(T_in, 1) * 4));
+  QCHK(ensure(c, c->off, (T_in + 1) * 8));
+  QCHK(ensure(c, c->scan_tmp, scan_tmp_words(T_in) * 8));
+  HIPCHK(c, launch_count(c->KC, k_in, T_in, pa, (uint32_t*)c->cnt.p, (uint32_t*)c->err.p, c->stream, &c->prof), "count");
+  HIPCHK(c, launch_scan_u32((const uint32_t*)c->cnt.p, (uint64_t*)c->off.p, T_in, (uint64_t*)c->scan_tmp.p,
+                            c->stream, &c->prof), "scan");
+  QCHK(ensure(c, c->img_seg, (S + 1) * 8));
+  HIPCHK(c, launch_gather_u64((const uint64_t*)c->off.p, seg_in, (uint64_t*)c->img_seg.p, S + 1, c->stream, &c->prof),
+         "gather");
+  uint32_t e = 0;
+  QCHK(readback(c, c->img_seg.p, S + 1, &e));
+  if (e) return fail(c, (e & kErrFanout) ? QIMAX_ETOOLARGE : QIMAX_EDEVICE, "count pass:" + err_text(e));
+  std::vector<uint64_t> so_img(c->pinned, c->pinned + S + 1);
+  const uint64_t T_img = so_img[S];
+  // expand into images
+  const size_t eb = c->kb, wbt = c->wb;
+  QCHK(ensure(c, c->ik[0], std::max<uint64_t>(T_img, 1) * eb));
+  QCHK(ensure(c, c->iw[0], std::max<uint64_t>(T_img, 1) * wbt));
+  QCHK(ensure(c, c->ik[1], std::max<uint64_t>(T_img, 1) * eb));
+  QCHK(ensure(c, c->iw[1], std::max<uint64_t>(T_img, 1) * wbt));
+  HIPCHK(c, launch_expand(c->KC, c->WP, k_in, w_in, T_in, (const uint64_t*)c->off.p, T_img, pa, c->ik[0].p,
+                          c->iw[0].p, (uint32_t*)c->err.p, c->stream, &c->prof), "expand");
+  // segmented LSD radix sort of the images
+  HostTiling ht;
+  make_tiling(so_img, ht);
+  Tiling tl{};
+  QCHK(upload_tiling(c, ht, tl));
+  const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
+  QCHK(ensure(c, c->hist, hsize * 8));
+  QCHK(ensure(c, c->hist_off, (hsize + 1) * 8));
+  QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
+  int cur = 0;
+  const uint32_t key_bits = 2u * c->n;
+  for (uint32_t shift = 0; shift < key_bits; shift += kRadixBits) {
+    HIPCHK(c, launch_sort_pass(c->KC, c->WP, c->ik[cur].p, c->iw[cur].p, c->ik[cur ^ 1].p, c->iw[cur ^ 1].p, T_img,
+                               shift, tl, (uint64_t*)c->hist.p, (uint64_t*)c->hist_off.p, (uint64_t*)c->scan_tmp.p,
+                               (uint32_t*)c->err.p, c->stream, &c->prof), "sort");
+    cur ^= 1;
+  }
+  // segmented reduce + prune + compaction into the pass output slot
+  QCHK(ensure(c, c->pk[slot], std::max<uint64_t>(T_img, 1) * eb));
+  QCHK(ensure(c, c->pw[slot], std::max<uint64_t>(T_img, 1) * wbt));
+  QCHK(ensure(c, c->pseg[slot], (S + 1) * 8));
+  QCHK(ensure(c, c->blk_cnt, (size_t)(tl.n_blocks + 1) * 4));
+  QCHK(ensure(c, c->blk_off, (size_t)(tl.n_blocks + 1) * 8));
+  HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, thr, c->pk[slot].p,
+                         c->pw[slot].p, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
+                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, (uint32_t*)c->err.p, c->stream, &c->prof),
+         "merge");
+  QCHK(readback(c, c->pseg[slot].p, S + 1, &e));
+  if (e) return fail(c, QIMAX_EDEVICE, "expand/sort/merge pass:" + err_text(e));
+  so_out.assign(c->pinned, c->pinned + S + 1);
+  const uint64_t T_out = so_out[S];
+  if (c->prof.on) c->prof.bytes[kKMergeWrite] += (double)T_out * (double)(eb + wbt);
+  // bookkeeping: one update per output image of every operator (Clifford operators
+  // count their input terms, the expanding operator its images)
+  auto groups = [&](const std::vector<const HostOp*>& v) {
+    std::vector<int> g;
+    for (auto* op : v)
+      if (op->group != p.egroup) g.push_back(op->group);
+    std::sort(g.begin(), g.end());
+    return (uint64_t)(std::unique(g.begin(), g.end()) - g.begin());
+  };
+  const uint64_t gA = groups(p.A), gB = groups(p.B);
+  c->st.term_updates += gA * T_in + (p.E.empty() ? 0 : T_img) + gB * T_out;
+  if (c->gen_updates.size() != S) c->gen_updates.assign(S, 0);
+  for (uint32_t j = 0; j < S; ++j)
+    c->gen_updates[j] += gA * (so_in[j + 1] - so_in[j]) + (p.E.empty() ? 0 : so_img[j + 1] - so_img[j]) +
+                         gB * (so_out[j + 1] - so_out[j]);
+  c->st.images += T_img;
+  c->st.sort_elems += T_img * ((key_bits + kRadixBits - 1) / kRadixBits);
+  if (!p.E.empty()) c->st.passes += 1;
+  return QIMAX_OK;
+}
+
+// Plans the operators into passes and runs them; commits only when every pass succeeded.
+qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  // the deferred Clifford operators of earlier calls come first
+  std::vector<HostOp> all;
+  all.reserve(c->pending.size() + ops.size());
+  for (auto& op : c->pending) all.push_back(op);
+  for (auto& op : ops) all.push_back(op);
+  std::vector<Pass> passes;
+  Pass cur;
+  for (const HostOp& op : all) {
+    if (op.perm) {
+      if (cur.E.empty() || (cur.B.empty() && !(op.mask & cur.emask))) {
+        cur.A.push_back(&op);  // before (or commuting past) the expanding operators
+      } else {
+        cur.B.push_back(&op);
+        cur.bmask |= op.mask;
+      }
+      continue;
+    }
+    const double f = (double)max_col_nnz(op.R, op.dim);
+    int n1 = 0, n2 = 0;
+    for (auto* e : cur.E) (e->arity == 1 ? n1 : n2)++;
+    const bool fits = (op.arity == 1 ? n1 + 1 <= kMaxE1 : n2 + 1 <= kMaxE2) && cur.fanout_bound * f <= kMaxFanout;
+    const bool join = !cur.E.empty() && op.group == cur.egroup && !(op.mask & cur.emask) && !(op.mask & cur.bmask) && fits;
+    if (!cur.E.empty() && !join) {
+      passes.push_back(cur);
+      cur = Pass();
+    }
+    cur.E.push_back(&op);
+    cur.emask |= op.mask;
+    cur.egroup = op.group;
+    cur.fanout_bound *= f;
+  }
+  std::vector<HostOp> new_pending;
+  if (cur.E.empty()) {
+    for (auto* op : cur.A) new_pending.push_back(*op);
+  } else {
+    passes.push_back(cur);
+  }
+  if (passes.empty()) {
+    c->pending.swap(new_pending);
+    return QIMAX_OK;
+  }
+  // run the passes: committed state -> pass slot 0 -> slot 1 -> ...
+  const void* k_in = c->keys.p;
+  const void* w_in = c->w.p;
+  const uint64_t* s_in = (const uint64_t*)c->seg.p;
+  std::vector<uint64_t> so_in = c->h_seg, so_out;
+  int slot = 0;
+  for (size_t i = 0; i < passes.size(); ++i) {
+    const double thr = (i + 1 == passes.size()) ? c->eps : 0.0;
+    qimax_status s = run_pass(c, passes[i], k_in, w_in, s_in, so_in, slot, thr, so_out);
+    if (s != QIMAX_OK) return s;  // committed state untouched
+    k_in = c->pk[slot].p;
+    w_in = c->pw[slot].p;
+    s_in = (const uint64_t*)c->pseg[slot].p;
+    so_in = so_out;
+    slot ^= 1;
+  }
+  const int last = slot ^ 1;
+  std::swap(c->keys, c->pk[last]);
+  std::swap(c->w, c->pw[last]);
+  std::swap(c->seg, c->pseg[last]);
+  c->h_seg = so_in;
+  c->T = so_in[c->n];
+  c->pending.swap(new_pending);
+  c->st.terms = c->T;
+  return QIMAX_OK;
+}
+
+qimax_status flush_pending(qimax_ctx* c) {
+  if (c->pending.empty()) return QIMAX_OK;
+  // a pass with only Clifford operators: images are the permuted terms, then sorted
+  std::vector<HostOp> none;
+  std::vector<HostOp> saved = c->pending;
+  Pass p;
+  for (auto& op : c->pending) p.A.push_back(&op);
+  std::vector<uint64_t> so_out;
+  qimax_status s = run_pass(c, p, c->keys.p, c->w.p, (const uint64_t*)c->seg.p, c->h_seg, 0, 0.0, so_out);
+  if (s != QIMAX_OK) return s;
+  std::swap(c->keys, c->pk[0]);
+  std::swap(c->w, c->pw[0]);
+  std::swap(c->seg, c->pseg[0]);
+  c->h_seg = so_out;
+  c->T = so_out[c->n];
+  c->pending.clear();
+  return QIMAX_OK;
+}
+
+qimax_status check_op_input(qimax_ctx* c, const qimax_op& in, int group, HostOp& op) {
+  if (in.arity != 1 && in.arity != 2) return fail(c, QIMAX_EINVAL, "op arity must be 1 or 2");
+  if (!in.ptm) return fail(c, QIMAX_EINVAL, "op ptm is NULL");
+  if (in.q[0] >= c->n || (in.arity == 2 && (in.q[1] >= c->n || in.q[1] == in.q[0])))
+    return fail(c, QIMAX_EINVAL, "op qubit out of range or repeated");
+  op.arity = (int)in.arity;
+  op.q0 = (int)in.q[0];
+  op.q1 = in.arity == 2 ? (int)in.q[1] : op.q0;
+  op.dim = in.arity == 1 ? 4 : 16;
+  op.group = group;
+  op.R.assign(in.ptm, in.ptm + op.dim * op.dim);
+  op.mask = (1ull << op.q0) | (in.arity == 2 ? (1ull << op.q1) : 0ull);
+  for (double v : op.R)
+    if (!std::isfinite(v)) return fail(c, QIMAX_EINVAL, "op ptm has a non-finite entry");
+  if (c->validate && !is_valid_ptm(op.R, op.dim, 1e-12))
+    return fail(c, QIMAX_EINVAL, "op ptm is not unital/orthogonal (set validate = 0 to allow)");
+  op.perm = is_signed_perm(op.R, op.dim);
+  return QIMAX_OK;
+}
+
+bool is_2q_code(uint8_t g) { return g == QIMAX_GATE_CX || g == QIMAX_GATE_CZ; }
+
+// The paper's grouping (Sec. III-A, Alg. 2): maximal runs of one-qubit gates (U_k) and
+// of two-qubit gates (V_k) in instruction order; inside U_k the gates of each wire form
+// U_{k,j}, composed into one transfer matrix on the device (Alg. 1).
+qimax_status group_circuit(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
+                           const double* theta, size_t m, std::vector<HostOp>& ops, size_t* n_u, size_t* n_v) {
+  for (size_t i = 0; i < m; ++i) {
+    if (gate[i] > QIMAX_GATE_CZ) return fail(c, QIMAX_EINVAL, "unknown gate code at instruction " + std::to_string(i));
+    if (q0[i] >= c->n) return fail(c, QIMAX_EINVAL, "qubit out of range at instruction " + std::to_string(i));
+    if (is_2q_code(gate[i]) && (q1[i] >= c->n || q1[i] == q0[i]))
+      return fail(c, QIMAX_EINVAL, "bad second qubit at instruction " + std::to_string(i));
+    if (theta && !std::isfinite(theta[i])) return fail(c, QIMAX_EINVAL, "non-finite angle");
+  }
+  // runs
+  struct Run { bool two; size_t a, b; };
+  std::vector<Run> runs;
+  for (size_t i = 0; i < m;) {
+    const bool two = is_2q_code(gate[i]);
+    size_t j = i;
+    while (j < m && is_2q_code(gate[j]) == two) ++j;
+    runs.push_back({two, i, j});
+    i = j;
+  }
+  size_t nu = 0, nv = 0;
+  // one-qubit chains: per U run, per wire in increasing order
+  std::vector<uint32_t> idx, chain_off{0};
+  struct ChainRef { int run; int wire; };
+  std::vector<ChainRef> chains;
+  std::vector<std::vector<uint32_t>> per_wire(c->n);
+  for (size_t r = 0; r < runs.size(); ++r) {
+    if (runs[r].two) { ++nv; continue; }
+    ++nu;
+    for (auto& v : per_wire) v.clear();
+    for (size_t i = runs[r].a; i < runs[r].b; ++i) per_wire[q0[i]].push_back((uint32_t)i);
+    for (uint32_t j = 0; j < c->n; ++j) {
+      if (per_wire[j].empty()) continue;
+      for (uint32_t gi : per_wire[j]) idx.push_back(gi);
+      chain_off.push_back((uint32_t)idx.size());
+      chains.push_back({(int)r, (int)j});
+    }
+  }
+  std::vector<double> ptm(chains.size() * 16);
+  if (!chains.empty()) {
+    QCHK(ensure(c, c->gr_gate, m));
+    QCHK(ensure(c, c->gr_theta, m * 8));
+    QCHK(ensure(c, c->gr_idx, idx.size() * 4));
+    QCHK(ensure(c, c->gr_off, chain_off.size() * 4));
+    QCHK(ensure(c, c->gr_out, chains.size() * 16 * 8));
+    std::vector<double> th(m, 0.0);
+    if (theta) std::copy(theta, theta + m, th.begin());
+    HIPCHK(c, hipMemcpyAsync(c->gr_gate.p, gate, m, hipMemcpyHostToDevice, c->stream), "group upload");
+    HIPCHK(c, hipMemcpyAsync(c->gr_theta.p, th.data(), m * 8, hipMemcpyHostToDevice, c->stream), "group upload");
+    HIPCHK(c, hipMemcpyAsync(c->gr_idx.p, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, c->stream), "group upload");
+    HIPCHK(c, hipMemcpyAsync(c->gr_off.p, chain_off.data(), chain_off.size() * 4, hipMemcpyHostToDevice, c->stream),
+           "group upload");
+    HIPCHK(c, launch_compose_ptm((const uint8_t*)c->gr_gate.p, (const double*)c->gr_theta.p,
+                                 (const uint32_t*)c->gr_idx.p, (const uint32_t*)c->gr_off.p, (uint32_t)chains.size(),
+                                 (double*)c->gr_out.p, c->stream, &c->prof), "compose_ptm");
+    HIPCHK(c, hipMemcpyAsync(ptm.data(), c->gr_out.p, ptm.size() * 8, hipMemcpyDeviceToHost, c->stream),
+           "group readback");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  }
+  // assemble the operator list in run order
+  double cx[256], cz[256];
+  cx_ptm(cx);
+  cz_ptm(cz);
+  size_t ci = 0;
+  ops.clear();
+  for (size_t r = 0; r < runs.size(); ++r) {
+    if (runs[r].two) {
+      for (size_t i = runs[r].a; i < runs[r].b; ++i) {
+        HostOp op;
+        op.arity = 2; op.dim = 16; op.q0 = (int)q0[i]; op.q1 = (int)q1[i]; op.group = (int)r;
+        op.R.assign(gate[i] == QIMAX_GATE_CX ? cx : cz, (gate[i] == QIMAX_GATE_CX ? cx : cz) + 256);
+        op.mask = (1ull << op.q0) | (1ull << op.q1);
+        op.perm = true;
+        ops.push_back(std::move(op));
+      }
+    } else {
+      while (ci < chains.size() && chains[ci].run == (int)r) {
+        HostOp op;
+        op.arity = 1; op.dim = 4; op.q0 = op.q1 = chains[ci].wire; op.group = (int)r;
+        op.R.assign(ptm.begin() + ci * 16, ptm.begin() + ci * 16 + 16);
+        op.mask = 1ull << op.q0;
+        op.perm = is_signed_perm(op.R, 4);
+        bool identity = true;
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b) identity &= op.R[a * 4 + b] == (a == b ? 1.0 : 0.0);
+        if (!identity) ops.push_back(std::move(op));
+        ++ci;
+      }
+    }
+  }
+  if (n_u) *n_u = nu;
+  if (n_v) *n_v = nv;
+  return QIMAX_OK;
+}
+
+// ------------------------------------------------------------------ host readout helpers
+struct HostGens {
+  std::vector<uint64_t> off, key;
+  std::vector<double> w;
+};
+
+qimax_status fetch(qimax_ctx* c, HostGens& g) {
+  QCHK(flush_pending(c));
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  g.off = c->h_seg;
+  const uint64_t T = c->T;
+  g.key.resize(T);
+  g.w.resize(T);
+  if (T == 0) return QIMAX_OK;
+  if (c->KC == 1) {
+    HIPCHK(c, hipMemcpy(g.key.data(), c->keys.p, T * 8, hipMemcpyDeviceToHost), "keys D2H");
+  } else {
+    std::vector<uint32_t> k32(T);
+    HIPCHK(c, hipMemcpy(k32.data(), c->keys.p, T * 4, hipMemcpyDeviceToHost), "keys D2H");
+    for (uint64_t i = 0; i < T; ++i) g.key[i] = k32[i];
+  }
+  if (c->WP == 64) {
+    HIPCHK(c, hipMemcpy(g.w.data(), c->w.p, T * 8, hipMemcpyDeviceToHost), "weights D2H");
+  } else {
+    std::vector<float> w32(T);
+    HIPCHK(c, hipMemcpy(w32.data(), c->w.p, T * 4, hipMemcpyDeviceToHost), "weights D2H");
+    for (uint64_t i = 0; i < T; ++i) g.w[i] = w32[i];
+  }
+  return QIMAX_OK;
+}
+
+int digit_of(uint64_t key, uint32_t n, uint32_t q) { return (int)((key >> (2 * (n - 1 - q))) & 3u); }
+
+// single-qubit Pauli products: sigma_a sigma_b = i^ph[a][b] sigma_{mul[a][b]}
+const int kMul[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
+const int kPh[4][4] = {{0, 0, 0, 0}, {0, 0, 1, 3}, {0, 3, 0, 1}, {0, 1, 3, 0}};
+
+// <P> when every generator is one signed Pauli string: P is +-(a product of generators)
+// or anticommutes with one of them (then <P> = 0). GF(2) elimination over the digits.
+qimax_status expect_clifford(qimax_ctx* c, const HostGens& g, const std::vector<int>& P, double* out) {
+  const uint32_t n = c->n;
+  // anticommutation test
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint64_t k = g.key[g.off[j]];
+    int anti = 0;
+    for (uint32_t q = 0; q < n; ++q) {
+      const int a = digit_of(k, n, q), b = P[q];
+      if (a && b && a != b) anti ^= 1;
+    }
+    if (anti) { *out = 0.0; return QIMAX_OK; }
+  }
+  // binary vectors (x|z) of 2n bits for each generator, tracked with the set of rows combined
+  const uint32_t N2 = 2 * n;
+  auto vec = [&](const std::vector<int>& d) {
+    std::vector<uint8_t> v(N2, 0);
+    for (uint32_t q = 0; q < n; ++q) {
+      v[q] = (d[q] == 1 || d[q] == 2);
+      v[n + q] = (d[q] == 2 || d[q] == 3);
+    }
+    return v;
+  };
+  std::vector<std::vector<uint8_t>> rows(n), combo(n, std::vector<uint8_t>(n, 0));
+  std::vector<std::vector<int>> dig(n, std::vector<int>(n));
+  for (uint32_t j = 0; j < n; ++j) {
+    for (uint32_t q = 0; q < n; ++q) dig[j][q] = digit_of(g.key[g.off[j]], n, q);
+    rows[j] = vec(dig[j]);
+    combo[j][j] = 1;
+  }
+  std::vector<uint8_t> target = vec(P);
+  std::vector<uint8_t> used(n, 0);
+  // reduce target by pivots
+  std::vector<uint8_t> sel(n, 0);
+  for (uint32_t col = 0; col < N2; ++col) {
+    int piv = -1;
+    for (uint32_t r = 0; r < n; ++r)
+      if (!used[r] && rows[r][col]) { piv = (int)r; break; }
+    if (piv < 0) continue;
+    used[piv] = 1;
+    for (uint32_t r = 0; r < n; ++r)
+      if (r != (uint32_t)piv && rows[r][col]) {
+        for (uint32_t k = 0; k < N2; ++k) rows[r][k] ^= rows[piv][k];
+        for (uint32_t k = 0; k < n; ++k) combo[r][k] ^= combo[piv][k];
+      }
+    if (target[col]) {
+      for (uint32_t k = 0; k < N2; ++k) target[k] ^= rows[piv][k];
+      for (uint32_t k = 0; k < n; ++k) sel[k] ^= combo[piv][k];
+    }
+  }
+  for (uint32_t k = 0; k < N2; ++k)
+    if (target[k]) { *out = 0.0; return QIMAX_OK; }
+  // product of the selected generators with its phase
+  std::vector<int> acc(n, 0);
+  int ph = 0;
+  double sign = 1.0;
+  for (uint32_t j = 0; j < n; ++j) {
+    if (!sel[j]) continue;
+    sign *= g.w[g.off[j]] < 0 ? -1.0 : 1.0;
+    for (uint32_t q = 0; q < n; ++q) {
+      ph += kPh[acc[q]][dig[j][q]];
+      acc[q] = kMul[acc[q]][dig[j][q]];
+    }
+  }
+  ph &= 3;
+  if (ph == 1 || ph == 3) return fail(c, QIMAX_EDEVICE, "inconsistent generator phases");
+  *out = sign * (ph == 2 ? -1.0 : 1.0);
+  return QIMAX_OK;
+}
+
+// <P> by projecting a random state onto the common +1 eigenspace prod_j (I + G_j)/2.
+qimax_status expect_state(qimax_ctx* c, const HostGens& g, const std::vector<int>& P, double* out) {
+  const uint32_t n = c->n;
+  if (n > 20) return fail(c, QIMAX_ETOOLARGE, "expect: non-Clifford state with n > 20");
+  const double work = (double)g.key.size() * (double)(1ull << n);
+  if (work > 6.9e10) return fail(c, QIMAX_ETOOLARGE, "expect: too many terms for the projection");
+  using cd = std::complex<double>;
+  const size_t D = (size_t)1 << n;
+  std::vector<cd> v(D), tmp(D);
+  std::mt19937_64 rng(12345);
+  std::normal_distribution<double> nd;
+  for (auto& x : v) x = cd(nd(rng), nd(rng));
+  // Pauli string on a basis state: qubit q is bit (n-1-q)
+  auto apply_pauli = [&](uint64_t key, const std::vector<cd>& src, std::vector<cd>& dst, double wt, bool accumulate) {
+    uint64_t xm = 0, zm = 0;
+    int ny = 0;
+    for (uint32_t q = 0; q < n; ++q) {
+      const int d = digit_of(key, n, q);
+      const uint64_t bit = 1ull << (n - 1 - q);
+      if (d == 1 || d == 2) xm |= bit;
+      if (d == 2 || d == 3) zm |= bit;
+      if (d == 2) ++ny;
+    }
+    static const cd iy[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    const cd ph = iy[ny & 3] * wt;
+    for (size_t i = 0; i < D; ++i) {
+      // P|i> = i^ny (-1)^{popcount(i & zm)} |i ^ xm>
+      const double s = (__builtin_popcountll(i & zm) & 1) ? -1.0 : 1.0;
+      if (accumulate) dst[i ^ xm] += ph * s * src[i];
+      else dst[i ^ xm] = ph * s * src[i];
+    }
+  };
+  for (uint32_t j = 0; j < n; ++j) {
+    std::fill(tmp.begin(), tmp.end(), cd(0, 0));
+    for (uint64_t t = g.off[j]; t < g.off[j + 1]; ++t) apply_pauli(g.key[t], v, tmp, g.w[t], true);
+    double nrm = 0;
+    for (size_t i = 0; i < D; ++i) {
+      v[i] = 0.5 * (v[i] + tmp[i]);
+      nrm += std::norm(v[i]);
+    }
+    if (!(nrm > 1e-250)) return fail(c, QIMAX_EDEVICE, "expect: projection vanished");
+    const double sc = 1.0 / std::sqrt(nrm);
+    for (auto& x : v) x *= sc;
+  }
+  uint64_t pk = 0;
+  for (uint32_t q = 0; q < n; ++q) pk |= (uint64_t)P[q] << (2 * (n - 1 - q));
+  apply_pauli(pk, v, tmp, 1.0, false);
+  cd s(0, 0);
+  for (size_t i = 0; i < D; ++i) s += std::conj(v[i]) * tmp[i];
+  *out = s.real();
+  return QIMAX_OK;
+}
+
+}  // namespace
+
+// ================================================================================ C ABI
+
+extern "C" {
+
+void qimax_default_opts(qimax_opts* o) {
+  if (!o) return;
+  o->precision = 64;
+  o->fp32_merge = 0;
+  o->prune_eps = 0.0;
+  o->mem_cap_bytes = 0;
+  o->hip_stream = nullptr;
+  o->validate = 1;
+  o->device = -1;
+}
+
+qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
+  if (!out) return QIMAX_EINVAL;
+  *out = nullptr;
+  qimax_opts o;
+  qimax_default_opts(&o);
+  if (opts) o = *opts;
+  if (n < 1) { g_create_error = "n must be >= 1"; return QIMAX_EINVAL; }
+  if (n > 32) { g_create_error = "n > 32 is not implemented"; return QIMAX_ETOOLARGE; }
+  if (o.precision != 64 && o.precision != 32) { g_create_error = "precision must be 32 or 64"; return QIMAX_EINVAL; }
+  if (!(o.prune_eps >= 0.0) || !std::isfinite(o.prune_eps)) { g_create_error = "prune_eps must be >= 0"; return QIMAX_EINVAL; }
+  qimax_ctx* c = new (std::nothrow) qimax_ctx;
+  if (!c) return QIMAX_ENOMEM;
+  c->n = n;
+  c->KC = n <= 16 ? 0 : 1;
+  c->kb = c->KC == 0 ? 4 : 8;
+  c->WP = o.precision;
+  c->wb = o.precision == 64 ? 8 : 4;
+  c->fp64_acc = o.fp32_merge ? 1 : 0;
+  c->eps = o.prune_eps;
+  c->cap = o.mem_cap_bytes;
+  c->validate = o.validate;
+  hipError_t e;
+  if (o.device >= 0) {
+    e = hipSetDevice(o.device);
+    if (e != hipSuccess) { g_create_error = hipGetErrorString(e); delete c; return QIMAX_EDEVICE; }
+  }
+  e = hipGetDevice(&c->device);
+  if (e != hipSuccess) { g_create_error = hipGetErrorString(e); delete c; return QIMAX_EDEVICE; }
+  if (o.hip_stream) {
+    c->stream = (hipStream_t)o.hip_stream;
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { g_create_error = hipGetErrorString(e); delete c; return QIMAX_EDEVICE; }
+    c->own_stream = true;
+  }
+  qimax_status s;
+  if ((s = ensure(c, c->keys, n * c->kb, false)) != QIMAX_OK || (s = ensure(c, c->w, n * c->wb, false)) != QIMAX_OK ||
+      (s = ensure(c, c->seg, (n + 1) * 8, false)) != QIMAX_OK || (s = ensure(c, c->err, 256, false)) != QIMAX_OK) {
+    g_create_error = c->last_error;
+    qimax_destroy(c);
+    return s;
+  }
+  e = launch_init(c->KC, c->WP, c->keys.p, c->w.p, (uint64_t*)c->seg.p, n, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    g_create_error = hipGetErrorString(e);
+    qimax_destroy(c);
+    return QIMAX_EDEVICE;
+  }
+  c->h_seg.resize(n + 1);
+  for (uint32_t j = 0; j <= n; ++j) c->h_seg[j] = j;
+  c->T = n;
+  c->st.terms = n;
+  *out = c;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_reset(qimax_ctx* c) {
+  if (!c) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  HIPCHK(c, launch_init(c->KC, c->WP, c->keys.p, c->w.p, (uint64_t*)c->seg.p, c->n, c->stream, &c->prof), "init");
+  for (uint32_t j = 0; j <= c->n; ++j) c->h_seg[j] = j;
+  c->T = c->n;
+  c->st.terms = c->n;
+  c->pending.clear();
+  return QIMAX_OK;
+}
+
+qimax_status qimax_apply_layer(qimax_ctx* c, const qimax_op* ops, size_t n_ops) {
+  if (!c) return QIMAX_EINVAL;
+  if (n_ops && !ops) return fail(c, QIMAX_EINVAL, "ops is NULL");
+  std::vector<HostOp> hops(n_ops);
+  // the paper's partition of the operator list: maximal runs of equal arity
+  int group = 0;
+  for (size_t i = 0; i < n_ops; ++i) {
+    if (i && ops[i].arity != ops[i - 1].arity) ++group;
+    QCHK(check_op_input(c, ops[i], group, hops[i]));
+  }
+  return apply_ops(c, hops);
+}
+
+qimax_status qimax_apply_circuit(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
+                                 const double* theta, size_t m) {
+  if (!c) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  if (m && (!gate || !q0 || !q1)) return fail(c, QIMAX_EINVAL, "instruction arrays are NULL");
+  std::vector<HostOp> ops;
+  QCHK(group_circuit(c, gate, q0, q1, theta, m, ops, nullptr, nullptr));
+  return apply_ops(c, ops);
+}
+
+qimax_status qimax_group_circuit(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
+                                 const double* theta, size_t m, qimax_op* ops, double* ptm_buf, size_t cap,
+                                 size_t* n_ops, size_t* n_u, size_t* n_v) {
+  if (!c || !n_ops) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  if (m && (!gate || !q0 || !q1)) return fail(c, QIMAX_EINVAL, "instruction arrays are NULL");
+  std::vector<HostOp> hops;
+  QCHK(group_circuit(c, gate, q0, q1, theta, m, hops, n_u, n_v));
+  *n_ops = hops.size();
+  if (cap == 0) return QIMAX_OK;
+  if (!ops || !ptm_buf) return fail(c, QIMAX_EINVAL, "ops / ptm_buf is NULL");
+  size_t off = 0;
+  for (size_t i = 0; i < hops.size() && i < cap; ++i) {
+    ops[i].arity = (uint32_t)hops[i].arity;
+    ops[i].q[0] = (uint32_t)hops[i].q0;
+    ops[i].q[1] = (uint32_t)hops[i].q1;
+    std::copy(hops[i].R.begin(), hops[i].R.end(), ptm_buf + off);
+    ops[i].ptm = ptm_buf + off;
+    off += hops[i].R.size();
+  }
+  return QIMAX_OK;
+}
+
+qimax_status qimax_num_terms(qimax_ctx* c, uint64_t* T) {
+  if (!c || !T) return QIMAX_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  *T = c->T;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_get_generators(qimax_ctx* c, uint64_t* gen_off, uint64_t* keys, double* w, size_t cap,
+                                  size_t* T) {
+  if (!c || !T) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  QCHK(flush_pending(c));
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  *T = (size_t)c->T;
+  if (cap < c->T) {
+    if (gen_off) std::copy(c->h_seg.begin(), c->h_seg.end(), gen_off);
+    return QIMAX_OK;
+  }
+  if (!gen_off || (c->T && (!keys || !w))) return fail(c, QIMAX_EINVAL, "output buffers are NULL");
+  HostGens g;
+  QCHK(fetch(c, g));
+  std::copy(g.off.begin(), g.off.end(), gen_off);
+  std::copy(g.key.begin(), g.key.end(), keys);
+  std::copy(g.w.begin(), g.w.end(), w);
+  return QIMAX_OK;
+}
+
+qimax_status qimax_expect(qimax_ctx* c, const char* pauli, double* out) {
+  if (!c || !pauli || !out) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  std::vector<int> P(c->n);
+  for (uint32_t q = 0; q < c->n; ++q) {
+    const char ch = pauli[q];
+    const char* pos = ch ? std::strchr("IXYZ", ch) : nullptr;
+    if (!pos) return fail(c, QIMAX_EINVAL, "pauli must be n letters of IXYZ");
+    P[q] = (int)(pos - "IXYZ");
+  }
+  if (pauli[c->n] != '\0') return fail(c, QIMAX_EINVAL, "pauli must be exactly n letters");
+  HostGens g;
+  QCHK(fetch(c, g));
+  bool single = true;
+  for (uint32_t j = 0; j < c->n; ++j) single &= (g.off[j + 1] - g.off[j]) == 1;
+  bool unit = single;
+  if (single)
+    for (uint32_t j = 0; j < c->n; ++j) unit &= std::fabs(std::fabs(g.w[g.off[j]]) - 1.0) < 1e-6;
+  if (unit) return expect_clifford(c, g, P, out);
+  return expect_state(c, g, P, out);
+}
+
+qimax_status qimax_get_stats(const qimax_ctx* c, qimax_stats* out) {
+  if (!c || !out) return QIMAX_EINVAL;
+  *out = c->st;
+  out->terms = c->T;
+  out->peak_bytes = c->peak_bytes;
+  out->alloc_bytes = c->alloc_bytes;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_profile(qimax_ctx* c, int enable) {
+  if (!c) return QIMAX_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  prof_resolve(&c->prof);
+  if (enable) prof_reset(&c->prof);
+  c->prof.on = enable != 0;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_profile_read(qimax_ctx* c, qimax_kernel_time* out, size_t cap, size_t* n) {
+  if (!c || !n) return QIMAX_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  prof_resolve(&c->prof);
+  size_t k = 0;
+  for (int i = 0; i < kKNum; ++i) {
+    if (!c->prof.launches[i]) continue;
+    if (out && k < cap) {
+      out[k].name = kernel_kind_name(i);
+      out[k].launches = c->prof.launches[i];
+      out[k].total_ms = c->prof.ms[i];
+      out[k].alg_bytes = c->prof.bytes[i];
+    }
+    ++k;
+  }
+  *n = k;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_get_generator_updates(const qimax_ctx* c, uint64_t* out, size_t n) {
+  if (!c || !out || n < c->n) return QIMAX_EINVAL;
+  for (uint32_t j = 0; j < c->n; ++j) out[j] = j < c->gen_updates.size() ? c->gen_updates[j] : 0;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_sync(qimax_ctx* c) {
+  if (!c) return QIMAX_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return QIMAX_OK;
+}
+
+const char* qimax_last_error(const qimax_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->last_error.c_str();
+}
+
+void qimax_destroy(qimax_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->keys, &c->w, &c->seg, &c->pk[0], &c->pk[1], &c->pw[0], &c->pw[1], &c->pseg[0],
+                    &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
+                    &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
+                    &c->blk_off, &c->img_seg, &c->desc, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
+                    &c->gr_idx, &c->gr_off, &c->gr_out};
+  for (DevBuf* b : bufs) dev_free(c, *b);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  prof_destroy(&c->prof);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

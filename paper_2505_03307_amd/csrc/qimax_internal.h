@@ -1,0 +1,165 @@
+// Internal declarations shared by the host runtime (qimax_ctx.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace qimax {
+
+// ---------------------------------------------------------------------------------
+// Operator descriptors as the kernels read them (device memory, uniform per launch).
+//
+// Digits: a key is the base-4 Pauli index; the digit of qubit q sits at bit position
+// pos(q) = 2*(n-1-q). Local index of a two-qubit op = 4*d(q0) + d(q1).
+
+// A signed permutation of the local Pauli basis (a Clifford operator: every column of
+// its PTM holds a single +-1). table byte e for local input index i (i < 16):
+// bits 0..3 output index, bit 4 sign flip. Entries 0..7 in lo, 8..15 in hi.
+struct PermDesc {
+  uint32_t arity;
+  uint32_t pa;  // bit position of q[0]
+  uint32_t pb;  // bit position of q[1] (arity 2)
+  uint32_t pad;
+  uint64_t lo, hi;
+};
+
+// An expanding one-qubit operator: for local digit d, cnt[d] nonzero images with output
+// digit out[d][k] and PTM value val[d][k] (FP64) / valf[d][k] (rounded to FP32).
+struct Exp1Desc {
+  uint32_t pos;
+  uint8_t cnt[4];
+  uint8_t out[4][4];
+  double val[4][4];
+  float valf[4][4];
+};
+
+// An expanding two-qubit operator (same layout over 16 local indices).
+struct Exp2Desc {
+  uint32_t pa, pb;
+  uint8_t cnt[16];
+  uint8_t out[16][16];
+  double val[16][16];
+  float valf[16][16];
+};
+
+// One pass: terms -> [A perms] -> [E expanding ops] -> [B perms] -> images.
+struct PassArgs {
+  const PermDesc* A;
+  const Exp1Desc* E1;
+  const Exp2Desc* E2;
+  const PermDesc* B;
+  uint32_t nA, nE1, nE2, nB;
+};
+
+// Segment-aligned tiling of an array of segments (generators): block b covers
+// [blk_begin[b], blk_end[b]) inside segment blk_seg[b]; segment s owns blocks
+// seg_blk[s] .. seg_blk[s+1]-1.
+struct Tiling {
+  const uint64_t* blk_begin;
+  const uint64_t* blk_end;
+  const uint32_t* blk_seg;
+  const uint32_t* seg_blk;
+  uint32_t n_blocks;
+  uint32_t n_segs;
+};
+
+constexpr int kSortBlock = 256;            // threads per sort / merge block
+constexpr int kSortItems = 16;             // items per thread
+constexpr int kSortTile = kSortBlock * kSortItems;  // elements per tile (4096)
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kExpandBlock = 256;
+constexpr int kExpandItems = 8;
+constexpr int kExpandTile = kExpandBlock * kExpandItems;
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+// Error bits a kernel may raise in the context's device flag word.
+enum : uint32_t {
+  kErrIndex = 1u,      // an index left its buffer (kernel refused to write)
+  kErrFanout = 2u,     // fan-out of a term exceeded the 32-bit range
+  kErrOrder = 4u,      // sorted order violated (debug checks)
+};
+
+
+// ------------------------------------------------------------------------ kernel timing
+// Optional per-kernel timing with HIP events recorded on the launch stream, plus the
+// algorithmic bytes each launch must move (what the roofline is measured against).
+enum KernelKind : int {
+  kKInit, kKCount, kKScan, kKExpand, kKSortHist, kKSortScatter, kKMergeCount, kKMergeWrite, kKCompose, kKNum
+};
+const char* kernel_kind_name(int k);
+
+struct Prof {
+  bool on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  uint64_t launches[kKNum] = {};
+  double ms[kKNum] = {};
+  double bytes[kKNum] = {};
+};
+hipEvent_t prof_begin(Prof* p, hipStream_t s);
+void prof_end(Prof* p, hipStream_t s, hipEvent_t a, int kind, double bytes);
+void prof_resolve(Prof* p);  // after the stream has been synchronised
+void prof_reset(Prof* p);
+void prof_destroy(Prof* p);
+
+// ----------------------------------------------------------------------------- launchers
+// KC: key class (0: uint32 keys, n <= 16; 1: uint64 keys, n <= 32).
+// WP: weight precision (64 or 32).
+
+hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, uint32_t n,
+                       hipStream_t s, Prof* prof = nullptr);
+
+hipError_t launch_count(int KC, const void* keys, uint64_t T, const PassArgs& pa, uint32_t* cnt,
+                        uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+
+// out[i] = exclusive prefix sum of in[0..i-1] for i in [0, N]; out has N+1 entries.
+// tmp must hold scan_tmp_words(N) uint64 words.
+size_t scan_tmp_words(uint64_t N);
+hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t N, uint64_t* tmp,
+                           hipStream_t s, Prof* prof = nullptr);
+hipError_t launch_scan_u64(const uint64_t* in, uint64_t* out, uint64_t N, uint64_t* tmp,
+                           hipStream_t s, Prof* prof = nullptr);
+
+// dst[s] = src_off[idx[s]] for s in [0, S]
+hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint64_t* dst,
+                             uint32_t S1, hipStream_t s, Prof* prof = nullptr);
+
+hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in,
+                         const uint64_t* off, uint64_t T_img, const PassArgs& pa, void* keys_out,
+                         void* w_out, uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+
+// One LSD radix pass over digit `shift` of every segment, stable, segment-local.
+// hist must hold kRadix * n_blocks uint64 words; tmp scan_tmp_words(kRadix * n_blocks).
+hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_in, void* keys_out,
+                            void* w_out, uint64_t T, uint32_t shift, const Tiling& tl,
+                            uint64_t* hist, uint64_t* hist_off, uint64_t* tmp, uint32_t* err,
+                            hipStream_t s, Prof* prof = nullptr);
+
+// Segmented sum of equal adjacent keys; keeps sums with |w| > thr (thr < 0 keeps
+// everything non-zero); compacts. seg_off_out[s] for s in [0, n_segs].
+// blk_cnt / blk_off must hold n_blocks (+1) words.
+hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in,
+                        uint64_t T, const Tiling& tl, double thr, void* keys_out, void* w_out,
+                        uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
+                        uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+
+// Weights to FP64 (readout).
+hipError_t launch_weights_to_f64(int WP, const void* w, double* out, uint64_t T, hipStream_t s, Prof* prof = nullptr);
+
+// Grouping pass: compose chains of one-qubit gates into 4x4 PTMs (R[out][in], FP64).
+// chain c covers gate indices idx[chain_off[c] .. chain_off[c+1]-1] in application order.
+hipError_t launch_compose_ptm(const uint8_t* gate, const double* theta, const uint32_t* idx,
+                              const uint32_t* chain_off, uint32_t n_chains, double* ptm_out,
+                              hipStream_t s, Prof* prof = nullptr);
+
+}  // namespace qimax

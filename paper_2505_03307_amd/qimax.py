@@ -1,0 +1,253 @@
+"""Thin Python binding of libqimax.so (argument marshalling only).
+
+Every step of the propagation runs in the HIP library; this module converts numpy
+arrays to pointers and status codes to exceptions. It never falls back to any other
+implementation: if the library is not built, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqimax.so")
+
+STATUS = {0: "QIMAX_OK", -1: "QIMAX_EINVAL", -2: "QIMAX_ENOMEM", -3: "QIMAX_EDEVICE",
+          -4: "QIMAX_ETOOLARGE", -5: "QIMAX_ESTATE"}
+
+
+class QimaxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("fp32_merge", ctypes.c_int), ("prune_eps", ctypes.c_double),
+                ("mem_cap_bytes", ctypes.c_size_t), ("hip_stream", ctypes.c_void_p), ("validate", ctypes.c_int),
+                ("device", ctypes.c_int)]
+
+
+class Op(ctypes.Structure):
+    _fields_ = [("arity", ctypes.c_uint32), ("q", ctypes.c_uint32 * 2), ("ptm", ctypes.POINTER(ctypes.c_double))]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in
+                ("terms", "passes", "term_updates", "images", "sort_elems", "peak_bytes", "alloc_bytes")]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
+
+
+EXPORTS = ["qimax_default_opts", "qimax_create", "qimax_reset", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
+           "qimax_num_terms", "qimax_get_generators", "qimax_expect", "qimax_get_stats", "qimax_sync",
+           "qimax_profile", "qimax_profile_read", "qimax_last_error", "qimax_destroy"]
+
+_lib = None
+
+
+def load():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    lib.qimax_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.qimax_default_opts.restype = None
+    lib.qimax_create.argtypes = [ctypes.c_uint32, ctypes.POINTER(Opts), ctypes.POINTER(P)]
+    lib.qimax_reset.argtypes = [P]
+    lib.qimax_get_generator_updates.argtypes = [P, u64p, ctypes.c_size_t]
+    lib.qimax_apply_layer.argtypes = [P, ctypes.POINTER(Op), ctypes.c_size_t]
+    lib.qimax_apply_circuit.argtypes = [P, u8p, u32p, u32p, dp, ctypes.c_size_t]
+    lib.qimax_group_circuit.argtypes = [P, u8p, u32p, u32p, dp, ctypes.c_size_t, ctypes.POINTER(Op), dp,
+                                        ctypes.c_size_t, szp, szp, szp]
+    lib.qimax_num_terms.argtypes = [P, u64p]
+    lib.qimax_get_generators.argtypes = [P, u64p, u64p, dp, ctypes.c_size_t, szp]
+    lib.qimax_expect.argtypes = [P, ctypes.c_char_p, dp]
+    lib.qimax_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.qimax_sync.argtypes = [P]
+    lib.qimax_profile.argtypes = [P, ctypes.c_int]
+    lib.qimax_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_size_t, szp]
+    lib.qimax_last_error.argtypes = [P]
+    lib.qimax_last_error.restype = ctypes.c_char_p
+    lib.qimax_destroy.argtypes = [P]
+    lib.qimax_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("qimax_default_opts", "qimax_last_error", "qimax_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _instr(circuit_or_arrays):
+    c = circuit_or_arrays
+    if isinstance(c, tuple):
+        g, a, b, t = c
+    else:
+        g, a, b, t = c.gate, c.q0, c.q1, c.theta
+    return (np.ascontiguousarray(g, dtype=np.uint8), np.ascontiguousarray(a, dtype=np.uint32),
+            np.ascontiguousarray(b, dtype=np.uint32), np.ascontiguousarray(t, dtype=np.float64))
+
+
+class Simulator:
+    """The n generators of |0^n> held on the GPU (one qimax context)."""
+
+    def __init__(self, n: int, precision: int = 64, fp32_merge: int = 0, prune_eps: float = 0.0,
+                 mem_cap_bytes: int = 0, stream: int | None = None, validate: bool = True, device: int = -1):
+        lib = load()
+        o = Opts()
+        lib.qimax_default_opts(ctypes.byref(o))
+        o.precision, o.fp32_merge, o.prune_eps = int(precision), int(fp32_merge), float(prune_eps)
+        o.mem_cap_bytes, o.validate, o.device = int(mem_cap_bytes), int(bool(validate)), int(device)
+        o.hip_stream = stream
+        h = ctypes.c_void_p()
+        st = lib.qimax_create(int(n), ctypes.byref(o), ctypes.byref(h))
+        if st != 0:
+            raise QimaxError(st, lib.qimax_last_error(None).decode())
+        self._h = h
+        self.n = n
+        self.precision = precision
+
+    # -------------------------------------------------------------------------- plumbing
+    def _check(self, st: int):
+        if st != 0:
+            raise QimaxError(st, load().qimax_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().qimax_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------------ propagation
+    def reset(self):
+        """Back to Z_0 .. Z_{n-1}, keeping the device buffers."""
+        self._check(load().qimax_reset(self._h))
+        return self
+
+    def apply_circuit(self, circuit_or_arrays):
+        g, a, b, t = _instr(circuit_or_arrays)
+        self._check(load().qimax_apply_circuit(self._h, _p(g, ctypes.c_uint8), _p(a, ctypes.c_uint32),
+                                               _p(b, ctypes.c_uint32), _p(t, ctypes.c_double), g.size))
+        return self
+
+    def run(self, circuit):
+        """Every layer of a workloads.Circuit, one apply call per layer."""
+        for a, b in circuit.layers():
+            self.apply_circuit((circuit.gate[a:b], circuit.q0[a:b], circuit.q1[a:b], circuit.theta[a:b]))
+        return self
+
+    def apply_layer(self, ops):
+        """ops: sequence of (qubits, R) with qubits an int or a pair and R 4x4 / 16x16 (R[out][in])."""
+        arr = (Op * max(len(ops), 1))()
+        keep = []
+        for i, (qs, R) in enumerate(ops):
+            qs = (qs,) if np.isscalar(qs) else tuple(qs)
+            R = np.ascontiguousarray(R, dtype=np.float64)
+            keep.append(R)
+            arr[i].arity = len(qs)
+            arr[i].q[0] = int(qs[0])
+            arr[i].q[1] = int(qs[1]) if len(qs) > 1 else int(qs[0])
+            arr[i].ptm = _p(R, ctypes.c_double)
+        self._check(load().qimax_apply_layer(self._h, arr, len(ops)))
+        return self
+
+    def group(self, circuit_or_arrays):
+        """The grouped operators (qubits, R) and (K, K') of a circuit, without applying it."""
+        g, a, b, t = _instr(circuit_or_arrays)
+        lib = load()
+        n_ops, nu, nv = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        args = (self._h, _p(g, ctypes.c_uint8), _p(a, ctypes.c_uint32), _p(b, ctypes.c_uint32),
+                _p(t, ctypes.c_double), g.size)
+        self._check(lib.qimax_group_circuit(*args, None, None, 0, ctypes.byref(n_ops), ctypes.byref(nu),
+                                            ctypes.byref(nv)))
+        cap = n_ops.value
+        ops = (Op * max(cap, 1))()
+        buf = np.zeros(256 * max(cap, 1), dtype=np.float64)
+        self._check(lib.qimax_group_circuit(*args, ops, _p(buf, ctypes.c_double), cap, ctypes.byref(n_ops),
+                                            ctypes.byref(nu), ctypes.byref(nv)))
+        out, off = [], 0
+        for i in range(cap):
+            d = 4 if ops[i].arity == 1 else 16
+            R = buf[off:off + d * d].reshape(d, d).copy()
+            off += d * d
+            qs = (ops[i].q[0],) if ops[i].arity == 1 else (ops[i].q[0], ops[i].q[1])
+            out.append((qs, R))
+        return out, nu.value, nv.value
+
+    # ---------------------------------------------------------------------------- readout
+    def num_terms(self) -> int:
+        T = ctypes.c_uint64()
+        self._check(load().qimax_num_terms(self._h, ctypes.byref(T)))
+        return T.value
+
+    def generators(self):
+        """(gen_off [n+1], keys [T, W] uint64 paper-index words, weights [T] float64)."""
+        lib = load()
+        T = ctypes.c_size_t()
+        self._check(lib.qimax_get_generators(self._h, None, None, None, 0, ctypes.byref(T)))
+        W = 1 if self.n <= 32 else 2
+        off = np.zeros(self.n + 1, dtype=np.uint64)
+        keys = np.zeros((max(T.value, 1), W), dtype=np.uint64)
+        w = np.zeros(max(T.value, 1), dtype=np.float64)
+        self._check(lib.qimax_get_generators(self._h, _p(off, ctypes.c_uint64), _p(keys, ctypes.c_uint64),
+                                             _p(w, ctypes.c_double), T.value, ctypes.byref(T)))
+        return off, keys[:T.value], w[:T.value]
+
+    def expect(self, pauli: str) -> float:
+        out = ctypes.c_double()
+        self._check(load().qimax_expect(self._h, pauli.encode(), ctypes.byref(out)))
+        return out.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(load().qimax_get_stats(self._h, ctypes.byref(s)))
+        return {k: int(getattr(s, k)) for k, _ in Stats._fields_}
+
+    def generator_updates(self) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.uint64)
+        self._check(load().qimax_get_generator_updates(self._h, _p(out, ctypes.c_uint64), self.n))
+        return out
+
+    def sync(self):
+        self._check(load().qimax_sync(self._h))
+
+    def profile(self, enable: bool):
+        self._check(load().qimax_profile(self._h, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        lib = load()
+        arr = (KernelTime * 32)()
+        n = ctypes.c_size_t()
+        self._check(lib.qimax_profile_read(self._h, arr, 32, ctypes.byref(n)))
+        return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
+                                        "alg_bytes": float(arr[i].alg_bytes)} for i in range(n.value)}

@@ -1,0 +1,79 @@
+"""GPU-vs-oracle comparison contract (test helper).
+
+FP64: on the significant set K_tau = {keys with |w| > tau}, tau = 1e-12, keys must match
+bit for bit (and so must |K_tau|), weights within `tol`. Residue keys with |w| <= tau may
+appear on either side (summation order differs between the two implementations); they are
+counted. With raw_exact=True the complete key sets must be identical.
+FP32 vs FP64: per generator ||w32 - w64||_2 / ||w64||_2 <= rel on the union of keys.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from _keys import xz_to_index
+
+
+def oracle_arrays(o, n):
+    """(gen_off, keys [T, W], w) from an oracle state, keys as paper-index words."""
+    offs, ks, ws = [0], [], []
+    for g in range(o.num_gens):
+        x, z, w = o.read(g)
+        ks.append(xz_to_index(x, z, n))
+        ws.append(w)
+        offs.append(offs[-1] + len(w))
+    W = 1 if n <= 32 else 2
+    keys = np.concatenate(ks) if ks else np.zeros((0, W), np.uint64)
+    return np.array(offs, dtype=np.uint64), keys, (np.concatenate(ws) if ws else np.zeros(0))
+
+
+def compare_fp64(gpu, ref, tau=1e-12, tol=1e-12, raw_exact=False, gens=None, label=""):
+    """gpu, ref: (gen_off, keys, w). gens: generator ids of ref's slots (None = all)."""
+    g_off, g_keys, g_w = gpu
+    r_off, r_keys, r_w = ref
+    n_ref = len(r_off) - 1
+    gens = list(range(n_ref)) if gens is None else list(gens)
+    residues = 0
+    worst = 0.0
+    for slot, j in enumerate(gens):
+        ga, gb = int(g_off[j]), int(g_off[j + 1])
+        ra, rb = int(r_off[slot]), int(r_off[slot + 1])
+        gk, gw = g_keys[ga:gb], g_w[ga:gb]
+        rk, rw = r_keys[ra:rb], r_w[ra:rb]
+        if raw_exact:
+            assert gk.shape == rk.shape, f"{label} gen {j}: {gk.shape[0]} vs {rk.shape[0]} terms"
+            assert np.array_equal(gk, rk), f"{label} gen {j}: raw key sets differ"
+        gm = np.abs(gw) > tau
+        rm = np.abs(rw) > tau
+        residues += int((~gm).sum() + (~rm).sum())
+        gk_s, rk_s = gk[gm], rk[rm]
+        assert gk_s.shape == rk_s.shape, f"{label} gen {j}: |K_tau| {gk_s.shape[0]} vs {rk_s.shape[0]}"
+        assert np.array_equal(gk_s, rk_s), f"{label} gen {j}: significant keys differ"
+        if gk_s.shape[0]:
+            d = float(np.max(np.abs(gw[gm] - rw[rm])))
+            worst = max(worst, d)
+            assert d <= tol, f"{label} gen {j}: max |dw| = {d:.3e} > {tol:.1e}"
+    return {"residues": residues, "max_abs_dw": worst}
+
+
+def _key_rows(keys):
+    k = np.ascontiguousarray(keys)
+    return k.view(np.dtype((np.void, k.dtype.itemsize * k.shape[1]))).reshape(-1)
+
+
+def fp32_relative_errors(g32, g64):
+    """Per generator ||w32 - w64||_2 / ||w64||_2 over the union of keys, and the max |dw|."""
+    o32, k32, w32 = g32
+    o64, k64, w64 = g64
+    rel, mx = [], 0.0
+    for j in range(len(o64) - 1):
+        a = _key_rows(k32[int(o32[j]):int(o32[j + 1])]); wa = w32[int(o32[j]):int(o32[j + 1])]
+        b = _key_rows(k64[int(o64[j]):int(o64[j + 1])]); wb = w64[int(o64[j]):int(o64[j + 1])]
+        allk = np.union1d(a, b)
+        va = np.zeros(allk.shape[0]); vb = np.zeros(allk.shape[0])
+        va[np.searchsorted(allk, a)] = wa
+        vb[np.searchsorted(allk, b)] = wb
+        nrm = float(np.linalg.norm(vb))
+        rel.append(float(np.linalg.norm(va - vb)) / (nrm if nrm > 0 else 1.0))
+        if allk.shape[0]:
+            mx = max(mx, float(np.max(np.abs(va - vb))))
+    return np.array(rel), mx
