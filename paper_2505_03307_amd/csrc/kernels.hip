@@ -40,6 +40,52 @@ __device__ __forceinline__ K apply_perm(K key, const PermDesc& p, uint32_t& neg)
   return key;
 }
 
+// Phase exponent (mod 4) of the product a*b of two Pauli strings given as digit keys:
+// per qubit XY = iZ, YZ = iX, ZX = iY (+1) and the reverse orders (-1).
+template <typename K>
+__device__ __forceinline__ uint32_t product_phase(K a, K b) {
+  constexpr K kEven = (K)0x5555555555555555ull;
+  const K al = a & kEven, ah = (a >> 1) & kEven;
+  const K bl = b & kEven, bh = (b >> 1) & kEven;
+  const K xa = al & ~ah, ya = ah & ~al, za = ah & al;
+  const K xb = bl & ~bh, yb = bh & ~bl, zb = bh & bl;
+  const K plus = (xa & yb) | (ya & zb) | (za & xb);
+  const K minus = (xa & zb) | (ya & xb) | (za & yb);
+  int p, m;
+  if constexpr (sizeof(K) == 8) { p = __popcll(plus); m = __popcll(minus); }
+  else { p = __popc(plus); m = __popc(minus); }
+  return (uint32_t)(p - m) & 3u;
+}
+
+// Image of a key under a compiled Clifford chain (tables staged in LDS by the caller).
+template <typename K>
+__device__ __forceinline__ K apply_table(K key, const K* __restrict__ tk, const uint8_t* __restrict__ tn,
+                                         uint32_t& neg) {
+  K acc = 0;
+  uint32_t ph = 0;
+#pragma unroll
+  for (int k = 0; k < (int)sizeof(K); ++k) {
+    const uint32_t b = (uint32_t)(key >> (8 * k)) & 0xFFu;
+    if (b == 0) continue;  // four identities map to identity
+    const K img = tk[k * 256 + b];
+    neg ^= tn[k * 256 + b];
+    ph += product_phase(acc, img);
+    acc ^= img;
+  }
+  neg ^= (ph >> 1) & 1u;  // images commute: the product's phase is +1 or -1
+  return acc;
+}
+
+// Stage a chain table into LDS (all threads of the block take part).
+template <typename K>
+__device__ __forceinline__ void stage_table(const ChainTable& t, K* sk, uint8_t* sn) {
+  const K* gk = (const K*)t.tab_key;
+  for (int i = threadIdx.x; i < (int)sizeof(K) * 256; i += blockDim.x) {
+    sk[i] = gk[i];
+    sn[i] = t.tab_neg[i];
+  }
+}
+
 template <typename K>
 __device__ __forceinline__ uint32_t local2(K key, uint32_t pa, uint32_t pb) {
   return (get_d(key, pa) << 2) | get_d(key, pb);
@@ -95,11 +141,18 @@ __global__ void k_init(K* keys, W* w, uint64_t* seg_off, uint32_t n) {
 template <typename K>
 __global__ void __launch_bounds__(256) k_count(const K* __restrict__ keys, uint64_t T, PassArgs pa,
                                                uint32_t* __restrict__ cnt, uint32_t* err) {
+  __shared__ K tk[sizeof(K) * 256];
+  __shared__ uint8_t tn[sizeof(K) * 256];
+  if (pa.useA) {
+    stage_table(pa.tA, tk, tn);
+    __syncthreads();
+  }
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T) return;
   K key = keys[i];
   uint32_t neg = 0;
-  for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+  if (pa.useA) key = apply_table(key, tk, tn, neg);
+  else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
   uint64_t f = 1;
   for (uint32_t e = 0; e < pa.nE1; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
   for (uint32_t e = 0; e < pa.nE2; ++e) {
@@ -219,10 +272,23 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
          typename WTraits<WP>::W* __restrict__ w_out, uint32_t* err) {
   using W = typename WTraits<WP>::W;
   constexpr int kWin = kExpandTile + 1;
-  __shared__ uint64_t win[kWin];
+  constexpr int kTab = (int)sizeof(K) * 256;
+  // dynamic LDS: offset window, then the chain tables that this pass uses
+  extern __shared__ __align__(16) uint8_t lds[];
+  uint64_t* win = (uint64_t*)lds;
+  uint8_t* cur = lds + kWin * 8;
+  K* tak = (K*)cur;
+  cur += pa.useA ? kTab * sizeof(K) : 0;
+  uint8_t* tan_ = cur;
+  cur += pa.useA ? kTab : 0;
+  K* tbk = (K*)cur;
+  cur += pa.useB ? kTab * sizeof(K) : 0;
+  uint8_t* tbn = cur;
   __shared__ uint64_t bounds[2];
   const uint64_t g0 = (uint64_t)blockIdx.x * kExpandTile;
   if (g0 >= T_img) return;
+  if (pa.useA) stage_table(pa.tA, tak, tan_);
+  if (pa.useB) stage_table(pa.tB, tbk, tbn);
   const uint64_t g1 = min(g0 + (uint64_t)kExpandTile, T_img);
   if (threadIdx.x == 0) {
     const uint64_t plo = upper_bound_u64(off, 0, T_in + 1, g0) - 1;
@@ -262,7 +328,8 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
     K key = keys[p];
     W wv = w[p];
     uint32_t neg = 0;
-    for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+    if (pa.useA) key = apply_table(key, tak, tan_, neg);
+    else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
     uint32_t r = (uint32_t)(g - start);
     for (uint32_t e = 0; e < pa.nE1; ++e) {
       const Exp1Desc& E = pa.E1[e];
@@ -288,7 +355,8 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
       key = set_d(key, E.pb, o & 3u);
       if constexpr (WP == 64) wv *= E.val[in][k]; else wv *= E.valf[in][k];
     }
-    for (uint32_t b = 0; b < pa.nB; ++b) key = apply_perm(key, pa.B[b], neg);
+    if (pa.useB) key = apply_table(key, tbk, tbn, neg);
+    else for (uint32_t b = 0; b < pa.nB; ++b) key = apply_perm(key, pa.B[b], neg);
     if (neg) wv = -wv;
     keys_out[g] = key;
     w_out[g] = wv;
@@ -331,11 +399,32 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_hist(const K* __restrict__ 
   }
 }
 
-template <typename K, typename W>
+// Status words of the single-sweep radix pass: [epoch:16][flag:2][value:46] per (tile, digit).
+constexpr uint64_t kStAgg = 1ull << 46;   // value = this tile's count of the digit
+constexpr uint64_t kStPre = 2ull << 46;   // value = inclusive prefix over the segment's tiles so far
+constexpr uint64_t kStValMask = (1ull << 46) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// The flag and the count share one 64-bit word, so relaxed device-scope atomics suffice: a
+// reader that sees the flag also sees the count, and no other data is published with it.
+__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One stable LSD pass over a segment-aligned tile. kSweep = false: the destination of each
+// (tile, digit) comes from the scanned per-tile histograms (hist_off). kSweep = true: tiles are
+// claimed in order through tile_ctr, each publishes its digit counts and looks back over the
+// earlier tiles of its segment for their prefix (decoupled look-back), and the digit's base
+// within the segment comes from the upfront histogram (base).
+template <typename K, typename W, bool kSweep>
 __global__ void __launch_bounds__(kSortBlock)
 k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __restrict__ keys_out,
                W* __restrict__ w_out, uint64_t T, uint32_t shift, Tiling tl,
-               const uint64_t* __restrict__ hist_off, uint32_t* err) {
+               const uint64_t* __restrict__ hist_off, const uint64_t* __restrict__ base, uint32_t base_stride,
+               uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr, uint64_t epoch, uint32_t* err) {
   constexpr int kWaves = kSortBlock / 64;
   constexpr int kRounds = kSortItems;                 // rounds per wave
   constexpr int kWaveSpan = 64 * kRounds;             // tile elements per wave
@@ -344,8 +433,14 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   __shared__ uint32_t dstart[kRadix];                  // tile-local start of each digit
   __shared__ uint64_t gbase[kRadix];                   // global destination of each digit
   __shared__ uint64_t scan_sh[kSortBlock / 64];
+  __shared__ uint32_t tile_sh;
 
-  const uint32_t b = blockIdx.x;
+  uint32_t b = blockIdx.x;
+  if constexpr (kSweep) {
+    if (threadIdx.x == 0) tile_sh = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    b = tile_sh;
+  }
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
   const uint32_t n_tile = (uint32_t)(end - begin);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -370,31 +465,52 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
       const uint64_t bb = __ballot(on);
       m &= on ? bb : ~bb;
     }
-    uint32_t base = 0;
+    uint32_t bs = 0;
     const int leader = __ffsll((long long)m) - 1;  // lowest lane with this digit
-    if (valid && lane == leader) base = atomicAdd(&wrun[wid][d], (uint32_t)__popcll(m));
-    base = __shfl(base, leader < 0 ? 0 : leader, 64);
-    rank[r] = valid ? base + (uint32_t)__popcll(m & lt) : 0u;
+    if (valid && lane == leader) bs = atomicAdd(&wrun[wid][d], (uint32_t)__popcll(m));
+    bs = __shfl(bs, leader < 0 ? 0 : leader, 64);
+    rank[r] = valid ? bs + (uint32_t)__popcll(m & lt) : 0u;
   }
   __syncthreads();
   // per-digit totals of the tile, wave prefixes, digit starts
   uint32_t tile_cnt = 0;
-  {
-    const int d = threadIdx.x;  // kSortBlock == kRadix
+  const int d = threadIdx.x;  // kSortBlock == kRadix
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = wrun[w][d];
-      wrun[w][d] = tile_cnt;  // becomes the wave prefix
-      tile_cnt += c;
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t c = wrun[w][d];
+    wrun[w][d] = tile_cnt;  // becomes the wave prefix
+    tile_cnt += c;
+  }
+  if constexpr (kSweep) {
+    // publish this tile's count, then collect the prefix of the earlier tiles of the segment
+    uint64_t* my = status + (uint64_t)b * kRadix + d;
+    const uint32_t s = tl.blk_seg[b];
+    const uint32_t first = tl.seg_blk[s];
+    const uint64_t ep = epoch << 48;
+    st_store(my, ep | (b == first ? kStPre : kStAgg) | tile_cnt);
+    uint64_t excl = 0;
+    if (b != first) {
+      uint32_t t = b - 1;
+      uint32_t spins = 0;
+      while (true) {
+        const uint64_t v = st_load(status + (uint64_t)t * kRadix + d);
+        const bool ready = (v >> 48) == epoch && (v & (kStAgg | kStPre));
+        if (!ready) {
+          if (++spins > kSpinLimit) { atomicOr(err, kErrSpin); break; }
+          continue;
+        }
+        excl += v & kStValMask;
+        if ((v & kStPre) || t == first) break;
+        --t;
+      }
+      st_store(my, ep | kStPre | (excl + tile_cnt));
     }
+    gbase[d] = base[(uint64_t)s * base_stride + d] + excl;
   }
   uint64_t tot;
   const uint64_t ds = block_excl_scan<kSortBlock>(tile_cnt, scan_sh, &tot);
-  {
-    const int d = threadIdx.x;
-    dstart[d] = (uint32_t)ds;
-    gbase[d] = tile_cnt ? hist_off[hist_pos(tl, b, d)] : 0;
-  }
+  dstart[d] = (uint32_t)ds;
+  if constexpr (!kSweep) gbase[d] = tile_cnt ? hist_off[hist_pos(tl, b, d)] : 0;
   __syncthreads();
   // stage keys at their tile-local sorted positions
   uint32_t pos[kRounds];
@@ -402,8 +518,8 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t li = wid * kWaveSpan + r * 64 + lane;
     if (li < n_tile) {
-      const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
-      pos[r] = dstart[d] + wrun[wid][d] + rank[r];
+      const uint32_t dd = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+      pos[r] = dstart[dd] + wrun[wid][dd] + rank[r];
       if (pos[r] < (uint32_t)kSortTile) stage[pos[r]] = (uint64_t)key[r];
       else atomicOr(err, kErrIndex);
     } else {
@@ -418,11 +534,11 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
     const uint32_t j = r * kSortBlock + threadIdx.x;
     outd[r] = 0xFFFFFFFFu;
     if (j < n_tile) {
-      const K k = (K)stage[j];
-      const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
-      outd[r] = d;
-      const uint64_t dst = gbase[d] + (j - dstart[d]);
-      if (dst < T) keys_out[dst] = k; else atomicOr(err, kErrIndex);
+      const K kk = (K)stage[j];
+      const uint32_t dd = (uint32_t)(kk >> shift) & (kRadix - 1);
+      outd[r] = dd;
+      const uint64_t dst = gbase[dd] + (j - dstart[dd]);
+      if (dst < T) keys_out[dst] = kk; else atomicOr(err, kErrIndex);
     }
   }
   __syncthreads();
@@ -438,14 +554,65 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t j = r * kSortBlock + threadIdx.x;
     if (j < n_tile) {
-      const uint32_t d = outd[r];
-      const uint64_t dst = gbase[d] + (j - dstart[d]);
+      const uint32_t dd = outd[r];
+      const uint64_t dst = gbase[dd] + (j - dstart[dd]);
       W v;
       if constexpr (sizeof(W) == 8) v = __longlong_as_double((long long)stage[j]);
       else v = __uint_as_float((uint32_t)stage[j]);
       if (dst < T) w_out[dst] = v;
     }
   }
+}
+
+// Digit histograms of every radix pass at once, per segment: ghist[(s*n_pass + p)*256 + d].
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict__ keys, Tiling tl, uint32_t n_pass,
+                                                             uint32_t* __restrict__ ghist) {
+  constexpr int kWaves = kSortBlock / 64;
+  constexpr int kMaxPass = (int)sizeof(K);
+  __shared__ uint32_t h[kWaves][kMaxPass][kRadix];
+  const int wid = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < kWaves * kMaxPass * kRadix; i += kSortBlock) (&h[0][0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t b = blockIdx.x;
+  const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
+  for (uint64_t i = begin + threadIdx.x; i < end; i += kSortBlock) {
+    const K key = keys[i];
+    for (uint32_t p = 0; p < n_pass; ++p) atomicAdd(&h[wid][p][(uint32_t)(key >> (8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+  const uint32_t s = tl.blk_seg[b];
+  for (uint32_t i = threadIdx.x; i < n_pass * kRadix; i += kSortBlock) {
+    const uint32_t p = i / kRadix, dd = i % kRadix;
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += h[w][p][dd];
+    if (c) atomicAdd(&ghist[((uint64_t)s * n_pass + p) * kRadix + dd], c);
+  }
+}
+
+// base[(s*n_pass + p)*256 + d] = seg_off[s] + (elements of segment s with a smaller digit in pass p);
+// one block per (segment, pass).
+__global__ void __launch_bounds__(kSortBlock) k_sort_bases(const uint32_t* __restrict__ ghist,
+                                                           const uint64_t* __restrict__ seg_off, uint32_t n_pass,
+                                                           uint64_t* __restrict__ base) {
+  __shared__ uint64_t sh[kSortBlock / 64];
+  const uint32_t sp = blockIdx.x;  // s * n_pass + p
+  const uint32_t s = sp / n_pass;
+  const uint64_t v = ghist[(uint64_t)sp * kRadix + threadIdx.x];
+  uint64_t tot;
+  const uint64_t ex = block_excl_scan<kSortBlock>(v, sh, &tot);
+  base[(uint64_t)sp * kRadix + threadIdx.x] = seg_off[s] + ex;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // ------------------------------------------------------------------------------ merge
@@ -540,6 +707,20 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, double t
       ++o;
     }
   }
+}
+
+// One thread per (byte position, byte value): push that 4-qubit Pauli string through the
+// chain one op at a time.
+template <typename K>
+__global__ void k_build_table(const PermDesc* __restrict__ ops, uint32_t n_ops, K* __restrict__ tab_key,
+                              uint8_t* __restrict__ tab_neg) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= sizeof(K) * 256) return;
+  K key = (K)(i & 255u) << (8 * (i >> 8));
+  uint32_t neg = 0;
+  for (uint32_t o = 0; o < n_ops; ++o) key = apply_perm(key, ops[o], neg);
+  tab_key[i] = key;
+  tab_neg[i] = (uint8_t)neg;
 }
 
 template <int WP>
@@ -749,12 +930,14 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64
   const uint64_t nb = (T_img + kExpandTile - 1) / kExpandTile;
   hipEvent_t ev = prof_begin(prof, s);
   QIMAX_DISPATCH_K(KC, {
+    const size_t tab = sizeof(K) * 256 * (sizeof(K) + 1);
+    const size_t lds = (size_t)(kExpandTile + 1) * 8 + (pa.useA ? tab : 0) + (pa.useB ? tab : 0) + 64;
     if (WP == 64)
-      k_expand<K, 64><<<(uint32_t)nb, kExpandBlock, 0, s>>>((const K*)keys, (const double*)w, T_in, off, T_img,
-                                                             pa, (K*)keys_out, (double*)w_out, err);
+      k_expand<K, 64><<<(uint32_t)nb, kExpandBlock, lds, s>>>((const K*)keys, (const double*)w, T_in, off, T_img,
+                                                               pa, (K*)keys_out, (double*)w_out, err);
     else
-      k_expand<K, 32><<<(uint32_t)nb, kExpandBlock, 0, s>>>((const K*)keys, (const float*)w, T_in, off, T_img,
-                                                             pa, (K*)keys_out, (float*)w_out, err);
+      k_expand<K, 32><<<(uint32_t)nb, kExpandBlock, lds, s>>>((const K*)keys, (const float*)w, T_in, off, T_img,
+                                                               pa, (K*)keys_out, (float*)w_out, err);
   });
   const double per = (KC == 0 ? 4 : 8) + (WP == 64 ? 8 : 4);
   prof_end(prof, s, ev, kKExpand, per * (double)(T_in + T_img) + 8.0 * (double)T_in);
@@ -775,13 +958,56 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
     if (e != hipSuccess) return e;
     ev = prof_begin(prof, s);
     if (WP == 64)
-      k_sort_scatter<K, double><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const double*)w_in, (K*)keys_out, (double*)w_out, T, shift, tl, hist_off, err);
+      k_sort_scatter<K, double, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
+          (const K*)keys_in, (const double*)w_in, (K*)keys_out, (double*)w_out, T, shift, tl, hist_off, nullptr, 0,
+          nullptr, nullptr, 0, err);
     else
-      k_sort_scatter<K, float><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const float*)w_in, (K*)keys_out, (float*)w_out, T, shift, tl, hist_off, err);
+      k_sort_scatter<K, float, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
+          (const K*)keys_in, (const float*)w_in, (K*)keys_out, (float*)w_out, T, shift, tl, hist_off, nullptr, 0,
+          nullptr, nullptr, 0, err);
     prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[2], uint64_t T, uint32_t key_bits,
+                             const Tiling& tl, const uint64_t* seg_off, uint32_t* ghist, uint64_t* base,
+                             uint64_t* status, uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err, int* cur,
+                             hipStream_t s, Prof* prof) {
+  *cur = 0;
+  if (T == 0 || tl.n_blocks == 0) return hipSuccess;
+  const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
+  const uint64_t nh = (uint64_t)tl.n_segs * n_pass * kRadix;
+  const double kb = KC == 0 ? 4 : 8, wb = WP == 64 ? 8 : 4;
+  k_fill_u32<<<grid_for(nh, 256), 256, 0, s>>>(ghist, nh, 0u);
+  k_fill_u32<<<1, 64, 0, s>>>(tile_ctr, n_pass, 0u);
+  QIMAX_DISPATCH_K(KC, {
+    hipEvent_t ev = prof_begin(prof, s);
+    k_sort_upsweep<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys[0], tl, n_pass, ghist);
+    prof_end(prof, s, ev, kKSortHist, kb * (double)T);
+    k_sort_bases<<<tl.n_segs * n_pass, kSortBlock, 0, s>>>(ghist, seg_off, n_pass, base);
+    for (uint32_t p = 0; p < n_pass; ++p) {
+      *epoch += 1;  // the caller keeps *epoch + n_pass below 2^16 (clearing status on wrap)
+      ev = prof_begin(prof, s);
+      const int c = *cur;
+      if (WP == 64)
+        k_sort_scatter<K, double, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
+            (const K*)keys[c], (const double*)w[c], (K*)keys[c ^ 1], (double*)w[c ^ 1], T, 8u * p, tl, nullptr,
+            base + (uint64_t)p * kRadix, n_pass * kRadix, status, tile_ctr + p, *epoch, err);
+      else
+        k_sort_scatter<K, float, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
+            (const K*)keys[c], (const float*)w[c], (K*)keys[c ^ 1], (float*)w[c ^ 1], T, 8u * p, tl, nullptr,
+            base + (uint64_t)p * kRadix, n_pass * kRadix, status, tile_ctr + p, *epoch, err);
+      prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T);
+      *cur ^= 1;
+    }
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_fill_u64<<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
   return hipGetLastError();
 }
 
@@ -824,6 +1050,15 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
     prof_end(prof, s, ev, kKMergeWrite, (kb + wb) * (double)T);
   });
   k_gather_u64_by_u32<<<grid_for(tl.n_segs + 1, 64), 64, 0, s>>>(blk_off, tl.seg_blk, seg_off_out, tl.n_segs + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_table(int KC, const PermDesc* ops, uint32_t n_ops, void* tab_key, uint8_t* tab_neg,
+                              hipStream_t s, Prof* prof) {
+  (void)prof;
+  QIMAX_DISPATCH_K(KC, {
+    k_build_table<K><<<(uint32_t)(sizeof(K) * 256 / 256), 256, 0, s>>>(ops, n_ops, (K*)tab_key, tab_neg);
+  });
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <random>
@@ -33,6 +34,7 @@ struct HostOp {
   int dim = 4;
   int group = 0;
   bool perm = false;
+  bool conj = false;  // a signed permutation that is a conjugation by a unitary (multiplicative)
   uint64_t mask = 0;  // wires touched
   std::vector<double> R;  // dim*dim
 };
@@ -131,6 +133,51 @@ bool is_valid_ptm(const std::vector<double>& R, int dim, double tol) {
   return true;
 }
 
+// single-qubit Pauli products: sigma_a sigma_b = i^kPh[a][b] sigma_{kMul[a][b]}
+const int kMul[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
+const int kPh[4][4] = {{0, 0, 0, 0}, {0, 0, 1, 3}, {0, 3, 0, 1}, {0, 1, 3, 0}};
+
+// Product of two local Pauli strings of `nq` digits (index 4*d0 + d1 for two digits).
+void local_product(int a, int b, int nq, int* r, int* ph) {
+  *r = 0;
+  *ph = 0;
+  for (int k = nq - 1; k >= 0; --k) {
+    const int da = (a >> (2 * k)) & 3, db = (b >> (2 * k)) & 3;
+    *r |= kMul[da][db] << (2 * k);
+    *ph += kPh[da][db];
+  }
+  *ph &= 3;
+}
+
+// A signed permutation PTM that maps products to products (with phases) is a conjugation
+// by a unitary, so its action on a whole Pauli string is the product of its actions on
+// any split of the string; only such operators may be compiled into chain tables.
+bool is_conjugation(const std::vector<double>& R, int dim) {
+  const int nq = dim == 4 ? 1 : 2;
+  std::vector<int> out(dim), neg(dim);
+  for (int i = 0; i < dim; ++i) {
+    out[i] = -1;
+    for (int r = 0; r < dim; ++r)
+      if (R[r * dim + i] != 0.0) {
+        out[i] = r;
+        neg[i] = R[r * dim + i] < 0;
+      }
+    if (out[i] < 0) return false;
+  }
+  if (out[0] != 0 || neg[0]) return false;
+  for (int a = 0; a < dim; ++a)
+    for (int b = 0; b < dim; ++b) {
+      int r, ph, r2, ph2;
+      local_product(a, b, nq, &r, &ph);
+      local_product(out[a], out[b], nq, &r2, &ph2);
+      if (out[r] != r2) return false;
+      const int lhs = (neg[r] ? 2 : 0) + ph;
+      const int rhs = ((neg[a] ^ neg[b]) ? 2 : 0) + ph2;
+      if ((lhs - rhs) & 3) return false;
+    }
+  return true;
+}
+
 constexpr int kMaxE1 = 64;
 constexpr int kMaxE2 = 8;
 constexpr double kMaxFanout = 2147483647.0;
@@ -162,6 +209,9 @@ struct qimax_ctx {
   DevBuf ik[2], iw[2];
   DevBuf cnt, off, scan_tmp, hist, hist_off, blk_begin, blk_end, blk_seg, seg_blk, blk_cnt, blk_off, img_seg;
   DevBuf desc, err, f64tmp;
+  DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
+  uint64_t epoch = 0;
+  bool classic_sort = false;
   DevBuf gr_gate, gr_theta, gr_idx, gr_off, gr_out;
   uint64_t* pinned = nullptr;  // small pinned host scratch
   size_t pinned_words = 0;
@@ -328,7 +378,19 @@ qimax_status upload_pass(qimax_ctx* c, const Pass& p, PassArgs& pa) {
   const size_t oA = 0, oB = align256(oA + A.size() * sizeof(PermDesc));
   const size_t o1 = align256(oB + B.size() * sizeof(PermDesc));
   const size_t o2 = align256(o1 + E1.size() * sizeof(Exp1Desc));
-  const size_t total = align256(o2 + E2.size() * sizeof(Exp2Desc)) + 256;
+  auto tableable = [](const std::vector<const HostOp*>& v) {
+    if ((int)v.size() < kChainTableMin) return false;
+    for (auto* op : v)
+      if (!op->conj) return false;
+    return true;
+  };
+  const bool useA = tableable(p.A), useB = tableable(p.B);
+  const size_t entries = c->kb * 256;
+  const size_t oTAk = align256(o2 + E2.size() * sizeof(Exp2Desc));
+  const size_t oTAn = align256(oTAk + (useA ? entries * c->kb : 0));
+  const size_t oTBk = align256(oTAn + (useA ? entries : 0));
+  const size_t oTBn = align256(oTBk + (useB ? entries * c->kb : 0));
+  const size_t total = align256(oTBn + (useB ? entries : 0)) + 256;
   QCHK(ensure(c, c->desc, total));
   std::vector<uint8_t>& host = c->stage_desc;
   host.assign(total, 0);
@@ -346,6 +408,14 @@ qimax_status upload_pass(qimax_ctx* c, const Pass& p, PassArgs& pa) {
   pa.nB = (uint32_t)B.size();
   pa.nE1 = (uint32_t)E1.size();
   pa.nE2 = (uint32_t)E2.size();
+  pa.useA = useA;
+  pa.useB = useB;
+  pa.tA = ChainTable{base + oTAk, base + oTAn};
+  pa.tB = ChainTable{base + oTBk, base + oTBn};
+  if (useA)
+    HIPCHK(c, launch_build_table(c->KC, pa.A, pa.nA, base + oTAk, base + oTAn, c->stream, &c->prof), "chain table");
+  if (useB)
+    HIPCHK(c, launch_build_table(c->KC, pa.B, pa.nB, base + oTBk, base + oTBn, c->stream, &c->prof), "chain table");
   return QIMAX_OK;
 }
 
@@ -420,6 +490,7 @@ std::string err_text(uint32_t e) {
   if (e & kErrIndex) s += " index-out-of-range";
   if (e & kErrFanout) s += " fanout-overflow";
   if (e & kErrOrder) s += " order";
+  if (e & kErrSpin) s += " look-back-timeout";
   return s;
 }
 
@@ -461,16 +532,37 @@ qimax_status run_pass(qimax_ctx* c, const Pass& p, const void* k_in, const void*
   Tiling tl{};
   QCHK(upload_tiling(c, ht, tl));
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
-  QCHK(ensure(c, c->hist, hsize * 8));
-  QCHK(ensure(c, c->hist_off, (hsize + 1) * 8));
   QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
   int cur = 0;
   const uint32_t key_bits = 2u * c->n;
-  for (uint32_t shift = 0; shift < key_bits; shift += kRadixBits) {
-    HIPCHK(c, launch_sort_pass(c->KC, c->WP, c->ik[cur].p, c->iw[cur].p, c->ik[cur ^ 1].p, c->iw[cur ^ 1].p, T_img,
-                               shift, tl, (uint64_t*)c->hist.p, (uint64_t*)c->hist_off.p, (uint64_t*)c->scan_tmp.p,
-                               (uint32_t*)c->err.p, c->stream, &c->prof), "sort");
-    cur ^= 1;
+  if (c->classic_sort) {
+    QCHK(ensure(c, c->hist, hsize * 8));
+    QCHK(ensure(c, c->hist_off, (hsize + 1) * 8));
+    for (uint32_t shift = 0; shift < key_bits; shift += kRadixBits) {
+      HIPCHK(c, launch_sort_pass(c->KC, c->WP, c->ik[cur].p, c->iw[cur].p, c->ik[cur ^ 1].p, c->iw[cur ^ 1].p, T_img,
+                                 shift, tl, (uint64_t*)c->hist.p, (uint64_t*)c->hist_off.p, (uint64_t*)c->scan_tmp.p,
+                                 (uint32_t*)c->err.p, c->stream, &c->prof), "sort");
+      cur ^= 1;
+    }
+  } else {
+    const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
+    const uint64_t nh = (uint64_t)S * n_pass * kRadix;
+    QCHK(ensure(c, c->ghist, nh * 4));
+    QCHK(ensure(c, c->sbase, nh * 8));
+    QCHK(ensure(c, c->tile_ctr, 64 * 4));
+    void* old_status = c->sstatus.p;
+    QCHK(ensure(c, c->sstatus, hsize * 8));
+    if (c->sstatus.p != old_status || c->epoch + n_pass >= 0xFFFFull) {
+      // fresh memory or epoch wrap: clear every word so that no stale epoch can match
+      HIPCHK(c, launch_fill_u64((uint64_t*)c->sstatus.p, c->sstatus.bytes / 8, 0ull, c->stream), "clear status");
+      c->epoch = 0;
+    }
+    void* const kk[2] = {c->ik[0].p, c->ik[1].p};
+    void* const ww[2] = {c->iw[0].p, c->iw[1].p};
+    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, tl, (const uint64_t*)c->img_seg.p,
+                                (uint32_t*)c->ghist.p, (uint64_t*)c->sbase.p, (uint64_t*)c->sstatus.p,
+                                (uint32_t*)c->tile_ctr.p, &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof),
+           "sort");
   }
   // segmented reduce + prune + compaction into the pass output slot
   QCHK(ensure(c, c->pk[slot], std::max<uint64_t>(T_img, 1) * eb));
@@ -615,6 +707,7 @@ qimax_status check_op_input(qimax_ctx* c, const qimax_op& in, int group, HostOp&
   if (c->validate && !is_valid_ptm(op.R, op.dim, 1e-12))
     return fail(c, QIMAX_EINVAL, "op ptm is not unital/orthogonal (set validate = 0 to allow)");
   op.perm = is_signed_perm(op.R, op.dim);
+  op.conj = op.perm && is_conjugation(op.R, op.dim);
   return QIMAX_OK;
 }
 
@@ -695,6 +788,7 @@ qimax_status group_circuit(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0
         op.R.assign(gate[i] == QIMAX_GATE_CX ? cx : cz, (gate[i] == QIMAX_GATE_CX ? cx : cz) + 256);
         op.mask = (1ull << op.q0) | (1ull << op.q1);
         op.perm = true;
+        op.conj = true;
         ops.push_back(std::move(op));
       }
     } else {
@@ -704,6 +798,7 @@ qimax_status group_circuit(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0
         op.R.assign(ptm.begin() + ci * 16, ptm.begin() + ci * 16 + 16);
         op.mask = 1ull << op.q0;
         op.perm = is_signed_perm(op.R, 4);
+        op.conj = op.perm && is_conjugation(op.R, 4);
         bool identity = true;
         for (int a = 0; a < 4; ++a)
           for (int b = 0; b < 4; ++b) identity &= op.R[a * 4 + b] == (a == b ? 1.0 : 0.0);
@@ -750,9 +845,6 @@ qimax_status fetch(qimax_ctx* c, HostGens& g) {
 
 int digit_of(uint64_t key, uint32_t n, uint32_t q) { return (int)((key >> (2 * (n - 1 - q))) & 3u); }
 
-// single-qubit Pauli products: sigma_a sigma_b = i^ph[a][b] sigma_{mul[a][b]}
-const int kMul[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
-const int kPh[4][4] = {{0, 0, 0, 0}, {0, 0, 1, 3}, {0, 3, 0, 1}, {0, 1, 3, 0}};
 
 // <P> when every generator is one signed Pauli string: P is +-(a product of generators)
 // or anticommutes with one of them (then <P> = 0). GF(2) elimination over the digits.
@@ -916,6 +1008,10 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
   c->eps = o.prune_eps;
   c->cap = o.mem_cap_bytes;
   c->validate = o.validate;
+  {
+    const char* env = std::getenv("QIMAX_SORT_CLASSIC");
+    c->classic_sort = env && env[0] == '1';
+  }
   hipError_t e;
   if (o.device >= 0) {
     e = hipSetDevice(o.device);
@@ -1119,7 +1215,7 @@ void qimax_destroy(qimax_ctx* c) {
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
                     &c->blk_off, &c->img_seg, &c->desc, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
-                    &c->gr_idx, &c->gr_off, &c->gr_out};
+                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   prof_destroy(&c->prof);

@@ -45,13 +45,26 @@ struct Exp2Desc {
 };
 
 // One pass: terms -> [A perms] -> [E expanding ops] -> [B perms] -> images.
+// A Clifford chain compiled into per-byte tables: byte k of a key holds the digits of four
+// qubits; tab_key[k*256 + b] is the image key of that 4-qubit Pauli string under the chain
+// and tab_neg[k*256 + b] its sign bit. Conjugation is multiplicative, so the image of a
+// whole key is the product of its bytes' images (they commute) with the product's phase.
+struct ChainTable {
+  const void* tab_key;     // K[nbytes * 256]
+  const uint8_t* tab_neg;  // [nbytes * 256]
+};
+
 struct PassArgs {
   const PermDesc* A;
   const Exp1Desc* E1;
   const Exp2Desc* E2;
   const PermDesc* B;
   uint32_t nA, nE1, nE2, nB;
+  ChainTable tA, tB;       // used instead of the op lists when useA / useB is set
+  uint32_t useA, useB;
 };
+
+constexpr int kChainTableMin = 12;  // chains at least this long are compiled into tables
 
 // Segment-aligned tiling of an array of segments (generators): block b covers
 // [blk_begin[b], blk_end[b]) inside segment blk_seg[b]; segment s owns blocks
@@ -82,6 +95,7 @@ enum : uint32_t {
   kErrIndex = 1u,      // an index left its buffer (kernel refused to write)
   kErrFanout = 2u,     // fan-out of a term exceeded the 32-bit range
   kErrOrder = 4u,      // sorted order violated (debug checks)
+  kErrSpin = 8u,       // a look-back wait gave up (bounded spin)
 };
 
 
@@ -145,6 +159,17 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
                             uint64_t* hist, uint64_t* hist_off, uint64_t* tmp, uint32_t* err,
                             hipStream_t s, Prof* prof = nullptr);
 
+// The whole segment-local LSD sort in single-sweep form: one upfront histogram of every
+// digit position, then one decoupled-look-back scatter per digit. keys/w are ping-pong
+// pairs with the input in slot 0; *cur receives the slot holding the sorted result.
+// ghist: n_segs*n_pass*256 u32; base: n_segs*n_pass*256 u64; status: n_blocks*256 u64
+// (zeroed when allocated); tile_ctr: n_pass u32; *epoch is advanced per digit pass.
+hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[2], uint64_t T, uint32_t key_bits,
+                             const Tiling& tl, const uint64_t* seg_off, uint32_t* ghist, uint64_t* base,
+                             uint64_t* status, uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err, int* cur,
+                             hipStream_t s, Prof* prof = nullptr);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+
 // Segmented sum of equal adjacent keys; keeps sums with |w| > thr (thr < 0 keeps
 // everything non-zero); compacts. seg_off_out[s] for s in [0, n_segs].
 // blk_cnt / blk_off must hold n_blocks (+1) words.
@@ -152,6 +177,10 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
                         uint64_t T, const Tiling& tl, double thr, void* keys_out, void* w_out,
                         uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
                         uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+
+// Compile a chain of permutation ops into a ChainTable (nbytes = key bytes).
+hipError_t launch_build_table(int KC, const PermDesc* ops, uint32_t n_ops, void* tab_key, uint8_t* tab_neg,
+                              hipStream_t s, Prof* prof = nullptr);
 
 // Weights to FP64 (readout).
 hipError_t launch_weights_to_f64(int WP, const void* w, double* out, uint64_t T, hipStream_t s, Prof* prof = nullptr);
