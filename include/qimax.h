@@ -162,6 +162,59 @@ typedef struct {
 qimax_status qimax_profile(qimax_ctx* ctx, int enable);
 qimax_status qimax_profile_read(qimax_ctx* ctx, qimax_kernel_time* out, size_t cap, size_t* n);
 
+/* ------------------------------------------------------------------ batches of circuits
+ * A batch holds the generators of many circuits (each with its own n <= 32, layers and
+ * prune threshold) in one device term array. Every qimax_batch_step advances each active
+ * circuit by one propagation pass, all circuits together in one set of kernel launches, so
+ * small circuits share launches instead of paying them one by one (multi-circuit execution
+ * is the paper's stated next step, Sec. VI). Circuits may be submitted at any time; they
+ * join the array at the next step (continuous batching). A finished circuit's generators
+ * are copied to host memory at the end of its last step and are identical to what a
+ * single-circuit context computes for the same instructions: each generator is its own
+ * segment and is never mixed with other segments. */
+typedef struct qimax_batch qimax_batch;
+
+typedef struct {
+  uint32_t n;               /* qubits, 1..32                                              */
+  const uint8_t* gate;      /* instruction arrays as for qimax_apply_circuit (host memory) */
+  const uint32_t* q0;
+  const uint32_t* q1;
+  const double* theta;      /* may be NULL when no gate has a parameter                    */
+  size_t m;
+  const uint64_t* layer_end; /* optional: ends of the layers (prune points); NULL = one layer */
+  size_t n_layers;
+  double prune_eps;         /* as qimax_opts.prune_eps, for this circuit                   */
+} qimax_circuit;
+
+typedef struct {
+  uint64_t queued, active, finished, rounds, terms, term_updates, alloc_bytes, peak_bytes;
+} qimax_batch_info_t;
+
+/* opts: precision, fp32_merge, mem_cap_bytes, hip_stream, device apply to the whole batch
+ * (validate and prune_eps are per circuit). */
+qimax_status qimax_batch_create(const qimax_opts* opts, qimax_batch** out);
+/* Groups and plans the circuit (inputs are copied) and queues it; *id names it. */
+qimax_status qimax_batch_submit(qimax_batch* b, const qimax_circuit* c, uint64_t* id);
+/* Admits queued circuits, then runs one pass of every active circuit. *n_active (may be
+ * NULL) receives the number of circuits still queued or active afterwards. */
+qimax_status qimax_batch_step(qimax_batch* b, size_t* n_active);
+/* Steps until no circuit is queued or active. */
+qimax_status qimax_batch_run(qimax_batch* b);
+/* Ids of circuits finished since the last poll. With cap < count only *n is written. */
+qimax_status qimax_batch_poll(qimax_batch* b, uint64_t* ids, size_t cap, size_t* n);
+/* A finished circuit's generators in the qimax_get_generators format (two-call size query;
+ * a successful full copy releases the circuit). */
+qimax_status qimax_batch_fetch(qimax_batch* b, uint64_t id, uint64_t* gen_off, uint64_t* keys, double* w,
+                               size_t cap, size_t* T);
+qimax_status qimax_batch_info(const qimax_batch* b, qimax_batch_info_t* out);
+/* Term updates attributed to one circuit so far (same definition as qimax_stats). */
+qimax_status qimax_batch_circuit_updates(const qimax_batch* b, uint64_t id, uint64_t* updates);
+/* The batch's internal context, for qimax_profile / qimax_profile_read / qimax_get_stats /
+ * qimax_sync only. */
+qimax_ctx* qimax_batch_context(qimax_batch* b);
+const char* qimax_batch_last_error(const qimax_batch* b);
+void qimax_batch_destroy(qimax_batch* b);
+
 /* Blocks until all work of the context has finished. */
 qimax_status qimax_sync(qimax_ctx* ctx);
 

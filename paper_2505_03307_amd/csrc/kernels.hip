@@ -138,32 +138,39 @@ __global__ void k_init(K* keys, W* w, uint64_t* seg_off, uint32_t n) {
 }
 
 // ----------------------------------------------------------------------- fan-out count
+// One block per segment-aligned tile of input terms; the tile's segment selects the pass
+// of its circuit (pas[seg_entry[segment]]).
 template <typename K>
-__global__ void __launch_bounds__(256) k_count(const K* __restrict__ keys, uint64_t T, PassArgs pa,
-                                               uint32_t* __restrict__ cnt, uint32_t* err) {
+__global__ void __launch_bounds__(256) k_count(const K* __restrict__ keys, Tiling tl, const PassArgs* __restrict__ pas,
+                                               const uint32_t* __restrict__ seg_entry, uint32_t* __restrict__ cnt,
+                                               uint32_t* err) {
   __shared__ K tk[sizeof(K) * 256];
   __shared__ uint8_t tn[sizeof(K) * 256];
+  const uint32_t b = blockIdx.x;
+  const PassArgs pa = pas[seg_entry[tl.blk_seg[b]]];
+  const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
+  if (pa.drop) {
+    for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) cnt[i] = 0u;
+    return;
+  }
   if (pa.useA) {
     stage_table(pa.tA, tk, tn);
     __syncthreads();
   }
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= T) return;
-  K key = keys[i];
-  uint32_t neg = 0;
-  if (pa.useA) key = apply_table(key, tk, tn, neg);
-  else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
-  uint64_t f = 1;
-  for (uint32_t e = 0; e < pa.nE1; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
-  for (uint32_t e = 0; e < pa.nE2; ++e) {
-    f *= pa.E2[e].cnt[local2(key, pa.E2[e].pa, pa.E2[e].pb)];
-    if (f > 0xFFFFFFFFull) break;
+  for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+    K key = keys[i];
+    uint32_t neg = 0;
+    if (pa.useA) key = apply_table(key, tk, tn, neg);
+    else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+    uint64_t f = 1;
+    for (uint32_t e = 0; e < pa.nE1 && f <= 0xFFFFFFFFull; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
+    for (uint32_t e = 0; e < pa.nE2 && f <= 0xFFFFFFFFull; ++e) f *= pa.E2[e].cnt[local2(key, pa.E2[e].pa, pa.E2[e].pb)];
+    if (f > 0xFFFFFFFFull) {
+      atomicOr(err, kErrFanout);
+      f = 0;
+    }
+    cnt[i] = (uint32_t)f;
   }
-  if (f > 0xFFFFFFFFull) {
-    atomicOr(err, kErrFanout);
-    f = 0;
-  }
-  cnt[i] = (uint32_t)f;
 }
 
 // ------------------------------------------------------------------------------ scans
@@ -268,13 +275,16 @@ __device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t* a, uint64_t 
 template <typename K, int WP>
 __global__ void __launch_bounds__(kExpandBlock)
 k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__ w, uint64_t T_in,
-         const uint64_t* __restrict__ off, uint64_t T_img, PassArgs pa, K* __restrict__ keys_out,
+         const uint64_t* __restrict__ off, uint64_t T_img, Tiling tl, const PassArgs* __restrict__ pas,
+         const uint32_t* __restrict__ seg_entry, K* __restrict__ keys_out,
          typename WTraits<WP>::W* __restrict__ w_out, uint32_t* err) {
   using W = typename WTraits<WP>::W;
   constexpr int kWin = kExpandTile + 1;
   constexpr int kTab = (int)sizeof(K) * 256;
   // dynamic LDS: offset window, then the chain tables that this pass uses
   extern __shared__ __align__(16) uint8_t lds[];
+  const uint32_t blk = blockIdx.x;
+  const PassArgs pa = pas[seg_entry[tl.blk_seg[blk]]];
   uint64_t* win = (uint64_t*)lds;
   uint8_t* cur = lds + kWin * 8;
   K* tak = (K*)cur;
@@ -285,11 +295,12 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   cur += pa.useB ? kTab * sizeof(K) : 0;
   uint8_t* tbn = cur;
   __shared__ uint64_t bounds[2];
-  const uint64_t g0 = (uint64_t)blockIdx.x * kExpandTile;
-  if (g0 >= T_img) return;
+  // this block's images: one segment-aligned tile of at most kExpandTile
+  const uint64_t g0 = tl.blk_begin[blk];
+  const uint64_t g1 = min(tl.blk_end[blk], T_img);
+  if (g0 >= g1) return;
   if (pa.useA) stage_table(pa.tA, tak, tan_);
   if (pa.useB) stage_table(pa.tB, tbk, tbn);
-  const uint64_t g1 = min(g0 + (uint64_t)kExpandTile, T_img);
   if (threadIdx.x == 0) {
     const uint64_t plo = upper_bound_u64(off, 0, T_in + 1, g0) - 1;
     const uint64_t phi = upper_bound_u64(off, plo, T_in + 1, g1 - 1) - 1;
@@ -654,14 +665,16 @@ __device__ __forceinline__ W run_sum(const K* __restrict__ keys, const W* __rest
 
 template <typename K, typename W, bool kWrite>
 __global__ void __launch_bounds__(kSortBlock)
-k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, double thr, int fp64_acc,
-        uint32_t* __restrict__ blk_cnt, const uint64_t* __restrict__ blk_off, K* __restrict__ keys_out,
-        W* __restrict__ w_out, uint64_t out_cap, uint32_t* err) {
+k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const PassArgs* __restrict__ pas,
+        const uint32_t* __restrict__ seg_entry, int fp64_acc, uint32_t* __restrict__ blk_cnt,
+        const uint64_t* __restrict__ blk_off, K* __restrict__ keys_out, W* __restrict__ w_out, uint64_t out_cap,
+        uint32_t* err) {
   __shared__ K sk[kSortTile + 1];
   __shared__ uint64_t scan_sh[kSortBlock / 64];
   const uint32_t b = blockIdx.x;
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
   const uint32_t s = tl.blk_seg[b];
+  const double thr = pas[seg_entry[s]].thr;
   const uint64_t seg_begin = tl.blk_begin[tl.seg_blk[s]];
   const uint64_t seg_end = tl.blk_end[tl.seg_blk[s + 1] - 1];
   const uint32_t n_tile = (uint32_t)(end - begin);
@@ -709,18 +722,32 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, double t
   }
 }
 
-// One thread per (byte position, byte value): push that 4-qubit Pauli string through the
-// chain one op at a time.
+// One thread per (job, byte position, byte value): push that 4-qubit Pauli string through
+// the job's chain one op at a time.
 template <typename K>
-__global__ void k_build_table(const PermDesc* __restrict__ ops, uint32_t n_ops, K* __restrict__ tab_key,
-                              uint8_t* __restrict__ tab_neg) {
+__global__ void k_build_tables(const TableJob* __restrict__ jobs) {
+  const TableJob jb = jobs[blockIdx.y];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= sizeof(K) * 256) return;
   K key = (K)(i & 255u) << (8 * (i >> 8));
   uint32_t neg = 0;
-  for (uint32_t o = 0; o < n_ops; ++o) key = apply_perm(key, ops[o], neg);
-  tab_key[i] = key;
-  tab_neg[i] = (uint8_t)neg;
+  for (uint32_t o = 0; o < jb.n_ops; ++o) key = apply_perm(key, jb.ops[o], neg);
+  ((K*)jb.tab_key)[i] = key;
+  jb.tab_neg[i] = (uint8_t)neg;
+}
+
+// Z_j of freshly admitted circuits, written at the end of the term array: for entry c,
+// nq[c] terms starting at dst[c].
+template <typename K, typename W>
+__global__ void k_init_many(K* keys, W* w, const uint32_t* __restrict__ nq, const uint64_t* __restrict__ dst,
+                            uint32_t n_circ) {
+  const uint32_t c = blockIdx.x;
+  if (c >= n_circ) return;
+  const uint32_t n = nq[c];
+  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+    keys[dst[c] + j] = (K)3 << (2u * (n - 1u - j));
+    w[dst[c] + j] = (W)1;
+  }
 }
 
 template <int WP>
@@ -881,11 +908,11 @@ hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, u
   return hipGetLastError();
 }
 
-hipError_t launch_count(int KC, const void* keys, uint64_t T, const PassArgs& pa, uint32_t* cnt, uint32_t* err,
-                        hipStream_t s, Prof* prof) {
-  if (T == 0) return hipSuccess;
+hipError_t launch_count(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
+                        const uint32_t* seg_entry, uint32_t* cnt, uint32_t* err, hipStream_t s, Prof* prof) {
+  if (T == 0 || tl.n_blocks == 0) return hipSuccess;
   hipEvent_t ev = prof_begin(prof, s);
-  QIMAX_DISPATCH_K(KC, { k_count<K><<<grid_for(T, 256), 256, 0, s>>>((const K*)keys, T, pa, cnt, err); });
+  QIMAX_DISPATCH_K(KC, { k_count<K><<<tl.n_blocks, 256, 0, s>>>((const K*)keys, tl, pas, seg_entry, cnt, err); });
   prof_end(prof, s, ev, kKCount, (double)T * ((KC == 0 ? 4 : 8) + 4));
   return hipGetLastError();
 }
@@ -924,20 +951,19 @@ hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint6
 }
 
 hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const uint64_t* off,
-                         uint64_t T_img, const PassArgs& pa, void* keys_out, void* w_out, uint32_t* err,
-                         hipStream_t s, Prof* prof) {
-  if (T_img == 0) return hipSuccess;
-  const uint64_t nb = (T_img + kExpandTile - 1) / kExpandTile;
+                         uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
+                         bool any_tables, void* keys_out, void* w_out, uint32_t* err, hipStream_t s, Prof* prof) {
+  if (T_img == 0 || tl.n_blocks == 0) return hipSuccess;
   hipEvent_t ev = prof_begin(prof, s);
   QIMAX_DISPATCH_K(KC, {
     const size_t tab = sizeof(K) * 256 * (sizeof(K) + 1);
-    const size_t lds = (size_t)(kExpandTile + 1) * 8 + (pa.useA ? tab : 0) + (pa.useB ? tab : 0) + 64;
+    const size_t lds = (size_t)(kExpandTile + 1) * 8 + (any_tables ? 2 * tab : 0) + 64;
     if (WP == 64)
-      k_expand<K, 64><<<(uint32_t)nb, kExpandBlock, lds, s>>>((const K*)keys, (const double*)w, T_in, off, T_img,
-                                                               pa, (K*)keys_out, (double*)w_out, err);
+      k_expand<K, 64><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, (const double*)w, T_in, off, T_img, tl,
+                                                              pas, seg_entry, (K*)keys_out, (double*)w_out, err);
     else
-      k_expand<K, 32><<<(uint32_t)nb, kExpandBlock, lds, s>>>((const K*)keys, (const float*)w, T_in, off, T_img,
-                                                               pa, (K*)keys_out, (float*)w_out, err);
+      k_expand<K, 32><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, (const float*)w, T_in, off, T_img, tl,
+                                                              pas, seg_entry, (K*)keys_out, (float*)w_out, err);
   });
   const double per = (KC == 0 ? 4 : 8) + (WP == 64 ? 8 : 4);
   prof_end(prof, s, ev, kKExpand, per * (double)(T_in + T_img) + 8.0 * (double)T_in);
@@ -1012,9 +1038,9 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
 }
 
 hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, uint64_t T,
-                        const Tiling& tl, double thr, void* keys_out, void* w_out, uint64_t* seg_off_out,
-                        uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp, uint32_t* err, hipStream_t s,
-                        Prof* prof) {
+                        const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out, void* w_out,
+                        uint64_t out_cap, uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
+                        uint32_t* err, hipStream_t s, Prof* prof) {
   if (tl.n_blocks == 0) {
     // no terms at all: every segment offset is zero
     k_zero_one<<<1, 1, 0, s>>>(blk_off);
@@ -1027,10 +1053,12 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
     hipEvent_t ev = prof_begin(prof, s);
     if (WP == 64) {
       k_merge<K, double, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const double*)w_in, tl, thr, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0, err);
+          (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0,
+          err);
     } else {
       k_merge<K, float, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const float*)w_in, tl, thr, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0, err);
+          (const K*)keys_in, (const float*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0,
+          err);
     }
     prof_end(prof, s, ev, kKMergeCount, (kb + wb) * (double)T);
     hipError_t e = scan_impl<uint32_t>(blk_cnt, blk_off, tl.n_blocks, tmp, s, prof);
@@ -1038,26 +1066,33 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
     ev = prof_begin(prof, s);
     if (WP == 64) {
       k_merge<K, double, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const double*)w_in, tl, thr, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
-          (double*)w_out, T, err);
+          (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
+          (double*)w_out, out_cap, err);
     } else {
       k_merge<K, float, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const float*)w_in, tl, thr, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
-          (float*)w_out, T, err);
+          (const K*)keys_in, (const float*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
+          (float*)w_out, out_cap, err);
     }
-    // output size is known only on the device; the read side is counted here and the
-    // written terms are added by the caller once the count is back on the host
+    // the written terms are added by the caller once their count is back on the host
     prof_end(prof, s, ev, kKMergeWrite, (kb + wb) * (double)T);
   });
   k_gather_u64_by_u32<<<grid_for(tl.n_segs + 1, 64), 64, 0, s>>>(blk_off, tl.seg_blk, seg_off_out, tl.n_segs + 1);
   return hipGetLastError();
 }
 
-hipError_t launch_build_table(int KC, const PermDesc* ops, uint32_t n_ops, void* tab_key, uint8_t* tab_neg,
-                              hipStream_t s, Prof* prof) {
+hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hipStream_t s, Prof* prof) {
   (void)prof;
+  if (n_jobs == 0) return hipSuccess;
+  QIMAX_DISPATCH_K(KC, { k_build_tables<K><<<dim3((uint32_t)sizeof(K), n_jobs), 256, 0, s>>>(jobs); });
+  return hipGetLastError();
+}
+
+hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t* nq, const uint64_t* dst,
+                            uint32_t n_circ, hipStream_t s) {
+  if (n_circ == 0) return hipSuccess;
   QIMAX_DISPATCH_K(KC, {
-    k_build_table<K><<<(uint32_t)(sizeof(K) * 256 / 256), 256, 0, s>>>(ops, n_ops, (K*)tab_key, tab_neg);
+    if (WP == 64) k_init_many<K, double><<<n_circ, 64, 0, s>>>((K*)keys, (double*)w, nq, dst, n_circ);
+    else k_init_many<K, float><<<n_circ, 64, 0, s>>>((K*)keys, (float*)w, nq, dst, n_circ);
   });
   return hipGetLastError();
 }

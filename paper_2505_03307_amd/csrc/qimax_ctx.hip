@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <random>
 #include <string>
@@ -208,7 +210,7 @@ struct qimax_ctx {
   // images and sort ping-pong
   DevBuf ik[2], iw[2];
   DevBuf cnt, off, scan_tmp, hist, hist_off, blk_begin, blk_end, blk_seg, seg_blk, blk_cnt, blk_off, img_seg;
-  DevBuf desc, err, f64tmp;
+  DevBuf desc, desc2, err, f64tmp;
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
   bool classic_sort = false;
@@ -222,16 +224,18 @@ struct qimax_ctx {
   qimax_stats st{};
   Prof prof;
   std::vector<uint64_t> gen_updates;
-  // host staging of asynchronous uploads; kept alive until the next stream synchronisation
-  std::vector<uint8_t> stage_desc;
-  std::vector<uint64_t> stage_begin, stage_end;
-  std::vector<uint32_t> stage_seg, stage_seg_blk;
+  // pinned host staging of the two uploads of a round (descriptors + count tiling, then
+  // the image tilings); each is reused only after the stream synchronisation that follows it
+  void* stage[2] = {nullptr, nullptr};
+  size_t stage_bytes[2] = {0, 0};
 };
 
 namespace {
 
 
 thread_local std::string g_create_error;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 qimax_status fail(qimax_ctx* c, qimax_status s, const std::string& msg) {
   if (c) c->last_error = msg;
@@ -293,6 +297,41 @@ qimax_status ensure(qimax_ctx* c, DevBuf& b, size_t bytes, bool headroom = true)
   return QIMAX_OK;
 }
 
+// Grow a buffer keeping its first `keep` bytes.
+qimax_status ensure_keep(qimax_ctx* c, DevBuf& b, size_t bytes, size_t keep) {
+  if (bytes <= b.bytes && b.p) return QIMAX_OK;
+  DevBuf nb;
+  size_t want = align256(bytes + bytes / 4 + 256);
+  if (c->cap && c->alloc_bytes + want > c->cap) {
+    want = align256(bytes);
+    if (c->alloc_bytes + want > c->cap)
+      return fail(c, QIMAX_ENOMEM, "memory cap exceeded (requested " + std::to_string(bytes) + " bytes)");
+  }
+  hipError_t e = hipMalloc(&nb.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, QIMAX_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  nb.bytes = want;
+  c->alloc_bytes += want;
+  c->peak_bytes = std::max(c->peak_bytes, c->alloc_bytes);
+  if (b.p && keep) {
+    e = hipMemcpyAsync(nb.p, b.p, std::min(keep, b.bytes), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(nb.p);
+      c->alloc_bytes -= want;
+      return hip_fail(c, e, "grow copy");
+    }
+  }
+  if (b.p) {
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, b);
+  }
+  b = nb;
+  return QIMAX_OK;
+}
+
 #define QCHK(expr)                         \
   do {                                     \
     qimax_status _s = (expr);              \
@@ -301,13 +340,13 @@ qimax_status ensure(qimax_ctx* c, DevBuf& b, size_t bytes, bool headroom = true)
 
 __global__ void k_clear_u32(uint32_t* p) { *p = 0u; }
 
-uint32_t bitpos(const qimax_ctx* c, int q) { return 2u * (c->n - 1u - (uint32_t)q); }
+uint32_t bitpos(uint32_t n, int q) { return 2u * (n - 1u - (uint32_t)q); }
 
-PermDesc make_perm(const qimax_ctx* c, const HostOp& op) {
+PermDesc make_perm(uint32_t n, const HostOp& op) {
   PermDesc d{};
   d.arity = (uint32_t)op.arity;
-  d.pa = bitpos(c, op.q0);
-  d.pb = op.arity == 2 ? bitpos(c, op.q1) : 0u;
+  d.pa = bitpos(n, op.q0);
+  d.pb = op.arity == 2 ? bitpos(n, op.q1) : 0u;
   for (int in = 0; in < op.dim; ++in) {
     int out = 0;
     bool neg = false;
@@ -325,9 +364,9 @@ PermDesc make_perm(const qimax_ctx* c, const HostOp& op) {
   return d;
 }
 
-Exp1Desc make_exp1(const qimax_ctx* c, const HostOp& op) {
+Exp1Desc make_exp1(uint32_t n, const HostOp& op) {
   Exp1Desc d{};
-  d.pos = bitpos(c, op.q0);
+  d.pos = bitpos(n, op.q0);
   for (int in = 0; in < 4; ++in) {
     int k = 0;
     for (int r = 0; r < 4; ++r) {
@@ -343,10 +382,10 @@ Exp1Desc make_exp1(const qimax_ctx* c, const HostOp& op) {
   return d;
 }
 
-Exp2Desc make_exp2(const qimax_ctx* c, const HostOp& op) {
+Exp2Desc make_exp2(uint32_t n, const HostOp& op) {
   Exp2Desc d{};
-  d.pa = bitpos(c, op.q0);
-  d.pb = bitpos(c, op.q1);
+  d.pa = bitpos(n, op.q0);
+  d.pb = bitpos(n, op.q1);
   for (int in = 0; in < 16; ++in) {
     int k = 0;
     for (int r = 0; r < 16; ++r) {
@@ -362,108 +401,62 @@ Exp2Desc make_exp2(const qimax_ctx* c, const HostOp& op) {
   return d;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Upload the pass's operator descriptors; fills pa with device pointers.
-qimax_status upload_pass(qimax_ctx* c, const Pass& p, PassArgs& pa) {
-  std::vector<PermDesc> A, B;
-  std::vector<Exp1Desc> E1;
-  std::vector<Exp2Desc> E2;
-  for (auto* op : p.A) A.push_back(make_perm(c, *op));
-  for (auto* op : p.B) B.push_back(make_perm(c, *op));
-  for (auto* op : p.E) {
-    if (op->arity == 1) E1.push_back(make_exp1(c, *op));
-    else E2.push_back(make_exp2(c, *op));
-  }
-  const size_t oA = 0, oB = align256(oA + A.size() * sizeof(PermDesc));
-  const size_t o1 = align256(oB + B.size() * sizeof(PermDesc));
-  const size_t o2 = align256(o1 + E1.size() * sizeof(Exp1Desc));
-  auto tableable = [](const std::vector<const HostOp*>& v) {
-    if ((int)v.size() < kChainTableMin) return false;
-    for (auto* op : v)
-      if (!op->conj) return false;
-    return true;
-  };
-  const bool useA = tableable(p.A), useB = tableable(p.B);
-  const size_t entries = c->kb * 256;
-  const size_t oTAk = align256(o2 + E2.size() * sizeof(Exp2Desc));
-  const size_t oTAn = align256(oTAk + (useA ? entries * c->kb : 0));
-  const size_t oTBk = align256(oTAn + (useA ? entries : 0));
-  const size_t oTBn = align256(oTBk + (useB ? entries * c->kb : 0));
-  const size_t total = align256(oTBn + (useB ? entries : 0)) + 256;
-  QCHK(ensure(c, c->desc, total));
-  std::vector<uint8_t>& host = c->stage_desc;
-  host.assign(total, 0);
-  if (!A.empty()) std::memcpy(host.data() + oA, A.data(), A.size() * sizeof(PermDesc));
-  if (!B.empty()) std::memcpy(host.data() + oB, B.data(), B.size() * sizeof(PermDesc));
-  if (!E1.empty()) std::memcpy(host.data() + o1, E1.data(), E1.size() * sizeof(Exp1Desc));
-  if (!E2.empty()) std::memcpy(host.data() + o2, E2.data(), E2.size() * sizeof(Exp2Desc));
-  HIPCHK(c, hipMemcpyAsync(c->desc.p, host.data(), total, hipMemcpyHostToDevice, c->stream), "upload descriptors");
-  uint8_t* base = (uint8_t*)c->desc.p;
-  pa.A = (const PermDesc*)(base + oA);
-  pa.B = (const PermDesc*)(base + oB);
-  pa.E1 = (const Exp1Desc*)(base + o1);
-  pa.E2 = (const Exp2Desc*)(base + o2);
-  pa.nA = (uint32_t)A.size();
-  pa.nB = (uint32_t)B.size();
-  pa.nE1 = (uint32_t)E1.size();
-  pa.nE2 = (uint32_t)E2.size();
-  pa.useA = useA;
-  pa.useB = useB;
-  pa.tA = ChainTable{base + oTAk, base + oTAn};
-  pa.tB = ChainTable{base + oTBk, base + oTBn};
-  if (useA)
-    HIPCHK(c, launch_build_table(c->KC, pa.A, pa.nA, base + oTAk, base + oTAn, c->stream, &c->prof), "chain table");
-  if (useB)
-    HIPCHK(c, launch_build_table(c->KC, pa.B, pa.nB, base + oTBk, base + oTBn, c->stream, &c->prof), "chain table");
-  return QIMAX_OK;
-}
-
-// Segment-aligned tiles of at most kSortTile elements over segment offsets so[0..S].
+// Segment-aligned tiles of at most `tile` elements over segment offsets so[0..S].
 struct HostTiling {
   std::vector<uint64_t> begin, end;
   std::vector<uint32_t> seg, seg_blk;
 };
 
-void make_tiling(const std::vector<uint64_t>& so, HostTiling& t) {
+void make_tiling(const std::vector<uint64_t>& so, uint64_t tile, HostTiling& t) {
   const size_t S = so.size() - 1;
   t.begin.clear(); t.end.clear(); t.seg.clear(); t.seg_blk.assign(S + 1, 0);
   for (size_t s = 0; s < S; ++s) {
     t.seg_blk[s] = (uint32_t)t.begin.size();
-    for (uint64_t b = so[s]; b < so[s + 1]; b += kSortTile) {
+    for (uint64_t b = so[s]; b < so[s + 1]; b += tile) {
       t.begin.push_back(b);
-      t.end.push_back(std::min(b + (uint64_t)kSortTile, so[s + 1]));
+      t.end.push_back(std::min(b + tile, so[s + 1]));
       t.seg.push_back((uint32_t)s);
     }
   }
   t.seg_blk[S] = (uint32_t)t.begin.size();
 }
 
-qimax_status upload_tiling(qimax_ctx* c, const HostTiling& hin, Tiling& tl) {
-  c->stage_begin = hin.begin;
-  c->stage_end = hin.end;
-  c->stage_seg = hin.seg;
-  c->stage_seg_blk = hin.seg_blk;
-  struct { std::vector<uint64_t>& begin; std::vector<uint64_t>& end; std::vector<uint32_t>& seg;
-           std::vector<uint32_t>& seg_blk; } h{c->stage_begin, c->stage_end, c->stage_seg, c->stage_seg_blk};
-  const size_t nb = h.begin.size();
-  QCHK(ensure(c, c->blk_begin, std::max<size_t>(nb, 1) * 8));
-  QCHK(ensure(c, c->blk_end, std::max<size_t>(nb, 1) * 8));
-  QCHK(ensure(c, c->blk_seg, std::max<size_t>(nb, 1) * 4));
-  QCHK(ensure(c, c->seg_blk, h.seg_blk.size() * 4));
+// Bytes a tiling occupies in a staging area (four arrays, each 256-aligned).
+size_t tiling_bytes(const HostTiling& t) {
+  const size_t nb = std::max<size_t>(t.begin.size(), 1);
+  return align256(nb * 8) * 2 + align256(nb * 4) + align256(t.seg_blk.size() * 4);
+}
+
+// Copy a tiling into host staging at `off` and describe it by its device addresses.
+size_t put_tiling(const HostTiling& t, uint8_t* host, uint8_t* dev, size_t off, Tiling& tl) {
+  const size_t nb = t.begin.size(), nbm = std::max<size_t>(nb, 1);
+  const size_t o1 = off, o2 = o1 + align256(nbm * 8), o3 = o2 + align256(nbm * 8), o4 = o3 + align256(nbm * 4);
   if (nb) {
-    HIPCHK(c, hipMemcpyAsync(c->blk_begin.p, h.begin.data(), nb * 8, hipMemcpyHostToDevice, c->stream), "tiling");
-    HIPCHK(c, hipMemcpyAsync(c->blk_end.p, h.end.data(), nb * 8, hipMemcpyHostToDevice, c->stream), "tiling");
-    HIPCHK(c, hipMemcpyAsync(c->blk_seg.p, h.seg.data(), nb * 4, hipMemcpyHostToDevice, c->stream), "tiling");
+    std::memcpy(host + o1, t.begin.data(), nb * 8);
+    std::memcpy(host + o2, t.end.data(), nb * 8);
+    std::memcpy(host + o3, t.seg.data(), nb * 4);
   }
-  HIPCHK(c, hipMemcpyAsync(c->seg_blk.p, h.seg_blk.data(), h.seg_blk.size() * 4, hipMemcpyHostToDevice, c->stream),
-         "tiling");
-  tl.blk_begin = (const uint64_t*)c->blk_begin.p;
-  tl.blk_end = (const uint64_t*)c->blk_end.p;
-  tl.blk_seg = (const uint32_t*)c->blk_seg.p;
-  tl.seg_blk = (const uint32_t*)c->seg_blk.p;
+  std::memcpy(host + o4, t.seg_blk.data(), t.seg_blk.size() * 4);
+  tl.blk_begin = (const uint64_t*)(dev + o1);
+  tl.blk_end = (const uint64_t*)(dev + o2);
+  tl.blk_seg = (const uint32_t*)(dev + o3);
+  tl.seg_blk = (const uint32_t*)(dev + o4);
   tl.n_blocks = (uint32_t)nb;
-  tl.n_segs = (uint32_t)(h.seg_blk.size() - 1);
+  tl.n_segs = (uint32_t)(t.seg_blk.size() - 1);
+  return o4 + align256(t.seg_blk.size() * 4);
+}
+
+qimax_status ensure_stage(qimax_ctx* c, int i, size_t bytes) {
+  if (bytes <= c->stage_bytes[i] && c->stage[i]) return QIMAX_OK;
+  if (c->stage[i]) {
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    (void)hipHostFree(c->stage[i]);
+    c->stage[i] = nullptr;
+    c->stage_bytes[i] = 0;
+  }
+  const size_t want = align256(bytes + bytes / 4 + 4096);
+  HIPCHK(c, hipHostMalloc(&c->stage[i], want, hipHostMallocDefault), "hipHostMalloc staging");
+  c->stage_bytes[i] = want;
   return QIMAX_OK;
 }
 
@@ -494,20 +487,130 @@ std::string err_text(uint32_t e) {
   return s;
 }
 
-// Runs one pass on terms (k_in, w_in, seg_in [device], so_in [host]) and writes the merged
-// result to pass buffer `slot`. On success fills so_out (host) and returns the count.
-qimax_status run_pass(qimax_ctx* c, const Pass& p, const void* k_in, const void* w_in, const uint64_t* seg_in,
-                      const std::vector<uint64_t>& so_in, int slot, double thr, std::vector<uint64_t>& so_out) {
-  const uint32_t S = c->n;
+// One circuit's share of a round: its next pass (or a drop of all its terms), the digit
+// positions of its n qubits and the merge threshold of that pass.
+struct RoundEntry {
+  const Pass* pass = nullptr;
+  uint32_t n = 0;
+  double thr = 0.0;
+  bool drop = false;
+};
+
+uint64_t op_groups(const std::vector<const HostOp*>& v, int exclude) {
+  std::vector<int> g;
+  for (auto* op : v)
+    if (op->group != exclude) g.push_back(op->group);
+  std::sort(g.begin(), g.end());
+  return (uint64_t)(std::unique(g.begin(), g.end()) - g.begin());
+}
+
+// Runs one round: every segment s of the input (k_in, w_in; device offsets seg_in, host
+// offsets so_in) is processed with the pass of entries[seg_entry[s]], in one set of
+// launches for all segments. The merged result goes to pass slot `slot`; so_out / so_img
+// receive the output and image segment offsets. upd[e] receives entry e's term updates.
+qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, const std::vector<uint32_t>& seg_entry,
+                       const void* k_in, const void* w_in, const uint64_t* seg_in, const std::vector<uint64_t>& so_in,
+                       int slot, std::vector<uint64_t>& so_out, std::vector<uint64_t>& so_img,
+                       std::vector<uint64_t>* upd) {
+  const uint32_t S = (uint32_t)seg_entry.size();
   const uint64_t T_in = so_in[S];
-  PassArgs pa{};
-  QCHK(upload_pass(c, p, pa));
+  const size_t E = entries.size();
+  // ---- descriptors of every entry
+  std::vector<PermDesc> perms;
+  std::vector<Exp1Desc> e1;
+  std::vector<Exp2Desc> e2;
+  struct Lay { size_t a, b, x1, x2; uint32_t nA, nB, nE1, nE2; bool useA, useB; };
+  std::vector<Lay> lay(E);
+  size_t n_jobs = 0;
+  bool any_tables = false;
+  uint32_t max_n = 1;
+  auto tableable = [](const std::vector<const HostOp*>& v) {
+    if ((int)v.size() < kChainTableMin) return false;
+    for (auto* op : v)
+      if (!op->conj) return false;
+    return true;
+  };
+  for (size_t e = 0; e < E; ++e) {
+    Lay& L = lay[e];
+    L = Lay{perms.size(), 0, e1.size(), e2.size(), 0, 0, 0, 0, false, false};
+    max_n = std::max(max_n, entries[e].n);
+    const Pass* p = entries[e].pass;
+    if (!p || entries[e].drop) continue;
+    for (auto* op : p->A) perms.push_back(make_perm(entries[e].n, *op));
+    L.nA = (uint32_t)p->A.size();
+    L.b = perms.size();
+    for (auto* op : p->B) perms.push_back(make_perm(entries[e].n, *op));
+    L.nB = (uint32_t)p->B.size();
+    for (auto* op : p->E) {
+      if (op->arity == 1) { e1.push_back(make_exp1(entries[e].n, *op)); ++L.nE1; }
+      else { e2.push_back(make_exp2(entries[e].n, *op)); ++L.nE2; }
+    }
+    L.useA = tableable(p->A);
+    L.useB = tableable(p->B);
+    n_jobs += L.useA + L.useB;
+    any_tables |= L.useA || L.useB;
+  }
+  HostTiling t_in;
+  make_tiling(so_in, kSortTile, t_in);
+  const size_t entries_tab = c->kb * 256;
+  const size_t tab_bytes = align256(entries_tab * c->kb) + align256(entries_tab);
+  const size_t oP = 0;
+  const size_t o1 = align256(oP + perms.size() * sizeof(PermDesc));
+  const size_t o2 = align256(o1 + e1.size() * sizeof(Exp1Desc));
+  const size_t oA = align256(o2 + e2.size() * sizeof(Exp2Desc));
+  const size_t oS = align256(oA + E * sizeof(PassArgs));
+  const size_t oJ = align256(oS + S * 4);
+  const size_t oT = align256(oJ + n_jobs * sizeof(TableJob));
+  const size_t host_bytes = oT + tiling_bytes(t_in);
+  const size_t oTab = align256(host_bytes);
+  const size_t total = oTab + n_jobs * tab_bytes + 256;
+  QCHK(ensure(c, c->desc, total));
+  QCHK(ensure_stage(c, 0, host_bytes));
+  uint8_t* hs = (uint8_t*)c->stage[0];
+  uint8_t* ds = (uint8_t*)c->desc.p;
+  std::memset(hs, 0, oT);
+  if (!perms.empty()) std::memcpy(hs + oP, perms.data(), perms.size() * sizeof(PermDesc));
+  if (!e1.empty()) std::memcpy(hs + o1, e1.data(), e1.size() * sizeof(Exp1Desc));
+  if (!e2.empty()) std::memcpy(hs + o2, e2.data(), e2.size() * sizeof(Exp2Desc));
+  PassArgs* pas_h = (PassArgs*)(hs + oA);
+  TableJob* jobs_h = (TableJob*)(hs + oJ);
+  size_t job = 0;
+  for (size_t e = 0; e < E; ++e) {
+    const Lay& L = lay[e];
+    PassArgs pa{};
+    pa.A = (const PermDesc*)(ds + oP + L.a * sizeof(PermDesc));
+    pa.B = (const PermDesc*)(ds + oP + L.b * sizeof(PermDesc));
+    pa.E1 = (const Exp1Desc*)(ds + o1 + L.x1 * sizeof(Exp1Desc));
+    pa.E2 = (const Exp2Desc*)(ds + o2 + L.x2 * sizeof(Exp2Desc));
+    pa.nA = L.nA; pa.nB = L.nB; pa.nE1 = L.nE1; pa.nE2 = L.nE2;
+    pa.drop = entries[e].drop ? 1u : 0u;
+    pa.thr = entries[e].thr;
+    auto table_for = [&](const PermDesc* ops, uint32_t nops, ChainTable& t) {
+      uint8_t* tk = ds + oTab + job * tab_bytes;
+      uint8_t* tn = tk + align256(entries_tab * c->kb);
+      jobs_h[job] = TableJob{ops, nops, 0, tk, tn};
+      t = ChainTable{tk, tn};
+      ++job;
+    };
+    if (L.useA) { pa.useA = 1; table_for(pa.A, pa.nA, pa.tA); }
+    if (L.useB) { pa.useB = 1; table_for(pa.B, pa.nB, pa.tB); }
+    pas_h[e] = pa;
+  }
+  std::memcpy(hs + oS, seg_entry.data(), S * 4);
+  Tiling tl_in{};
+  put_tiling(t_in, hs, ds, oT, tl_in);
+  HIPCHK(c, hipMemcpyAsync(ds, hs, host_bytes, hipMemcpyHostToDevice, c->stream), "upload round");
+  const PassArgs* pas = (const PassArgs*)(ds + oA);
+  const uint32_t* sent = (const uint32_t*)(ds + oS);
+  HIPCHK(c, launch_build_tables(c->KC, (const TableJob*)(ds + oJ), (uint32_t)n_jobs, c->stream, &c->prof),
+         "chain tables");
   k_clear_u32<<<1, 1, 0, c->stream>>>((uint32_t*)c->err.p);
-  // fan-out count and scan -> image offsets
+  // ---- fan-out count and scan -> image offsets
   QCHK(ensure(c, c->cnt, std::max<uint64_t>(T_in, 1) * 4));
   QCHK(ensure(c, c->off, (T_in + 1) * 8));
   QCHK(ensure(c, c->scan_tmp, scan_tmp_words(T_in) * 8));
-  HIPCHK(c, launch_count(c->KC, k_in, T_in, pa, (uint32_t*)c->cnt.p, (uint32_t*)c->err.p, c->stream, &c->prof), "count");
+  HIPCHK(c, launch_count(c->KC, k_in, T_in, tl_in, pas, sent, (uint32_t*)c->cnt.p, (uint32_t*)c->err.p, c->stream,
+                         &c->prof), "count");
   HIPCHK(c, launch_scan_u32((const uint32_t*)c->cnt.p, (uint64_t*)c->off.p, T_in, (uint64_t*)c->scan_tmp.p,
                             c->stream, &c->prof), "scan");
   QCHK(ensure(c, c->img_seg, (S + 1) * 8));
@@ -516,25 +619,32 @@ qimax_status run_pass(qimax_ctx* c, const Pass& p, const void* k_in, const void*
   uint32_t e = 0;
   QCHK(readback(c, c->img_seg.p, S + 1, &e));
   if (e) return fail(c, (e & kErrFanout) ? QIMAX_ETOOLARGE : QIMAX_EDEVICE, "count pass:" + err_text(e));
-  std::vector<uint64_t> so_img(c->pinned, c->pinned + S + 1);
+  so_img.assign(c->pinned, c->pinned + S + 1);
   const uint64_t T_img = so_img[S];
-  // expand into images
+  // ---- image tilings (expand tiles, sort/merge tiles) in one upload
+  HostTiling t_exp, t_sort;
+  make_tiling(so_img, kExpandTile, t_exp);
+  make_tiling(so_img, kSortTile, t_sort);
+  const size_t img_bytes = tiling_bytes(t_exp) + tiling_bytes(t_sort);
+  QCHK(ensure(c, c->desc2, img_bytes + 256));
+  QCHK(ensure_stage(c, 1, img_bytes));
+  Tiling tl_exp{}, tl{};
+  const size_t mid = put_tiling(t_exp, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, 0, tl_exp);
+  put_tiling(t_sort, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, mid, tl);
+  HIPCHK(c, hipMemcpyAsync(c->desc2.p, c->stage[1], img_bytes, hipMemcpyHostToDevice, c->stream), "upload tiling");
+  // ---- expand into images
   const size_t eb = c->kb, wbt = c->wb;
   QCHK(ensure(c, c->ik[0], std::max<uint64_t>(T_img, 1) * eb));
   QCHK(ensure(c, c->iw[0], std::max<uint64_t>(T_img, 1) * wbt));
   QCHK(ensure(c, c->ik[1], std::max<uint64_t>(T_img, 1) * eb));
   QCHK(ensure(c, c->iw[1], std::max<uint64_t>(T_img, 1) * wbt));
-  HIPCHK(c, launch_expand(c->KC, c->WP, k_in, w_in, T_in, (const uint64_t*)c->off.p, T_img, pa, c->ik[0].p,
-                          c->iw[0].p, (uint32_t*)c->err.p, c->stream, &c->prof), "expand");
-  // segmented LSD radix sort of the images
-  HostTiling ht;
-  make_tiling(so_img, ht);
-  Tiling tl{};
-  QCHK(upload_tiling(c, ht, tl));
+  HIPCHK(c, launch_expand(c->KC, c->WP, k_in, w_in, T_in, (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent,
+                          any_tables, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream, &c->prof), "expand");
+  // ---- segment-local LSD radix sort of the images
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
   QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
   int cur = 0;
-  const uint32_t key_bits = 2u * c->n;
+  const uint32_t key_bits = 2u * max_n;
   if (c->classic_sort) {
     QCHK(ensure(c, c->hist, hsize * 8));
     QCHK(ensure(c, c->hist_off, (hsize + 1) * 8));
@@ -564,56 +674,53 @@ qimax_status run_pass(qimax_ctx* c, const Pass& p, const void* k_in, const void*
                                 (uint32_t*)c->tile_ctr.p, &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof),
            "sort");
   }
-  // segmented reduce + prune + compaction into the pass output slot
+  // ---- segmented reduce + prune + compaction into the pass output slot
   QCHK(ensure(c, c->pk[slot], std::max<uint64_t>(T_img, 1) * eb));
   QCHK(ensure(c, c->pw[slot], std::max<uint64_t>(T_img, 1) * wbt));
   QCHK(ensure(c, c->pseg[slot], (S + 1) * 8));
   QCHK(ensure(c, c->blk_cnt, (size_t)(tl.n_blocks + 1) * 4));
   QCHK(ensure(c, c->blk_off, (size_t)(tl.n_blocks + 1) * 8));
-  HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, thr, c->pk[slot].p,
-                         c->pw[slot].p, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
-                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, (uint32_t*)c->err.p, c->stream, &c->prof),
-         "merge");
+  HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, pas, sent, c->pk[slot].p,
+                         c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
+                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, (uint32_t*)c->err.p, c->stream,
+                         &c->prof), "merge");
   QCHK(readback(c, c->pseg[slot].p, S + 1, &e));
   if (e) return fail(c, QIMAX_EDEVICE, "expand/sort/merge pass:" + err_text(e));
   so_out.assign(c->pinned, c->pinned + S + 1);
   const uint64_t T_out = so_out[S];
   if (c->prof.on) c->prof.bytes[kKMergeWrite] += (double)T_out * (double)(eb + wbt);
-  // bookkeeping: one update per output image of every operator (Clifford operators
-  // count their input terms, the expanding operator its images)
-  auto groups = [&](const std::vector<const HostOp*>& v) {
-    std::vector<int> g;
-    for (auto* op : v)
-      if (op->group != p.egroup) g.push_back(op->group);
-    std::sort(g.begin(), g.end());
-    return (uint64_t)(std::unique(g.begin(), g.end()) - g.begin());
-  };
-  const uint64_t gA = groups(p.A), gB = groups(p.B);
-  c->st.term_updates += gA * T_in + (p.E.empty() ? 0 : T_img) + gB * T_out;
-  if (c->gen_updates.size() != S) c->gen_updates.assign(S, 0);
-  for (uint32_t j = 0; j < S; ++j)
-    c->gen_updates[j] += gA * (so_in[j + 1] - so_in[j]) + (p.E.empty() ? 0 : so_img[j + 1] - so_img[j]) +
-                         gB * (so_out[j + 1] - so_out[j]);
+  // ---- bookkeeping: one update per output image of every operator (a Clifford operator
+  // counts its terms, the expanding operator its images), attributed per entry
+  if (upd) upd->assign(E, 0);
+  uint64_t total_upd = 0;
+  for (uint32_t s = 0; s < S; ++s) {
+    const RoundEntry& en = entries[seg_entry[s]];
+    if (en.drop || !en.pass) continue;
+    const Pass& p = *en.pass;
+    const uint64_t u = op_groups(p.A, p.egroup) * (so_in[s + 1] - so_in[s]) +
+                       (p.E.empty() ? 0 : so_img[s + 1] - so_img[s]) +
+                       op_groups(p.B, p.egroup) * (so_out[s + 1] - so_out[s]);
+    total_upd += u;
+    if (upd) (*upd)[seg_entry[s]] += u;
+  }
+  c->st.term_updates += total_upd;
   c->st.images += T_img;
   c->st.sort_elems += T_img * ((key_bits + kRadixBits - 1) / kRadixBits);
-  if (!p.E.empty()) c->st.passes += 1;
   return QIMAX_OK;
 }
 
-// Plans the operators into passes and runs them; commits only when every pass succeeded.
-qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
-  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
-  // the deferred Clifford operators of earlier calls come first
-  std::vector<HostOp> all;
-  all.reserve(c->pending.size() + ops.size());
-  for (auto& op : c->pending) all.push_back(op);
-  for (auto& op : ops) all.push_back(op);
-  std::vector<Pass> passes;
+// The pass planner: operators in order become passes [A perms] -> [E expanding ops of one
+// operator group on disjoint wires] -> [B perms]. A perm after E that touches none of E's
+// wires commutes past E into A. Trailing perms with no expanding operator after them are
+// returned in `pending` (deferred). thr: merge threshold of the last pass, 0 for the others.
+void plan_passes(const std::vector<const HostOp*>& all, std::vector<Pass>& passes,
+                 std::vector<const HostOp*>& pending) {
   Pass cur;
-  for (const HostOp& op : all) {
+  for (const HostOp* opp : all) {
+    const HostOp& op = *opp;
     if (op.perm) {
       if (cur.E.empty() || (cur.B.empty() && !(op.mask & cur.emask))) {
-        cur.A.push_back(&op);  // before (or commuting past) the expanding operators
+        cur.A.push_back(&op);
       } else {
         cur.B.push_back(&op);
         cur.bmask |= op.mask;
@@ -624,7 +731,8 @@ qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
     int n1 = 0, n2 = 0;
     for (auto* e : cur.E) (e->arity == 1 ? n1 : n2)++;
     const bool fits = (op.arity == 1 ? n1 + 1 <= kMaxE1 : n2 + 1 <= kMaxE2) && cur.fanout_bound * f <= kMaxFanout;
-    const bool join = !cur.E.empty() && op.group == cur.egroup && !(op.mask & cur.emask) && !(op.mask & cur.bmask) && fits;
+    const bool join = !cur.E.empty() && op.group == cur.egroup && !(op.mask & cur.emask) &&
+                      !(op.mask & cur.bmask) && fits;
     if (!cur.E.empty() && !join) {
       passes.push_back(cur);
       cur = Pass();
@@ -634,26 +742,52 @@ qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
     cur.egroup = op.group;
     cur.fanout_bound *= f;
   }
-  std::vector<HostOp> new_pending;
+  pending.clear();
   if (cur.E.empty()) {
-    for (auto* op : cur.A) new_pending.push_back(*op);
+    pending = cur.A;
   } else {
     passes.push_back(cur);
   }
+}
+
+// Single-circuit contexts: plan the operators (after the deferred ones of earlier calls) and
+// run the passes as one-entry rounds; commit only when every pass succeeded.
+qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  std::vector<HostOp> all;
+  all.reserve(c->pending.size() + ops.size());
+  for (auto& op : c->pending) all.push_back(op);
+  for (auto& op : ops) all.push_back(op);
+  std::vector<const HostOp*> ptrs;
+  for (auto& op : all) ptrs.push_back(&op);
+  std::vector<Pass> passes;
+  std::vector<const HostOp*> pend;
+  plan_passes(ptrs, passes, pend);
+  std::vector<HostOp> new_pending;
+  for (auto* op : pend) new_pending.push_back(*op);
   if (passes.empty()) {
     c->pending.swap(new_pending);
     return QIMAX_OK;
   }
-  // run the passes: committed state -> pass slot 0 -> slot 1 -> ...
   const void* k_in = c->keys.p;
   const void* w_in = c->w.p;
   const uint64_t* s_in = (const uint64_t*)c->seg.p;
-  std::vector<uint64_t> so_in = c->h_seg, so_out;
+  std::vector<uint64_t> so_in = c->h_seg, so_out, so_img, upd;
+  std::vector<uint32_t> seg_entry(c->n, 0);
   int slot = 0;
   for (size_t i = 0; i < passes.size(); ++i) {
-    const double thr = (i + 1 == passes.size()) ? c->eps : 0.0;
-    qimax_status s = run_pass(c, passes[i], k_in, w_in, s_in, so_in, slot, thr, so_out);
+    RoundEntry en;
+    en.pass = &passes[i];
+    en.n = c->n;
+    en.thr = (i + 1 == passes.size()) ? c->eps : 0.0;
+    qimax_status s = run_round(c, {en}, seg_entry, k_in, w_in, s_in, so_in, slot, so_out, so_img, nullptr);
     if (s != QIMAX_OK) return s;  // committed state untouched
+    if (c->gen_updates.size() != c->n) c->gen_updates.assign(c->n, 0);
+    for (uint32_t j = 0; j < c->n; ++j)
+      c->gen_updates[j] += op_groups(en.pass->A, en.pass->egroup) * (so_in[j + 1] - so_in[j]) +
+                           (en.pass->E.empty() ? 0 : so_img[j + 1] - so_img[j]) +
+                           op_groups(en.pass->B, en.pass->egroup) * (so_out[j + 1] - so_out[j]);
+    if (!en.pass->E.empty()) c->st.passes += 1;
     k_in = c->pk[slot].p;
     w_in = c->pw[slot].p;
     s_in = (const uint64_t*)c->pseg[slot].p;
@@ -666,6 +800,8 @@ qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
   std::swap(c->seg, c->pseg[last]);
   c->h_seg = so_in;
   c->T = so_in[c->n];
+  // deferred operators of later calls get group ids that cannot collide with this call's
+  for (auto& op : new_pending) op.group = -1000000 - op.group;
   c->pending.swap(new_pending);
   c->st.terms = c->T;
   return QIMAX_OK;
@@ -674,13 +810,19 @@ qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
 qimax_status flush_pending(qimax_ctx* c) {
   if (c->pending.empty()) return QIMAX_OK;
   // a pass with only Clifford operators: images are the permuted terms, then sorted
-  std::vector<HostOp> none;
-  std::vector<HostOp> saved = c->pending;
   Pass p;
   for (auto& op : c->pending) p.A.push_back(&op);
-  std::vector<uint64_t> so_out;
-  qimax_status s = run_pass(c, p, c->keys.p, c->w.p, (const uint64_t*)c->seg.p, c->h_seg, 0, 0.0, so_out);
+  RoundEntry en;
+  en.pass = &p;
+  en.n = c->n;
+  std::vector<uint64_t> so_out, so_img;
+  std::vector<uint32_t> seg_entry(c->n, 0);
+  qimax_status s = run_round(c, {en}, seg_entry, c->keys.p, c->w.p, (const uint64_t*)c->seg.p, c->h_seg, 0, so_out,
+                             so_img, nullptr);
   if (s != QIMAX_OK) return s;
+  if (c->gen_updates.size() != c->n) c->gen_updates.assign(c->n, 0);
+  for (uint32_t j = 0; j < c->n; ++j)
+    c->gen_updates[j] += op_groups(p.A, -1) * (c->h_seg[j + 1] - c->h_seg[j]);
   std::swap(c->keys, c->pk[0]);
   std::swap(c->w, c->pw[0]);
   std::swap(c->seg, c->pseg[0]);
@@ -716,12 +858,12 @@ bool is_2q_code(uint8_t g) { return g == QIMAX_GATE_CX || g == QIMAX_GATE_CZ; }
 // The paper's grouping (Sec. III-A, Alg. 2): maximal runs of one-qubit gates (U_k) and
 // of two-qubit gates (V_k) in instruction order; inside U_k the gates of each wire form
 // U_{k,j}, composed into one transfer matrix on the device (Alg. 1).
-qimax_status group_circuit(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
+qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
                            const double* theta, size_t m, std::vector<HostOp>& ops, size_t* n_u, size_t* n_v) {
   for (size_t i = 0; i < m; ++i) {
     if (gate[i] > QIMAX_GATE_CZ) return fail(c, QIMAX_EINVAL, "unknown gate code at instruction " + std::to_string(i));
-    if (q0[i] >= c->n) return fail(c, QIMAX_EINVAL, "qubit out of range at instruction " + std::to_string(i));
-    if (is_2q_code(gate[i]) && (q1[i] >= c->n || q1[i] == q0[i]))
+    if (q0[i] >= n) return fail(c, QIMAX_EINVAL, "qubit out of range at instruction " + std::to_string(i));
+    if (is_2q_code(gate[i]) && (q1[i] >= n || q1[i] == q0[i]))
       return fail(c, QIMAX_EINVAL, "bad second qubit at instruction " + std::to_string(i));
     if (theta && !std::isfinite(theta[i])) return fail(c, QIMAX_EINVAL, "non-finite angle");
   }
@@ -740,13 +882,13 @@ qimax_status group_circuit(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0
   std::vector<uint32_t> idx, chain_off{0};
   struct ChainRef { int run; int wire; };
   std::vector<ChainRef> chains;
-  std::vector<std::vector<uint32_t>> per_wire(c->n);
+  std::vector<std::vector<uint32_t>> per_wire(n);
   for (size_t r = 0; r < runs.size(); ++r) {
     if (runs[r].two) { ++nv; continue; }
     ++nu;
     for (auto& v : per_wire) v.clear();
     for (size_t i = runs[r].a; i < runs[r].b; ++i) per_wire[q0[i]].push_back((uint32_t)i);
-    for (uint32_t j = 0; j < c->n; ++j) {
+    for (uint32_t j = 0; j < n; ++j) {
       if (per_wire[j].empty()) continue;
       for (uint32_t gi : per_wire[j]) idx.push_back(gi);
       chain_off.push_back((uint32_t)idx.size());
@@ -1078,7 +1220,7 @@ qimax_status qimax_apply_circuit(qimax_ctx* c, const uint8_t* gate, const uint32
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
   if (m && (!gate || !q0 || !q1)) return fail(c, QIMAX_EINVAL, "instruction arrays are NULL");
   std::vector<HostOp> ops;
-  QCHK(group_circuit(c, gate, q0, q1, theta, m, ops, nullptr, nullptr));
+  QCHK(group_circuit(c, c->n, gate, q0, q1, theta, m, ops, nullptr, nullptr));
   return apply_ops(c, ops);
 }
 
@@ -1089,7 +1231,7 @@ qimax_status qimax_group_circuit(qimax_ctx* c, const uint8_t* gate, const uint32
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
   if (m && (!gate || !q0 || !q1)) return fail(c, QIMAX_EINVAL, "instruction arrays are NULL");
   std::vector<HostOp> hops;
-  QCHK(group_circuit(c, gate, q0, q1, theta, m, hops, n_u, n_v));
+  QCHK(group_circuit(c, c->n, gate, q0, q1, theta, m, hops, n_u, n_v));
   *n_ops = hops.size();
   if (cap == 0) return QIMAX_OK;
   if (!ops || !ptm_buf) return fail(c, QIMAX_EINVAL, "ops / ptm_buf is NULL");
@@ -1214,13 +1356,380 @@ void qimax_destroy(qimax_ctx* c) {
   DevBuf* bufs[] = {&c->keys, &c->w, &c->seg, &c->pk[0], &c->pk[1], &c->pw[0], &c->pw[1], &c->pseg[0],
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
-                    &c->blk_off, &c->img_seg, &c->desc, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
+                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
                     &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  for (int i = 0; i < 2; ++i)
+    if (c->stage[i]) (void)hipHostFree(c->stage[i]);
   prof_destroy(&c->prof);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
+}
+
+}  // extern "C"
+
+// ================================================================== batch engine (C ABI)
+
+namespace {
+
+// One circuit of a batch: its operators (stable storage), its planned passes with the merge
+// threshold of each, and where it is in its life (queued -> active -> draining -> done).
+struct BatchCirc {
+  uint64_t id = 0;
+  uint32_t n = 0;
+  std::deque<HostOp> ops;
+  std::vector<Pass> passes;
+  std::vector<double> thr;
+  size_t next = 0;
+  int state = 0;  // 0 queued, 1 active, 2 draining (result taken; terms leave next round), 3 done
+  uint64_t updates = 0;
+  std::vector<uint64_t> res_off, res_key;
+  std::vector<double> res_w;
+};
+
+}  // namespace
+
+struct qimax_batch {
+  qimax_ctx* c = nullptr;
+  uint64_t next_id = 1;
+  std::map<uint64_t, BatchCirc> circs;
+  std::vector<uint64_t> order;  // circuits whose generators are in the term array, in order
+  std::vector<uint64_t> queue;  // submitted, not yet admitted into the array
+  std::vector<uint64_t> done;   // finished and not yet reported by poll
+  std::vector<uint64_t> so{0};  // host segment offsets of the term array
+  uint64_t rounds = 0;
+};
+
+namespace {
+
+qimax_status bfail(qimax_batch* b, qimax_status s, const std::string& msg) {
+  b->c->last_error = msg;
+  return s;
+}
+
+// Plan every layer of a circuit into passes (the eps prune closes each layer).
+qimax_status plan_circuit(qimax_batch* b, const qimax_circuit* q, double eps, BatchCirc& bc) {
+  qimax_ctx* c = b->c;
+  std::vector<std::pair<size_t, size_t>> layers;
+  if (q->layer_end && q->n_layers) {
+    size_t a = 0;
+    for (size_t l = 0; l < q->n_layers; ++l) {
+      const size_t e = (size_t)q->layer_end[l];
+      if (e < a || e > q->m) return bfail(b, QIMAX_EINVAL, "layer_end must be non-decreasing and <= m");
+      layers.push_back({a, e});
+      a = e;
+    }
+    if (a != q->m) return bfail(b, QIMAX_EINVAL, "the last layer_end must equal m");
+  } else {
+    layers.push_back({0, q->m});
+  }
+  std::vector<const HostOp*> pending;
+  for (size_t l = 0; l < layers.size(); ++l) {
+    const size_t a = layers[l].first, e = layers[l].second;
+    std::vector<HostOp> ops;
+    QCHK(group_circuit(c, bc.n, q->gate + a, q->q0 + a, q->q1 + a, q->theta ? q->theta + a : nullptr, e - a, ops,
+                       nullptr, nullptr));
+    std::vector<const HostOp*> all = pending;
+    for (auto& op : ops) {
+      op.group += (int)(l * 1000000);
+      bc.ops.push_back(std::move(op));
+      all.push_back(&bc.ops.back());
+    }
+    std::vector<Pass> passes;
+    plan_passes(all, passes, pending);
+    for (size_t i = 0; i < passes.size(); ++i) {
+      bc.passes.push_back(passes[i]);
+      bc.thr.push_back(i + 1 == passes.size() ? eps : 0.0);
+    }
+  }
+  if (!pending.empty()) {  // trailing Clifford operators: one permutation-only pass
+    Pass p;
+    p.A = pending;
+    bc.passes.push_back(p);
+    bc.thr.push_back(0.0);
+  }
+  return QIMAX_OK;
+}
+
+void initial_result(BatchCirc& bc) {
+  bc.res_off.resize(bc.n + 1);
+  bc.res_key.resize(bc.n);
+  bc.res_w.assign(bc.n, 1.0);
+  for (uint32_t j = 0; j <= bc.n; ++j) bc.res_off[j] = j;
+  for (uint32_t j = 0; j < bc.n; ++j) bc.res_key[j] = 3ull << (2 * (bc.n - 1 - j));
+}
+
+// Admit the queued circuits: their Z_j terms go to the end of the term array.
+qimax_status admit(qimax_batch* b) {
+  if (b->queue.empty()) return QIMAX_OK;
+  qimax_ctx* c = b->c;
+  const uint64_t T = b->so.back();
+  uint64_t add = 0;
+  std::vector<uint32_t> nq;
+  std::vector<uint64_t> dst;
+  for (uint64_t id : b->queue) {
+    BatchCirc& bc = b->circs[id];
+    nq.push_back(bc.n);
+    dst.push_back(T + add);
+    add += bc.n;
+  }
+  QCHK(ensure_keep(c, c->keys, (T + add) * c->kb, T * c->kb));
+  QCHK(ensure_keep(c, c->w, (T + add) * c->wb, T * c->wb));
+  QCHK(ensure(c, c->gr_idx, nq.size() * 4));
+  QCHK(ensure(c, c->gr_off, dst.size() * 8));
+  HIPCHK(c, hipMemcpyAsync(c->gr_idx.p, nq.data(), nq.size() * 4, hipMemcpyHostToDevice, c->stream), "admit");
+  HIPCHK(c, hipMemcpyAsync(c->gr_off.p, dst.data(), dst.size() * 8, hipMemcpyHostToDevice, c->stream), "admit");
+  HIPCHK(c, launch_init_many(c->KC, c->WP, c->keys.p, c->w.p, (const uint32_t*)c->gr_idx.p,
+                             (const uint64_t*)c->gr_off.p, (uint32_t)nq.size(), c->stream), "init");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  for (uint64_t id : b->queue) {
+    BatchCirc& bc = b->circs[id];
+    bc.state = 1;
+    b->order.push_back(id);
+    for (uint32_t j = 0; j < bc.n; ++j) b->so.push_back(b->so.back() + 1);
+  }
+  b->queue.clear();
+  return QIMAX_OK;
+}
+
+// Copy a finished circuit's generators (segments [s0, s0+n) of the committed array) to the host.
+qimax_status take_result(qimax_batch* b, BatchCirc& bc, size_t s0) {
+  qimax_ctx* c = b->c;
+  const uint64_t a = b->so[s0], e = b->so[s0 + bc.n];
+  bc.res_off.resize(bc.n + 1);
+  for (uint32_t j = 0; j <= bc.n; ++j) bc.res_off[j] = b->so[s0 + j] - a;
+  bc.res_key.resize(e - a);
+  bc.res_w.resize(e - a);
+  if (e == a) return QIMAX_OK;
+  if (c->KC == 1) {
+    HIPCHK(c, hipMemcpy(bc.res_key.data(), (uint64_t*)c->keys.p + a, (e - a) * 8, hipMemcpyDeviceToHost), "result");
+  } else {
+    std::vector<uint32_t> k32(e - a);
+    HIPCHK(c, hipMemcpy(k32.data(), (uint32_t*)c->keys.p + a, (e - a) * 4, hipMemcpyDeviceToHost), "result");
+    for (size_t i = 0; i < k32.size(); ++i) bc.res_key[i] = k32[i];
+  }
+  if (c->WP == 64) {
+    HIPCHK(c, hipMemcpy(bc.res_w.data(), (double*)c->w.p + a, (e - a) * 8, hipMemcpyDeviceToHost), "result");
+  } else {
+    std::vector<float> w32(e - a);
+    HIPCHK(c, hipMemcpy(w32.data(), (float*)c->w.p + a, (e - a) * 4, hipMemcpyDeviceToHost), "result");
+    for (size_t i = 0; i < w32.size(); ++i) bc.res_w[i] = w32[i];
+  }
+  return QIMAX_OK;
+}
+
+size_t active_count(const qimax_batch* b) {
+  size_t k = 0;
+  for (uint64_t id : b->order)
+    if (b->circs.at(id).state == 1) ++k;
+  return k + b->queue.size();
+}
+
+}  // namespace
+
+extern "C" {
+
+qimax_status qimax_batch_create(const qimax_opts* opts, qimax_batch** out) {
+  if (!out) return QIMAX_EINVAL;
+  *out = nullptr;
+  qimax_ctx* c = nullptr;
+  qimax_status s = qimax_create(32, opts, &c);  // a 32-qubit context: uint64 keys, buffers, stream
+  if (s != QIMAX_OK) return s;
+  qimax_batch* b = new (std::nothrow) qimax_batch;
+  if (!b) {
+    qimax_destroy(c);
+    return QIMAX_ENOMEM;
+  }
+  b->c = c;
+  c->T = 0;
+  c->h_seg.assign(1, 0);
+  *out = b;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_batch_submit(qimax_batch* b, const qimax_circuit* q, uint64_t* id) {
+  if (!b || !q || !id) return QIMAX_EINVAL;
+  qimax_ctx* c = b->c;
+  if (c->broken) return bfail(b, QIMAX_ESTATE, "batch unusable after an earlier device error");
+  if (q->n < 1 || q->n > 32) return bfail(b, q->n < 1 ? QIMAX_EINVAL : QIMAX_ETOOLARGE, "circuit n must be 1..32");
+  if (q->m && (!q->gate || !q->q0 || !q->q1)) return bfail(b, QIMAX_EINVAL, "instruction arrays are NULL");
+  if (!(q->prune_eps >= 0.0) || !std::isfinite(q->prune_eps)) return bfail(b, QIMAX_EINVAL, "prune_eps must be >= 0");
+  BatchCirc bc;
+  bc.id = b->next_id;
+  bc.n = q->n;
+  QCHK(plan_circuit(b, q, q->prune_eps, bc));
+  const uint64_t cid = b->next_id++;
+  if (bc.passes.empty()) {  // nothing to propagate: the result is Z_0 .. Z_{n-1}
+    initial_result(bc);
+    bc.state = 3;
+    b->done.push_back(cid);
+  } else {
+    b->queue.push_back(cid);
+  }
+  b->circs.emplace(cid, std::move(bc));
+  *id = cid;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_batch_step(qimax_batch* b, size_t* n_active) {
+  if (!b) return QIMAX_EINVAL;
+  qimax_ctx* c = b->c;
+  if (c->broken) return bfail(b, QIMAX_ESTATE, "batch unusable after an earlier device error");
+  QCHK(admit(b));
+  // one entry per circuit in the array: its next pass, or a drop of a finished circuit
+  std::vector<RoundEntry> entries;
+  std::vector<uint32_t> seg_entry;
+  bool any = false;
+  for (uint64_t id : b->order) {
+    BatchCirc& bc = b->circs.at(id);
+    RoundEntry en;
+    en.n = bc.n;
+    if (bc.state == 1) {
+      en.pass = &bc.passes[bc.next];
+      en.thr = bc.thr[bc.next];
+      any = true;
+    } else {
+      en.drop = true;
+    }
+    for (uint32_t j = 0; j < bc.n; ++j) seg_entry.push_back((uint32_t)entries.size());
+    entries.push_back(en);
+  }
+  if (!any) {  // only finished circuits left in the array: empty it
+    for (uint64_t id : b->order) {
+      BatchCirc& bc = b->circs.at(id);
+      if (bc.state == 4) b->circs.erase(id);
+      else bc.state = 3;
+    }
+    b->order.clear();
+    b->so.assign(1, 0);
+    c->T = 0;
+    if (n_active) *n_active = active_count(b);
+    return QIMAX_OK;
+  }
+  QCHK(ensure(c, c->seg, b->so.size() * 8));
+  HIPCHK(c, hipMemcpyAsync(c->seg.p, b->so.data(), b->so.size() * 8, hipMemcpyHostToDevice, c->stream), "offsets");
+  std::vector<uint64_t> so_out, so_img, upd;
+  QCHK(run_round(c, entries, seg_entry, c->keys.p, c->w.p, (const uint64_t*)c->seg.p, b->so, 0, so_out, so_img,
+                 &upd));
+  std::swap(c->keys, c->pk[0]);
+  std::swap(c->w, c->pw[0]);
+  std::swap(c->seg, c->pseg[0]);
+  b->so = so_out;
+  c->T = so_out.back();
+  b->rounds += 1;
+  // finished circuits hand over their result; dropped ones leave the segment list
+  std::vector<uint64_t> keep_order, erase;
+  std::vector<uint64_t> keep_so{0};
+  size_t s0 = 0;
+  for (size_t e = 0; e < b->order.size(); ++e) {
+    BatchCirc& bc = b->circs.at(b->order[e]);
+    bc.updates += upd[e];
+    bool leaves = false;
+    if (bc.state == 1) {
+      if (!bc.passes[bc.next].E.empty()) c->st.passes += 1;
+      bc.next += 1;
+      if (bc.next == bc.passes.size()) {
+        QCHK(take_result(b, bc, s0));
+        bc.state = 2;
+        b->done.push_back(bc.id);
+      }
+    } else {  // dropped this round: no terms left in the array
+      leaves = true;
+      if (bc.state == 4) erase.push_back(bc.id);
+      else bc.state = 3;
+    }
+    if (!leaves) {
+      keep_order.push_back(bc.id);
+      for (uint32_t j = 0; j < bc.n; ++j) keep_so.push_back(keep_so.back() + (b->so[s0 + j + 1] - b->so[s0 + j]));
+    }
+    s0 += bc.n;
+  }
+  for (uint64_t id : erase) b->circs.erase(id);
+  bool still_active = false;
+  for (uint64_t id : keep_order) still_active |= b->circs.at(id).state == 1;
+  if (!still_active) {  // every remaining circuit has handed over its result: empty the array
+    for (uint64_t id : keep_order) b->circs.at(id).state = 3;
+    keep_order.clear();
+    keep_so.assign(1, 0);
+    c->T = 0;
+  }
+  // the dropped circuits hold no terms any more, so the kept segments stay contiguous
+  b->order.swap(keep_order);
+  b->so.swap(keep_so);
+  if (n_active) *n_active = active_count(b);
+  return QIMAX_OK;
+}
+
+qimax_status qimax_batch_run(qimax_batch* b) {
+  if (!b) return QIMAX_EINVAL;
+  size_t act = 1;
+  while (act) QCHK(qimax_batch_step(b, &act));
+  return QIMAX_OK;
+}
+
+qimax_status qimax_batch_poll(qimax_batch* b, uint64_t* ids, size_t cap, size_t* n) {
+  if (!b || !n) return QIMAX_EINVAL;
+  *n = b->done.size();
+  if (!ids || cap < b->done.size()) return QIMAX_OK;
+  std::copy(b->done.begin(), b->done.end(), ids);
+  b->done.clear();
+  return QIMAX_OK;
+}
+
+qimax_status qimax_batch_fetch(qimax_batch* b, uint64_t id, uint64_t* gen_off, uint64_t* keys, double* w, size_t cap,
+                               size_t* T) {
+  if (!b || !T) return QIMAX_EINVAL;
+  auto it = b->circs.find(id);
+  if (it == b->circs.end()) return bfail(b, QIMAX_EINVAL, "unknown circuit id");
+  BatchCirc& bc = it->second;
+  if (bc.state < 2) return bfail(b, QIMAX_ESTATE, "circuit not finished");
+  *T = bc.res_w.size();
+  if (cap < bc.res_w.size()) return QIMAX_OK;
+  if (!gen_off || (*T && (!keys || !w))) return bfail(b, QIMAX_EINVAL, "output buffers are NULL");
+  std::copy(bc.res_off.begin(), bc.res_off.end(), gen_off);
+  std::copy(bc.res_key.begin(), bc.res_key.end(), keys);
+  std::copy(bc.res_w.begin(), bc.res_w.end(), w);
+  if (bc.state == 3) {
+    b->circs.erase(it);
+  } else {
+    bc.res_off.clear(); bc.res_key.clear(); bc.res_w.clear();
+    bc.state = 4;  // taken; its terms leave the array next round, then the record goes
+  }
+  return QIMAX_OK;
+}
+
+qimax_status qimax_batch_info(const qimax_batch* b, qimax_batch_info_t* out) {
+  if (!b || !out) return QIMAX_EINVAL;
+  out->queued = b->queue.size();
+  out->active = 0;
+  for (uint64_t id : b->order)
+    if (b->circs.at(id).state == 1) ++out->active;
+  out->finished = b->done.size();
+  out->rounds = b->rounds;
+  out->terms = b->so.back();
+  out->term_updates = b->c->st.term_updates;
+  out->alloc_bytes = b->c->alloc_bytes;
+  out->peak_bytes = b->c->peak_bytes;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_batch_circuit_updates(const qimax_batch* b, uint64_t id, uint64_t* updates) {
+  if (!b || !updates) return QIMAX_EINVAL;
+  auto it = b->circs.find(id);
+  if (it == b->circs.end()) return QIMAX_EINVAL;
+  *updates = it->second.updates;
+  return QIMAX_OK;
+}
+
+qimax_ctx* qimax_batch_context(qimax_batch* b) { return b ? b->c : nullptr; }
+
+const char* qimax_batch_last_error(const qimax_batch* b) { return b ? b->c->last_error.c_str() : ""; }
+
+void qimax_batch_destroy(qimax_batch* b) {
+  if (!b) return;
+  qimax_destroy(b->c);
+  delete b;
 }
 
 }  // extern "C"

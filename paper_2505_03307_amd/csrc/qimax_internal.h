@@ -62,6 +62,18 @@ struct PassArgs {
   uint32_t nA, nE1, nE2, nB;
   ChainTable tA, tB;       // used instead of the op lists when useA / useB is set
   uint32_t useA, useB;
+  uint32_t drop;           // the entry's terms leave the array (f = 0)
+  uint32_t pad;
+  double thr;              // merge keeps |w| > thr
+};
+
+// A chain of permutation ops to compile into a ChainTable.
+struct TableJob {
+  const PermDesc* ops;
+  uint32_t n_ops;
+  uint32_t pad;
+  void* tab_key;
+  uint8_t* tab_neg;
 };
 
 constexpr int kChainTableMin = 12;  // chains at least this long are compiled into tables
@@ -133,8 +145,9 @@ void prof_destroy(Prof* p);
 hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, uint32_t n,
                        hipStream_t s, Prof* prof = nullptr);
 
-hipError_t launch_count(int KC, const void* keys, uint64_t T, const PassArgs& pa, uint32_t* cnt,
-                        uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+hipError_t launch_count(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
+                        const uint32_t* seg_entry, uint32_t* cnt, uint32_t* err, hipStream_t s,
+                        Prof* prof = nullptr);
 
 // out[i] = exclusive prefix sum of in[0..i-1] for i in [0, N]; out has N+1 entries.
 // tmp must hold scan_tmp_words(N) uint64 words.
@@ -148,9 +161,12 @@ hipError_t launch_scan_u64(const uint64_t* in, uint64_t* out, uint64_t N, uint64
 hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint64_t* dst,
                              uint32_t S1, hipStream_t s, Prof* prof = nullptr);
 
-hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in,
-                         const uint64_t* off, uint64_t T_img, const PassArgs& pa, void* keys_out,
-                         void* w_out, uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+// Images of each tile of tl (segment-aligned, at most kExpandTile each). any_tables: some
+// entry uses chain tables (sizes the dynamic LDS).
+hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const uint64_t* off,
+                         uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
+                         bool any_tables, void* keys_out, void* w_out, uint32_t* err, hipStream_t s,
+                         Prof* prof = nullptr);
 
 // One LSD radix pass over digit `shift` of every segment, stable, segment-local.
 // hist must hold kRadix * n_blocks uint64 words; tmp scan_tmp_words(kRadix * n_blocks).
@@ -173,14 +189,17 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 // Segmented sum of equal adjacent keys; keeps sums with |w| > thr (thr < 0 keeps
 // everything non-zero); compacts. seg_off_out[s] for s in [0, n_segs].
 // blk_cnt / blk_off must hold n_blocks (+1) words.
-hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in,
-                        uint64_t T, const Tiling& tl, double thr, void* keys_out, void* w_out,
-                        uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
+hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, uint64_t T,
+                        const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out, void* w_out,
+                        uint64_t out_cap, uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
                         uint32_t* err, hipStream_t s, Prof* prof = nullptr);
 
-// Compile a chain of permutation ops into a ChainTable (nbytes = key bytes).
-hipError_t launch_build_table(int KC, const PermDesc* ops, uint32_t n_ops, void* tab_key, uint8_t* tab_neg,
-                              hipStream_t s, Prof* prof = nullptr);
+// Compile chains of permutation ops into ChainTables, one job per chain (jobs in device memory).
+hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hipStream_t s, Prof* prof = nullptr);
+
+// Z_j of n_circ new circuits: circuit c's nq[c] terms are written from position dst[c].
+hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t* nq, const uint64_t* dst,
+                            uint32_t n_circ, hipStream_t s);
 
 // Weights to FP64 (readout).
 hipError_t launch_weights_to_f64(int WP, const void* w, double* out, uint64_t T, hipStream_t s, Prof* prof = nullptr);

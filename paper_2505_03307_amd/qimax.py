@@ -39,12 +39,27 @@ class Stats(ctypes.Structure):
                 ("terms", "passes", "term_updates", "images", "sort_elems", "peak_bytes", "alloc_bytes")]
 
 
+class CircuitC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("gate", ctypes.POINTER(ctypes.c_uint8)), ("q0", ctypes.POINTER(ctypes.c_uint32)),
+                ("q1", ctypes.POINTER(ctypes.c_uint32)), ("theta", ctypes.POINTER(ctypes.c_double)),
+                ("m", ctypes.c_size_t), ("layer_end", ctypes.POINTER(ctypes.c_uint64)), ("n_layers", ctypes.c_size_t),
+                ("prune_eps", ctypes.c_double)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in
+                ("queued", "active", "finished", "rounds", "terms", "term_updates", "alloc_bytes", "peak_bytes")]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double)]
 
 
-EXPORTS = ["qimax_default_opts", "qimax_create", "qimax_reset", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
+EXPORTS = ["qimax_batch_create", "qimax_batch_submit", "qimax_batch_step", "qimax_batch_run", "qimax_batch_poll",
+           "qimax_batch_fetch", "qimax_batch_info", "qimax_batch_circuit_updates", "qimax_batch_context",
+           "qimax_batch_last_error", "qimax_batch_destroy",
+           "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
            "qimax_num_terms", "qimax_get_generators", "qimax_expect", "qimax_get_stats", "qimax_sync",
            "qimax_profile", "qimax_profile_read", "qimax_last_error", "qimax_destroy"]
 
@@ -86,8 +101,23 @@ def load():
     lib.qimax_last_error.restype = ctypes.c_char_p
     lib.qimax_destroy.argtypes = [P]
     lib.qimax_destroy.restype = None
+    lib.qimax_batch_create.argtypes = [ctypes.POINTER(Opts), ctypes.POINTER(P)]
+    lib.qimax_batch_submit.argtypes = [P, ctypes.POINTER(CircuitC), u64p]
+    lib.qimax_batch_step.argtypes = [P, szp]
+    lib.qimax_batch_run.argtypes = [P]
+    lib.qimax_batch_poll.argtypes = [P, u64p, ctypes.c_size_t, szp]
+    lib.qimax_batch_fetch.argtypes = [P, ctypes.c_uint64, u64p, u64p, dp, ctypes.c_size_t, szp]
+    lib.qimax_batch_info.argtypes = [P, ctypes.POINTER(BatchInfo)]
+    lib.qimax_batch_circuit_updates.argtypes = [P, ctypes.c_uint64, u64p]
+    lib.qimax_batch_context.argtypes = [P]
+    lib.qimax_batch_context.restype = P
+    lib.qimax_batch_last_error.argtypes = [P]
+    lib.qimax_batch_last_error.restype = ctypes.c_char_p
+    lib.qimax_batch_destroy.argtypes = [P]
+    lib.qimax_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("qimax_default_opts", "qimax_last_error", "qimax_destroy"):
+        if name not in ("qimax_default_opts", "qimax_last_error", "qimax_destroy", "qimax_batch_context",
+                        "qimax_batch_last_error", "qimax_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -249,5 +279,121 @@ class Simulator:
         arr = (KernelTime * 32)()
         n = ctypes.c_size_t()
         self._check(lib.qimax_profile_read(self._h, arr, 32, ctypes.byref(n)))
+        return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
+                                        "alg_bytes": float(arr[i].alg_bytes)} for i in range(n.value)}
+
+
+class Batch:
+    """Many circuits propagated together (one qimax_batch): every step advances each active
+    circuit by one pass in one set of kernel launches; circuits may join at any step."""
+
+    def __init__(self, precision: int = 64, fp32_merge: int = 0, mem_cap_bytes: int = 0, stream: int | None = None,
+                 device: int = -1):
+        lib = load()
+        o = Opts()
+        lib.qimax_default_opts(ctypes.byref(o))
+        o.precision, o.fp32_merge, o.mem_cap_bytes, o.device = int(precision), int(fp32_merge), int(mem_cap_bytes), int(device)
+        o.hip_stream = stream
+        h = ctypes.c_void_p()
+        st = lib.qimax_batch_create(ctypes.byref(o), ctypes.byref(h))
+        if st != 0:
+            raise QimaxError(st, lib.qimax_last_error(None).decode())
+        self._h = h
+        self.precision = precision
+        self._n = {}
+
+    def _check(self, st: int):
+        if st != 0:
+            raise QimaxError(st, load().qimax_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().qimax_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, circuit) -> int:
+        """Queue a workloads.Circuit (its layers and eps); returns its id."""
+        g, a, b, t = _instr(circuit)
+        ends = np.ascontiguousarray(circuit.layer_end, dtype=np.uint64)
+        cc = CircuitC()
+        cc.n = int(circuit.n)
+        cc.gate, cc.q0, cc.q1, cc.theta = _p(g, ctypes.c_uint8), _p(a, ctypes.c_uint32), _p(b, ctypes.c_uint32), _p(t, ctypes.c_double)
+        cc.m = g.size
+        cc.layer_end = _p(ends, ctypes.c_uint64)
+        cc.n_layers = ends.size
+        cc.prune_eps = float(circuit.eps)
+        cid = ctypes.c_uint64()
+        self._check(load().qimax_batch_submit(self._h, ctypes.byref(cc), ctypes.byref(cid)))
+        self._n[cid.value] = int(circuit.n)
+        return cid.value
+
+    def step(self) -> int:
+        act = ctypes.c_size_t()
+        self._check(load().qimax_batch_step(self._h, ctypes.byref(act)))
+        return act.value
+
+    def run(self):
+        self._check(load().qimax_batch_run(self._h))
+        return self
+
+    def poll(self) -> list:
+        lib = load()
+        n = ctypes.c_size_t()
+        self._check(lib.qimax_batch_poll(self._h, None, 0, ctypes.byref(n)))
+        ids = np.zeros(max(n.value, 1), dtype=np.uint64)
+        self._check(lib.qimax_batch_poll(self._h, _p(ids, ctypes.c_uint64), ids.size, ctypes.byref(n)))
+        return [int(x) for x in ids[:n.value]]
+
+    def fetch(self, cid: int):
+        """(gen_off, keys [T, 1], weights) of a finished circuit; releases it."""
+        lib = load()
+        T = ctypes.c_size_t()
+        self._check(lib.qimax_batch_fetch(self._h, int(cid), None, None, None, 0, ctypes.byref(T)))
+        n = self._n.pop(int(cid))
+        off = np.zeros(n + 1, dtype=np.uint64)
+        keys = np.zeros((max(T.value, 1), 1), dtype=np.uint64)
+        w = np.zeros(max(T.value, 1), dtype=np.float64)
+        self._check(lib.qimax_batch_fetch(self._h, int(cid), _p(off, ctypes.c_uint64), _p(keys, ctypes.c_uint64),
+                                          _p(w, ctypes.c_double), T.value, ctypes.byref(T)))
+        return off, keys[:T.value], w[:T.value]
+
+    def info(self) -> dict:
+        s = BatchInfo()
+        self._check(load().qimax_batch_info(self._h, ctypes.byref(s)))
+        return {k: int(getattr(s, k)) for k, _ in BatchInfo._fields_}
+
+    def circuit_updates(self, cid: int) -> int:
+        u = ctypes.c_uint64()
+        self._check(load().qimax_batch_circuit_updates(self._h, int(cid), ctypes.byref(u)))
+        return u.value
+
+    def _ctx(self):
+        return load().qimax_batch_context(self._h)
+
+    def sync(self):
+        st = load().qimax_sync(self._ctx())
+        if st != 0:
+            raise QimaxError(st, "sync")
+
+    def profile(self, enable: bool):
+        load().qimax_profile(self._ctx(), int(bool(enable)))
+
+    def profile_read(self) -> dict:
+        lib = load()
+        arr = (KernelTime * 32)()
+        n = ctypes.c_size_t()
+        lib.qimax_profile_read(self._ctx(), arr, 32, ctypes.byref(n))
         return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
                                         "alg_bytes": float(arr[i].alg_bytes)} for i in range(n.value)}

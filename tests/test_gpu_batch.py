@@ -1,0 +1,92 @@
+"""Batches of circuits (one qimax_batch): every result equals the single-circuit result
+bit for bit and matches the oracle; circuits can join a running batch."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_03307_amd import workloads as W
+from paper_2505_03307_amd.qimax import Batch, QimaxError, Simulator
+
+from _compare import compare_fp64, oracle_arrays
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[batch]", *a, file=sys.stderr, flush=True)
+
+
+def mixed_circuits():
+    cs = [W.c1_random_hst(s) for s in range(3)]
+    cs += [W.c2_clifford_rz(seed=s, n=n, depth=d, n_rz=k) for s, (n, d, k) in enumerate([(16, 60, 10), (24, 80, 14), (32, 120, 18)])]
+    cs += [W.c3_hea(seed=s, n=n, layers=2, eps=e) for s, (n, e) in enumerate([(4, 0.0), (7, 1e-3), (9, 1e-9)])]
+    cs += [W.random_layered(7, 5, layers=3, gates_per_layer=30)]
+    cs += [W.random_circuit(8, 6, 0)]  # empty circuit
+    return cs
+
+
+def alone(c, **kw):
+    with Simulator(c.n, prune_eps=c.eps, **kw) as s:
+        s.run(c)
+        return s.generators()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_batch_equals_alone_bit_for_bit(precision):
+    cs = mixed_circuits()
+    say("batch of", len(cs), "precision", precision)
+    with Batch(precision=precision) as b:
+        ids = [b.submit(c) for c in cs]
+        b.run()
+        done = set(b.poll())
+        assert done == set(ids)
+        for c, cid in zip(cs, ids):
+            got = b.fetch(cid)
+            ref = alone(c, precision=precision)
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y), c.name
+
+
+def test_batch_matches_oracle():
+    cs = mixed_circuits()
+    with Batch() as b:
+        ids = [b.submit(c) for c in cs]
+        b.run()
+        for c, cid in zip(cs, ids):
+            compare_fp64(b.fetch(cid), oracle_arrays(oracle.propagate(c), c.n), label=c.name)
+
+
+def test_circuits_join_a_running_batch():
+    cs = mixed_circuits()
+    with Batch() as b:
+        first = [b.submit(c) for c in cs[:4]]
+        b.step()
+        b.step()
+        later = [b.submit(c) for c in cs[4:]]
+        steps = 0
+        while b.step():
+            steps += 1
+            assert steps < 10000
+        for c, cid in zip(cs, first + later):
+            got = b.fetch(cid)
+            ref = alone(c)
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y), c.name
+        info = b.info()
+        assert info["active"] == 0 and info["queued"] == 0 and info["terms"] == 0
+
+
+def test_batch_rejects_bad_circuits():
+    with Batch() as b:
+        bad = W.random_circuit(1, 40, 10)
+        with pytest.raises(QimaxError, match="ETOOLARGE"):
+            b.submit(bad)
+        c = W.c1_random_hst(0)
+        c.q0 = c.q0.copy()
+        c.q0[3] = 99
+        with pytest.raises(QimaxError, match="EINVAL"):
+            b.submit(c)
