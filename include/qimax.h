@@ -10,7 +10,7 @@
  * Keys are the paper's base-4 Pauli index (Sec. III-B): digit d_j of qubit j in
  * {I=0, X=1, Y=2, Z=3}, key = sum_j d_j 4^(n-1-j), qubit 0 the most significant digit.
  * For n <= 32 a key is one uint64 word; for 32 < n <= 64 it is two words, word 0 the
- * low 64 bits. (This release implements n <= 32.)
+ * low 64 bits. On the device keys are 32-, 64- or 128-bit integers (n <= 16, 32, 64).
  *
  * Threading: a context is not thread-safe; distinct contexts are independent.
  * Errors: every call returns a qimax_status; no exception crosses this boundary.
@@ -78,7 +78,7 @@ typedef struct {
 
 /* Creates a context on the device holding the n generators Z_0 .. Z_{n-1} of |0^n>
  * (Sec. II-A; the initial simple form of Sec. IV: weights all 1, every digit string a
- * single Z). 1 <= n <= 32 in this release (QIMAX_ETOOLARGE beyond). opts may be NULL
+ * single Z). 1 <= n <= 64 (QIMAX_ETOOLARGE beyond). opts may be NULL
  * for the defaults. On success *out owns all device memory of the context. */
 qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out);
 
@@ -117,7 +117,7 @@ qimax_status qimax_num_terms(qimax_ctx* ctx, uint64_t* T);
 
 /* Copies the generators to host memory (the paper's Lambda and index tensor, Alg. 2):
  * gen_off[0..n] (n+1 words, generator j owns terms gen_off[j] .. gen_off[j+1]-1),
- * keys (T*W words, W = 1 for n <= 32) and weights as FP64. Terms come out ascending by
+ * keys (T*W words, W = 1 for n <= 32, 2 for n <= 64) and weights as FP64. Terms come out ascending by
  * key within each generator. Two-call size query: with cap < T only *T is written
  * (gen_off, keys and w may then be NULL) and QIMAX_OK is returned. */
 qimax_status qimax_get_generators(qimax_ctx* ctx, uint64_t* gen_off, uint64_t* keys, double* w,
@@ -163,7 +163,7 @@ qimax_status qimax_profile(qimax_ctx* ctx, int enable);
 qimax_status qimax_profile_read(qimax_ctx* ctx, qimax_kernel_time* out, size_t cap, size_t* n);
 
 /* ------------------------------------------------------------------ batches of circuits
- * A batch holds the generators of many circuits (each with its own n <= 32, layers and
+ * A batch holds the generators of many circuits (each with its own n <= max_n, layers and
  * prune threshold) in one device term array. Every qimax_batch_step advances each active
  * circuit by one propagation pass, all circuits together in one set of kernel launches, so
  * small circuits share launches instead of paying them one by one (multi-circuit execution
@@ -175,7 +175,7 @@ qimax_status qimax_profile_read(qimax_ctx* ctx, qimax_kernel_time* out, size_t c
 typedef struct qimax_batch qimax_batch;
 
 typedef struct {
-  uint32_t n;               /* qubits, 1..32                                              */
+  uint32_t n;               /* qubits, 1..max_n of the batch                              */
   const uint8_t* gate;      /* instruction arrays as for qimax_apply_circuit (host memory) */
   const uint32_t* q0;
   const uint32_t* q1;
@@ -191,8 +191,9 @@ typedef struct {
 } qimax_batch_info_t;
 
 /* opts: precision, fp32_merge, mem_cap_bytes, hip_stream, device apply to the whole batch
- * (validate and prune_eps are per circuit). */
-qimax_status qimax_batch_create(const qimax_opts* opts, qimax_batch** out);
+ * (prune_eps is per circuit). max_n: the largest n the batch accepts (<= 32: 64-bit keys;
+ * <= 64: 128-bit keys; group circuits by key class for speed). */
+qimax_status qimax_batch_create(const qimax_opts* opts, uint32_t max_n, qimax_batch** out);
 /* Groups and plans the circuit (inputs are copied) and queues it; *id names it. */
 qimax_status qimax_batch_submit(qimax_batch* b, const qimax_circuit* c, uint64_t* id);
 /* Admits queued circuits, then runs one pass of every active circuit. *n_active (may be

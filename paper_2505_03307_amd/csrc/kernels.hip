@@ -43,18 +43,28 @@ __device__ __forceinline__ K apply_perm(K key, const PermDesc& p, uint32_t& neg)
 // Phase exponent (mod 4) of the product a*b of two Pauli strings given as digit keys:
 // per qubit XY = iZ, YZ = iX, ZX = iY (+1) and the reverse orders (-1).
 template <typename K>
+__device__ __forceinline__ K even_bits() {
+  if constexpr (sizeof(K) > 8) return ((K)0x5555555555555555ull << 64) | (K)0x5555555555555555ull;
+  else return (K)0x5555555555555555ull;
+}
+
+template <typename K>
+__device__ __forceinline__ int popc_k(K x) {
+  if constexpr (sizeof(K) > 8) return __popcll((uint64_t)x) + __popcll((uint64_t)(x >> 64));
+  else if constexpr (sizeof(K) == 8) return __popcll(x);
+  else return __popc(x);
+}
+
+template <typename K>
 __device__ __forceinline__ uint32_t product_phase(K a, K b) {
-  constexpr K kEven = (K)0x5555555555555555ull;
+  const K kEven = even_bits<K>();
   const K al = a & kEven, ah = (a >> 1) & kEven;
   const K bl = b & kEven, bh = (b >> 1) & kEven;
   const K xa = al & ~ah, ya = ah & ~al, za = ah & al;
   const K xb = bl & ~bh, yb = bh & ~bl, zb = bh & bl;
   const K plus = (xa & yb) | (ya & zb) | (za & xb);
   const K minus = (xa & zb) | (ya & xb) | (za & yb);
-  int p, m;
-  if constexpr (sizeof(K) == 8) { p = __popcll(plus); m = __popcll(minus); }
-  else { p = __popc(plus); m = __popc(minus); }
-  return (uint32_t)(p - m) & 3u;
+  return (uint32_t)(popc_k(plus) - popc_k(minus)) & 3u;
 }
 
 // Image of a key under a compiled Clifford chain (tables staged in LDS by the caller).
@@ -144,8 +154,9 @@ template <typename K>
 __global__ void __launch_bounds__(256) k_count(const K* __restrict__ keys, Tiling tl, const PassArgs* __restrict__ pas,
                                                const uint32_t* __restrict__ seg_entry, uint32_t* __restrict__ cnt,
                                                uint32_t* err) {
-  __shared__ K tk[sizeof(K) * 256];
-  __shared__ uint8_t tn[sizeof(K) * 256];
+  constexpr int kTabN = sizeof(K) <= 8 ? (int)sizeof(K) * 256 : 1;  // no tables for 16-byte keys
+  __shared__ K tk[kTabN];
+  __shared__ uint8_t tn[kTabN];
   const uint32_t b = blockIdx.x;
   const PassArgs pa = pas[seg_entry[tl.blk_seg[b]]];
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
@@ -439,7 +450,8 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   constexpr int kWaves = kSortBlock / 64;
   constexpr int kRounds = kSortItems;                 // rounds per wave
   constexpr int kWaveSpan = 64 * kRounds;             // tile elements per wave
-  __shared__ uint64_t stage[kSortTile];               // keys, then weights (as raw 64-bit)
+  __shared__ uint64_t stage[kSortTile];               // key words, then weights (as raw 64-bit)
+  __shared__ uint8_t sdig[kSortTile];                  // digit of each sorted slot
   __shared__ uint32_t wrun[kWaves][kRadix];            // per-wave running digit counts
   __shared__ uint32_t dstart[kRadix];                  // tile-local start of each digit
   __shared__ uint64_t gbase[kRadix];                   // global destination of each digit
@@ -523,7 +535,7 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   dstart[d] = (uint32_t)ds;
   if constexpr (!kSweep) gbase[d] = tile_cnt ? hist_off[hist_pos(tl, b, d)] : 0;
   __syncthreads();
-  // stage keys at their tile-local sorted positions
+  // stage keys at their tile-local sorted positions (one 64-bit word of the key per round)
   uint32_t pos[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -531,25 +543,41 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
     if (li < n_tile) {
       const uint32_t dd = (uint32_t)(key[r] >> shift) & (kRadix - 1);
       pos[r] = dstart[dd] + wrun[wid][dd] + rank[r];
-      if (pos[r] < (uint32_t)kSortTile) stage[pos[r]] = (uint64_t)key[r];
-      else atomicOr(err, kErrIndex);
+      if (pos[r] < (uint32_t)kSortTile) {
+        stage[pos[r]] = (uint64_t)key[r];
+        sdig[pos[r]] = (uint8_t)dd;
+      } else {
+        atomicOr(err, kErrIndex);
+      }
     } else {
       pos[r] = 0xFFFFFFFFu;
     }
   }
   __syncthreads();
   // write keys out in sorted tile order (coalesced within each digit run)
-  uint32_t outd[kRounds];
+  constexpr int kWords = sizeof(K) > 8 ? 2 : 1;
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const uint32_t j = r * kSortBlock + threadIdx.x;
-    outd[r] = 0xFFFFFFFFu;
-    if (j < n_tile) {
-      const K kk = (K)stage[j];
-      const uint32_t dd = (uint32_t)(kk >> shift) & (kRadix - 1);
-      outd[r] = dd;
-      const uint64_t dst = gbase[dd] + (j - dstart[dd]);
-      if (dst < T) keys_out[dst] = kk; else atomicOr(err, kErrIndex);
+  for (int word = 0; word < kWords; ++word) {
+    if (word) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r)
+        if (pos[r] < (uint32_t)kSortTile) stage[pos[r]] = (uint64_t)(key[r] >> (64 * word));
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint32_t j = r * kSortBlock + threadIdx.x;
+      if (j < n_tile) {
+        const uint32_t dd = sdig[j];
+        const uint64_t dst = gbase[dd] + (j - dstart[dd]);
+        if (dst < T) {
+          if constexpr (kWords == 1) keys_out[dst] = (K)stage[j];
+          else ((uint64_t*)keys_out)[2 * dst + word] = stage[j];
+        } else {
+          atomicOr(err, kErrIndex);
+        }
+      }
     }
   }
   __syncthreads();
@@ -565,7 +593,7 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t j = r * kSortBlock + threadIdx.x;
     if (j < n_tile) {
-      const uint32_t dd = outd[r];
+      const uint32_t dd = sdig[j];
       const uint64_t dst = gbase[dd] + (j - dstart[dd]);
       W v;
       if constexpr (sizeof(W) == 8) v = __longlong_as_double((long long)stage[j]);
@@ -579,10 +607,10 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict__ keys, Tiling tl, uint32_t n_pass,
                                                              uint32_t* __restrict__ ghist) {
-  constexpr int kWaves = kSortBlock / 64;
+  constexpr int kWaves = sizeof(K) <= 8 ? kSortBlock / 64 : 1;  // private copies per wave
   constexpr int kMaxPass = (int)sizeof(K);
   __shared__ uint32_t h[kWaves][kMaxPass][kRadix];
-  const int wid = threadIdx.x >> 6;
+  const int wid = (threadIdx.x >> 6) % kWaves;
   for (int i = threadIdx.x; i < kWaves * kMaxPass * kRadix; i += kSortBlock) (&h[0][0][0])[i] = 0;
   __syncthreads();
   const uint32_t b = blockIdx.x;
@@ -669,7 +697,8 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
         const uint32_t* __restrict__ seg_entry, int fp64_acc, uint32_t* __restrict__ blk_cnt,
         const uint64_t* __restrict__ blk_off, K* __restrict__ keys_out, W* __restrict__ w_out, uint64_t out_cap,
         uint32_t* err) {
-  __shared__ K sk[kSortTile + 1];
+  constexpr bool kLds = sizeof(K) <= 8;  // 16-byte keys are read from global memory
+  __shared__ K sk[kLds ? kSortTile + 1 : 1];
   __shared__ uint64_t scan_sh[kSortBlock / 64];
   const uint32_t b = blockIdx.x;
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
@@ -678,10 +707,16 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
   const uint64_t seg_begin = tl.blk_begin[tl.seg_blk[s]];
   const uint64_t seg_end = tl.blk_end[tl.seg_blk[s + 1] - 1];
   const uint32_t n_tile = (uint32_t)(end - begin);
-  // sk[0] holds the key before the tile (if inside the segment), sk[1 + i] the tile
-  for (uint32_t i = threadIdx.x; i < n_tile; i += kSortBlock) sk[1 + i] = keys[begin + i];
-  if (threadIdx.x == 0 && begin > seg_begin) sk[0] = keys[begin - 1];
-  __syncthreads();
+  // key(i) for i in [-1, n_tile): sk[0] holds the key before the tile (if inside the segment)
+  if constexpr (kLds) {
+    for (uint32_t i = threadIdx.x; i < n_tile; i += kSortBlock) sk[1 + i] = keys[begin + i];
+    if (threadIdx.x == 0 && begin > seg_begin) sk[0] = keys[begin - 1];
+    __syncthreads();
+  }
+  auto key_at = [&](uint32_t i1) -> K {  // i1 = tile-local index + 1
+    if constexpr (kLds) return sk[i1];
+    else return keys[begin + i1 - 1];
+  };
   const uint32_t i0 = threadIdx.x * kSortItems;
   uint32_t keep = 0;
   uint32_t keep_mask = 0;
@@ -692,8 +727,8 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
     const uint32_t li = i0 + k;
     if (li >= n_tile) continue;
     const uint64_t gi = begin + li;
-    const K key = sk[1 + li];
-    const bool head = (gi == seg_begin) || (sk[li] != key);
+    const K key = key_at(1 + li);
+    const bool head = (gi == seg_begin) || (key_at(li) != key);
     if (!head) continue;
     const W v = run_sum(keys, w, gi, seg_end, key, fp64_acc);
     if (fabs((double)v) > thr) {
@@ -712,7 +747,7 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
     for (int k = 0; k < kSortItems; ++k) {
       if (!(keep_mask & (1u << k))) continue;
       if (o < out_cap) {
-        keys_out[o] = sk[1 + i0 + k];
+        keys_out[o] = key_at(1 + i0 + k);
         w_out[o] = sums[k];
       } else {
         atomicOr(err, kErrIndex);
@@ -891,10 +926,11 @@ void prof_destroy(Prof* p) {
   p->pool.clear();
 }
 
-#define QIMAX_DISPATCH_K(KC, ...)                    \
-  do {                                               \
-    if ((KC) == 0) { using K = uint32_t; __VA_ARGS__; } \
-    else { using K = uint64_t; __VA_ARGS__; }        \
+#define QIMAX_DISPATCH_K(KC, ...)                                    \
+  do {                                                               \
+    if ((KC) == 0) { using K = uint32_t; __VA_ARGS__; }              \
+    else if ((KC) == 1) { using K = uint64_t; __VA_ARGS__; }         \
+    else { using K = unsigned __int128; __VA_ARGS__; }               \
   } while (0)
 
 hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, uint32_t n, hipStream_t s,
@@ -913,7 +949,7 @@ hipError_t launch_count(int KC, const void* keys, uint64_t T, const Tiling& tl, 
   if (T == 0 || tl.n_blocks == 0) return hipSuccess;
   hipEvent_t ev = prof_begin(prof, s);
   QIMAX_DISPATCH_K(KC, { k_count<K><<<tl.n_blocks, 256, 0, s>>>((const K*)keys, tl, pas, seg_entry, cnt, err); });
-  prof_end(prof, s, ev, kKCount, (double)T * ((KC == 0 ? 4 : 8) + 4));
+  prof_end(prof, s, ev, kKCount, (double)T * ((4 << KC) + 4));
   return hipGetLastError();
 }
 
@@ -965,7 +1001,7 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64
       k_expand<K, 32><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, (const float*)w, T_in, off, T_img, tl,
                                                               pas, seg_entry, (K*)keys_out, (float*)w_out, err);
   });
-  const double per = (KC == 0 ? 4 : 8) + (WP == 64 ? 8 : 4);
+  const double per = (4 << KC) + (WP == 64 ? 8 : 4);
   prof_end(prof, s, ev, kKExpand, per * (double)(T_in + T_img) + 8.0 * (double)T_in);
   return hipGetLastError();
 }
@@ -975,7 +1011,7 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
                             uint64_t* tmp, uint32_t* err, hipStream_t s, Prof* prof) {
   if (T == 0 || tl.n_blocks == 0) return hipSuccess;
   const uint64_t hsize = (uint64_t)kRadix * tl.n_blocks;
-  const double kb = KC == 0 ? 4 : 8, wb = WP == 64 ? 8 : 4;
+  const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   QIMAX_DISPATCH_K(KC, {
     hipEvent_t ev = prof_begin(prof, s);
     k_sort_hist<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys_in, shift, tl, hist, hsize, err);
@@ -1004,7 +1040,7 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
   if (T == 0 || tl.n_blocks == 0) return hipSuccess;
   const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
   const uint64_t nh = (uint64_t)tl.n_segs * n_pass * kRadix;
-  const double kb = KC == 0 ? 4 : 8, wb = WP == 64 ? 8 : 4;
+  const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   k_fill_u32<<<grid_for(nh, 256), 256, 0, s>>>(ghist, nh, 0u);
   k_fill_u32<<<1, 64, 0, s>>>(tile_ctr, n_pass, 0u);
   QIMAX_DISPATCH_K(KC, {
@@ -1048,7 +1084,7 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
                                                                    tl.n_segs + 1);
     return hipGetLastError();
   }
-  const double kb = KC == 0 ? 4 : 8, wb = WP == 64 ? 8 : 4;
+  const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   QIMAX_DISPATCH_K(KC, {
     hipEvent_t ev = prof_begin(prof, s);
     if (WP == 64) {

@@ -524,8 +524,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   size_t n_jobs = 0;
   bool any_tables = false;
   uint32_t max_n = 1;
-  auto tableable = [](const std::vector<const HostOp*>& v) {
-    if ((int)v.size() < kChainTableMin) return false;
+  auto tableable = [c](const std::vector<const HostOp*>& v) {
+    if (c->kb > 8 || (int)v.size() < kChainTableMin) return false;  // no tables for 16-byte keys
     for (auto* op : v)
       if (!op->conj) return false;
     return true;
@@ -955,26 +955,48 @@ qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const 
 }
 
 // ------------------------------------------------------------------ host readout helpers
+using u128 = unsigned __int128;
+
 struct HostGens {
-  std::vector<uint64_t> off, key;
+  std::vector<uint64_t> off;
+  std::vector<u128> key;
   std::vector<double> w;
 };
+
+// Copy T keys of class KC from device memory into host u128 values.
+hipError_t keys_to_host(const qimax_ctx* c, const void* dev, uint64_t T, std::vector<u128>& out) {
+  out.resize(T);
+  if (T == 0) return hipSuccess;
+  if (c->KC == 2) return hipMemcpy(out.data(), dev, T * 16, hipMemcpyDeviceToHost);
+  if (c->KC == 1) {
+    std::vector<uint64_t> k(T);
+    hipError_t e = hipMemcpy(k.data(), dev, T * 8, hipMemcpyDeviceToHost);
+    for (uint64_t i = 0; i < T; ++i) out[i] = k[i];
+    return e;
+  }
+  std::vector<uint32_t> k(T);
+  hipError_t e = hipMemcpy(k.data(), dev, T * 4, hipMemcpyDeviceToHost);
+  for (uint64_t i = 0; i < T; ++i) out[i] = k[i];
+  return e;
+}
+
+// Keys as W little-endian uint64 words each (W = 1 for n <= 32, else 2).
+void keys_to_words(const std::vector<u128>& k, uint32_t n, uint64_t* out) {
+  const int W = n <= 32 ? 1 : 2;
+  for (size_t i = 0; i < k.size(); ++i) {
+    out[i * W] = (uint64_t)k[i];
+    if (W == 2) out[i * W + 1] = (uint64_t)(k[i] >> 64);
+  }
+}
 
 qimax_status fetch(qimax_ctx* c, HostGens& g) {
   QCHK(flush_pending(c));
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   g.off = c->h_seg;
   const uint64_t T = c->T;
-  g.key.resize(T);
   g.w.resize(T);
+  HIPCHK(c, keys_to_host(c, c->keys.p, T, g.key), "keys D2H");
   if (T == 0) return QIMAX_OK;
-  if (c->KC == 1) {
-    HIPCHK(c, hipMemcpy(g.key.data(), c->keys.p, T * 8, hipMemcpyDeviceToHost), "keys D2H");
-  } else {
-    std::vector<uint32_t> k32(T);
-    HIPCHK(c, hipMemcpy(k32.data(), c->keys.p, T * 4, hipMemcpyDeviceToHost), "keys D2H");
-    for (uint64_t i = 0; i < T; ++i) g.key[i] = k32[i];
-  }
   if (c->WP == 64) {
     HIPCHK(c, hipMemcpy(g.w.data(), c->w.p, T * 8, hipMemcpyDeviceToHost), "weights D2H");
   } else {
@@ -985,7 +1007,7 @@ qimax_status fetch(qimax_ctx* c, HostGens& g) {
   return QIMAX_OK;
 }
 
-int digit_of(uint64_t key, uint32_t n, uint32_t q) { return (int)((key >> (2 * (n - 1 - q))) & 3u); }
+int digit_of(u128 key, uint32_t n, uint32_t q) { return (int)((key >> (2 * (n - 1 - q))) & 3u); }
 
 
 // <P> when every generator is one signed Pauli string: P is +-(a product of generators)
@@ -1072,7 +1094,7 @@ qimax_status expect_state(qimax_ctx* c, const HostGens& g, const std::vector<int
   std::normal_distribution<double> nd;
   for (auto& x : v) x = cd(nd(rng), nd(rng));
   // Pauli string on a basis state: qubit q is bit (n-1-q)
-  auto apply_pauli = [&](uint64_t key, const std::vector<cd>& src, std::vector<cd>& dst, double wt, bool accumulate) {
+  auto apply_pauli = [&](u128 key, const std::vector<cd>& src, std::vector<cd>& dst, double wt, bool accumulate) {
     uint64_t xm = 0, zm = 0;
     int ny = 0;
     for (uint32_t q = 0; q < n; ++q) {
@@ -1103,8 +1125,8 @@ qimax_status expect_state(qimax_ctx* c, const HostGens& g, const std::vector<int
     const double sc = 1.0 / std::sqrt(nrm);
     for (auto& x : v) x *= sc;
   }
-  uint64_t pk = 0;
-  for (uint32_t q = 0; q < n; ++q) pk |= (uint64_t)P[q] << (2 * (n - 1 - q));
+  u128 pk = 0;
+  for (uint32_t q = 0; q < n; ++q) pk |= (u128)P[q] << (2 * (n - 1 - q));
   apply_pauli(pk, v, tmp, 1.0, false);
   cd s(0, 0);
   for (size_t i = 0; i < D; ++i) s += std::conj(v[i]) * tmp[i];
@@ -1136,14 +1158,14 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
   qimax_default_opts(&o);
   if (opts) o = *opts;
   if (n < 1) { g_create_error = "n must be >= 1"; return QIMAX_EINVAL; }
-  if (n > 32) { g_create_error = "n > 32 is not implemented"; return QIMAX_ETOOLARGE; }
+  if (n > 64) { g_create_error = "n must be <= 64"; return QIMAX_ETOOLARGE; }
   if (o.precision != 64 && o.precision != 32) { g_create_error = "precision must be 32 or 64"; return QIMAX_EINVAL; }
   if (!(o.prune_eps >= 0.0) || !std::isfinite(o.prune_eps)) { g_create_error = "prune_eps must be >= 0"; return QIMAX_EINVAL; }
   qimax_ctx* c = new (std::nothrow) qimax_ctx;
   if (!c) return QIMAX_ENOMEM;
   c->n = n;
-  c->KC = n <= 16 ? 0 : 1;
-  c->kb = c->KC == 0 ? 4 : 8;
+  c->KC = n <= 16 ? 0 : (n <= 32 ? 1 : 2);
+  c->kb = (size_t)4 << c->KC;
   c->WP = o.precision;
   c->wb = o.precision == 64 ? 8 : 4;
   c->fp64_acc = o.fp32_merge ? 1 : 0;
@@ -1269,7 +1291,7 @@ qimax_status qimax_get_generators(qimax_ctx* c, uint64_t* gen_off, uint64_t* key
   HostGens g;
   QCHK(fetch(c, g));
   std::copy(g.off.begin(), g.off.end(), gen_off);
-  std::copy(g.key.begin(), g.key.end(), keys);
+  keys_to_words(g.key, c->n, keys);
   std::copy(g.w.begin(), g.w.end(), w);
   return QIMAX_OK;
 }
@@ -1392,6 +1414,7 @@ struct BatchCirc {
 
 struct qimax_batch {
   qimax_ctx* c = nullptr;
+  uint32_t max_n = 32;
   uint64_t next_id = 1;
   std::map<uint64_t, BatchCirc> circs;
   std::vector<uint64_t> order;  // circuits whose generators are in the term array, in order
@@ -1454,10 +1477,12 @@ qimax_status plan_circuit(qimax_batch* b, const qimax_circuit* q, double eps, Ba
 
 void initial_result(BatchCirc& bc) {
   bc.res_off.resize(bc.n + 1);
-  bc.res_key.resize(bc.n);
   bc.res_w.assign(bc.n, 1.0);
   for (uint32_t j = 0; j <= bc.n; ++j) bc.res_off[j] = j;
-  for (uint32_t j = 0; j < bc.n; ++j) bc.res_key[j] = 3ull << (2 * (bc.n - 1 - j));
+  std::vector<u128> k(bc.n);
+  for (uint32_t j = 0; j < bc.n; ++j) k[j] = (u128)3 << (2 * (bc.n - 1 - j));
+  bc.res_key.resize((size_t)bc.n * (bc.n <= 32 ? 1 : 2));
+  keys_to_words(k, bc.n, bc.res_key.data());
 }
 
 // Admit the queued circuits: their Z_j terms go to the end of the term array.
@@ -1499,16 +1524,12 @@ qimax_status take_result(qimax_batch* b, BatchCirc& bc, size_t s0) {
   const uint64_t a = b->so[s0], e = b->so[s0 + bc.n];
   bc.res_off.resize(bc.n + 1);
   for (uint32_t j = 0; j <= bc.n; ++j) bc.res_off[j] = b->so[s0 + j] - a;
-  bc.res_key.resize(e - a);
   bc.res_w.resize(e - a);
+  std::vector<u128> k;
+  HIPCHK(c, keys_to_host(c, (const uint8_t*)c->keys.p + a * c->kb, e - a, k), "result");
+  bc.res_key.resize((e - a) * (bc.n <= 32 ? 1 : 2));
+  keys_to_words(k, bc.n, bc.res_key.data());
   if (e == a) return QIMAX_OK;
-  if (c->KC == 1) {
-    HIPCHK(c, hipMemcpy(bc.res_key.data(), (uint64_t*)c->keys.p + a, (e - a) * 8, hipMemcpyDeviceToHost), "result");
-  } else {
-    std::vector<uint32_t> k32(e - a);
-    HIPCHK(c, hipMemcpy(k32.data(), (uint32_t*)c->keys.p + a, (e - a) * 4, hipMemcpyDeviceToHost), "result");
-    for (size_t i = 0; i < k32.size(); ++i) bc.res_key[i] = k32[i];
-  }
   if (c->WP == 64) {
     HIPCHK(c, hipMemcpy(bc.res_w.data(), (double*)c->w.p + a, (e - a) * 8, hipMemcpyDeviceToHost), "result");
   } else {
@@ -1530,11 +1551,13 @@ size_t active_count(const qimax_batch* b) {
 
 extern "C" {
 
-qimax_status qimax_batch_create(const qimax_opts* opts, qimax_batch** out) {
+qimax_status qimax_batch_create(const qimax_opts* opts, uint32_t max_n, qimax_batch** out) {
   if (!out) return QIMAX_EINVAL;
   *out = nullptr;
+  if (max_n > 64) return QIMAX_ETOOLARGE;
   qimax_ctx* c = nullptr;
-  qimax_status s = qimax_create(32, opts, &c);  // a 32-qubit context: uint64 keys, buffers, stream
+  // the batch's context: its key class fits max_n (at least uint64 keys), buffers, stream
+  qimax_status s = qimax_create(max_n <= 32 ? 32 : 64, opts, &c);
   if (s != QIMAX_OK) return s;
   qimax_batch* b = new (std::nothrow) qimax_batch;
   if (!b) {
@@ -1542,6 +1565,7 @@ qimax_status qimax_batch_create(const qimax_opts* opts, qimax_batch** out) {
     return QIMAX_ENOMEM;
   }
   b->c = c;
+  b->max_n = max_n <= 32 ? 32 : 64;
   c->T = 0;
   c->h_seg.assign(1, 0);
   *out = b;
@@ -1552,7 +1576,8 @@ qimax_status qimax_batch_submit(qimax_batch* b, const qimax_circuit* q, uint64_t
   if (!b || !q || !id) return QIMAX_EINVAL;
   qimax_ctx* c = b->c;
   if (c->broken) return bfail(b, QIMAX_ESTATE, "batch unusable after an earlier device error");
-  if (q->n < 1 || q->n > 32) return bfail(b, q->n < 1 ? QIMAX_EINVAL : QIMAX_ETOOLARGE, "circuit n must be 1..32");
+  if (q->n < 1 || q->n > b->max_n)
+    return bfail(b, q->n < 1 ? QIMAX_EINVAL : QIMAX_ETOOLARGE, "circuit n must be 1..max_n of the batch");
   if (q->m && (!q->gate || !q->q0 || !q->q1)) return bfail(b, QIMAX_EINVAL, "instruction arrays are NULL");
   if (!(q->prune_eps >= 0.0) || !std::isfinite(q->prune_eps)) return bfail(b, QIMAX_EINVAL, "prune_eps must be >= 0");
   BatchCirc bc;

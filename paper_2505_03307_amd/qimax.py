@@ -101,7 +101,7 @@ def load():
     lib.qimax_last_error.restype = ctypes.c_char_p
     lib.qimax_destroy.argtypes = [P]
     lib.qimax_destroy.restype = None
-    lib.qimax_batch_create.argtypes = [ctypes.POINTER(Opts), ctypes.POINTER(P)]
+    lib.qimax_batch_create.argtypes = [ctypes.POINTER(Opts), ctypes.c_uint32, ctypes.POINTER(P)]
     lib.qimax_batch_submit.argtypes = [P, ctypes.POINTER(CircuitC), u64p]
     lib.qimax_batch_step.argtypes = [P, szp]
     lib.qimax_batch_run.argtypes = [P]
@@ -288,14 +288,14 @@ class Batch:
     circuit by one pass in one set of kernel launches; circuits may join at any step."""
 
     def __init__(self, precision: int = 64, fp32_merge: int = 0, mem_cap_bytes: int = 0, stream: int | None = None,
-                 device: int = -1):
+                 device: int = -1, max_n: int = 32):
         lib = load()
         o = Opts()
         lib.qimax_default_opts(ctypes.byref(o))
         o.precision, o.fp32_merge, o.mem_cap_bytes, o.device = int(precision), int(fp32_merge), int(mem_cap_bytes), int(device)
         o.hip_stream = stream
         h = ctypes.c_void_p()
-        st = lib.qimax_batch_create(ctypes.byref(o), ctypes.byref(h))
+        st = lib.qimax_batch_create(ctypes.byref(o), int(max_n), ctypes.byref(h))
         if st != 0:
             raise QimaxError(st, lib.qimax_last_error(None).decode())
         self._h = h
@@ -357,13 +357,13 @@ class Batch:
         return [int(x) for x in ids[:n.value]]
 
     def fetch(self, cid: int):
-        """(gen_off, keys [T, 1], weights) of a finished circuit; releases it."""
+        """(gen_off, keys [T, W], weights) of a finished circuit; releases it."""
         lib = load()
         T = ctypes.c_size_t()
         self._check(lib.qimax_batch_fetch(self._h, int(cid), None, None, None, 0, ctypes.byref(T)))
         n = self._n.pop(int(cid))
         off = np.zeros(n + 1, dtype=np.uint64)
-        keys = np.zeros((max(T.value, 1), 1), dtype=np.uint64)
+        keys = np.zeros((max(T.value, 1), 1 if n <= 32 else 2), dtype=np.uint64)
         w = np.zeros(max(T.value, 1), dtype=np.float64)
         self._check(lib.qimax_batch_fetch(self._h, int(cid), _p(off, ctypes.c_uint64), _p(keys, ctypes.c_uint64),
                                           _p(w, ctypes.c_double), T.value, ctypes.byref(T)))

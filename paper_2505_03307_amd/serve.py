@@ -1,0 +1,185 @@
+"""Serving loop: circuits arrive over time and are propagated with continuous batching.
+
+Requests (workloads.Circuit) arrive at given times. The server keeps one batch
+(qimax_batch) on the GPU; between steps it admits arrived requests in arrival order while
+their predicted device footprint fits the memory budget, runs one step (every admitted
+circuit advances one pass, all in one set of launches), and hands finished results back
+with their latency (arrival -> result on the host). The sequential reference serves the
+same trace one circuit at a time on a single-circuit context.
+
+The footprint predictor follows the paper's feasibility bound (Sec. IV: the number of
+Pauli strings a run can hold is limited by memory / (bytes per string)): predicted bytes =
+peak images in flight x bytes per image + terms x bytes per term, with the peak image
+count taken from the closed form of the hardware-efficient ansatz when the circuit is of
+that family (3n terms after one layer; 3^(n+1) + 9n - 21 after two, from 4*3^n + 9n - 12
+images), and otherwise from the bound min(4^n - 1, 2^(#non-Clifford gates)) per generator.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from . import workloads as W
+from .qimax import Batch, Simulator
+
+_NON_CLIFFORD = (W.Gate.T, W.Gate.TDG, W.Gate.RX, W.Gate.RY, W.Gate.RZ)
+
+
+def _hea_layers(c: W.Circuit):
+    """Number of layers if c is the Rx/Ry/Rz + CX-ladder ansatz, else None."""
+    n = c.n
+    per = 3 * n + (n - 1)
+    if c.m == 0 or c.m % per:
+        return None
+    L = c.m // per
+    g = c.gate.reshape(L, per)
+    want = np.array([W.Gate.RX, W.Gate.RY, W.Gate.RZ] * n + [W.Gate.CX] * (n - 1), dtype=np.uint8)
+    return L if np.all(g == want[None, :]) else None
+
+
+def predict_terms(c: W.Circuit):
+    """(peak images of one pass, final terms), upper bounds, for admission."""
+    n = c.n
+    L = _hea_layers(c)
+    if L == 1:
+        return 3 * n, 3 * n
+    if L == 2:
+        return 4 * 3 ** n + 9 * n - 12, 3 ** (n + 1) + 9 * n - 21
+    k = int(np.isin(c.gate, np.array(_NON_CLIFFORD, dtype=np.uint8)).sum())
+    per_gen = min(4 ** n - 1, 2 ** min(k, 62))
+    return 3 * n * per_gen, n * per_gen
+
+
+def predict_bytes(c: W.Circuit, precision: int = 32) -> int:
+    kb = 4 if c.n <= 16 else (8 if c.n <= 32 else 16)
+    kb = max(kb, 8)  # batches hold at least 64-bit keys
+    wb = 8 if precision == 64 else 4
+    img, terms = predict_terms(c)
+    # images live in two ping-pong buffers plus the merged output; count + offset per term
+    return int(img * 3 * (kb + wb) + terms * (kb + wb + 12))
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    terms: int
+    updates: int
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    """Continuous batching over one qimax_batch with admission by predicted memory."""
+
+    def __init__(self, budget_bytes: int, precision: int = 32, max_n: int = 32, keep_results: bool = False,
+                 batch=None):
+        # batch: anything with submit/step/poll/fetch/circuit_updates/close (default: a qimax_batch)
+        self.batch = batch if batch is not None else Batch(precision=precision, max_n=max_n)
+        self.precision = precision
+        self.budget = int(budget_bytes)
+        self.in_flight = {}   # batch id -> (rid, arrival, admitted, predicted bytes)
+        self.reserved = 0
+        self.keep_results = keep_results
+        self.outputs = {}
+
+    def close(self):
+        self.batch.close()
+
+    def try_admit(self, rid: int, circuit: W.Circuit, arrival: float, now: float) -> bool:
+        need = predict_bytes(circuit, self.precision)
+        if need > self.budget:
+            raise ValueError(f"request {rid} needs {need} bytes, more than the whole budget")
+        if self.in_flight and self.reserved + need > self.budget:
+            return False
+        bid = self.batch.submit(circuit)
+        self.in_flight[bid] = (rid, arrival, now, need)
+        self.reserved += need
+        return True
+
+    def step(self, clock) -> list[Result]:
+        if not self.in_flight:
+            return []
+        self.batch.step()
+        out = []
+        for bid in self.batch.poll():
+            rid, arrival, admitted, need = self.in_flight.pop(bid)
+            updates = self.batch.circuit_updates(bid)
+            res = self.batch.fetch(bid)
+            self.reserved -= need
+            if self.keep_results:
+                self.outputs[rid] = res
+            out.append(Result(rid, arrival, admitted, clock(), int(res[0][-1]), updates))
+        return out
+
+
+def serve_trace(circuits, arrivals, budget_bytes: int, precision: int = 32, keep_results: bool = False,
+                batch=None):
+    """Serve the trace in real time with continuous batching. Returns (results, server)."""
+    order = np.argsort(arrivals, kind="stable")
+    srv = Server(budget_bytes, precision, max_n=32 if max(c.n for c in circuits) <= 32 else 64,
+                 keep_results=keep_results, batch=batch)
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0  # noqa: E731
+    pending = list(order)
+    results = []
+    while pending or srv.in_flight:
+        now = clock()
+        # admit arrived requests in arrival order while their footprint fits
+        while pending and arrivals[pending[0]] <= now:
+            i = pending[0]
+            if not srv.try_admit(int(i), circuits[i], float(arrivals[i]), now):
+                break
+            pending.pop(0)
+        if srv.in_flight:
+            results.extend(srv.step(clock))
+        elif pending:
+            wait = arrivals[pending[0]] - clock()
+            if wait > 0:
+                time.sleep(min(wait, 0.01))
+    return results, srv
+
+
+def serve_sequential(circuits, arrivals, precision: int = 32, keep_results: bool = False):
+    """The plain path on the same trace: one circuit at a time, FIFO, in real time."""
+    order = np.argsort(arrivals, kind="stable")
+    t0 = time.perf_counter()
+    results, outputs = [], {}
+    sims = {}
+    for i in order:
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        c = circuits[i]
+        start = time.perf_counter() - t0
+        key = (c.n, float(c.eps))
+        if key not in sims:
+            sims[key] = Simulator(c.n, precision=precision, prune_eps=c.eps)
+        s = sims[key]
+        s.reset()
+        u0 = s.stats()["term_updates"]
+        s.run(c)
+        res = s.generators()
+        done = time.perf_counter() - t0
+        if keep_results:
+            outputs[int(i)] = res
+        results.append(Result(int(i), float(arrivals[i]), start, done, int(res[0][-1]),
+                              s.stats()["term_updates"] - u0))
+    for s in sims.values():
+        s.close()
+    return results, outputs
+
+
+def summarize(results, wall: float) -> dict:
+    lat = np.array([r.latency for r in results])
+    upd = float(sum(r.updates for r in results))
+    return {"requests": len(results), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "mean_ms": round(float(lat.mean()) * 1e3, 3), "wall_s": round(wall, 3),
+            "requests_per_s": round(len(results) / wall, 2), "term_updates_per_s": round(upd / wall, 1)}

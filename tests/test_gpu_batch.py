@@ -90,3 +90,18 @@ def test_batch_rejects_bad_circuits():
         c.q0[3] = 99
         with pytest.raises(QimaxError, match="EINVAL"):
             b.submit(c)
+
+
+def test_wide_batch_of_the_n8_to_48_family():
+    """Circuits of the 256-circuit batch recipe (n from 8 to 48) in a 64-qubit-class batch:
+    every result equals the single-circuit result bit for bit."""
+    cs = [c for c in W.c4_batch(count=24, depth_range=(30, 80), rz_range=(3, 10))]
+    say("wide batch", [c.n for c in cs])
+    with Batch(max_n=64) as b:
+        ids = [b.submit(c) for c in cs]
+        b.run()
+        for c, cid in zip(cs, ids):
+            got = b.fetch(cid)
+            ref = alone(c)
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y), c.name

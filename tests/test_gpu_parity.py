@@ -258,7 +258,7 @@ def test_memory_cap_gives_enomem_and_keeps_state():
 
 def test_create_rejects_bad_arguments():
     with pytest.raises(QimaxError, match="ETOOLARGE"):
-        Simulator(33)
+        Simulator(65)
     with pytest.raises(QimaxError, match="EINVAL"):
         Simulator(0)
     with pytest.raises(QimaxError, match="EINVAL"):
@@ -340,3 +340,30 @@ def test_expect_matches_statevector():
                 want = float(np.real(np.vdot(psi, D.apply_pauli_state(psi.copy(), c.n,
                                                                      [LETTER.index(ch) for ch in p]))))
                 assert abs(s.expect(p) - want) < 1e-9, p
+
+
+# -------------------------------------------------------------- 128-bit keys (32 < n <= 64)
+
+@pytest.mark.parametrize("n", [33, 40, 48, 64])
+def test_wide_keys_random(n):
+    c = W.random_layered(n, n, layers=2, gates_per_layer=6 * n, p_nonclifford=0.05)
+    _, g, r = run_both(c)
+    assert g[1].shape[1] == 2
+    compare_fp64(g, r, label=c.name)
+
+
+def test_wide_keys_clifford_rz():
+    c = W.c2_clifford_rz(seed=5, n=48, depth=150, n_rz=22)
+    _, g, r = run_both(c)
+    compare_fp64(g, r, label=c.name)
+
+
+def test_wide_keys_initial_and_expect():
+    n = 48
+    with Simulator(n) as s:
+        off, keys, w = s.generators()
+        for j in range(n):
+            v = int(keys[j, 0]) | (int(keys[j, 1]) << 64)
+            assert v == 3 << (2 * (n - 1 - j))
+        assert s.expect("Z" + "I" * (n - 1)) == 1.0
+        assert s.expect("X" + "I" * (n - 1)) == 0.0
