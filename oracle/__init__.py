@@ -15,7 +15,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# QIMAX_ORACLE_LIB may name another build of oracle.cpp (used to check that the pins reject
+# deliberately broken copies of the oracle).
+LIB_PATH = os.environ.get("QIMAX_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "oracle.cpp")
 
 _lib = None

@@ -403,3 +403,26 @@ def test_subset_equals_full():
         a, b = full.read(j), sub.read(slot)
         for u, v in zip(a, b):
             assert np.array_equal(u, v)
+
+
+def test_exact_cancellation_is_dropped():
+    """Rz(t) then Rz(-t) on X: the Y coefficient cos(t)sin(t) - sin(t)cos(t) is an exact zero
+    in floating point and must not be stored (only non-zero weights are kept, Sec. III-B)."""
+    o = oracle.Oracle(1)
+    o.gate(Gate.H, 0)
+    o.gate(Gate.RZ, 0, theta=0.7)
+    o.gate(Gate.RZ, 0, theta=-0.7)
+    d = oracle_generator_dict(o, 0)
+    assert list(d) == ["X"] and abs(d["X"] - 1.0) < 1e-15
+
+
+def test_prune_drops_weights_equal_to_eps():
+    """The prune keeps |w| > eps: a weight exactly equal to eps is dropped."""
+    R = np.eye(4)
+    R[:, 3] = 0.0
+    R[1, 3] = 0.5     # Z -> 0.5 X + 0.25 Y (a linear map, not a unitary)
+    R[2, 3] = 0.25
+    o = oracle.Oracle(1)
+    o.ptm1(0, R)
+    o.prune(0.25)
+    assert oracle_generator_dict(o, 0) == {"X": 0.5}
