@@ -58,6 +58,108 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def bench_batch(log, count: int = 256):
+    """The 256-circuit recipe (n 8..48, depth 50..400, 5..30 Rz): every circuit propagated
+    one at a time on a single-circuit context (plain) vs all together in batches (one per
+    key class), FP64 and FP32; FP32 error against FP64 per circuit."""
+    from paper_2505_03307_amd import workloads as W
+    from paper_2505_03307_amd.qimax import Batch, Simulator
+    from paper_2505_03307_amd.serve import key_class
+
+    circs = W.c4_batch(count=count)
+    classes = {}
+    for i, c in enumerate(circs):
+        classes.setdefault(key_class(c.n), []).append(i)
+    out = {"circuits": len(circs), "n_range": [min(c.n for c in circs), max(c.n for c in circs)],
+           "key_classes": {str(k): len(v) for k, v in sorted(classes.items())}}
+    results = {}
+    for precision in (64, 32):
+        batches = {cls: Batch(precision=precision, max_n=cls, device=0) for cls in classes}
+        sims = {}
+        for rep in range(2):  # the first repetition grows the device buffers
+            t0 = time.perf_counter()
+            upd_b = 0
+            res_b = {}
+            for cls, idx in classes.items():
+                bt = batches[cls]
+                ids = [bt.submit(circs[i]) for i in idx]
+                bt.run()
+                for i, cid in zip(idx, ids):
+                    upd_b += bt.circuit_updates(cid)
+                    res_b[i] = bt.fetch(cid)
+            t1 = time.perf_counter()
+            upd_p = 0
+            for i, c in enumerate(circs):
+                s = sims.get(c.n)
+                if s is None:
+                    s = sims[c.n] = Simulator(c.n, precision=precision, device=0)
+                s.reset()
+                u0 = s.stats()["term_updates"]
+                s.run(c)
+                g = s.generators()
+                upd_p += s.stats()["term_updates"] - u0
+                if rep == 1 and precision == 64:
+                    for x, y in zip(g, res_b[i]):
+                        if not np.array_equal(x, y):
+                            raise RuntimeError(f"batched result differs from plain for circuit {i}")
+            t2 = time.perf_counter()
+        for bt in batches.values():
+            bt.close()
+        for s in sims.values():
+            s.close()
+        results[precision] = res_b
+        key = "fp64" if precision == 64 else "fp32"
+        out[key] = {"batched_updates_per_s": round(upd_b / (t1 - t0), 1), "plain_updates_per_s": round(upd_p / (t2 - t1), 1),
+                    "batched_s": round(t1 - t0, 4), "plain_s": round(t2 - t1, 4),
+                    "speedup": round((t2 - t1) / (t1 - t0), 3), "term_updates": int(upd_b),
+                    "final_terms": int(sum(int(r[0][-1]) for r in res_b.values()))}
+        log("batch", key, out[key])
+    # FP32 against FP64, per circuit (norm-wise over the union of keys)
+    worst = 0.0
+    for i in results[64]:
+        o64, k64, w64 = results[64][i]
+        o32, k32, w32 = results[32][i]
+        for j in range(len(o64) - 1):
+            a = {tuple(r): v for r, v in zip(k64[o64[j]:o64[j + 1]].tolist(), w64[o64[j]:o64[j + 1]].tolist())}
+            bb = {tuple(r): v for r, v in zip(k32[o32[j]:o32[j + 1]].tolist(), w32[o32[j]:o32[j + 1]].tolist())}
+            num = sum((a.get(k, 0.0) - bb.get(k, 0.0)) ** 2 for k in set(a) | set(bb)) ** 0.5
+            den = sum(v * v for v in a.values()) ** 0.5
+            worst = max(worst, num / (den or 1.0))
+    out["fp32_max_rel_err_vs_fp64"] = worst
+    out["fp32_within_5e-6"] = bool(worst <= 5e-6)
+    return out
+
+
+def bench_serve(log, count: int = 400, budget_gb: float = 200.0):
+    """Poisson arrivals of ansatz circuits (n 10..16, 1 or 2 layers, FP32, eps 1e-9) at 0.7x
+    the measured sequential capacity: continuous batching vs the sequential plain path."""
+    from paper_2505_03307_amd import workloads as W
+    from paper_2505_03307_amd import serve
+
+    circuits, gaps = W.c5_stream(seed=0, count=count)
+    # sequential capacity, measured back to back on the first requests
+    probe = min(60, count)
+    res, _ = serve.serve_sequential(circuits[:probe], np.zeros(probe), precision=32)  # warm-up
+    t0 = time.perf_counter()
+    res, _ = serve.serve_sequential(circuits[:probe], np.zeros(probe), precision=32)
+    cap = probe / (time.perf_counter() - t0)
+    lam = 0.7 * cap
+    arrivals = np.cumsum(gaps) / lam
+    log("serve: sequential capacity", round(cap, 1), "req/s; arrival rate", round(lam, 1))
+    t0 = time.perf_counter()
+    seq, _ = serve.serve_sequential(circuits, arrivals, precision=32)
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    srv_res, srv = serve.serve_trace(circuits, arrivals, int(budget_gb * 1e9), precision=32)
+    t_srv = time.perf_counter() - t0
+    srv.close()
+    out = {"requests": count, "arrival_rate_per_s": round(lam, 2), "sequential_capacity_per_s": round(cap, 2),
+           "budget_GB": budget_gb, "served": serve.summarize(srv_res, t_srv),
+           "sequential": serve.summarize(seq, t_seq)}
+    log("serve", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +169,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-gens", type=str, default="all",
                     help="oracle sample: 'all', 'none', or a comma list of generator ids")
+    ap.add_argument("--batch", type=int, default=256, help="circuits in the batched-vs-plain section (0: skip)")
+    ap.add_argument("--serve", type=int, default=400, help="requests in the serving section (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -102,6 +206,10 @@ def main():
     s1 = sim.stats()
     terms = sim.num_terms()
     updates = (s1["term_updates"] - s0["term_updates"]) / args.steps
+    host = {"busy_ms_per_step": round((s1["host_busy_ms"] - s0["host_busy_ms"]) / args.steps, 3),
+            "sync_wait_ms_per_step": round((s1["host_wait_ms"] - s0["host_wait_ms"]) / args.steps, 3),
+            "syncs_per_step": (s1["syncs"] - s0["syncs"]) / args.steps}
+    log("host", host)
     sec = (t1 - t0) / args.steps
     log("timed", args.steps, "steps, ms/step", round(sec * 1e3, 3), "updates/step", int(updates), "terms", terms)
 
@@ -140,6 +248,8 @@ def main():
         log("cpu", cpu)
 
     sim.close()
+    batch = bench_batch(log, args.batch) if args.batch else None
+    serving = bench_serve(log, args.serve) if args.serve else None
     out = {
         "metric": "Pauli-term updates/sec + HBM GB/s fraction; batched vs plain at 5e-6 rel err",
         "value": round(updates / sec, 1),
@@ -160,6 +270,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "host": host,
+        "batched_vs_plain": batch,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

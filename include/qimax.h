@@ -139,6 +139,9 @@ typedef struct {
   uint64_t sort_elems;     /* elements sorted                                             */
   uint64_t peak_bytes;     /* peak device bytes held by the context                       */
   uint64_t alloc_bytes;    /* device bytes currently held                                 */
+  double host_wait_ms;     /* host time blocked in stream synchronisations of passes      */
+  double host_busy_ms;     /* host time spent inside apply calls outside those waits      */
+  uint64_t syncs;          /* stream synchronisations of passes                           */
 } qimax_stats;
 
 qimax_status qimax_get_stats(const qimax_ctx* ctx, qimax_stats* out);
@@ -191,8 +194,8 @@ typedef struct {
 } qimax_batch_info_t;
 
 /* opts: precision, fp32_merge, mem_cap_bytes, hip_stream, device apply to the whole batch
- * (prune_eps is per circuit). max_n: the largest n the batch accepts (<= 32: 64-bit keys;
- * <= 64: 128-bit keys; group circuits by key class for speed). */
+ * (prune_eps is per circuit). max_n: the largest n the batch accepts; it picks the key
+ * class (<= 16: 32-bit, <= 32: 64-bit, <= 64: 128-bit keys), so group circuits by class. */
 qimax_status qimax_batch_create(const qimax_opts* opts, uint32_t max_n, qimax_batch** out);
 /* Groups and plans the circuit (inputs are copied) and queues it; *id names it. */
 qimax_status qimax_batch_submit(qimax_batch* b, const qimax_circuit* c, uint64_t* id);

@@ -344,7 +344,7 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
       start = off[p];
     }
     if (p >= T_in) {
-      atomicOr(err, kErrIndex);
+      atomicOr(err, kErrIndex | kErrExpand);
       continue;
     }
     K key = keys[p];
@@ -357,7 +357,7 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
       const Exp1Desc& E = pa.E1[e];
       const uint32_t d = get_d(key, E.pos);
       const uint32_t c = E.cnt[d];
-      if (c == 0) { atomicOr(err, kErrIndex); break; }
+      if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
       const uint32_t q = r / c;
       const uint32_t k = r - q * c;
       r = q;
@@ -368,7 +368,7 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
       const Exp2Desc& E = pa.E2[e];
       const uint32_t in = local2(key, E.pa, E.pb);
       const uint32_t c = E.cnt[in];
-      if (c == 0) { atomicOr(err, kErrIndex); break; }
+      if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
       const uint32_t q = r / c;
       const uint32_t k = r - q * c;
       r = q;
@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_hist(const K* __restrict__ 
 #pragma unroll
     for (int w = 0; w < kSortBlock / 64; ++w) c += h[w][d];
     const uint64_t pos = hist_pos(tl, b, d);
-    if (pos < hist_size) hist[pos] = c; else atomicOr(err, kErrIndex);
+    if (pos < hist_size) hist[pos] = c; else atomicOr(err, kErrIndex | kErrSort);
   }
 }
 
@@ -547,7 +547,7 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
         stage[pos[r]] = (uint64_t)key[r];
         sdig[pos[r]] = (uint8_t)dd;
       } else {
-        atomicOr(err, kErrIndex);
+        atomicOr(err, kErrIndex | kErrSort);
       }
     } else {
       pos[r] = 0xFFFFFFFFu;
@@ -575,7 +575,7 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
           if constexpr (kWords == 1) keys_out[dst] = (K)stage[j];
           else ((uint64_t*)keys_out)[2 * dst + word] = stage[j];
         } else {
-          atomicOr(err, kErrIndex);
+          atomicOr(err, kErrIndex | kErrSort);
         }
       }
     }
@@ -691,16 +691,27 @@ __device__ __forceinline__ W run_sum(const K* __restrict__ keys, const W* __rest
   }
 }
 
-template <typename K, typename W, bool kWrite>
+// kMode 0: count the kept runs of each tile (blk_cnt); 1: write them at the scanned
+// offsets (blk_off); 2: single sweep - tiles are claimed in order, each publishes its
+// count and looks back over the earlier tiles for its output offset (written to blk_off,
+// with the total at blk_off[n_blocks]), then writes.
+template <typename K, typename W, int kMode>
 __global__ void __launch_bounds__(kSortBlock)
 k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const PassArgs* __restrict__ pas,
         const uint32_t* __restrict__ seg_entry, int fp64_acc, uint32_t* __restrict__ blk_cnt,
-        const uint64_t* __restrict__ blk_off, K* __restrict__ keys_out, W* __restrict__ w_out, uint64_t out_cap,
-        uint32_t* err) {
+        uint64_t* __restrict__ blk_off, K* __restrict__ keys_out, W* __restrict__ w_out, uint64_t out_cap,
+        uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr, uint64_t epoch, uint32_t* err) {
   constexpr bool kLds = sizeof(K) <= 8;  // 16-byte keys are read from global memory
   __shared__ K sk[kLds ? kSortTile + 1 : 1];
   __shared__ uint64_t scan_sh[kSortBlock / 64];
-  const uint32_t b = blockIdx.x;
+  __shared__ uint64_t base_sh;
+  uint32_t b = blockIdx.x;
+  if constexpr (kMode == 2) {
+    if (threadIdx.x == 0) base_sh = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    b = (uint32_t)base_sh;
+    __syncthreads();
+  }
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
   const uint32_t s = tl.blk_seg[b];
   const double thr = pas[seg_entry[s]].thr;
@@ -739,10 +750,37 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
   }
   uint64_t tot;
   const uint64_t pre = block_excl_scan<kSortBlock>(keep, scan_sh, &tot);
-  if constexpr (!kWrite) {
+  if constexpr (kMode == 0) {
     if (threadIdx.x == 0) blk_cnt[b] = (uint32_t)tot;
   } else {
-    uint64_t o = blk_off[b] + pre;
+    if constexpr (kMode == 2) {
+      if (threadIdx.x == 0) {
+        const uint64_t ep = epoch << 48;
+        st_store(status + b, ep | (b == 0 ? kStPre : kStAgg) | tot);
+        uint64_t excl = 0;
+        if (b > 0) {
+          uint32_t t = b - 1;
+          uint32_t spins = 0;
+          while (true) {
+            const uint64_t v = st_load(status + t);
+            const bool ready = (v >> 48) == epoch && (v & (kStAgg | kStPre));
+            if (!ready) {
+              if (++spins > kSpinLimit) { atomicOr(err, kErrSpin); break; }
+              continue;
+            }
+            excl += v & kStValMask;
+            if ((v & kStPre) || t == 0) break;
+            --t;
+          }
+          st_store(status + b, ep | kStPre | (excl + tot));
+        }
+        base_sh = excl;
+        blk_off[b] = excl;
+        if (b + 1 == tl.n_blocks) blk_off[tl.n_blocks] = excl + tot;
+      }
+      __syncthreads();
+    }
+    uint64_t o = (kMode == 2 ? base_sh : blk_off[b]) + pre;
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
       if (!(keep_mask & (1u << k))) continue;
@@ -750,7 +788,7 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
         keys_out[o] = key_at(1 + i0 + k);
         w_out[o] = sums[k];
       } else {
-        atomicOr(err, kErrIndex);
+        atomicOr(err, kErrIndex | kErrMerge);
       }
       ++o;
     }
@@ -1076,7 +1114,8 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
 hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, uint64_t T,
                         const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out, void* w_out,
                         uint64_t out_cap, uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
-                        uint32_t* err, hipStream_t s, Prof* prof) {
+                        uint64_t* status, uint32_t* tile_ctr, uint64_t epoch, uint32_t* err, hipStream_t s,
+                        Prof* prof) {
   if (tl.n_blocks == 0) {
     // no terms at all: every segment offset is zero
     k_zero_one<<<1, 1, 0, s>>>(blk_off);
@@ -1086,31 +1125,43 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
   }
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   QIMAX_DISPATCH_K(KC, {
-    hipEvent_t ev = prof_begin(prof, s);
-    if (WP == 64) {
-      k_merge<K, double, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0,
-          err);
+    if (status) {  // single sweep
+      k_fill_u32<<<1, 64, 0, s>>>(tile_ctr, 1, 0u);
+      hipEvent_t ev = prof_begin(prof, s);
+      if (WP == 64)
+        k_merge<K, double, 2><<<tl.n_blocks, kSortBlock, 0, s>>>(
+            (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, nullptr, blk_off, (K*)keys_out,
+            (double*)w_out, out_cap, status, tile_ctr, epoch, err);
+      else
+        k_merge<K, float, 2><<<tl.n_blocks, kSortBlock, 0, s>>>(
+            (const K*)keys_in, (const float*)w_in, tl, pas, seg_entry, fp64_acc, nullptr, blk_off, (K*)keys_out,
+            (float*)w_out, out_cap, status, tile_ctr, epoch, err);
+      // the written terms are added by the caller once their count is back on the host
+      prof_end(prof, s, ev, kKMergeWrite, (kb + wb) * (double)T);
     } else {
-      k_merge<K, float, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const float*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0,
-          err);
+      hipEvent_t ev = prof_begin(prof, s);
+      if (WP == 64)
+        k_merge<K, double, 0><<<tl.n_blocks, kSortBlock, 0, s>>>(
+            (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0,
+            nullptr, nullptr, 0, err);
+      else
+        k_merge<K, float, 0><<<tl.n_blocks, kSortBlock, 0, s>>>(
+            (const K*)keys_in, (const float*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0,
+            nullptr, nullptr, 0, err);
+      prof_end(prof, s, ev, kKMergeCount, (kb + wb) * (double)T);
+      hipError_t e = scan_impl<uint32_t>(blk_cnt, blk_off, tl.n_blocks, tmp, s, prof);
+      if (e != hipSuccess) return e;
+      ev = prof_begin(prof, s);
+      if (WP == 64)
+        k_merge<K, double, 1><<<tl.n_blocks, kSortBlock, 0, s>>>(
+            (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
+            (double*)w_out, out_cap, nullptr, nullptr, 0, err);
+      else
+        k_merge<K, float, 1><<<tl.n_blocks, kSortBlock, 0, s>>>(
+            (const K*)keys_in, (const float*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
+            (float*)w_out, out_cap, nullptr, nullptr, 0, err);
+      prof_end(prof, s, ev, kKMergeWrite, (kb + wb) * (double)T);
     }
-    prof_end(prof, s, ev, kKMergeCount, (kb + wb) * (double)T);
-    hipError_t e = scan_impl<uint32_t>(blk_cnt, blk_off, tl.n_blocks, tmp, s, prof);
-    if (e != hipSuccess) return e;
-    ev = prof_begin(prof, s);
-    if (WP == 64) {
-      k_merge<K, double, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
-          (double*)w_out, out_cap, err);
-    } else {
-      k_merge<K, float, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
-          (const K*)keys_in, (const float*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
-          (float*)w_out, out_cap, err);
-    }
-    // the written terms are added by the caller once their count is back on the host
-    prof_end(prof, s, ev, kKMergeWrite, (kb + wb) * (double)T);
   });
   k_gather_u64_by_u32<<<grid_for(tl.n_segs + 1, 64), 64, 0, s>>>(blk_off, tl.seg_blk, seg_off_out, tl.n_segs + 1);
   return hipGetLastError();

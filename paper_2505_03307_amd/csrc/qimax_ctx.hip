@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -213,6 +214,8 @@ struct qimax_ctx {
   DevBuf desc, desc2, err, f64tmp;
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
+  DevBuf mstatus;  // single-sweep merge state (tile counter at tile_ctr[32])
+  uint64_t mepoch = 0;
   bool classic_sort = false;
   DevBuf gr_gate, gr_theta, gr_idx, gr_off, gr_out;
   uint64_t* pinned = nullptr;  // small pinned host scratch
@@ -472,7 +475,10 @@ qimax_status readback(qimax_ctx* c, const void* dev, size_t words, uint32_t* err
   if (words)
     HIPCHK(c, hipMemcpyAsync(c->pinned, dev, words * 8, hipMemcpyDeviceToHost, c->stream), "readback");
   HIPCHK(c, hipMemcpyAsync(c->pinned + words, c->err.p, 4, hipMemcpyDeviceToHost, c->stream), "readback err");
+  const auto t0 = std::chrono::steady_clock::now();
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->st.host_wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  c->st.syncs += 1;
   prof_resolve(&c->prof);
   *err_out = (uint32_t)(c->pinned[words] & 0xFFFFFFFFu);
   return QIMAX_OK;
@@ -484,6 +490,9 @@ std::string err_text(uint32_t e) {
   if (e & kErrFanout) s += " fanout-overflow";
   if (e & kErrOrder) s += " order";
   if (e & kErrSpin) s += " look-back-timeout";
+  if (e & kErrExpand) s += " (expand)";
+  if (e & kErrSort) s += " (sort)";
+  if (e & kErrMerge) s += " (merge)";
   return s;
 }
 
@@ -660,9 +669,11 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     QCHK(ensure(c, c->ghist, nh * 4));
     QCHK(ensure(c, c->sbase, nh * 8));
     QCHK(ensure(c, c->tile_ctr, 64 * 4));
-    void* old_status = c->sstatus.p;
+    // a grown buffer may come back at the same address with stale contents: detect the
+    // reallocation by its size, never by its pointer
+    const size_t old_bytes = c->sstatus.bytes;
     QCHK(ensure(c, c->sstatus, hsize * 8));
-    if (c->sstatus.p != old_status || c->epoch + n_pass >= 0xFFFFull) {
+    if (c->sstatus.bytes != old_bytes || c->epoch + n_pass >= 0xFFFFull) {
       // fresh memory or epoch wrap: clear every word so that no stale epoch can match
       HIPCHK(c, launch_fill_u64((uint64_t*)c->sstatus.p, c->sstatus.bytes / 8, 0ull, c->stream), "clear status");
       c->epoch = 0;
@@ -680,12 +691,28 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->pseg[slot], (S + 1) * 8));
   QCHK(ensure(c, c->blk_cnt, (size_t)(tl.n_blocks + 1) * 4));
   QCHK(ensure(c, c->blk_off, (size_t)(tl.n_blocks + 1) * 8));
+  uint64_t* mstatus = nullptr;
+  if (!c->classic_sort) {
+    const size_t old_m = c->mstatus.bytes;
+    QCHK(ensure(c, c->mstatus, (size_t)(tl.n_blocks + 1) * 8));
+    if (c->mstatus.bytes != old_m || c->mepoch + 1 >= 0xFFFFull) {
+      HIPCHK(c, launch_fill_u64((uint64_t*)c->mstatus.p, c->mstatus.bytes / 8, 0ull, c->stream), "clear status");
+      c->mepoch = 0;
+    }
+    c->mepoch += 1;
+    mstatus = (uint64_t*)c->mstatus.p;
+  }
   HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, pas, sent, c->pk[slot].p,
                          c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
-                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, (uint32_t*)c->err.p, c->stream,
-                         &c->prof), "merge");
+                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, (uint32_t*)c->tile_ctr.p + 32,
+                         c->mepoch, (uint32_t*)c->err.p, c->stream, &c->prof), "merge");
   QCHK(readback(c, c->pseg[slot].p, S + 1, &e));
-  if (e) return fail(c, QIMAX_EDEVICE, "expand/sort/merge pass:" + err_text(e));
+  if (e) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), " [segments %u, T_in %llu, T_img %llu, tiles %u, key bits %u, entries %zu]", S,
+                  (unsigned long long)T_in, (unsigned long long)T_img, tl.n_blocks, key_bits, E);
+    return fail(c, QIMAX_EDEVICE, "expand/sort/merge pass:" + err_text(e) + buf);
+  }
   so_out.assign(c->pinned, c->pinned + S + 1);
   const uint64_t T_out = so_out[S];
   if (c->prof.on) c->prof.bytes[kKMergeWrite] += (double)T_out * (double)(eb + wbt);
@@ -752,8 +779,21 @@ void plan_passes(const std::vector<const HostOp*>& all, std::vector<Pass>& passe
 
 // Single-circuit contexts: plan the operators (after the deferred ones of earlier calls) and
 // run the passes as one-entry rounds; commit only when every pass succeeded.
+// Host time of a call minus the time it spent blocked in pass synchronisations.
+struct BusyTimer {
+  qimax_ctx* c;
+  std::chrono::steady_clock::time_point t0;
+  double wait0;
+  explicit BusyTimer(qimax_ctx* cc) : c(cc), t0(std::chrono::steady_clock::now()), wait0(cc->st.host_wait_ms) {}
+  ~BusyTimer() {
+    const double all = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->st.host_busy_ms += all - (c->st.host_wait_ms - wait0);
+  }
+};
+
 qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  BusyTimer bt(c);
   std::vector<HostOp> all;
   all.reserve(c->pending.size() + ops.size());
   for (auto& op : c->pending) all.push_back(op);
@@ -1242,7 +1282,10 @@ qimax_status qimax_apply_circuit(qimax_ctx* c, const uint8_t* gate, const uint32
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
   if (m && (!gate || !q0 || !q1)) return fail(c, QIMAX_EINVAL, "instruction arrays are NULL");
   std::vector<HostOp> ops;
-  QCHK(group_circuit(c, c->n, gate, q0, q1, theta, m, ops, nullptr, nullptr));
+  {
+    BusyTimer bt(c);
+    QCHK(group_circuit(c, c->n, gate, q0, q1, theta, m, ops, nullptr, nullptr));
+  }
   return apply_ops(c, ops);
 }
 
@@ -1379,7 +1422,7 @@ void qimax_destroy(qimax_ctx* c) {
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
                     &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
-                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr};
+                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 2; ++i)
@@ -1556,8 +1599,9 @@ qimax_status qimax_batch_create(const qimax_opts* opts, uint32_t max_n, qimax_ba
   *out = nullptr;
   if (max_n > 64) return QIMAX_ETOOLARGE;
   qimax_ctx* c = nullptr;
-  // the batch's context: its key class fits max_n (at least uint64 keys), buffers, stream
-  qimax_status s = qimax_create(max_n <= 32 ? 32 : 64, opts, &c);
+  // the batch's context: its key class fits max_n, buffers, stream
+  const uint32_t cls = max_n <= 16 ? 16 : (max_n <= 32 ? 32 : 64);
+  qimax_status s = qimax_create(cls, opts, &c);
   if (s != QIMAX_OK) return s;
   qimax_batch* b = new (std::nothrow) qimax_batch;
   if (!b) {
@@ -1565,7 +1609,7 @@ qimax_status qimax_batch_create(const qimax_opts* opts, uint32_t max_n, qimax_ba
     return QIMAX_ENOMEM;
   }
   b->c = c;
-  b->max_n = max_n <= 32 ? 32 : 64;
+  b->max_n = cls;
   c->T = 0;
   c->h_seg.assign(1, 0);
   *out = b;
@@ -1600,6 +1644,7 @@ qimax_status qimax_batch_submit(qimax_batch* b, const qimax_circuit* q, uint64_t
 qimax_status qimax_batch_step(qimax_batch* b, size_t* n_active) {
   if (!b) return QIMAX_EINVAL;
   qimax_ctx* c = b->c;
+  BusyTimer bt(c);
   if (c->broken) return bfail(b, QIMAX_ESTATE, "batch unusable after an earlier device error");
   QCHK(admit(b));
   // one entry per circuit in the array: its next pass, or a drop of a finished circuit

@@ -108,6 +108,9 @@ enum : uint32_t {
   kErrFanout = 2u,     // fan-out of a term exceeded the 32-bit range
   kErrOrder = 4u,      // sorted order violated (debug checks)
   kErrSpin = 8u,       // a look-back wait gave up (bounded spin)
+  kErrExpand = 16u,    // set with kErrIndex by the expand kernel
+  kErrSort = 32u,      // set with kErrIndex by the sort kernels
+  kErrMerge = 64u,     // set with kErrIndex by the merge kernel
 };
 
 
@@ -189,10 +192,13 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 // Segmented sum of equal adjacent keys; keeps sums with |w| > thr (thr < 0 keeps
 // everything non-zero); compacts. seg_off_out[s] for s in [0, n_segs].
 // blk_cnt / blk_off must hold n_blocks (+1) words.
+// status != nullptr: single-sweep merge (status: n_blocks u64 words with a fresh epoch,
+// tile_ctr: one u32); otherwise count, scan, write.
 hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, uint64_t T,
                         const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out, void* w_out,
                         uint64_t out_cap, uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
-                        uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+                        uint64_t* status, uint32_t* tile_ctr, uint64_t epoch, uint32_t* err, hipStream_t s,
+                        Prof* prof = nullptr);
 
 // Compile chains of permutation ops into ChainTables, one job per chain (jobs in device memory).
 hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hipStream_t s, Prof* prof = nullptr);

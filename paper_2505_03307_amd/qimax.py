@@ -36,7 +36,8 @@ class Op(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
-                ("terms", "passes", "term_updates", "images", "sort_elems", "peak_bytes", "alloc_bytes")]
+                ("terms", "passes", "term_updates", "images", "sort_elems", "peak_bytes", "alloc_bytes")] + \
+               [("host_wait_ms", ctypes.c_double), ("host_busy_ms", ctypes.c_double), ("syncs", ctypes.c_uint64)]
 
 
 class CircuitC(ctypes.Structure):
@@ -261,7 +262,7 @@ class Simulator:
     def stats(self) -> dict:
         s = Stats()
         self._check(load().qimax_get_stats(self._h, ctypes.byref(s)))
-        return {k: int(getattr(s, k)) for k, _ in Stats._fields_}
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
 
     def generator_updates(self) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.uint64)

@@ -52,9 +52,14 @@ def predict_terms(c: W.Circuit):
     return 3 * n * per_gen, n * per_gen
 
 
-def predict_bytes(c: W.Circuit, precision: int = 32) -> int:
-    kb = 4 if c.n <= 16 else (8 if c.n <= 32 else 16)
-    kb = max(kb, 8)  # batches hold at least 64-bit keys
+def key_class(n: int) -> int:
+    """Qubit limit of the key class a circuit of n qubits needs (16, 32 or 64)."""
+    return 16 if n <= 16 else (32 if n <= 32 else 64)
+
+
+def predict_bytes(c: W.Circuit, precision: int = 32, batch_max_n: int | None = None) -> int:
+    cls = batch_max_n or key_class(c.n)
+    kb = 4 if cls <= 16 else (8 if cls <= 32 else 16)
     wb = 8 if precision == 64 else 4
     img, terms = predict_terms(c)
     # images live in two ping-pong buffers plus the merged output; count + offset per term
@@ -83,6 +88,7 @@ class Server:
         # batch: anything with submit/step/poll/fetch/circuit_updates/close (default: a qimax_batch)
         self.batch = batch if batch is not None else Batch(precision=precision, max_n=max_n)
         self.precision = precision
+        self.max_n = max_n
         self.budget = int(budget_bytes)
         self.in_flight = {}   # batch id -> (rid, arrival, admitted, predicted bytes)
         self.reserved = 0
@@ -93,7 +99,7 @@ class Server:
         self.batch.close()
 
     def try_admit(self, rid: int, circuit: W.Circuit, arrival: float, now: float) -> bool:
-        need = predict_bytes(circuit, self.precision)
+        need = predict_bytes(circuit, self.precision, self.max_n)
         if need > self.budget:
             raise ValueError(f"request {rid} needs {need} bytes, more than the whole budget")
         if self.in_flight and self.reserved + need > self.budget:
@@ -123,7 +129,7 @@ def serve_trace(circuits, arrivals, budget_bytes: int, precision: int = 32, keep
                 batch=None):
     """Serve the trace in real time with continuous batching. Returns (results, server)."""
     order = np.argsort(arrivals, kind="stable")
-    srv = Server(budget_bytes, precision, max_n=32 if max(c.n for c in circuits) <= 32 else 64,
+    srv = Server(budget_bytes, precision, max_n=key_class(max(c.n for c in circuits)),
                  keep_results=keep_results, batch=batch)
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0  # noqa: E731

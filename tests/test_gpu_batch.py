@@ -105,3 +105,21 @@ def test_wide_batch_of_the_n8_to_48_family():
             ref = alone(c)
             for x, y in zip(got, ref):
                 assert np.array_equal(x, y), c.name
+
+
+def test_status_buffers_regrown_between_circuits():
+    """Circuits of growing size on one reused context: the look-back status buffers grow
+    between them (possibly at the same address) and must not keep stale words. The n=26
+    circuit of the 256-circuit recipe exposed this."""
+    cs = W.c4_batch(count=64)
+    for i in (53, 0, 16, 48):
+        c = cs[i]
+        if c.n > 32:
+            continue
+        say("regrow", i, c.n)
+        with Simulator(c.n) as s:
+            for small in (W.c2_clifford_rz(seed=9, n=c.n, depth=20, n_rz=2), c):
+                s.reset()
+                s.run(small)
+            got = s.generators()
+        compare_fp64(got, oracle_arrays(oracle.propagate(c), c.n), label=c.name)
