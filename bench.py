@@ -130,7 +130,7 @@ def bench_batch(log, count: int = 256):
     return out
 
 
-def bench_serve(log, count: int = 400, budget_gb: float = 200.0):
+def bench_serve(log, count: int = 200, budget_gb: float = 200.0, one_batch: bool = False):
     """Poisson arrivals of ansatz circuits (n 10..16, 1 or 2 layers, FP32, eps 1e-9) at 0.7x
     the measured sequential capacity: continuous batching vs the sequential plain path."""
     from paper_2505_03307_amd import workloads as W
@@ -150,12 +150,18 @@ def bench_serve(log, count: int = 400, budget_gb: float = 200.0):
     seq, _ = serve.serve_sequential(circuits, arrivals, precision=32)
     t_seq = time.perf_counter() - t0
     t0 = time.perf_counter()
-    srv_res, srv = serve.serve_trace(circuits, arrivals, int(budget_gb * 1e9), precision=32)
+    srv_res, _ = serve.serve_trace_lanes(circuits, arrivals, int(budget_gb * 1e9), precision=32)
     t_srv = time.perf_counter() - t0
-    srv.close()
     out = {"requests": count, "arrival_rate_per_s": round(lam, 2), "sequential_capacity_per_s": round(cap, 2),
            "budget_GB": budget_gb, "served": serve.summarize(srv_res, t_srv),
-           "sequential": serve.summarize(seq, t_seq)}
+           "sequential": serve.summarize(seq, t_seq),
+           "server": "continuous batching, two lanes split at 256 MB predicted footprint, one HIP stream each, "
+                     "one large request in flight"}
+    if one_batch:
+        t0 = time.perf_counter()
+        one, srv = serve.serve_trace(circuits, arrivals, int(budget_gb * 1e9), precision=32)
+        srv.close()
+        out["served_one_batch"] = serve.summarize(one, time.perf_counter() - t0)
     log("serve", out)
     return out
 
@@ -170,7 +176,8 @@ def main():
     ap.add_argument("--cpu-gens", type=str, default="all",
                     help="oracle sample: 'all', 'none', or a comma list of generator ids")
     ap.add_argument("--batch", type=int, default=256, help="circuits in the batched-vs-plain section (0: skip)")
-    ap.add_argument("--serve", type=int, default=400, help="requests in the serving section (0: skip)")
+    ap.add_argument("--serve", type=int, default=200, help="requests in the serving section (0: skip)")
+    ap.add_argument("--serve-one-batch", action="store_true", help="also serve the trace with a single batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -249,7 +256,7 @@ def main():
 
     sim.close()
     batch = bench_batch(log, args.batch) if args.batch else None
-    serving = bench_serve(log, args.serve) if args.serve else None
+    serving = bench_serve(log, args.serve, one_batch=args.serve_one_batch) if args.serve else None
     out = {
         "metric": "Pauli-term updates/sec + HBM GB/s fraction; batched vs plain at 5e-6 rel err",
         "value": round(updates / sec, 1),

@@ -189,3 +189,120 @@ def summarize(results, wall: float) -> dict:
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
             "mean_ms": round(float(lat.mean()) * 1e3, 3), "wall_s": round(wall, 3),
             "requests_per_s": round(len(results) / wall, 2), "term_updates_per_s": round(upd / wall, 1)}
+
+
+class _Budget:
+    """Device bytes reserved by admitted requests, shared by the lanes."""
+
+    def __init__(self, total: int):
+        import threading
+        self.total = int(total)
+        self.used = 0
+        self.lock = threading.Lock()
+
+    def try_reserve(self, need: int, force: bool) -> bool:
+        with self.lock:
+            if force or self.used + need <= self.total:
+                self.used += need
+                return True
+            return False
+
+    def release(self, need: int):
+        with self.lock:
+            self.used -= need
+
+
+def serve_trace_lanes(circuits, arrivals, budget_bytes: int, precision: int = 32, split_bytes: int = 256 << 20,
+                      large_in_flight: int = 1, keep_results: bool = False, batch_factory=None):
+    """Continuous batching with two lanes: requests predicted to need less than split_bytes
+    go to one batch, the others to a second; each batch runs on its own HIP stream, driven by
+    its own host thread, so small requests do not wait behind the rounds of large ones. The
+    large lane keeps at most large_in_flight requests in flight (large requests already fill
+    the device, so sharing rounds among them only delays each one). Admission in arrival
+    order per lane, against one shared memory budget (a lane with nothing in flight may always
+    admit its next request). Returns (results, outputs)."""
+    import collections
+    import threading
+
+    order = np.argsort(arrivals, kind="stable")
+    max_n = key_class(max(c.n for c in circuits))
+    budget = _Budget(budget_bytes)
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0  # noqa: E731
+
+    class Lane:
+        def __init__(self, cap):
+            self.cap = cap
+            self.batch = batch_factory() if batch_factory else Batch(precision=precision, max_n=max_n)
+            self.queue = collections.deque()
+            self.cv = threading.Condition()
+            self.closed = False
+            self.in_flight = {}
+            self.results = []
+            self.outputs = {}
+            self.error = None
+
+    lanes = [Lane(None), Lane(large_in_flight)]
+
+    def work(lane):
+        try:
+            while True:
+                with lane.cv:
+                    while not lane.queue and not lane.in_flight and not lane.closed:
+                        lane.cv.wait(timeout=0.01)
+                    if lane.closed and not lane.queue and not lane.in_flight:
+                        return
+                    admitted = []
+                    while lane.queue:
+                        if lane.cap is not None and len(lane.in_flight) + len(admitted) >= lane.cap:
+                            break
+                        rid, need = lane.queue[0]
+                        if not budget.try_reserve(need, force=not lane.in_flight and not admitted):
+                            break
+                        lane.queue.popleft()
+                        admitted.append((rid, need))
+                now = clock()
+                for rid, need in admitted:
+                    bid = lane.batch.submit(circuits[rid])
+                    lane.in_flight[bid] = (rid, float(arrivals[rid]), now, need)
+                if lane.in_flight:
+                    lane.batch.step()
+                    for bid in lane.batch.poll():
+                        rid, arr, adm, need = lane.in_flight.pop(bid)
+                        upd = lane.batch.circuit_updates(bid)
+                        res = lane.batch.fetch(bid)
+                        budget.release(need)
+                        if keep_results:
+                            lane.outputs[rid] = res
+                        lane.results.append(Result(rid, arr, adm, clock(), int(res[0][-1]), upd))
+        except Exception as e:  # surfaced by the caller
+            lane.error = e
+
+    threads = [threading.Thread(target=work, args=(ln,), daemon=True) for ln in lanes]
+    for t in threads:
+        t.start()
+    for i in order:
+        wait = arrivals[i] - clock()
+        if wait > 0:
+            time.sleep(wait)
+        need = predict_bytes(circuits[i], precision, max_n)
+        if need > budget.total:
+            raise ValueError(f"request {i} needs {need} bytes, more than the whole budget")
+        lane = lanes[0] if need < split_bytes else lanes[1]
+        with lane.cv:
+            lane.queue.append((int(i), need))
+            lane.cv.notify()
+    for ln in lanes:
+        with ln.cv:
+            ln.closed = True
+            ln.cv.notify()
+    for t in threads:
+        t.join()
+    results, outputs = [], {}
+    for ln in lanes:
+        if ln.error:
+            raise ln.error
+        results += ln.results
+        outputs.update(ln.outputs)
+        ln.batch.close()
+    return results, outputs

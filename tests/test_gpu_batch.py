@@ -123,3 +123,19 @@ def test_status_buffers_regrown_between_circuits():
                 s.run(small)
             got = s.generators()
         compare_fp64(got, oracle_arrays(oracle.propagate(c), c.n), label=c.name)
+
+
+def test_served_results_equal_alone():
+    """A Poisson trace through the two-lane continuous-batching server: every request's
+    generators are bit-identical to the same circuit run alone."""
+    from paper_2505_03307_amd import serve
+    circuits, gaps = W.c5_stream(seed=5, count=24, n_range=(6, 11))
+    arrivals = np.cumsum(gaps) * 2e-3
+    results, outputs = serve.serve_trace_lanes(circuits, arrivals, budget_bytes=8 << 30, split_bytes=1 << 20,
+                                               keep_results=True)
+    assert sorted(r.rid for r in results) == list(range(24))
+    for r in results:
+        c = circuits[r.rid]
+        ref = alone(c, precision=32)
+        for x, y in zip(outputs[r.rid], ref):
+            assert np.array_equal(x, y), c.name

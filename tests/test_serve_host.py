@@ -96,3 +96,16 @@ def test_summary():
     rs = [serve.Result(i, 0.0, 0.0, 0.001 * (i + 1), 10, 5) for i in range(100)]
     s = serve.summarize(rs, 1.0)
     assert s["requests"] == 100 and abs(s["p50_ms"] - 50.5) < 1e-9 and s["p99_ms"] > s["p50_ms"]
+
+
+def test_two_lane_server_with_fake_executors():
+    circuits, gaps = W.c5_stream(seed=4, count=16, n_range=(4, 7))
+    arrivals = np.cumsum(gaps) * 1e-4
+    results, outputs = serve.serve_trace_lanes(circuits, arrivals, budget_bytes=10 ** 12, split_bytes=20000,
+                                               keep_results=True, batch_factory=FakeBatch)
+    assert sorted(r.rid for r in results) == list(range(16))
+    for r in results:
+        assert r.finished >= r.admitted >= r.arrival - 1e-9
+        want = oracle_arrays(oracle.propagate(circuits[r.rid]), circuits[r.rid].n)
+        for a, b in zip(outputs[r.rid], want):
+            assert np.array_equal(a, b)
