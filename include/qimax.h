@@ -219,6 +219,12 @@ qimax_ctx* qimax_batch_context(qimax_batch* b);
 const char* qimax_batch_last_error(const qimax_batch* b);
 void qimax_batch_destroy(qimax_batch* b);
 
+/* Measurement aid, not part of propagation: copies `bytes` (rounded down to 8-byte words)
+ * between two fresh device buffers `reps` times with a plain copy kernel on the null stream
+ * and returns the average milliseconds per copy. Read traffic counters of this run give
+ * the scale between counter units and bytes moved. */
+qimax_status qimax_copy_probe(size_t bytes, int reps, double* ms);
+
 /* Blocks until all work of the context has finished. */
 qimax_status qimax_sync(qimax_ctx* ctx);
 

@@ -168,8 +168,20 @@ __global__ void __launch_bounds__(256) k_count(const K* __restrict__ keys, Tilin
     stage_table(pa.tA, tk, tn);
     __syncthreads();
   }
-  for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
-    K key = keys[i];
+  constexpr int kItems = kSortTile / 256;  // input tiles hold at most kSortTile terms
+  const uint32_t n = (uint32_t)(end - begin);
+  K kr[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {  // every load in flight before the first use
+    const uint32_t li = r * 256 + threadIdx.x;
+    kr[r] = keys[n ? begin + min(li, n - 1) : 0];
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t li = r * 256 + threadIdx.x;
+    if (li >= n) break;
+    const uint64_t i = begin + li;
+    K key = kr[r];
     uint32_t neg = 0;
     if (pa.useA) key = apply_table(key, tk, tn, neg);
     else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
@@ -326,10 +338,12 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
     for (uint64_t k = threadIdx.x; k < nwin; k += kExpandBlock) win[k] = off[plo + k];
   }
   __syncthreads();
-#pragma unroll 1
+  // parents of every item first, then every parent load in flight, then the arithmetic
+  uint64_t par[kExpandItems];
+  uint32_t rk[kExpandItems];
+#pragma unroll
   for (int it = 0; it < kExpandItems; ++it) {
-    const uint64_t g = g0 + (uint64_t)it * kExpandBlock + threadIdx.x;
-    if (g >= g1) break;
+    const uint64_t g = min(g0 + (uint64_t)it * kExpandBlock + threadIdx.x, g1 - 1);
     uint64_t p, start;
     if (in_lds) {
       uint32_t lo = 0, hi = (uint32_t)nwin;
@@ -343,16 +357,31 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
       p = upper_bound_u64(off, plo, phi + 2, g) - 1;
       start = off[p];
     }
-    if (p >= T_in) {
+    par[it] = p;
+    rk[it] = (uint32_t)(g - start);
+  }
+  K kp[kExpandItems];
+  W wp[kExpandItems];
+#pragma unroll
+  for (int it = 0; it < kExpandItems; ++it) {
+    const uint64_t p = min(par[it], T_in - 1);  // T_in >= 1: this tile has images
+    kp[it] = keys[p];
+    wp[it] = w[p];
+  }
+#pragma unroll
+  for (int it = 0; it < kExpandItems; ++it) {
+    const uint64_t g = g0 + (uint64_t)it * kExpandBlock + threadIdx.x;
+    if (g >= g1) break;
+    if (par[it] >= T_in) {
       atomicOr(err, kErrIndex | kErrExpand);
       continue;
     }
-    K key = keys[p];
-    W wv = w[p];
+    K key = kp[it];
+    W wv = wp[it];
     uint32_t neg = 0;
     if (pa.useA) key = apply_table(key, tak, tan_, neg);
     else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
-    uint32_t r = (uint32_t)(g - start);
+    uint32_t r = rk[it];
     for (uint32_t e = 0; e < pa.nE1; ++e) {
       const Exp1Desc& E = pa.E1[e];
       const uint32_t d = get_d(key, E.pos);
@@ -464,6 +493,7 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
     __syncthreads();
     b = tile_sh;
   }
+  if (tl.n_dev && b >= *tl.n_dev) return;  // past the tiles that exist
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
   const uint32_t n_tile = (uint32_t)(end - begin);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -474,12 +504,19 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   W wv[kRounds];
   uint32_t rank[kRounds];
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  // all loads first, with no branch (slots past the tile re-read its last element), so that
+  // every load of the thread is in flight at once
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t li = wid * kWaveSpan + r * 64 + lane;
+    const uint64_t gi = n_tile ? begin + min(li, n_tile - 1) : 0;
+    key[r] = keys_in[gi];
+    wv[r] = w_in[gi];
+  }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t li = wid * kWaveSpan + r * 64 + lane;  // tile-local index, stable order
     const bool valid = li < n_tile;
-    key[r] = valid ? keys_in[begin + li] : (K)0;
-    wv[r] = valid ? w_in[begin + li] : (W)0;
     const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
     uint64_t m = __ballot(valid);
 #pragma unroll
@@ -615,9 +652,17 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict
   __syncthreads();
   const uint32_t b = blockIdx.x;
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
-  for (uint64_t i = begin + threadIdx.x; i < end; i += kSortBlock) {
-    const K key = keys[i];
-    for (uint32_t p = 0; p < n_pass; ++p) atomicAdd(&h[wid][p][(uint32_t)(key >> (8 * p)) & 255u], 1u);
+  const uint32_t n = (uint32_t)(end - begin);  // at most kSortTile
+  K kr[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {  // every load in flight before the first use
+    const uint32_t li = r * kSortBlock + threadIdx.x;
+    kr[r] = keys[n ? begin + min(li, n - 1) : 0];
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (r * kSortBlock + threadIdx.x >= n) break;
+    for (uint32_t p = 0; p < n_pass; ++p) atomicAdd(&h[wid][p][(uint32_t)(kr[r] >> (8 * p)) & 255u], 1u);
   }
   __syncthreads();
   const uint32_t s = tl.blk_seg[b];
@@ -671,25 +716,34 @@ struct RunSum {
   __device__ __forceinline__ W value() const { return s + c; }
 };
 
-template <typename K, typename W>
-__device__ __forceinline__ W run_sum(const K* __restrict__ keys, const W* __restrict__ w, uint64_t i,
-                                     uint64_t seg_end, K key, int fp64_acc) {
-  if constexpr (sizeof(W) == 8) {
-    double s = w[i];
-    for (uint64_t j = i + 1; j < seg_end && keys[j] == key; ++j) s += w[j];
-    return s;
-  } else {
-    if (fp64_acc) {
-      double s = (double)w[i];
-      for (uint64_t j = i + 1; j < seg_end && keys[j] == key; ++j) s += (double)w[j];
-      return (float)s;
-    }
-    RunSum<float> rs;
-    rs.add(w[i]);
-    for (uint64_t j = i + 1; j < seg_end && keys[j] == key; ++j) rs.add(w[j]);
-    return rs.value();
-  }
+// Sum of a run starting at tile-local index li: from the staged tile (key_at / sw) while the
+// run stays inside the tile, then from global memory up to the segment end: the elements are
+// added in array order whatever the tiling, so results do not depend on it.
+template <typename Acc, typename W, typename K, typename KeyAt>
+__device__ __forceinline__ W run_sum_tile(const KeyAt& key_at, const W* sw, uint32_t li, uint32_t n_tile,
+                                          const K* __restrict__ keys, const W* __restrict__ w, uint64_t begin,
+                                          uint64_t seg_end, K key) {
+  Acc a;
+  a.add(sw[li]);
+  uint32_t j = li + 1;
+  for (; j < n_tile && key_at(1 + j) == key; ++j) a.add(sw[j]);
+  if (j == n_tile)
+    for (uint64_t g = begin + j; g < seg_end && keys[g] == key; ++g) a.add(w[g]);
+  return a.value();
 }
+
+template <typename W>
+struct PlainSum {  // in W, array order
+  W s = 0;
+  __device__ __forceinline__ void add(W x) { s += x; }
+  __device__ __forceinline__ W value() const { return s; }
+};
+
+struct F64Sum {  // FP32 weights accumulated in FP64, rounded once
+  double s = 0;
+  __device__ __forceinline__ void add(float x) { s += (double)x; }
+  __device__ __forceinline__ float value() const { return (float)s; }
+};
 
 // kMode 0: count the kept runs of each tile (blk_cnt); 1: write them at the scanned
 // offsets (blk_off); 2: single sweep - tiles are claimed in order, each publishes its
@@ -703,6 +757,7 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
         uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr, uint64_t epoch, uint32_t* err) {
   constexpr bool kLds = sizeof(K) <= 8;  // 16-byte keys are read from global memory
   __shared__ K sk[kLds ? kSortTile + 1 : 1];
+  __shared__ W sw[kSortTile];
   __shared__ uint64_t scan_sh[kSortBlock / 64];
   __shared__ uint64_t base_sh;
   uint32_t b = blockIdx.x;
@@ -712,16 +767,42 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
     b = (uint32_t)base_sh;
     __syncthreads();
   }
+  const uint32_t n_tiles = tl.n_dev ? *tl.n_dev : tl.n_blocks;
+  if (b >= n_tiles) {  // past the tiles that exist
+    if constexpr (kMode == 2) {
+      if (n_tiles == 0 && b == 0 && threadIdx.x == 0) blk_off[0] = 0;  // no images: every offset is 0
+    }
+    return;
+  }
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
   const uint32_t s = tl.blk_seg[b];
   const double thr = pas[seg_entry[s]].thr;
   const uint64_t seg_begin = tl.blk_begin[tl.seg_blk[s]];
   const uint64_t seg_end = tl.blk_end[tl.seg_blk[s + 1] - 1];
   const uint32_t n_tile = (uint32_t)(end - begin);
-  // key(i) for i in [-1, n_tile): sk[0] holds the key before the tile (if inside the segment)
-  if constexpr (kLds) {
-    for (uint32_t i = threadIdx.x; i < n_tile; i += kSortBlock) sk[1 + i] = keys[begin + i];
-    if (threadIdx.x == 0 && begin > seg_begin) sk[0] = keys[begin - 1];
+  // key(i) for i in [-1, n_tile): sk[0] holds the key before the tile (if inside the segment);
+  // weights in sw. Coalesced loads, all in flight before the first LDS store.
+  {
+    K kr[kLds ? kSortItems : 1];
+    W wr[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const uint32_t li = r * kSortBlock + threadIdx.x;
+      const uint64_t gi = n_tile ? begin + min(li, n_tile - 1) : 0;
+      if constexpr (kLds) kr[r] = keys[gi];
+      wr[r] = w[gi];
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const uint32_t li = r * kSortBlock + threadIdx.x;
+      if (li < n_tile) {
+        if constexpr (kLds) sk[1 + li] = kr[r];
+        sw[li] = wr[r];
+      }
+    }
+    if constexpr (kLds) {
+      if (threadIdx.x == 0 && begin > seg_begin) sk[0] = keys[begin - 1];
+    }
     __syncthreads();
   }
   auto key_at = [&](uint32_t i1) -> K {  // i1 = tile-local index + 1
@@ -741,7 +822,13 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
     const K key = key_at(1 + li);
     const bool head = (gi == seg_begin) || (key_at(li) != key);
     if (!head) continue;
-    const W v = run_sum(keys, w, gi, seg_end, key, fp64_acc);
+    W v;
+    if constexpr (sizeof(W) == 8) {
+      v = run_sum_tile<PlainSum<W>>(key_at, sw, li, n_tile, keys, w, begin, seg_end, key);
+    } else {
+      if (fp64_acc) v = run_sum_tile<F64Sum>(key_at, sw, li, n_tile, keys, w, begin, seg_end, key);
+      else v = run_sum_tile<RunSum<float>>(key_at, sw, li, n_tile, keys, w, begin, seg_end, key);
+    }
     if (fabs((double)v) > thr) {
       sums[k] = v;
       keep_mask |= 1u << k;
@@ -776,7 +863,7 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
         }
         base_sh = excl;
         blk_off[b] = excl;
-        if (b + 1 == tl.n_blocks) blk_off[tl.n_blocks] = excl + tot;
+        if (b + 1 == n_tiles) blk_off[n_tiles] = excl + tot;
       }
       __syncthreads();
     }
@@ -1181,6 +1268,76 @@ hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t*
     if (WP == 64) k_init_many<K, double><<<n_circ, 64, 0, s>>>((K*)keys, (double*)w, nq, dst, n_circ);
     else k_init_many<K, float><<<n_circ, 64, 0, s>>>((K*)keys, (float*)w, nq, dst, n_circ);
   });
+  return hipGetLastError();
+}
+
+// One block: per-segment tile counts, their exclusive scan (seg_blk), then every tile of
+// the cap range (empty past the total).
+__global__ void __launch_bounds__(256) k_make_tiles(const uint64_t* __restrict__ so, uint32_t S, uint64_t tile,
+                                                    uint32_t cap, uint64_t* __restrict__ blk_begin,
+                                                    uint64_t* __restrict__ blk_end, uint32_t* __restrict__ blk_seg,
+                                                    uint32_t* __restrict__ seg_blk, uint32_t* __restrict__ n_dev,
+                                                    uint64_t limit, uint32_t* err) {
+  __shared__ uint64_t sh[4];
+  __shared__ uint64_t carry_sh;
+  if (threadIdx.x == 0) carry_sh = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < S; base += 256) {
+    const uint32_t s = base + threadIdx.x;
+    const uint64_t len = s < S ? so[s + 1] - so[s] : 0;
+    const uint64_t nt = (len + tile - 1) / tile;
+    uint64_t tot;
+    const uint64_t pre = block_excl_scan<256>(nt, sh, &tot);
+    const uint64_t carry = carry_sh;
+    if (s < S) seg_blk[s] = (uint32_t)(carry + pre);
+    __syncthreads();
+    if (threadIdx.x == 0) carry_sh = carry + tot;
+    __syncthreads();
+  }
+  // more tiles or elements than the capacity: the bound was not an upper bound (tiles are
+  // clamped below so that nothing reads past the buffers; the pass reports the error)
+  if (threadIdx.x == 0 && (carry_sh > cap || so[S] > limit)) atomicOr(err, kErrIndex | kErrFanout);
+  const uint32_t total = (uint32_t)min<uint64_t>(carry_sh, cap);
+  if (threadIdx.x == 0) {
+    seg_blk[S] = total;
+    *n_dev = total;
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < cap; t += 256) {
+    if (t < total) {
+      uint32_t lo = 0, hi = S;  // last segment s with seg_blk[s] <= t (non-empty)
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (seg_blk[mid] <= t) lo = mid; else hi = mid;
+      }
+      while (lo + 1 < S && seg_blk[lo + 1] <= t) ++lo;  // skip empty segments sharing the start
+      const uint64_t b0 = so[lo] + (uint64_t)(t - seg_blk[lo]) * tile;
+      blk_begin[t] = min(b0, limit);
+      blk_end[t] = min(min(b0 + tile, so[lo + 1]), limit);
+      blk_seg[t] = lo;
+    } else {
+      blk_begin[t] = 0;
+      blk_end[t] = 0;
+      blk_seg[t] = 0;
+    }
+  }
+}
+
+__global__ void k_copy_u64(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = in[i];
+}
+
+hipError_t launch_make_tiles(const uint64_t* so, uint32_t S, uint64_t tile, uint32_t cap, uint64_t* blk_begin,
+                             uint64_t* blk_end, uint32_t* blk_seg, uint32_t* seg_blk, uint32_t* n_dev, uint64_t limit,
+                             uint32_t* err, hipStream_t s) {
+  k_make_tiles<<<1, 256, 0, s>>>(so, S, tile, cap, blk_begin, blk_end, blk_seg, seg_blk, n_dev, limit, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_copy_u64<<<std::min<uint64_t>(grid_for(n, 256), 65536), 256, 0, s>>>(in, out, n);
   return hipGetLastError();
 }
 

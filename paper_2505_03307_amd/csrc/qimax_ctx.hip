@@ -182,6 +182,7 @@ bool is_conjugation(const std::vector<double>& R, int dim) {
 }
 
 constexpr int kMaxE1 = 64;
+constexpr int kBoundPathMaxFanout = 16;  // rounds with a larger fan-out bound read back their image count
 constexpr int kMaxE2 = 8;
 constexpr double kMaxFanout = 2147483647.0;
 
@@ -215,8 +216,10 @@ struct qimax_ctx {
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
   DevBuf mstatus;  // single-sweep merge state (tile counter at tile_ctr[32])
+  DevBuf dtile[2];  // device-built image tilings (expand, sort/merge) of the bound path
   uint64_t mepoch = 0;
   bool classic_sort = false;
+  bool host_tiling = false;
   DevBuf gr_gate, gr_theta, gr_idx, gr_off, gr_out;
   uint64_t* pinned = nullptr;  // small pinned host scratch
   size_t pinned_words = 0;
@@ -484,6 +487,27 @@ qimax_status readback(qimax_ctx* c, const void* dev, size_t words, uint32_t* err
   return QIMAX_OK;
 }
 
+// Two arrays of `words` uint64 each (a then b) to the pinned scratch, plus the error word.
+qimax_status readback2(qimax_ctx* c, const void* a, const void* b, size_t words, uint32_t* err_out) {
+  if (2 * words + 1 > c->pinned_words) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    size_t want = std::max<size_t>(2 * words + 1, 4096);
+    HIPCHK(c, hipHostMalloc((void**)&c->pinned, want * 8, hipHostMallocDefault), "hipHostMalloc");
+    c->pinned_words = want;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->pinned, a, words * 8, hipMemcpyDeviceToHost, c->stream), "readback");
+  HIPCHK(c, hipMemcpyAsync(c->pinned + words, b, words * 8, hipMemcpyDeviceToHost, c->stream), "readback");
+  HIPCHK(c, hipMemcpyAsync(c->pinned + 2 * words, c->err.p, 4, hipMemcpyDeviceToHost, c->stream), "readback err");
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->st.host_wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  c->st.syncs += 1;
+  prof_resolve(&c->prof);
+  *err_out = (uint32_t)(c->pinned[2 * words] & 0xFFFFFFFFu);
+  return QIMAX_OK;
+}
+
 std::string err_text(uint32_t e) {
   std::string s;
   if (e & kErrIndex) s += " index-out-of-range";
@@ -626,21 +650,50 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   HIPCHK(c, launch_gather_u64((const uint64_t*)c->off.p, seg_in, (uint64_t*)c->img_seg.p, S + 1, c->stream, &c->prof),
          "gather");
   uint32_t e = 0;
-  QCHK(readback(c, c->img_seg.p, S + 1, &e));
-  if (e) return fail(c, (e & kErrFanout) ? QIMAX_ETOOLARGE : QIMAX_EDEVICE, "count pass:" + err_text(e));
-  so_img.assign(c->pinned, c->pinned + S + 1);
-  const uint64_t T_img = so_img[S];
-  // ---- image tilings (expand tiles, sort/merge tiles) in one upload
-  HostTiling t_exp, t_sort;
-  make_tiling(so_img, kExpandTile, t_exp);
-  make_tiling(so_img, kSortTile, t_sort);
-  const size_t img_bytes = tiling_bytes(t_exp) + tiling_bytes(t_sort);
-  QCHK(ensure(c, c->desc2, img_bytes + 256));
-  QCHK(ensure_stage(c, 1, img_bytes));
+  // Bound path: with a small fan-out bound f, T_img <= f * T_in, so the image tilings are
+  // built on the device and every launch is sized by the bound (tiles past the real count
+  // are empty), and the image offsets come back with the merge's. Otherwise the image
+  // offsets are read back now and the tilings are built on the host.
+  double f_round = 0.0;
+  for (const RoundEntry& en : entries)
+    if (en.pass && !en.drop) f_round = std::max(f_round, en.pass->fanout_bound);
+  const bool bound_path = !c->classic_sort && !c->host_tiling && f_round <= (double)kBoundPathMaxFanout && T_in > 0;
+  uint64_t T_img = 0;
   Tiling tl_exp{}, tl{};
-  const size_t mid = put_tiling(t_exp, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, 0, tl_exp);
-  put_tiling(t_sort, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, mid, tl);
-  HIPCHK(c, hipMemcpyAsync(c->desc2.p, c->stage[1], img_bytes, hipMemcpyHostToDevice, c->stream), "upload tiling");
+  if (bound_path) {
+    T_img = (uint64_t)f_round * T_in;  // capacity: an upper bound of the image count
+    const uint32_t cap_exp = (uint32_t)((T_img + kExpandTile - 1) / kExpandTile + S);
+    const uint32_t cap_sort = (uint32_t)((T_img + kSortTile - 1) / kSortTile + S);
+    const uint32_t caps[2] = {cap_exp, cap_sort};
+    const uint64_t tiles[2] = {(uint64_t)kExpandTile, (uint64_t)kSortTile};
+    Tiling* tls[2] = {&tl_exp, &tl};
+    for (int i = 0; i < 2; ++i) {
+      const size_t o1 = 0, o2 = align256((size_t)caps[i] * 8), o3 = o2 + align256((size_t)caps[i] * 8);
+      const size_t o4 = o3 + align256((size_t)caps[i] * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
+      QCHK(ensure(c, c->dtile[i], o5 + 256));
+      uint8_t* d = (uint8_t*)c->dtile[i].p;
+      HIPCHK(c, launch_make_tiles((const uint64_t*)c->img_seg.p, S, tiles[i], caps[i], (uint64_t*)(d + o1),
+                                  (uint64_t*)(d + o2), (uint32_t*)(d + o3), (uint32_t*)(d + o4), (uint32_t*)(d + o5),
+                                  T_img, (uint32_t*)c->err.p, c->stream), "tiles");
+      *tls[i] = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
+                       (const uint32_t*)(d + o4), caps[i], S, (const uint32_t*)(d + o5)};
+    }
+  } else {
+    QCHK(readback(c, c->img_seg.p, S + 1, &e));
+    if (e) return fail(c, (e & kErrFanout) ? QIMAX_ETOOLARGE : QIMAX_EDEVICE, "count pass:" + err_text(e));
+    so_img.assign(c->pinned, c->pinned + S + 1);
+    T_img = so_img[S];
+    // ---- image tilings (expand tiles, sort/merge tiles) in one upload
+    HostTiling t_exp, t_sort;
+    make_tiling(so_img, kExpandTile, t_exp);
+    make_tiling(so_img, kSortTile, t_sort);
+    const size_t img_bytes = tiling_bytes(t_exp) + tiling_bytes(t_sort);
+    QCHK(ensure(c, c->desc2, img_bytes + 256));
+    QCHK(ensure_stage(c, 1, img_bytes));
+    const size_t mid = put_tiling(t_exp, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, 0, tl_exp);
+    put_tiling(t_sort, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, mid, tl);
+    HIPCHK(c, hipMemcpyAsync(c->desc2.p, c->stage[1], img_bytes, hipMemcpyHostToDevice, c->stream), "upload tiling");
+  }
   // ---- expand into images
   const size_t eb = c->kb, wbt = c->wb;
   QCHK(ensure(c, c->ik[0], std::max<uint64_t>(T_img, 1) * eb));
@@ -706,7 +759,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
                          c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
                          (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, (uint32_t*)c->tile_ctr.p + 32,
                          c->mepoch, (uint32_t*)c->err.p, c->stream, &c->prof), "merge");
-  QCHK(readback(c, c->pseg[slot].p, S + 1, &e));
+  QCHK(bound_path ? readback2(c, c->pseg[slot].p, c->img_seg.p, S + 1, &e) : readback(c, c->pseg[slot].p, S + 1, &e));
   if (e) {
     char buf[256];
     std::snprintf(buf, sizeof(buf), " [segments %u, T_in %llu, T_img %llu, tiles %u, key bits %u, entries %zu]", S,
@@ -715,6 +768,20 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   }
   so_out.assign(c->pinned, c->pinned + S + 1);
   const uint64_t T_out = so_out[S];
+  if (bound_path) {
+    so_img.assign(c->pinned + S + 1, c->pinned + 2 * (S + 1));
+    // the launches were recorded with the capacity; count the real images
+    const uint64_t cap = T_img;
+    T_img = so_img[S];
+    if (c->prof.on) {
+      const double d = (double)(cap - T_img);
+      const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
+      c->prof.bytes[kKExpand] -= (double)(eb + wbt) * d;
+      c->prof.bytes[kKSortHist] -= (double)eb * d;
+      c->prof.bytes[kKSortScatter] -= 2.0 * (double)(eb + wbt) * n_pass * d;
+      c->prof.bytes[kKMergeWrite] -= (double)(eb + wbt) * d;
+    }
+  }
   if (c->prof.on) c->prof.bytes[kKMergeWrite] += (double)T_out * (double)(eb + wbt);
   // ---- bookkeeping: one update per output image of every operator (a Clifford operator
   // counts its terms, the expanding operator its images), attributed per entry
@@ -1215,6 +1282,8 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
   {
     const char* env = std::getenv("QIMAX_SORT_CLASSIC");
     c->classic_sort = env && env[0] == '1';
+    env = std::getenv("QIMAX_HOST_TILING");  // always read the image count back before expanding
+    c->host_tiling = env && env[0] == '1';
   }
   hipError_t e;
   if (o.device >= 0) {
@@ -1404,6 +1473,33 @@ qimax_status qimax_get_generator_updates(const qimax_ctx* c, uint64_t* out, size
   return QIMAX_OK;
 }
 
+qimax_status qimax_copy_probe(size_t bytes, int reps, double* ms) {
+  if (bytes < 8 || reps < 1 || !ms) return QIMAX_EINVAL;
+  const uint64_t n = bytes / 8;
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, n * 8) != hipSuccess || hipMalloc(&b, n * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) (void)hipFree(a);
+    return QIMAX_ENOMEM;
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)launch_copy_u64((const uint64_t*)a, (uint64_t*)b, n, nullptr);  // warm-up
+  (void)hipEventRecord(e0, nullptr);
+  for (int r = 0; r < reps; ++r) (void)launch_copy_u64((const uint64_t*)a, (uint64_t*)b, n, nullptr);
+  (void)hipEventRecord(e1, nullptr);
+  hipError_t e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  *ms = (double)t / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  return e == hipSuccess ? QIMAX_OK : QIMAX_EDEVICE;
+}
+
 qimax_status qimax_sync(qimax_ctx* c) {
   if (!c) return QIMAX_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
@@ -1422,7 +1518,7 @@ void qimax_destroy(qimax_ctx* c) {
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
                     &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
-                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus};
+                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1]};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 2; ++i)

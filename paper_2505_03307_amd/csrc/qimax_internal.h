@@ -86,8 +86,10 @@ struct Tiling {
   const uint64_t* blk_end;
   const uint32_t* blk_seg;
   const uint32_t* seg_blk;
-  uint32_t n_blocks;
+  uint32_t n_blocks;  // tiles launched (an upper bound when n_dev is set)
   uint32_t n_segs;
+  const uint32_t* n_dev;  // if set: the actual number of tiles, known only on the device;
+                          // tiles beyond it are empty and their blocks return at once
 };
 
 constexpr int kSortBlock = 256;            // threads per sort / merge block
@@ -206,6 +208,17 @@ hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hi
 // Z_j of n_circ new circuits: circuit c's nq[c] terms are written from position dst[c].
 hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t* nq, const uint64_t* dst,
                             uint32_t n_circ, hipStream_t s);
+
+// Segment-aligned tiles of at most `tile` elements built on the device from device segment
+// offsets so[0..S]; cap tiles are written (the ones past the actual count are empty) and the
+// actual count goes to *n_dev. Tile ranges are clamped to [0, limit) (elements of the
+// buffers they index); a tile count above cap or so[S] above limit sets an error bit.
+hipError_t launch_make_tiles(const uint64_t* so, uint32_t S, uint64_t tile, uint32_t cap, uint64_t* blk_begin,
+                             uint64_t* blk_end, uint32_t* blk_seg, uint32_t* seg_blk, uint32_t* n_dev, uint64_t limit,
+                             uint32_t* err, hipStream_t s);
+
+// Plain copy of n words (calibration of hardware traffic counters).
+hipError_t launch_copy_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s);
 
 // Weights to FP64 (readout).
 hipError_t launch_weights_to_f64(int WP, const void* w, double* out, uint64_t T, hipStream_t s, Prof* prof = nullptr);

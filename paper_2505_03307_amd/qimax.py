@@ -62,7 +62,7 @@ EXPORTS = ["qimax_batch_create", "qimax_batch_submit", "qimax_batch_step", "qima
            "qimax_batch_last_error", "qimax_batch_destroy",
            "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
            "qimax_num_terms", "qimax_get_generators", "qimax_expect", "qimax_get_stats", "qimax_sync",
-           "qimax_profile", "qimax_profile_read", "qimax_last_error", "qimax_destroy"]
+           "qimax_profile", "qimax_profile_read", "qimax_copy_probe", "qimax_last_error", "qimax_destroy"]
 
 _lib = None
 
@@ -98,6 +98,7 @@ def load():
     lib.qimax_sync.argtypes = [P]
     lib.qimax_profile.argtypes = [P, ctypes.c_int]
     lib.qimax_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_size_t, szp]
+    lib.qimax_copy_probe.argtypes = [ctypes.c_size_t, ctypes.c_int, dp]
     lib.qimax_last_error.argtypes = [P]
     lib.qimax_last_error.restype = ctypes.c_char_p
     lib.qimax_destroy.argtypes = [P]
@@ -398,3 +399,12 @@ class Batch:
         lib.qimax_profile_read(self._ctx(), arr, 32, ctypes.byref(n))
         return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
                                         "alg_bytes": float(arr[i].alg_bytes)} for i in range(n.value)}
+
+
+def copy_probe(nbytes: int, reps: int = 5) -> float:
+    """Average ms of a plain device copy of nbytes (calibration of traffic counters)."""
+    ms = ctypes.c_double()
+    st = load().qimax_copy_probe(int(nbytes), int(reps), ctypes.byref(ms))
+    if st != 0:
+        raise QimaxError(st, "copy probe failed")
+    return ms.value

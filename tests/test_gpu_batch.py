@@ -139,3 +139,28 @@ def test_served_results_equal_alone():
         ref = alone(c, precision=32)
         for x, y in zip(outputs[r.rid], ref):
             assert np.array_equal(x, y), c.name
+
+
+@pytest.mark.parametrize("variant", ["QIMAX_HOST_TILING", "QIMAX_SORT_CLASSIC"])
+def test_tiling_and_sort_variants_bit_identical(variant, monkeypatch):
+    """Image tilings built on the device from the fan-out bound (the default for rounds whose
+    bound is small), tilings built on the host after reading the image count back, and the
+    classic multi-launch sort give identical tiles and a stable sort, hence identical sums:
+    the results must agree bit for bit, alone and batched."""
+    cs = mixed_circuits()
+    with Batch(precision=64) as b:
+        ids = [b.submit(c) for c in cs]
+        b.run()
+        ref = [b.fetch(i) for i in ids]
+    ref_alone = [alone(c) for c in cs[3:6]]
+    monkeypatch.setenv(variant, "1")
+    say("variant", variant)
+    with Batch(precision=64) as b:
+        ids = [b.submit(c) for c in cs]
+        b.run()
+        for c, cid, r in zip(cs, ids, ref):
+            for x, y in zip(b.fetch(cid), r):
+                assert np.array_equal(x, y), (variant, c.name)
+    for c, r in zip(cs[3:6], ref_alone):
+        for x, y in zip(alone(c), r):
+            assert np.array_equal(x, y), (variant, c.name)
