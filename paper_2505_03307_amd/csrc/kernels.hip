@@ -96,6 +96,24 @@ __device__ __forceinline__ void stage_table(const ChainTable& t, K* sk, uint8_t*
   }
 }
 
+// The XCD (accelerator complex die) this wave runs on.
+__device__ __forceinline__ uint32_t xcd_id() {
+  uint32_t x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  return x & (kXcds - 1);
+}
+
+// First tile b >= target with b a segment's first tile (seg_blk[0..S] is non-decreasing and
+// ends with the tile count).
+__device__ __forceinline__ uint32_t seg_boundary_at_or_after(const uint32_t* seg_blk, uint32_t S, uint32_t target) {
+  uint32_t lo = 0, hi = S;  // seg_blk[hi] >= target
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (seg_blk[mid] >= target) hi = mid; else lo = mid + 1;
+  }
+  return seg_blk[lo];
+}
+
 template <typename K>
 __device__ __forceinline__ uint32_t local2(K key, uint32_t pa, uint32_t pb) {
   return (get_d(key, pa) << 2) | get_d(key, pb);
@@ -436,9 +454,17 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_hist(const K* __restrict__ 
   for (int k = threadIdx.x; k < (kSortBlock / 64) * kRadix; k += kSortBlock) (&h[0][0])[k] = 0;
   __syncthreads();
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
-  for (uint64_t i = begin + threadIdx.x; i < end; i += kSortBlock) {
-    const uint32_t d = (uint32_t)(keys[i] >> shift) & (kRadix - 1);
-    atomicAdd(&h[wid][d], 1u);
+  const uint32_t n = (uint32_t)(end - begin);  // at most kSortTile
+  K kr[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {  // every load in flight before the first use
+    const uint32_t li = r * kSortBlock + threadIdx.x;
+    kr[r] = keys[n ? begin + min(li, n - 1) : 0];
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (r * kSortBlock + threadIdx.x >= n) break;
+    atomicAdd(&h[wid][(uint32_t)(kr[r] >> shift) & (kRadix - 1)], 1u);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kSortBlock) {
@@ -489,9 +515,36 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
 
   uint32_t b = blockIdx.x;
   if constexpr (kSweep) {
-    if (threadIdx.x == 0) tile_sh = atomicAdd(tile_ctr, 1u);
+    // launched for a bound on the tile count: the first n_dev blocks claim the n_dev tiles
+    if (tl.n_dev && b >= *tl.n_dev) return;
+    // Tiles are claimed in order. With per-XCD ranges, a block claims from the range of its
+    // own XCD first (whole segments, so every look-back chain and every pair of neighbouring
+    // digit runs stays on one XCD and its L2), then from the others; every tile is claimed
+    // once whatever the placement of the blocks (there are at least as many blocks as tiles).
+    if (threadIdx.x == 0) {
+      uint32_t got = 0xFFFFFFFFu;
+      if (tl.xrange) {
+        const uint32_t x = xcd_id();
+        for (int j = 0; j < kXcds; ++j) {
+          const uint32_t y = (x + j) & (kXcds - 1);
+          const uint32_t a = tl.xrange[y], len = tl.xrange[y + 1] - a;
+          if (len == 0) continue;
+          const uint32_t k = atomicAdd(tile_ctr + y, 1u);
+          if (k < len) { got = a + k; break; }
+        }
+      } else {
+        got = atomicAdd(tile_ctr, 1u);
+      }
+      tile_sh = got;
+    }
     __syncthreads();
     b = tile_sh;
+    if (b == 0xFFFFFFFFu) return;  // every tile was claimed already
+  } else {
+    // independent tiles: consecutive tiles on one XCD (blocks are dealt to the XCDs in turn),
+    // so the partial cache lines where neighbouring tiles' digit runs meet merge in one L2
+    const uint32_t n = gridDim.x, x = b & (kXcds - 1), i = b / kXcds, q = n / kXcds, r = n % kXcds;
+    b = x * q + min(x, r) + i;
   }
   if (tl.n_dev && b >= *tl.n_dev) return;  // past the tiles that exist
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
@@ -762,6 +815,11 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
   __shared__ uint64_t base_sh;
   uint32_t b = blockIdx.x;
   if constexpr (kMode == 2) {
+    // launched for a bound on the tile count: the first n_dev blocks claim the n_dev tiles
+    if (tl.n_dev && b >= *tl.n_dev) {
+      if (b == 0 && threadIdx.x == 0) blk_off[0] = 0;  // no tiles: every offset is 0
+      return;
+    }
     if (threadIdx.x == 0) base_sh = atomicAdd(tile_ctr, 1u);
     __syncthreads();
     b = (uint32_t)base_sh;
@@ -1167,7 +1225,7 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
   const uint64_t nh = (uint64_t)tl.n_segs * n_pass * kRadix;
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   k_fill_u32<<<grid_for(nh, 256), 256, 0, s>>>(ghist, nh, 0u);
-  k_fill_u32<<<1, 64, 0, s>>>(tile_ctr, n_pass, 0u);
+  k_fill_u32<<<1, 256, 0, s>>>(tile_ctr, (uint64_t)n_pass * kXcds, 0u);
   QIMAX_DISPATCH_K(KC, {
     hipEvent_t ev = prof_begin(prof, s);
     k_sort_upsweep<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys[0], tl, n_pass, ghist);
@@ -1180,11 +1238,11 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
       if (WP == 64)
         k_sort_scatter<K, double, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
             (const K*)keys[c], (const double*)w[c], (K*)keys[c ^ 1], (double*)w[c ^ 1], T, 8u * p, tl, nullptr,
-            base + (uint64_t)p * kRadix, n_pass * kRadix, status, tile_ctr + p, *epoch, err);
+            base + (uint64_t)p * kRadix, n_pass * kRadix, status, tile_ctr + (uint64_t)p * kXcds, *epoch, err);
       else
         k_sort_scatter<K, float, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
             (const K*)keys[c], (const float*)w[c], (K*)keys[c ^ 1], (float*)w[c ^ 1], T, 8u * p, tl, nullptr,
-            base + (uint64_t)p * kRadix, n_pass * kRadix, status, tile_ctr + p, *epoch, err);
+            base + (uint64_t)p * kRadix, n_pass * kRadix, status, tile_ctr + (uint64_t)p * kXcds, *epoch, err);
       prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T);
       *cur ^= 1;
     }
@@ -1277,7 +1335,7 @@ __global__ void __launch_bounds__(256) k_make_tiles(const uint64_t* __restrict__
                                                     uint32_t cap, uint64_t* __restrict__ blk_begin,
                                                     uint64_t* __restrict__ blk_end, uint32_t* __restrict__ blk_seg,
                                                     uint32_t* __restrict__ seg_blk, uint32_t* __restrict__ n_dev,
-                                                    uint64_t limit, uint32_t* err) {
+                                                    uint32_t* __restrict__ xrange, uint64_t limit, uint32_t* err) {
   __shared__ uint64_t sh[4];
   __shared__ uint64_t carry_sh;
   if (threadIdx.x == 0) carry_sh = 0;
@@ -1303,6 +1361,12 @@ __global__ void __launch_bounds__(256) k_make_tiles(const uint64_t* __restrict__
     *n_dev = total;
   }
   __syncthreads();
+  if (threadIdx.x <= kXcds)
+    xrange[threadIdx.x] =
+        threadIdx.x == kXcds
+            ? total
+            : min(total, seg_boundary_at_or_after(seg_blk, S,
+                                                  (uint32_t)(((uint64_t)threadIdx.x * total + kXcds - 1) / kXcds)));
   for (uint32_t t = threadIdx.x; t < cap; t += 256) {
     if (t < total) {
       uint32_t lo = 0, hi = S;  // last segment s with seg_blk[s] <= t (non-empty)
@@ -1329,9 +1393,9 @@ __global__ void k_copy_u64(const uint64_t* __restrict__ in, uint64_t* __restrict
 }
 
 hipError_t launch_make_tiles(const uint64_t* so, uint32_t S, uint64_t tile, uint32_t cap, uint64_t* blk_begin,
-                             uint64_t* blk_end, uint32_t* blk_seg, uint32_t* seg_blk, uint32_t* n_dev, uint64_t limit,
-                             uint32_t* err, hipStream_t s) {
-  k_make_tiles<<<1, 256, 0, s>>>(so, S, tile, cap, blk_begin, blk_end, blk_seg, seg_blk, n_dev, limit, err);
+                             uint64_t* blk_end, uint32_t* blk_seg, uint32_t* seg_blk, uint32_t* n_dev, uint32_t* xrange,
+                             uint64_t limit, uint32_t* err, hipStream_t s) {
+  k_make_tiles<<<1, 256, 0, s>>>(so, S, tile, cap, blk_begin, blk_end, blk_seg, seg_blk, n_dev, xrange, limit, err);
   return hipGetLastError();
 }
 

@@ -215,11 +215,12 @@ struct qimax_ctx {
   DevBuf desc, desc2, err, f64tmp;
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
-  DevBuf mstatus;  // single-sweep merge state (tile counter at tile_ctr[32])
+  DevBuf mstatus;  // single-sweep merge state (tile counter at tile_ctr[255])
   DevBuf dtile[2];  // device-built image tilings (expand, sort/merge) of the bound path
   uint64_t mepoch = 0;
   bool classic_sort = false;
   bool host_tiling = false;
+  bool xcd_ranges = true;
   DevBuf gr_gate, gr_theta, gr_idx, gr_off, gr_out;
   uint64_t* pinned = nullptr;  // small pinned host scratch
   size_t pinned_words = 0;
@@ -411,6 +412,7 @@ Exp2Desc make_exp2(uint32_t n, const HostOp& op) {
 struct HostTiling {
   std::vector<uint64_t> begin, end;
   std::vector<uint32_t> seg, seg_blk;
+  uint32_t xr[kXcds + 1] = {};  // per-XCD ranges of whole segments (see Tiling::xrange)
 };
 
 void make_tiling(const std::vector<uint64_t>& so, uint64_t tile, HostTiling& t) {
@@ -425,12 +427,18 @@ void make_tiling(const std::vector<uint64_t>& so, uint64_t tile, HostTiling& t) 
     }
   }
   t.seg_blk[S] = (uint32_t)t.begin.size();
+  const uint32_t total = t.seg_blk[S];
+  for (int x = 0; x < kXcds; ++x) {
+    const uint32_t target = (uint32_t)(((uint64_t)x * total + kXcds - 1) / kXcds);
+    t.xr[x] = *std::lower_bound(t.seg_blk.begin(), t.seg_blk.end(), target);
+  }
+  t.xr[kXcds] = total;
 }
 
 // Bytes a tiling occupies in a staging area (four arrays, each 256-aligned).
 size_t tiling_bytes(const HostTiling& t) {
   const size_t nb = std::max<size_t>(t.begin.size(), 1);
-  return align256(nb * 8) * 2 + align256(nb * 4) + align256(t.seg_blk.size() * 4);
+  return align256(nb * 8) * 2 + align256(nb * 4) + align256(t.seg_blk.size() * 4) + 256;
 }
 
 // Copy a tiling into host staging at `off` and describe it by its device addresses.
@@ -443,13 +451,16 @@ size_t put_tiling(const HostTiling& t, uint8_t* host, uint8_t* dev, size_t off, 
     std::memcpy(host + o3, t.seg.data(), nb * 4);
   }
   std::memcpy(host + o4, t.seg_blk.data(), t.seg_blk.size() * 4);
+  const size_t o5 = o4 + align256(t.seg_blk.size() * 4);
+  std::memcpy(host + o5, t.xr, sizeof(t.xr));
+  tl.xrange = (const uint32_t*)(dev + o5);
   tl.blk_begin = (const uint64_t*)(dev + o1);
   tl.blk_end = (const uint64_t*)(dev + o2);
   tl.blk_seg = (const uint32_t*)(dev + o3);
   tl.seg_blk = (const uint32_t*)(dev + o4);
   tl.n_blocks = (uint32_t)nb;
   tl.n_segs = (uint32_t)(t.seg_blk.size() - 1);
-  return o4 + align256(t.seg_blk.size() * 4);
+  return o5 + 256;
 }
 
 qimax_status ensure_stage(qimax_ctx* c, int i, size_t bytes) {
@@ -670,13 +681,14 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     for (int i = 0; i < 2; ++i) {
       const size_t o1 = 0, o2 = align256((size_t)caps[i] * 8), o3 = o2 + align256((size_t)caps[i] * 8);
       const size_t o4 = o3 + align256((size_t)caps[i] * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
-      QCHK(ensure(c, c->dtile[i], o5 + 256));
+      const size_t o6 = o5 + 256;
+      QCHK(ensure(c, c->dtile[i], o6 + 256));
       uint8_t* d = (uint8_t*)c->dtile[i].p;
       HIPCHK(c, launch_make_tiles((const uint64_t*)c->img_seg.p, S, tiles[i], caps[i], (uint64_t*)(d + o1),
                                   (uint64_t*)(d + o2), (uint32_t*)(d + o3), (uint32_t*)(d + o4), (uint32_t*)(d + o5),
-                                  T_img, (uint32_t*)c->err.p, c->stream), "tiles");
+                                  (uint32_t*)(d + o6), T_img, (uint32_t*)c->err.p, c->stream), "tiles");
       *tls[i] = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
-                       (const uint32_t*)(d + o4), caps[i], S, (const uint32_t*)(d + o5)};
+                       (const uint32_t*)(d + o4), caps[i], S, (const uint32_t*)(d + o5), (const uint32_t*)(d + o6)};
     }
   } else {
     QCHK(readback(c, c->img_seg.p, S + 1, &e));
@@ -721,7 +733,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     const uint64_t nh = (uint64_t)S * n_pass * kRadix;
     QCHK(ensure(c, c->ghist, nh * 4));
     QCHK(ensure(c, c->sbase, nh * 8));
-    QCHK(ensure(c, c->tile_ctr, 64 * 4));
+    QCHK(ensure(c, c->tile_ctr, 256 * 4));
     // a grown buffer may come back at the same address with stale contents: detect the
     // reallocation by its size, never by its pointer
     const size_t old_bytes = c->sstatus.bytes;
@@ -733,6 +745,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     void* const kk[2] = {c->ik[0].p, c->ik[1].p};
     void* const ww[2] = {c->iw[0].p, c->iw[1].p};
+    if (!c->xcd_ranges) tl.xrange = nullptr;
     HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, tl, (const uint64_t*)c->img_seg.p,
                                 (uint32_t*)c->ghist.p, (uint64_t*)c->sbase.p, (uint64_t*)c->sstatus.p,
                                 (uint32_t*)c->tile_ctr.p, &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof),
@@ -757,7 +770,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   }
   HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, pas, sent, c->pk[slot].p,
                          c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
-                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, (uint32_t*)c->tile_ctr.p + 32,
+                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, (uint32_t*)c->tile_ctr.p + 255,
                          c->mepoch, (uint32_t*)c->err.p, c->stream, &c->prof), "merge");
   QCHK(bound_path ? readback2(c, c->pseg[slot].p, c->img_seg.p, S + 1, &e) : readback(c, c->pseg[slot].p, S + 1, &e));
   if (e) {
@@ -1284,6 +1297,8 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     c->classic_sort = env && env[0] == '1';
     env = std::getenv("QIMAX_HOST_TILING");  // always read the image count back before expanding
     c->host_tiling = env && env[0] == '1';
+    env = std::getenv("QIMAX_XCD_RANGES");  // 0: sort tiles claimed in one global order
+    c->xcd_ranges = !(env && env[0] == '0');
   }
   hipError_t e;
   if (o.device >= 0) {

@@ -90,7 +90,10 @@ struct Tiling {
   uint32_t n_segs;
   const uint32_t* n_dev;  // if set: the actual number of tiles, known only on the device;
                           // tiles beyond it are empty and their blocks return at once
+  const uint32_t* xrange; // if set (9 entries): tiles [xrange[x], xrange[x+1]) form whole
+                          // segments and are claimed first by the blocks running on XCD x
 };
+constexpr int kXcds = 8;  // accelerator complex dies of the chip; each has its own L2
 
 constexpr int kSortBlock = 256;            // threads per sort / merge block
 constexpr int kSortItems = 16;             // items per thread
@@ -210,12 +213,12 @@ hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t*
                             uint32_t n_circ, hipStream_t s);
 
 // Segment-aligned tiles of at most `tile` elements built on the device from device segment
-// offsets so[0..S]; cap tiles are written (the ones past the actual count are empty) and the
-// actual count goes to *n_dev. Tile ranges are clamped to [0, limit) (elements of the
+// offsets so[0..S]; cap tiles are written (the ones past the actual count are empty), the
+// actual count goes to *n_dev and the per-XCD ranges of whole segments to xrange[0..8]. Tile ranges are clamped to [0, limit) (elements of the
 // buffers they index); a tile count above cap or so[S] above limit sets an error bit.
 hipError_t launch_make_tiles(const uint64_t* so, uint32_t S, uint64_t tile, uint32_t cap, uint64_t* blk_begin,
-                             uint64_t* blk_end, uint32_t* blk_seg, uint32_t* seg_blk, uint32_t* n_dev, uint64_t limit,
-                             uint32_t* err, hipStream_t s);
+                             uint64_t* blk_end, uint32_t* blk_seg, uint32_t* seg_blk, uint32_t* n_dev, uint32_t* xrange,
+                             uint64_t limit, uint32_t* err, hipStream_t s);
 
 // Plain copy of n words (calibration of hardware traffic counters).
 hipError_t launch_copy_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s);

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqimax.so")
+# QIMAX_LIB may name another build of the library (experiments with build variants)
+LIB_PATH = os.environ.get("QIMAX_LIB") or os.path.join(_HERE, "libqimax.so")
 
 STATUS = {0: "QIMAX_OK", -1: "QIMAX_EINVAL", -2: "QIMAX_ENOMEM", -3: "QIMAX_EDEVICE",
           -4: "QIMAX_ETOOLARGE", -5: "QIMAX_ESTATE"}
