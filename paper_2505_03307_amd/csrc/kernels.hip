@@ -165,55 +165,6 @@ __global__ void k_init(K* keys, W* w, uint64_t* seg_off, uint32_t n) {
   if (j == 0) seg_off[n] = n;
 }
 
-// ----------------------------------------------------------------------- fan-out count
-// One block per segment-aligned tile of input terms; the tile's segment selects the pass
-// of its circuit (pas[seg_entry[segment]]).
-template <typename K>
-__global__ void __launch_bounds__(256) k_count(const K* __restrict__ keys, Tiling tl, const PassArgs* __restrict__ pas,
-                                               const uint32_t* __restrict__ seg_entry, uint32_t* __restrict__ cnt,
-                                               uint32_t* err) {
-  constexpr int kTabN = sizeof(K) <= 8 ? (int)sizeof(K) * 256 : 1;  // no tables for 16-byte keys
-  __shared__ K tk[kTabN];
-  __shared__ uint8_t tn[kTabN];
-  const uint32_t b = blockIdx.x;
-  const PassArgs pa = pas[seg_entry[tl.blk_seg[b]]];
-  const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
-  if (pa.drop) {
-    for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) cnt[i] = 0u;
-    return;
-  }
-  if (pa.useA) {
-    stage_table(pa.tA, tk, tn);
-    __syncthreads();
-  }
-  constexpr int kItems = kSortTile / 256;  // input tiles hold at most kSortTile terms
-  const uint32_t n = (uint32_t)(end - begin);
-  K kr[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {  // every load in flight before the first use
-    const uint32_t li = r * 256 + threadIdx.x;
-    kr[r] = keys[n ? begin + min(li, n - 1) : 0];
-  }
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t li = r * 256 + threadIdx.x;
-    if (li >= n) break;
-    const uint64_t i = begin + li;
-    K key = kr[r];
-    uint32_t neg = 0;
-    if (pa.useA) key = apply_table(key, tk, tn, neg);
-    else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
-    uint64_t f = 1;
-    for (uint32_t e = 0; e < pa.nE1 && f <= 0xFFFFFFFFull; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
-    for (uint32_t e = 0; e < pa.nE2 && f <= 0xFFFFFFFFull; ++e) f *= pa.E2[e].cnt[local2(key, pa.E2[e].pa, pa.E2[e].pb)];
-    if (f > 0xFFFFFFFFull) {
-      atomicOr(err, kErrFanout);
-      f = 0;
-    }
-    cnt[i] = (uint32_t)f;
-  }
-}
-
 // ------------------------------------------------------------------------------ scans
 template <typename TI>
 __global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const TI* __restrict__ in, uint64_t N,
@@ -500,8 +451,9 @@ template <typename K, typename W, bool kSweep>
 __global__ void __launch_bounds__(kSortBlock)
 k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __restrict__ keys_out,
                W* __restrict__ w_out, uint64_t T, uint32_t shift, Tiling tl,
-               const uint64_t* __restrict__ hist_off, const uint64_t* __restrict__ base, uint32_t base_stride,
-               uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr, uint64_t epoch, uint32_t* err) {
+               const uint64_t* __restrict__ hist_off, const uint32_t* __restrict__ ghist_p, uint32_t gstride,
+               const uint64_t* __restrict__ seg_off, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
+               uint64_t epoch, uint32_t* err) {
   constexpr int kWaves = kSortBlock / 64;
   constexpr int kRounds = kSortItems;                 // rounds per wave
   constexpr int kWaveSpan = 64 * kRounds;             // tile elements per wave
@@ -550,6 +502,13 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
   const uint32_t n_tile = (uint32_t)(end - begin);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // sweep: the segment's count of this thread's digit (all tiles) and the segment start
+  uint64_t seg_cnt = 0, seg_begin = 0;
+  if constexpr (kSweep) {
+    const uint32_t s = tl.blk_seg[b];
+    seg_cnt = ghist_p[(uint64_t)s * gstride + threadIdx.x];
+    seg_begin = seg_off[s];
+  }
   for (int k = threadIdx.x; k < kWaves * kRadix; k += kSortBlock) (&wrun[0][0])[k] = 0;
   __syncthreads();
 
@@ -618,10 +577,14 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
       }
       st_store(my, ep | kStPre | (excl + tile_cnt));
     }
-    gbase[d] = base[(uint64_t)s * base_stride + d] + excl;
+    gbase[d] = excl;
   }
+  // one scan gives the tile-local digit starts (low 16 bits: a tile holds at most 4096 < 2^16
+  // elements) and, in a sweep, the segment-wide start of every digit (high bits)
   uint64_t tot;
-  const uint64_t ds = block_excl_scan<kSortBlock>(tile_cnt, scan_sh, &tot);
+  const uint64_t ds2 = block_excl_scan<kSortBlock>((seg_cnt << 16) | tile_cnt, scan_sh, &tot);
+  const uint64_t ds = ds2 & 0xFFFFu;
+  if constexpr (kSweep) gbase[d] += seg_begin + (ds2 >> 16);
   dstart[d] = (uint32_t)ds;
   if constexpr (!kSweep) gbase[d] = tile_cnt ? hist_off[hist_pos(tl, b, d)] : 0;
   __syncthreads();
@@ -693,6 +656,112 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   }
 }
 
+// Fan-out count and its exclusive scan in one sweep: tiles of input terms are claimed in
+// order; each computes f = prod nnz(PTM column) for its terms (the A chain applied first),
+// publishes its total and looks back over the earlier tiles for its global offset, then
+// writes off[i] = first image of term i (off[T_in] = image count, from the last tile).
+template <typename K>
+__global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, Tiling tl,
+                                                    const PassArgs* __restrict__ pas,
+                                                    const uint32_t* __restrict__ seg_entry, uint64_t* __restrict__ off,
+                                                    uint64_t T_in, uint64_t* __restrict__ status,
+                                                    uint32_t* __restrict__ ctr, uint64_t epoch, uint32_t* err) {
+  constexpr int kItems = kSortTile / 256;  // input tiles hold at most kSortTile terms
+  constexpr int kTabN = sizeof(K) <= 8 ? (int)sizeof(K) * 256 : 1;  // no tables for 16-byte keys
+  __shared__ K tk[kTabN];
+  __shared__ uint8_t tn[kTabN];
+  __shared__ uint64_t sf[kSortTile + kSortTile / kItems];  // one pad word per thread's run of items
+  __shared__ uint64_t scan_sh[4];
+  __shared__ uint64_t base_sh;
+  __shared__ uint32_t tile_sh;
+  if (threadIdx.x == 0) tile_sh = atomicAdd(ctr, 1u);
+  __syncthreads();
+  const uint32_t b = tile_sh;  // launched with exactly n_blocks blocks
+  const PassArgs pa = pas[seg_entry[tl.blk_seg[b]]];
+  const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
+  const uint32_t n = (uint32_t)(end - begin);
+  auto pad = [](uint32_t li) { return li + li / kItems; };
+  K kr[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {  // every load in flight before the first use
+    const uint32_t li = r * 256 + threadIdx.x;
+    kr[r] = keys[n ? begin + min(li, n - 1) : 0];
+  }
+  if (pa.useA && !pa.drop) {
+    stage_table(pa.tA, tk, tn);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t li = r * 256 + threadIdx.x;
+    if (li >= n) break;
+    uint64_t f = 0;
+    if (!pa.drop) {
+      K key = kr[r];
+      uint32_t neg = 0;
+      if (pa.useA) key = apply_table(key, tk, tn, neg);
+      else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+      f = 1;
+      for (uint32_t e = 0; e < pa.nE1 && f <= 0xFFFFFFFFull; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
+      for (uint32_t e = 0; e < pa.nE2 && f <= 0xFFFFFFFFull; ++e)
+        f *= pa.E2[e].cnt[local2(key, pa.E2[e].pa, pa.E2[e].pb)];
+      if (f > 0xFFFFFFFFull) {
+        atomicOr(err, kErrFanout);
+        f = 0;
+      }
+    }
+    sf[pad(li)] = f;
+  }
+  __syncthreads();
+  // each thread sums a run of kItems consecutive terms; block scan of the run sums
+  const uint32_t l0 = threadIdx.x * kItems;
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k2 = 0; k2 < kItems; ++k2)
+    if (l0 + k2 < n) sum += sf[pad(l0 + k2)];
+  uint64_t tot;
+  const uint64_t pre = block_excl_scan<256>(sum, scan_sh, &tot);
+  if (threadIdx.x == 0) {
+    const uint64_t ep = epoch << 48;
+    st_store(status + b, ep | (b == 0 ? kStPre : kStAgg) | tot);
+    uint64_t excl = 0;
+    if (b > 0) {
+      uint32_t t = b - 1;
+      uint32_t spins = 0;
+      while (true) {
+        const uint64_t v = st_load(status + t);
+        const bool ready = (v >> 48) == epoch && (v & (kStAgg | kStPre));
+        if (!ready) {
+          if (++spins > kSpinLimit) { atomicOr(err, kErrSpin); break; }
+          continue;
+        }
+        excl += v & kStValMask;
+        if ((v & kStPre) || t == 0) break;
+        --t;
+      }
+      st_store(status + b, ep | kStPre | (excl + tot));
+    }
+    base_sh = excl;
+    if (b + 1 == tl.n_blocks) off[T_in] = excl + tot;
+  }
+  __syncthreads();
+  uint64_t run = base_sh + pre;
+#pragma unroll
+  for (int k2 = 0; k2 < kItems; ++k2) {
+    if (l0 + k2 < n) {
+      const uint64_t v = sf[pad(l0 + k2)];
+      sf[pad(l0 + k2)] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t li = r * 256 + threadIdx.x;
+    if (li < n) off[begin + li] = sf[pad(li)];
+  }
+}
+
 // Digit histograms of every radix pass at once, per segment: ghist[(s*n_pass + p)*256 + d].
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict__ keys, Tiling tl, uint32_t n_pass,
@@ -726,20 +795,6 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict
     for (int w = 0; w < kWaves; ++w) c += h[w][p][dd];
     if (c) atomicAdd(&ghist[((uint64_t)s * n_pass + p) * kRadix + dd], c);
   }
-}
-
-// base[(s*n_pass + p)*256 + d] = seg_off[s] + (elements of segment s with a smaller digit in pass p);
-// one block per (segment, pass).
-__global__ void __launch_bounds__(kSortBlock) k_sort_bases(const uint32_t* __restrict__ ghist,
-                                                           const uint64_t* __restrict__ seg_off, uint32_t n_pass,
-                                                           uint64_t* __restrict__ base) {
-  __shared__ uint64_t sh[kSortBlock / 64];
-  const uint32_t sp = blockIdx.x;  // s * n_pass + p
-  const uint32_t s = sp / n_pass;
-  const uint64_t v = ghist[(uint64_t)sp * kRadix + threadIdx.x];
-  uint64_t tot;
-  const uint64_t ex = block_excl_scan<kSortBlock>(v, sh, &tot);
-  base[(uint64_t)sp * kRadix + threadIdx.x] = seg_off[s] + ex;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
@@ -802,6 +857,20 @@ struct F64Sum {  // FP32 weights accumulated in FP64, rounded once
 // offsets (blk_off); 2: single sweep - tiles are claimed in order, each publishes its
 // count and looks back over the earlier tiles for its output offset (written to blk_off,
 // with the total at blk_off[n_blocks]), then writes.
+// After the merge (one block): the segment output offsets seg_off_out[s] = blk_off[seg_blk[s]]
+// (all 0 when there are no tiles) and the packed readback area (see MergeFin).
+__global__ void k_merge_publish(Tiling tl, const uint64_t* __restrict__ blk_off, uint64_t* __restrict__ seg_off_out,
+                                MergeFin fin, const uint32_t* __restrict__ err, int none) {
+  const uint32_t S = tl.n_segs;
+  for (uint32_t s = threadIdx.x; s <= S; s += blockDim.x) {
+    const uint64_t v = none ? 0ull : blk_off[tl.seg_blk[s]];
+    seg_off_out[s] = v;
+    fin.result[s] = v;
+    fin.result[S + 1 + s] = fin.img_seg[s];
+  }
+  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err;
+}
+
 template <typename K, typename W, int kMode>
 __global__ void __launch_bounds__(kSortBlock)
 k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const PassArgs* __restrict__ pas,
@@ -1127,12 +1196,18 @@ hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, u
   return hipGetLastError();
 }
 
-hipError_t launch_count(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
-                        const uint32_t* seg_entry, uint32_t* cnt, uint32_t* err, hipStream_t s, Prof* prof) {
-  if (T == 0 || tl.n_blocks == 0) return hipSuccess;
+hipError_t launch_count_scan(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
+                             const uint32_t* seg_entry, uint64_t* off, uint64_t* status, uint32_t* ctr, uint64_t epoch,
+                             uint32_t* err, hipStream_t s, Prof* prof) {
+  if (T == 0 || tl.n_blocks == 0) {
+    k_zero_one<<<1, 1, 0, s>>>(off);
+    return hipGetLastError();
+  }
   hipEvent_t ev = prof_begin(prof, s);
-  QIMAX_DISPATCH_K(KC, { k_count<K><<<tl.n_blocks, 256, 0, s>>>((const K*)keys, tl, pas, seg_entry, cnt, err); });
-  prof_end(prof, s, ev, kKCount, (double)T * ((4 << KC) + 4));
+  QIMAX_DISPATCH_K(KC, {
+    k_count_scan<K><<<tl.n_blocks, 256, 0, s>>>((const K*)keys, tl, pas, seg_entry, off, T, status, ctr, epoch, err);
+  });
+  prof_end(prof, s, ev, kKCount, (double)T * ((4 << KC) + 8));
   return hipGetLastError();
 }
 
@@ -1205,32 +1280,28 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
     if (WP == 64)
       k_sort_scatter<K, double, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
           (const K*)keys_in, (const double*)w_in, (K*)keys_out, (double*)w_out, T, shift, tl, hist_off, nullptr, 0,
-          nullptr, nullptr, 0, err);
+          nullptr, nullptr, nullptr, 0, err);
     else
       k_sort_scatter<K, float, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
           (const K*)keys_in, (const float*)w_in, (K*)keys_out, (float*)w_out, T, shift, tl, hist_off, nullptr, 0,
-          nullptr, nullptr, 0, err);
+          nullptr, nullptr, nullptr, 0, err);
     prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[2], uint64_t T, uint32_t key_bits,
-                             const Tiling& tl, const uint64_t* seg_off, uint32_t* ghist, uint64_t* base,
-                             uint64_t* status, uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err, int* cur,
-                             hipStream_t s, Prof* prof) {
+                             const Tiling& tl, const uint64_t* seg_off, uint32_t* ghist, uint64_t* status,
+                             uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err, int* cur, hipStream_t s,
+                             Prof* prof) {
   *cur = 0;
   if (T == 0 || tl.n_blocks == 0) return hipSuccess;
   const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
-  const uint64_t nh = (uint64_t)tl.n_segs * n_pass * kRadix;
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
-  k_fill_u32<<<grid_for(nh, 256), 256, 0, s>>>(ghist, nh, 0u);
-  k_fill_u32<<<1, 256, 0, s>>>(tile_ctr, (uint64_t)n_pass * kXcds, 0u);
   QIMAX_DISPATCH_K(KC, {
     hipEvent_t ev = prof_begin(prof, s);
     k_sort_upsweep<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys[0], tl, n_pass, ghist);
     prof_end(prof, s, ev, kKSortHist, kb * (double)T);
-    k_sort_bases<<<tl.n_segs * n_pass, kSortBlock, 0, s>>>(ghist, seg_off, n_pass, base);
     for (uint32_t p = 0; p < n_pass; ++p) {
       *epoch += 1;  // the caller keeps *epoch + n_pass below 2^16 (clearing status on wrap)
       ev = prof_begin(prof, s);
@@ -1238,11 +1309,13 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
       if (WP == 64)
         k_sort_scatter<K, double, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
             (const K*)keys[c], (const double*)w[c], (K*)keys[c ^ 1], (double*)w[c ^ 1], T, 8u * p, tl, nullptr,
-            base + (uint64_t)p * kRadix, n_pass * kRadix, status, tile_ctr + (uint64_t)p * kXcds, *epoch, err);
+            ghist + (uint64_t)p * kRadix, n_pass * kRadix, seg_off, status, tile_ctr + (uint64_t)p * kXcds, *epoch,
+            err);
       else
         k_sort_scatter<K, float, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
             (const K*)keys[c], (const float*)w[c], (K*)keys[c ^ 1], (float*)w[c ^ 1], T, 8u * p, tl, nullptr,
-            base + (uint64_t)p * kRadix, n_pass * kRadix, status, tile_ctr + (uint64_t)p * kXcds, *epoch, err);
+            ghist + (uint64_t)p * kRadix, n_pass * kRadix, seg_off, status, tile_ctr + (uint64_t)p * kXcds, *epoch,
+            err);
       prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T);
       *cur ^= 1;
     }
@@ -1259,8 +1332,12 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
 hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, uint64_t T,
                         const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out, void* w_out,
                         uint64_t out_cap, uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
-                        uint64_t* status, uint32_t* tile_ctr, uint64_t epoch, uint32_t* err, hipStream_t s,
-                        Prof* prof) {
+                        uint64_t* status, uint32_t* tile_ctr, uint64_t epoch, uint32_t* err, const MergeFin* fin,
+                        hipStream_t s, Prof* prof) {
+  if (tl.n_blocks == 0 && fin) {
+    k_merge_publish<<<1, 256, 0, s>>>(tl, nullptr, seg_off_out, *fin, err, 1);
+    return hipGetLastError();
+  }
   if (tl.n_blocks == 0) {
     // no terms at all: every segment offset is zero
     k_zero_one<<<1, 1, 0, s>>>(blk_off);
@@ -1271,7 +1348,7 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   QIMAX_DISPATCH_K(KC, {
     if (status) {  // single sweep
-      k_fill_u32<<<1, 64, 0, s>>>(tile_ctr, 1, 0u);
+      if (!fin) k_fill_u32<<<1, 64, 0, s>>>(tile_ctr, 1, 0u);  // with fin: zeroed by the caller
       hipEvent_t ev = prof_begin(prof, s);
       if (WP == 64)
         k_merge<K, double, 2><<<tl.n_blocks, kSortBlock, 0, s>>>(
@@ -1308,7 +1385,10 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
       prof_end(prof, s, ev, kKMergeWrite, (kb + wb) * (double)T);
     }
   });
-  k_gather_u64_by_u32<<<grid_for(tl.n_segs + 1, 64), 64, 0, s>>>(blk_off, tl.seg_blk, seg_off_out, tl.n_segs + 1);
+  if (fin)  // offsets and the packed readback area
+    k_merge_publish<<<1, 256, 0, s>>>(tl, blk_off, seg_off_out, *fin, err, 0);
+  else
+    k_gather_u64_by_u32<<<grid_for(tl.n_segs + 1, 64), 64, 0, s>>>(blk_off, tl.seg_blk, seg_off_out, tl.n_segs + 1);
   return hipGetLastError();
 }
 
@@ -1329,20 +1409,33 @@ hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t*
   return hipGetLastError();
 }
 
-// One block: per-segment tile counts, their exclusive scan (seg_blk), then every tile of
-// the cap range (empty past the total).
-__global__ void __launch_bounds__(256) k_make_tiles(const uint64_t* __restrict__ so, uint32_t S, uint64_t tile,
-                                                    uint32_t cap, uint64_t* __restrict__ blk_begin,
-                                                    uint64_t* __restrict__ blk_end, uint32_t* __restrict__ blk_seg,
-                                                    uint32_t* __restrict__ seg_blk, uint32_t* __restrict__ n_dev,
-                                                    uint32_t* __restrict__ xrange, uint64_t limit, uint32_t* err) {
+// Block i builds tiling i (segment-aligned tiles of at most job.tile images; cap tiles are
+// written, the ones past the actual count empty) from the image offsets of the segments,
+// so[s] = off[seg_in[s]]; block 0 also stores those offsets in img_seg.
+__global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict__ off,
+                                                     const uint64_t* __restrict__ seg_in, uint32_t S,
+                                                     uint64_t* __restrict__ img_seg, TileJob2 j0, TileJob2 j1,
+                                                     uint64_t limit, uint32_t* err) {
+  const TileJob2 job = blockIdx.x == 0 ? j0 : j1;
+  const uint64_t tile = job.tile;
+  const uint32_t cap = job.cap;
+  uint32_t* __restrict__ seg_blk = job.seg_blk;
+  auto so = [&](uint32_t s) { return off[seg_in[s]]; };
   __shared__ uint64_t sh[4];
   __shared__ uint64_t carry_sh;
   if (threadIdx.x == 0) carry_sh = 0;
   __syncthreads();
   for (uint32_t base = 0; base < S; base += 256) {
     const uint32_t s = base + threadIdx.x;
-    const uint64_t len = s < S ? so[s + 1] - so[s] : 0;
+    uint64_t len = 0;
+    if (s < S) {
+      const uint64_t a = so(s), b = so(s + 1);
+      len = b - a;
+      if (blockIdx.x == 0) {
+        img_seg[s] = a;
+        if (s + 1 == S) img_seg[S] = b;
+      }
+    }
     const uint64_t nt = (len + tile - 1) / tile;
     uint64_t tot;
     const uint64_t pre = block_excl_scan<256>(nt, sh, &tot);
@@ -1352,17 +1445,19 @@ __global__ void __launch_bounds__(256) k_make_tiles(const uint64_t* __restrict__
     if (threadIdx.x == 0) carry_sh = carry + tot;
     __syncthreads();
   }
-  // more tiles or elements than the capacity: the bound was not an upper bound (tiles are
+  if (S == 0 && blockIdx.x == 0 && threadIdx.x == 0) img_seg[0] = so(0);
+  const uint64_t total_img = so(S);
+  // more tiles or images than the capacity: the bound was not an upper bound (tiles are
   // clamped below so that nothing reads past the buffers; the pass reports the error)
-  if (threadIdx.x == 0 && (carry_sh > cap || so[S] > limit)) atomicOr(err, kErrIndex | kErrFanout);
+  if (threadIdx.x == 0 && (carry_sh > cap || total_img > limit)) atomicOr(err, kErrIndex | kErrFanout);
   const uint32_t total = (uint32_t)min<uint64_t>(carry_sh, cap);
   if (threadIdx.x == 0) {
     seg_blk[S] = total;
-    *n_dev = total;
+    *job.n_dev = total;
   }
   __syncthreads();
   if (threadIdx.x <= kXcds)
-    xrange[threadIdx.x] =
+    job.xrange[threadIdx.x] =
         threadIdx.x == kXcds
             ? total
             : min(total, seg_boundary_at_or_after(seg_blk, S,
@@ -1374,17 +1469,25 @@ __global__ void __launch_bounds__(256) k_make_tiles(const uint64_t* __restrict__
         const uint32_t mid = (lo + hi) >> 1;
         if (seg_blk[mid] <= t) lo = mid; else hi = mid;
       }
-      while (lo + 1 < S && seg_blk[lo + 1] <= t) ++lo;  // skip empty segments sharing the start
-      const uint64_t b0 = so[lo] + (uint64_t)(t - seg_blk[lo]) * tile;
-      blk_begin[t] = min(b0, limit);
-      blk_end[t] = min(min(b0 + tile, so[lo + 1]), limit);
-      blk_seg[t] = lo;
+      const uint64_t b0 = so(lo) + (uint64_t)(t - seg_blk[lo]) * tile;
+      job.blk_begin[t] = min(b0, limit);
+      job.blk_end[t] = min(min(b0 + tile, so(lo + 1)), limit);
+      job.blk_seg[t] = lo;
     } else {
-      blk_begin[t] = 0;
-      blk_end[t] = 0;
-      blk_seg[t] = 0;
+      job.blk_begin[t] = 0;
+      job.blk_end[t] = 0;
+      job.blk_seg[t] = 0;
     }
   }
+}
+
+// Clears the round's error word, tile counters and digit histograms (one launch).
+__global__ void k_round_prep(uint32_t* __restrict__ err, uint32_t* __restrict__ ctr, uint32_t n_ctr,
+                             uint32_t* __restrict__ ghist, uint64_t nh) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *err = 0u;
+  if (i < n_ctr) ctr[i] = 0u;
+  for (uint64_t j = i; j < nh; j += (uint64_t)gridDim.x * blockDim.x) ghist[j] = 0u;
 }
 
 __global__ void k_copy_u64(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n) {
@@ -1392,10 +1495,17 @@ __global__ void k_copy_u64(const uint64_t* __restrict__ in, uint64_t* __restrict
     out[i] = in[i];
 }
 
-hipError_t launch_make_tiles(const uint64_t* so, uint32_t S, uint64_t tile, uint32_t cap, uint64_t* blk_begin,
-                             uint64_t* blk_end, uint32_t* blk_seg, uint32_t* seg_blk, uint32_t* n_dev, uint32_t* xrange,
-                             uint64_t limit, uint32_t* err, hipStream_t s) {
-  k_make_tiles<<<1, 256, 0, s>>>(so, S, tile, cap, blk_begin, blk_end, blk_seg, seg_blk, n_dev, xrange, limit, err);
+hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint32_t S, uint64_t* img_seg,
+                              const TileJob2& j0, const TileJob2& j1, uint64_t limit, uint32_t* err, hipStream_t s) {
+  k_make_tiles2<<<2, 256, 0, s>>>(off, seg_in, S, img_seg, j0, j1, limit, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_prep(uint32_t* err, uint32_t* ctr, uint32_t n_ctr, uint32_t* ghist, uint64_t nh,
+                             hipStream_t s) {
+  const uint64_t n = std::max<uint64_t>(nh, n_ctr);
+  k_round_prep<<<(uint32_t)std::min<uint64_t>(grid_for(std::max<uint64_t>(n, 1), 256), 1024), 256, 0, s>>>(
+      err, ctr, n_ctr, ghist, nh);
   return hipGetLastError();
 }
 

@@ -183,6 +183,8 @@ bool is_conjugation(const std::vector<double>& R, int dim) {
 
 constexpr int kMaxE1 = 64;
 constexpr int kBoundPathMaxFanout = 16;  // rounds with a larger fan-out bound read back their image count
+// tile counters of a round (after the per-pass, per-XCD sort counters)
+constexpr int kCtrCount = 252, kCtrMerge = 253;
 constexpr int kMaxE2 = 8;
 constexpr double kMaxFanout = 2147483647.0;
 
@@ -215,7 +217,8 @@ struct qimax_ctx {
   DevBuf desc, desc2, err, f64tmp;
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
-  DevBuf mstatus;  // single-sweep merge state (tile counter at tile_ctr[255])
+  DevBuf mstatus;  // single-sweep count and merge state (one word per tile)
+  DevBuf result;   // packed readback of a round
   DevBuf dtile[2];  // device-built image tilings (expand, sort/merge) of the bound path
   uint64_t mepoch = 0;
   bool classic_sort = false;
@@ -345,7 +348,6 @@ qimax_status ensure_keep(qimax_ctx* c, DevBuf& b, size_t bytes, size_t keep) {
     if (_s != QIMAX_OK) return _s;         \
   } while (0)
 
-__global__ void k_clear_u32(uint32_t* p) { *p = 0u; }
 
 uint32_t bitpos(uint32_t n, int q) { return 2u * (n - 1u - (uint32_t)q); }
 
@@ -478,7 +480,9 @@ qimax_status ensure_stage(qimax_ctx* c, int i, size_t bytes) {
 }
 
 // Copy `words` uint64 from device to the pinned scratch (plus the error word) and wait.
-qimax_status readback(qimax_ctx* c, const void* dev, size_t words, uint32_t* err_out) {
+// `words` uint64 from the device to the pinned scratch, then the error word: the context's
+// (one more copy) or, with err_packed, the last of the words.
+qimax_status readback(qimax_ctx* c, const void* dev, size_t words, uint32_t* err_out, bool err_packed = false) {
   if (words + 1 > c->pinned_words) {
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
@@ -488,34 +492,14 @@ qimax_status readback(qimax_ctx* c, const void* dev, size_t words, uint32_t* err
   }
   if (words)
     HIPCHK(c, hipMemcpyAsync(c->pinned, dev, words * 8, hipMemcpyDeviceToHost, c->stream), "readback");
-  HIPCHK(c, hipMemcpyAsync(c->pinned + words, c->err.p, 4, hipMemcpyDeviceToHost, c->stream), "readback err");
+  if (!err_packed)
+    HIPCHK(c, hipMemcpyAsync(c->pinned + words, c->err.p, 4, hipMemcpyDeviceToHost, c->stream), "readback err");
   const auto t0 = std::chrono::steady_clock::now();
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   c->st.host_wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   c->st.syncs += 1;
   prof_resolve(&c->prof);
-  *err_out = (uint32_t)(c->pinned[words] & 0xFFFFFFFFu);
-  return QIMAX_OK;
-}
-
-// Two arrays of `words` uint64 each (a then b) to the pinned scratch, plus the error word.
-qimax_status readback2(qimax_ctx* c, const void* a, const void* b, size_t words, uint32_t* err_out) {
-  if (2 * words + 1 > c->pinned_words) {
-    if (c->pinned) (void)hipHostFree(c->pinned);
-    c->pinned = nullptr;
-    size_t want = std::max<size_t>(2 * words + 1, 4096);
-    HIPCHK(c, hipHostMalloc((void**)&c->pinned, want * 8, hipHostMallocDefault), "hipHostMalloc");
-    c->pinned_words = want;
-  }
-  HIPCHK(c, hipMemcpyAsync(c->pinned, a, words * 8, hipMemcpyDeviceToHost, c->stream), "readback");
-  HIPCHK(c, hipMemcpyAsync(c->pinned + words, b, words * 8, hipMemcpyDeviceToHost, c->stream), "readback");
-  HIPCHK(c, hipMemcpyAsync(c->pinned + 2 * words, c->err.p, 4, hipMemcpyDeviceToHost, c->stream), "readback err");
-  const auto t0 = std::chrono::steady_clock::now();
-  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  c->st.host_wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  c->st.syncs += 1;
-  prof_resolve(&c->prof);
-  *err_out = (uint32_t)(c->pinned[2 * words] & 0xFFFFFFFFu);
+  *err_out = (uint32_t)(c->pinned[err_packed ? words - 1 : words] & 0xFFFFFFFFu);
   return QIMAX_OK;
 }
 
@@ -646,20 +630,36 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   HIPCHK(c, hipMemcpyAsync(ds, hs, host_bytes, hipMemcpyHostToDevice, c->stream), "upload round");
   const PassArgs* pas = (const PassArgs*)(ds + oA);
   const uint32_t* sent = (const uint32_t*)(ds + oS);
+  const bool sweep = !c->classic_sort;
+  const uint32_t key_bits = 2u * max_n;
+  const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
+  // ---- round prep: error word, tile counters, digit histograms (one launch)
+  // tile_ctr: [0, n_pass*kXcds) sort passes, [kCtrCount] count tiles, [kCtrMerge] merge tiles
+  const uint64_t nh = sweep ? (uint64_t)S * n_pass * kRadix : 0;
+  if (sweep) QCHK(ensure(c, c->ghist, std::max<uint64_t>(nh, 1) * 4));
+  QCHK(ensure(c, c->tile_ctr, 256 * 4));
+  uint32_t* const ctr = (uint32_t*)c->tile_ctr.p;
+  HIPCHK(c, launch_round_prep((uint32_t*)c->err.p, ctr, 256, (uint32_t*)c->ghist.p, nh, c->stream), "prep");
   HIPCHK(c, launch_build_tables(c->KC, (const TableJob*)(ds + oJ), (uint32_t)n_jobs, c->stream, &c->prof),
          "chain tables");
-  k_clear_u32<<<1, 1, 0, c->stream>>>((uint32_t*)c->err.p);
-  // ---- fan-out count and scan -> image offsets
-  QCHK(ensure(c, c->cnt, std::max<uint64_t>(T_in, 1) * 4));
+  // ---- fan-out count fused with its scan -> image offsets of every input term
+  // mstatus: one word per tile, shared by the count and merge sweeps (distinct epochs)
+  auto status_words = [&](uint64_t tiles) -> qimax_status {
+    const size_t old_m = c->mstatus.bytes;
+    QCHK(ensure(c, c->mstatus, (size_t)(tiles + 1) * 8));
+    if (c->mstatus.bytes != old_m || c->mepoch + 2 >= 0xFFFFull) {
+      // fresh memory or epoch wrap: clear every word so that no stale epoch can match
+      HIPCHK(c, launch_fill_u64((uint64_t*)c->mstatus.p, c->mstatus.bytes / 8, 0ull, c->stream), "clear status");
+      c->mepoch = 0;
+    }
+    return QIMAX_OK;
+  };
   QCHK(ensure(c, c->off, (T_in + 1) * 8));
-  QCHK(ensure(c, c->scan_tmp, scan_tmp_words(T_in) * 8));
-  HIPCHK(c, launch_count(c->KC, k_in, T_in, tl_in, pas, sent, (uint32_t*)c->cnt.p, (uint32_t*)c->err.p, c->stream,
-                         &c->prof), "count");
-  HIPCHK(c, launch_scan_u32((const uint32_t*)c->cnt.p, (uint64_t*)c->off.p, T_in, (uint64_t*)c->scan_tmp.p,
-                            c->stream, &c->prof), "scan");
+  QCHK(status_words(tl_in.n_blocks));
+  c->mepoch += 1;
+  HIPCHK(c, launch_count_scan(c->KC, k_in, T_in, tl_in, pas, sent, (uint64_t*)c->off.p, (uint64_t*)c->mstatus.p,
+                              ctr + kCtrCount, c->mepoch, (uint32_t*)c->err.p, c->stream, &c->prof), "count");
   QCHK(ensure(c, c->img_seg, (S + 1) * 8));
-  HIPCHK(c, launch_gather_u64((const uint64_t*)c->off.p, seg_in, (uint64_t*)c->img_seg.p, S + 1, c->stream, &c->prof),
-         "gather");
   uint32_t e = 0;
   // Bound path: with a small fan-out bound f, T_img <= f * T_in, so the image tilings are
   // built on the device and every launch is sized by the bound (tiles past the real count
@@ -668,29 +668,32 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   double f_round = 0.0;
   for (const RoundEntry& en : entries)
     if (en.pass && !en.drop) f_round = std::max(f_round, en.pass->fanout_bound);
-  const bool bound_path = !c->classic_sort && !c->host_tiling && f_round <= (double)kBoundPathMaxFanout && T_in > 0;
+  const bool bound_path = sweep && !c->host_tiling && f_round <= (double)kBoundPathMaxFanout && T_in > 0;
   uint64_t T_img = 0;
   Tiling tl_exp{}, tl{};
   if (bound_path) {
     T_img = (uint64_t)f_round * T_in;  // capacity: an upper bound of the image count
-    const uint32_t cap_exp = (uint32_t)((T_img + kExpandTile - 1) / kExpandTile + S);
-    const uint32_t cap_sort = (uint32_t)((T_img + kSortTile - 1) / kSortTile + S);
-    const uint32_t caps[2] = {cap_exp, cap_sort};
+    const uint32_t caps[2] = {(uint32_t)((T_img + kExpandTile - 1) / kExpandTile + S),
+                              (uint32_t)((T_img + kSortTile - 1) / kSortTile + S)};
     const uint64_t tiles[2] = {(uint64_t)kExpandTile, (uint64_t)kSortTile};
     Tiling* tls[2] = {&tl_exp, &tl};
+    TileJob2 jobs[2];
     for (int i = 0; i < 2; ++i) {
       const size_t o1 = 0, o2 = align256((size_t)caps[i] * 8), o3 = o2 + align256((size_t)caps[i] * 8);
       const size_t o4 = o3 + align256((size_t)caps[i] * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
       const size_t o6 = o5 + 256;
       QCHK(ensure(c, c->dtile[i], o6 + 256));
       uint8_t* d = (uint8_t*)c->dtile[i].p;
-      HIPCHK(c, launch_make_tiles((const uint64_t*)c->img_seg.p, S, tiles[i], caps[i], (uint64_t*)(d + o1),
-                                  (uint64_t*)(d + o2), (uint32_t*)(d + o3), (uint32_t*)(d + o4), (uint32_t*)(d + o5),
-                                  (uint32_t*)(d + o6), T_img, (uint32_t*)c->err.p, c->stream), "tiles");
+      jobs[i] = TileJob2{tiles[i], caps[i], 0, (uint64_t*)(d + o1), (uint64_t*)(d + o2), (uint32_t*)(d + o3),
+                         (uint32_t*)(d + o4), (uint32_t*)(d + o5), (uint32_t*)(d + o6)};
       *tls[i] = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
                        (const uint32_t*)(d + o4), caps[i], S, (const uint32_t*)(d + o5), (const uint32_t*)(d + o6)};
     }
+    HIPCHK(c, launch_make_tiles2((const uint64_t*)c->off.p, seg_in, S, (uint64_t*)c->img_seg.p, jobs[0], jobs[1],
+                                 T_img, (uint32_t*)c->err.p, c->stream), "tiles");
   } else {
+    HIPCHK(c, launch_gather_u64((const uint64_t*)c->off.p, seg_in, (uint64_t*)c->img_seg.p, S + 1, c->stream,
+                                &c->prof), "gather");
     QCHK(readback(c, c->img_seg.p, S + 1, &e));
     if (e) return fail(c, (e & kErrFanout) ? QIMAX_ETOOLARGE : QIMAX_EDEVICE, "count pass:" + err_text(e));
     so_img.assign(c->pinned, c->pinned + S + 1);
@@ -716,10 +719,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
                           any_tables, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream, &c->prof), "expand");
   // ---- segment-local LSD radix sort of the images
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
-  QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
   int cur = 0;
-  const uint32_t key_bits = 2u * max_n;
-  if (c->classic_sort) {
+  if (!sweep) {
+    QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
     QCHK(ensure(c, c->hist, hsize * 8));
     QCHK(ensure(c, c->hist_off, (hsize + 1) * 8));
     for (uint32_t shift = 0; shift < key_bits; shift += kRadixBits) {
@@ -729,11 +731,6 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       cur ^= 1;
     }
   } else {
-    const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
-    const uint64_t nh = (uint64_t)S * n_pass * kRadix;
-    QCHK(ensure(c, c->ghist, nh * 4));
-    QCHK(ensure(c, c->sbase, nh * 8));
-    QCHK(ensure(c, c->tile_ctr, 256 * 4));
     // a grown buffer may come back at the same address with stale contents: detect the
     // reallocation by its size, never by its pointer
     const size_t old_bytes = c->sstatus.bytes;
@@ -747,9 +744,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     void* const ww[2] = {c->iw[0].p, c->iw[1].p};
     if (!c->xcd_ranges) tl.xrange = nullptr;
     HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, tl, (const uint64_t*)c->img_seg.p,
-                                (uint32_t*)c->ghist.p, (uint64_t*)c->sbase.p, (uint64_t*)c->sstatus.p,
-                                (uint32_t*)c->tile_ctr.p, &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof),
-           "sort");
+                                (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr, &c->epoch, (uint32_t*)c->err.p,
+                                &cur, c->stream, &c->prof), "sort");
   }
   // ---- segmented reduce + prune + compaction into the pass output slot
   QCHK(ensure(c, c->pk[slot], std::max<uint64_t>(T_img, 1) * eb));
@@ -757,27 +753,29 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->pseg[slot], (S + 1) * 8));
   QCHK(ensure(c, c->blk_cnt, (size_t)(tl.n_blocks + 1) * 4));
   QCHK(ensure(c, c->blk_off, (size_t)(tl.n_blocks + 1) * 8));
+  QCHK(ensure(c, c->result, (size_t)(2 * S + 3) * 8));
   uint64_t* mstatus = nullptr;
-  if (!c->classic_sort) {
-    const size_t old_m = c->mstatus.bytes;
-    QCHK(ensure(c, c->mstatus, (size_t)(tl.n_blocks + 1) * 8));
-    if (c->mstatus.bytes != old_m || c->mepoch + 1 >= 0xFFFFull) {
-      HIPCHK(c, launch_fill_u64((uint64_t*)c->mstatus.p, c->mstatus.bytes / 8, 0ull, c->stream), "clear status");
-      c->mepoch = 0;
-    }
+  MergeFin fin{(const uint64_t*)c->img_seg.p, (uint64_t*)c->result.p};
+  if (sweep) {
+    QCHK(status_words(tl.n_blocks));
     c->mepoch += 1;
     mstatus = (uint64_t*)c->mstatus.p;
   }
   HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, pas, sent, c->pk[slot].p,
                          c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
-                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, (uint32_t*)c->tile_ctr.p + 255,
-                         c->mepoch, (uint32_t*)c->err.p, c->stream, &c->prof), "merge");
-  QCHK(bound_path ? readback2(c, c->pseg[slot].p, c->img_seg.p, S + 1, &e) : readback(c, c->pseg[slot].p, S + 1, &e));
+                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, ctr + kCtrMerge, c->mepoch,
+                         (uint32_t*)c->err.p, sweep ? &fin : nullptr, c->stream, &c->prof), "merge");
+  // ---- one readback: output offsets, image offsets, error word
+  if (sweep) {
+    QCHK(readback(c, c->result.p, 2 * (size_t)S + 3, &e, /*err_packed=*/true));
+  } else {
+    QCHK(readback(c, c->pseg[slot].p, S + 1, &e));
+  }
   if (e) {
     char buf[256];
     std::snprintf(buf, sizeof(buf), " [segments %u, T_in %llu, T_img %llu, tiles %u, key bits %u, entries %zu]", S,
                   (unsigned long long)T_in, (unsigned long long)T_img, tl.n_blocks, key_bits, E);
-    return fail(c, QIMAX_EDEVICE, "expand/sort/merge pass:" + err_text(e) + buf);
+    return fail(c, (e & kErrFanout) ? QIMAX_ETOOLARGE : QIMAX_EDEVICE, "propagation round:" + err_text(e) + buf);
   }
   so_out.assign(c->pinned, c->pinned + S + 1);
   const uint64_t T_out = so_out[S];
@@ -788,7 +786,6 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     T_img = so_img[S];
     if (c->prof.on) {
       const double d = (double)(cap - T_img);
-      const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
       c->prof.bytes[kKExpand] -= (double)(eb + wbt) * d;
       c->prof.bytes[kKSortHist] -= (double)eb * d;
       c->prof.bytes[kKSortScatter] -= 2.0 * (double)(eb + wbt) * n_pass * d;
@@ -1533,7 +1530,7 @@ void qimax_destroy(qimax_ctx* c) {
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
                     &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
-                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1]};
+                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->result};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 2; ++i)

@@ -118,7 +118,6 @@ enum : uint32_t {
   kErrMerge = 64u,     // set with kErrIndex by the merge kernel
 };
 
-
 // ------------------------------------------------------------------------ kernel timing
 // Optional per-kernel timing with HIP events recorded on the launch stream, plus the
 // algorithmic bytes each launch must move (what the roofline is measured against).
@@ -153,9 +152,12 @@ void prof_destroy(Prof* p);
 hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, uint32_t n,
                        hipStream_t s, Prof* prof = nullptr);
 
-hipError_t launch_count(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
-                        const uint32_t* seg_entry, uint32_t* cnt, uint32_t* err, hipStream_t s,
-                        Prof* prof = nullptr);
+// Fan-out count fused with its scan (single sweep with decoupled look-back over the tiles of
+// tl, claimed through *ctr): off[i] = first image of input term i, off[T] = image count.
+// status: tl.n_blocks words whose epoch field differs from `epoch`.
+hipError_t launch_count_scan(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
+                             const uint32_t* seg_entry, uint64_t* off, uint64_t* status, uint32_t* ctr, uint64_t epoch,
+                             uint32_t* err, hipStream_t s, Prof* prof = nullptr);
 
 // out[i] = exclusive prefix sum of in[0..i-1] for i in [0, N]; out has N+1 entries.
 // tmp must hold scan_tmp_words(N) uint64 words.
@@ -186,12 +188,13 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
 // The whole segment-local LSD sort in single-sweep form: one upfront histogram of every
 // digit position, then one decoupled-look-back scatter per digit. keys/w are ping-pong
 // pairs with the input in slot 0; *cur receives the slot holding the sorted result.
-// ghist: n_segs*n_pass*256 u32; base: n_segs*n_pass*256 u64; status: n_blocks*256 u64
-// (zeroed when allocated); tile_ctr: n_pass u32; *epoch is advanced per digit pass.
+// ghist: n_segs*n_pass*256 u32, zero on entry; seg_off: the segment offsets (n_segs + 1);
+// status: n_blocks*256 u64 (zeroed when allocated); tile_ctr: n_pass*kXcds u32, zero on
+// entry; *epoch is advanced per digit pass.
 hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[2], uint64_t T, uint32_t key_bits,
-                             const Tiling& tl, const uint64_t* seg_off, uint32_t* ghist, uint64_t* base,
-                             uint64_t* status, uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err, int* cur,
-                             hipStream_t s, Prof* prof = nullptr);
+                             const Tiling& tl, const uint64_t* seg_off, uint32_t* ghist, uint64_t* status,
+                             uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err, int* cur, hipStream_t s,
+                             Prof* prof = nullptr);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 
 // Segmented sum of equal adjacent keys; keeps sums with |w| > thr (thr < 0 keeps
@@ -199,11 +202,17 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 // blk_cnt / blk_off must hold n_blocks (+1) words.
 // status != nullptr: single-sweep merge (status: n_blocks u64 words with a fresh epoch,
 // tile_ctr: one u32); otherwise count, scan, write.
+// fin: seg_off_out and the packed readback area are written by one small kernel after the
+// merge; in a single sweep *tile_ctr must then be zero on entry.
+struct MergeFin {
+  const uint64_t* img_seg;  // image offsets of the segments (S + 1)
+  uint64_t* result;         // [0..S] output offsets, [S+1..2S+1] img_seg, [2S+2] error word
+};
 hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, uint64_t T,
                         const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out, void* w_out,
                         uint64_t out_cap, uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
-                        uint64_t* status, uint32_t* tile_ctr, uint64_t epoch, uint32_t* err, hipStream_t s,
-                        Prof* prof = nullptr);
+                        uint64_t* status, uint32_t* tile_ctr, uint64_t epoch, uint32_t* err, const MergeFin* fin,
+                        hipStream_t s, Prof* prof = nullptr);
 
 // Compile chains of permutation ops into ChainTables, one job per chain (jobs in device memory).
 hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hipStream_t s, Prof* prof = nullptr);
@@ -212,13 +221,29 @@ hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hi
 hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t* nq, const uint64_t* dst,
                             uint32_t n_circ, hipStream_t s);
 
-// Segment-aligned tiles of at most `tile` elements built on the device from device segment
-// offsets so[0..S]; cap tiles are written (the ones past the actual count are empty), the
-// actual count goes to *n_dev and the per-XCD ranges of whole segments to xrange[0..8]. Tile ranges are clamped to [0, limit) (elements of the
-// buffers they index); a tile count above cap or so[S] above limit sets an error bit.
-hipError_t launch_make_tiles(const uint64_t* so, uint32_t S, uint64_t tile, uint32_t cap, uint64_t* blk_begin,
-                             uint64_t* blk_end, uint32_t* blk_seg, uint32_t* seg_blk, uint32_t* n_dev, uint32_t* xrange,
-                             uint64_t limit, uint32_t* err, hipStream_t s);
+// One segment-aligned tiling built on the device: at most `tile` elements per tile, cap tiles
+// written (the ones past the actual count are empty), the actual count in *n_dev and the
+// per-XCD ranges of whole segments in xrange[0..8].
+struct TileJob2 {
+  uint64_t tile;
+  uint32_t cap, pad;
+  uint64_t* blk_begin;
+  uint64_t* blk_end;
+  uint32_t* blk_seg;
+  uint32_t* seg_blk;  // S + 1 entries
+  uint32_t* n_dev;
+  uint32_t* xrange;   // kXcds + 1 entries
+};
+// The two image tilings (expand, sort/merge) of a round from the image offsets of the
+// segments, so[s] = off[seg_in[s]], which also go to img_seg[0..S]. Tile ranges are clamped
+// to [0, limit) (elements of the buffers they index); a tile count above cap or so[S] above
+// limit sets an error bit.
+hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint32_t S, uint64_t* img_seg,
+                              const TileJob2& j0, const TileJob2& j1, uint64_t limit, uint32_t* err, hipStream_t s);
+
+// Zero the error word, n_ctr tile counters and nh digit-histogram words (one launch).
+hipError_t launch_round_prep(uint32_t* err, uint32_t* ctr, uint32_t n_ctr, uint32_t* ghist, uint64_t nh,
+                             hipStream_t s);
 
 // Plain copy of n words (calibration of hardware traffic counters).
 hipError_t launch_copy_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s);
