@@ -264,11 +264,35 @@ __device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t* a, uint64_t 
   return lo;
 }
 
+// upper_bound by one wave: first index i in [lo, hi) with a[i] > x (hi if none), a sorted
+// non-decreasing. Each round probes 64 evenly spaced elements at once and keeps the interval
+// between the last probe <= x and the first probe > x, so n elements take ceil(log64 n)
+// rounds of one parallel load instead of log2 n dependent loads.
+__device__ __forceinline__ uint64_t wave_upper_bound(const uint64_t* __restrict__ a, uint64_t lo, uint64_t hi,
+                                                     uint64_t x) {
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    const uint64_t n = hi - lo;
+    if (n == 0) return lo;
+    const uint64_t step = n <= 64 ? 1 : (n + 63) / 64;
+    const uint64_t i = lo + (uint64_t)lane * step;
+    const bool gt = i < hi ? a[i] > x : true;
+    const uint64_t m = __ballot(gt);
+    const int first = m ? __ffsll((long long)m) - 1 : 64;
+    if (step == 1) return first == 64 ? hi : lo + (uint64_t)first;
+    if (first == 0) return lo;
+    const uint64_t nlo = lo + (uint64_t)(first - 1) * step + 1;
+    const uint64_t nhi = first == 64 ? hi : min(lo + (uint64_t)first * step, hi);
+    lo = nlo;
+    hi = nhi;
+  }
+}
+
 template <typename K, int WP>
 __global__ void __launch_bounds__(kExpandBlock)
 k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__ w, uint64_t T_in,
          const uint64_t* __restrict__ off, uint64_t T_img, Tiling tl, const PassArgs* __restrict__ pas,
-         const uint32_t* __restrict__ seg_entry, K* __restrict__ keys_out,
+         const uint32_t* __restrict__ seg_entry, const uint64_t* __restrict__ seg_in, K* __restrict__ keys_out,
          typename WTraits<WP>::W* __restrict__ w_out, uint32_t* err) {
   using W = typename WTraits<WP>::W;
   constexpr int kWin = kExpandTile + 1;
@@ -276,7 +300,8 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   // dynamic LDS: offset window, then the chain tables that this pass uses
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t blk = blockIdx.x;
-  const PassArgs pa = pas[seg_entry[tl.blk_seg[blk]]];
+  const uint32_t seg = tl.blk_seg[blk];
+  const PassArgs pa = pas[seg_entry[seg]];
   uint64_t* win = (uint64_t*)lds;
   uint8_t* cur = lds + kWin * 8;
   K* tak = (K*)cur;
@@ -293,11 +318,13 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   if (g0 >= g1) return;
   if (pa.useA) stage_table(pa.tA, tak, tan_);
   if (pa.useB) stage_table(pa.tB, tbk, tbn);
-  if (threadIdx.x == 0) {
-    const uint64_t plo = upper_bound_u64(off, 0, T_in + 1, g0) - 1;
-    const uint64_t phi = upper_bound_u64(off, plo, T_in + 1, g1 - 1) - 1;
-    bounds[0] = plo;
-    bounds[1] = phi;
+  // parents of the first and last image: wave 0 and wave 1 search the segment's parents
+  // (off is the global image offset of every parent; the segment's are seg_in[seg] ..)
+  if (threadIdx.x < 128) {
+    const uint64_t lo = seg_in[seg], hi = seg_in[seg + 1] + 1;
+    const uint64_t x = threadIdx.x < 64 ? g0 : g1 - 1;
+    const uint64_t p = wave_upper_bound(off, lo, hi, x) - 1;
+    if ((threadIdx.x & 63) == 0) bounds[threadIdx.x >> 6] = p;
   }
   __syncthreads();
   const uint64_t plo = bounds[0], phi = bounds[1];
@@ -1246,7 +1273,8 @@ hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint6
 
 hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const uint64_t* off,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
-                         bool any_tables, void* keys_out, void* w_out, uint32_t* err, hipStream_t s, Prof* prof) {
+                         const uint64_t* seg_in, bool any_tables, void* keys_out, void* w_out, uint32_t* err,
+                         hipStream_t s, Prof* prof) {
   if (T_img == 0 || tl.n_blocks == 0) return hipSuccess;
   hipEvent_t ev = prof_begin(prof, s);
   QIMAX_DISPATCH_K(KC, {
@@ -1254,10 +1282,10 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64
     const size_t lds = (size_t)(kExpandTile + 1) * 8 + (any_tables ? 2 * tab : 0) + 64;
     if (WP == 64)
       k_expand<K, 64><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, (const double*)w, T_in, off, T_img, tl,
-                                                              pas, seg_entry, (K*)keys_out, (double*)w_out, err);
+                                                              pas, seg_entry, seg_in, (K*)keys_out, (double*)w_out, err);
     else
       k_expand<K, 32><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, (const float*)w, T_in, off, T_img, tl,
-                                                              pas, seg_entry, (K*)keys_out, (float*)w_out, err);
+                                                              pas, seg_entry, seg_in, (K*)keys_out, (float*)w_out, err);
   });
   const double per = (4 << KC) + (WP == 64 ? 8 : 4);
   prof_end(prof, s, ev, kKExpand, per * (double)(T_in + T_img) + 8.0 * (double)T_in);

@@ -716,7 +716,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->ik[1], std::max<uint64_t>(T_img, 1) * eb));
   QCHK(ensure(c, c->iw[1], std::max<uint64_t>(T_img, 1) * wbt));
   HIPCHK(c, launch_expand(c->KC, c->WP, k_in, w_in, T_in, (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent,
-                          any_tables, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream, &c->prof), "expand");
+                          seg_in, any_tables, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream, &c->prof),
+         "expand");
   // ---- segment-local LSD radix sort of the images
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
   int cur = 0;
