@@ -297,13 +297,15 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   using W = typename WTraits<WP>::W;
   constexpr int kWin = kExpandTile + 1;
   constexpr int kTab = (int)sizeof(K) * 256;
-  // dynamic LDS: offset window, then the chain tables that this pass uses
+  // dynamic LDS: offset window, image -> parent map, the chain tables that this pass uses,
+  // then its expanding operators' descriptors
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t blk = blockIdx.x;
   const uint32_t seg = tl.blk_seg[blk];
   const PassArgs pa = pas[seg_entry[seg]];
   uint64_t* win = (uint64_t*)lds;
-  uint8_t* cur = lds + kWin * 8;
+  uint16_t* pmap = (uint16_t*)(lds + kWin * 8);
+  uint8_t* cur = lds + kWin * 8 + kExpandTile * 2;
   K* tak = (K*)cur;
   cur += pa.useA ? kTab * sizeof(K) : 0;
   uint8_t* tan_ = cur;
@@ -311,6 +313,8 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   K* tbk = (K*)cur;
   cur += pa.useB ? kTab * sizeof(K) : 0;
   uint8_t* tbn = cur;
+  cur += pa.useB ? kTab : 0;
+  uint64_t* edesc = (uint64_t*)cur;
   __shared__ uint64_t bounds[2];
   // this block's images: one segment-aligned tile of at most kExpandTile
   const uint64_t g0 = tl.blk_begin[blk];
@@ -318,6 +322,12 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   if (g0 >= g1) return;
   if (pa.useA) stage_table(pa.tA, tak, tan_);
   if (pa.useB) stage_table(pa.tB, tbk, tbn);
+  // the expanding operators' descriptors, read many times per image, go to LDS
+  const uint32_t e1w = pa.nE1 * (uint32_t)(sizeof(Exp1Desc) / 8), e2w = pa.nE2 * (uint32_t)(sizeof(Exp2Desc) / 8);
+  for (uint32_t i = threadIdx.x; i < e1w; i += kExpandBlock) edesc[i] = ((const uint64_t*)pa.E1)[i];
+  for (uint32_t i = threadIdx.x; i < e2w; i += kExpandBlock) edesc[e1w + i] = ((const uint64_t*)pa.E2)[i];
+  const Exp1Desc* E1s = (const Exp1Desc*)edesc;
+  const Exp2Desc* E2s = (const Exp2Desc*)(edesc + e1w);
   // parents of the first and last image: wave 0 and wave 1 search the segment's parents
   // (off is the global image offset of every parent; the segment's are seg_in[seg] ..)
   if (threadIdx.x < 128) {
@@ -332,6 +342,12 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   const bool in_lds = nwin <= (uint64_t)kWin;
   if (in_lds) {
     for (uint64_t k = threadIdx.x; k < nwin; k += kExpandBlock) win[k] = off[plo + k];
+    __syncthreads();
+    // image -> parent map of the tile: window parent j covers images [win[j], win[j+1])
+    for (uint32_t j = threadIdx.x; j + 1 < (uint32_t)nwin; j += kExpandBlock) {
+      const uint64_t a = max(win[j], g0), b = min(win[j + 1], g1);
+      for (uint64_t g = a; g < b; ++g) pmap[g - g0] = (uint16_t)j;
+    }
   }
   __syncthreads();
   // parents of every item first, then every parent load in flight, then the arithmetic
@@ -342,13 +358,9 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
     const uint64_t g = min(g0 + (uint64_t)it * kExpandBlock + threadIdx.x, g1 - 1);
     uint64_t p, start;
     if (in_lds) {
-      uint32_t lo = 0, hi = (uint32_t)nwin;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (win[mid] > g) hi = mid; else lo = mid + 1;
-      }
-      p = plo + lo - 1;
-      start = win[lo - 1];
+      const uint32_t j = pmap[g - g0];
+      p = plo + j;
+      start = win[j];
     } else {
       p = upper_bound_u64(off, plo, phi + 2, g) - 1;
       start = off[p];
@@ -379,7 +391,7 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
     else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
     uint32_t r = rk[it];
     for (uint32_t e = 0; e < pa.nE1; ++e) {
-      const Exp1Desc& E = pa.E1[e];
+      const Exp1Desc& E = E1s[e];
       const uint32_t d = get_d(key, E.pos);
       const uint32_t c = E.cnt[d];
       if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
@@ -390,7 +402,7 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
       if constexpr (WP == 64) wv *= E.val[d][k]; else wv *= E.valf[d][k];
     }
     for (uint32_t e = 0; e < pa.nE2; ++e) {
-      const Exp2Desc& E = pa.E2[e];
+      const Exp2Desc& E = E2s[e];
       const uint32_t in = local2(key, E.pa, E.pb);
       const uint32_t c = E.cnt[in];
       if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
@@ -1273,13 +1285,14 @@ hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint6
 
 hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const uint64_t* off,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
-                         const uint64_t* seg_in, bool any_tables, void* keys_out, void* w_out, uint32_t* err,
-                         hipStream_t s, Prof* prof) {
+                         const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
+                         uint32_t* err, hipStream_t s, Prof* prof) {
   if (T_img == 0 || tl.n_blocks == 0) return hipSuccess;
   hipEvent_t ev = prof_begin(prof, s);
   QIMAX_DISPATCH_K(KC, {
     const size_t tab = sizeof(K) * 256 * (sizeof(K) + 1);
-    const size_t lds = (size_t)(kExpandTile + 1) * 8 + (any_tables ? 2 * tab : 0) + 64;
+    const size_t lds = (size_t)(kExpandTile + 1) * 8 + (size_t)kExpandTile * 2 + (any_tables ? 2 * tab : 0) +
+                       e_bytes + 64;
     if (WP == 64)
       k_expand<K, 64><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, (const double*)w, T_in, off, T_img, tl,
                                                               pas, seg_entry, seg_in, (K*)keys_out, (double*)w_out, err);

@@ -550,6 +550,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   struct Lay { size_t a, b, x1, x2; uint32_t nA, nB, nE1, nE2; bool useA, useB; };
   std::vector<Lay> lay(E);
   size_t n_jobs = 0;
+  size_t e_bytes = 0;  // largest expanding-operator descriptor set of an entry (staged in LDS)
   bool any_tables = false;
   uint32_t max_n = 1;
   auto tableable = [c](const std::vector<const HostOp*>& v) {
@@ -573,6 +574,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       if (op->arity == 1) { e1.push_back(make_exp1(entries[e].n, *op)); ++L.nE1; }
       else { e2.push_back(make_exp2(entries[e].n, *op)); ++L.nE2; }
     }
+    e_bytes = std::max(e_bytes, L.nE1 * sizeof(Exp1Desc) + L.nE2 * sizeof(Exp2Desc));
     L.useA = tableable(p->A);
     L.useB = tableable(p->B);
     n_jobs += L.useA + L.useB;
@@ -716,8 +718,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->ik[1], std::max<uint64_t>(T_img, 1) * eb));
   QCHK(ensure(c, c->iw[1], std::max<uint64_t>(T_img, 1) * wbt));
   HIPCHK(c, launch_expand(c->KC, c->WP, k_in, w_in, T_in, (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent,
-                          seg_in, any_tables, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream, &c->prof),
-         "expand");
+                          seg_in, any_tables, e_bytes, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream,
+                          &c->prof), "expand");
   // ---- segment-local LSD radix sort of the images
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
   int cur = 0;

@@ -175,8 +175,8 @@ hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint6
 // entry uses chain tables (sizes the dynamic LDS).
 hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const uint64_t* off,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
-                         const uint64_t* seg_in, bool any_tables, void* keys_out, void* w_out, uint32_t* err,
-                         hipStream_t s, Prof* prof = nullptr);
+                         const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
+                         uint32_t* err, hipStream_t s, Prof* prof = nullptr);
 
 // One LSD radix pass over digit `shift` of every segment, stable, segment-local.
 // hist must hold kRadix * n_blocks uint64 words; tmp scan_tmp_words(kRadix * n_blocks).
