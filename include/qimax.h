@@ -163,6 +163,10 @@ typedef struct {
 } qimax_kernel_time;
 
 qimax_status qimax_profile(qimax_ctx* ctx, int enable);
+/* Restrict the timing to one kernel kind (its name as qimax_profile_read reports it, e.g.
+ * "sort_scatter"); NULL or "" times every kind again. Fewer timed kinds, fewer event records
+ * on the host. QIMAX_EINVAL for an unknown name. */
+qimax_status qimax_profile_only(qimax_ctx* ctx, const char* kernel);
 qimax_status qimax_profile_read(qimax_ctx* ctx, qimax_kernel_time* out, size_t cap, size_t* n);
 
 /* ------------------------------------------------------------------ batches of circuits

@@ -1156,8 +1156,8 @@ const char* kernel_kind_name(int k) {
   return (k >= 0 && k < kKNum) ? names[k] : "?";
 }
 
-hipEvent_t prof_begin(Prof* p, hipStream_t s) {
-  if (!p || !p->on) return nullptr;
+hipEvent_t prof_begin(Prof* p, hipStream_t s, int kind) {
+  if (!p || !p->on || !((p->mask >> kind) & 1u)) return nullptr;
   hipEvent_t e = nullptr;
   if (!p->pool.empty()) {
     e = p->pool.back();
@@ -1169,7 +1169,7 @@ hipEvent_t prof_begin(Prof* p, hipStream_t s) {
   return e;
 }
 
-void prof_end(Prof* p, hipStream_t s, hipEvent_t a, int kind, double bytes) {
+void prof_end(Prof* p, hipStream_t s, hipEvent_t a, int kind, double bytes, uint32_t count) {
   if (!p || !p->on || !a) return;
   hipEvent_t b = nullptr;
   if (!p->pool.empty()) {
@@ -1179,7 +1179,7 @@ void prof_end(Prof* p, hipStream_t s, hipEvent_t a, int kind, double bytes) {
     return;
   }
   if (hipEventRecord(b, s) != hipSuccess) return;
-  p->recs.push_back({kind, a, b, bytes});
+  p->recs.push_back({kind, a, b, bytes, count});
 }
 
 void prof_resolve(Prof* p) {
@@ -1187,7 +1187,7 @@ void prof_resolve(Prof* p) {
   for (auto& r : p->recs) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-      p->launches[r.kind] += 1;
+      p->launches[r.kind] += r.count;
       p->ms[r.kind] += ms;
       p->bytes[r.kind] += r.bytes;
     }
@@ -1226,7 +1226,7 @@ void prof_destroy(Prof* p) {
 
 hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, uint32_t n, hipStream_t s,
                        Prof* prof) {
-  hipEvent_t ev = prof_begin(prof, s);
+  hipEvent_t ev = prof_begin(prof, s, kKInit);
   QIMAX_DISPATCH_K(KC, {
     if (WP == 64) k_init<K, double><<<grid_for(n, 64), 64, 0, s>>>((K*)keys, (double*)w, seg_off, n);
     else k_init<K, float><<<grid_for(n, 64), 64, 0, s>>>((K*)keys, (float*)w, seg_off, n);
@@ -1242,7 +1242,7 @@ hipError_t launch_count_scan(int KC, const void* keys, uint64_t T, const Tiling&
     k_zero_one<<<1, 1, 0, s>>>(off);
     return hipGetLastError();
   }
-  hipEvent_t ev = prof_begin(prof, s);
+  hipEvent_t ev = prof_begin(prof, s, kKCount);
   QIMAX_DISPATCH_K(KC, {
     k_count_scan<K><<<tl.n_blocks, 256, 0, s>>>((const K*)keys, tl, pas, seg_entry, off, T, status, ctr, epoch, err);
   });
@@ -1254,7 +1254,7 @@ size_t scan_tmp_words(uint64_t N) { return (size_t)((N + kScanTile - 1) / kScanT
 
 template <typename TI>
 static hipError_t scan_impl(const TI* in, uint64_t* out, uint64_t N, uint64_t* tmp, hipStream_t s, Prof* prof) {
-  hipEvent_t ev = prof_begin(prof, s);
+  hipEvent_t ev = prof_begin(prof, s, kKScan);
   if (N == 0) {
     k_zero_one<<<1, 1, 0, s>>>(out);
   } else {
@@ -1288,7 +1288,7 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64
                          const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
                          uint32_t* err, hipStream_t s, Prof* prof) {
   if (T_img == 0 || tl.n_blocks == 0) return hipSuccess;
-  hipEvent_t ev = prof_begin(prof, s);
+  hipEvent_t ev = prof_begin(prof, s, kKExpand);
   QIMAX_DISPATCH_K(KC, {
     const size_t tab = sizeof(K) * 256 * (sizeof(K) + 1);
     const size_t lds = (size_t)(kExpandTile + 1) * 8 + (size_t)kExpandTile * 2 + (any_tables ? 2 * tab : 0) +
@@ -1312,12 +1312,12 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
   const uint64_t hsize = (uint64_t)kRadix * tl.n_blocks;
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   QIMAX_DISPATCH_K(KC, {
-    hipEvent_t ev = prof_begin(prof, s);
+    hipEvent_t ev = prof_begin(prof, s, kKSortHist);
     k_sort_hist<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys_in, shift, tl, hist, hsize, err);
     prof_end(prof, s, ev, kKSortHist, kb * (double)T + 8.0 * (double)hsize);
     hipError_t e = scan_impl<uint64_t>(hist, hist_off, hsize, tmp, s, prof);
     if (e != hipSuccess) return e;
-    ev = prof_begin(prof, s);
+    ev = prof_begin(prof, s, kKSortScatter);
     if (WP == 64)
       k_sort_scatter<K, double, false><<<tl.n_blocks, kSortBlock, 0, s>>>(
           (const K*)keys_in, (const double*)w_in, (K*)keys_out, (double*)w_out, T, shift, tl, hist_off, nullptr, 0,
@@ -1340,12 +1340,14 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
   const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   QIMAX_DISPATCH_K(KC, {
-    hipEvent_t ev = prof_begin(prof, s);
+    hipEvent_t ev = prof_begin(prof, s, kKSortHist);
     k_sort_upsweep<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys[0], tl, n_pass, ghist);
     prof_end(prof, s, ev, kKSortHist, kb * (double)T);
+    // the digit passes run back to back: one pair of events times them all (fewer event
+    // records on the host), and the average launch is their time over n_pass
+    ev = prof_begin(prof, s, kKSortScatter);
     for (uint32_t p = 0; p < n_pass; ++p) {
       *epoch += 1;  // the caller keeps *epoch + n_pass below 2^16 (clearing status on wrap)
-      ev = prof_begin(prof, s);
       const int c = *cur;
       if (WP == 64)
         k_sort_scatter<K, double, true><<<tl.n_blocks, kSortBlock, 0, s>>>(
@@ -1357,9 +1359,9 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
             (const K*)keys[c], (const float*)w[c], (K*)keys[c ^ 1], (float*)w[c ^ 1], T, 8u * p, tl, nullptr,
             ghist + (uint64_t)p * kRadix, n_pass * kRadix, seg_off, status, tile_ctr + (uint64_t)p * kXcds, *epoch,
             err);
-      prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T);
       *cur ^= 1;
     }
+    prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T * n_pass, n_pass);
   });
   return hipGetLastError();
 }
@@ -1390,7 +1392,7 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
   QIMAX_DISPATCH_K(KC, {
     if (status) {  // single sweep
       if (!fin) k_fill_u32<<<1, 64, 0, s>>>(tile_ctr, 1, 0u);  // with fin: zeroed by the caller
-      hipEvent_t ev = prof_begin(prof, s);
+      hipEvent_t ev = prof_begin(prof, s, kKMergeWrite);
       if (WP == 64)
         k_merge<K, double, 2><<<tl.n_blocks, kSortBlock, 0, s>>>(
             (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, nullptr, blk_off, (K*)keys_out,
@@ -1402,7 +1404,7 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
       // the written terms are added by the caller once their count is back on the host
       prof_end(prof, s, ev, kKMergeWrite, (kb + wb) * (double)T);
     } else {
-      hipEvent_t ev = prof_begin(prof, s);
+      hipEvent_t ev = prof_begin(prof, s, kKMergeCount);
       if (WP == 64)
         k_merge<K, double, 0><<<tl.n_blocks, kSortBlock, 0, s>>>(
             (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, nullptr, nullptr, nullptr, 0,
@@ -1414,7 +1416,7 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
       prof_end(prof, s, ev, kKMergeCount, (kb + wb) * (double)T);
       hipError_t e = scan_impl<uint32_t>(blk_cnt, blk_off, tl.n_blocks, tmp, s, prof);
       if (e != hipSuccess) return e;
-      ev = prof_begin(prof, s);
+      ev = prof_begin(prof, s, kKMergeWrite);
       if (WP == 64)
         k_merge<K, double, 1><<<tl.n_blocks, kSortBlock, 0, s>>>(
             (const K*)keys_in, (const double*)w_in, tl, pas, seg_entry, fp64_acc, blk_cnt, blk_off, (K*)keys_out,
@@ -1568,7 +1570,7 @@ hipError_t launch_compose_ptm(const uint8_t* gate, const double* theta, const ui
                               const uint32_t* chain_off, uint32_t n_chains, double* ptm_out, hipStream_t s,
                               Prof* prof) {
   if (n_chains == 0) return hipSuccess;
-  hipEvent_t ev = prof_begin(prof, s);
+  hipEvent_t ev = prof_begin(prof, s, kKCompose);
   k_compose_ptm<<<grid_for(n_chains, 64), 64, 0, s>>>(gate, theta, idx, chain_off, n_chains, ptm_out);
   prof_end(prof, s, ev, kKCompose, 0.0);
   return hipGetLastError();

@@ -47,6 +47,7 @@ struct Pass {
   uint64_t emask = 0, bmask = 0;
   int egroup = -1;
   double fanout_bound = 1.0;
+  ChainTable pre[2] = {};  // A / B chain tables compiled ahead of the rounds (tab_key set)
 };
 
 // The paper's CX look-up tables (Sec. III-C-2), indexed [p_c][p_t] with I=0, X=1, Y=2, Z=3:
@@ -215,6 +216,7 @@ struct qimax_ctx {
   DevBuf ik[2], iw[2];
   DevBuf cnt, off, scan_tmp, hist, hist_off, blk_begin, blk_end, blk_seg, seg_blk, blk_cnt, blk_off, img_seg;
   DevBuf desc, desc2, err, f64tmp;
+  DevBuf ptab;  // chain tables of a whole call, compiled in one launch
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
   DevBuf mstatus;  // single-sweep count and merge state (one word per tile)
@@ -577,7 +579,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     e_bytes = std::max(e_bytes, L.nE1 * sizeof(Exp1Desc) + L.nE2 * sizeof(Exp2Desc));
     L.useA = tableable(p->A);
     L.useB = tableable(p->B);
-    n_jobs += L.useA + L.useB;
+    n_jobs += (L.useA && !p->pre[0].tab_key) + (L.useB && !p->pre[1].tab_key);
     any_tables |= L.useA || L.useB;
   }
   HostTiling t_in;
@@ -622,8 +624,15 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       t = ChainTable{tk, tn};
       ++job;
     };
-    if (L.useA) { pa.useA = 1; table_for(pa.A, pa.nA, pa.tA); }
-    if (L.useB) { pa.useB = 1; table_for(pa.B, pa.nB, pa.tB); }
+    const Pass* pp = entries[e].pass;
+    if (L.useA) {
+      pa.useA = 1;
+      if (pp->pre[0].tab_key) pa.tA = pp->pre[0]; else table_for(pa.A, pa.nA, pa.tA);
+    }
+    if (L.useB) {
+      pa.useB = 1;
+      if (pp->pre[1].tab_key) pa.tB = pp->pre[1]; else table_for(pa.B, pa.nB, pa.tB);
+    }
     pas_h[e] = pa;
   }
   std::memcpy(hs + oS, seg_entry.data(), S * 4);
@@ -789,13 +798,16 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     T_img = so_img[S];
     if (c->prof.on) {
       const double d = (double)(cap - T_img);
-      c->prof.bytes[kKExpand] -= (double)(eb + wbt) * d;
-      c->prof.bytes[kKSortHist] -= (double)eb * d;
-      c->prof.bytes[kKSortScatter] -= 2.0 * (double)(eb + wbt) * n_pass * d;
-      c->prof.bytes[kKMergeWrite] -= (double)(eb + wbt) * d;
+      auto fix = [&](int kind, double bytes) {
+        if ((c->prof.mask >> kind) & 1u) c->prof.bytes[kind] -= bytes;
+      };
+      fix(kKExpand, (double)(eb + wbt) * d);
+      fix(kKSortHist, (double)eb * d);
+      fix(kKSortScatter, 2.0 * (double)(eb + wbt) * n_pass * d);
+      fix(kKMergeWrite, (double)(eb + wbt) * d);
     }
   }
-  if (c->prof.on) c->prof.bytes[kKMergeWrite] += (double)T_out * (double)(eb + wbt);
+  if (c->prof.on && ((c->prof.mask >> kKMergeWrite) & 1u)) c->prof.bytes[kKMergeWrite] += (double)T_out * (double)(eb + wbt);
   // ---- bookkeeping: one update per output image of every operator (a Clifford operator
   // counts its terms, the expanding operator its images), attributed per entry
   if (upd) upd->assign(E, 0);
@@ -871,6 +883,56 @@ struct BusyTimer {
   }
 };
 
+// Compile every chain table of a call's passes in one launch ahead of the rounds (a chain
+// table depends on the operators only), so that rounds need no table launch of their own.
+qimax_status prebuild_tables(qimax_ctx* c, std::vector<Pass>& passes) {
+  if (c->kb > 8) return QIMAX_OK;  // no tables for 16-byte keys
+  auto tableable = [](const std::vector<const HostOp*>& v) {
+    if ((int)v.size() < kChainTableMin) return false;
+    for (auto* op : v)
+      if (!op->conj) return false;
+    return true;
+  };
+  std::vector<std::pair<Pass*, int>> chains;
+  size_t n_perm = 0;
+  for (auto& p : passes)
+    for (int ab = 0; ab < 2; ++ab) {
+      const auto& v = ab ? p.B : p.A;
+      if (tableable(v)) {
+        chains.push_back({&p, ab});
+        n_perm += v.size();
+      }
+    }
+  if (chains.empty()) return QIMAX_OK;
+  const size_t entries_tab = c->kb * 256;
+  const size_t tab_bytes = align256(entries_tab * c->kb) + align256(entries_tab);
+  const size_t oJ = 0, oP = align256(chains.size() * sizeof(TableJob));
+  const size_t host_bytes = oP + align256(n_perm * sizeof(PermDesc));
+  const size_t oT = align256(host_bytes);
+  QCHK(ensure(c, c->ptab, oT + chains.size() * tab_bytes + 256));
+  QCHK(ensure_stage(c, 1, host_bytes));
+  uint8_t* hs = (uint8_t*)c->stage[1];
+  uint8_t* ds = (uint8_t*)c->ptab.p;
+  TableJob* jobs = (TableJob*)(hs + oJ);
+  PermDesc* perms = (PermDesc*)(hs + oP);
+  size_t np = 0;
+  for (size_t j = 0; j < chains.size(); ++j) {
+    Pass& p = *chains[j].first;
+    const int ab = chains[j].second;
+    const auto& v = ab ? p.B : p.A;
+    const size_t first = np;
+    for (auto* op : v) perms[np++] = make_perm(c->n, *op);
+    uint8_t* tk = ds + oT + j * tab_bytes;
+    uint8_t* tn = tk + align256(entries_tab * c->kb);
+    jobs[j] = TableJob{(const PermDesc*)(ds + oP) + first, (uint32_t)v.size(), 0, tk, tn};
+    p.pre[ab] = ChainTable{tk, tn};
+  }
+  HIPCHK(c, hipMemcpyAsync(ds, hs, host_bytes, hipMemcpyHostToDevice, c->stream), "upload chains");
+  HIPCHK(c, launch_build_tables(c->KC, (const TableJob*)(ds + oJ), (uint32_t)chains.size(), c->stream, &c->prof),
+         "chain tables");
+  return QIMAX_OK;
+}
+
 qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
   BusyTimer bt(c);
@@ -889,6 +951,7 @@ qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
     c->pending.swap(new_pending);
     return QIMAX_OK;
   }
+  QCHK(prebuild_tables(c, passes));
   const void* k_in = c->keys.p;
   const void* w_in = c->w.p;
   const uint64_t* s_in = (const uint64_t*)c->seg.p;
@@ -1463,6 +1526,20 @@ qimax_status qimax_profile(qimax_ctx* c, int enable) {
   return QIMAX_OK;
 }
 
+qimax_status qimax_profile_only(qimax_ctx* c, const char* kernel) {
+  if (!c) return QIMAX_EINVAL;
+  if (!kernel || !kernel[0]) {
+    c->prof.mask = ~0u;
+    return QIMAX_OK;
+  }
+  for (int i = 0; i < kKNum; ++i)
+    if (std::strcmp(kernel, kernel_kind_name(i)) == 0) {
+      c->prof.mask = 1u << i;
+      return QIMAX_OK;
+    }
+  return fail(c, QIMAX_EINVAL, std::string("unknown kernel name ") + kernel);
+}
+
 qimax_status qimax_profile_read(qimax_ctx* c, qimax_kernel_time* out, size_t cap, size_t* n) {
   if (!c || !n) return QIMAX_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
@@ -1533,7 +1610,7 @@ void qimax_destroy(qimax_ctx* c) {
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
                     &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
-                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->result};
+                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->result, &c->ptab};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 2; ++i)

@@ -128,10 +128,12 @@ const char* kernel_kind_name(int k);
 
 struct Prof {
   bool on = false;
+  uint32_t mask = ~0u;  // kernel kinds timed while on (bit k: kind k)
   struct Rec {
     int kind;
     hipEvent_t a, b;
     double bytes;
+    uint32_t count;  // back-to-back launches of `kind` between the two events
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -139,8 +141,8 @@ struct Prof {
   double ms[kKNum] = {};
   double bytes[kKNum] = {};
 };
-hipEvent_t prof_begin(Prof* p, hipStream_t s);
-void prof_end(Prof* p, hipStream_t s, hipEvent_t a, int kind, double bytes);
+hipEvent_t prof_begin(Prof* p, hipStream_t s, int kind);  // nullptr when `kind` is not timed
+void prof_end(Prof* p, hipStream_t s, hipEvent_t a, int kind, double bytes, uint32_t count = 1);
 void prof_resolve(Prof* p);  // after the stream has been synchronised
 void prof_reset(Prof* p);
 void prof_destroy(Prof* p);

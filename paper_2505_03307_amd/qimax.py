@@ -63,7 +63,7 @@ EXPORTS = ["qimax_batch_create", "qimax_batch_submit", "qimax_batch_step", "qima
            "qimax_batch_last_error", "qimax_batch_destroy",
            "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
            "qimax_num_terms", "qimax_get_generators", "qimax_expect", "qimax_get_stats", "qimax_sync",
-           "qimax_profile", "qimax_profile_read", "qimax_copy_probe", "qimax_last_error", "qimax_destroy"]
+           "qimax_profile", "qimax_profile_only", "qimax_profile_read", "qimax_copy_probe", "qimax_last_error", "qimax_destroy"]
 
 _lib = None
 
@@ -100,6 +100,7 @@ def load():
     lib.qimax_profile.argtypes = [P, ctypes.c_int]
     lib.qimax_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_size_t, szp]
     lib.qimax_copy_probe.argtypes = [ctypes.c_size_t, ctypes.c_int, dp]
+    lib.qimax_profile_only.argtypes = [P, ctypes.c_char_p]
     lib.qimax_last_error.argtypes = [P]
     lib.qimax_last_error.restype = ctypes.c_char_p
     lib.qimax_destroy.argtypes = [P]
@@ -276,6 +277,10 @@ class Simulator:
 
     def profile(self, enable: bool):
         self._check(load().qimax_profile(self._h, int(bool(enable))))
+
+    def profile_only(self, kernel: str | None):
+        """Time only one kernel kind (None: all kinds)."""
+        self._check(load().qimax_profile_only(self._h, kernel.encode() if kernel else None))
 
     def profile_read(self) -> dict:
         lib = load()
