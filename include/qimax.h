@@ -142,6 +142,8 @@ typedef struct {
   double host_wait_ms;     /* host time blocked in stream synchronisations of passes      */
   double host_busy_ms;     /* host time spent inside apply calls outside those waits      */
   uint64_t syncs;          /* stream synchronisations of passes                           */
+  uint64_t sort_redos;     /* rounds sorted again with global passes only (a bucket of
+                              equal top digits did not fit a chunk-local sort)            */
 } qimax_stats;
 
 qimax_status qimax_get_stats(const qimax_ctx* ctx, qimax_stats* out);

@@ -268,15 +268,16 @@ __device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t* a, uint64_t 
 // non-decreasing. Each round probes 64 evenly spaced elements at once and keeps the interval
 // between the last probe <= x and the first probe > x, so n elements take ceil(log64 n)
 // rounds of one parallel load instead of log2 n dependent loads.
-__device__ __forceinline__ uint64_t wave_upper_bound(const uint64_t* __restrict__ a, uint64_t lo, uint64_t hi,
-                                                     uint64_t x) {
+template <typename Pred>
+__device__ __forceinline__ uint64_t wave_first_true(uint64_t lo, uint64_t hi, const Pred& pred) {
+  // first i in [lo, hi) with pred(i) (hi if none), pred monotone (false..false true..true)
   const int lane = threadIdx.x & 63;
   while (true) {
     const uint64_t n = hi - lo;
     if (n == 0) return lo;
     const uint64_t step = n <= 64 ? 1 : (n + 63) / 64;
     const uint64_t i = lo + (uint64_t)lane * step;
-    const bool gt = i < hi ? a[i] > x : true;
+    const bool gt = i < hi ? pred(i) : true;
     const uint64_t m = __ballot(gt);
     const int first = m ? __ffsll((long long)m) - 1 : 64;
     if (step == 1) return first == 64 ? hi : lo + (uint64_t)first;
@@ -286,6 +287,11 @@ __device__ __forceinline__ uint64_t wave_upper_bound(const uint64_t* __restrict_
     lo = nlo;
     hi = nhi;
   }
+}
+
+__device__ __forceinline__ uint64_t wave_upper_bound(const uint64_t* __restrict__ a, uint64_t lo, uint64_t hi,
+                                                     uint64_t x) {
+  return wave_first_true(lo, hi, [&](uint64_t i) { return a[i] > x; });
 }
 
 template <typename K, int WP>
@@ -801,6 +807,156 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
   }
 }
 
+// ----------------------------------------------------------------- chunk-local sort
+// After stable global passes over the top m digits, every segment is grouped into buckets of
+// equal top digits, in order. Chunk c starts at the first bucket boundary at or after the
+// start of nominal tile c (the segment start for its first tile), so chunks are runs of whole
+// buckets; each chunk (at most kChunkCap elements) is sorted in LDS by the full key with
+// stable 8-bit passes, or by the low digits only when it holds one bucket, which completes a
+// stable sort of the segment. A bucket too large for a chunk raises kErrRedo (not an error:
+// the caller sorts the round again with global passes only).
+template <typename K, typename W>
+__global__ void __launch_bounds__(256) k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in,
+                                                    K* __restrict__ keys_out, W* __restrict__ w_out, Tiling tc,
+                                                    uint32_t n_pass, uint32_t m, uint32_t* err) {
+  constexpr int kItems = kChunkCap / 256, kWaves = 4;
+  __shared__ K sk[kChunkCap];
+  __shared__ uint16_t sidx[kChunkCap];
+  __shared__ uint32_t wrun[kWaves][kRadix];
+  __shared__ uint32_t wdummy[kWaves][64];
+  __shared__ uint32_t dstart[kRadix];
+  __shared__ uint64_t scan_sh[kWaves];
+  __shared__ uint64_t cb[2];
+  const uint32_t blk = blockIdx.x;
+  if (tc.n_dev && blk >= *tc.n_dev) return;
+  const uint64_t a = tc.blk_begin[blk], b = tc.blk_end[blk];
+  if (a >= b) return;
+  const uint32_t s = tc.blk_seg[blk];
+  const uint64_t seg_lo = tc.blk_begin[tc.seg_blk[s]], seg_hi = tc.blk_end[tc.seg_blk[s + 1] - 1];
+  const uint32_t top_shift = 8u * (n_pass - m);
+  auto top = [&](K key) -> K { return m == 0 ? (K)0 : (K)(key >> top_shift); };
+  // chunk bounds: wave 0 for the tile start, wave 1 for the tile end
+  if (threadIdx.x < 128) {
+    const uint64_t x = threadIdx.x < 64 ? a : b;
+    uint64_t r = x;
+    if (x != seg_lo && x != seg_hi) {
+      const K t = top(keys_in[x - 1]);
+      // a bucket holding x-1 ends before x + kChunkCap unless it is too large for a chunk
+      const uint64_t lim = min(seg_hi, x + (uint64_t)kChunkCap);
+      r = wave_first_true(x, lim, [&](uint64_t i) { return top(keys_in[i]) != t; });
+      if (r == lim && lim < seg_hi && (threadIdx.x & 63) == 0) atomicOr(err, kErrRedo);
+    }
+    if ((threadIdx.x & 63) == 0) cb[threadIdx.x >> 6] = r;
+  }
+  __syncthreads();
+  const uint64_t c0 = cb[0], c1 = cb[1];
+  if (c1 <= c0) return;  // every element of the tile belongs to an earlier chunk
+  if (c1 - c0 > (uint64_t)kChunkCap) {
+    if (threadIdx.x == 0) atomicOr(err, kErrRedo);
+    return;
+  }
+  const uint32_t n = (uint32_t)(c1 - c0);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  {
+    K kr[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) kr[r] = keys_in[c0 + min((uint32_t)(r * 256 + threadIdx.x), n - 1)];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t j = r * 256 + threadIdx.x;
+      if (j < n) {
+        sk[j] = kr[r];
+        sidx[j] = (uint16_t)j;
+      }
+    }
+  }
+  __syncthreads();
+  const bool one_bucket = top(sk[0]) == top(sk[n - 1]);
+  const uint32_t p_end = one_bucket ? n_pass - m : n_pass;
+  // the n elements in four equal wave spans of whole 64-element rounds
+  const uint32_t span = (n + kWaves * 64 - 1) / (kWaves * 64) * 64, nr = span / 64;
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  // the rounds of a wave run in two halves; the second only when the span needs it (no
+  // branch inside a half, so LDS operations of different rounds overlap)
+  static_assert(kItems == 16, "two halves of eight rounds");
+  const bool second = nr > 8;
+  auto rounds = [&](auto&& body) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) body(r);
+    if (second) {
+#pragma unroll
+      for (int r = 8; r < 16; ++r) body(r);
+    }
+  };
+  for (uint32_t p = 0; p < p_end; ++p) {
+    for (int i = threadIdx.x; i < kWaves * kRadix; i += 256) (&wrun[0][0])[i] = 0;
+    __syncthreads();
+    K key[kItems];
+    uint16_t ix[kItems];
+    uint32_t rank[kItems], dig[kItems];
+    uint8_t lead[kItems], below[kItems];
+    // every read of the pass first (clamped indices), then the ranking
+    rounds([&](int r) {
+      const uint32_t li = min(wid * span + r * 64 + lane, n - 1);
+      key[r] = sk[li];
+      ix[r] = sidx[li];
+    });
+    rounds([&](int r) {
+      const uint32_t li = wid * span + r * 64 + lane;  // stable order: wave span, round, lane
+      const bool valid = (uint32_t)r < nr && li < n;    // rounds past nr belong to the next wave
+      const uint32_t d = (uint32_t)(key[r] >> (8u * p)) & (kRadix - 1);
+      dig[r] = d;
+      uint64_t mk = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < kRadixBits; ++bit) {
+        const bool bon = (d >> bit) & 1u;
+        const uint64_t bb = __ballot(bon);
+        mk &= bon ? bb : ~bb;
+      }
+      // the leader of each digit group reserves its slots (every lane issues the atomic, the
+      // others adding 0 to a slot of their own); a wave's LDS atomics complete in issue order
+      const int leader = __ffsll((long long)mk) - 1;
+      const bool lead_me = valid && lane == leader;
+      rank[r] = atomicAdd(lead_me ? &wrun[wid][d] : &wdummy[wid][lane], lead_me ? (uint32_t)__popcll(mk) : 0u);
+      lead[r] = (uint8_t)(leader < 0 ? 0 : leader);
+      below[r] = (uint8_t)__popcll(mk & lt);
+    });
+    rounds([&](int r) { rank[r] = __shfl(rank[r], lead[r], 64); });
+    rounds([&](int r) { rank[r] += below[r]; });
+    __syncthreads();
+    {
+      const int d = threadIdx.x;  // 256 threads, 256 digits
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wrun[w][d];
+        wrun[w][d] = cnt;  // becomes the wave prefix
+        cnt += c;
+      }
+      uint64_t tot;
+      dstart[d] = (uint32_t)block_excl_scan<256>(cnt, scan_sh, &tot);
+    }
+    __syncthreads();
+    uint32_t dst[kItems];
+    rounds([&](int r) { dst[r] = dstart[dig[r]] + wrun[wid][dig[r]] + rank[r]; });
+    rounds([&](int r) {
+      if ((uint32_t)r < nr && wid * span + r * 64 + lane < n) {
+        sk[dst[r]] = key[r];
+        sidx[dst[r]] = ix[r];
+      }
+    });
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t j = r * 256 + threadIdx.x;
+    if (j < n) {
+      keys_out[c0 + j] = sk[j];
+      w_out[c0 + j] = w_in[c0 + sidx[j]];
+    }
+  }
+}
+
 // Digit histograms of every radix pass at once, per segment: ghist[(s*n_pass + p)*256 + d].
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict__ keys, Tiling tl, uint32_t n_pass,
@@ -1152,7 +1308,7 @@ inline uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)((n + bl
 
 const char* kernel_kind_name(int k) {
   static const char* names[kKNum] = {"init", "count", "scan", "expand", "sort_hist", "sort_scatter",
-                                     "merge_count", "merge_write", "compose_ptm"};
+                                     "merge_count", "merge_write", "compose_ptm", "chunk_sort"};
   return (k >= 0 && k < kKNum) ? names[k] : "?";
 }
 
@@ -1332,21 +1488,24 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
 }
 
 hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[2], uint64_t T, uint32_t key_bits,
-                             const Tiling& tl, const uint64_t* seg_off, uint32_t* ghist, uint64_t* status,
-                             uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err, int* cur, hipStream_t s,
-                             Prof* prof) {
+                             uint32_t p_begin, bool upsweep, const Tiling& tl, const uint64_t* seg_off,
+                             uint32_t* ghist, uint64_t* status, uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err,
+                             int* cur, hipStream_t s, Prof* prof) {
   *cur = 0;
   if (T == 0 || tl.n_blocks == 0) return hipSuccess;
   const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   QIMAX_DISPATCH_K(KC, {
-    hipEvent_t ev = prof_begin(prof, s, kKSortHist);
-    k_sort_upsweep<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys[0], tl, n_pass, ghist);
-    prof_end(prof, s, ev, kKSortHist, kb * (double)T);
+    hipEvent_t ev = nullptr;
+    if (upsweep) {
+      ev = prof_begin(prof, s, kKSortHist);
+      k_sort_upsweep<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys[0], tl, n_pass, ghist);
+      prof_end(prof, s, ev, kKSortHist, kb * (double)T);
+    }
     // the digit passes run back to back: one pair of events times them all (fewer event
-    // records on the host), and the average launch is their time over n_pass
+    // records on the host), and the average launch is their time over the passes
     ev = prof_begin(prof, s, kKSortScatter);
-    for (uint32_t p = 0; p < n_pass; ++p) {
+    for (uint32_t p = p_begin; p < n_pass; ++p) {
       *epoch += 1;  // the caller keeps *epoch + n_pass below 2^16 (clearing status on wrap)
       const int c = *cur;
       if (WP == 64)
@@ -1361,8 +1520,27 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
             err);
       *cur ^= 1;
     }
-    prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T * n_pass, n_pass);
+    if (n_pass > p_begin)
+      prof_end(prof, s, ev, kKSortScatter, 2.0 * (kb + wb) * (double)T * (n_pass - p_begin), n_pass - p_begin);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_sort(int KC, int WP, const void* keys_in, const void* w_in, void* keys_out, void* w_out,
+                             uint64_t T, const Tiling& tc, uint32_t n_pass, uint32_t m, uint32_t* err, hipStream_t s,
+                             Prof* prof) {
+  if (T == 0 || tc.n_blocks == 0) return hipSuccess;
+  const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
+  hipEvent_t ev = prof_begin(prof, s, kKChunkSort);
+  QIMAX_DISPATCH_K(KC, {
+    if (WP == 64)
+      k_chunk_sort<K, double><<<tc.n_blocks, 256, 0, s>>>((const K*)keys_in, (const double*)w_in, (K*)keys_out,
+                                                          (double*)w_out, tc, n_pass, m, err);
+    else
+      k_chunk_sort<K, float><<<tc.n_blocks, 256, 0, s>>>((const K*)keys_in, (const float*)w_in, (K*)keys_out,
+                                                         (float*)w_out, tc, n_pass, m, err);
+  });
+  prof_end(prof, s, ev, kKChunkSort, 2.0 * (kb + wb) * (double)T);
   return hipGetLastError();
 }
 

@@ -226,6 +226,9 @@ struct qimax_ctx {
   bool classic_sort = false;
   bool host_tiling = false;
   bool xcd_ranges = true;
+  bool local_sort = true;     // top-digit passes + chunk-local sorts instead of all global passes
+  int local_sort_m = -1;      // >= 0: force the number of top-digit passes
+  uint32_t redo_cooldown = 0; // rounds left with global passes only after a chunk overflow
   DevBuf gr_gate, gr_theta, gr_idx, gr_off, gr_out;
   uint64_t* pinned = nullptr;  // small pinned host scratch
   size_t pinned_words = 0;
@@ -732,6 +735,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   // ---- segment-local LSD radix sort of the images
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
   int cur = 0;
+  uint32_t m_top = n_pass;  // digits sorted by global passes (the rest chunk-locally)
+  int pre_chunk = -1;       // slot holding the images before the chunk-local sort
   if (!sweep) {
     QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
     QCHK(ensure(c, c->hist, hsize * 8));
@@ -755,9 +760,29 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     void* const kk[2] = {c->ik[0].p, c->ik[1].p};
     void* const ww[2] = {c->iw[0].p, c->iw[1].p};
     if (!c->xcd_ranges) tl.xrange = nullptr;
-    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, tl, (const uint64_t*)c->img_seg.p,
-                                (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr, &c->epoch, (uint32_t*)c->err.p,
-                                &cur, c->stream, &c->prof), "sort");
+    // Global passes over every digit, or over the top m digits only, followed by chunk-local
+    // sorts in LDS. m is the fewest top digits that split the largest segment (its image count
+    // or a bound of it) into buckets of about 512 on average.
+    m_top = n_pass;
+    if (c->local_sort && c->redo_cooldown == 0) {
+      uint64_t seg_max = 0;
+      for (uint32_t s = 0; s < S; ++s)
+        seg_max = std::max<uint64_t>(seg_max, bound_path ? (uint64_t)(f_round * (double)(so_in[s + 1] - so_in[s]))
+                                                         : so_img[s + 1] - so_img[s]);
+      uint32_t mm = 0;
+      for (double cap_b = 512.0; mm < n_pass && (double)seg_max > cap_b; cap_b *= 256.0) ++mm;
+      m_top = c->local_sort_m >= 0 ? std::min<uint32_t>((uint32_t)c->local_sort_m, n_pass) : mm;
+    }
+    if (c->redo_cooldown > 0) --c->redo_cooldown;
+    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, n_pass - m_top, true, tl,
+                                (const uint64_t*)c->img_seg.p, (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr,
+                                &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof), "sort");
+    if (m_top < n_pass) {
+      pre_chunk = cur;
+      HIPCHK(c, launch_chunk_sort(c->KC, c->WP, c->ik[cur].p, c->iw[cur].p, c->ik[cur ^ 1].p, c->iw[cur ^ 1].p, T_img,
+                                  tl_exp, n_pass, m_top, (uint32_t*)c->err.p, c->stream, &c->prof), "chunk sort");
+      cur ^= 1;
+    }
   }
   // ---- segmented reduce + prune + compaction into the pass output slot
   QCHK(ensure(c, c->pk[slot], std::max<uint64_t>(T_img, 1) * eb));
@@ -766,22 +791,44 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->blk_cnt, (size_t)(tl.n_blocks + 1) * 4));
   QCHK(ensure(c, c->blk_off, (size_t)(tl.n_blocks + 1) * 8));
   QCHK(ensure(c, c->result, (size_t)(2 * S + 3) * 8));
-  uint64_t* mstatus = nullptr;
   MergeFin fin{(const uint64_t*)c->img_seg.p, (uint64_t*)c->result.p};
-  if (sweep) {
-    QCHK(status_words(tl.n_blocks));
-    c->mepoch += 1;
-    mstatus = (uint64_t*)c->mstatus.p;
-  }
-  HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, pas, sent, c->pk[slot].p,
-                         c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
-                         (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, ctr + kCtrMerge, c->mepoch,
-                         (uint32_t*)c->err.p, sweep ? &fin : nullptr, c->stream, &c->prof), "merge");
-  // ---- one readback: output offsets, image offsets, error word
-  if (sweep) {
-    QCHK(readback(c, c->result.p, 2 * (size_t)S + 3, &e, /*err_packed=*/true));
-  } else {
-    QCHK(readback(c, c->pseg[slot].p, S + 1, &e));
+  auto merge_and_read = [&]() -> qimax_status {
+    uint64_t* mstatus = nullptr;
+    if (sweep) {
+      QCHK(status_words(tl.n_blocks));
+      c->mepoch += 1;
+      mstatus = (uint64_t*)c->mstatus.p;
+    }
+    HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, pas, sent, c->pk[slot].p,
+                           c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
+                           (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, ctr + kCtrMerge, c->mepoch,
+                           (uint32_t*)c->err.p, sweep ? &fin : nullptr, c->stream, &c->prof), "merge");
+    // ---- one readback: output offsets, image offsets, error word
+    if (sweep) return readback(c, c->result.p, 2 * (size_t)S + 3, &e, /*err_packed=*/true);
+    return readback(c, c->pseg[slot].p, S + 1, &e);
+  };
+  QCHK(merge_and_read());
+  bool sorted_again = false;
+  if (e == kErrRedo && pre_chunk >= 0) {
+    sorted_again = true;
+    // a bucket did not fit a chunk: sort the round again with global passes over every digit
+    // (stable passes on the top-digit grouping give the same order as on the images) and merge
+    // again; the next rounds use global passes only for a while
+    c->redo_cooldown = 8;
+    c->st.sort_redos += 1;
+    HIPCHK(c, launch_round_prep((uint32_t*)c->err.p, ctr, 256, nullptr, 0, c->stream), "prep");
+    void* const kk2[2] = {c->ik[pre_chunk].p, c->ik[pre_chunk ^ 1].p};
+    void* const ww2[2] = {c->iw[pre_chunk].p, c->iw[pre_chunk ^ 1].p};
+    int cur2 = 0;
+    if (c->epoch + n_pass >= 0xFFFFull) {
+      HIPCHK(c, launch_fill_u64((uint64_t*)c->sstatus.p, c->sstatus.bytes / 8, 0ull, c->stream), "clear status");
+      c->epoch = 0;
+    }
+    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk2, ww2, T_img, key_bits, 0, false, tl, (const uint64_t*)c->img_seg.p,
+                                (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr, &c->epoch, (uint32_t*)c->err.p,
+                                &cur2, c->stream, &c->prof), "sort");
+    cur = pre_chunk ^ cur2;
+    QCHK(merge_and_read());
   }
   if (e) {
     char buf[256];
@@ -803,7 +850,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       };
       fix(kKExpand, (double)(eb + wbt) * d);
       fix(kKSortHist, (double)eb * d);
-      fix(kKSortScatter, 2.0 * (double)(eb + wbt) * n_pass * d);
+      fix(kKSortScatter, 2.0 * (double)(eb + wbt) * (sorted_again ? n_pass + m_top : m_top) * d);
+      if (m_top < n_pass) fix(kKChunkSort, 2.0 * (double)(eb + wbt) * d);
       fix(kKMergeWrite, (double)(eb + wbt) * d);
     }
   }
@@ -1362,6 +1410,10 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     c->host_tiling = env && env[0] == '1';
     env = std::getenv("QIMAX_XCD_RANGES");  // 0: sort tiles claimed in one global order
     c->xcd_ranges = !(env && env[0] == '0');
+    env = std::getenv("QIMAX_LOCAL_SORT");  // 0: every digit by global passes
+    c->local_sort = !(env && env[0] == '0');
+    env = std::getenv("QIMAX_LOCAL_SORT_M");  // force the number of top-digit passes (tests)
+    if (env && env[0]) c->local_sort_m = std::atoi(env);
   }
   hipError_t e;
   if (o.device >= 0) {

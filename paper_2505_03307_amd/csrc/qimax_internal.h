@@ -99,6 +99,7 @@ constexpr int kSortBlock = 256;            // threads per sort / merge block
 constexpr int kSortItems = 16;             // items per thread
 constexpr int kSortTile = kSortBlock * kSortItems;  // elements per tile (4096)
 constexpr int kRadixBits = 8;
+constexpr int kChunkCap = 4096;  // elements a chunk-local sort holds in LDS (nominal chunks: kExpandTile)
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kExpandBlock = 256;
 constexpr int kExpandItems = 8;
@@ -116,13 +117,15 @@ enum : uint32_t {
   kErrExpand = 16u,    // set with kErrIndex by the expand kernel
   kErrSort = 32u,      // set with kErrIndex by the sort kernels
   kErrMerge = 64u,     // set with kErrIndex by the merge kernel
+  kErrRedo = 128u,     // not an error: a chunk-local sort met a bucket larger than a chunk
 };
 
 // ------------------------------------------------------------------------ kernel timing
 // Optional per-kernel timing with HIP events recorded on the launch stream, plus the
 // algorithmic bytes each launch must move (what the roofline is measured against).
 enum KernelKind : int {
-  kKInit, kKCount, kKScan, kKExpand, kKSortHist, kKSortScatter, kKMergeCount, kKMergeWrite, kKCompose, kKNum
+  kKInit, kKCount, kKScan, kKExpand, kKSortHist, kKSortScatter, kKMergeCount, kKMergeWrite, kKCompose, kKChunkSort,
+  kKNum
 };
 const char* kernel_kind_name(int k);
 
@@ -193,9 +196,18 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
 // ghist: n_segs*n_pass*256 u32, zero on entry; seg_off: the segment offsets (n_segs + 1);
 // status: n_blocks*256 u64 (zeroed when allocated); tile_ctr: n_pass*kXcds u32, zero on
 // entry; *epoch is advanced per digit pass.
+// p_begin: first digit pass (the passes p_begin .. n_pass-1 run; p_begin > 0 groups the
+// segments by their top digits only); upsweep: compute ghist first (else it is current).
 hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[2], uint64_t T, uint32_t key_bits,
-                             const Tiling& tl, const uint64_t* seg_off, uint32_t* ghist, uint64_t* status,
-                             uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err, int* cur, hipStream_t s,
+                             uint32_t p_begin, bool upsweep, const Tiling& tl, const uint64_t* seg_off,
+                             uint32_t* ghist, uint64_t* status, uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err,
+                             int* cur, hipStream_t s, Prof* prof = nullptr);
+
+// Chunk-local sort after the top m digit passes (see k_chunk_sort): nominal chunks are the
+// tiles of tc (at most kChunkCap/2 elements, segment-aligned); sorted data to keys_out/w_out
+// at the same positions. Sets kErrRedo when a bucket does not fit a chunk.
+hipError_t launch_chunk_sort(int KC, int WP, const void* keys_in, const void* w_in, void* keys_out, void* w_out,
+                             uint64_t T, const Tiling& tc, uint32_t n_pass, uint32_t m, uint32_t* err, hipStream_t s,
                              Prof* prof = nullptr);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 

@@ -141,26 +141,49 @@ def test_served_results_equal_alone():
             assert np.array_equal(x, y), c.name
 
 
-@pytest.mark.parametrize("variant", ["QIMAX_HOST_TILING", "QIMAX_SORT_CLASSIC"])
+@pytest.mark.parametrize("variant", [("QIMAX_HOST_TILING", "1"), ("QIMAX_SORT_CLASSIC", "1"),
+                                     ("QIMAX_LOCAL_SORT", "0"), ("QIMAX_LOCAL_SORT_M", "0"),
+                                     ("QIMAX_LOCAL_SORT_M", "1"), ("QIMAX_XCD_RANGES", "0")])
 def test_tiling_and_sort_variants_bit_identical(variant, monkeypatch):
     """Image tilings built on the device from the fan-out bound (the default for rounds whose
-    bound is small), tilings built on the host after reading the image count back, and the
-    classic multi-launch sort give identical tiles and a stable sort, hence identical sums:
-    the results must agree bit for bit, alone and batched."""
+    bound is small) or on the host after reading the image count back; the classic
+    multi-launch sort; every digit by global passes, or the top 0 / 1 digits followed by
+    chunk-local sorts (0 makes every segment above a chunk fall back to global passes): all
+    are stable sorts of the same images, hence identical sums, so the results must agree bit
+    for bit, alone and batched."""
+    name, value = variant
     cs = mixed_circuits()
     with Batch(precision=64) as b:
         ids = [b.submit(c) for c in cs]
         b.run()
         ref = [b.fetch(i) for i in ids]
     ref_alone = [alone(c) for c in cs[3:6]]
-    monkeypatch.setenv(variant, "1")
-    say("variant", variant)
+    monkeypatch.setenv(name, value)
+    say("variant", name, value)
     with Batch(precision=64) as b:
         ids = [b.submit(c) for c in cs]
         b.run()
         for c, cid, r in zip(cs, ids, ref):
             for x, y in zip(b.fetch(cid), r):
-                assert np.array_equal(x, y), (variant, c.name)
+                assert np.array_equal(x, y), (name, value, c.name)
     for c, r in zip(cs[3:6], ref_alone):
         for x, y in zip(alone(c), r):
-            assert np.array_equal(x, y), (variant, c.name)
+            assert np.array_equal(x, y), (name, value, c.name)
+
+
+def test_chunk_overflow_sorts_again(monkeypatch):
+    """With no top-digit pass forced, a segment larger than a chunk cannot be sorted
+    chunk-locally: the round is sorted again with global passes (counted in sort_redos) and
+    the result equals the oracle's and the default path's."""
+    c = W.c2_clifford_rz(seed=3, n=24, depth=150, n_rz=24)  # largest generator: 37,825 terms
+    ref = alone(c)
+    monkeypatch.setenv("QIMAX_LOCAL_SORT_M", "0")
+    with Simulator(c.n, prune_eps=c.eps) as s:
+        s.run(c)
+        got = s.generators()
+        redos = s.stats()["sort_redos"]
+    say("redos", redos, "terms", int(got[0][-1]))
+    assert redos > 0
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
+    compare_fp64(got, oracle_arrays(oracle.propagate(c), c.n), label=c.name)
