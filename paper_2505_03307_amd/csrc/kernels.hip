@@ -815,17 +815,17 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
 // stable 8-bit passes, or by the low digits only when it holds one bucket, which completes a
 // stable sort of the segment. A bucket too large for a chunk raises kErrRedo (not an error:
 // the caller sorts the round again with global passes only).
+constexpr int kChunkBlock = 512;  // threads of a chunk-local sort (8 waves)
 template <typename K, typename W>
-__global__ void __launch_bounds__(256) k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in,
+__global__ void __launch_bounds__(kChunkBlock) k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in,
                                                     K* __restrict__ keys_out, W* __restrict__ w_out, Tiling tc,
                                                     uint32_t n_pass, uint32_t m, uint32_t* err) {
-  constexpr int kItems = kChunkCap / 256, kWaves = 4;
+  constexpr int kItems = kChunkCap / kChunkBlock, kWaves = kChunkBlock / 64;
   __shared__ K sk[kChunkCap];
   __shared__ uint16_t sidx[kChunkCap];
-  __shared__ uint32_t wrun[kWaves][kRadix];
+  __shared__ __align__(16) uint32_t wrun[2][kWaves][kRadix];
   __shared__ uint32_t wdummy[kWaves][64];
-  __shared__ uint32_t dstart[kRadix];
-  __shared__ uint64_t scan_sh[kWaves];
+  __shared__ __align__(16) uint32_t dbase[kWaves][kRadix];
   __shared__ uint64_t cb[2];
   const uint32_t blk = blockIdx.x;
   if (tc.n_dev && blk >= *tc.n_dev) return;
@@ -860,10 +860,10 @@ __global__ void __launch_bounds__(256) k_chunk_sort(const K* __restrict__ keys_i
   {
     K kr[kItems];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) kr[r] = keys_in[c0 + min((uint32_t)(r * 256 + threadIdx.x), n - 1)];
+    for (int r = 0; r < kItems; ++r) kr[r] = keys_in[c0 + min((uint32_t)(r * kChunkBlock + threadIdx.x), n - 1)];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-      const uint32_t j = r * 256 + threadIdx.x;
+      const uint32_t j = r * kChunkBlock + threadIdx.x;
       if (j < n) {
         sk[j] = kr[r];
         sidx[j] = (uint16_t)j;
@@ -873,28 +873,30 @@ __global__ void __launch_bounds__(256) k_chunk_sort(const K* __restrict__ keys_i
   __syncthreads();
   const bool one_bucket = top(sk[0]) == top(sk[n - 1]);
   const uint32_t p_end = one_bucket ? n_pass - m : n_pass;
-  // the n elements in four equal wave spans of whole 64-element rounds
+  // the n elements in equal wave spans of whole 64-element rounds
   const uint32_t span = (n + kWaves * 64 - 1) / (kWaves * 64) * 64, nr = span / 64;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   // the rounds of a wave run in two halves; the second only when the span needs it (no
   // branch inside a half, so LDS operations of different rounds overlap)
-  static_assert(kItems == 16, "two halves of eight rounds");
-  const bool second = nr > 8;
+  constexpr int kHalf = kItems / 2;
+  const bool second = nr > (uint32_t)kHalf;
   auto rounds = [&](auto&& body) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) body(r);
+    for (int r = 0; r < kHalf; ++r) body(r);
     if (second) {
 #pragma unroll
-      for (int r = 8; r < 16; ++r) body(r);
+      for (int r = kHalf; r < kItems; ++r) body(r);
     }
   };
+  // per-wave digit counters, double-buffered by pass parity (a wave clears its row of the
+  // other buffer for the next pass), so that a pass needs only two block barriers
+  for (int i = threadIdx.x; i < 2 * kWaves * kRadix; i += kChunkBlock) (&wrun[0][0][0])[i] = 0;
+  __syncthreads();
   for (uint32_t p = 0; p < p_end; ++p) {
-    for (int i = threadIdx.x; i < kWaves * kRadix; i += 256) (&wrun[0][0])[i] = 0;
-    __syncthreads();
+    const int pb = p & 1;
     K key[kItems];
     uint16_t ix[kItems];
-    uint32_t rank[kItems], dig[kItems];
-    uint8_t lead[kItems], below[kItems];
+    uint32_t rank[kItems], pk[kItems];  // pk: digit | leader lane << 8 | lanes below with that digit << 16
     // every read of the pass first (clamped indices), then the ranking
     rounds([&](int r) {
       const uint32_t li = min(wid * span + r * 64 + lane, n - 1);
@@ -905,7 +907,6 @@ __global__ void __launch_bounds__(256) k_chunk_sort(const K* __restrict__ keys_i
       const uint32_t li = wid * span + r * 64 + lane;  // stable order: wave span, round, lane
       const bool valid = (uint32_t)r < nr && li < n;    // rounds past nr belong to the next wave
       const uint32_t d = (uint32_t)(key[r] >> (8u * p)) & (kRadix - 1);
-      dig[r] = d;
       uint64_t mk = __ballot(valid);
 #pragma unroll
       for (int bit = 0; bit < kRadixBits; ++bit) {
@@ -917,39 +918,48 @@ __global__ void __launch_bounds__(256) k_chunk_sort(const K* __restrict__ keys_i
       // others adding 0 to a slot of their own); a wave's LDS atomics complete in issue order
       const int leader = __ffsll((long long)mk) - 1;
       const bool lead_me = valid && lane == leader;
-      rank[r] = atomicAdd(lead_me ? &wrun[wid][d] : &wdummy[wid][lane], lead_me ? (uint32_t)__popcll(mk) : 0u);
-      lead[r] = (uint8_t)(leader < 0 ? 0 : leader);
-      below[r] = (uint8_t)__popcll(mk & lt);
+      rank[r] = atomicAdd(lead_me ? &wrun[pb][wid][d] : &wdummy[wid][lane], lead_me ? (uint32_t)__popcll(mk) : 0u);
+      pk[r] = d | ((uint32_t)(leader < 0 ? 0 : leader) << 8) | ((uint32_t)__popcll(mk & lt) << 16);
     });
-    rounds([&](int r) { rank[r] = __shfl(rank[r], lead[r], 64); });
-    rounds([&](int r) { rank[r] += below[r]; });
+    rounds([&](int r) { rank[r] = __shfl(rank[r], (pk[r] >> 8) & 63u, 64); });
+    rounds([&](int r) { rank[r] += pk[r] >> 16; });
     __syncthreads();
     {
-      const int d = threadIdx.x;  // 256 threads, 256 digits
-      uint32_t cnt = 0;
+      // every wave scans all 256 digit totals itself (lane l: digits 4l..4l+3) and keeps, in
+      // its own row of dbase, where its elements of each digit start
+      uint32_t tot[4] = {0, 0, 0, 0}, pre[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = wrun[w][d];
-        wrun[w][d] = cnt;  // becomes the wave prefix
-        cnt += c;
+        const uint4 c = *(const uint4*)&wrun[pb][w][4 * lane];
+        const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (w < wid) pre[j] += cw[j];
+          tot[j] += cw[j];
+        }
       }
-      uint64_t tot;
-      dstart[d] = (uint32_t)block_excl_scan<256>(cnt, scan_sh, &tot);
+      const uint32_t lane_sum = tot[0] + tot[1] + tot[2] + tot[3];
+      uint32_t run = (uint32_t)(wave_incl_scan((uint64_t)lane_sum) - lane_sum);
+      uint4 base;
+      base.x = run + pre[0]; run += tot[0];
+      base.y = run + pre[1]; run += tot[1];
+      base.z = run + pre[2]; run += tot[2];
+      base.w = run + pre[3];
+      *(uint4*)&dbase[wid][4 * lane] = base;
+      *(uint4*)&wrun[pb ^ 1][wid][4 * lane] = make_uint4(0u, 0u, 0u, 0u);
     }
-    __syncthreads();
-    uint32_t dst[kItems];
-    rounds([&](int r) { dst[r] = dstart[dig[r]] + wrun[wid][dig[r]] + rank[r]; });
     rounds([&](int r) {
       if ((uint32_t)r < nr && wid * span + r * 64 + lane < n) {
-        sk[dst[r]] = key[r];
-        sidx[dst[r]] = ix[r];
+        const uint32_t dst = dbase[wid][pk[r] & 255u] + rank[r];
+        sk[dst] = key[r];
+        sidx[dst] = ix[r];
       }
     });
     __syncthreads();
   }
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const uint32_t j = r * 256 + threadIdx.x;
+    const uint32_t j = r * kChunkBlock + threadIdx.x;
     if (j < n) {
       keys_out[c0 + j] = sk[j];
       w_out[c0 + j] = w_in[c0 + sidx[j]];
@@ -1534,10 +1544,10 @@ hipError_t launch_chunk_sort(int KC, int WP, const void* keys_in, const void* w_
   hipEvent_t ev = prof_begin(prof, s, kKChunkSort);
   QIMAX_DISPATCH_K(KC, {
     if (WP == 64)
-      k_chunk_sort<K, double><<<tc.n_blocks, 256, 0, s>>>((const K*)keys_in, (const double*)w_in, (K*)keys_out,
+      k_chunk_sort<K, double><<<tc.n_blocks, kChunkBlock, 0, s>>>((const K*)keys_in, (const double*)w_in, (K*)keys_out,
                                                           (double*)w_out, tc, n_pass, m, err);
     else
-      k_chunk_sort<K, float><<<tc.n_blocks, 256, 0, s>>>((const K*)keys_in, (const float*)w_in, (K*)keys_out,
+      k_chunk_sort<K, float><<<tc.n_blocks, kChunkBlock, 0, s>>>((const K*)keys_in, (const float*)w_in, (K*)keys_out,
                                                          (float*)w_out, tc, n_pass, m, err);
   });
   prof_end(prof, s, ev, kKChunkSort, 2.0 * (kb + wb) * (double)T);
