@@ -876,16 +876,16 @@ __global__ void __launch_bounds__(kChunkBlock) k_chunk_sort(const K* __restrict_
   // the n elements in equal wave spans of whole 64-element rounds
   const uint32_t span = (n + kWaves * 64 - 1) / (kWaves * 64) * 64, nr = span / 64;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  // the rounds of a wave run in two halves; the second only when the span needs it (no
-  // branch inside a half, so LDS operations of different rounds overlap)
-  constexpr int kHalf = kItems / 2;
-  const bool second = nr > (uint32_t)kHalf;
+  // the rounds of a wave run in pairs; a pair wholly past the span is skipped (no branch
+  // inside a pair, so LDS operations of different rounds overlap)
+  static_assert(kItems % 2 == 0, "rounds in pairs");
   auto rounds = [&](auto&& body) {
 #pragma unroll
-    for (int r = 0; r < kHalf; ++r) body(r);
-    if (second) {
-#pragma unroll
-      for (int r = kHalf; r < kItems; ++r) body(r);
+    for (int r2 = 0; r2 < kItems; r2 += 2) {
+      if ((uint32_t)r2 < nr) {
+        body(r2);
+        body(r2 + 1);
+      }
     }
   };
   // per-wave digit counters, double-buffered by pass parity (a wave clears its row of the
@@ -907,13 +907,18 @@ __global__ void __launch_bounds__(kChunkBlock) k_chunk_sort(const K* __restrict_
       const uint32_t li = wid * span + r * 64 + lane;  // stable order: wave span, round, lane
       const bool valid = (uint32_t)r < nr && li < n;    // rounds past nr belong to the next wave
       const uint32_t d = (uint32_t)(key[r] >> (8u * p)) & (kRadix - 1);
-      uint64_t mk = __ballot(valid);
+      // lanes whose digit differs from this lane's in some bit: OR of (ballot of the bit) XOR
+      // (this lane's bit spread over the mask)
+      const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
+      uint32_t dlo = ~(uint32_t)vm, dhi = ~(uint32_t)(vm >> 32);
 #pragma unroll
       for (int bit = 0; bit < kRadixBits; ++bit) {
-        const bool bon = (d >> bit) & 1u;
-        const uint64_t bb = __ballot(bon);
-        mk &= bon ? bb : ~bb;
+        const int spread = __builtin_amdgcn_sbfe((int)d, bit, 1);  // 0 or all ones
+        const uint64_t bb = __builtin_amdgcn_ballot_w64(spread != 0);
+        dlo |= (uint32_t)bb ^ (uint32_t)spread;
+        dhi |= (uint32_t)(bb >> 32) ^ (uint32_t)spread;
       }
+      const uint64_t mk = ~(((uint64_t)dhi << 32) | dlo);
       // the leader of each digit group reserves its slots (every lane issues the atomic, the
       // others adding 0 to a slot of their own); a wave's LDS atomics complete in issue order
       const int leader = __ffsll((long long)mk) - 1;
