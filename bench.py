@@ -172,7 +172,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--precision", type=int, default=64, choices=(32, 64))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-gens", type=str, default="all",

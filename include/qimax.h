@@ -144,6 +144,7 @@ typedef struct {
   uint64_t syncs;          /* stream synchronisations of passes                           */
   uint64_t sort_redos;     /* rounds sorted again with global passes only (a bucket of
                               equal top digits did not fit a chunk-local sort)            */
+  uint64_t tuned_classes;  /* round size classes whose sort variant the autotuner fixed   */
 } qimax_stats;
 
 qimax_status qimax_get_stats(const qimax_ctx* ctx, qimax_stats* out);

@@ -42,6 +42,18 @@ struct HostOp {
   std::vector<double> R;  // dim*dim
 };
 
+// Autotuner state of one size class of rounds: the sort variants tried (0: heuristic number
+// of top-digit passes, 1: one more, 2: heuristic without per-XCD tile ranges), their measured
+// device times, and the winner once every candidate has run once.
+struct TuneState {
+  static constexpr int kCand = 3;
+  int tried = 0;
+  int best = -1;
+  float ms[kCand] = {};
+};
+
+inline int ilog2_u64(uint64_t x) { return x ? 63 - __builtin_clzll(x) : 0; }
+
 struct Pass {
   std::vector<const HostOp*> A, E, B;
   uint64_t emask = 0, bmask = 0;
@@ -229,6 +241,9 @@ struct qimax_ctx {
   bool local_sort = true;     // top-digit passes + chunk-local sorts instead of all global passes
   int local_sort_m = -1;      // >= 0: force the number of top-digit passes
   uint32_t redo_cooldown = 0; // rounds left with global passes only after a chunk overflow
+  bool autotune = true;       // choose among sort variants by measured time per size class
+  std::map<uint32_t, TuneState> tune;
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   DevBuf gr_gate, gr_theta, gr_idx, gr_off, gr_out;
   uint64_t* pinned = nullptr;  // small pinned host scratch
   size_t pinned_words = 0;
@@ -737,6 +752,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   int cur = 0;
   uint32_t m_top = n_pass;  // digits sorted by global passes (the rest chunk-locally)
   int pre_chunk = -1;       // slot holding the images before the chunk-local sort
+  uint32_t tune_key = 0;    // autotuner: size class of this round's sort, candidate, timed?
+  int tune_cand = 0;
+  bool tune_timed = false;
   if (!sweep) {
     QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
     QCHK(ensure(c, c->hist, hsize * 8));
@@ -759,11 +777,12 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     void* const kk[2] = {c->ik[0].p, c->ik[1].p};
     void* const ww[2] = {c->iw[0].p, c->iw[1].p};
-    if (!c->xcd_ranges) tl.xrange = nullptr;
     // Global passes over every digit, or over the top m digits only, followed by chunk-local
     // sorts in LDS. m is the fewest top digits that split the largest segment (its image count
-    // or a bound of it) into buckets of about 512 on average.
+    // or a bound of it) into buckets of about 512 on average; the autotuner may add one, and
+    // may turn the per-XCD tile ranges off, by what it measured for rounds of this size.
     m_top = n_pass;
+    bool xr = c->xcd_ranges;
     if (c->local_sort && c->redo_cooldown == 0) {
       uint64_t seg_max = 0;
       for (uint32_t s = 0; s < S; ++s)
@@ -772,8 +791,20 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       uint32_t mm = 0;
       for (double cap_b = 512.0; mm < n_pass && (double)seg_max > cap_b; cap_b *= 256.0) ++mm;
       m_top = c->local_sort_m >= 0 ? std::min<uint32_t>((uint32_t)c->local_sort_m, n_pass) : mm;
+      if (c->autotune && c->local_sort_m < 0 && m_top < n_pass) {
+        tune_key = (uint32_t)c->KC * 4096u + (uint32_t)c->WP * 64u + (uint32_t)std::min(63, ilog2_u64(T_img));
+        TuneState& ts = c->tune[tune_key];
+        tune_cand = ts.best >= 0 ? ts.best : ts.tried;
+        if (tune_cand == 1) m_top = std::min(m_top + 1, n_pass);
+        if (tune_cand == 2) xr = false;
+        if (ts.best < 0) {  // exploring: time the sort of this round
+          HIPCHK(c, hipEventRecord(c->tune_ev[0], c->stream), "tune event");
+          tune_timed = true;
+        }
+      }
     }
     if (c->redo_cooldown > 0) --c->redo_cooldown;
+    if (!xr) tl.xrange = nullptr;
     HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, n_pass - m_top, true, tl,
                                 (const uint64_t*)c->img_seg.p, (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr,
                                 &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof), "sort");
@@ -783,6 +814,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
                                   tl_exp, n_pass, m_top, (uint32_t*)c->err.p, c->stream, &c->prof), "chunk sort");
       cur ^= 1;
     }
+    if (tune_timed) HIPCHK(c, hipEventRecord(c->tune_ev[1], c->stream), "tune event");
   }
   // ---- segmented reduce + prune + compaction into the pass output slot
   QCHK(ensure(c, c->pk[slot], std::max<uint64_t>(T_img, 1) * eb));
@@ -829,6 +861,19 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
                                 &cur2, c->stream, &c->prof), "sort");
     cur = pre_chunk ^ cur2;
     QCHK(merge_and_read());
+  }
+  if (tune_timed) {  // the round has synchronised: both events are complete
+    TuneState& ts = c->tune[tune_key];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]) != hipSuccess) ms = 1e30f;
+    if (sorted_again) ms = 1e30f;  // a candidate that overflows chunks is never chosen
+    ts.ms[tune_cand] = ms;
+    if (++ts.tried >= TuneState::kCand) {
+      ts.best = 0;
+      for (int i = 1; i < TuneState::kCand; ++i)
+        if (ts.ms[i] < ts.ms[ts.best]) ts.best = i;
+      c->st.tuned_classes += 1;
+    }
   }
   if (e) {
     char buf[256];
@@ -1414,6 +1459,8 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     c->local_sort = !(env && env[0] == '0');
     env = std::getenv("QIMAX_LOCAL_SORT_M");  // force the number of top-digit passes (tests)
     if (env && env[0]) c->local_sort_m = std::atoi(env);
+    env = std::getenv("QIMAX_AUTOTUNE");  // 0: always the heuristic's sort variant
+    c->autotune = !(env && env[0] == '0');
   }
   hipError_t e;
   if (o.device >= 0) {
@@ -1429,6 +1476,11 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     if (e != hipSuccess) { g_create_error = hipGetErrorString(e); delete c; return QIMAX_EDEVICE; }
     c->own_stream = true;
   }
+  for (hipEvent_t& ev : c->tune_ev)
+    if (hipEventCreate(&ev) != hipSuccess) {
+      ev = nullptr;
+      c->autotune = false;
+    }
   qimax_status s;
   if ((s = ensure(c, c->keys, n * c->kb, false)) != QIMAX_OK || (s = ensure(c, c->w, n * c->wb, false)) != QIMAX_OK ||
       (s = ensure(c, c->seg, (n + 1) * 8, false)) != QIMAX_OK || (s = ensure(c, c->err, 256, false)) != QIMAX_OK) {
@@ -1668,6 +1720,8 @@ void qimax_destroy(qimax_ctx* c) {
   for (int i = 0; i < 2; ++i)
     if (c->stage[i]) (void)hipHostFree(c->stage[i]);
   prof_destroy(&c->prof);
+  for (hipEvent_t e : c->tune_ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

@@ -39,7 +39,7 @@ class Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("terms", "passes", "term_updates", "images", "sort_elems", "peak_bytes", "alloc_bytes")] + \
                [("host_wait_ms", ctypes.c_double), ("host_busy_ms", ctypes.c_double), ("syncs", ctypes.c_uint64),
-                ("sort_redos", ctypes.c_uint64)]
+                ("sort_redos", ctypes.c_uint64), ("tuned_classes", ctypes.c_uint64)]
 
 
 class CircuitC(ctypes.Structure):

@@ -187,3 +187,22 @@ def test_chunk_overflow_sorts_again(monkeypatch):
     for x, y in zip(got, ref):
         assert np.array_equal(x, y)
     compare_fp64(got, oracle_arrays(oracle.propagate(c), c.n), label=c.name)
+
+
+def test_autotuner_settles_and_keeps_results():
+    """The sort variant is chosen per size class of rounds from measured times: after a few
+    runs of the same circuit every explored class is fixed, and every run gives the same
+    generators bit for bit (the variants are the same stable sort)."""
+    c = W.c2_clifford_rz(seed=1, n=24, depth=100, n_rz=20)
+    with Simulator(c.n, prune_eps=c.eps) as s:
+        runs = []
+        for _ in range(4):
+            s.reset()
+            s.run(c)
+            runs.append(s.generators())
+        st = s.stats()
+    say("tuned classes", st["tuned_classes"])
+    assert st["tuned_classes"] > 0
+    for r in runs[1:]:
+        for x, y in zip(r, runs[0]):
+            assert np.array_equal(x, y)
