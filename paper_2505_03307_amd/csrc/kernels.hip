@@ -296,8 +296,8 @@ __device__ __forceinline__ uint64_t wave_upper_bound(const uint64_t* __restrict_
 
 template <typename K, int WP>
 __global__ void __launch_bounds__(kExpandBlock)
-k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__ w, uint64_t T_in,
-         const uint64_t* __restrict__ off, uint64_t T_img, Tiling tl, const PassArgs* __restrict__ pas,
+k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const typename WTraits<WP>::W* __restrict__ w,
+         uint64_t T_in, const uint64_t* __restrict__ off, uint64_t T_img, Tiling tl, const PassArgs* __restrict__ pas,
          const uint32_t* __restrict__ seg_entry, const uint64_t* __restrict__ seg_in, K* __restrict__ keys_out,
          typename WTraits<WP>::W* __restrict__ w_out, uint32_t* err) {
   using W = typename WTraits<WP>::W;
@@ -312,10 +312,6 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   uint64_t* win = (uint64_t*)lds;
   uint16_t* pmap = (uint16_t*)(lds + kWin * 8);
   uint8_t* cur = lds + kWin * 8 + kExpandTile * 2;
-  K* tak = (K*)cur;
-  cur += pa.useA ? kTab * sizeof(K) : 0;
-  uint8_t* tan_ = cur;
-  cur += pa.useA ? kTab : 0;
   K* tbk = (K*)cur;
   cur += pa.useB ? kTab * sizeof(K) : 0;
   uint8_t* tbn = cur;
@@ -326,7 +322,6 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   const uint64_t g0 = tl.blk_begin[blk];
   const uint64_t g1 = min(tl.blk_end[blk], T_img);
   if (g0 >= g1) return;
-  if (pa.useA) stage_table(pa.tA, tak, tan_);
   if (pa.useB) stage_table(pa.tB, tbk, tbn);
   // the expanding operators' descriptors, read many times per image, go to LDS
   const uint32_t e1w = pa.nE1 * (uint32_t)(sizeof(Exp1Desc) / 8), e2w = pa.nE2 * (uint32_t)(sizeof(Exp2Desc) / 8);
@@ -376,11 +371,13 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
   }
   K kp[kExpandItems];
   W wp[kExpandItems];
+  uint32_t sp[kExpandItems];
 #pragma unroll
   for (int it = 0; it < kExpandItems; ++it) {
     const uint64_t p = min(par[it], T_in - 1);  // T_in >= 1: this tile has images
     kp[it] = keys[p];
     wp[it] = w[p];
+    sp[it] = asign[p];
   }
 #pragma unroll
   for (int it = 0; it < kExpandItems; ++it) {
@@ -390,11 +387,9 @@ k_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__
       atomicOr(err, kErrIndex | kErrExpand);
       continue;
     }
-    K key = kp[it];
+    K key = kp[it];  // the parent's image under the A chain (and its sign), from the count
     W wv = wp[it];
-    uint32_t neg = 0;
-    if (pa.useA) key = apply_table(key, tak, tan_, neg);
-    else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+    uint32_t neg = sp[it];
     uint32_t r = rk[it];
     for (uint32_t e = 0; e < pa.nE1; ++e) {
       const Exp1Desc& E = E1s[e];
@@ -710,7 +705,8 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
                                                     const PassArgs* __restrict__ pas,
                                                     const uint32_t* __restrict__ seg_entry, uint64_t* __restrict__ off,
                                                     uint64_t T_in, uint64_t* __restrict__ status,
-                                                    uint32_t* __restrict__ ctr, uint64_t epoch, uint32_t* err) {
+                                                    uint32_t* __restrict__ ctr, uint64_t epoch, uint32_t* err,
+                                                    K* __restrict__ akeys, uint8_t* __restrict__ asign) {
   constexpr int kItems = kSortTile / 256;  // input tiles hold at most kSortTile terms
   constexpr int kTabN = sizeof(K) <= 8 ? (int)sizeof(K) * 256 : 1;  // no tables for 16-byte keys
   __shared__ K tk[kTabN];
@@ -741,9 +737,9 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
     const uint32_t li = r * 256 + threadIdx.x;
     if (li >= n) break;
     uint64_t f = 0;
+    K key = kr[r];
+    uint32_t neg = 0;
     if (!pa.drop) {
-      K key = kr[r];
-      uint32_t neg = 0;
       if (pa.useA) key = apply_table(key, tk, tn, neg);
       else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
       f = 1;
@@ -756,6 +752,9 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
       }
     }
     sf[pad(li)] = f;
+    // the A chain is applied once per term here; the expand kernel starts from this image
+    akeys[begin + li] = key;
+    asign[begin + li] = (uint8_t)(neg & 1u);
   }
   __syncthreads();
   // each thread sums a run of kItems consecutive terms; block scan of the run sums
@@ -972,10 +971,11 @@ __global__ void __launch_bounds__(kChunkBlock) k_chunk_sort(const K* __restrict_
   }
 }
 
-// Digit histograms of every radix pass at once, per segment: ghist[(s*n_pass + p)*256 + d].
+// Digit histograms of the radix passes p_begin .. n_pass-1 at once, per segment:
+// ghist[(s*n_pass + p)*256 + d].
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict__ keys, Tiling tl, uint32_t n_pass,
-                                                             uint32_t* __restrict__ ghist) {
+                                                             uint32_t p_begin, uint32_t* __restrict__ ghist) {
   constexpr int kWaves = sizeof(K) <= 8 ? kSortBlock / 64 : 1;  // private copies per wave
   constexpr int kMaxPass = (int)sizeof(K);
   __shared__ uint32_t h[kWaves][kMaxPass][kRadix];
@@ -994,11 +994,11 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     if (r * kSortBlock + threadIdx.x >= n) break;
-    for (uint32_t p = 0; p < n_pass; ++p) atomicAdd(&h[wid][p][(uint32_t)(kr[r] >> (8 * p)) & 255u], 1u);
+    for (uint32_t p = p_begin; p < n_pass; ++p) atomicAdd(&h[wid][p][(uint32_t)(kr[r] >> (8 * p)) & 255u], 1u);
   }
   __syncthreads();
   const uint32_t s = tl.blk_seg[b];
-  for (uint32_t i = threadIdx.x; i < n_pass * kRadix; i += kSortBlock) {
+  for (uint32_t i = p_begin * kRadix + threadIdx.x; i < n_pass * kRadix; i += kSortBlock) {
     const uint32_t p = i / kRadix, dd = i % kRadix;
     uint32_t c = 0;
 #pragma unroll
@@ -1408,16 +1408,17 @@ hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, u
 
 hipError_t launch_count_scan(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
                              const uint32_t* seg_entry, uint64_t* off, uint64_t* status, uint32_t* ctr, uint64_t epoch,
-                             uint32_t* err, hipStream_t s, Prof* prof) {
+                             uint32_t* err, void* akeys, uint8_t* asign, hipStream_t s, Prof* prof) {
   if (T == 0 || tl.n_blocks == 0) {
     k_zero_one<<<1, 1, 0, s>>>(off);
     return hipGetLastError();
   }
   hipEvent_t ev = prof_begin(prof, s, kKCount);
   QIMAX_DISPATCH_K(KC, {
-    k_count_scan<K><<<tl.n_blocks, 256, 0, s>>>((const K*)keys, tl, pas, seg_entry, off, T, status, ctr, epoch, err);
+    k_count_scan<K><<<tl.n_blocks, 256, 0, s>>>((const K*)keys, tl, pas, seg_entry, off, T, status, ctr, epoch, err,
+                                                 (K*)akeys, asign);
   });
-  prof_end(prof, s, ev, kKCount, (double)T * ((4 << KC) + 8));
+  prof_end(prof, s, ev, kKCount, (double)T * (2 * (4 << KC) + 9));
   return hipGetLastError();
 }
 
@@ -1454,21 +1455,22 @@ hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint6
   return hipGetLastError();
 }
 
-hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const uint64_t* off,
+hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign, const void* w, uint64_t T_in,
+                         const uint64_t* off,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
                          const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
                          uint32_t* err, hipStream_t s, Prof* prof) {
   if (T_img == 0 || tl.n_blocks == 0) return hipSuccess;
   hipEvent_t ev = prof_begin(prof, s, kKExpand);
   QIMAX_DISPATCH_K(KC, {
-    const size_t tab = sizeof(K) * 256 * (sizeof(K) + 1);
-    const size_t lds = (size_t)(kExpandTile + 1) * 8 + (size_t)kExpandTile * 2 + (any_tables ? 2 * tab : 0) +
+    const size_t tab = sizeof(K) * 256 * (sizeof(K) + 1);  // a B-chain table (A chains: done by the count)
+    const size_t lds = (size_t)(kExpandTile + 1) * 8 + (size_t)kExpandTile * 2 + (any_tables ? tab : 0) +
                        e_bytes + 64;
     if (WP == 64)
-      k_expand<K, 64><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, (const double*)w, T_in, off, T_img, tl,
+      k_expand<K, 64><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, asign, (const double*)w, T_in, off, T_img, tl,
                                                               pas, seg_entry, seg_in, (K*)keys_out, (double*)w_out, err);
     else
-      k_expand<K, 32><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, (const float*)w, T_in, off, T_img, tl,
+      k_expand<K, 32><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, asign, (const float*)w, T_in, off, T_img, tl,
                                                               pas, seg_entry, seg_in, (K*)keys_out, (float*)w_out, err);
   });
   const double per = (4 << KC) + (WP == 64 ? 8 : 4);
@@ -1514,7 +1516,7 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
     hipEvent_t ev = nullptr;
     if (upsweep) {
       ev = prof_begin(prof, s, kKSortHist);
-      k_sort_upsweep<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys[0], tl, n_pass, ghist);
+      k_sort_upsweep<K><<<tl.n_blocks, kSortBlock, 0, s>>>((const K*)keys[0], tl, n_pass, p_begin, ghist);
       prof_end(prof, s, ev, kKSortHist, kb * (double)T);
     }
     // the digit passes run back to back: one pair of events times them all (fewer event

@@ -229,6 +229,7 @@ struct qimax_ctx {
   DevBuf cnt, off, scan_tmp, hist, hist_off, blk_begin, blk_end, blk_seg, seg_blk, blk_cnt, blk_off, img_seg;
   DevBuf desc, desc2, err, f64tmp;
   DevBuf ptab;  // chain tables of a whole call, compiled in one launch
+  DevBuf akeys, asign;  // input terms after their pass's A chain, and the signs (count -> expand)
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
   DevBuf mstatus;  // single-sweep count and merge state (one word per tile)
@@ -572,6 +573,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   size_t n_jobs = 0;
   size_t e_bytes = 0;  // largest expanding-operator descriptor set of an entry (staged in LDS)
   bool any_tables = false;
+  bool any_b_tables = false;
   uint32_t max_n = 1;
   auto tableable = [c](const std::vector<const HostOp*>& v) {
     if (c->kb > 8 || (int)v.size() < kChainTableMin) return false;  // no tables for 16-byte keys
@@ -599,6 +601,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     L.useB = tableable(p->B);
     n_jobs += (L.useA && !p->pre[0].tab_key) + (L.useB && !p->pre[1].tab_key);
     any_tables |= L.useA || L.useB;
+    any_b_tables |= L.useB;
   }
   HostTiling t_in;
   make_tiling(so_in, kSortTile, t_in);
@@ -684,10 +687,13 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     return QIMAX_OK;
   };
   QCHK(ensure(c, c->off, (T_in + 1) * 8));
+  QCHK(ensure(c, c->akeys, std::max<uint64_t>(T_in, 1) * c->kb));
+  QCHK(ensure(c, c->asign, std::max<uint64_t>(T_in, 1)));
   QCHK(status_words(tl_in.n_blocks));
   c->mepoch += 1;
   HIPCHK(c, launch_count_scan(c->KC, k_in, T_in, tl_in, pas, sent, (uint64_t*)c->off.p, (uint64_t*)c->mstatus.p,
-                              ctr + kCtrCount, c->mepoch, (uint32_t*)c->err.p, c->stream, &c->prof), "count");
+                              ctr + kCtrCount, c->mepoch, (uint32_t*)c->err.p, c->akeys.p, (uint8_t*)c->asign.p,
+                              c->stream, &c->prof), "count");
   QCHK(ensure(c, c->img_seg, (S + 1) * 8));
   uint32_t e = 0;
   // Bound path: with a small fan-out bound f, T_img <= f * T_in, so the image tilings are
@@ -744,8 +750,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->iw[0], std::max<uint64_t>(T_img, 1) * wbt));
   QCHK(ensure(c, c->ik[1], std::max<uint64_t>(T_img, 1) * eb));
   QCHK(ensure(c, c->iw[1], std::max<uint64_t>(T_img, 1) * wbt));
-  HIPCHK(c, launch_expand(c->KC, c->WP, k_in, w_in, T_in, (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent,
-                          seg_in, any_tables, e_bytes, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream,
+  HIPCHK(c, launch_expand(c->KC, c->WP, c->akeys.p, (const uint8_t*)c->asign.p, w_in, T_in,
+                          (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent, seg_in, any_b_tables, e_bytes, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream,
                           &c->prof), "expand");
   // ---- segment-local LSD radix sort of the images
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
@@ -848,7 +854,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     // again; the next rounds use global passes only for a while
     c->redo_cooldown = 8;
     c->st.sort_redos += 1;
-    HIPCHK(c, launch_round_prep((uint32_t*)c->err.p, ctr, 256, nullptr, 0, c->stream), "prep");
+    HIPCHK(c, launch_round_prep((uint32_t*)c->err.p, ctr, 256, (uint32_t*)c->ghist.p, nh, c->stream), "prep");
     void* const kk2[2] = {c->ik[pre_chunk].p, c->ik[pre_chunk ^ 1].p};
     void* const ww2[2] = {c->iw[pre_chunk].p, c->iw[pre_chunk ^ 1].p};
     int cur2 = 0;
@@ -856,7 +862,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       HIPCHK(c, launch_fill_u64((uint64_t*)c->sstatus.p, c->sstatus.bytes / 8, 0ull, c->stream), "clear status");
       c->epoch = 0;
     }
-    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk2, ww2, T_img, key_bits, 0, false, tl, (const uint64_t*)c->img_seg.p,
+    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk2, ww2, T_img, key_bits, 0, true, tl, (const uint64_t*)c->img_seg.p,
                                 (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr, &c->epoch, (uint32_t*)c->err.p,
                                 &cur2, c->stream, &c->prof), "sort");
     cur = pre_chunk ^ cur2;
@@ -1714,7 +1720,7 @@ void qimax_destroy(qimax_ctx* c) {
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
                     &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
-                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->result, &c->ptab};
+                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->result, &c->ptab, &c->akeys, &c->asign};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 2; ++i)

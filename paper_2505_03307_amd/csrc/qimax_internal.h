@@ -158,11 +158,13 @@ hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, u
                        hipStream_t s, Prof* prof = nullptr);
 
 // Fan-out count fused with its scan (single sweep with decoupled look-back over the tiles of
-// tl, claimed through *ctr): off[i] = first image of input term i, off[T] = image count.
-// status: tl.n_blocks words whose epoch field differs from `epoch`.
+// tl, claimed through *ctr): off[i] = first image of input term i, off[T] = image count;
+// akeys[i] / asign[i] = the term's image under its pass's A chain and that image's sign (the
+// expand kernel starts from them). status: tl.n_blocks words whose epoch field differs from
+// `epoch`.
 hipError_t launch_count_scan(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
                              const uint32_t* seg_entry, uint64_t* off, uint64_t* status, uint32_t* ctr, uint64_t epoch,
-                             uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+                             uint32_t* err, void* akeys, uint8_t* asign, hipStream_t s, Prof* prof = nullptr);
 
 // out[i] = exclusive prefix sum of in[0..i-1] for i in [0, N]; out has N+1 entries.
 // tmp must hold scan_tmp_words(N) uint64 words.
@@ -178,7 +180,10 @@ hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint6
 
 // Images of each tile of tl (segment-aligned, at most kExpandTile each). any_tables: some
 // entry uses chain tables (sizes the dynamic LDS).
-hipError_t launch_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const uint64_t* off,
+// keys/asign: the input terms' images under the A chain and their signs (from the count);
+// any_tables: some entry has a B-chain table.
+hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign, const void* w, uint64_t T_in,
+                         const uint64_t* off,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
                          const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
                          uint32_t* err, hipStream_t s, Prof* prof = nullptr);
@@ -197,7 +202,8 @@ hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_i
 // status: n_blocks*256 u64 (zeroed when allocated); tile_ctr: n_pass*kXcds u32, zero on
 // entry; *epoch is advanced per digit pass.
 // p_begin: first digit pass (the passes p_begin .. n_pass-1 run; p_begin > 0 groups the
-// segments by their top digits only); upsweep: compute ghist first (else it is current).
+// segments by their top digits only); upsweep: compute ghist for those passes first (else
+// it is current).
 hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[2], uint64_t T, uint32_t key_bits,
                              uint32_t p_begin, bool upsweep, const Tiling& tl, const uint64_t* seg_off,
                              uint32_t* ghist, uint64_t* status, uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err,
