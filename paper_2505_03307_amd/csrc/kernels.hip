@@ -810,22 +810,26 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
 // After stable global passes over the top m digits, every segment is grouped into buckets of
 // equal top digits, in order. Chunk c starts at the first bucket boundary at or after the
 // start of nominal tile c (the segment start for its first tile), so chunks are runs of whole
-// buckets; each chunk (at most kChunkCap elements) is sorted in LDS by the full key with
-// stable 8-bit passes, or by the low digits only when it holds one bucket, which completes a
-// stable sort of the segment. A bucket too large for a chunk raises kErrRedo (not an error:
-// the caller sorts the round again with global passes only).
+// buckets; each chunk (at most kChunkCap elements) is sorted in LDS, stably, which completes a
+// stable sort of the segment: stable 8-bit passes bring equal top m+1 digits together within
+// each bucket, and the resulting small groups are sorted by insertion. A bucket too large for
+// a chunk raises kErrRedo (not an error: the caller sorts the round again with global passes
+// only).
 constexpr int kChunkBlock = 512;  // threads of a chunk-local sort (8 waves)
 template <typename K, typename W>
-__global__ void __launch_bounds__(kChunkBlock) k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in,
+__global__ void __launch_bounds__(kChunkBlock) __attribute__((amdgpu_waves_per_eu(4))) k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in,
                                                     K* __restrict__ keys_out, W* __restrict__ w_out, Tiling tc,
                                                     uint32_t n_pass, uint32_t m, uint32_t* err) {
   constexpr int kItems = kChunkCap / kChunkBlock, kWaves = kChunkBlock / 64;
   __shared__ K sk[kChunkCap];
   __shared__ uint16_t sidx[kChunkCap];
+  __shared__ uint16_t sbk[kChunkCap];
   __shared__ __align__(16) uint32_t wrun[2][kWaves][kRadix];
   __shared__ uint32_t wdummy[kWaves][64];
   __shared__ __align__(16) uint32_t dbase[kWaves][kRadix];
+  __shared__ uint64_t scan_sh[kWaves];
   __shared__ uint64_t cb[2];
+  __shared__ uint32_t nb_sh, fallback_sh;
   const uint32_t blk = blockIdx.x;
   if (tc.n_dev && blk >= *tc.n_dev) return;
   const uint64_t a = tc.blk_begin[blk], b = tc.blk_end[blk];
@@ -870,8 +874,6 @@ __global__ void __launch_bounds__(kChunkBlock) k_chunk_sort(const K* __restrict_
     }
   }
   __syncthreads();
-  const bool one_bucket = top(sk[0]) == top(sk[n - 1]);
-  const uint32_t p_end = one_bucket ? n_pass - m : n_pass;
   // the n elements in equal wave spans of whole 64-element rounds
   const uint32_t span = (n + kWaves * 64 - 1) / (kWaves * 64) * 64, nr = span / 64;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -890,22 +892,48 @@ __global__ void __launch_bounds__(kChunkBlock) k_chunk_sort(const K* __restrict_
   // per-wave digit counters, double-buffered by pass parity (a wave clears its row of the
   // other buffer for the next pass), so that a pass needs only two block barriers
   for (int i = threadIdx.x; i < 2 * kWaves * kRadix; i += kChunkBlock) (&wrun[0][0][0])[i] = 0;
+  // bucket of every element (runs of equal top digits, numbered in order): heads, block scan
+  {
+    const uint32_t j0 = threadIdx.x * kItems;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int t = 0; t < kItems; ++t) {
+      const uint32_t j = j0 + t;
+      if (j < n && (j == 0 || top(sk[j]) != top(sk[j - 1]))) ++cnt;
+    }
+    uint64_t tot;
+    uint32_t id = (uint32_t)block_excl_scan<kChunkBlock>(cnt, scan_sh, &tot);
+#pragma unroll
+    for (int t = 0; t < kItems; ++t) {
+      const uint32_t j = j0 + t;
+      if (j < n) {
+        if (j == 0 || top(sk[j]) != top(sk[j - 1])) ++id;
+        sbk[j] = (uint16_t)(id - 1);
+      }
+    }
+    if (threadIdx.x == 0) nb_sh = (uint32_t)tot;
+  }
   __syncthreads();
-  for (uint32_t p = 0; p < p_end; ++p) {
-    const int pb = p & 1;
+  const uint32_t nb = nb_sh;
+  // One stable LDS radix pass: the digit of an element comes from dig(key, bucket); key,
+  // original index and bucket move together.
+  uint32_t pass_no = 0;
+  auto radix_pass = [&](auto&& dig) {
+    const int pb = pass_no++ & 1;
     K key[kItems];
-    uint16_t ix[kItems];
+    uint16_t ix[kItems], bk[kItems];
     uint32_t rank[kItems], pk[kItems];  // pk: digit | leader lane << 8 | lanes below with that digit << 16
     // every read of the pass first (clamped indices), then the ranking
     rounds([&](int r) {
       const uint32_t li = min(wid * span + r * 64 + lane, n - 1);
       key[r] = sk[li];
       ix[r] = sidx[li];
+      bk[r] = sbk[li];
     });
     rounds([&](int r) {
       const uint32_t li = wid * span + r * 64 + lane;  // stable order: wave span, round, lane
       const bool valid = (uint32_t)r < nr && li < n;    // rounds past nr belong to the next wave
-      const uint32_t d = (uint32_t)(key[r] >> (8u * p)) & (kRadix - 1);
+      const uint32_t d = dig(key[r], (uint32_t)bk[r]) & (kRadix - 1);
       // lanes whose digit differs from this lane's in some bit: OR of (ballot of the bit) XOR
       // (this lane's bit spread over the mask)
       const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
@@ -957,8 +985,57 @@ __global__ void __launch_bounds__(kChunkBlock) k_chunk_sort(const K* __restrict_
         const uint32_t dst = dbase[wid][pk[r] & 255u] + rank[r];
         sk[dst] = key[r];
         sidx[dst] = ix[r];
+        sbk[dst] = bk[r];
       }
     });
+    __syncthreads();
+  };
+  // Few buckets: one pass by the digit just below the bucket digits, one by the bucket number
+  // (skipped for a single bucket), which leaves groups of equal top m+1 digits in order.
+  // Many buckets (fewer than 16 elements each on average): the buckets are the groups. The
+  // groups are then sorted by insertion (stable); a group above kMaxGroup elements sends the
+  // chunk through stable passes over every digit instead (same order from here).
+  constexpr uint32_t kMaxGroup = 32;
+  const bool two_pass = nb <= (uint32_t)kRadix && m < n_pass;
+  const uint32_t g_shift = two_pass ? top_shift - 8u : top_shift;
+  auto gkey = [&](K key) -> K { return (two_pass || m > 0) ? (K)(key >> g_shift) : (K)0; };
+  if (two_pass) {
+    radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> g_shift); });
+    if (nb > 1) radix_pass([&](K, uint32_t bkt) { return bkt; });
+  }
+  if (threadIdx.x == 0) fallback_sh = 0;
+  __syncthreads();
+  // group lengths at their heads (sbk is free now), all found before any group is sorted
+  for (uint32_t j = threadIdx.x; j < n; j += kChunkBlock) {
+    uint32_t len = 0;
+    if (j == 0 || gkey(sk[j]) != gkey(sk[j - 1])) {
+      const K g = gkey(sk[j]);
+      uint32_t e = j + 1;
+      while (e < n && e - j <= kMaxGroup && gkey(sk[e]) == g) ++e;
+      len = e - j;
+      if (len > kMaxGroup) fallback_sh = 1;
+    }
+    sbk[j] = (uint16_t)len;
+  }
+  __syncthreads();
+  if (fallback_sh) {
+    for (uint32_t p = 0; p < n_pass; ++p) radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> (8u * p)); });
+  } else {
+    for (uint32_t j = threadIdx.x; j < n; j += kChunkBlock) {
+      const uint32_t e = j + sbk[j];
+      for (uint32_t i = j + 1; i < e; ++i) {  // insertion sort of the group [j, e), stable
+        const K kv = sk[i];
+        const uint16_t iv = sidx[i];
+        uint32_t t = i;
+        while (t > j && sk[t - 1] > kv) {
+          sk[t] = sk[t - 1];
+          sidx[t] = sidx[t - 1];
+          --t;
+        }
+        sk[t] = kv;
+        sidx[t] = iv;
+      }
+    }
     __syncthreads();
   }
 #pragma unroll
