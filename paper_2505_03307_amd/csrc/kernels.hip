@@ -806,6 +806,55 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
   }
 }
 
+// --------------------------------------------------------------- run accumulators
+// Equal keys are adjacent inside a segment after the sort. The thread that owns the
+// first element of a run (its head) sums the run in array order (deterministic), then
+// keeps it when |sum| > thr. FP32 runs are summed with the TwoSum-compensated
+// (Kahan-Babuska) recurrence, or in FP64 and rounded once.
+template <typename W>
+struct RunSum {
+  W s = 0;
+  W c = 0;
+  __device__ __forceinline__ void add(W x) {
+    const W t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ W value() const { return s + c; }
+};
+
+template <typename W>
+struct PlainSum {  // in W, array order
+  W s = 0;
+  __device__ __forceinline__ void add(W x) { s += x; }
+  __device__ __forceinline__ W value() const { return s; }
+};
+
+struct F64Sum {  // FP32 weights accumulated in FP64, rounded once
+  double s = 0;
+  __device__ __forceinline__ void add(float x) { s += (double)x; }
+  __device__ __forceinline__ float value() const { return (float)s; }
+};
+
+// kMode 0: count the kept runs of each tile (blk_cnt); 1: write them at the scanned
+// offsets (blk_off); 2: single sweep - tiles are claimed in order, each publishes its
+// count and looks back over the earlier tiles for its output offset (written to blk_off,
+// with the total at blk_off[n_blocks]), then writes.
+// After the merge (one block): the segment output offsets seg_off_out[s] = blk_off[seg_blk[s]]
+// (all 0 when there are no tiles) and the packed readback area (see MergeFin).
+__global__ void k_merge_publish(Tiling tl, const uint64_t* __restrict__ blk_off, uint64_t* __restrict__ seg_off_out,
+                                MergeFin fin, const uint32_t* __restrict__ err, int none) {
+  const uint32_t S = tl.n_segs;
+  for (uint32_t s = threadIdx.x; s <= S; s += blockDim.x) {
+    const uint64_t v = none ? 0ull : blk_off[tl.seg_blk[s]];
+    seg_off_out[s] = v;
+    fin.result[s] = v;
+    fin.result[S + 1 + s] = fin.img_seg[s];
+  }
+  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err;
+}
+
+
 // ----------------------------------------------------------------- chunk-local sort
 // After stable global passes over the top m digits, every segment is grouped into buckets of
 // equal top digits, in order. Chunk c starts at the first bucket boundary at or after the
@@ -817,9 +866,11 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
 // only).
 constexpr int kChunkBlock = 512;  // threads of a chunk-local sort (8 waves)
 template <typename K, typename W>
-__global__ void __launch_bounds__(kChunkBlock) __attribute__((amdgpu_waves_per_eu(4))) k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in,
-                                                    K* __restrict__ keys_out, W* __restrict__ w_out, Tiling tc,
-                                                    uint32_t n_pass, uint32_t m, uint32_t* err) {
+__global__ void __launch_bounds__(kChunkBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __restrict__ keys_out, W* __restrict__ w_out,
+             Tiling tc, uint32_t n_pass, uint32_t m, const PassArgs* __restrict__ pas,
+             const uint32_t* __restrict__ seg_entry, int fp64_acc, uint32_t* __restrict__ chunk_cnt,
+             uint64_t* __restrict__ chunk_start, uint32_t* err) {
   constexpr int kItems = kChunkCap / kChunkBlock, kWaves = kChunkBlock / 64;
   __shared__ K sk[kChunkCap];
   __shared__ uint16_t sidx[kChunkCap];
@@ -832,8 +883,17 @@ __global__ void __launch_bounds__(kChunkBlock) __attribute__((amdgpu_waves_per_e
   __shared__ uint32_t nb_sh, fallback_sh;
   const uint32_t blk = blockIdx.x;
   if (tc.n_dev && blk >= *tc.n_dev) return;
+  auto none = [&]() {  // this chunk keeps nothing (empty, or handed to the fallback)
+    if (threadIdx.x == 0) {
+      chunk_cnt[blk] = 0;
+      chunk_start[blk] = 0;
+    }
+  };
   const uint64_t a = tc.blk_begin[blk], b = tc.blk_end[blk];
-  if (a >= b) return;
+  if (a >= b) {
+    none();
+    return;
+  }
   const uint32_t s = tc.blk_seg[blk];
   const uint64_t seg_lo = tc.blk_begin[tc.seg_blk[s]], seg_hi = tc.blk_end[tc.seg_blk[s + 1] - 1];
   const uint32_t top_shift = 8u * (n_pass - m);
@@ -853,9 +913,13 @@ __global__ void __launch_bounds__(kChunkBlock) __attribute__((amdgpu_waves_per_e
   }
   __syncthreads();
   const uint64_t c0 = cb[0], c1 = cb[1];
-  if (c1 <= c0) return;  // every element of the tile belongs to an earlier chunk
+  if (c1 <= c0) {  // every element of the tile belongs to an earlier chunk
+    none();
+    return;
+  }
   if (c1 - c0 > (uint64_t)kChunkCap) {
     if (threadIdx.x == 0) atomicOr(err, kErrRedo);
+    none();
     return;
   }
   const uint32_t n = (uint32_t)(c1 - c0);
@@ -1038,13 +1102,110 @@ __global__ void __launch_bounds__(kChunkBlock) __attribute__((amdgpu_waves_per_e
     }
     __syncthreads();
   }
+  // Merge in place: runs of equal keys lie in one chunk (equal keys share their top digits).
+  // The thread owning a run's head sums it in array order, keeps it when |sum| > thr; the kept
+  // runs are compacted to the front of the chunk's range and counted for the publishing scan.
+  const double thr = pas[seg_entry[s]].thr;
+  const uint32_t j0 = threadIdx.x * kItems;  // this thread's run of sorted positions
+  W wr[kItems], sums[kItems];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t j = r * kChunkBlock + threadIdx.x;
-    if (j < n) {
-      keys_out[c0 + j] = sk[j];
-      w_out[c0 + j] = w_in[c0 + sidx[j]];
+  for (int t = 0; t < kItems; ++t) wr[t] = w_in[c0 + sidx[min(j0 + t, n - 1)]];  // every gather in flight
+  uint32_t keep_mask = 0, keep = 0;
+  auto run_sum = [&](auto acc, int t) {
+    const uint32_t j = j0 + t;
+    acc.add(wr[t]);
+#pragma unroll
+    for (int u = t + 1; u < kItems; ++u) {
+      if (j0 + u >= n || sk[j0 + u] != sk[j]) return acc.value();
+      acc.add(wr[u]);
     }
+    for (uint32_t i = j0 + kItems; i < n && sk[i] == sk[j]; ++i) acc.add(w_in[c0 + sidx[i]]);
+    return acc.value();
+  };
+#pragma unroll
+  for (int t = 0; t < kItems; ++t) {
+    const uint32_t j = j0 + t;
+    sums[t] = 0;
+    if (j >= n || (j > 0 && sk[j] == sk[j - 1])) continue;
+    W v;
+    if constexpr (sizeof(W) == 8) v = run_sum(PlainSum<W>{}, t);
+    else v = fp64_acc ? run_sum(F64Sum{}, t) : run_sum(RunSum<float>{}, t);
+    if (fabs((double)v) > thr) {
+      sums[t] = v;
+      keep_mask |= 1u << t;
+      ++keep;
+    }
+  }
+  uint64_t tot;
+  uint64_t o = c0 + block_excl_scan<kChunkBlock>(keep, scan_sh, &tot);
+#pragma unroll
+  for (int t = 0; t < kItems; ++t) {
+    if (!(keep_mask & (1u << t))) continue;
+    keys_out[o] = sk[j0 + t];
+    w_out[o] = sums[t];
+    ++o;
+  }
+  if (threadIdx.x == 0) {
+    chunk_cnt[blk] = (uint32_t)tot;
+    chunk_start[blk] = c0;
+  }
+}
+
+// After the chunk-local sort and merge (one block): chunk_off = exclusive scan of the kept
+// counts of the n_chunks chunks (n_dev or n_blocks of tc), the segment output offsets
+// seg_off_out[s] = chunk_off[seg_blk[s]], and the packed readback area (see MergeFin); a total
+// above out_cap is reported in the error word there (the compaction then writes nothing).
+__global__ void __launch_bounds__(512) k_chunk_publish(Tiling tc, const uint32_t* __restrict__ chunk_cnt,
+                                                       uint64_t* __restrict__ chunk_off,
+                                                       uint64_t* __restrict__ seg_off_out, MergeFin fin,
+                                                       uint64_t out_cap, const uint32_t* __restrict__ err) {
+  __shared__ uint64_t sh[8];
+  __shared__ uint64_t carry_sh;
+  const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
+  if (threadIdx.x == 0) carry_sh = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < nc; base += 512) {
+    const uint32_t i = base + threadIdx.x;
+    const uint64_t v = i < nc ? chunk_cnt[i] : 0;
+    uint64_t tot;
+    const uint64_t pre = block_excl_scan<512>(v, sh, &tot);
+    const uint64_t carry = carry_sh;
+    if (i < nc) chunk_off[i] = carry + pre;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_sh = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) chunk_off[nc] = carry_sh;
+  __syncthreads();
+  const uint32_t S = tc.n_segs;
+  for (uint32_t s = threadIdx.x; s <= S; s += 512) {
+    const uint64_t v = chunk_off[min(tc.seg_blk[s], nc)];
+    seg_off_out[s] = v;
+    fin.result[s] = v;
+    fin.result[S + 1 + s] = fin.img_seg[s];
+  }
+  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (carry_sh > out_cap ? kErrIndex | kErrMerge : 0u);
+}
+
+// Moves every chunk's kept runs from the front of its range to their output offset.
+template <typename K, typename W>
+__global__ void __launch_bounds__(256) k_chunk_compact(const K* __restrict__ keys_in, const W* __restrict__ w_in,
+                                                       K* __restrict__ keys_out, W* __restrict__ w_out, Tiling tc,
+                                                       const uint32_t* __restrict__ chunk_cnt,
+                                                       const uint64_t* __restrict__ chunk_start,
+                                                       const uint64_t* __restrict__ chunk_off, uint64_t out_cap,
+                                                       uint32_t* err) {
+  const uint32_t blk = blockIdx.x;
+  if (tc.n_dev && blk >= *tc.n_dev) return;
+  const uint32_t cnt = chunk_cnt[blk];
+  const uint64_t src = chunk_start[blk], dst = chunk_off[blk];
+  if (dst + cnt > out_cap) {
+    if (threadIdx.x == 0 && cnt) atomicOr(err, kErrIndex | kErrMerge);
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+    keys_out[dst + i] = keys_in[src + i];
+    w_out[dst + i] = w_in[src + i];
   }
 }
 
@@ -1095,22 +1256,6 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
 }
 
 // ------------------------------------------------------------------------------ merge
-// Equal keys are adjacent inside a segment after the sort. The thread that owns the
-// first element of a run (its head) sums the run in array order (deterministic), then
-// keeps it when |sum| > thr. FP32 runs are summed with the TwoSum-compensated
-// (Kahan-Babuska) recurrence, or in FP64 and rounded once.
-template <typename W>
-struct RunSum {
-  W s = 0;
-  W c = 0;
-  __device__ __forceinline__ void add(W x) {
-    const W t = s + x;
-    if (fabs(s) >= fabs(x)) c += (s - t) + x; else c += (x - t) + s;
-    s = t;
-  }
-  __device__ __forceinline__ W value() const { return s + c; }
-};
-
 // Sum of a run starting at tile-local index li: from the staged tile (key_at / sw) while the
 // run stays inside the tile, then from global memory up to the segment end: the elements are
 // added in array order whatever the tiling, so results do not depend on it.
@@ -1125,37 +1270,6 @@ __device__ __forceinline__ W run_sum_tile(const KeyAt& key_at, const W* sw, uint
   if (j == n_tile)
     for (uint64_t g = begin + j; g < seg_end && keys[g] == key; ++g) a.add(w[g]);
   return a.value();
-}
-
-template <typename W>
-struct PlainSum {  // in W, array order
-  W s = 0;
-  __device__ __forceinline__ void add(W x) { s += x; }
-  __device__ __forceinline__ W value() const { return s; }
-};
-
-struct F64Sum {  // FP32 weights accumulated in FP64, rounded once
-  double s = 0;
-  __device__ __forceinline__ void add(float x) { s += (double)x; }
-  __device__ __forceinline__ float value() const { return (float)s; }
-};
-
-// kMode 0: count the kept runs of each tile (blk_cnt); 1: write them at the scanned
-// offsets (blk_off); 2: single sweep - tiles are claimed in order, each publishes its
-// count and looks back over the earlier tiles for its output offset (written to blk_off,
-// with the total at blk_off[n_blocks]), then writes.
-// After the merge (one block): the segment output offsets seg_off_out[s] = blk_off[seg_blk[s]]
-// (all 0 when there are no tiles) and the packed readback area (see MergeFin).
-__global__ void k_merge_publish(Tiling tl, const uint64_t* __restrict__ blk_off, uint64_t* __restrict__ seg_off_out,
-                                MergeFin fin, const uint32_t* __restrict__ err, int none) {
-  const uint32_t S = tl.n_segs;
-  for (uint32_t s = threadIdx.x; s <= S; s += blockDim.x) {
-    const uint64_t v = none ? 0ull : blk_off[tl.seg_blk[s]];
-    seg_off_out[s] = v;
-    fin.result[s] = v;
-    fin.result[S + 1 + s] = fin.img_seg[s];
-  }
-  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err;
 }
 
 template <typename K, typename W, int kMode>
@@ -1620,21 +1734,43 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
   return hipGetLastError();
 }
 
-hipError_t launch_chunk_sort(int KC, int WP, const void* keys_in, const void* w_in, void* keys_out, void* w_out,
-                             uint64_t T, const Tiling& tc, uint32_t n_pass, uint32_t m, uint32_t* err, hipStream_t s,
-                             Prof* prof) {
-  if (T == 0 || tc.n_blocks == 0) return hipSuccess;
+hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* tmp_keys,
+                                   void* tmp_w, void* keys_out, void* w_out, uint64_t T, const Tiling& tc,
+                                   uint32_t n_pass, uint32_t m, const PassArgs* pas, const uint32_t* seg_entry,
+                                   uint32_t* chunk_cnt, uint64_t* chunk_start, uint64_t* chunk_off,
+                                   uint64_t* seg_off_out, const MergeFin& fin, uint32_t* err, hipStream_t s,
+                                   Prof* prof) {
+  if (tc.n_blocks == 0) {
+    k_merge_publish<<<1, 256, 0, s>>>(tc, nullptr, seg_off_out, fin, err, 1);
+    return hipGetLastError();
+  }
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   hipEvent_t ev = prof_begin(prof, s, kKChunkSort);
   QIMAX_DISPATCH_K(KC, {
     if (WP == 64)
-      k_chunk_sort<K, double><<<tc.n_blocks, kChunkBlock, 0, s>>>((const K*)keys_in, (const double*)w_in, (K*)keys_out,
-                                                          (double*)w_out, tc, n_pass, m, err);
+      k_chunk_sort<K, double><<<tc.n_blocks, kChunkBlock, 0, s>>>(
+          (const K*)keys_in, (const double*)w_in, (K*)tmp_keys, (double*)tmp_w, tc, n_pass, m, pas, seg_entry,
+          fp64_acc, chunk_cnt, chunk_start, err);
     else
-      k_chunk_sort<K, float><<<tc.n_blocks, kChunkBlock, 0, s>>>((const K*)keys_in, (const float*)w_in, (K*)keys_out,
-                                                         (float*)w_out, tc, n_pass, m, err);
+      k_chunk_sort<K, float><<<tc.n_blocks, kChunkBlock, 0, s>>>(
+          (const K*)keys_in, (const float*)w_in, (K*)tmp_keys, (float*)tmp_w, tc, n_pass, m, pas, seg_entry,
+          fp64_acc, chunk_cnt, chunk_start, err);
   });
-  prof_end(prof, s, ev, kKChunkSort, 2.0 * (kb + wb) * (double)T);
+  // bytes: every image read; the kept terms' bytes are added by the caller once known
+  prof_end(prof, s, ev, kKChunkSort, (kb + wb) * (double)T);
+  k_chunk_publish<<<1, 512, 0, s>>>(tc, chunk_cnt, chunk_off, seg_off_out, fin, T, err);
+  ev = prof_begin(prof, s, kKMergeWrite);
+  QIMAX_DISPATCH_K(KC, {
+    if (WP == 64)
+      k_chunk_compact<K, double><<<tc.n_blocks, 256, 0, s>>>((const K*)tmp_keys, (const double*)tmp_w, (K*)keys_out,
+                                                             (double*)w_out, tc, chunk_cnt, chunk_start, chunk_off, T,
+                                                             err);
+    else
+      k_chunk_compact<K, float><<<tc.n_blocks, 256, 0, s>>>((const K*)tmp_keys, (const float*)tmp_w, (K*)keys_out,
+                                                            (float*)w_out, tc, chunk_cnt, chunk_start, chunk_off, T,
+                                                            err);
+  });
+  prof_end(prof, s, ev, kKMergeWrite, 0.0);
   return hipGetLastError();
 }
 

@@ -230,6 +230,7 @@ struct qimax_ctx {
   DevBuf desc, desc2, err, f64tmp;
   DevBuf ptab;  // chain tables of a whole call, compiled in one launch
   DevBuf akeys, asign;  // input terms after their pass's A chain, and the signs (count -> expand)
+  DevBuf chunk_cnt, chunk_start, chunk_off;  // chunk-local merge: kept runs per chunk
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
   DevBuf mstatus;  // single-sweep count and merge state (one word per tile)
@@ -814,13 +815,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, n_pass - m_top, true, tl,
                                 (const uint64_t*)c->img_seg.p, (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr,
                                 &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof), "sort");
-    if (m_top < n_pass) {
-      pre_chunk = cur;
-      HIPCHK(c, launch_chunk_sort(c->KC, c->WP, c->ik[cur].p, c->iw[cur].p, c->ik[cur ^ 1].p, c->iw[cur ^ 1].p, T_img,
-                                  tl_exp, n_pass, m_top, (uint32_t*)c->err.p, c->stream, &c->prof), "chunk sort");
-      cur ^= 1;
-    }
-    if (tune_timed) HIPCHK(c, hipEventRecord(c->tune_ev[1], c->stream), "tune event");
+    if (m_top < n_pass) pre_chunk = cur;  // the chunk-local sort runs with the merge
   }
   // ---- segmented reduce + prune + compaction into the pass output slot
   QCHK(ensure(c, c->pk[slot], std::max<uint64_t>(T_img, 1) * eb));
@@ -830,24 +825,38 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->blk_off, (size_t)(tl.n_blocks + 1) * 8));
   QCHK(ensure(c, c->result, (size_t)(2 * S + 3) * 8));
   MergeFin fin{(const uint64_t*)c->img_seg.p, (uint64_t*)c->result.p};
+  bool chunk_path = pre_chunk >= 0;  // chunk-local sort fused with the merge
   auto merge_and_read = [&]() -> qimax_status {
-    uint64_t* mstatus = nullptr;
-    if (sweep) {
-      QCHK(status_words(tl.n_blocks));
-      c->mepoch += 1;
-      mstatus = (uint64_t*)c->mstatus.p;
+    if (chunk_path) {
+      const size_t nc = std::max<uint32_t>(tl_exp.n_blocks, 1);
+      QCHK(ensure(c, c->chunk_cnt, nc * 4));
+      QCHK(ensure(c, c->chunk_start, nc * 8));
+      QCHK(ensure(c, c->chunk_off, (nc + 1) * 8));
+      HIPCHK(c, launch_chunk_sort_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, c->ik[cur ^ 1].p,
+                                        c->iw[cur ^ 1].p, c->pk[slot].p, c->pw[slot].p, T_img, tl_exp, n_pass, m_top,
+                                        pas, sent, (uint32_t*)c->chunk_cnt.p, (uint64_t*)c->chunk_start.p,
+                                        (uint64_t*)c->chunk_off.p, (uint64_t*)c->pseg[slot].p, fin,
+                                        (uint32_t*)c->err.p, c->stream, &c->prof), "chunk sort");
+    } else {
+      uint64_t* mstatus = nullptr;
+      if (sweep) {
+        QCHK(status_words(tl.n_blocks));
+        c->mepoch += 1;
+        mstatus = (uint64_t*)c->mstatus.p;
+      }
+      HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, pas, sent,
+                             c->pk[slot].p, c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
+                             (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, ctr + kCtrMerge, c->mepoch,
+                             (uint32_t*)c->err.p, sweep ? &fin : nullptr, c->stream, &c->prof), "merge");
     }
-    HIPCHK(c, launch_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, T_img, tl, pas, sent, c->pk[slot].p,
-                           c->pw[slot].p, T_img, (uint64_t*)c->pseg[slot].p, (uint32_t*)c->blk_cnt.p,
-                           (uint64_t*)c->blk_off.p, (uint64_t*)c->scan_tmp.p, mstatus, ctr + kCtrMerge, c->mepoch,
-                           (uint32_t*)c->err.p, sweep ? &fin : nullptr, c->stream, &c->prof), "merge");
+    if (tune_timed) HIPCHK(c, hipEventRecord(c->tune_ev[1], c->stream), "tune event");
     // ---- one readback: output offsets, image offsets, error word
     if (sweep) return readback(c, c->result.p, 2 * (size_t)S + 3, &e, /*err_packed=*/true);
     return readback(c, c->pseg[slot].p, S + 1, &e);
   };
   QCHK(merge_and_read());
   bool sorted_again = false;
-  if (e == kErrRedo && pre_chunk >= 0) {
+  if (e == kErrRedo && chunk_path) {
     sorted_again = true;
     // a bucket did not fit a chunk: sort the round again with global passes over every digit
     // (stable passes on the top-digit grouping give the same order as on the images) and merge
@@ -866,6 +875,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
                                 (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr, &c->epoch, (uint32_t*)c->err.p,
                                 &cur2, c->stream, &c->prof), "sort");
     cur = pre_chunk ^ cur2;
+    chunk_path = false;
+    tune_timed = false;
     QCHK(merge_and_read());
   }
   if (tune_timed) {  // the round has synchronised: both events are complete
@@ -902,11 +913,15 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       fix(kKExpand, (double)(eb + wbt) * d);
       fix(kKSortHist, (double)eb * d);
       fix(kKSortScatter, 2.0 * (double)(eb + wbt) * (sorted_again ? n_pass + m_top : m_top) * d);
-      if (m_top < n_pass) fix(kKChunkSort, 2.0 * (double)(eb + wbt) * d);
-      fix(kKMergeWrite, (double)(eb + wbt) * d);
+      if (m_top < n_pass) fix(kKChunkSort, (double)(eb + wbt) * d);
+      if (!chunk_path) fix(kKMergeWrite, (double)(eb + wbt) * d);
     }
   }
-  if (c->prof.on && ((c->prof.mask >> kKMergeWrite) & 1u)) c->prof.bytes[kKMergeWrite] += (double)T_out * (double)(eb + wbt);
+  if (c->prof.on) {  // the kept terms' bytes, known now
+    const double kept = (double)T_out * (double)(eb + wbt);
+    if ((c->prof.mask >> kKMergeWrite) & 1u) c->prof.bytes[kKMergeWrite] += chunk_path ? 2.0 * kept : kept;
+    if (chunk_path && ((c->prof.mask >> kKChunkSort) & 1u)) c->prof.bytes[kKChunkSort] += kept;
+  }
   // ---- bookkeeping: one update per output image of every operator (a Clifford operator
   // counts its terms, the expanding operator its images), attributed per entry
   if (upd) upd->assign(E, 0);
@@ -1720,7 +1735,8 @@ void qimax_destroy(qimax_ctx* c) {
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
                     &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
-                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->result, &c->ptab, &c->akeys, &c->asign};
+                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->result, &c->ptab, &c->akeys, &c->asign, &c->chunk_cnt, &c->chunk_start,
+                    &c->chunk_off};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 2; ++i)

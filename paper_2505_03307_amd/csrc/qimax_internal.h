@@ -209,12 +209,7 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
                              uint32_t* ghist, uint64_t* status, uint32_t* tile_ctr, uint64_t* epoch, uint32_t* err,
                              int* cur, hipStream_t s, Prof* prof = nullptr);
 
-// Chunk-local sort after the top m digit passes (see k_chunk_sort): nominal chunks are the
-// tiles of tc (at most kChunkCap/2 elements, segment-aligned); sorted data to keys_out/w_out
-// at the same positions. Sets kErrRedo when a bucket does not fit a chunk.
-hipError_t launch_chunk_sort(int KC, int WP, const void* keys_in, const void* w_in, void* keys_out, void* w_out,
-                             uint64_t T, const Tiling& tc, uint32_t n_pass, uint32_t m, uint32_t* err, hipStream_t s,
-                             Prof* prof = nullptr);
+
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 
 // Segmented sum of equal adjacent keys; keeps sums with |w| > thr (thr < 0 keeps
@@ -233,6 +228,20 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
                         uint64_t out_cap, uint64_t* seg_off_out, uint32_t* blk_cnt, uint64_t* blk_off, uint64_t* tmp,
                         uint64_t* status, uint32_t* tile_ctr, uint64_t epoch, uint32_t* err, const MergeFin* fin,
                         hipStream_t s, Prof* prof = nullptr);
+
+// Chunk-local sort and merge after the top m digit passes (see k_chunk_sort): nominal chunks
+// are the tiles of tc (at most kChunkCap/2 images, segment-aligned). Each chunk is sorted in
+// LDS, its runs of equal keys summed and pruned (|sum| > its pass's thr) and compacted into
+// tmp at the chunk's range; a one-block scan of the kept counts gives the output offsets,
+// seg_off_out and the packed readback area (fin); the kept runs then move to keys_out/w_out.
+// chunk_cnt / chunk_start: tc.n_blocks words; chunk_off: tc.n_blocks + 1. Sets kErrRedo when
+// a bucket does not fit a chunk (the outputs are then not valid).
+hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* tmp_keys,
+                                   void* tmp_w, void* keys_out, void* w_out, uint64_t T, const Tiling& tc,
+                                   uint32_t n_pass, uint32_t m, const PassArgs* pas, const uint32_t* seg_entry,
+                                   uint32_t* chunk_cnt, uint64_t* chunk_start, uint64_t* chunk_off,
+                                   uint64_t* seg_off_out, const MergeFin& fin, uint32_t* err, hipStream_t s,
+                                   Prof* prof = nullptr);
 
 // Compile chains of permutation ops into ChainTables, one job per chain (jobs in device memory).
 hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hipStream_t s, Prof* prof = nullptr);
