@@ -1862,7 +1862,8 @@ hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t*
 
 // Block i builds tiling i (segment-aligned tiles of at most job.tile images; cap tiles are
 // written, the ones past the actual count empty) from the image offsets of the segments,
-// so[s] = off[seg_in[s]]; block 0 also stores those offsets in img_seg.
+// so[s] = off[seg_in[s]] (so[s] = seg_in[s] when off is null: a tiling of the terms
+// themselves); block 0 also stores those offsets in img_seg unless it is null.
 __global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict__ off,
                                                      const uint64_t* __restrict__ seg_in, uint32_t S,
                                                      uint64_t* __restrict__ img_seg, TileJob2 j0, TileJob2 j1,
@@ -1871,7 +1872,7 @@ __global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict_
   const uint64_t tile = job.tile;
   const uint32_t cap = job.cap;
   uint32_t* __restrict__ seg_blk = job.seg_blk;
-  auto so = [&](uint32_t s) { return off[seg_in[s]]; };
+  auto so = [&](uint32_t s) { return off ? off[seg_in[s]] : seg_in[s]; };
   __shared__ uint64_t sh[4];
   __shared__ uint64_t carry_sh;
   if (threadIdx.x == 0) carry_sh = 0;
@@ -1882,7 +1883,7 @@ __global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict_
     if (s < S) {
       const uint64_t a = so(s), b = so(s + 1);
       len = b - a;
-      if (blockIdx.x == 0) {
+      if (blockIdx.x == 0 && img_seg) {
         img_seg[s] = a;
         if (s + 1 == S) img_seg[S] = b;
       }
@@ -1896,7 +1897,7 @@ __global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict_
     if (threadIdx.x == 0) carry_sh = carry + tot;
     __syncthreads();
   }
-  if (S == 0 && blockIdx.x == 0 && threadIdx.x == 0) img_seg[0] = so(0);
+  if (S == 0 && blockIdx.x == 0 && threadIdx.x == 0 && img_seg) img_seg[0] = so(0);
   const uint64_t total_img = so(S);
   // more tiles or images than the capacity: the bound was not an upper bound (tiles are
   // clamped below so that nothing reads past the buffers; the pass reports the error)
@@ -1949,6 +1950,12 @@ __global__ void k_copy_u64(const uint64_t* __restrict__ in, uint64_t* __restrict
 hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint32_t S, uint64_t* img_seg,
                               const TileJob2& j0, const TileJob2& j1, uint64_t limit, uint32_t* err, hipStream_t s) {
   k_make_tiles2<<<2, 256, 0, s>>>(off, seg_in, S, img_seg, j0, j1, limit, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_make_tiles_terms(const uint64_t* seg_in, uint32_t S, const TileJob2& job, uint64_t T,
+                                   uint32_t* err, hipStream_t s) {
+  k_make_tiles2<<<1, 256, 0, s>>>(nullptr, seg_in, S, nullptr, job, job, T, err);
   return hipGetLastError();
 }
 

@@ -12,9 +12,11 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <new>
 #include <random>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/qimax.h"
@@ -29,6 +31,46 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// A transfer matrix R[out][in], immutable once made and shared by every copy of an
+// operator (all CX and all CZ gates share one each), with its permutation table: per input
+// index, the last nonzero row and its sign (out | 16 * negative), eight per word.
+struct PtmData {
+  std::vector<double> v;
+  uint64_t lo = 0, hi = 0;
+};
+struct Ptm {
+  std::shared_ptr<const PtmData> p;
+  void assign(const double* a, const double* b) {
+    auto d = std::make_shared<PtmData>();
+    d->v.assign(a, b);
+    const int dim = (int)std::lround(std::sqrt((double)d->v.size()));
+    for (int in = 0; in < dim; ++in) {
+      int out = 0;
+      bool neg = false;
+      for (int r = 0; r < dim; ++r) {
+        const double x = d->v[r * dim + in];
+        if (x != 0.0) {
+          out = r;
+          neg = x < 0;
+        }
+      }
+      const uint64_t e = (uint64_t)(out | (neg ? 16 : 0));
+      if (in < 8) d->lo |= e << (8 * in);
+      else d->hi |= e << (8 * (in - 8));
+    }
+    p = std::move(d);
+  }
+  const std::vector<double>& vec() const {
+    static const std::vector<double> none;
+    return p ? p->v : none;
+  }
+  operator const std::vector<double>&() const { return vec(); }
+  double operator[](size_t i) const { return p->v[i]; }
+  size_t size() const { return vec().size(); }
+  std::vector<double>::const_iterator begin() const { return vec().begin(); }
+  std::vector<double>::const_iterator end() const { return vec().end(); }
+};
+
 // One operator on the host: PTM R[out][in] (dim 4 or 16), its wires and its operator
 // group (the index of the U_k / V_k run it belongs to).
 struct HostOp {
@@ -39,7 +81,7 @@ struct HostOp {
   bool perm = false;
   bool conj = false;  // a signed permutation that is a conjugation by a unitary (multiplicative)
   uint64_t mask = 0;  // wires touched
-  std::vector<double> R;  // dim*dim
+  Ptm R;              // dim*dim
 };
 
 // Autotuner state of one size class of rounds: the sort variants tried (0: heuristic number
@@ -235,7 +277,7 @@ struct qimax_ctx {
   uint64_t epoch = 0;
   DevBuf mstatus;  // single-sweep count and merge state (one word per tile)
   DevBuf result;   // packed readback of a round
-  DevBuf dtile[2];  // device-built image tilings (expand, sort/merge) of the bound path
+  DevBuf dtile[3];  // device-built tilings: images (expand, sort/merge; bound path), input terms
   uint64_t mepoch = 0;
   bool classic_sort = false;
   bool host_tiling = false;
@@ -246,7 +288,7 @@ struct qimax_ctx {
   bool autotune = true;       // choose among sort variants by measured time per size class
   std::map<uint32_t, TuneState> tune;
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
-  DevBuf gr_gate, gr_theta, gr_idx, gr_off, gr_out;
+  DevBuf gr_in, gr_out;  // grouping pass: gate codes, angles, chains in; composed PTMs out
   uint64_t* pinned = nullptr;  // small pinned host scratch
   size_t pinned_words = 0;
 
@@ -378,20 +420,8 @@ PermDesc make_perm(uint32_t n, const HostOp& op) {
   d.arity = (uint32_t)op.arity;
   d.pa = bitpos(n, op.q0);
   d.pb = op.arity == 2 ? bitpos(n, op.q1) : 0u;
-  for (int in = 0; in < op.dim; ++in) {
-    int out = 0;
-    bool neg = false;
-    for (int r = 0; r < op.dim; ++r) {
-      const double v = op.R[r * op.dim + in];
-      if (v != 0.0) {
-        out = r;
-        neg = v < 0;
-      }
-    }
-    const uint64_t e = (uint64_t)(out | (neg ? 16 : 0));
-    if (in < 8) d.lo |= e << (8 * in);
-    else d.hi |= e << (8 * (in - 8));
-  }
+  d.lo = op.R.p->lo;  // made with the matrix
+  d.hi = op.R.p->hi;
   return d;
 }
 
@@ -604,8 +634,6 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     any_tables |= L.useA || L.useB;
     any_b_tables |= L.useB;
   }
-  HostTiling t_in;
-  make_tiling(so_in, kSortTile, t_in);
   const size_t entries_tab = c->kb * 256;
   const size_t tab_bytes = align256(entries_tab * c->kb) + align256(entries_tab);
   const size_t oP = 0;
@@ -614,15 +642,14 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   const size_t oA = align256(o2 + e2.size() * sizeof(Exp2Desc));
   const size_t oS = align256(oA + E * sizeof(PassArgs));
   const size_t oJ = align256(oS + S * 4);
-  const size_t oT = align256(oJ + n_jobs * sizeof(TableJob));
-  const size_t host_bytes = oT + tiling_bytes(t_in);
+  const size_t host_bytes = align256(oJ + n_jobs * sizeof(TableJob));
   const size_t oTab = align256(host_bytes);
   const size_t total = oTab + n_jobs * tab_bytes + 256;
   QCHK(ensure(c, c->desc, total));
   QCHK(ensure_stage(c, 0, host_bytes));
   uint8_t* hs = (uint8_t*)c->stage[0];
   uint8_t* ds = (uint8_t*)c->desc.p;
-  std::memset(hs, 0, oT);
+  std::memset(hs, 0, host_bytes);
   if (!perms.empty()) std::memcpy(hs + oP, perms.data(), perms.size() * sizeof(PermDesc));
   if (!e1.empty()) std::memcpy(hs + o1, e1.data(), e1.size() * sizeof(Exp1Desc));
   if (!e2.empty()) std::memcpy(hs + o2, e2.data(), e2.size() * sizeof(Exp2Desc));
@@ -658,8 +685,6 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     pas_h[e] = pa;
   }
   std::memcpy(hs + oS, seg_entry.data(), S * 4);
-  Tiling tl_in{};
-  put_tiling(t_in, hs, ds, oT, tl_in);
   HIPCHK(c, hipMemcpyAsync(ds, hs, host_bytes, hipMemcpyHostToDevice, c->stream), "upload round");
   const PassArgs* pas = (const PassArgs*)(ds + oA);
   const uint32_t* sent = (const uint32_t*)(ds + oS);
@@ -687,6 +712,23 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     return QIMAX_OK;
   };
+  // input tiling: segment-aligned tiles of at most kSortTile terms, built on the device from
+  // the segment offsets (the tile count is known here exactly)
+  Tiling tl_in{};
+  {
+    uint32_t n_tin = 0;
+    for (uint32_t s = 0; s < S; ++s) n_tin += (uint32_t)((so_in[s + 1] - so_in[s] + kSortTile - 1) / kSortTile);
+    const size_t o1 = 0, o2 = align256((size_t)n_tin * 8), o3 = o2 + align256((size_t)n_tin * 8);
+    const size_t o4 = o3 + align256((size_t)n_tin * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
+    const size_t o6 = o5 + 256;
+    QCHK(ensure(c, c->dtile[2], o6 + 256));
+    uint8_t* d = (uint8_t*)c->dtile[2].p;
+    const TileJob2 job{(uint64_t)kSortTile, n_tin, 0, (uint64_t*)(d + o1), (uint64_t*)(d + o2), (uint32_t*)(d + o3),
+                       (uint32_t*)(d + o4), (uint32_t*)(d + o5), (uint32_t*)(d + o6)};
+    tl_in = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
+                   (const uint32_t*)(d + o4), n_tin, S, nullptr, nullptr};
+    HIPCHK(c, launch_make_tiles_terms(seg_in, S, job, T_in, (uint32_t*)c->err.p, c->stream), "tiles");
+  }
   QCHK(ensure(c, c->off, (T_in + 1) * 8));
   QCHK(ensure(c, c->akeys, std::max<uint64_t>(T_in, 1) * c->kb));
   QCHK(ensure(c, c->asign, std::max<uint64_t>(T_in, 1)));
@@ -1050,12 +1092,10 @@ qimax_status prebuild_tables(qimax_ctx* c, std::vector<Pass>& passes) {
 qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
   BusyTimer bt(c);
-  std::vector<HostOp> all;
-  all.reserve(c->pending.size() + ops.size());
-  for (auto& op : c->pending) all.push_back(op);
-  for (auto& op : ops) all.push_back(op);
-  std::vector<const HostOp*> ptrs;
-  for (auto& op : all) ptrs.push_back(&op);
+  std::vector<const HostOp*> ptrs;  // the deferred operators, then these (both outlive the passes)
+  ptrs.reserve(c->pending.size() + ops.size());
+  for (auto& op : c->pending) ptrs.push_back(&op);
+  for (auto& op : ops) ptrs.push_back(&op);
   std::vector<Pass> passes;
   std::vector<const HostOp*> pend;
   plan_passes(ptrs, passes, pend);
@@ -1152,6 +1192,26 @@ qimax_status check_op_input(qimax_ctx* c, const qimax_op& in, int group, HostOp&
 
 bool is_2q_code(uint8_t g) { return g == QIMAX_GATE_CX || g == QIMAX_GATE_CZ; }
 
+// A 4x4 matrix with one entry of +-1 per column and zeros elsewhere, as a code: per column c,
+// (row | 4 * negative) << 3c; -1 for any other matrix.
+int signed_perm_code4(const double* R) {
+  int code = 0;
+  for (int col = 0; col < 4; ++col) {
+    int row = -1, neg = 0;
+    for (int r = 0; r < 4; ++r) {
+      const double v = R[r * 4 + col];
+      if (v == 0.0) continue;
+      if ((v != 1.0 && v != -1.0) || row >= 0) return -1;
+      row = r;
+      neg = v < 0;
+    }
+    if (row < 0) return -1;
+    code |= (row | (neg << 2)) << (3 * col);
+  }
+  return code;
+}
+constexpr int kIdentityCode4 = 0 | (1 << 3) | (2 << 6) | (3 << 9);
+
 // The paper's grouping (Sec. III-A, Alg. 2): maximal runs of one-qubit gates (U_k) and
 // of two-qubit gates (V_k) in instruction order; inside U_k the gates of each wire form
 // U_{k,j}, composed into one transfer matrix on the device (Alg. 1).
@@ -1192,39 +1252,60 @@ qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const 
       chains.push_back({(int)r, (int)j});
     }
   }
-  std::vector<double> ptm(chains.size() * 16);
+  const double* ptm = nullptr;
   if (!chains.empty()) {
-    QCHK(ensure(c, c->gr_gate, m));
-    QCHK(ensure(c, c->gr_theta, m * 8));
-    QCHK(ensure(c, c->gr_idx, idx.size() * 4));
-    QCHK(ensure(c, c->gr_off, chain_off.size() * 4));
-    QCHK(ensure(c, c->gr_out, chains.size() * 16 * 8));
-    std::vector<double> th(m, 0.0);
-    if (theta) std::copy(theta, theta + m, th.begin());
-    HIPCHK(c, hipMemcpyAsync(c->gr_gate.p, gate, m, hipMemcpyHostToDevice, c->stream), "group upload");
-    HIPCHK(c, hipMemcpyAsync(c->gr_theta.p, th.data(), m * 8, hipMemcpyHostToDevice, c->stream), "group upload");
-    HIPCHK(c, hipMemcpyAsync(c->gr_idx.p, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, c->stream), "group upload");
-    HIPCHK(c, hipMemcpyAsync(c->gr_off.p, chain_off.data(), chain_off.size() * 4, hipMemcpyHostToDevice, c->stream),
-           "group upload");
-    HIPCHK(c, launch_compose_ptm((const uint8_t*)c->gr_gate.p, (const double*)c->gr_theta.p,
-                                 (const uint32_t*)c->gr_idx.p, (const uint32_t*)c->gr_off.p, (uint32_t)chains.size(),
-                                 (double*)c->gr_out.p, c->stream, &c->prof), "compose_ptm");
-    HIPCHK(c, hipMemcpyAsync(ptm.data(), c->gr_out.p, ptm.size() * 8, hipMemcpyDeviceToHost, c->stream),
-           "group readback");
+    // one upload and one readback, both through pinned staging (idle stream: no earlier
+    // copy still reads the staging areas)
+    const size_t oG = 0, oT = align256(m), oI = oT + align256(m * 8), oO = oI + align256(idx.size() * 4);
+    const size_t up = oO + align256(chain_off.size() * 4), down = chains.size() * 16 * 8;
+    QCHK(ensure(c, c->gr_in, up));
+    QCHK(ensure(c, c->gr_out, down));
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    QCHK(ensure_stage(c, 0, up));
+    QCHK(ensure_stage(c, 1, down));
+    uint8_t* hs = (uint8_t*)c->stage[0];
+    std::memcpy(hs + oG, gate, m);
+    if (theta) std::memcpy(hs + oT, theta, m * 8);
+    else std::memset(hs + oT, 0, m * 8);
+    std::memcpy(hs + oI, idx.data(), idx.size() * 4);
+    std::memcpy(hs + oO, chain_off.data(), chain_off.size() * 4);
+    const uint8_t* dg = (const uint8_t*)c->gr_in.p;
+    HIPCHK(c, hipMemcpyAsync(c->gr_in.p, hs, up, hipMemcpyHostToDevice, c->stream), "group upload");
+    HIPCHK(c, launch_compose_ptm(dg + oG, (const double*)(dg + oT), (const uint32_t*)(dg + oI),
+                                 (const uint32_t*)(dg + oO), (uint32_t)chains.size(), (double*)c->gr_out.p, c->stream,
+                                 &c->prof), "compose_ptm");
+    HIPCHK(c, hipMemcpyAsync(c->stage[1], c->gr_out.p, down, hipMemcpyDeviceToHost, c->stream), "group readback");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    ptm = (const double*)c->stage[1];
   }
   // assemble the operator list in run order
-  double cx[256], cz[256];
-  cx_ptm(cx);
-  cz_ptm(cz);
+  static const Ptm kCx = [] {
+    double R[256];
+    cx_ptm(R);
+    Ptm t;
+    t.assign(R, R + 256);
+    return t;
+  }();
+  static const Ptm kCz = [] {
+    double R[256];
+    cz_ptm(R);
+    Ptm t;
+    t.assign(R, R + 256);
+    return t;
+  }();
   size_t ci = 0;
   ops.clear();
+  ops.reserve(m);
+  // the one-qubit Clifford chains give few distinct signed permutations: one shared matrix
+  // and one classification each
+  struct Cls { Ptm R; bool conj = false; };
+  std::unordered_map<int, Cls> perm_cache;
   for (size_t r = 0; r < runs.size(); ++r) {
     if (runs[r].two) {
       for (size_t i = runs[r].a; i < runs[r].b; ++i) {
         HostOp op;
         op.arity = 2; op.dim = 16; op.q0 = (int)q0[i]; op.q1 = (int)q1[i]; op.group = (int)r;
-        op.R.assign(gate[i] == QIMAX_GATE_CX ? cx : cz, (gate[i] == QIMAX_GATE_CX ? cx : cz) + 256);
+        op.R = gate[i] == QIMAX_GATE_CX ? kCx : kCz;
         op.mask = (1ull << op.q0) | (1ull << op.q1);
         op.perm = true;
         op.conj = true;
@@ -1232,16 +1313,28 @@ qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const 
       }
     } else {
       while (ci < chains.size() && chains[ci].run == (int)r) {
+        const double* R = ptm + ci * 16;
         HostOp op;
         op.arity = 1; op.dim = 4; op.q0 = op.q1 = chains[ci].wire; op.group = (int)r;
-        op.R.assign(ptm.begin() + ci * 16, ptm.begin() + ci * 16 + 16);
         op.mask = 1ull << op.q0;
-        op.perm = is_signed_perm(op.R, 4);
-        op.conj = op.perm && is_conjugation(op.R, 4);
-        bool identity = true;
-        for (int a = 0; a < 4; ++a)
-          for (int b = 0; b < 4; ++b) identity &= op.R[a * 4 + b] == (a == b ? 1.0 : 0.0);
-        if (!identity) ops.push_back(std::move(op));
+        const int code = signed_perm_code4(R);
+        if (code < 0) {  // not a signed permutation (a rotation chain)
+          op.R.assign(R, R + 16);
+          op.perm = op.conj = false;
+          ops.push_back(std::move(op));
+        } else if (code != kIdentityCode4) {
+          auto it = perm_cache.find(code);
+          if (it == perm_cache.end()) {
+            Cls k;
+            k.R.assign(R, R + 16);
+            k.conj = is_conjugation(k.R, 4);
+            it = perm_cache.emplace(code, std::move(k)).first;
+          }
+          op.R = it->second.R;
+          op.perm = true;
+          op.conj = it->second.conj;
+          ops.push_back(std::move(op));
+        }
         ++ci;
       }
     }
@@ -1734,8 +1827,7 @@ void qimax_destroy(qimax_ctx* c) {
   DevBuf* bufs[] = {&c->keys, &c->w, &c->seg, &c->pk[0], &c->pk[1], &c->pw[0], &c->pw[1], &c->pseg[0],
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
-                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_gate, &c->gr_theta,
-                    &c->gr_idx, &c->gr_off, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->result, &c->ptab, &c->akeys, &c->asign, &c->chunk_cnt, &c->chunk_start,
+                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->result, &c->ptab, &c->akeys, &c->asign, &c->chunk_cnt, &c->chunk_start,
                     &c->chunk_off};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
@@ -1860,12 +1952,12 @@ qimax_status admit(qimax_batch* b) {
   }
   QCHK(ensure_keep(c, c->keys, (T + add) * c->kb, T * c->kb));
   QCHK(ensure_keep(c, c->w, (T + add) * c->wb, T * c->wb));
-  QCHK(ensure(c, c->gr_idx, nq.size() * 4));
-  QCHK(ensure(c, c->gr_off, dst.size() * 8));
-  HIPCHK(c, hipMemcpyAsync(c->gr_idx.p, nq.data(), nq.size() * 4, hipMemcpyHostToDevice, c->stream), "admit");
-  HIPCHK(c, hipMemcpyAsync(c->gr_off.p, dst.data(), dst.size() * 8, hipMemcpyHostToDevice, c->stream), "admit");
-  HIPCHK(c, launch_init_many(c->KC, c->WP, c->keys.p, c->w.p, (const uint32_t*)c->gr_idx.p,
-                             (const uint64_t*)c->gr_off.p, (uint32_t)nq.size(), c->stream), "init");
+  QCHK(ensure(c, c->gr_in, nq.size() * 4));  // the grouping buffers, free between calls
+  QCHK(ensure(c, c->gr_out, dst.size() * 8));
+  HIPCHK(c, hipMemcpyAsync(c->gr_in.p, nq.data(), nq.size() * 4, hipMemcpyHostToDevice, c->stream), "admit");
+  HIPCHK(c, hipMemcpyAsync(c->gr_out.p, dst.data(), dst.size() * 8, hipMemcpyHostToDevice, c->stream), "admit");
+  HIPCHK(c, launch_init_many(c->KC, c->WP, c->keys.p, c->w.p, (const uint32_t*)c->gr_in.p,
+                             (const uint64_t*)c->gr_out.p, (uint32_t)nq.size(), c->stream), "init");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   for (uint64_t id : b->queue) {
     BatchCirc& bc = b->circs[id];
