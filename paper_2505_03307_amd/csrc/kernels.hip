@@ -1864,11 +1864,9 @@ hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t*
 // written, the ones past the actual count empty) from the image offsets of the segments,
 // so[s] = off[seg_in[s]] (so[s] = seg_in[s] when off is null: a tiling of the terms
 // themselves); block 0 also stores those offsets in img_seg unless it is null.
-__global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict__ off,
-                                                     const uint64_t* __restrict__ seg_in, uint32_t S,
-                                                     uint64_t* __restrict__ img_seg, TileJob2 j0, TileJob2 j1,
-                                                     uint64_t limit, uint32_t* err) {
-  const TileJob2 job = blockIdx.x == 0 ? j0 : j1;
+__device__ __forceinline__ void make_tiling_block(const uint64_t* __restrict__ off, const uint64_t* __restrict__ seg_in,
+                                                  uint32_t S, uint64_t* __restrict__ img_seg, const TileJob2& job,
+                                                  uint64_t limit, uint32_t* err) {
   const uint64_t tile = job.tile;
   const uint32_t cap = job.cap;
   uint32_t* __restrict__ seg_blk = job.seg_blk;
@@ -1883,7 +1881,7 @@ __global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict_
     if (s < S) {
       const uint64_t a = so(s), b = so(s + 1);
       len = b - a;
-      if (blockIdx.x == 0 && img_seg) {
+      if (img_seg) {
         img_seg[s] = a;
         if (s + 1 == S) img_seg[S] = b;
       }
@@ -1897,7 +1895,7 @@ __global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict_
     if (threadIdx.x == 0) carry_sh = carry + tot;
     __syncthreads();
   }
-  if (S == 0 && blockIdx.x == 0 && threadIdx.x == 0 && img_seg) img_seg[0] = so(0);
+  if (S == 0 && threadIdx.x == 0 && img_seg) img_seg[0] = so(0);
   const uint64_t total_img = so(S);
   // more tiles or images than the capacity: the bound was not an upper bound (tiles are
   // clamped below so that nothing reads past the buffers; the pass reports the error)
@@ -1933,6 +1931,37 @@ __global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict_
   }
 }
 
+__global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict__ off,
+                                                     const uint64_t* __restrict__ seg_in, uint32_t S,
+                                                     uint64_t* __restrict__ img_seg, TileJob2 j0, TileJob2 j1,
+                                                     uint64_t limit, uint32_t* err) {
+  if (blockIdx.x == 0) make_tiling_block(off, seg_in, S, img_seg, j0, limit, err);
+  else make_tiling_block(off, seg_in, S, nullptr, j1, limit, err);
+}
+
+// The first launch of a round. Block 0 clears the error word, then builds the tiling of the
+// input terms (see make_tiling_block; segments at seg_in[0..S], T terms). The other blocks
+// clear the tile counters and digit histograms and copy the round's descriptors (n16 16-byte
+// words) from mapped host memory to the device.
+__global__ void __launch_bounds__(256) k_round_start(const uint4* __restrict__ blob_host, uint4* __restrict__ blob_dev,
+                                                     uint64_t n16, uint32_t* __restrict__ err,
+                                                     uint32_t* __restrict__ ctr, uint32_t n_ctr,
+                                                     uint32_t* __restrict__ ghist, uint64_t nh,
+                                                     const uint64_t* __restrict__ seg_in, uint32_t S, TileJob2 job,
+                                                     uint64_t T) {
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *err = 0u;
+    __syncthreads();
+    make_tiling_block(nullptr, seg_in, S, nullptr, job, T, err);
+    return;
+  }
+  const uint64_t stride = (uint64_t)(gridDim.x - 1) * blockDim.x;
+  const uint64_t i0 = (uint64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  for (uint64_t i = i0; i < n_ctr; i += stride) ctr[i] = 0u;
+  for (uint64_t i = i0; i < nh; i += stride) ghist[i] = 0u;
+  for (uint64_t i = i0; i < n16; i += stride) blob_dev[i] = blob_host[i];
+}
+
 // Clears the round's error word, tile counters and digit histograms (one launch).
 __global__ void k_round_prep(uint32_t* __restrict__ err, uint32_t* __restrict__ ctr, uint32_t n_ctr,
                              uint32_t* __restrict__ ghist, uint64_t nh) {
@@ -1953,9 +1982,15 @@ hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint3
   return hipGetLastError();
 }
 
-hipError_t launch_make_tiles_terms(const uint64_t* seg_in, uint32_t S, const TileJob2& job, uint64_t T,
-                                   uint32_t* err, hipStream_t s) {
-  k_make_tiles2<<<1, 256, 0, s>>>(nullptr, seg_in, S, nullptr, job, job, T, err);
+hipError_t launch_round_start(const void* blob_host, void* blob_dev, size_t blob_bytes, uint32_t* err, uint32_t* ctr,
+                              uint32_t n_ctr, uint32_t* ghist, uint64_t nh, const uint64_t* seg_in, uint32_t S,
+                              const TileJob2& job, uint64_t T, hipStream_t s) {
+  if (blob_bytes % 16 || ((uintptr_t)blob_host | (uintptr_t)blob_dev) % 16) return hipErrorInvalidValue;
+  const uint64_t n16 = blob_bytes / 16;
+  const uint64_t work = std::max<uint64_t>(std::max<uint64_t>(nh, n16), n_ctr);
+  const uint32_t g = (uint32_t)std::min<uint64_t>(grid_for(std::max<uint64_t>(work, 1), 256), 1024);
+  k_round_start<<<1 + g, 256, 0, s>>>((const uint4*)blob_host, (uint4*)blob_dev, n16, err, ctr, n_ctr, ghist, nh,
+                                      seg_in, S, job, T);
   return hipGetLastError();
 }
 

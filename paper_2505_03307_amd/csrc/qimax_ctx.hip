@@ -276,7 +276,6 @@ struct qimax_ctx {
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
   DevBuf mstatus;  // single-sweep count and merge state (one word per tile)
-  DevBuf result;   // packed readback of a round
   DevBuf dtile[3];  // device-built tilings: images (expand, sort/merge; bound path), input terms
   uint64_t mepoch = 0;
   bool classic_sort = false;
@@ -298,10 +297,16 @@ struct qimax_ctx {
   qimax_stats st{};
   Prof prof;
   std::vector<uint64_t> gen_updates;
-  // pinned host staging of the two uploads of a round (descriptors + count tiling, then
-  // the image tilings); each is reused only after the stream synchronisation that follows it
+  // pinned, device-mapped host staging: [0] a round's descriptors (read by its first launch),
+  // [1] the image tilings of the unbound path; each is rewritten only after the stream
+  // synchronisation that follows its use
   void* stage[2] = {nullptr, nullptr};
+  void* stage_dev[2] = {nullptr, nullptr};  // device addresses of the same memory
   size_t stage_bytes[2] = {0, 0};
+  // pinned, device-mapped words the last launch of a round writes its results into
+  uint64_t* zres = nullptr;
+  uint64_t* zres_dev = nullptr;
+  size_t zres_words = 0;
 };
 
 namespace {
@@ -526,8 +531,38 @@ qimax_status ensure_stage(qimax_ctx* c, int i, size_t bytes) {
     c->stage_bytes[i] = 0;
   }
   const size_t want = align256(bytes + bytes / 4 + 4096);
-  HIPCHK(c, hipHostMalloc(&c->stage[i], want, hipHostMallocDefault), "hipHostMalloc staging");
+  HIPCHK(c, hipHostMalloc(&c->stage[i], want, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc staging");
   c->stage_bytes[i] = want;
+  HIPCHK(c, hipHostGetDevicePointer(&c->stage_dev[i], c->stage[i], 0), "hipHostGetDevicePointer");
+  return QIMAX_OK;
+}
+
+// Result words written by the device into mapped host memory (read after a synchronisation).
+qimax_status ensure_zres(qimax_ctx* c, size_t words) {
+  if (words <= c->zres_words && c->zres) return QIMAX_OK;
+  if (c->zres) {
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    (void)hipHostFree(c->zres);
+    c->zres = c->zres_dev = nullptr;
+    c->zres_words = 0;
+  }
+  const size_t want = std::max<size_t>(words + words / 4, 512);
+  HIPCHK(c, hipHostMalloc((void**)&c->zres, want * 8, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc");
+  c->zres_words = want;
+  void* d = nullptr;
+  HIPCHK(c, hipHostGetDevicePointer(&d, c->zres, 0), "hipHostGetDevicePointer");
+  c->zres_dev = (uint64_t*)d;
+  return QIMAX_OK;
+}
+
+// Wait for the words the device writes into zres; the error word is the last of them.
+qimax_status wait_zres(qimax_ctx* c, size_t words, uint32_t* err_out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->st.host_wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  c->st.syncs += 1;
+  prof_resolve(&c->prof);
+  *err_out = (uint32_t)(c->zres[words - 1] & 0xFFFFFFFFu);
   return QIMAX_OK;
 }
 
@@ -685,7 +720,6 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     pas_h[e] = pa;
   }
   std::memcpy(hs + oS, seg_entry.data(), S * 4);
-  HIPCHK(c, hipMemcpyAsync(ds, hs, host_bytes, hipMemcpyHostToDevice, c->stream), "upload round");
   const PassArgs* pas = (const PassArgs*)(ds + oA);
   const uint32_t* sent = (const uint32_t*)(ds + oS);
   const bool sweep = !c->classic_sort;
@@ -697,7 +731,25 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   if (sweep) QCHK(ensure(c, c->ghist, std::max<uint64_t>(nh, 1) * 4));
   QCHK(ensure(c, c->tile_ctr, 256 * 4));
   uint32_t* const ctr = (uint32_t*)c->tile_ctr.p;
-  HIPCHK(c, launch_round_prep((uint32_t*)c->err.p, ctr, 256, (uint32_t*)c->ghist.p, nh, c->stream), "prep");
+  // input tiling: segment-aligned tiles of at most kSortTile terms, built on the device from
+  // the segment offsets (the tile count is known here exactly) by the round's first launch,
+  // which also clears the error word, counters and histograms and pulls the descriptors
+  Tiling tl_in{};
+  {
+    uint32_t n_tin = 0;
+    for (uint32_t s = 0; s < S; ++s) n_tin += (uint32_t)((so_in[s + 1] - so_in[s] + kSortTile - 1) / kSortTile);
+    const size_t o1 = 0, o2 = align256((size_t)n_tin * 8), o3 = o2 + align256((size_t)n_tin * 8);
+    const size_t o4 = o3 + align256((size_t)n_tin * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
+    const size_t o6 = o5 + 256;
+    QCHK(ensure(c, c->dtile[2], o6 + 256));
+    uint8_t* d = (uint8_t*)c->dtile[2].p;
+    const TileJob2 job{(uint64_t)kSortTile, n_tin, 0, (uint64_t*)(d + o1), (uint64_t*)(d + o2), (uint32_t*)(d + o3),
+                       (uint32_t*)(d + o4), (uint32_t*)(d + o5), (uint32_t*)(d + o6)};
+    tl_in = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
+                   (const uint32_t*)(d + o4), n_tin, S, nullptr, nullptr};
+    HIPCHK(c, launch_round_start(c->stage_dev[0], ds, host_bytes, (uint32_t*)c->err.p, ctr, 256,
+                                 (uint32_t*)c->ghist.p, nh, seg_in, S, job, T_in, c->stream), "round start");
+  }
   HIPCHK(c, launch_build_tables(c->KC, (const TableJob*)(ds + oJ), (uint32_t)n_jobs, c->stream, &c->prof),
          "chain tables");
   // ---- fan-out count fused with its scan -> image offsets of every input term
@@ -712,23 +764,6 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     return QIMAX_OK;
   };
-  // input tiling: segment-aligned tiles of at most kSortTile terms, built on the device from
-  // the segment offsets (the tile count is known here exactly)
-  Tiling tl_in{};
-  {
-    uint32_t n_tin = 0;
-    for (uint32_t s = 0; s < S; ++s) n_tin += (uint32_t)((so_in[s + 1] - so_in[s] + kSortTile - 1) / kSortTile);
-    const size_t o1 = 0, o2 = align256((size_t)n_tin * 8), o3 = o2 + align256((size_t)n_tin * 8);
-    const size_t o4 = o3 + align256((size_t)n_tin * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
-    const size_t o6 = o5 + 256;
-    QCHK(ensure(c, c->dtile[2], o6 + 256));
-    uint8_t* d = (uint8_t*)c->dtile[2].p;
-    const TileJob2 job{(uint64_t)kSortTile, n_tin, 0, (uint64_t*)(d + o1), (uint64_t*)(d + o2), (uint32_t*)(d + o3),
-                       (uint32_t*)(d + o4), (uint32_t*)(d + o5), (uint32_t*)(d + o6)};
-    tl_in = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
-                   (const uint32_t*)(d + o4), n_tin, S, nullptr, nullptr};
-    HIPCHK(c, launch_make_tiles_terms(seg_in, S, job, T_in, (uint32_t*)c->err.p, c->stream), "tiles");
-  }
   QCHK(ensure(c, c->off, (T_in + 1) * 8));
   QCHK(ensure(c, c->akeys, std::max<uint64_t>(T_in, 1) * c->kb));
   QCHK(ensure(c, c->asign, std::max<uint64_t>(T_in, 1)));
@@ -865,8 +900,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->pseg[slot], (S + 1) * 8));
   QCHK(ensure(c, c->blk_cnt, (size_t)(tl.n_blocks + 1) * 4));
   QCHK(ensure(c, c->blk_off, (size_t)(tl.n_blocks + 1) * 8));
-  QCHK(ensure(c, c->result, (size_t)(2 * S + 3) * 8));
-  MergeFin fin{(const uint64_t*)c->img_seg.p, (uint64_t*)c->result.p};
+  QCHK(ensure_zres(c, 2 * (size_t)S + 3));
+  MergeFin fin{(const uint64_t*)c->img_seg.p, c->zres_dev};
   bool chunk_path = pre_chunk >= 0;  // chunk-local sort fused with the merge
   auto merge_and_read = [&]() -> qimax_status {
     if (chunk_path) {
@@ -893,7 +928,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     if (tune_timed) HIPCHK(c, hipEventRecord(c->tune_ev[1], c->stream), "tune event");
     // ---- one readback: output offsets, image offsets, error word
-    if (sweep) return readback(c, c->result.p, 2 * (size_t)S + 3, &e, /*err_packed=*/true);
+    if (sweep) return wait_zres(c, 2 * (size_t)S + 3, &e);
     return readback(c, c->pseg[slot].p, S + 1, &e);
   };
   QCHK(merge_and_read());
@@ -940,10 +975,11 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
                   (unsigned long long)T_in, (unsigned long long)T_img, tl.n_blocks, key_bits, E);
     return fail(c, (e & kErrFanout) ? QIMAX_ETOOLARGE : QIMAX_EDEVICE, "propagation round:" + err_text(e) + buf);
   }
-  so_out.assign(c->pinned, c->pinned + S + 1);
+  const uint64_t* rb = sweep ? c->zres : c->pinned;  // where the round's results came back
+  so_out.assign(rb, rb + S + 1);
   const uint64_t T_out = so_out[S];
   if (bound_path) {
-    so_img.assign(c->pinned + S + 1, c->pinned + 2 * (S + 1));
+    so_img.assign(rb + S + 1, rb + 2 * (S + 1));
     // the launches were recorded with the capacity; count the real images
     const uint64_t cap = T_img;
     T_img = so_img[S];
@@ -1827,12 +1863,13 @@ void qimax_destroy(qimax_ctx* c) {
   DevBuf* bufs[] = {&c->keys, &c->w, &c->seg, &c->pk[0], &c->pk[1], &c->pw[0], &c->pw[1], &c->pseg[0],
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
-                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->result, &c->ptab, &c->akeys, &c->asign, &c->chunk_cnt, &c->chunk_start,
+                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->chunk_cnt, &c->chunk_start,
                     &c->chunk_off};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 2; ++i)
     if (c->stage[i]) (void)hipHostFree(c->stage[i]);
+  if (c->zres) (void)hipHostFree(c->zres);
   prof_destroy(&c->prof);
   for (hipEvent_t e : c->tune_ev)
     if (e) (void)hipEventDestroy(e);

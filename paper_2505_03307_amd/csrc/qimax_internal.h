@@ -269,10 +269,13 @@ struct TileJob2 {
 // limit sets an error bit.
 hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint32_t S, uint64_t* img_seg,
                               const TileJob2& j0, const TileJob2& j1, uint64_t limit, uint32_t* err, hipStream_t s);
-// One tiling (block 0's job) of the terms themselves, segments at seg_in[0..S] (device), T
-// terms in all; no image offsets are stored.
-hipError_t launch_make_tiles_terms(const uint64_t* seg_in, uint32_t S, const TileJob2& job, uint64_t T,
-                                   uint32_t* err, hipStream_t s);
+// The first launch of a round: clears *err, ctr[0..n_ctr) and ghist[0..nh), copies blob_bytes
+// (a multiple of 16, both addresses 16-byte aligned) from blob_host (mapped host memory, its
+// device address) to blob_dev, and builds one tiling of the terms themselves (segments at
+// seg_in[0..S] on the device, T terms in all; no image offsets stored).
+hipError_t launch_round_start(const void* blob_host, void* blob_dev, size_t blob_bytes, uint32_t* err, uint32_t* ctr,
+                              uint32_t n_ctr, uint32_t* ghist, uint64_t nh, const uint64_t* seg_in, uint32_t S,
+                              const TileJob2& job, uint64_t T, hipStream_t s);
 
 // Zero the error word, n_ctr tile counters and nh digit-histogram words (one launch).
 hipError_t launch_round_prep(uint32_t* err, uint32_t* ctr, uint32_t n_ctr, uint32_t* ghist, uint64_t nh,
