@@ -842,6 +842,14 @@ struct F64Sum {  // FP32 weights accumulated in FP64, rounded once
 // with the total at blk_off[n_blocks]), then writes.
 // After the merge (one block): the segment output offsets seg_off_out[s] = blk_off[seg_blk[s]]
 // (all 0 when there are no tiles) and the packed readback area (see MergeFin).
+// The end of a publishing kernel (one block): every thread's result words reach memory before
+// the sequence word is stored, so a host that sees the sequence word may read them all.
+__device__ __forceinline__ void publish_seq(const MergeFin& fin, uint32_t S) {
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) *(volatile uint64_t*)&fin.result[2 * (uint64_t)S + 3] = fin.seq;
+}
+
 __global__ void k_merge_publish(Tiling tl, const uint64_t* __restrict__ blk_off, uint64_t* __restrict__ seg_off_out,
                                 MergeFin fin, const uint32_t* __restrict__ err, int none) {
   const uint32_t S = tl.n_segs;
@@ -852,6 +860,7 @@ __global__ void k_merge_publish(Tiling tl, const uint64_t* __restrict__ blk_off,
     fin.result[S + 1 + s] = fin.img_seg[s];
   }
   if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err;
+  publish_seq(fin, S);
 }
 
 
@@ -1185,6 +1194,7 @@ __global__ void __launch_bounds__(512) k_chunk_publish(Tiling tc, const uint32_t
     fin.result[S + 1 + s] = fin.img_seg[s];
   }
   if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (carry_sh > out_cap ? kErrIndex | kErrMerge : 0u);
+  publish_seq(fin, S);
 }
 
 // Moves every chunk's kept runs from the front of its range to their output offset.
@@ -1546,7 +1556,12 @@ void prof_end(Prof* p, hipStream_t s, hipEvent_t a, int kind, double bytes, uint
 
 void prof_resolve(Prof* p) {
   if (!p) return;
+  size_t keep = 0;  // records whose end event has not completed stay for a later call
   for (auto& r : p->recs) {
+    if (hipEventQuery(r.b) == hipErrorNotReady) {
+      p->recs[keep++] = r;
+      continue;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       p->launches[r.kind] += r.count;
@@ -1556,7 +1571,7 @@ void prof_resolve(Prof* p) {
     p->pool.push_back(r.a);
     p->pool.push_back(r.b);
   }
-  p->recs.clear();
+  p->recs.resize(keep);
 }
 
 void prof_reset(Prof* p) {

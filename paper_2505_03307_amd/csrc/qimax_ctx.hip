@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -307,6 +308,7 @@ struct qimax_ctx {
   uint64_t* zres = nullptr;
   uint64_t* zres_dev = nullptr;
   size_t zres_words = 0;
+  uint64_t zseq = 0;  // sequence word of the last results asked for
 };
 
 namespace {
@@ -555,14 +557,32 @@ qimax_status ensure_zres(qimax_ctx* c, size_t words) {
   return QIMAX_OK;
 }
 
-// Wait for the words the device writes into zres; the error word is the last of them.
+// Wait for the words the device writes into zres (words - 2: the error word, words - 1: the
+// sequence word, stored last). The host polls the sequence word rather than waiting for the
+// stream: launches queued after the publishing one (a compaction) keep running meanwhile.
+// Once a millisecond of polling the stream is queried (a query is not free: it is kept rare),
+// so that a failed or finished stream ends the wait.
 qimax_status wait_zres(qimax_ctx* c, size_t words, uint32_t* err_out) {
   const auto t0 = std::chrono::steady_clock::now();
-  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  auto t_query = t0;
+  volatile const uint64_t* seq = c->zres + words - 1;
+  for (uint32_t it = 1; *seq != c->zseq; ++it) {
+    if ((it & 63u) == 0 && std::chrono::steady_clock::now() - t_query > std::chrono::milliseconds(1)) {
+      t_query = std::chrono::steady_clock::now();
+      const hipError_t q = hipStreamQuery(c->stream);
+      if (q == hipSuccess) {
+        if (*seq != c->zseq) return fail(c, QIMAX_EDEVICE, "round results missing after the stream finished");
+        break;
+      }
+      if (q != hipErrorNotReady) return hip_fail(c, q, "hipStreamQuery");
+    }
+    __builtin_ia32_pause();
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   c->st.host_wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   c->st.syncs += 1;
   prof_resolve(&c->prof);
-  *err_out = (uint32_t)(c->zres[words - 1] & 0xFFFFFFFFu);
+  *err_out = (uint32_t)(c->zres[words - 2] & 0xFFFFFFFFu);
   return QIMAX_OK;
 }
 
@@ -900,10 +920,14 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->pseg[slot], (S + 1) * 8));
   QCHK(ensure(c, c->blk_cnt, (size_t)(tl.n_blocks + 1) * 4));
   QCHK(ensure(c, c->blk_off, (size_t)(tl.n_blocks + 1) * 8));
-  QCHK(ensure_zres(c, 2 * (size_t)S + 3));
-  MergeFin fin{(const uint64_t*)c->img_seg.p, c->zres_dev};
+  QCHK(ensure_zres(c, 2 * (size_t)S + 4));
+  MergeFin fin{(const uint64_t*)c->img_seg.p, c->zres_dev, 0};
   bool chunk_path = pre_chunk >= 0;  // chunk-local sort fused with the merge
   auto merge_and_read = [&]() -> qimax_status {
+    if (sweep) {  // a fresh sequence word for these results
+      fin.seq = ++c->zseq;
+      c->zres[2 * (size_t)S + 3] = 0;
+    }
     if (chunk_path) {
       const size_t nc = std::max<uint32_t>(tl_exp.n_blocks, 1);
       QCHK(ensure(c, c->chunk_cnt, nc * 4));
@@ -928,7 +952,11 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     if (tune_timed) HIPCHK(c, hipEventRecord(c->tune_ev[1], c->stream), "tune event");
     // ---- one readback: output offsets, image offsets, error word
-    if (sweep) return wait_zres(c, 2 * (size_t)S + 3, &e);
+    if (sweep) {
+      QCHK(wait_zres(c, 2 * (size_t)S + 4, &e));
+      if (tune_timed) HIPCHK(c, hipEventSynchronize(c->tune_ev[1]), "tune event");
+      return QIMAX_OK;
+    }
     return readback(c, c->pseg[slot].p, S + 1, &e);
   };
   QCHK(merge_and_read());

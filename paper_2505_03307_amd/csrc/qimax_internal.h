@@ -221,7 +221,9 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 // merge; in a single sweep *tile_ctr must then be zero on entry.
 struct MergeFin {
   const uint64_t* img_seg;  // image offsets of the segments (S + 1)
-  uint64_t* result;         // [0..S] output offsets, [S+1..2S+1] img_seg, [2S+2] error word
+  uint64_t* result;         // [0..S] output offsets, [S+1..2S+1] img_seg, [2S+2] error word,
+                            // [2S+3] seq, written after every other word has reached memory
+  uint64_t seq;
 };
 hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, uint64_t T,
                         const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out, void* w_out,
