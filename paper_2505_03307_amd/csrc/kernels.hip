@@ -299,8 +299,10 @@ __global__ void __launch_bounds__(kExpandBlock)
 k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const typename WTraits<WP>::W* __restrict__ w,
          uint64_t T_in, const uint64_t* __restrict__ off, uint64_t T_img, Tiling tl, const PassArgs* __restrict__ pas,
          const uint32_t* __restrict__ seg_entry, const uint64_t* __restrict__ seg_in, K* __restrict__ keys_out,
-         typename WTraits<WP>::W* __restrict__ w_out, uint32_t* err) {
+         typename WTraits<WP>::W* __restrict__ w_out, uint32_t* __restrict__ ghist, uint32_t n_pass, uint32_t hp_begin,
+         uint32_t* err) {
   using W = typename WTraits<WP>::W;
+  constexpr int kWaves = kExpandBlock / 64;
   constexpr int kWin = kExpandTile + 1;
   constexpr int kTab = (int)sizeof(K) * 256;
   // dynamic LDS: offset window, image -> parent map, the chain tables that this pass uses,
@@ -318,6 +320,9 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
   cur += pa.useB ? kTab : 0;
   uint64_t* edesc = (uint64_t*)cur;
   __shared__ uint64_t bounds[2];
+  // digit counts of the images for the sort passes hp_begin .. n_pass-1 (one copy per wave),
+  // added to the segment's histograms ghist[(seg*n_pass + p)*256 + d] at the end
+  const uint32_t n_hp = ghist ? n_pass - hp_begin : 0u;
   // this block's images: one segment-aligned tile of at most kExpandTile
   const uint64_t g0 = tl.blk_begin[blk];
   const uint64_t g1 = min(tl.blk_end[blk], T_img);
@@ -329,6 +334,9 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
   for (uint32_t i = threadIdx.x; i < e2w; i += kExpandBlock) edesc[e1w + i] = ((const uint64_t*)pa.E2)[i];
   const Exp1Desc* E1s = (const Exp1Desc*)edesc;
   const Exp2Desc* E2s = (const Exp2Desc*)(edesc + e1w);
+  uint32_t* hh = (uint32_t*)(edesc + e1w + e2w);
+  for (uint32_t i = threadIdx.x; i < n_hp * kWaves * kRadix; i += kExpandBlock) hh[i] = 0u;
+  uint32_t* hw = hh + (threadIdx.x >> 6) * n_hp * kRadix;
   // parents of the first and last image: wave 0 and wave 1 search the segment's parents
   // (off is the global image offset of every parent; the segment's are seg_in[seg] ..)
   if (threadIdx.x < 128) {
@@ -420,6 +428,17 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
     if (neg) wv = -wv;
     keys_out[g] = key;
     w_out[g] = wv;
+    for (uint32_t p = 0; p < n_hp; ++p) atomicAdd(&hw[p * kRadix + ((uint32_t)(key >> (8u * (hp_begin + p))) & 255u)], 1u);
+  }
+  if (n_hp) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_hp * kRadix; i += kExpandBlock) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) c += hh[w * n_hp * kRadix + i];
+      const uint32_t p = hp_begin + i / kRadix, d = i % kRadix;
+      if (c) atomicAdd(&ghist[((uint64_t)seg * n_pass + p) * kRadix + d], c);
+    }
   }
 }
 
@@ -1665,19 +1684,24 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign,
                          const uint64_t* off,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
                          const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
-                         uint32_t* err, hipStream_t s, Prof* prof) {
+                         uint32_t* ghist, uint32_t n_pass, uint32_t hp_begin, uint32_t* err, hipStream_t s,
+                         Prof* prof) {
   if (T_img == 0 || tl.n_blocks == 0) return hipSuccess;
+  if (ghist && (hp_begin > n_pass || n_pass - hp_begin > kExpandHistPasses)) return hipErrorInvalidValue;
+  const size_t hist = ghist ? (size_t)(n_pass - hp_begin) * (kExpandBlock / 64) * kRadix * 4 : 0;
   hipEvent_t ev = prof_begin(prof, s, kKExpand);
   QIMAX_DISPATCH_K(KC, {
     const size_t tab = sizeof(K) * 256 * (sizeof(K) + 1);  // a B-chain table (A chains: done by the count)
     const size_t lds = (size_t)(kExpandTile + 1) * 8 + (size_t)kExpandTile * 2 + (any_tables ? tab : 0) +
-                       e_bytes + 64;
+                       e_bytes + hist + 64;
     if (WP == 64)
       k_expand<K, 64><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, asign, (const double*)w, T_in, off, T_img, tl,
-                                                              pas, seg_entry, seg_in, (K*)keys_out, (double*)w_out, err);
+                                                              pas, seg_entry, seg_in, (K*)keys_out, (double*)w_out,
+                                                              ghist, n_pass, hp_begin, err);
     else
       k_expand<K, 32><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, asign, (const float*)w, T_in, off, T_img, tl,
-                                                              pas, seg_entry, seg_in, (K*)keys_out, (float*)w_out, err);
+                                                              pas, seg_entry, seg_in, (K*)keys_out, (float*)w_out,
+                                                              ghist, n_pass, hp_begin, err);
   });
   const double per = (4 << KC) + (WP == 64 ? 8 : 4);
   prof_end(prof, s, ev, kKExpand, per * (double)(T_in + T_img) + 8.0 * (double)T_in);

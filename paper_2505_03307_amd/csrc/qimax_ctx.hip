@@ -842,6 +842,41 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     put_tiling(t_sort, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, mid, tl);
     HIPCHK(c, hipMemcpyAsync(c->desc2.p, c->stage[1], img_bytes, hipMemcpyHostToDevice, c->stream), "upload tiling");
   }
+  // ---- sort plan (single-sweep sort): global passes over every digit, or over the top m
+  // digits only, followed by chunk-local sorts in LDS. m is the fewest top digits that split
+  // the largest segment (its image count or a bound of it) into buckets of about 512 on
+  // average; the autotuner may add one, and may turn the per-XCD tile ranges off, by what it
+  // measured for rounds of this size (the expansion, sort and merge, timed together). The
+  // expansion counts the digits of up to kExpandHistPasses global passes itself.
+  uint32_t m_top = n_pass;  // digits sorted by global passes (the rest chunk-locally)
+  uint32_t tune_key = 0;    // autotuner: size class of this round's sort, candidate, timed?
+  int tune_cand = 0;
+  bool tune_timed = false;
+  bool xr = c->xcd_ranges;
+  if (sweep) {
+    if (c->local_sort && c->redo_cooldown == 0) {
+      uint64_t seg_max = 0;
+      for (uint32_t s = 0; s < S; ++s)
+        seg_max = std::max<uint64_t>(seg_max, bound_path ? (uint64_t)(f_round * (double)(so_in[s + 1] - so_in[s]))
+                                                         : so_img[s + 1] - so_img[s]);
+      uint32_t mm = 0;
+      for (double cap_b = 512.0; mm < n_pass && (double)seg_max > cap_b; cap_b *= 256.0) ++mm;
+      m_top = c->local_sort_m >= 0 ? std::min<uint32_t>((uint32_t)c->local_sort_m, n_pass) : mm;
+      if (c->autotune && c->local_sort_m < 0 && m_top < n_pass) {
+        tune_key = (uint32_t)c->KC * 4096u + (uint32_t)c->WP * 64u + (uint32_t)std::min(63, ilog2_u64(T_img));
+        TuneState& ts = c->tune[tune_key];
+        tune_cand = ts.best >= 0 ? ts.best : ts.tried;
+        if (tune_cand == 1) m_top = std::min(m_top + 1, n_pass);
+        if (tune_cand == 2) xr = false;
+        if (ts.best < 0) {  // exploring: time this round
+          HIPCHK(c, hipEventRecord(c->tune_ev[0], c->stream), "tune event");
+          tune_timed = true;
+        }
+      }
+    }
+    if (c->redo_cooldown > 0) --c->redo_cooldown;
+  }
+  const bool hist_in_expand = sweep && m_top <= kExpandHistPasses;
   // ---- expand into images
   const size_t eb = c->kb, wbt = c->wb;
   QCHK(ensure(c, c->ik[0], std::max<uint64_t>(T_img, 1) * eb));
@@ -849,16 +884,13 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure(c, c->ik[1], std::max<uint64_t>(T_img, 1) * eb));
   QCHK(ensure(c, c->iw[1], std::max<uint64_t>(T_img, 1) * wbt));
   HIPCHK(c, launch_expand(c->KC, c->WP, c->akeys.p, (const uint8_t*)c->asign.p, w_in, T_in,
-                          (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent, seg_in, any_b_tables, e_bytes, c->ik[0].p, c->iw[0].p, (uint32_t*)c->err.p, c->stream,
-                          &c->prof), "expand");
+                          (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent, seg_in, any_b_tables, e_bytes,
+                          c->ik[0].p, c->iw[0].p, hist_in_expand ? (uint32_t*)c->ghist.p : nullptr, n_pass,
+                          n_pass - m_top, (uint32_t*)c->err.p, c->stream, &c->prof), "expand");
   // ---- segment-local LSD radix sort of the images
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
   int cur = 0;
-  uint32_t m_top = n_pass;  // digits sorted by global passes (the rest chunk-locally)
   int pre_chunk = -1;       // slot holding the images before the chunk-local sort
-  uint32_t tune_key = 0;    // autotuner: size class of this round's sort, candidate, timed?
-  int tune_cand = 0;
-  bool tune_timed = false;
   if (!sweep) {
     QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
     QCHK(ensure(c, c->hist, hsize * 8));
@@ -881,35 +913,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     void* const kk[2] = {c->ik[0].p, c->ik[1].p};
     void* const ww[2] = {c->iw[0].p, c->iw[1].p};
-    // Global passes over every digit, or over the top m digits only, followed by chunk-local
-    // sorts in LDS. m is the fewest top digits that split the largest segment (its image count
-    // or a bound of it) into buckets of about 512 on average; the autotuner may add one, and
-    // may turn the per-XCD tile ranges off, by what it measured for rounds of this size.
-    m_top = n_pass;
-    bool xr = c->xcd_ranges;
-    if (c->local_sort && c->redo_cooldown == 0) {
-      uint64_t seg_max = 0;
-      for (uint32_t s = 0; s < S; ++s)
-        seg_max = std::max<uint64_t>(seg_max, bound_path ? (uint64_t)(f_round * (double)(so_in[s + 1] - so_in[s]))
-                                                         : so_img[s + 1] - so_img[s]);
-      uint32_t mm = 0;
-      for (double cap_b = 512.0; mm < n_pass && (double)seg_max > cap_b; cap_b *= 256.0) ++mm;
-      m_top = c->local_sort_m >= 0 ? std::min<uint32_t>((uint32_t)c->local_sort_m, n_pass) : mm;
-      if (c->autotune && c->local_sort_m < 0 && m_top < n_pass) {
-        tune_key = (uint32_t)c->KC * 4096u + (uint32_t)c->WP * 64u + (uint32_t)std::min(63, ilog2_u64(T_img));
-        TuneState& ts = c->tune[tune_key];
-        tune_cand = ts.best >= 0 ? ts.best : ts.tried;
-        if (tune_cand == 1) m_top = std::min(m_top + 1, n_pass);
-        if (tune_cand == 2) xr = false;
-        if (ts.best < 0) {  // exploring: time the sort of this round
-          HIPCHK(c, hipEventRecord(c->tune_ev[0], c->stream), "tune event");
-          tune_timed = true;
-        }
-      }
-    }
-    if (c->redo_cooldown > 0) --c->redo_cooldown;
     if (!xr) tl.xrange = nullptr;
-    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, n_pass - m_top, true, tl,
+    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, n_pass - m_top, !hist_in_expand, tl,
                                 (const uint64_t*)c->img_seg.p, (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr,
                                 &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof), "sort");
     if (m_top < n_pass) pre_chunk = cur;  // the chunk-local sort runs with the merge
@@ -1017,7 +1022,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
         if ((c->prof.mask >> kind) & 1u) c->prof.bytes[kind] -= bytes;
       };
       fix(kKExpand, (double)(eb + wbt) * d);
-      fix(kKSortHist, (double)eb * d);
+      fix(kKSortHist, (double)eb * d * ((hist_in_expand ? 0 : 1) + (sorted_again ? 1 : 0)));  // upsweeps run
       fix(kKSortScatter, 2.0 * (double)(eb + wbt) * (sorted_again ? n_pass + m_top : m_top) * d);
       if (m_top < n_pass) fix(kKChunkSort, (double)(eb + wbt) * d);
       if (!chunk_path) fix(kKMergeWrite, (double)(eb + wbt) * d);

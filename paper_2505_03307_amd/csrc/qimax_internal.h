@@ -104,6 +104,7 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kExpandBlock = 256;
 constexpr int kExpandItems = 8;
 constexpr int kExpandTile = kExpandBlock * kExpandItems;
+constexpr uint32_t kExpandHistPasses = 2;  // digit histograms the expansion may count itself
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
@@ -178,15 +179,17 @@ hipError_t launch_scan_u64(const uint64_t* in, uint64_t* out, uint64_t N, uint64
 hipError_t launch_gather_u64(const uint64_t* src_off, const uint64_t* idx, uint64_t* dst,
                              uint32_t S1, hipStream_t s, Prof* prof = nullptr);
 
-// Images of each tile of tl (segment-aligned, at most kExpandTile each). any_tables: some
-// entry uses chain tables (sizes the dynamic LDS).
+// Images of each tile of tl (segment-aligned, at most kExpandTile each).
 // keys/asign: the input terms' images under the A chain and their signs (from the count);
-// any_tables: some entry has a B-chain table.
+// any_tables: some entry has a B-chain table (sizes the dynamic LDS). With ghist set, the
+// images' digits of the sort passes hp_begin .. n_pass-1 (at most kExpandHistPasses) are
+// added to the segments' digit histograms ghist[(s*n_pass + p)*256 + d] (cleared before).
 hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign, const void* w, uint64_t T_in,
                          const uint64_t* off,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
                          const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
-                         uint32_t* err, hipStream_t s, Prof* prof = nullptr);
+                         uint32_t* ghist, uint32_t n_pass, uint32_t hp_begin, uint32_t* err, hipStream_t s,
+                         Prof* prof = nullptr);
 
 // One LSD radix pass over digit `shift` of every segment, stable, segment-local.
 // hist must hold kRadix * n_blocks uint64 words; tmp scan_tmp_words(kRadix * n_blocks).
