@@ -1183,36 +1183,38 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
 // counts of the n_chunks chunks (n_dev or n_blocks of tc), the segment output offsets
 // seg_off_out[s] = chunk_off[seg_blk[s]], and the packed readback area (see MergeFin); a total
 // above out_cap is reported in the error word there (the compaction then writes nothing).
-__global__ void __launch_bounds__(512) k_chunk_publish(Tiling tc, const uint32_t* __restrict__ chunk_cnt,
-                                                       uint64_t* __restrict__ chunk_off,
-                                                       uint64_t* __restrict__ seg_off_out, MergeFin fin,
-                                                       uint64_t out_cap, const uint32_t* __restrict__ err) {
-  __shared__ uint64_t sh[8];
-  __shared__ uint64_t carry_sh;
+constexpr int kPublishBlock = 1024;
+__global__ void __launch_bounds__(kPublishBlock) k_chunk_publish(Tiling tc, const uint32_t* __restrict__ chunk_cnt,
+                                                                 uint64_t* __restrict__ chunk_off,
+                                                                 uint64_t* __restrict__ seg_off_out, MergeFin fin,
+                                                                 uint64_t out_cap, const uint32_t* __restrict__ err) {
+  __shared__ uint64_t sh[kPublishBlock / 64];
+  __shared__ uint64_t total_sh;
   const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
-  if (threadIdx.x == 0) carry_sh = 0;
-  __syncthreads();
-  for (uint32_t base = 0; base < nc; base += 512) {
-    const uint32_t i = base + threadIdx.x;
-    const uint64_t v = i < nc ? chunk_cnt[i] : 0;
-    uint64_t tot;
-    const uint64_t pre = block_excl_scan<512>(v, sh, &tot);
-    const uint64_t carry = carry_sh;
-    if (i < nc) chunk_off[i] = carry + pre;
-    __syncthreads();
-    if (threadIdx.x == 0) carry_sh = carry + tot;
-    __syncthreads();
+  // thread t scans the run [t*per, (t+1)*per) serially: one block scan for all the runs
+  const uint32_t per = (nc + kPublishBlock - 1) / kPublishBlock;
+  const uint32_t r0 = min(threadIdx.x * per, nc), r1 = min(r0 + per, nc);
+  uint64_t sum = 0;
+  for (uint32_t i = r0; i < r1; ++i) sum += chunk_cnt[i];
+  uint64_t tot;
+  uint64_t run = block_excl_scan<kPublishBlock>(sum, sh, &tot);
+  for (uint32_t i = r0; i < r1; ++i) {
+    chunk_off[i] = run;
+    run += chunk_cnt[i];
   }
-  if (threadIdx.x == 0) chunk_off[nc] = carry_sh;
+  if (threadIdx.x == 0) {
+    chunk_off[nc] = tot;
+    total_sh = tot;
+  }
   __syncthreads();
   const uint32_t S = tc.n_segs;
-  for (uint32_t s = threadIdx.x; s <= S; s += 512) {
+  for (uint32_t s = threadIdx.x; s <= S; s += kPublishBlock) {
     const uint64_t v = chunk_off[min(tc.seg_blk[s], nc)];
     seg_off_out[s] = v;
     fin.result[s] = v;
     fin.result[S + 1 + s] = fin.img_seg[s];
   }
-  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (carry_sh > out_cap ? kErrIndex | kErrMerge : 0u);
+  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (total_sh > out_cap ? kErrIndex | kErrMerge : 0u);
   publish_seq(fin, S);
 }
 
@@ -1797,7 +1799,7 @@ hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* key
   });
   // bytes: every image read; the kept terms' bytes are added by the caller once known
   prof_end(prof, s, ev, kKChunkSort, (kb + wb) * (double)T);
-  k_chunk_publish<<<1, 512, 0, s>>>(tc, chunk_cnt, chunk_off, seg_off_out, fin, T, err);
+  k_chunk_publish<<<1, kPublishBlock, 0, s>>>(tc, chunk_cnt, chunk_off, seg_off_out, fin, T, err);
   ev = prof_begin(prof, s, kKMergeWrite);
   QIMAX_DISPATCH_K(KC, {
     if (WP == 64)
@@ -1899,19 +1901,28 @@ hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t*
   return hipGetLastError();
 }
 
-// Block i builds tiling i (segment-aligned tiles of at most job.tile images; cap tiles are
-// written, the ones past the actual count empty) from the image offsets of the segments,
-// so[s] = off[seg_in[s]] (so[s] = seg_in[s] when off is null: a tiling of the terms
-// themselves); block 0 also stores those offsets in img_seg unless it is null.
-__device__ __forceinline__ void make_tiling_block(const uint64_t* __restrict__ off, const uint64_t* __restrict__ seg_in,
-                                                  uint32_t S, uint64_t* __restrict__ img_seg, const TileJob2& job,
-                                                  uint64_t limit, uint32_t* err) {
-  const uint64_t tile = job.tile;
-  const uint32_t cap = job.cap;
-  uint32_t* __restrict__ seg_blk = job.seg_blk;
-  auto so = [&](uint32_t s) { return off ? off[seg_in[s]] : seg_in[s]; };
+// Even blocks build tiling j0, odd blocks tiling j1, each tiling in gridDim/2 parts (see
+// make_tiling_part); j0's lead part also stores the offsets in img_seg.
+constexpr uint32_t kTileLdsSegs = 2048;  // segments a tiling block keeps in LDS (more: one block)
+
+// Part `part` of n_parts blocks building one tiling (segment-aligned tiles of at most job.tile
+// elements; cap tiles written, the ones past the actual count empty) from the segment
+// offsets so[s] = off[seg_in[s]] (so[s] = seg_in[s] when off is null). Every part scans the
+// per-segment tile counts itself, keeping them and the offsets in LDS (n_parts must be 1
+// when S exceeds kTileLdsSegs), and writes tiles part*256 + i, stepping by n_parts*256;
+// part 0 also writes seg_blk, n_dev, xrange, the offsets to img_seg (unless null) and the
+// error bits.
+__device__ __forceinline__ void make_tiling_part(const uint64_t* __restrict__ off, const uint64_t* __restrict__ seg_in,
+                                                 uint32_t S, uint64_t* __restrict__ img_seg, const TileJob2& job,
+                                                 uint64_t limit, uint32_t* err, uint32_t part, uint32_t n_parts) {
+  __shared__ uint32_t sblk[kTileLdsSegs + 1];
+  __shared__ uint64_t sso[kTileLdsSegs + 1];
   __shared__ uint64_t sh[4];
   __shared__ uint64_t carry_sh;
+  const uint64_t tile = job.tile;
+  const uint32_t cap = job.cap;
+  const bool in_lds = S <= kTileLdsSegs, lead = part == 0;
+  auto so = [&](uint32_t s) { return off ? off[seg_in[s]] : seg_in[s]; };
   if (threadIdx.x == 0) carry_sh = 0;
   __syncthreads();
   for (uint32_t base = 0; base < S; base += 256) {
@@ -1920,7 +1931,11 @@ __device__ __forceinline__ void make_tiling_block(const uint64_t* __restrict__ o
     if (s < S) {
       const uint64_t a = so(s), b = so(s + 1);
       len = b - a;
-      if (img_seg) {
+      if (in_lds) {
+        sso[s] = a;
+        if (s + 1 == S) sso[S] = b;
+      }
+      if (lead && img_seg) {
         img_seg[s] = a;
         if (s + 1 == S) img_seg[S] = b;
       }
@@ -1929,38 +1944,47 @@ __device__ __forceinline__ void make_tiling_block(const uint64_t* __restrict__ o
     uint64_t tot;
     const uint64_t pre = block_excl_scan<256>(nt, sh, &tot);
     const uint64_t carry = carry_sh;
-    if (s < S) seg_blk[s] = (uint32_t)(carry + pre);
+    if (s < S) {
+      if (in_lds) sblk[s] = (uint32_t)(carry + pre);
+      if (lead) job.seg_blk[s] = (uint32_t)(carry + pre);
+    }
     __syncthreads();
     if (threadIdx.x == 0) carry_sh = carry + tot;
     __syncthreads();
   }
-  if (S == 0 && threadIdx.x == 0 && img_seg) img_seg[0] = so(0);
+  if (S == 0 && threadIdx.x == 0) {
+    if (in_lds) sso[0] = so(0);
+    if (lead && img_seg) img_seg[0] = so(0);
+  }
   const uint64_t total_img = so(S);
-  // more tiles or images than the capacity: the bound was not an upper bound (tiles are
-  // clamped below so that nothing reads past the buffers; the pass reports the error)
-  if (threadIdx.x == 0 && (carry_sh > cap || total_img > limit)) atomicOr(err, kErrIndex | kErrFanout);
   const uint32_t total = (uint32_t)min<uint64_t>(carry_sh, cap);
-  if (threadIdx.x == 0) {
-    seg_blk[S] = total;
+  if (lead && threadIdx.x == 0) {
+    // more tiles or elements than the capacity: the bound was not an upper bound (tiles are
+    // clamped below so that nothing reads past the buffers; the pass reports the error)
+    if (carry_sh > cap || total_img > limit) atomicOr(err, kErrIndex | kErrFanout);
+    job.seg_blk[S] = total;
     *job.n_dev = total;
   }
+  if (in_lds && threadIdx.x == 0) sblk[S] = total;
   __syncthreads();
-  if (threadIdx.x <= kXcds)
+  const uint32_t* blk_of = in_lds ? sblk : job.seg_blk;
+  if (lead && threadIdx.x <= kXcds)
     job.xrange[threadIdx.x] =
         threadIdx.x == kXcds
             ? total
-            : min(total, seg_boundary_at_or_after(seg_blk, S,
+            : min(total, seg_boundary_at_or_after(blk_of, S,
                                                   (uint32_t)(((uint64_t)threadIdx.x * total + kXcds - 1) / kXcds)));
-  for (uint32_t t = threadIdx.x; t < cap; t += 256) {
+  for (uint32_t t = part * 256 + threadIdx.x; t < cap; t += n_parts * 256) {
     if (t < total) {
       uint32_t lo = 0, hi = S;  // last segment s with seg_blk[s] <= t (non-empty)
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (seg_blk[mid] <= t) lo = mid; else hi = mid;
+        if (blk_of[mid] <= t) lo = mid; else hi = mid;
       }
-      const uint64_t b0 = so(lo) + (uint64_t)(t - seg_blk[lo]) * tile;
+      const uint64_t s0 = in_lds ? sso[lo] : so(lo), s1 = in_lds ? sso[lo + 1] : so(lo + 1);
+      const uint64_t b0 = s0 + (uint64_t)(t - blk_of[lo]) * tile;
       job.blk_begin[t] = min(b0, limit);
-      job.blk_end[t] = min(min(b0 + tile, so(lo + 1)), limit);
+      job.blk_end[t] = min(min(b0 + tile, s1), limit);
       job.blk_seg[t] = lo;
     } else {
       job.blk_begin[t] = 0;
@@ -1974,28 +1998,28 @@ __global__ void __launch_bounds__(256) k_make_tiles2(const uint64_t* __restrict_
                                                      const uint64_t* __restrict__ seg_in, uint32_t S,
                                                      uint64_t* __restrict__ img_seg, TileJob2 j0, TileJob2 j1,
                                                      uint64_t limit, uint32_t* err) {
-  if (blockIdx.x == 0) make_tiling_block(off, seg_in, S, img_seg, j0, limit, err);
-  else make_tiling_block(off, seg_in, S, nullptr, j1, limit, err);
+  const uint32_t part = blockIdx.x >> 1, n_parts = gridDim.x >> 1;
+  if ((blockIdx.x & 1) == 0) make_tiling_part(off, seg_in, S, img_seg, j0, limit, err, part, n_parts);
+  else make_tiling_part(off, seg_in, S, nullptr, j1, limit, err, part, n_parts);
 }
 
-// The first launch of a round. Block 0 clears the error word, then builds the tiling of the
-// input terms (see make_tiling_block; segments at seg_in[0..S], T terms). The other blocks
-// clear the tile counters and digit histograms and copy the round's descriptors (n16 16-byte
-// words) from mapped host memory to the device.
+// The first launch of a round. Blocks [0, n_tparts) build the tiling of the input terms (see
+// make_tiling_part; segments at seg_in[0..S], T terms), block 0 after clearing the error
+// word. The other blocks clear the tile counters and digit histograms and copy the round's
+// descriptors (n16 16-byte words) from mapped host memory to the device.
 __global__ void __launch_bounds__(256) k_round_start(const uint4* __restrict__ blob_host, uint4* __restrict__ blob_dev,
                                                      uint64_t n16, uint32_t* __restrict__ err,
                                                      uint32_t* __restrict__ ctr, uint32_t n_ctr,
                                                      uint32_t* __restrict__ ghist, uint64_t nh,
                                                      const uint64_t* __restrict__ seg_in, uint32_t S, TileJob2 job,
-                                                     uint64_t T) {
-  if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) *err = 0u;
-    __syncthreads();
-    make_tiling_block(nullptr, seg_in, S, nullptr, job, T, err);
+                                                     uint64_t T, uint32_t n_tparts) {
+  if (blockIdx.x < n_tparts) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0u;
+    make_tiling_part(nullptr, seg_in, S, nullptr, job, T, err, blockIdx.x, n_tparts);
     return;
   }
-  const uint64_t stride = (uint64_t)(gridDim.x - 1) * blockDim.x;
-  const uint64_t i0 = (uint64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)(gridDim.x - n_tparts) * blockDim.x;
+  const uint64_t i0 = (uint64_t)(blockIdx.x - n_tparts) * blockDim.x + threadIdx.x;
   for (uint64_t i = i0; i < n_ctr; i += stride) ctr[i] = 0u;
   for (uint64_t i = i0; i < nh; i += stride) ghist[i] = 0u;
   for (uint64_t i = i0; i < n16; i += stride) blob_dev[i] = blob_host[i];
@@ -2015,9 +2039,17 @@ __global__ void k_copy_u64(const uint64_t* __restrict__ in, uint64_t* __restrict
     out[i] = in[i];
 }
 
+// Blocks building one tiling of cap tiles: about 1024 tiles each, at most 64, one when the
+// segments do not fit a block's LDS.
+static uint32_t tiling_parts(uint32_t S, uint32_t cap) {
+  if (S > kTileLdsSegs) return 1;
+  return std::min<uint32_t>(cap / 1024 + 1, 64);
+}
+
 hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint32_t S, uint64_t* img_seg,
                               const TileJob2& j0, const TileJob2& j1, uint64_t limit, uint32_t* err, hipStream_t s) {
-  k_make_tiles2<<<2, 256, 0, s>>>(off, seg_in, S, img_seg, j0, j1, limit, err);
+  k_make_tiles2<<<2 * tiling_parts(S, std::max(j0.cap, j1.cap)), 256, 0, s>>>(off, seg_in, S, img_seg, j0, j1,
+                                                                               limit, err);
   return hipGetLastError();
 }
 
@@ -2028,8 +2060,9 @@ hipError_t launch_round_start(const void* blob_host, void* blob_dev, size_t blob
   const uint64_t n16 = blob_bytes / 16;
   const uint64_t work = std::max<uint64_t>(std::max<uint64_t>(nh, n16), n_ctr);
   const uint32_t g = (uint32_t)std::min<uint64_t>(grid_for(std::max<uint64_t>(work, 1), 256), 1024);
-  k_round_start<<<1 + g, 256, 0, s>>>((const uint4*)blob_host, (uint4*)blob_dev, n16, err, ctr, n_ctr, ghist, nh,
-                                      seg_in, S, job, T);
+  const uint32_t tp = tiling_parts(S, job.cap);
+  k_round_start<<<tp + g, 256, 0, s>>>((const uint4*)blob_host, (uint4*)blob_dev, n16, err, ctr, n_ctr, ghist, nh,
+                                       seg_in, S, job, T, tp);
   return hipGetLastError();
 }
 

@@ -31,8 +31,9 @@ KERNELS = {
     "expand": r"k_expand",
     "sort_hist": r"k_sort_(upsweep|hist)",
     "sort_scatter": r"k_sort_scatter",
+    "chunk_sort": r"k_chunk_sort",
     "merge_count": r"k_merge<[^,]+, [^,]+, 0>",
-    "merge_write": r"k_merge<[^,]+, [^,]+, [12]>",
+    "merge_write": r"k_merge<[^,]+, [^,]+, [12]>|k_chunk_compact",
     "copy": r"k_copy_u64",
 }
 
