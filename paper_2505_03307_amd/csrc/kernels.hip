@@ -135,6 +135,27 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
 }
 
 // Exclusive scan over a block of NT threads (NT a multiple of 64). sh: NT/64 words.
+// OR of v over the block (every thread gets it); sh holds NT/64 values.
+template <int NT, typename K>
+__device__ __forceinline__ K block_or(K v, K* sh) {
+  for (int o = 32; o > 0; o >>= 1) {
+    if constexpr (sizeof(K) <= 8) {
+      v |= (K)__shfl_xor((unsigned long long)v, o, 64);
+    } else {
+      const uint64_t lo = __shfl_xor((unsigned long long)(uint64_t)v, o, 64);
+      const uint64_t hi = __shfl_xor((unsigned long long)(uint64_t)(v >> 64), o, 64);
+      v |= ((K)hi << 64) | (K)lo;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  K r = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) r |= sh[w];
+  __syncthreads();
+  return r;
+}
+
 template <int NT>
 __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t* sh, uint64_t* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -294,6 +315,55 @@ __device__ __forceinline__ uint64_t wave_upper_bound(const uint64_t* __restrict_
   return wave_first_true(lo, hi, [&](uint64_t i) { return a[i] > x; });
 }
 
+// Image number r (mixed radix over the operators' column counts, first operator fastest) of
+// a term under the expanding operators: key and weight updated in place.
+template <typename K, int WP>
+__device__ __forceinline__ void expand_ops(K& key, typename WTraits<WP>::W& wv, uint32_t r, const PassArgs& pa,
+                                           const Exp1Desc* E1s, const Exp2Desc* E2s, uint32_t* err) {
+  for (uint32_t e = 0; e < pa.nE1; ++e) {
+    const Exp1Desc& E = E1s[e];
+    const uint32_t d = get_d(key, E.pos);
+    const uint32_t c = E.cnt[d];
+    if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
+    const uint32_t q = r / c;
+    const uint32_t k = r - q * c;
+    r = q;
+    key = set_d(key, E.pos, E.out[d][k]);
+    if constexpr (WP == 64) wv *= E.val[d][k]; else wv *= E.valf[d][k];
+  }
+  for (uint32_t e = 0; e < pa.nE2; ++e) {
+    const Exp2Desc& E = E2s[e];
+    const uint32_t in = local2(key, E.pa, E.pb);
+    const uint32_t c = E.cnt[in];
+    if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
+    const uint32_t q = r / c;
+    const uint32_t k = r - q * c;
+    r = q;
+    const uint32_t o = E.out[in][k];
+    key = set_d(key, E.pa, o >> 2);
+    key = set_d(key, E.pb, o & 3u);
+    if constexpr (WP == 64) wv *= E.val[in][k]; else wv *= E.valf[in][k];
+  }
+}
+
+// A term's image under the A chain (table or op list) and its fan-out f = prod of the
+// expanding operators' column counts (0 for a dropped entry; errors as in the count).
+template <typename K>
+__device__ __forceinline__ uint64_t a_chain_and_fanout(K& key, uint32_t& neg, const PassArgs& pa, const K* tk,
+                                                        const uint8_t* tn, uint32_t* err) {
+  if (pa.drop) return 0;
+  if (pa.useA) key = apply_table(key, tk, tn, neg);
+  else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+  uint64_t f = 1;
+  for (uint32_t e = 0; e < pa.nE1 && f <= 0xFFFFFFFFull; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
+  for (uint32_t e = 0; e < pa.nE2 && f <= 0xFFFFFFFFull; ++e) f *= pa.E2[e].cnt[local2(key, pa.E2[e].pa, pa.E2[e].pb)];
+  if (f > 0xFFFFFFFFull) {
+    atomicOr(err, kErrFanout);
+    f = 0;
+  }
+  return f;
+}
+
 template <typename K, int WP>
 __global__ void __launch_bounds__(kExpandBlock)
 k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const typename WTraits<WP>::W* __restrict__ w,
@@ -398,31 +468,7 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
     K key = kp[it];  // the parent's image under the A chain (and its sign), from the count
     W wv = wp[it];
     uint32_t neg = sp[it];
-    uint32_t r = rk[it];
-    for (uint32_t e = 0; e < pa.nE1; ++e) {
-      const Exp1Desc& E = E1s[e];
-      const uint32_t d = get_d(key, E.pos);
-      const uint32_t c = E.cnt[d];
-      if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
-      const uint32_t q = r / c;
-      const uint32_t k = r - q * c;
-      r = q;
-      key = set_d(key, E.pos, E.out[d][k]);
-      if constexpr (WP == 64) wv *= E.val[d][k]; else wv *= E.valf[d][k];
-    }
-    for (uint32_t e = 0; e < pa.nE2; ++e) {
-      const Exp2Desc& E = E2s[e];
-      const uint32_t in = local2(key, E.pa, E.pb);
-      const uint32_t c = E.cnt[in];
-      if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
-      const uint32_t q = r / c;
-      const uint32_t k = r - q * c;
-      r = q;
-      const uint32_t o = E.out[in][k];
-      key = set_d(key, E.pa, o >> 2);
-      key = set_d(key, E.pb, o & 3u);
-      if constexpr (WP == 64) wv *= E.val[in][k]; else wv *= E.valf[in][k];
-    }
+    expand_ops<K, WP>(key, wv, rk[it], pa, E1s, E2s, err);
     if (pa.useB) key = apply_table(key, tbk, tbn, neg);
     else for (uint32_t b = 0; b < pa.nB; ++b) key = apply_perm(key, pa.B[b], neg);
     if (neg) wv = -wv;
@@ -439,6 +485,113 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
       const uint32_t p = hp_begin + i / kRadix, d = i % kRadix;
       if (c) atomicAdd(&ghist[((uint64_t)seg * n_pass + p) * kRadix + d], c);
     }
+  }
+}
+
+// A round of small segments (every segment at most kChunkCap terms and images), one block
+// per segment: the A chain and fan-out of each term (as the count), their scan in LDS, and
+// the images (as the expansion), written to the segment's own chunk [s*kChunkCap, +n_img)
+// of keys_out / w_out. The chunk tiling (tiles = segments) goes to blk_begin, blk_end,
+// blk_seg, seg_blk (S + 1 entries) and the image count of segment s to img_cnt[s].
+constexpr int kSmallBlock = 256;
+template <typename K, int WP>
+__global__ void __launch_bounds__(kSmallBlock)
+k_expand_small(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__ w,
+               const uint64_t* __restrict__ seg_in, uint32_t S, const PassArgs* __restrict__ pas,
+               const uint32_t* __restrict__ seg_entry, K* __restrict__ keys_out,
+               typename WTraits<WP>::W* __restrict__ w_out, uint32_t* __restrict__ img_cnt,
+               uint64_t* __restrict__ blk_begin, uint64_t* __restrict__ blk_end, uint32_t* __restrict__ blk_seg,
+               uint32_t* __restrict__ seg_blk, uint32_t* err) {
+  using W = typename WTraits<WP>::W;
+  constexpr int kTabN = sizeof(K) <= 8 ? (int)sizeof(K) * 256 : 1;  // no tables for 16-byte keys
+  constexpr uint32_t kPer = kChunkCap / kSmallBlock;                 // scan run per thread
+  __shared__ K tk[kTabN];
+  __shared__ uint8_t tn[kTabN];
+  __shared__ K akey[kChunkCap];
+  __shared__ uint32_t off[kChunkCap + 1];
+  __shared__ uint8_t negs[kChunkCap];
+  __shared__ uint16_t pmap[kChunkCap];
+  __shared__ uint64_t scan_sh[kSmallBlock / 64];
+  __shared__ uint32_t nimg_sh;
+  const uint32_t s = blockIdx.x;
+  const PassArgs pa = pas[seg_entry[s]];
+  const uint64_t a0 = seg_in[s];
+  const uint64_t n64 = seg_in[s + 1] - a0;
+  const uint64_t c0 = (uint64_t)s * kChunkCap;
+  if (threadIdx.x == 0) {
+    blk_begin[s] = c0;
+    blk_seg[s] = s;
+    seg_blk[s] = s;
+    if (s + 1 == S) seg_blk[S] = S;
+  }
+  if (n64 > (uint64_t)kChunkCap) {  // the caller's bound did not hold
+    if (threadIdx.x == 0) {
+      atomicOr(err, kErrIndex | kErrFanout);
+      blk_end[s] = c0;
+      img_cnt[s] = 0;
+    }
+    return;
+  }
+  const uint32_t n = (uint32_t)n64;
+  if (pa.useA && !pa.drop) {
+    stage_table(pa.tA, tk, tn);
+    __syncthreads();
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += kSmallBlock) {
+    K key = keys[a0 + i];
+    uint32_t neg = 0;
+    const uint64_t f = a_chain_and_fanout(key, neg, pa, tk, tn, err);
+    akey[i] = key;
+    negs[i] = (uint8_t)(neg & 1u);
+    off[i] = (uint32_t)min<uint64_t>(f, kChunkCap + 1);  // larger: flagged by the total below
+  }
+  __syncthreads();
+  // exclusive scan of the fan-outs: thread t sums the run [t*kPer, (t+1)*kPer)
+  {
+    const uint32_t r0 = min(threadIdx.x * kPer, n), r1 = min(r0 + kPer, n);
+    uint64_t sum = 0;
+    for (uint32_t i = r0; i < r1; ++i) sum += off[i];
+    uint64_t tot;
+    uint64_t run = block_excl_scan<kSmallBlock>(sum, scan_sh, &tot);
+    __syncthreads();  // every run read before any is overwritten
+    for (uint32_t i = r0; i < r1; ++i) {
+      const uint32_t f = off[i];
+      off[i] = (uint32_t)min<uint64_t>(run, kChunkCap);
+      run += f;
+    }
+    if (threadIdx.x == 0) {
+      if (tot > (uint64_t)kChunkCap) atomicOr(err, kErrIndex | kErrFanout);
+      nimg_sh = tot > (uint64_t)kChunkCap ? 0u : (uint32_t)tot;
+      off[n] = nimg_sh;
+    }
+  }
+  __syncthreads();
+  const uint32_t n_img = nimg_sh;
+  // image -> parent map
+  for (uint32_t j = threadIdx.x; j < n; j += kSmallBlock) {
+    const uint32_t e = min(off[j + 1], n_img);
+    for (uint32_t g = off[j]; g < e; ++g) pmap[g] = (uint16_t)j;
+  }
+  if (pa.useB) {
+    __syncthreads();  // the A table is no longer read
+    stage_table(pa.tB, tk, tn);
+  }
+  __syncthreads();
+  for (uint32_t g = threadIdx.x; g < n_img; g += kSmallBlock) {
+    const uint32_t j = pmap[g];
+    K key = akey[j];
+    W wv = w[a0 + j];
+    uint32_t neg = negs[j];
+    expand_ops<K, WP>(key, wv, g - off[j], pa, pa.E1, pa.E2, err);
+    if (pa.useB) key = apply_table(key, tk, tn, neg);
+    else for (uint32_t b = 0; b < pa.nB; ++b) key = apply_perm(key, pa.B[b], neg);
+    if (neg) wv = -wv;
+    keys_out[c0 + g] = key;
+    w_out[c0 + g] = wv;
+  }
+  if (threadIdx.x == 0) {
+    blk_end[s] = c0 + n_img;
+    img_cnt[s] = n_img;
   }
 }
 
@@ -755,21 +908,9 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
   for (int r = 0; r < kItems; ++r) {
     const uint32_t li = r * 256 + threadIdx.x;
     if (li >= n) break;
-    uint64_t f = 0;
     K key = kr[r];
     uint32_t neg = 0;
-    if (!pa.drop) {
-      if (pa.useA) key = apply_table(key, tk, tn, neg);
-      else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
-      f = 1;
-      for (uint32_t e = 0; e < pa.nE1 && f <= 0xFFFFFFFFull; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
-      for (uint32_t e = 0; e < pa.nE2 && f <= 0xFFFFFFFFull; ++e)
-        f *= pa.E2[e].cnt[local2(key, pa.E2[e].pa, pa.E2[e].pb)];
-      if (f > 0xFFFFFFFFull) {
-        atomicOr(err, kErrFanout);
-        f = 0;
-      }
-    }
+    const uint64_t f = a_chain_and_fanout(key, neg, pa, tk, tn, err);
     sf[pad(li)] = f;
     // the A chain is applied once per term here; the expand kernel starts from this image
     akeys[begin + li] = key;
@@ -909,6 +1050,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   __shared__ uint64_t scan_sh[kWaves];
   __shared__ uint64_t cb[2];
   __shared__ uint32_t nb_sh, fallback_sh;
+  __shared__ __align__(16) uint8_t vary_sh[kWaves * sizeof(K)];
   const uint32_t blk = blockIdx.x;
   if (tc.n_dev && blk >= *tc.n_dev) return;
   auto none = [&]() {  // this chunk keeps nothing (empty, or handed to the fallback)
@@ -1088,7 +1230,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   // groups are then sorted by insertion (stable); a group above kMaxGroup elements sends the
   // chunk through stable passes over every digit instead (same order from here).
   constexpr uint32_t kMaxGroup = 32;
-  const bool two_pass = nb <= (uint32_t)kRadix && m < n_pass;
+  const bool two_pass = nb <= (uint32_t)kRadix && m > 0 && m < n_pass;
   const uint32_t g_shift = two_pass ? top_shift - 8u : top_shift;
   auto gkey = [&](K key) -> K { return (two_pass || m > 0) ? (K)(key >> g_shift) : (K)0; };
   if (two_pass) {
@@ -1111,7 +1253,13 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   }
   __syncthreads();
   if (fallback_sh) {
-    for (uint32_t p = 0; p < n_pass; ++p) radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> (8u * p)); });
+    // stable passes over the digits that vary inside the chunk (a constant digit leaves a
+    // stable pass's order unchanged)
+    K vary = 0;
+    for (uint32_t j = threadIdx.x; j < n; j += kChunkBlock) vary |= sk[j] ^ sk[0];
+    vary = block_or<kChunkBlock>(vary, (K*)vary_sh);
+    for (uint32_t p = 0; p < n_pass; ++p)
+      if ((uint32_t)(vary >> (8u * p)) & 255u) radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> (8u * p)); });
   } else {
     for (uint32_t j = threadIdx.x; j < n; j += kChunkBlock) {
       const uint32_t e = j + sbk[j];
@@ -1181,13 +1329,15 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
 
 // After the chunk-local sort and merge (one block): chunk_off = exclusive scan of the kept
 // counts of the n_chunks chunks (n_dev or n_blocks of tc), the segment output offsets
-// seg_off_out[s] = chunk_off[seg_blk[s]], and the packed readback area (see MergeFin); a total
-// above out_cap is reported in the error word there (the compaction then writes nothing).
+// seg_off_out[s] = chunk_off[seg_blk[s]], and the packed readback area (see MergeFin), whose
+// image offsets are fin.img_seg, or the scan of img_cnt when set; a total above out_cap is
+// reported in the error word there (the compaction then writes nothing).
 constexpr int kPublishBlock = 1024;
 __global__ void __launch_bounds__(kPublishBlock) k_chunk_publish(Tiling tc, const uint32_t* __restrict__ chunk_cnt,
                                                                  uint64_t* __restrict__ chunk_off,
                                                                  uint64_t* __restrict__ seg_off_out, MergeFin fin,
-                                                                 uint64_t out_cap, const uint32_t* __restrict__ err) {
+                                                                 const uint32_t* __restrict__ img_cnt, uint64_t out_cap,
+                                                                 const uint32_t* __restrict__ err) {
   __shared__ uint64_t sh[kPublishBlock / 64];
   __shared__ uint64_t total_sh;
   const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
@@ -1212,7 +1362,20 @@ __global__ void __launch_bounds__(kPublishBlock) k_chunk_publish(Tiling tc, cons
     const uint64_t v = chunk_off[min(tc.seg_blk[s], nc)];
     seg_off_out[s] = v;
     fin.result[s] = v;
-    fin.result[S + 1 + s] = fin.img_seg[s];
+    if (!img_cnt) fin.result[S + 1 + s] = fin.img_seg[s];
+  }
+  if (img_cnt) {  // image offsets of the segments from their counts (same serial-run scan)
+    const uint32_t ps = (S + kPublishBlock - 1) / kPublishBlock;
+    const uint32_t q0 = min(threadIdx.x * ps, S), q1 = min(q0 + ps, S);
+    uint64_t isum = 0;
+    for (uint32_t q = q0; q < q1; ++q) isum += img_cnt[q];
+    uint64_t itot;
+    uint64_t irun = block_excl_scan<kPublishBlock>(isum, sh, &itot);
+    for (uint32_t q = q0; q < q1; ++q) {
+      fin.result[S + 1 + q] = irun;
+      irun += img_cnt[q];
+    }
+    if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 1] = itot;
   }
   if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (total_sh > out_cap ? kErrIndex | kErrMerge : 0u);
   publish_seq(fin, S);
@@ -1710,6 +1873,27 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign,
   return hipGetLastError();
 }
 
+hipError_t launch_expand_small(int KC, int WP, const void* keys, const void* w, const uint64_t* seg_in, uint32_t S,
+                               uint64_t T_in, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out,
+                               void* w_out, uint32_t* img_cnt, const TileJob2& tiles, uint32_t* err, hipStream_t s,
+                               Prof* prof) {
+  if (S == 0) return hipSuccess;
+  hipEvent_t ev = prof_begin(prof, s, kKExpand);
+  QIMAX_DISPATCH_K(KC, {
+    if (WP == 64)
+      k_expand_small<K, 64><<<S, kSmallBlock, 0, s>>>((const K*)keys, (const double*)w, seg_in, S, pas, seg_entry,
+                                                      (K*)keys_out, (double*)w_out, img_cnt, tiles.blk_begin,
+                                                      tiles.blk_end, tiles.blk_seg, tiles.seg_blk, err);
+    else
+      k_expand_small<K, 32><<<S, kSmallBlock, 0, s>>>((const K*)keys, (const float*)w, seg_in, S, pas, seg_entry,
+                                                      (K*)keys_out, (float*)w_out, img_cnt, tiles.blk_begin,
+                                                      tiles.blk_end, tiles.blk_seg, tiles.seg_blk, err);
+  });
+  const double per = (4 << KC) + (WP == 64 ? 8 : 4);
+  prof_end(prof, s, ev, kKExpand, per * (double)T_in);  // the images' bytes are added once known
+  return hipGetLastError();
+}
+
 hipError_t launch_sort_pass(int KC, int WP, const void* keys_in, const void* w_in, void* keys_out, void* w_out,
                             uint64_t T, uint32_t shift, const Tiling& tl, uint64_t* hist, uint64_t* hist_off,
                             uint64_t* tmp, uint32_t* err, hipStream_t s, Prof* prof) {
@@ -1779,9 +1963,10 @@ hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* key
                                    void* tmp_w, void* keys_out, void* w_out, uint64_t T, const Tiling& tc,
                                    uint32_t n_pass, uint32_t m, const PassArgs* pas, const uint32_t* seg_entry,
                                    uint32_t* chunk_cnt, uint64_t* chunk_start, uint64_t* chunk_off,
-                                   uint64_t* seg_off_out, const MergeFin& fin, uint32_t* err, hipStream_t s,
-                                   Prof* prof) {
+                                   uint64_t* seg_off_out, const MergeFin& fin, const uint32_t* img_cnt, uint32_t* err,
+                                   hipStream_t s, Prof* prof) {
   if (tc.n_blocks == 0) {
+    if (img_cnt) return hipErrorInvalidValue;  // chunks are the segments: S is 0 too
     k_merge_publish<<<1, 256, 0, s>>>(tc, nullptr, seg_off_out, fin, err, 1);
     return hipGetLastError();
   }
@@ -1799,7 +1984,7 @@ hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* key
   });
   // bytes: every image read; the kept terms' bytes are added by the caller once known
   prof_end(prof, s, ev, kKChunkSort, (kb + wb) * (double)T);
-  k_chunk_publish<<<1, kPublishBlock, 0, s>>>(tc, chunk_cnt, chunk_off, seg_off_out, fin, T, err);
+  k_chunk_publish<<<1, kPublishBlock, 0, s>>>(tc, chunk_cnt, chunk_off, seg_off_out, fin, img_cnt, T, err);
   ev = prof_begin(prof, s, kKMergeWrite);
   QIMAX_DISPATCH_K(KC, {
     if (WP == 64)

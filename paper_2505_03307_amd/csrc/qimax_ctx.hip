@@ -274,6 +274,7 @@ struct qimax_ctx {
   DevBuf ptab;  // chain tables of a whole call, compiled in one launch
   DevBuf akeys, asign;  // input terms after their pass's A chain, and the signs (count -> expand)
   DevBuf chunk_cnt, chunk_start, chunk_off;  // chunk-local merge: kept runs per chunk
+  DevBuf img_cnt;                            // small rounds: image count per segment
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
   DevBuf mstatus;  // single-sweep count and merge state (one word per tile)
@@ -283,6 +284,7 @@ struct qimax_ctx {
   bool host_tiling = false;
   bool xcd_ranges = true;
   bool local_sort = true;     // top-digit passes + chunk-local sorts instead of all global passes
+  bool small_rounds = true;   // rounds of small segments: one block per segment (see run_round)
   int local_sort_m = -1;      // >= 0: force the number of top-digit passes
   uint32_t redo_cooldown = 0; // rounds left with global passes only after a chunk overflow
   bool autotune = true;       // choose among sort variants by measured time per size class
@@ -751,6 +753,24 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   if (sweep) QCHK(ensure(c, c->ghist, std::max<uint64_t>(nh, 1) * 4));
   QCHK(ensure(c, c->tile_ctr, 256 * 4));
   uint32_t* const ctr = (uint32_t*)c->tile_ctr.p;
+  // Bound path: with a small fan-out bound f, T_img <= f * T_in, so the image tilings are
+  // built on the device and every launch is sized by the bound (tiles past the real count
+  // are empty), and the image offsets come back with the merge's. Otherwise the image
+  // offsets are read back after the count and the tilings are built on the host.
+  double f_round = 0.0;
+  for (const RoundEntry& en : entries)
+    if (en.pass && !en.drop) f_round = std::max(f_round, en.pass->fanout_bound);
+  const bool bound_path = sweep && !c->host_tiling && f_round <= (double)kBoundPathMaxFanout && T_in > 0;
+  // Small round: every segment's terms and bounded images fit one chunk. One block per
+  // segment counts and expands it, then the chunk-local sort (whole segments) and merge run:
+  // four launches in all, where the fixed costs of the general path's launches would
+  // dominate rounds this small.
+  bool small = false;
+  if (bound_path && c->small_rounds && S <= kSmallMaxSegs) {
+    uint64_t len_max = 0;
+    for (uint32_t s = 0; s < S; ++s) len_max = std::max<uint64_t>(len_max, so_in[s + 1] - so_in[s]);
+    small = std::max(1.0, f_round) * (double)len_max <= (double)kChunkCap;
+  }
   // input tiling: segment-aligned tiles of at most kSortTile terms, built on the device from
   // the segment offsets (the tile count is known here exactly) by the round's first launch,
   // which also clears the error word, counters and histograms and pulls the descriptors
@@ -784,24 +804,18 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     return QIMAX_OK;
   };
-  QCHK(ensure(c, c->off, (T_in + 1) * 8));
-  QCHK(ensure(c, c->akeys, std::max<uint64_t>(T_in, 1) * c->kb));
-  QCHK(ensure(c, c->asign, std::max<uint64_t>(T_in, 1)));
-  QCHK(status_words(tl_in.n_blocks));
-  c->mepoch += 1;
-  HIPCHK(c, launch_count_scan(c->KC, k_in, T_in, tl_in, pas, sent, (uint64_t*)c->off.p, (uint64_t*)c->mstatus.p,
-                              ctr + kCtrCount, c->mepoch, (uint32_t*)c->err.p, c->akeys.p, (uint8_t*)c->asign.p,
-                              c->stream, &c->prof), "count");
+  if (!small) {
+    QCHK(ensure(c, c->off, (T_in + 1) * 8));
+    QCHK(ensure(c, c->akeys, std::max<uint64_t>(T_in, 1) * c->kb));
+    QCHK(ensure(c, c->asign, std::max<uint64_t>(T_in, 1)));
+    QCHK(status_words(tl_in.n_blocks));
+    c->mepoch += 1;
+    HIPCHK(c, launch_count_scan(c->KC, k_in, T_in, tl_in, pas, sent, (uint64_t*)c->off.p, (uint64_t*)c->mstatus.p,
+                                ctr + kCtrCount, c->mepoch, (uint32_t*)c->err.p, c->akeys.p, (uint8_t*)c->asign.p,
+                                c->stream, &c->prof), "count");
+  }
   QCHK(ensure(c, c->img_seg, (S + 1) * 8));
   uint32_t e = 0;
-  // Bound path: with a small fan-out bound f, T_img <= f * T_in, so the image tilings are
-  // built on the device and every launch is sized by the bound (tiles past the real count
-  // are empty), and the image offsets come back with the merge's. Otherwise the image
-  // offsets are read back now and the tilings are built on the host.
-  double f_round = 0.0;
-  for (const RoundEntry& en : entries)
-    if (en.pass && !en.drop) f_round = std::max(f_round, en.pass->fanout_bound);
-  const bool bound_path = sweep && !c->host_tiling && f_round <= (double)kBoundPathMaxFanout && T_in > 0;
   uint64_t T_img = 0;
   Tiling tl_exp{}, tl{};
   if (bound_path) {
@@ -822,8 +836,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       *tls[i] = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
                        (const uint32_t*)(d + o4), caps[i], S, (const uint32_t*)(d + o5), (const uint32_t*)(d + o6)};
     }
-    HIPCHK(c, launch_make_tiles2((const uint64_t*)c->off.p, seg_in, S, (uint64_t*)c->img_seg.p, jobs[0], jobs[1],
-                                 T_img, (uint32_t*)c->err.p, c->stream), "tiles");
+    if (!small)
+      HIPCHK(c, launch_make_tiles2((const uint64_t*)c->off.p, seg_in, S, (uint64_t*)c->img_seg.p, jobs[0], jobs[1],
+                                   T_img, (uint32_t*)c->err.p, c->stream), "tiles");
   } else {
     HIPCHK(c, launch_gather_u64((const uint64_t*)c->off.p, seg_in, (uint64_t*)c->img_seg.p, S + 1, c->stream,
                                 &c->prof), "gather");
@@ -853,7 +868,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   int tune_cand = 0;
   bool tune_timed = false;
   bool xr = c->xcd_ranges;
-  if (sweep) {
+  if (small) m_top = 0;  // whole segments sorted in LDS
+  if (sweep && !small) {
     if (c->local_sort && c->redo_cooldown == 0) {
       uint64_t seg_max = 0;
       for (uint32_t s = 0; s < S; ++s)
@@ -879,10 +895,27 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   const bool hist_in_expand = sweep && m_top <= kExpandHistPasses;
   // ---- expand into images
   const size_t eb = c->kb, wbt = c->wb;
-  QCHK(ensure(c, c->ik[0], std::max<uint64_t>(T_img, 1) * eb));
-  QCHK(ensure(c, c->iw[0], std::max<uint64_t>(T_img, 1) * wbt));
-  QCHK(ensure(c, c->ik[1], std::max<uint64_t>(T_img, 1) * eb));
-  QCHK(ensure(c, c->iw[1], std::max<uint64_t>(T_img, 1) * wbt));
+  // image buffers: the capacity, or for a small round S chunks of kChunkCap
+  const uint64_t n_work = std::max<uint64_t>(small ? std::max<uint64_t>(T_img, (uint64_t)S * kChunkCap) : T_img, 1);
+  QCHK(ensure(c, c->ik[0], n_work * eb));
+  QCHK(ensure(c, c->iw[0], n_work * wbt));
+  QCHK(ensure(c, c->ik[1], n_work * eb));
+  QCHK(ensure(c, c->iw[1], n_work * wbt));
+  Tiling tc_small{};
+  if (small) {
+    const size_t o1 = 0, o2 = align256((size_t)S * 8), o3 = o2 + align256((size_t)S * 8);
+    const size_t o4 = o3 + align256((size_t)S * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
+    QCHK(ensure(c, c->dtile[0], o5 + 256));
+    QCHK(ensure(c, c->img_cnt, (size_t)std::max<uint32_t>(S, 1) * 4));
+    uint8_t* d = (uint8_t*)c->dtile[0].p;
+    const TileJob2 job{(uint64_t)kChunkCap, S, 0, (uint64_t*)(d + o1), (uint64_t*)(d + o2), (uint32_t*)(d + o3),
+                       (uint32_t*)(d + o4), nullptr, nullptr};
+    tc_small = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
+                      (const uint32_t*)(d + o4), S, S, nullptr, nullptr};
+    HIPCHK(c, launch_expand_small(c->KC, c->WP, k_in, w_in, seg_in, S, T_in, pas, sent, c->ik[0].p, c->iw[0].p,
+                                  (uint32_t*)c->img_cnt.p, job, (uint32_t*)c->err.p, c->stream, &c->prof),
+           "expand");
+  } else
   HIPCHK(c, launch_expand(c->KC, c->WP, c->akeys.p, (const uint8_t*)c->asign.p, w_in, T_in,
                           (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent, seg_in, any_b_tables, e_bytes,
                           c->ik[0].p, c->iw[0].p, hist_in_expand ? (uint32_t*)c->ghist.p : nullptr, n_pass,
@@ -891,7 +924,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
   int cur = 0;
   int pre_chunk = -1;       // slot holding the images before the chunk-local sort
-  if (!sweep) {
+  if (small) {
+    pre_chunk = 0;
+  } else if (!sweep) {
     QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
     QCHK(ensure(c, c->hist, hsize * 8));
     QCHK(ensure(c, c->hist_off, (hsize + 1) * 8));
@@ -928,21 +963,23 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure_zres(c, 2 * (size_t)S + 4));
   MergeFin fin{(const uint64_t*)c->img_seg.p, c->zres_dev, 0};
   bool chunk_path = pre_chunk >= 0;  // chunk-local sort fused with the merge
+  const Tiling& tc_chunk = small ? tc_small : tl_exp;  // the chunks' nominal tiles
   auto merge_and_read = [&]() -> qimax_status {
     if (sweep) {  // a fresh sequence word for these results
       fin.seq = ++c->zseq;
       c->zres[2 * (size_t)S + 3] = 0;
     }
     if (chunk_path) {
-      const size_t nc = std::max<uint32_t>(tl_exp.n_blocks, 1);
+      const size_t nc = std::max<uint32_t>(tc_chunk.n_blocks, 1);
       QCHK(ensure(c, c->chunk_cnt, nc * 4));
       QCHK(ensure(c, c->chunk_start, nc * 8));
       QCHK(ensure(c, c->chunk_off, (nc + 1) * 8));
       HIPCHK(c, launch_chunk_sort_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, c->ik[cur ^ 1].p,
-                                        c->iw[cur ^ 1].p, c->pk[slot].p, c->pw[slot].p, T_img, tl_exp, n_pass, m_top,
+                                        c->iw[cur ^ 1].p, c->pk[slot].p, c->pw[slot].p, T_img, tc_chunk, n_pass, m_top,
                                         pas, sent, (uint32_t*)c->chunk_cnt.p, (uint64_t*)c->chunk_start.p,
                                         (uint64_t*)c->chunk_off.p, (uint64_t*)c->pseg[slot].p, fin,
-                                        (uint32_t*)c->err.p, c->stream, &c->prof), "chunk sort");
+                                        small ? (const uint32_t*)c->img_cnt.p : nullptr, (uint32_t*)c->err.p,
+                                        c->stream, &c->prof), "chunk sort");
     } else {
       uint64_t* mstatus = nullptr;
       if (sweep) {
@@ -966,7 +1003,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   };
   QCHK(merge_and_read());
   bool sorted_again = false;
-  if (e == kErrRedo && chunk_path) {
+  if (e == kErrRedo && chunk_path && !small) {  // (whole-segment chunks never overflow)
     sorted_again = true;
     // a bucket did not fit a chunk: sort the round again with global passes over every digit
     // (stable passes on the top-digit grouping give the same order as on the images) and merge
@@ -1021,9 +1058,13 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       auto fix = [&](int kind, double bytes) {
         if ((c->prof.mask >> kind) & 1u) c->prof.bytes[kind] -= bytes;
       };
-      fix(kKExpand, (double)(eb + wbt) * d);
-      fix(kKSortHist, (double)eb * d * ((hist_in_expand ? 0 : 1) + (sorted_again ? 1 : 0)));  // upsweeps run
-      fix(kKSortScatter, 2.0 * (double)(eb + wbt) * (sorted_again ? n_pass + m_top : m_top) * d);
+      if (small) {  // the images' bytes, known now
+        if ((c->prof.mask >> kKExpand) & 1u) c->prof.bytes[kKExpand] += (double)(eb + wbt) * (double)T_img;
+      } else {
+        fix(kKExpand, (double)(eb + wbt) * d);
+      }
+      if (!small) fix(kKSortHist, (double)eb * d * ((hist_in_expand ? 0 : 1) + (sorted_again ? 1 : 0)));  // upsweeps run
+      if (!small) fix(kKSortScatter, 2.0 * (double)(eb + wbt) * (sorted_again ? n_pass + m_top : m_top) * d);
       if (m_top < n_pass) fix(kKChunkSort, (double)(eb + wbt) * d);
       if (!chunk_path) fix(kKMergeWrite, (double)(eb + wbt) * d);
     }
@@ -1638,6 +1679,8 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     c->host_tiling = env && env[0] == '1';
     env = std::getenv("QIMAX_XCD_RANGES");  // 0: sort tiles claimed in one global order
     c->xcd_ranges = !(env && env[0] == '0');
+    env = std::getenv("QIMAX_SMALL_ROUNDS");  // 0: small rounds take the general path too
+    c->small_rounds = !(env && env[0] == '0');
     env = std::getenv("QIMAX_LOCAL_SORT");  // 0: every digit by global passes
     c->local_sort = !(env && env[0] == '0');
     env = std::getenv("QIMAX_LOCAL_SORT_M");  // force the number of top-digit passes (tests)
@@ -1896,7 +1939,7 @@ void qimax_destroy(qimax_ctx* c) {
   DevBuf* bufs[] = {&c->keys, &c->w, &c->seg, &c->pk[0], &c->pk[1], &c->pw[0], &c->pw[1], &c->pseg[0],
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
-                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->chunk_cnt, &c->chunk_start,
+                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->chunk_cnt, &c->chunk_start, &c->img_cnt,
                     &c->chunk_off};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);

@@ -99,6 +99,7 @@ constexpr int kSortBlock = 256;            // threads per sort / merge block
 constexpr int kSortItems = 16;             // items per thread
 constexpr int kSortTile = kSortBlock * kSortItems;  // elements per tile (4096)
 constexpr int kRadixBits = 8;
+constexpr uint32_t kSmallMaxSegs = 8192;  // segments of a small round (one block each)
 constexpr int kChunkCap = 4096;  // elements a chunk-local sort holds in LDS (nominal chunks: kExpandTile)
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kExpandBlock = 256;
@@ -240,13 +241,15 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
 // tmp at the chunk's range; a one-block scan of the kept counts gives the output offsets,
 // seg_off_out and the packed readback area (fin); the kept runs then move to keys_out/w_out.
 // chunk_cnt / chunk_start: tc.n_blocks words; chunk_off: tc.n_blocks + 1. Sets kErrRedo when
-// a bucket does not fit a chunk (the outputs are then not valid).
+// a bucket does not fit a chunk (the outputs are then not valid). With m = 0 every chunk must
+// be a whole segment (at most kChunkCap elements). img_cnt (S words, or null): the image
+// counts of the segments, scanned into the readback area instead of fin.img_seg.
 hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* tmp_keys,
                                    void* tmp_w, void* keys_out, void* w_out, uint64_t T, const Tiling& tc,
                                    uint32_t n_pass, uint32_t m, const PassArgs* pas, const uint32_t* seg_entry,
                                    uint32_t* chunk_cnt, uint64_t* chunk_start, uint64_t* chunk_off,
-                                   uint64_t* seg_off_out, const MergeFin& fin, uint32_t* err, hipStream_t s,
-                                   Prof* prof = nullptr);
+                                   uint64_t* seg_off_out, const MergeFin& fin, const uint32_t* img_cnt, uint32_t* err,
+                                   hipStream_t s, Prof* prof = nullptr);
 
 // Compile chains of permutation ops into ChainTables, one job per chain (jobs in device memory).
 hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hipStream_t s, Prof* prof = nullptr);
@@ -274,6 +277,16 @@ struct TileJob2 {
 // limit sets an error bit.
 hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint32_t S, uint64_t* img_seg,
                               const TileJob2& j0, const TileJob2& j1, uint64_t limit, uint32_t* err, hipStream_t s);
+
+// A round whose segments each hold at most kChunkCap terms and images, one block per
+// segment: A chain, fan-out, scan and images of segment s, written to its chunk
+// [s*kChunkCap, s*kChunkCap + n_img(s)) of keys_out / w_out (S*kChunkCap elements); the
+// chunk tiling goes to tiles.blk_begin / blk_end / blk_seg (S entries) and seg_blk (S + 1),
+// n_img(s) to img_cnt[s]. Segments whose counts exceed the bound raise kErrFanout.
+hipError_t launch_expand_small(int KC, int WP, const void* keys, const void* w, const uint64_t* seg_in, uint32_t S,
+                               uint64_t T_in, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out,
+                               void* w_out, uint32_t* img_cnt, const TileJob2& tiles, uint32_t* err, hipStream_t s,
+                               Prof* prof = nullptr);
 // The first launch of a round: clears *err, ctr[0..n_ctr) and ghist[0..nh), copies blob_bytes
 // (a multiple of 16, both addresses 16-byte aligned) from blob_host (mapped host memory, its
 // device address) to blob_dev, and builds one tiling of the terms themselves (segments at

@@ -143,14 +143,16 @@ def test_served_results_equal_alone():
 
 @pytest.mark.parametrize("variant", [("QIMAX_HOST_TILING", "1"), ("QIMAX_SORT_CLASSIC", "1"),
                                      ("QIMAX_LOCAL_SORT", "0"), ("QIMAX_LOCAL_SORT_M", "0"),
-                                     ("QIMAX_LOCAL_SORT_M", "1"), ("QIMAX_XCD_RANGES", "0")])
+                                     ("QIMAX_LOCAL_SORT_M", "1"), ("QIMAX_XCD_RANGES", "0"),
+                                     ("QIMAX_SMALL_ROUNDS", "0")])
 def test_tiling_and_sort_variants_bit_identical(variant, monkeypatch):
     """Image tilings built on the device from the fan-out bound (the default for rounds whose
     bound is small) or on the host after reading the image count back; the classic
     multi-launch sort; every digit by global passes, or the top 0 / 1 digits followed by
-    chunk-local sorts (0 makes every segment above a chunk fall back to global passes): all
-    are stable sorts of the same images, hence identical sums, so the results must agree bit
-    for bit, alone and batched."""
+    chunk-local sorts (0 makes every segment above a chunk fall back to global passes); small
+    rounds (one block per segment) or the general path for them: all are stable sorts of the
+    same images, hence identical sums, so the results must agree bit for bit, alone and
+    batched."""
     name, value = variant
     cs = mixed_circuits()
     with Batch(precision=64) as b:
@@ -189,10 +191,12 @@ def test_chunk_overflow_sorts_again(monkeypatch):
     compare_fp64(got, oracle_arrays(oracle.propagate(c), c.n), label=c.name)
 
 
-def test_autotuner_settles_and_keeps_results():
+def test_autotuner_settles_and_keeps_results(monkeypatch):
     """The sort variant is chosen per size class of rounds from measured times: after a few
     runs of the same circuit every explored class is fixed, and every run gives the same
-    generators bit for bit (the variants are the same stable sort)."""
+    generators bit for bit (the variants are the same stable sort). Small rounds (one block
+    per segment, no sort variants) are turned off so that this circuit's rounds are tuned."""
+    monkeypatch.setenv("QIMAX_SMALL_ROUNDS", "0")
     c = W.c2_clifford_rz(seed=1, n=24, depth=100, n_rz=20)
     with Simulator(c.n, prune_eps=c.eps) as s:
         runs = []
@@ -206,3 +210,20 @@ def test_autotuner_settles_and_keeps_results():
     for r in runs[1:]:
         for x, y in zip(r, runs[0]):
             assert np.array_equal(x, y)
+
+
+def test_batch_with_more_segments_than_a_tiling_block_holds():
+    """More than 2048 generators in one batch: the round tilings are then built by a single
+    block reading its segment offsets from global memory instead of LDS. Every result equals
+    the single-circuit result bit for bit."""
+    cs = [W.c2_clifford_rz(seed=100 + i, n=48, depth=12, n_rz=2) for i in range(45)]
+    say("segments", sum(c.n for c in cs))
+    assert sum(c.n for c in cs) > 2048
+    with Batch(max_n=64) as b:
+        ids = [b.submit(c) for c in cs]
+        b.run()
+        for c, cid in zip(cs, ids):
+            got = b.fetch(cid)
+            ref = alone(c)
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y), c.name
