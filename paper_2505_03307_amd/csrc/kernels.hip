@@ -1393,13 +1393,30 @@ __global__ void __launch_bounds__(256) k_chunk_compact(const K* __restrict__ key
   if (tc.n_dev && blk >= *tc.n_dev) return;
   const uint32_t cnt = chunk_cnt[blk];
   const uint64_t src = chunk_start[blk], dst = chunk_off[blk];
-  if (dst + cnt > out_cap) {
+  if (dst + cnt > out_cap || cnt > (uint32_t)kChunkCap) {
     if (threadIdx.x == 0 && cnt) atomicOr(err, kErrIndex | kErrMerge);
     return;
   }
-  for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
-    keys_out[dst + i] = keys_in[src + i];
-    w_out[dst + i] = w_in[src + i];
+  // every load of a thread's share in flight before its stores (a chunk keeps at most
+  // kChunkCap terms: kChunkCap / 256 per thread)
+  constexpr int kPer = kChunkCap / 256;
+  K kv[kPer];
+  W wv[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const uint32_t i = r * 256 + threadIdx.x;
+    if (i < cnt) {
+      kv[r] = keys_in[src + i];
+      wv[r] = w_in[src + i];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const uint32_t i = r * 256 + threadIdx.x;
+    if (i < cnt) {
+      keys_out[dst + i] = kv[r];
+      w_out[dst + i] = wv[r];
+    }
   }
 }
 
