@@ -103,6 +103,7 @@ struct Pass {
   int egroup = -1;
   double fanout_bound = 1.0;
   ChainTable pre[2] = {};  // A / B chain tables compiled ahead of the rounds (tab_key set)
+  mutable int64_t groups[2] = {-1, -1};  // operator groups of A / B (see pass_groups)
 };
 
 // The paper's CX look-up tables (Sec. III-C-2), indexed [p_c][p_t] with I=0, X=1, Y=2, Z=3:
@@ -641,6 +642,13 @@ uint64_t op_groups(const std::vector<const HostOp*>& v, int exclude) {
   return (uint64_t)(std::unique(g.begin(), g.end()) - g.begin());
 }
 
+// Operator groups of a pass's A (ab = 0) or B (ab = 1) chain other than its expanding group:
+// the update count per term of that chain; found once per pass.
+uint64_t pass_groups(const Pass& p, int ab) {
+  if (p.groups[ab] < 0) p.groups[ab] = (int64_t)op_groups(ab ? p.B : p.A, p.egroup);
+  return (uint64_t)p.groups[ab];
+}
+
 // Runs one round: every segment s of the input (k_in, w_in; device offsets seg_in, host
 // offsets so_in) is processed with the pass of entries[seg_entry[s]], in one set of
 // launches for all segments. The merged result goes to pass slot `slot`; so_out / so_img
@@ -1082,9 +1090,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     const RoundEntry& en = entries[seg_entry[s]];
     if (en.drop || !en.pass) continue;
     const Pass& p = *en.pass;
-    const uint64_t u = op_groups(p.A, p.egroup) * (so_in[s + 1] - so_in[s]) +
+    const uint64_t u = pass_groups(p, 0) * (so_in[s + 1] - so_in[s]) +
                        (p.E.empty() ? 0 : so_img[s + 1] - so_img[s]) +
-                       op_groups(p.B, p.egroup) * (so_out[s + 1] - so_out[s]);
+                       pass_groups(p, 1) * (so_out[s + 1] - so_out[s]);
     total_upd += u;
     if (upd) (*upd)[seg_entry[s]] += u;
   }
@@ -1231,9 +1239,9 @@ qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
     if (s != QIMAX_OK) return s;  // committed state untouched
     if (c->gen_updates.size() != c->n) c->gen_updates.assign(c->n, 0);
     for (uint32_t j = 0; j < c->n; ++j)
-      c->gen_updates[j] += op_groups(en.pass->A, en.pass->egroup) * (so_in[j + 1] - so_in[j]) +
+      c->gen_updates[j] += pass_groups(*en.pass, 0) * (so_in[j + 1] - so_in[j]) +
                            (en.pass->E.empty() ? 0 : so_img[j + 1] - so_img[j]) +
-                           op_groups(en.pass->B, en.pass->egroup) * (so_out[j + 1] - so_out[j]);
+                           pass_groups(*en.pass, 1) * (so_out[j + 1] - so_out[j]);
     if (!en.pass->E.empty()) c->st.passes += 1;
     k_in = c->pk[slot].p;
     w_in = c->pw[slot].p;
