@@ -2086,6 +2086,20 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
   return hipGetLastError();
 }
 
+// Device memory <- mapped host memory, 16 bytes per thread and step.
+__global__ void k_pull(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n16) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_pull(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16) return hipErrorInvalidValue;
+  const uint64_t n16 = bytes / 16;
+  k_pull<<<std::min<uint32_t>(grid_for(n16, 256), 256), 256, 0, s>>>((const uint4*)src, (uint4*)dst, n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hipStream_t s, Prof* prof) {
   (void)prof;
   if (n_jobs == 0) return hipSuccess;

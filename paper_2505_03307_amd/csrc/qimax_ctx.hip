@@ -291,7 +291,7 @@ struct qimax_ctx {
   bool autotune = true;       // choose among sort variants by measured time per size class
   std::map<uint32_t, TuneState> tune;
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
-  DevBuf gr_in, gr_out;  // grouping pass: gate codes, angles, chains in; composed PTMs out
+  DevBuf gr_in, gr_out;  // grouping pass inputs; batch admission lists
   uint64_t* pinned = nullptr;  // small pinned host scratch
   size_t pinned_words = 0;
 
@@ -1201,7 +1201,7 @@ qimax_status prebuild_tables(qimax_ctx* c, std::vector<Pass>& passes) {
     jobs[j] = TableJob{(const PermDesc*)(ds + oP) + first, (uint32_t)v.size(), 0, tk, tn};
     p.pre[ab] = ChainTable{tk, tn};
   }
-  HIPCHK(c, hipMemcpyAsync(ds, hs, host_bytes, hipMemcpyHostToDevice, c->stream), "upload chains");
+  HIPCHK(c, launch_pull(c->stage_dev[1], ds, host_bytes, c->stream), "upload chains");
   HIPCHK(c, launch_build_tables(c->KC, (const TableJob*)(ds + oJ), (uint32_t)chains.size(), c->stream, &c->prof),
          "chain tables");
   return QIMAX_OK;
@@ -1372,13 +1372,13 @@ qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const 
   }
   const double* ptm = nullptr;
   if (!chains.empty()) {
-    // one upload and one readback, both through pinned staging (idle stream: no earlier
-    // copy still reads the staging areas)
+    // inputs through mapped staging, pulled to the device by a kernel; the composed PTMs
+    // written by the kernel straight into mapped staging. (No launch still reads or writes
+    // the staging areas here: a round's first launch reads them, and every round's results
+    // have been waited for; a call's grouping result has been read.)
     const size_t oG = 0, oT = align256(m), oI = oT + align256(m * 8), oO = oI + align256(idx.size() * 4);
     const size_t up = oO + align256(chain_off.size() * 4), down = chains.size() * 16 * 8;
     QCHK(ensure(c, c->gr_in, up));
-    QCHK(ensure(c, c->gr_out, down));
-    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     QCHK(ensure_stage(c, 0, up));
     QCHK(ensure_stage(c, 1, down));
     uint8_t* hs = (uint8_t*)c->stage[0];
@@ -1388,11 +1388,10 @@ qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const 
     std::memcpy(hs + oI, idx.data(), idx.size() * 4);
     std::memcpy(hs + oO, chain_off.data(), chain_off.size() * 4);
     const uint8_t* dg = (const uint8_t*)c->gr_in.p;
-    HIPCHK(c, hipMemcpyAsync(c->gr_in.p, hs, up, hipMemcpyHostToDevice, c->stream), "group upload");
+    HIPCHK(c, launch_pull(c->stage_dev[0], c->gr_in.p, up, c->stream), "group upload");
     HIPCHK(c, launch_compose_ptm(dg + oG, (const double*)(dg + oT), (const uint32_t*)(dg + oI),
-                                 (const uint32_t*)(dg + oO), (uint32_t)chains.size(), (double*)c->gr_out.p, c->stream,
-                                 &c->prof), "compose_ptm");
-    HIPCHK(c, hipMemcpyAsync(c->stage[1], c->gr_out.p, down, hipMemcpyDeviceToHost, c->stream), "group readback");
+                                 (const uint32_t*)(dg + oO), (uint32_t)chains.size(), (double*)c->stage_dev[1],
+                                 c->stream, &c->prof), "compose_ptm");
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     ptm = (const double*)c->stage[1];
   }

@@ -291,6 +291,10 @@ hipError_t launch_expand_small(int KC, int WP, const void* keys, const void* w, 
 // (a multiple of 16, both addresses 16-byte aligned) from blob_host (mapped host memory, its
 // device address) to blob_dev, and builds one tiling of the terms themselves (segments at
 // seg_in[0..S] on the device, T terms in all; no image offsets stored).
+// bytes (a multiple of 16, both addresses 16-byte aligned) from src (mapped host memory, its
+// device address) to dst (device memory), in stream order: an upload with no copy call.
+hipError_t launch_pull(const void* src, void* dst, size_t bytes, hipStream_t s);
+
 hipError_t launch_round_start(const void* blob_host, void* blob_dev, size_t blob_bytes, uint32_t* err, uint32_t* ctr,
                               uint32_t n_ctr, uint32_t* ghist, uint64_t nh, const uint64_t* seg_in, uint32_t S,
                               const TileJob2& job, uint64_t T, hipStream_t s);
