@@ -2092,6 +2092,10 @@ qimax_status admit(qimax_batch* b) {
 // Copy a finished circuit's generators (segments [s0, s0+n) of the committed array) to the host.
 qimax_status take_result(qimax_batch* b, BatchCirc& bc, size_t s0) {
   qimax_ctx* c = b->c;
+  // a round returns once its offsets are in, while its compaction may still write the
+  // terms: wait for the stream before copying them (the copies below are not ordered after
+  // the library's non-blocking stream)
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   const uint64_t a = b->so[s0], e = b->so[s0 + bc.n];
   bc.res_off.resize(bc.n + 1);
   for (uint32_t j = 0; j <= bc.n; ++j) bc.res_off[j] = b->so[s0 + j] - a;
