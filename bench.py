@@ -182,7 +182,7 @@ def main():
     ap.add_argument("--serve-one-batch", action="store_true", help="also serve the trace with a single batch")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported "
               "(generator sharding across GPUs is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
 
