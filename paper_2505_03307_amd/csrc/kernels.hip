@@ -375,15 +375,15 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
   constexpr int kWaves = kExpandBlock / 64;
   constexpr int kWin = kExpandTile + 1;
   constexpr int kTab = (int)sizeof(K) * 256;
-  // dynamic LDS: offset window, image -> parent map, the chain tables that this pass uses,
-  // then its expanding operators' descriptors
+  // dynamic LDS: offset window (relative to the tile's first image), image -> parent map,
+  // the chain tables that this pass uses, then its expanding operators' descriptors
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t blk = blockIdx.x;
   const uint32_t seg = tl.blk_seg[blk];
   const PassArgs pa = pas[seg_entry[seg]];
-  uint64_t* win = (uint64_t*)lds;
-  uint16_t* pmap = (uint16_t*)(lds + kWin * 8);
-  uint8_t* cur = lds + kWin * 8 + kExpandTile * 2;
+  int32_t* win = (int32_t*)lds;
+  uint16_t* pmap = (uint16_t*)(lds + kWin * 4);
+  uint8_t* cur = lds + kExpandLdsHead;
   K* tbk = (K*)cur;
   cur += pa.useB ? kTab * sizeof(K) : 0;
   uint8_t* tbn = cur;
@@ -418,63 +418,70 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
   __syncthreads();
   const uint64_t plo = bounds[0], phi = bounds[1];
   const uint64_t nwin = phi - plo + 2;  // off[plo .. phi+1]
-  const bool in_lds = nwin <= (uint64_t)kWin;
+  // (offsets below 2^31 keep every window entry minus g0 within 32 bits)
+  const bool in_lds = nwin <= (uint64_t)kWin && T_img < (1ull << 31);
   if (in_lds) {
-    for (uint64_t k = threadIdx.x; k < nwin; k += kExpandBlock) win[k] = off[plo + k];
+    for (uint64_t k = threadIdx.x; k < nwin; k += kExpandBlock) win[k] = (int32_t)((int64_t)off[plo + k] - (int64_t)g0);
     __syncthreads();
-    // image -> parent map of the tile: window parent j covers images [win[j], win[j+1])
+    // image -> parent map of the tile: window parent j covers images [g0 + win[j], g0 + win[j+1])
+    const int32_t n_t = (int32_t)(g1 - g0);
     for (uint32_t j = threadIdx.x; j + 1 < (uint32_t)nwin; j += kExpandBlock) {
-      const uint64_t a = max(win[j], g0), b = min(win[j + 1], g1);
-      for (uint64_t g = a; g < b; ++g) pmap[g - g0] = (uint16_t)j;
+      const int32_t a = max(win[j], 0), b = min(win[j + 1], n_t);
+      for (int32_t g = a; g < b; ++g) pmap[g] = (uint16_t)j;
     }
   }
   __syncthreads();
-  // parents of every item first, then every parent load in flight, then the arithmetic
-  uint64_t par[kExpandItems];
-  uint32_t rk[kExpandItems];
+  // the items in two halves (fewer registers live at once); in each, parents of every item
+  // first, then every parent load in flight, then the arithmetic
+  constexpr int kHalf = kExpandItems / 2;
 #pragma unroll
-  for (int it = 0; it < kExpandItems; ++it) {
-    const uint64_t g = min(g0 + (uint64_t)it * kExpandBlock + threadIdx.x, g1 - 1);
-    uint64_t p, start;
-    if (in_lds) {
-      const uint32_t j = pmap[g - g0];
-      p = plo + j;
-      start = win[j];
-    } else {
-      p = upper_bound_u64(off, plo, phi + 2, g) - 1;
-      start = off[p];
+  for (int h = 0; h < 2; ++h) {
+    uint64_t par[kHalf];
+    uint32_t rk[kHalf];
+#pragma unroll
+    for (int it = 0; it < kHalf; ++it) {
+      const uint64_t g = min(g0 + (uint64_t)(h * kHalf + it) * kExpandBlock + threadIdx.x, g1 - 1);
+      uint64_t p, start;
+      if (in_lds) {
+        const uint32_t j = pmap[g - g0];
+        p = plo + j;
+        start = (uint64_t)((int64_t)g0 + win[j]);
+      } else {
+        p = upper_bound_u64(off, plo, phi + 2, g) - 1;
+        start = off[p];
+      }
+      par[it] = p;
+      rk[it] = (uint32_t)(g - start);
     }
-    par[it] = p;
-    rk[it] = (uint32_t)(g - start);
-  }
-  K kp[kExpandItems];
-  W wp[kExpandItems];
-  uint32_t sp[kExpandItems];
+    K kp[kHalf];
+    W wp[kHalf];
+    uint32_t sp[kHalf];
 #pragma unroll
-  for (int it = 0; it < kExpandItems; ++it) {
-    const uint64_t p = min(par[it], T_in - 1);  // T_in >= 1: this tile has images
-    kp[it] = keys[p];
-    wp[it] = w[p];
-    sp[it] = asign[p];
-  }
-#pragma unroll
-  for (int it = 0; it < kExpandItems; ++it) {
-    const uint64_t g = g0 + (uint64_t)it * kExpandBlock + threadIdx.x;
-    if (g >= g1) break;
-    if (par[it] >= T_in) {
-      atomicOr(err, kErrIndex | kErrExpand);
-      continue;
+    for (int it = 0; it < kHalf; ++it) {
+      const uint64_t p = min(par[it], T_in - 1);  // T_in >= 1: this tile has images
+      kp[it] = keys[p];
+      wp[it] = w[p];
+      sp[it] = asign[p];
     }
-    K key = kp[it];  // the parent's image under the A chain (and its sign), from the count
-    W wv = wp[it];
-    uint32_t neg = sp[it];
-    expand_ops<K, WP>(key, wv, rk[it], pa, E1s, E2s, err);
-    if (pa.useB) key = apply_table(key, tbk, tbn, neg);
-    else for (uint32_t b = 0; b < pa.nB; ++b) key = apply_perm(key, pa.B[b], neg);
-    if (neg) wv = -wv;
-    keys_out[g] = key;
-    w_out[g] = wv;
-    for (uint32_t p = 0; p < n_hp; ++p) atomicAdd(&hw[p * kRadix + ((uint32_t)(key >> (8u * (hp_begin + p))) & 255u)], 1u);
+#pragma unroll
+    for (int it = 0; it < kHalf; ++it) {
+      const uint64_t g = g0 + (uint64_t)(h * kHalf + it) * kExpandBlock + threadIdx.x;
+      if (g >= g1) break;
+      if (par[it] >= T_in) {
+        atomicOr(err, kErrIndex | kErrExpand);
+        continue;
+      }
+      K key = kp[it];  // the parent's image under the A chain (and its sign), from the count
+      W wv = wp[it];
+      uint32_t neg = sp[it];
+      expand_ops<K, WP>(key, wv, rk[it], pa, E1s, E2s, err);
+      if (pa.useB) key = apply_table(key, tbk, tbn, neg);
+      else for (uint32_t b = 0; b < pa.nB; ++b) key = apply_perm(key, pa.B[b], neg);
+      if (neg) wv = -wv;
+      keys_out[g] = key;
+      w_out[g] = wv;
+      for (uint32_t p = 0; p < n_hp; ++p) atomicAdd(&hw[p * kRadix + ((uint32_t)(key >> (8u * (hp_begin + p))) & 255u)], 1u);
+    }
   }
   if (n_hp) {
     __syncthreads();
@@ -1874,7 +1881,7 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign,
   hipEvent_t ev = prof_begin(prof, s, kKExpand);
   QIMAX_DISPATCH_K(KC, {
     const size_t tab = sizeof(K) * 256 * (sizeof(K) + 1);  // a B-chain table (A chains: done by the count)
-    const size_t lds = (size_t)(kExpandTile + 1) * 8 + (size_t)kExpandTile * 2 + (any_tables ? tab : 0) +
+    const size_t lds = kExpandLdsHead + (any_tables ? tab : 0) +
                        e_bytes + hist + 64;
     if (WP == 64)
       k_expand<K, 64><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, asign, (const double*)w, T_in, off, T_img, tl,

@@ -105,6 +105,9 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kExpandBlock = 256;
 constexpr int kExpandItems = 8;
 constexpr int kExpandTile = kExpandBlock * kExpandItems;
+// the expansion's LDS before its tables: a window of kExpandTile + 1 32-bit relative offsets
+// and an image -> parent map of 16-bit entries, rounded up to 16 bytes
+constexpr size_t kExpandLdsHead = ((size_t)(kExpandTile + 1) * 4 + (size_t)kExpandTile * 2 + 15) / 16 * 16;
 constexpr uint32_t kExpandHistPasses = 2;  // digit histograms the expansion may count itself
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
