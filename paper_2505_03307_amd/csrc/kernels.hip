@@ -890,7 +890,7 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
   constexpr int kTabN = sizeof(K) <= 8 ? (int)sizeof(K) * 256 : 1;  // no tables for 16-byte keys
   __shared__ K tk[kTabN];
   __shared__ uint8_t tn[kTabN];
-  __shared__ uint64_t sf[kSortTile + kSortTile / kItems];  // one pad word per thread's run of items
+  __shared__ uint32_t sf[kSortTile + kSortTile / kItems];  // fan-outs (< 2^32); one pad word per run of items
   __shared__ uint64_t scan_sh[4];
   __shared__ uint64_t base_sh;
   __shared__ uint32_t tile_sh;
@@ -918,7 +918,7 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
     K key = kr[r];
     uint32_t neg = 0;
     const uint64_t f = a_chain_and_fanout(key, neg, pa, tk, tn, err);
-    sf[pad(li)] = f;
+    sf[pad(li)] = (uint32_t)f;
     // the A chain is applied once per term here; the expand kernel starts from this image
     akeys[begin + li] = key;
     asign[begin + li] = (uint8_t)(neg & 1u);
@@ -956,20 +956,34 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
     if (b + 1 == tl.n_blocks) off[T_in] = excl + tot;
   }
   __syncthreads();
-  uint64_t run = base_sh + pre;
+  const uint64_t base = base_sh;
+  if (tot < (1ull << 32)) {
+    // offsets within the tile fit 32 bits: they go back through LDS for coalesced stores
+    uint32_t run = (uint32_t)pre;
 #pragma unroll
-  for (int k2 = 0; k2 < kItems; ++k2) {
-    if (l0 + k2 < n) {
-      const uint64_t v = sf[pad(l0 + k2)];
-      sf[pad(l0 + k2)] = run;
-      run += v;
+    for (int k2 = 0; k2 < kItems; ++k2) {
+      if (l0 + k2 < n) {
+        const uint32_t v = sf[pad(l0 + k2)];
+        sf[pad(l0 + k2)] = run;
+        run += v;
+      }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t li = r * 256 + threadIdx.x;
-    if (li < n) off[begin + li] = sf[pad(li)];
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t li = r * 256 + threadIdx.x;
+      if (li < n) off[begin + li] = base + sf[pad(li)];
+    }
+  } else {
+    // (a tile with 2^32 images or more) each thread writes the offsets of its own run
+    uint64_t run = base + pre;
+#pragma unroll
+    for (int k2 = 0; k2 < kItems; ++k2) {
+      if (l0 + k2 < n) {
+        off[begin + l0 + k2] = run;
+        run += sf[pad(l0 + k2)];
+      }
+    }
   }
 }
 
