@@ -1365,13 +1365,27 @@ __global__ void __launch_bounds__(kPublishBlock) k_chunk_publish(Tiling tc, cons
   // thread t scans the run [t*per, (t+1)*per) serially: one block scan for all the runs
   const uint32_t per = (nc + kPublishBlock - 1) / kPublishBlock;
   const uint32_t r0 = min(threadIdx.x * per, nc), r1 = min(r0 + per, nc);
+  // (eight loads in flight at a time: the run is read twice)
+  constexpr uint32_t kBatch = 8;
   uint64_t sum = 0;
-  for (uint32_t i = r0; i < r1; ++i) sum += chunk_cnt[i];
+  for (uint32_t i0 = r0; i0 < r1; i0 += kBatch) {
+    uint32_t v[kBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) v[u] = i0 + u < r1 ? chunk_cnt[i0 + u] : 0u;
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) sum += v[u];
+  }
   uint64_t tot;
   uint64_t run = block_excl_scan<kPublishBlock>(sum, sh, &tot);
-  for (uint32_t i = r0; i < r1; ++i) {
-    chunk_off[i] = run;
-    run += chunk_cnt[i];
+  for (uint32_t i0 = r0; i0 < r1; i0 += kBatch) {
+    uint32_t v[kBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) v[u] = i0 + u < r1 ? chunk_cnt[i0 + u] : 0u;
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) {
+      if (i0 + u < r1) chunk_off[i0 + u] = run;
+      run += v[u];
+    }
   }
   if (threadIdx.x == 0) {
     chunk_off[nc] = tot;
