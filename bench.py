@@ -1,11 +1,13 @@
 """Benchmark: Pauli-term updates per second of generator propagation on one MI355X.
 
-Workload (one step): the n=32 random Clifford circuit of 200 moments (H, S, CX drawn
-uniformly per qubit) with 40 Rz(theta) gates at random slots, seed 0, FP64 weights,
+Headline workload (one step): the n=32 random Clifford circuit of 200 moments (H, S, CX
+drawn uniformly per qubit) with 40 Rz(theta) gates at random slots, seed 0, FP64 weights,
 prune eps = 0. A step resets the n generators to Z_j on the device, runs the grouping pass
 and every propagation pass, and ends with the final generators resident in HBM (the
-paper's timing window, Sec. V). One term update = one output image of one grouped
-operator (a Clifford operator counts its input terms).
+paper's timing window, Sec. V). One term update = one output image of one grouped operator
+(U_k / V_k run), each group counted once (a Clifford group counts the terms it acts on).
+Also measured: the same circuit in FP32, and the n=16 two-layer ansatz (the configuration
+whose images merge) in FP64 and FP32 with eps = 1e-9.
 
 Prints one JSON line. The roofline object covers the kernel with the largest share of
 device time (found in the warm-up, where every kernel is timed), timed with HIP events on
@@ -35,15 +37,16 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it is current."""
+def traffic_for(kernel: str, workload: str = "c2"):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary, if
+    it was taken on the current kernels."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             data = json.load(f)
-        ent = data.get(kernel)
+        ent = data.get(workload, {}).get(kernel)
         if ent and ent.get("source_hash") == _kernel_source_hash():
             return ent.get("bytes_per_launch")
     except Exception:
@@ -116,19 +119,24 @@ def bench_batch(log, count: int = 256):
                     "speedup": round((t2 - t1) / (t1 - t0), 3), "term_updates": int(upd_b),
                     "final_terms": int(sum(int(r[0][-1]) for r in res_b.values()))}
         log("batch", key, out[key])
-    # FP32 against FP64, per circuit (norm-wise over the union of keys)
-    worst = 0.0
+    # FP32 against FP64, stated per result: for each circuit the largest over its generators
+    # of ||w32 - w64||_2 / ||w64||_2 over the union of keys
+    per = []
     for i in results[64]:
         o64, k64, w64 = results[64][i]
         o32, k32, w32 = results[32][i]
+        worst = 0.0
         for j in range(len(o64) - 1):
             a = {tuple(r): v for r, v in zip(k64[o64[j]:o64[j + 1]].tolist(), w64[o64[j]:o64[j + 1]].tolist())}
             bb = {tuple(r): v for r, v in zip(k32[o32[j]:o32[j + 1]].tolist(), w32[o32[j]:o32[j + 1]].tolist())}
             num = sum((a.get(k, 0.0) - bb.get(k, 0.0)) ** 2 for k in set(a) | set(bb)) ** 0.5
             den = sum(v * v for v in a.values()) ** 0.5
             worst = max(worst, num / (den or 1.0))
-    out["fp32_max_rel_err_vs_fp64"] = worst
-    out["fp32_within_5e-6"] = bool(worst <= 5e-6)
+        per.append(worst)
+    per = np.array(per)
+    out["fp32_rel_err_vs_fp64_per_circuit"] = {"max": float(per.max()), "median": float(np.median(per)),
+                                               "p99": float(np.quantile(per, 0.99)), "circuits": int(per.size)}
+    out["fp32_within_5e-6"] = bool(per.max() <= 5e-6)
     return out
 
 
@@ -168,6 +176,122 @@ def bench_serve(log, count: int = 200, budget_gb: float = 200.0, one_batch: bool
     return out
 
 
+def run_workload(circ, precision: int, steps: int, warmup: int, fp32_merge: int = 0, label: str = ""):
+    """Time `steps` propagation steps of one workload on one context. A step resets the
+    generators to Z_j, runs every layer (grouping and passes) and ends with the final
+    generators in HBM. Returns the simulator (still open) and the measured figures."""
+    from paper_2505_03307_amd.qimax import Simulator
+
+    sim = Simulator(circ.n, precision=precision, fp32_merge=fp32_merge, prune_eps=circ.eps, device=0)
+
+    def step():
+        sim.reset()
+        sim.run(circ)
+
+    # warm-up with every kernel timed: finds the kernel with the largest device time
+    sim.profile(True)
+    for i in range(max(warmup, 1)):
+        step()
+        sim.sync()
+        log(label, "warmup", i, "terms", sim.num_terms())
+    warm = sim.profile_read()
+    sim.profile(False)
+    dom_name = max(warm.items(), key=lambda kv: kv[1]["total_ms"])[0]
+    # timed region: only the dominant kernel carries HIP events (one pair per launch group)
+    s0 = sim.stats()
+    sim.profile_only(dom_name)
+    sim.profile(True)
+    sim.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    sim.sync()
+    t1 = time.perf_counter()
+    prof = sim.profile_read()
+    sim.profile(False)
+    sim.profile_only(None)
+    s1 = sim.stats()
+    terms = sim.num_terms()
+    per = lambda k: (s1[k] - s0[k]) / steps
+    updates, alg_step, rounds = per("term_updates"), per("alg_bytes"), per("rounds")
+    host = {"busy_ms_per_step": round(per("host_busy_ms"), 3), "sync_wait_ms_per_step": round(per("host_wait_ms"), 3),
+            "syncs_per_step": per("syncs")}
+    sec = (t1 - t0) / steps
+    log(label, "timed", steps, "steps, ms/step", round(sec * 1e3, 3), "updates/step", int(updates), "terms", terms)
+    # dominant kernel, timed over the timed region: the step's algorithmic bytes (every live
+    # input term read once, every merged output term written once, per pass) per launch
+    d = prof[dom_name]
+    launches = d["launches"] / steps
+    avg_ms = d["total_ms"] / d["launches"]
+    alg_per_launch = alg_step / launches
+    achieved = alg_per_launch / (avg_ms * 1e-3) / 1e9
+    # every kernel, over the same number of extra steps (outside the timed region)
+    sim.profile(True)
+    for _ in range(steps):
+        step()
+    allk = sim.profile_read()
+    sim.profile(False)
+    kernels = {k: {"launches": v["launches"] // steps, "ms_per_step": round(v["total_ms"] / steps, 4),
+                   "moved_GBps": round(v["alg_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] else None}
+               for k, v in sorted(allk.items(), key=lambda kv: -kv[1]["total_ms"])}
+    log(label, "kernels", json.dumps(kernels))
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom_name, label),
+                "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(alg_per_launch),
+                "launches_per_step": launches,
+                "image_bytes_per_launch": int(d["alg_bytes"] / d["launches"])}
+    loop = {"alg_GB_per_step": round(alg_step / 1e9, 4), "alg_GBps": round(alg_step / sec / 1e9, 1),
+            "frac": round(alg_step / sec / 1e9 / HBM_PEAK_GBS, 4), "rounds_per_step": rounds,
+            "kernel_ms_per_step": round(sum(v["total_ms"] for v in allk.values()) / steps, 4)}
+    out = {"value": round(updates / sec, 1), "ms_per_step": round(sec * 1e3, 3), "term_updates_per_step": int(updates),
+           "final_terms": terms, "roofline": roofline, "loop": loop, "kernels": kernels, "host": host}
+    return sim, out
+
+
+def cpu_oracle_baseline(circ, gen_updates: np.ndarray, reps: int = 3):
+    """The CPU oracle (as it stands) on the host cores: all generators with the box's thread
+    share, and a sample of generators on one thread; medians of `reps` runs."""
+    import oracle
+
+    def timed(gens, threads):
+        ts = []
+        for _ in range(reps):
+            c0 = time.perf_counter()
+            o = oracle.propagate(circ, gens=gens, threads=threads)
+            ts.append(time.perf_counter() - c0)
+            o.close()
+        return float(np.median(ts)), float(np.mean(ts))
+
+    threads = min(16, os.cpu_count() or 1)
+    allg = list(range(circ.n))
+    med, mean = timed(allg, threads)
+    upd = float(gen_updates.sum())
+    res = {"value": round(upd / med, 1), "unit": "term-updates/s", "cores": threads, "kind": "oracle",
+           "seconds_median": round(med, 3), "seconds_mean": round(mean, 3), "runs": reps,
+           "sample": f"all {circ.n} generators of the workload, gate by gate in FP64, {threads} threads "
+                     f"(generators in parallel); median of {reps} runs"}
+    # one thread: the generators with the fewest updates that together hold about 1/16 of them
+    order = np.argsort(gen_updates)
+    pick, acc = [], 0.0
+    for j in order.tolist():
+        pick.append(int(j))
+        acc += float(gen_updates[j])
+        if acc >= upd / 16:
+            break
+    med1, mean1 = timed(sorted(pick), 1)
+    res["single_thread"] = {"value": round(acc / med1, 1), "cores": 1, "seconds_median": round(med1, 3),
+                            "seconds_mean": round(mean1, 3), "generators": sorted(pick),
+                            "sample_updates": int(acc)}
+    try:
+        import subprocess
+        res["host_cpu"] = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.split(
+            "Model name:")[1].splitlines()[0].strip()
+    except Exception:
+        pass
+    log("cpu", res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,8 +299,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--precision", type=int, default=64, choices=(32, 64))
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-gens", type=str, default="all",
-                    help="oracle sample: 'all', 'none', or a comma list of generator ids")
+    ap.add_argument("--cpu", type=int, default=1, help="time the CPU oracle baseline (0: skip)")
+    ap.add_argument("--hea", type=int, default=1, help="the n=16 two-layer ansatz section (0: skip)")
     ap.add_argument("--batch", type=int, default=256, help="circuits in the batched-vs-plain section (0: skip)")
     ap.add_argument("--serve", type=int, default=200, help="requests in the serving section (0: skip)")
     ap.add_argument("--serve-one-batch", action="store_true", help="also serve the trace with a single batch")
@@ -187,112 +311,70 @@ def main():
         sys.exit(2)
 
     from paper_2505_03307_amd import workloads as W
-    from paper_2505_03307_amd.qimax import Simulator
 
+    # ---- headline: the n=32 Clifford+Rz circuit
     circ = W.c2_clifford_rz(seed=args.seed)
-    g, a, b, t = circ.gate, circ.q0, circ.q1, circ.theta
     log("workload", circ.name, "instructions", circ.m)
-    sim = Simulator(circ.n, precision=args.precision, device=0)
-
-    def step():
-        sim.reset()
-        sim.apply_circuit((g, a, b, t))
-
-    # warm-up with every kernel timed: finds the kernel with the largest device time
-    sim.profile(True)
-    for i in range(max(args.warmup, 1)):
-        step()
-        sim.sync()
-        log("warmup", i, "terms", sim.num_terms())
-    warm = sim.profile_read()
-    sim.profile(False)
-    dom_name = max(warm.items(), key=lambda kv: kv[1]["total_ms"])[0]
-    # timed region: only the dominant kernel carries HIP events (one pair per launch group)
-    s0 = sim.stats()
-    sim.profile_only(dom_name)
-    sim.profile(True)
-    sim.sync()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    sim.sync()
-    t1 = time.perf_counter()
-    prof = sim.profile_read()
-    sim.profile(False)
-    sim.profile_only(None)
-    s1 = sim.stats()
-    terms = sim.num_terms()
-    updates = (s1["term_updates"] - s0["term_updates"]) / args.steps
-    host = {"busy_ms_per_step": round((s1["host_busy_ms"] - s0["host_busy_ms"]) / args.steps, 3),
-            "sync_wait_ms_per_step": round((s1["host_wait_ms"] - s0["host_wait_ms"]) / args.steps, 3),
-            "syncs_per_step": (s1["syncs"] - s0["syncs"]) / args.steps}
-    log("host", host)
-    sec = (t1 - t0) / args.steps
-    log("timed", args.steps, "steps, ms/step", round(sec * 1e3, 3), "updates/step", int(updates), "terms", terms)
-
-    # dominant kernel: timed over the timed region
-    name, d = dom_name, prof[dom_name]
-    avg_ms = d["total_ms"] / d["launches"]
-    alg_per_launch = d["alg_bytes"] / d["launches"]
-    achieved = alg_per_launch / (avg_ms * 1e-3) / 1e9
-    # every kernel, over the same number of extra steps (outside the timed region)
-    sim.profile(True)
-    for _ in range(args.steps):
-        step()
-    allk = sim.profile_read()
-    sim.profile(False)
-    kernels = {k: {"launches": v["launches"] // args.steps, "ms_per_step": round(v["total_ms"] / args.steps, 4),
-                   "alg_GBps": round(v["alg_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] else None}
-               for k, v in sorted(allk.items(), key=lambda kv: -kv[1]["total_ms"])}
-    log("kernels", json.dumps(kernels))
-    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(name),
-                "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(alg_per_launch)}
-
-    # CPU oracle on the host cores (test infrastructure, timed beside the GPU)
-    cpu = None
-    if args.cpu_gens != "none":
-        import oracle
-        gen_updates = sim.generator_updates()
-        gens = list(range(circ.n)) if args.cpu_gens == "all" else [int(x) for x in args.cpu_gens.split(",")]
-        threads = min(16, os.cpu_count() or 1)
-        log("cpu oracle on generators", gens, "threads", threads)
-        c0 = time.perf_counter()
-        o = oracle.propagate(circ, gens=gens, threads=threads)
-        c1 = time.perf_counter()
-        # generator_updates accumulates over every step run so far: scale to one step
-        runs = max(args.warmup, 1) + 2 * args.steps  # warm-up, timed and per-kernel steps
-        sample_updates = float(gen_updates[gens].sum()) / runs
-        cpu = {"value": round(sample_updates / (c1 - c0), 1), "unit": "term-updates/s", "cores": threads,
-               "kind": "oracle", "seconds": round(c1 - c0, 2),
-               "sample": f"{len(gens)} of {circ.n} generators of the same circuit, gate by gate in FP64 "
-                         f"({int(sum(o.count(i) for i in range(o.num_gens)))} final terms)"}
-        log("cpu", cpu)
-
+    sim, head = run_workload(circ, args.precision, args.steps, args.warmup, label="c2")
+    gen_updates = sim.generator_updates()
+    runs = max(args.warmup, 1) + 2 * args.steps  # generator_updates accumulates over every step
+    gen_updates = gen_updates / runs
+    # FP32 on the same circuit (compensated merge), with the library's stated error per generator
+    sim32, c2_32 = run_workload(circ, 32, args.steps, 2, label="c2-fp32")
+    dn, rn, kd = sim32.compare(sim, tau=1e-6)
+    c2_32["fp32_rel_err_vs_fp64_per_generator_max"] = float(np.max(dn / np.where(rn > 0, rn, 1.0)))
+    c2_32["keys_differing_on_K_1e-6"] = int(kd.sum())
+    sim32.close()
     sim.close()
+    cpu = cpu_oracle_baseline(circ, gen_updates) if args.cpu else None
+
+    # ---- the n=16 two-layer ansatz (the configuration with merging), FP64 and FP32
+    hea = None
+    if args.hea:
+        c3 = W.c3_hea(seed=0, n=16, layers=2, eps=1e-9)
+        log("workload", c3.name)
+        hsteps = max(3, args.steps)
+        s64, h64 = run_workload(c3, 64, hsteps, 3, label="hea-fp64")
+        s32, h32 = run_workload(c3, 32, hsteps, 3, label="hea-fp32")
+        dn, rn, kd = s32.compare(s64, tau=1e-6)
+        rel = dn / np.where(rn > 0, rn, 1.0)
+        h32["fp32_rel_err_vs_fp64_per_generator"] = [float(f"{x:.3e}") for x in rel]
+        h32["keys_differing_on_K_1e-6"] = int(kd.sum())
+        s32.close()
+        s64.close()
+        hea = {"workload": "hardware-efficient ansatz n=16, 2 layers (Rx,Ry,Rz per qubit + CX ladder), "
+                           "eps=1e-9, seed 0", "fp64": h64, "fp32": h32,
+               "note": "two layers reach 1.29e8 terms; a third would exceed 288 GB"}
+
     batch = bench_batch(log, args.batch) if args.batch else None
     serving = bench_serve(log, args.serve, one_batch=args.serve_one_batch) if args.serve else None
     out = {
         "metric": "Pauli-term updates/sec + HBM GB/s fraction; batched vs plain at 5e-6 rel err",
-        "value": round(updates / sec, 1),
+        "value": head["value"],
         "unit": "term-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(sec * 1e3, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 64 else "f32",
         "data": "synthetic",
         "config": {"workload": f"random Clifford+Rz circuit, n=32, 200 moments, 40 Rz, seed {args.seed}, "
-                               f"eps=0, final terms {terms}",
-                   "n_qubits": circ.n, "instructions": circ.m, "final_terms": terms,
-                   "term_updates_per_step": int(updates)},
-        "roofline": roofline,
+                               f"eps=0, final terms {head['final_terms']}",
+                   "n_qubits": circ.n, "instructions": circ.m, "final_terms": head["final_terms"],
+                   "term_updates_per_step": head["term_updates_per_step"],
+                   "note": "each grouped operator counted once; no two images of this circuit ever share a "
+                           "key, so its merges sum nothing (the ansatz section is the workload that merges); "
+                           "most updates are Clifford relabellings done by table lookup"},
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "kernels": kernels,
-        "host": host,
+        "loop": head["loop"],
+        "kernels": head["kernels"],
+        "host": head["host"],
+        "c2_fp32": c2_32,
+        "hea_n16": hea,
         "batched_vs_plain": batch,
         "serving": serving,
     }

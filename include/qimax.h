@@ -123,18 +123,55 @@ qimax_status qimax_num_terms(qimax_ctx* ctx, uint64_t* T);
 qimax_status qimax_get_generators(qimax_ctx* ctx, uint64_t* gen_off, uint64_t* keys, double* w,
                                   size_t cap, size_t* T);
 
+/* The generators in the paper's x/z form (Sec. II-A; the index tensor of Alg. 2 as bit
+ * vectors): gen_off[0..n] as for qimax_get_generators; for term i, bit q of x[i] is set when
+ * qubit q holds X or Y, bit q of z[i] when it holds Y or Z (one word each: n <= 64); weights
+ * as FP64. Terms come out in the same order as qimax_get_generators (ascending base-4 index
+ * within each generator). The conversion runs on the device. Two-call size query as above
+ * (gen_off is written in both calls when not NULL). */
+qimax_status qimax_get_generators_xz(qimax_ctx* ctx, uint64_t* gen_off, uint64_t* x, uint64_t* z,
+                                     double* w, size_t cap, size_t* T);
+
 /* <psi|P|psi> = Tr(rho P) for rho = 2^-n prod_j (I + G_j) (eq. (2)), P given as n letters
- * of "IXYZ", qubit 0 first. For a single-qubit projector the paper's p_{k,0} is
- * (1 + <Z_k>)/2 (Sec. II-B). Exact when every generator is a single term (GF(2)
- * elimination); otherwise by projecting a random state for n <= 20 (QIMAX_ETOOLARGE
- * beyond). Runs on the host after copying the generators; not part of propagation. */
+ * of "IXYZ", qubit 0 first. This is the coefficient of P in prod_j (I + G_j), not the sum
+ * of P's weights over the generators (that reading of the probability formula of Sec. II-B
+ * fails as soon as two generators share a string). Two methods, both exact up to rounding:
+ *  - every generator a single term of weight +-1 (a stabilizer state): GF(2) elimination of
+ *    the generators' x/z vectors on the host, O(n^3);
+ *  - otherwise, for n <= 30: a statevector on the device (2^n complex doubles, twice, plus
+ *    the terms; allocated for the call and freed): a seeded random vector is projected by
+ *    (I + G_j)/2 for every j, normalised, and <v|P|v> is reduced on the device. Cost: the
+ *    sum of all generators' term counts times 2^n. QIMAX_ETOOLARGE for n > 30 or a cost
+ *    above 4e13; QIMAX_ENOMEM when the statevector does not fit.
+ * Not part of propagation; the generators stay as they are. */
 qimax_status qimax_expect(qimax_ctx* ctx, const char* pauli, double* out);
+
+/* qimax_expect for k strings at once (paulis: k*n letters, string i at paulis + i*n; no
+ * terminators needed): one elimination or one projected statevector for all of them. */
+qimax_status qimax_expect_many(qimax_ctx* ctx, const char* paulis, size_t k, double* out);
+
+/* The paper's single-qubit outcome probabilities p_{k,0} = (1 + <Z_k>)/2 (Sec. II-B) for
+ * every qubit k in one call (p0: n doubles), by the methods of qimax_expect. */
+qimax_status qimax_prob_zero_all(qimax_ctx* ctx, double* p0);
+
+/* Compares the generators of two contexts of the same n on the same device, term lists
+ * matched by key, a missing key counting as weight 0: per generator j, diff_norm[j] =
+ * ||w_a - w_b||_2 over the union of keys, ref_norm[j] = ||w_b||_2, and n_tau_diff[j] = the
+ * number of keys with |w| > tau on exactly one side. Used to state the error of an FP32
+ * result (a) against an FP64 one (b): per generator diff_norm / ref_norm. Runs on the
+ * device, on a's stream (both streams are synchronised first). */
+qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
+                           uint64_t* n_tau_diff);
 
 /* Counters since qimax_create (host-side bookkeeping, no device work). */
 typedef struct {
   uint64_t terms;          /* current number of terms                                     */
   uint64_t passes;         /* expanding passes executed                                   */
-  uint64_t term_updates;   /* images produced, one per output image of every operator     */
+  uint64_t term_updates;   /* term updates: one per output image of every grouped operator
+                              (U_k / V_k run) of the circuit, each group counted once: an
+                              expanding group counts its images, sum over terms of the
+                              product of the nonzero counts of its wires' PTM columns; a
+                              Clifford group counts the terms it acts on                  */
   uint64_t images;         /* images materialised by the expand kernel                    */
   uint64_t sort_elems;     /* elements sorted                                             */
   uint64_t peak_bytes;     /* peak device bytes held by the context                       */
@@ -145,6 +182,9 @@ typedef struct {
   uint64_t sort_redos;     /* rounds sorted again with global passes only (a bucket of
                               equal top digits did not fit a chunk-local sort)            */
   uint64_t tuned_classes;  /* round size classes whose sort variant the autotuner fixed   */
+  uint64_t rounds;         /* propagation rounds run (one set of launches per pass)        */
+  double alg_bytes;        /* algorithmic bytes of those rounds: (T_in + T_out) * (key bytes
+                              + weight bytes) per round, the terms a pass must read and write */
 } qimax_stats;
 
 qimax_status qimax_get_stats(const qimax_ctx* ctx, qimax_stats* out);

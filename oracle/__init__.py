@@ -59,6 +59,11 @@ def _load():
                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32), dp,
                                ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64), ctypes.c_double,
                                ctypes.c_int]
+    lib.oracle_gates.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint32),
+                                 ctypes.POINTER(ctypes.c_uint32), dp, ctypes.c_int]
+    lib.oracle_fanout_sum.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint8),
+                                      u64p]
+    lib.oracle_fanout_sum.restype = None
     lib.oracle_count.restype = ctypes.c_size_t
     lib.oracle_count.argtypes = [P, ctypes.c_int]
     lib.oracle_gen_id.argtypes = [P, ctypes.c_int]
@@ -158,6 +163,27 @@ class Oracle:
         if rc != 0:
             raise OracleError("oracle_run rejected the circuit")
         return self
+
+    def gates(self, gate, q0, q1, theta, threads: int = 0):
+        """Apply a list of gates to every generator in order (no prune)."""
+        g = np.ascontiguousarray(gate, dtype=np.uint8)
+        a = np.ascontiguousarray(q0, dtype=np.uint32)
+        b = np.ascontiguousarray(q1, dtype=np.uint32)
+        t = np.ascontiguousarray(theta, dtype=np.float64)
+        if _load().oracle_gates(self._h, g.size, _ptr(g, ctypes.c_uint8), _ptr(a, ctypes.c_uint32),
+                                _ptr(b, ctypes.c_uint32), _ptr(t, ctypes.c_double), int(threads)) != 0:
+            raise OracleError("oracle_gates rejected the gates")
+        return self
+
+    def fanout_sum(self, wires, nnz) -> np.ndarray:
+        """Per generator: sum over terms of prod_i nnz[i][Pauli of the term on wires[i]]."""
+        w = np.ascontiguousarray(wires, dtype=np.int32)
+        z = np.ascontiguousarray(nnz, dtype=np.uint8).reshape(-1)
+        assert z.size == 4 * w.size
+        out = np.zeros(self.num_gens, dtype=np.uint64)
+        _load().oracle_fanout_sum(self._h, int(w.size), _ptr(w, ctypes.c_int), _ptr(z, ctypes.c_uint8),
+                                  _ptr(out, ctypes.c_uint64))
+        return out
 
     def count(self, g: int) -> int:
         return int(_load().oracle_count(self._h, int(g)))

@@ -373,6 +373,40 @@ int oracle_run(oracle_state* s, size_t m, const uint8_t* gate, const uint32_t* q
   return 0;
 }
 
+// Gates gate[0..m) applied to every generator in order (no prune), generators in parallel.
+int oracle_gates(oracle_state* s, size_t m, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
+                 const double* theta, int threads) {
+  for (size_t i = 0; i < m; ++i)
+    if (!valid_gate(s, gate[i], (int)q0[i], (int)q1[i])) return -1;
+  const int G = (int)s->gens.size();
+#ifdef _OPENMP
+  if (threads < 1) threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
+#endif
+  for (int gi = 0; gi < G; ++gi) {
+    std::vector<Term> scratch;
+    for (size_t i = 0; i < m; ++i) apply_gate(s->gens[gi], gate[i], (int)q0[i], (int)q1[i], theta[i], scratch);
+  }
+  (void)threads;
+  return 0;
+}
+
+// The number of images an operator acting on wires[0..k) produces from each generator's
+// current terms: sum over terms of prod_i nnz[4*i + p_i], p_i the term's Pauli on wires[i]
+// and nnz[4*i + p] the number of nonzero entries in column p of that wire's transfer
+// matrix (the count a term update is defined by). out[g] per generator slot.
+void oracle_fanout_sum(const oracle_state* s, int k, const int* wires, const uint8_t* nnz, uint64_t* out) {
+  for (size_t g = 0; g < s->gens.size(); ++g) {
+    uint64_t tot = 0;
+    for (const Term& t : s->gens[g]) {
+      uint64_t f = 1;
+      for (int i = 0; i < k; ++i) f *= nnz[4 * i + local_pauli(t, wires[i])];
+      tot += f;
+    }
+    out[g] = tot;
+  }
+}
+
 size_t oracle_count(const oracle_state* s, int g) {
   if (g < 0 || g >= (int)s->gens.size()) return 0;
   return s->gens[g].size();

@@ -78,7 +78,7 @@ struct HostOp {
   int arity = 1;
   int q0 = 0, q1 = 0;
   int dim = 4;
-  int group = 0;
+  int64_t group = 0;  // operator group (U_k / V_k run); ids increase in circuit order
   bool perm = false;
   bool conj = false;  // a signed permutation that is a conjugation by a unitary (multiplicative)
   uint64_t mask = 0;  // wires touched
@@ -100,10 +100,14 @@ inline int ilog2_u64(uint64_t x) { return x ? 63 - __builtin_clzll(x) : 0; }
 struct Pass {
   std::vector<const HostOp*> A, E, B;
   uint64_t emask = 0, bmask = 0;
-  int egroup = -1;
+  int64_t egroup = -1;
   double fanout_bound = 1.0;
   ChainTable pre[2] = {};  // A / B chain tables compiled ahead of the rounds (tab_key set)
-  mutable int64_t groups[2] = {-1, -1};  // operator groups of A / B (see pass_groups)
+  // Term updates of the pass's Clifford operator groups (each group counted once, whichever
+  // of A and B holds its operators): ng_in groups precede the expanding group in circuit
+  // order and see the pass's input terms, ng_out follow it and see the merged output.
+  // Operators of an expanding group that sit in A or B are counted by that group's images.
+  uint64_t ng_in = 0, ng_out = 0;
 };
 
 // The paper's CX look-up tables (Sec. III-C-2), indexed [p_c][p_t] with I=0, X=1, Y=2, Z=3:
@@ -265,6 +269,7 @@ struct qimax_ctx {
   uint64_t T = 0;
   std::vector<uint64_t> h_seg;
   std::vector<HostOp> pending;  // deferred Clifford operators (not yet applied)
+  int64_t group_base = 0;       // operator-group ids of the next call start here
 
   // pass outputs (ping-pong) and their segment offsets
   DevBuf pk[2], pw[2], pseg[2];
@@ -634,19 +639,10 @@ struct RoundEntry {
   bool drop = false;
 };
 
-uint64_t op_groups(const std::vector<const HostOp*>& v, int exclude) {
-  std::vector<int> g;
-  for (auto* op : v)
-    if (op->group != exclude) g.push_back(op->group);
-  std::sort(g.begin(), g.end());
-  return (uint64_t)(std::unique(g.begin(), g.end()) - g.begin());
-}
-
-// Operator groups of a pass's A (ab = 0) or B (ab = 1) chain other than its expanding group:
-// the update count per term of that chain; found once per pass.
-uint64_t pass_groups(const Pass& p, int ab) {
-  if (p.groups[ab] < 0) p.groups[ab] = (int64_t)op_groups(ab ? p.B : p.A, p.egroup);
-  return (uint64_t)p.groups[ab];
+// Term updates of segment s in a pass: one per output image of every operator group (an
+// expanding group counts its images, a Clifford group the terms it sees), each group once.
+inline uint64_t pass_updates(const Pass& p, uint64_t t_in, uint64_t t_img, uint64_t t_out) {
+  return p.ng_in * t_in + (p.E.empty() ? 0 : t_img) + p.ng_out * t_out;
 }
 
 // Runs one round: every segment s of the input (k_in, w_in; device offsets seg_in, host
@@ -1089,17 +1085,43 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   for (uint32_t s = 0; s < S; ++s) {
     const RoundEntry& en = entries[seg_entry[s]];
     if (en.drop || !en.pass) continue;
-    const Pass& p = *en.pass;
-    const uint64_t u = pass_groups(p, 0) * (so_in[s + 1] - so_in[s]) +
-                       (p.E.empty() ? 0 : so_img[s + 1] - so_img[s]) +
-                       pass_groups(p, 1) * (so_out[s + 1] - so_out[s]);
+    const uint64_t u = pass_updates(*en.pass, so_in[s + 1] - so_in[s], so_img[s + 1] - so_img[s],
+                                    so_out[s + 1] - so_out[s]);
     total_upd += u;
     if (upd) (*upd)[seg_entry[s]] += u;
   }
   c->st.term_updates += total_upd;
+  // algorithmic bytes of the round: every live input term read once, every merged output
+  // term written once (a leaving circuit's terms move nowhere)
+  double alg = 0.0;
+  for (uint32_t s = 0; s < S; ++s) {
+    const RoundEntry& en = entries[seg_entry[s]];
+    if (en.drop || !en.pass) continue;
+    alg += (double)((so_in[s + 1] - so_in[s]) + (so_out[s + 1] - so_out[s]));
+  }
+  c->st.alg_bytes += alg * (double)(eb + wbt);
+  c->st.rounds += 1;
   c->st.images += T_img;
   c->st.sort_elems += T_img * ((key_bits + kRadixBits - 1) / kRadixBits);
   return QIMAX_OK;
+}
+
+// Sets p.ng_in / p.ng_out: the distinct operator groups of p's A and B chains that hold no
+// expanding operator (exp_groups, sorted), split by their place before or after p's
+// expanding group in circuit order (group ids increase in circuit order). A pass without an
+// expanding operator counts all of them on its input.
+void count_clifford_groups(Pass& p, const std::vector<int64_t>& exp_groups) {
+  std::vector<int64_t> g;
+  for (const auto* v : {&p.A, &p.B})
+    for (const HostOp* op : *v)
+      if (!std::binary_search(exp_groups.begin(), exp_groups.end(), op->group)) g.push_back(op->group);
+  std::sort(g.begin(), g.end());
+  g.erase(std::unique(g.begin(), g.end()), g.end());
+  p.ng_in = p.ng_out = 0;
+  for (int64_t x : g) {
+    if (p.E.empty() || x < p.egroup) ++p.ng_in;
+    else ++p.ng_out;
+  }
 }
 
 // The pass planner: operators in order become passes [A perms] -> [E expanding ops of one
@@ -1141,6 +1163,13 @@ void plan_passes(const std::vector<const HostOp*>& all, std::vector<Pass>& passe
   } else {
     passes.push_back(cur);
   }
+  // update counts: a group with an expanding operator is counted by its images only; every
+  // other group once, before or after the pass's expanding group in circuit order
+  std::vector<int64_t> exp_groups;
+  for (const HostOp* op : all)
+    if (!op->perm) exp_groups.push_back(op->group);
+  std::sort(exp_groups.begin(), exp_groups.end());
+  for (Pass& p : passes) count_clifford_groups(p, exp_groups);
 }
 
 // Single-circuit contexts: plan the operators (after the deferred ones of earlier calls) and
@@ -1207,9 +1236,16 @@ qimax_status prebuild_tables(qimax_ctx* c, std::vector<Pass>& passes) {
   return QIMAX_OK;
 }
 
-qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
+qimax_status apply_ops(qimax_ctx* c, std::vector<HostOp>& ops) {
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
   BusyTimer bt(c);
+  // group ids continue from earlier calls, so that deferred operators precede this call's
+  int64_t next_base = c->group_base;
+  for (auto& op : ops) {
+    op.group += c->group_base;
+    next_base = std::max(next_base, op.group + 1);
+  }
+  c->group_base = next_base;
   std::vector<const HostOp*> ptrs;  // the deferred operators, then these (both outlive the passes)
   ptrs.reserve(c->pending.size() + ops.size());
   for (auto& op : c->pending) ptrs.push_back(&op);
@@ -1239,9 +1275,8 @@ qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
     if (s != QIMAX_OK) return s;  // committed state untouched
     if (c->gen_updates.size() != c->n) c->gen_updates.assign(c->n, 0);
     for (uint32_t j = 0; j < c->n; ++j)
-      c->gen_updates[j] += pass_groups(*en.pass, 0) * (so_in[j + 1] - so_in[j]) +
-                           (en.pass->E.empty() ? 0 : so_img[j + 1] - so_img[j]) +
-                           pass_groups(*en.pass, 1) * (so_out[j + 1] - so_out[j]);
+      c->gen_updates[j] += pass_updates(*en.pass, so_in[j + 1] - so_in[j], so_img[j + 1] - so_img[j],
+                                        so_out[j + 1] - so_out[j]);
     if (!en.pass->E.empty()) c->st.passes += 1;
     k_in = c->pk[slot].p;
     w_in = c->pw[slot].p;
@@ -1255,8 +1290,6 @@ qimax_status apply_ops(qimax_ctx* c, const std::vector<HostOp>& ops) {
   std::swap(c->seg, c->pseg[last]);
   c->h_seg = so_in;
   c->T = so_in[c->n];
-  // deferred operators of later calls get group ids that cannot collide with this call's
-  for (auto& op : new_pending) op.group = -1000000 - op.group;
   c->pending.swap(new_pending);
   c->st.terms = c->T;
   return QIMAX_OK;
@@ -1267,6 +1300,7 @@ qimax_status flush_pending(qimax_ctx* c) {
   // a pass with only Clifford operators: images are the permuted terms, then sorted
   Pass p;
   for (auto& op : c->pending) p.A.push_back(&op);
+  count_clifford_groups(p, {});
   RoundEntry en;
   en.pass = &p;
   en.n = c->n;
@@ -1277,7 +1311,7 @@ qimax_status flush_pending(qimax_ctx* c) {
   if (s != QIMAX_OK) return s;
   if (c->gen_updates.size() != c->n) c->gen_updates.assign(c->n, 0);
   for (uint32_t j = 0; j < c->n; ++j)
-    c->gen_updates[j] += op_groups(p.A, -1) * (c->h_seg[j + 1] - c->h_seg[j]);
+    c->gen_updates[j] += pass_updates(p, c->h_seg[j + 1] - c->h_seg[j], 0, 0);
   std::swap(c->keys, c->pk[0]);
   std::swap(c->w, c->pw[0]);
   std::swap(c->seg, c->pseg[0]);
@@ -1287,7 +1321,7 @@ qimax_status flush_pending(qimax_ctx* c) {
   return QIMAX_OK;
 }
 
-qimax_status check_op_input(qimax_ctx* c, const qimax_op& in, int group, HostOp& op) {
+qimax_status check_op_input(qimax_ctx* c, const qimax_op& in, int64_t group, HostOp& op) {
   if (in.arity != 1 && in.arity != 2) return fail(c, QIMAX_EINVAL, "op arity must be 1 or 2");
   if (!in.ptm) return fail(c, QIMAX_EINVAL, "op ptm is NULL");
   if (in.q[0] >= c->n || (in.arity == 2 && (in.q[1] >= c->n || in.q[1] == in.q[0])))
@@ -1517,128 +1551,208 @@ qimax_status fetch(qimax_ctx* c, HostGens& g) {
 int digit_of(u128 key, uint32_t n, uint32_t q) { return (int)((key >> (2 * (n - 1 - q))) & 3u); }
 
 
-// <P> when every generator is one signed Pauli string: P is +-(a product of generators)
-// or anticommutes with one of them (then <P> = 0). GF(2) elimination over the digits.
-qimax_status expect_clifford(qimax_ctx* c, const HostGens& g, const std::vector<int>& P, double* out) {
-  const uint32_t n = c->n;
-  // anticommutation test
-  for (uint32_t j = 0; j < n; ++j) {
-    const uint64_t k = g.key[g.off[j]];
-    int anti = 0;
-    for (uint32_t q = 0; q < n; ++q) {
-      const int a = digit_of(k, n, q), b = P[q];
-      if (a && b && a != b) anti ^= 1;
-    }
-    if (anti) { *out = 0.0; return QIMAX_OK; }
-  }
-  // binary vectors (x|z) of 2n bits for each generator, tracked with the set of rows combined
-  const uint32_t N2 = 2 * n;
-  auto vec = [&](const std::vector<int>& d) {
-    std::vector<uint8_t> v(N2, 0);
+// <P> when every generator is one signed Pauli string (the Clifford case): P is +-(a
+// product of generators) or anticommutes with one of them (then <P> = 0). The generators'
+// GF(2) vectors (x|z bits) are reduced once; every string is then reduced against the pivots.
+struct CliffordReducer {
+  uint32_t n = 0;
+  std::vector<std::vector<int>> dig;           // digits of generator j's string
+  std::vector<double> sign;                    // its weight's sign
+  std::vector<std::vector<uint8_t>> rows, combo;  // reduced rows and the generators they combine
+  std::vector<int> piv_col;                    // pivot column of row r (-1: zero row)
+
+  std::vector<uint8_t> vec(const std::vector<int>& d) const {
+    std::vector<uint8_t> v(2 * n, 0);
     for (uint32_t q = 0; q < n; ++q) {
       v[q] = (d[q] == 1 || d[q] == 2);
       v[n + q] = (d[q] == 2 || d[q] == 3);
     }
     return v;
-  };
-  std::vector<std::vector<uint8_t>> rows(n), combo(n, std::vector<uint8_t>(n, 0));
-  std::vector<std::vector<int>> dig(n, std::vector<int>(n));
-  for (uint32_t j = 0; j < n; ++j) {
-    for (uint32_t q = 0; q < n; ++q) dig[j][q] = digit_of(g.key[g.off[j]], n, q);
-    rows[j] = vec(dig[j]);
-    combo[j][j] = 1;
   }
-  std::vector<uint8_t> target = vec(P);
-  std::vector<uint8_t> used(n, 0);
-  // reduce target by pivots
-  std::vector<uint8_t> sel(n, 0);
-  for (uint32_t col = 0; col < N2; ++col) {
-    int piv = -1;
-    for (uint32_t r = 0; r < n; ++r)
-      if (!used[r] && rows[r][col]) { piv = (int)r; break; }
-    if (piv < 0) continue;
-    used[piv] = 1;
-    for (uint32_t r = 0; r < n; ++r)
-      if (r != (uint32_t)piv && rows[r][col]) {
-        for (uint32_t k = 0; k < N2; ++k) rows[r][k] ^= rows[piv][k];
-        for (uint32_t k = 0; k < n; ++k) combo[r][k] ^= combo[piv][k];
+  void init(uint32_t nq, const HostGens& g) {
+    n = nq;
+    const uint32_t N2 = 2 * n;
+    dig.assign(n, std::vector<int>(n));
+    sign.assign(n, 1.0);
+    rows.assign(n, {});
+    combo.assign(n, std::vector<uint8_t>(n, 0));
+    piv_col.assign(n, -1);
+    for (uint32_t j = 0; j < n; ++j) {
+      for (uint32_t q = 0; q < n; ++q) dig[j][q] = digit_of(g.key[g.off[j]], n, q);
+      sign[j] = g.w[g.off[j]] < 0 ? -1.0 : 1.0;
+      rows[j] = vec(dig[j]);
+      combo[j][j] = 1;
+    }
+    std::vector<uint8_t> used(n, 0);
+    for (uint32_t col = 0; col < N2; ++col) {
+      int piv = -1;
+      for (uint32_t r = 0; r < n; ++r)
+        if (!used[r] && rows[r][col]) { piv = (int)r; break; }
+      if (piv < 0) continue;
+      used[piv] = 1;
+      piv_col[piv] = (int)col;
+      for (uint32_t r = 0; r < n; ++r)
+        if (r != (uint32_t)piv && rows[r][col]) {
+          for (uint32_t k = 0; k < N2; ++k) rows[r][k] ^= rows[piv][k];
+          for (uint32_t k = 0; k < n; ++k) combo[r][k] ^= combo[piv][k];
+        }
+    }
+  }
+  // returns false on inconsistent phases
+  bool expect(const std::vector<int>& P, double* out) const {
+    for (uint32_t j = 0; j < n; ++j) {  // anticommutes with a generator: <P> = 0
+      int anti = 0;
+      for (uint32_t q = 0; q < n; ++q) {
+        const int a = dig[j][q], b = P[q];
+        if (a && b && a != b) anti ^= 1;
       }
-    if (target[col]) {
-      for (uint32_t k = 0; k < N2; ++k) target[k] ^= rows[piv][k];
-      for (uint32_t k = 0; k < n; ++k) sel[k] ^= combo[piv][k];
+      if (anti) { *out = 0.0; return true; }
     }
-  }
-  for (uint32_t k = 0; k < N2; ++k)
-    if (target[k]) { *out = 0.0; return QIMAX_OK; }
-  // product of the selected generators with its phase
-  std::vector<int> acc(n, 0);
-  int ph = 0;
-  double sign = 1.0;
-  for (uint32_t j = 0; j < n; ++j) {
-    if (!sel[j]) continue;
-    sign *= g.w[g.off[j]] < 0 ? -1.0 : 1.0;
-    for (uint32_t q = 0; q < n; ++q) {
-      ph += kPh[acc[q]][dig[j][q]];
-      acc[q] = kMul[acc[q]][dig[j][q]];
+    const uint32_t N2 = 2 * n;
+    std::vector<uint8_t> target = vec(P), sel(n, 0);
+    for (uint32_t r = 0; r < n; ++r) {
+      if (piv_col[r] < 0 || !target[piv_col[r]]) continue;
+      for (uint32_t k = 0; k < N2; ++k) target[k] ^= rows[r][k];
+      for (uint32_t k = 0; k < n; ++k) sel[k] ^= combo[r][k];
     }
+    for (uint32_t k = 0; k < N2; ++k)
+      if (target[k]) { *out = 0.0; return true; }
+    // product of the selected generators with its phase
+    std::vector<int> acc(n, 0);
+    int ph = 0;
+    double sg = 1.0;
+    for (uint32_t j = 0; j < n; ++j) {
+      if (!sel[j]) continue;
+      sg *= sign[j];
+      for (uint32_t q = 0; q < n; ++q) {
+        ph += kPh[acc[q]][dig[j][q]];
+        acc[q] = kMul[acc[q]][dig[j][q]];
+      }
+    }
+    ph &= 3;
+    if (ph == 1 || ph == 3) return false;
+    *out = sg * (ph == 2 ? -1.0 : 1.0);
+    return true;
   }
-  ph &= 3;
-  if (ph == 1 || ph == 3) return fail(c, QIMAX_EDEVICE, "inconsistent generator phases");
-  *out = sign * (ph == 2 ? -1.0 : 1.0);
+};
+
+constexpr uint32_t kSvMaxN = 30;     // device statevector readout: at most 2^30 amplitudes
+constexpr double kSvMaxWork = 4e13;  // sum over generators of terms x 2^n
+
+// Every generator a single term of weight +-1 (the state is a stabilizer state)?
+qimax_status clifford_reducer(qimax_ctx* c, bool* is_cliff, CliffordReducer& red) {
+  *is_cliff = false;
+  for (uint32_t j = 0; j < c->n; ++j)
+    if (c->h_seg[j + 1] - c->h_seg[j] != 1) return QIMAX_OK;
+  HostGens g;
+  QCHK(fetch(c, g));
+  for (uint32_t j = 0; j < c->n; ++j)
+    if (std::fabs(std::fabs(g.w[g.off[j]]) - 1.0) >= 1e-6) return QIMAX_OK;
+  red.init(c->n, g);
+  *is_cliff = true;
   return QIMAX_OK;
 }
 
-// <P> by projecting a random state onto the common +1 eigenspace prod_j (I + G_j)/2.
-qimax_status expect_state(qimax_ctx* c, const HostGens& g, const std::vector<int>& P, double* out) {
+// Strings of n letters "IXYZ" as digits.
+qimax_status parse_paulis(qimax_ctx* c, const char* s, size_t k, std::vector<std::vector<int>>& out) {
+  out.assign(k, std::vector<int>(c->n));
+  for (size_t i = 0; i < k; ++i)
+    for (uint32_t q = 0; q < c->n; ++q) {
+      const char ch = s[i * c->n + q];
+      const char* pos = ch ? std::strchr("IXYZ", ch) : nullptr;
+      if (!pos) return fail(c, QIMAX_EINVAL, "pauli strings must be n letters of IXYZ");
+      out[i][q] = (int)(pos - "IXYZ");
+    }
+  return QIMAX_OK;
+}
+
+// <P> for every string of Ps (zall: <Z_q> for every qubit instead) from a statevector on the
+// device: a seeded random vector projected by (I + G_j)/2 for every generator j is, once
+// normalised, the state rho = 2^-n prod_j (I + G_j) projects onto (eq. (2)).
+qimax_status expect_device(qimax_ctx* c, const std::vector<std::vector<int>>& Ps, bool zall, double* out) {
   const uint32_t n = c->n;
-  if (n > 20) return fail(c, QIMAX_ETOOLARGE, "expect: non-Clifford state with n > 20");
-  const double work = (double)g.key.size() * (double)(1ull << n);
-  if (work > 6.9e10) return fail(c, QIMAX_ETOOLARGE, "expect: too many terms for the projection");
-  using cd = std::complex<double>;
-  const size_t D = (size_t)1 << n;
-  std::vector<cd> v(D), tmp(D);
-  std::mt19937_64 rng(12345);
-  std::normal_distribution<double> nd;
-  for (auto& x : v) x = cd(nd(rng), nd(rng));
-  // Pauli string on a basis state: qubit q is bit (n-1-q)
-  auto apply_pauli = [&](u128 key, const std::vector<cd>& src, std::vector<cd>& dst, double wt, bool accumulate) {
-    uint64_t xm = 0, zm = 0;
+  if (n > kSvMaxN) return fail(c, QIMAX_ETOOLARGE, "expect: a state with non-Clifford generators and n > 30");
+  const uint64_t D = 1ull << n, T = c->T;
+  if ((double)T * (double)D > kSvMaxWork) return fail(c, QIMAX_ETOOLARGE, "expect: too many terms for the projection");
+  const size_t sv_bytes = (size_t)D * 16, t_bytes = (size_t)std::max<uint64_t>(T, 1) * 32;
+  const size_t need = 2 * sv_bytes + t_bytes + 512;
+  if (c->cap && c->alloc_bytes + need > c->cap) return fail(c, QIMAX_ENOMEM, "expect: memory cap exceeded");
+  void* mem = nullptr;
+  if (hipMalloc(&mem, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, QIMAX_ENOMEM, "expect: hipMalloc of the statevector failed");
+  }
+  c->peak_bytes = std::max(c->peak_bytes, (uint64_t)(c->alloc_bytes + need));
+  uint8_t* m = (uint8_t*)mem;
+  void* v = m;
+  void* tmp = m + sv_bytes;
+  uint64_t* xm = (uint64_t*)(m + 2 * sv_bytes);
+  uint64_t* zm = xm + std::max<uint64_t>(T, 1);
+  void* cf = zm + std::max<uint64_t>(T, 1);
+  double* acc = (double*)(m + 2 * sv_bytes + t_bytes);
+  auto done = [&](qimax_status st) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(mem);
+    return st;
+  };
+  hipError_t e = launch_sv_terms(c->KC, c->WP, c->keys.p, c->w.p, T, n, xm, zm, cf, c->stream);
+  if (e == hipSuccess) e = launch_sv_random(v, D, 0x5eed5eedull + n, c->stream);
+  for (uint32_t j = 0; j < n && e == hipSuccess; ++j) {
+    const uint64_t a = c->h_seg[j], b = c->h_seg[j + 1];
+    e = launch_sv_project(v, tmp, D, xm + a, zm + a, (uint8_t*)cf + a * 16, b - a, c->stream);
+  }
+  auto reduce = [&](uint64_t x, uint64_t z, double cre, double cim, int za, double* h) -> hipError_t {
+    hipError_t r = hipMemsetAsync(acc, 0, 64 * 8, c->stream);
+    if (r == hipSuccess) r = launch_sv_reduce(v, D, n, x, z, cre, cim, za, acc, c->stream);
+    if (r == hipSuccess) r = hipMemcpyAsync(h, acc, 64 * 8, hipMemcpyDeviceToHost, c->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+    return r;
+  };
+  double h[64];
+  if (e == hipSuccess && zall) {
+    e = reduce(0, 0, 0.0, 0.0, 1, h);
+    if (e == hipSuccess) {
+      if (!(h[0] > 1e-280)) return done(fail(c, QIMAX_EDEVICE, "expect: projection vanished"));
+      for (uint32_t q = 0; q < n; ++q) out[q] = h[1 + q] / h[0];
+    }
+  }
+  for (size_t i = 0; i < Ps.size() && e == hipSuccess && !zall; ++i) {
+    uint64_t x = 0, z = 0;
     int ny = 0;
     for (uint32_t q = 0; q < n; ++q) {
-      const int d = digit_of(key, n, q);
+      const int d = Ps[i][q];
       const uint64_t bit = 1ull << (n - 1 - q);
-      if (d == 1 || d == 2) xm |= bit;
-      if (d == 2 || d == 3) zm |= bit;
-      if (d == 2) ++ny;
+      if (d == 1 || d == 2) x |= bit;
+      if (d == 2 || d == 3) z |= bit;
+      ny += d == 2;
     }
-    static const cd iy[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
-    const cd ph = iy[ny & 3] * wt;
-    for (size_t i = 0; i < D; ++i) {
-      // P|i> = i^ny (-1)^{popcount(i & zm)} |i ^ xm>
-      const double s = (__builtin_popcountll(i & zm) & 1) ? -1.0 : 1.0;
-      if (accumulate) dst[i ^ xm] += ph * s * src[i];
-      else dst[i ^ xm] = ph * s * src[i];
+    static const double ph[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+    e = reduce(x, z, ph[ny & 3][0], ph[ny & 3][1], 0, h);
+    if (e == hipSuccess) {
+      if (!(h[0] > 1e-280)) return done(fail(c, QIMAX_EDEVICE, "expect: projection vanished"));
+      out[i] = h[1] / h[0];
     }
-  };
-  for (uint32_t j = 0; j < n; ++j) {
-    std::fill(tmp.begin(), tmp.end(), cd(0, 0));
-    for (uint64_t t = g.off[j]; t < g.off[j + 1]; ++t) apply_pauli(g.key[t], v, tmp, g.w[t], true);
-    double nrm = 0;
-    for (size_t i = 0; i < D; ++i) {
-      v[i] = 0.5 * (v[i] + tmp[i]);
-      nrm += std::norm(v[i]);
-    }
-    if (!(nrm > 1e-250)) return fail(c, QIMAX_EDEVICE, "expect: projection vanished");
-    const double sc = 1.0 / std::sqrt(nrm);
-    for (auto& x : v) x *= sc;
   }
-  u128 pk = 0;
-  for (uint32_t q = 0; q < n; ++q) pk |= (u128)P[q] << (2 * (n - 1 - q));
-  apply_pauli(pk, v, tmp, 1.0, false);
-  cd s(0, 0);
-  for (size_t i = 0; i < D; ++i) s += std::conj(v[i]) * tmp[i];
-  *out = s.real();
-  return QIMAX_OK;
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(c, e, "expect (device statevector)");
+  }
+  return done(QIMAX_OK);
+}
+
+// <P> for k strings: the GF(2) path for a stabilizer state, else the device statevector.
+qimax_status expect_strings(qimax_ctx* c, const std::vector<std::vector<int>>& Ps, double* out) {
+  QCHK(flush_pending(c));
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  bool cliff = false;
+  CliffordReducer red;
+  QCHK(clifford_reducer(c, &cliff, red));
+  if (cliff) {
+    for (size_t i = 0; i < Ps.size(); ++i)
+      if (!red.expect(Ps[i], &out[i])) return fail(c, QIMAX_EDEVICE, "inconsistent generator phases");
+    return QIMAX_OK;
+  }
+  return expect_device(c, Ps, false, out);
 }
 
 }  // namespace
@@ -1826,23 +1940,146 @@ qimax_status qimax_get_generators(qimax_ctx* c, uint64_t* gen_off, uint64_t* key
 qimax_status qimax_expect(qimax_ctx* c, const char* pauli, double* out) {
   if (!c || !pauli || !out) return QIMAX_EINVAL;
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
-  std::vector<int> P(c->n);
-  for (uint32_t q = 0; q < c->n; ++q) {
-    const char ch = pauli[q];
-    const char* pos = ch ? std::strchr("IXYZ", ch) : nullptr;
-    if (!pos) return fail(c, QIMAX_EINVAL, "pauli must be n letters of IXYZ");
-    P[q] = (int)(pos - "IXYZ");
+  if (std::strlen(pauli) != c->n) return fail(c, QIMAX_EINVAL, "pauli must be exactly n letters");
+  std::vector<std::vector<int>> Ps;
+  QCHK(parse_paulis(c, pauli, 1, Ps));
+  return expect_strings(c, Ps, out);
+}
+
+qimax_status qimax_expect_many(qimax_ctx* c, const char* paulis, size_t k, double* out) {
+  if (!c || (k && (!paulis || !out))) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  std::vector<std::vector<int>> Ps;
+  QCHK(parse_paulis(c, paulis, k, Ps));
+  if (k == 0) return QIMAX_OK;
+  return expect_strings(c, Ps, out);
+}
+
+qimax_status qimax_prob_zero_all(qimax_ctx* c, double* p0) {
+  if (!c || !p0) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  QCHK(flush_pending(c));
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  std::vector<double> z(c->n);
+  bool cliff = false;
+  CliffordReducer red;
+  QCHK(clifford_reducer(c, &cliff, red));
+  if (cliff) {
+    std::vector<int> P(c->n, 0);
+    for (uint32_t q = 0; q < c->n; ++q) {
+      std::fill(P.begin(), P.end(), 0);
+      P[q] = 3;
+      if (!red.expect(P, &z[q])) return fail(c, QIMAX_EDEVICE, "inconsistent generator phases");
+    }
+  } else {
+    QCHK(expect_device(c, {}, true, z.data()));
   }
-  if (pauli[c->n] != '\0') return fail(c, QIMAX_EINVAL, "pauli must be exactly n letters");
-  HostGens g;
-  QCHK(fetch(c, g));
-  bool single = true;
-  for (uint32_t j = 0; j < c->n; ++j) single &= (g.off[j + 1] - g.off[j]) == 1;
-  bool unit = single;
-  if (single)
-    for (uint32_t j = 0; j < c->n; ++j) unit &= std::fabs(std::fabs(g.w[g.off[j]]) - 1.0) < 1e-6;
-  if (unit) return expect_clifford(c, g, P, out);
-  return expect_state(c, g, P, out);
+  for (uint32_t q = 0; q < c->n; ++q) p0[q] = 0.5 * (1.0 + z[q]);
+  return QIMAX_OK;
+}
+
+qimax_status qimax_get_generators_xz(qimax_ctx* c, uint64_t* gen_off, uint64_t* x, uint64_t* z, double* w, size_t cap,
+                                     size_t* T) {
+  if (!c || !T) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  QCHK(flush_pending(c));
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  *T = (size_t)c->T;
+  if (gen_off) std::copy(c->h_seg.begin(), c->h_seg.end(), gen_off);
+  if (cap < c->T) return QIMAX_OK;
+  if (!gen_off || (c->T && (!x || !z || !w))) return fail(c, QIMAX_EINVAL, "output buffers are NULL");
+  if (c->T == 0) return QIMAX_OK;
+  const size_t tb = (size_t)c->T * 8;
+  void* mem = nullptr;
+  if (hipMalloc(&mem, 3 * tb) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, QIMAX_ENOMEM, "get_generators_xz: hipMalloc of the readout buffers failed");
+  }
+  uint64_t* dx = (uint64_t*)mem;
+  uint64_t* dz = dx + c->T;
+  double* dw = (double*)(dz + c->T);
+  hipError_t e = launch_keys_to_xz(c->KC, c->keys.p, c->T, c->n, dx, dz, c->stream);
+  if (e == hipSuccess) {
+    if (c->WP == 64) e = hipMemcpyAsync(dw, c->w.p, tb, hipMemcpyDeviceToDevice, c->stream);
+    else e = launch_weights_to_f64(c->WP, c->w.p, dw, c->T, c->stream);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(x, dx, tb, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(z, dz, tb, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(w, dw, tb, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(mem);
+  if (e != hipSuccess) return hip_fail(c, e, "get_generators_xz");
+  return QIMAX_OK;
+}
+
+qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
+                           uint64_t* n_tau_diff) {
+  if (!a || !b || !diff_norm || !ref_norm || !n_tau_diff) return QIMAX_EINVAL;
+  if (a->n != b->n) return fail(a, QIMAX_EINVAL, "compare: contexts of different n");
+  if (a->device != b->device) return fail(a, QIMAX_EINVAL, "compare: contexts on different devices");
+  if (a->broken || b->broken) return fail(a, QIMAX_ESTATE, "context unusable after an earlier device error");
+  QCHK(flush_pending(a));
+  {
+    qimax_status sb = flush_pending(b);
+    if (sb != QIMAX_OK) return fail(a, sb, std::string("compare: ") + b->last_error);
+  }
+  HIPCHK(a, hipStreamSynchronize(a->stream), "hipStreamSynchronize");
+  HIPCHK(a, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  const uint32_t n = a->n;
+  const uint64_t tile = compare_tile();
+  // tiles of one side's segments, side a then side b
+  HostTiling ta, tb;
+  make_tiling(a->h_seg, tile, ta);
+  make_tiling(b->h_seg, tile, tb);
+  const size_t na = ta.begin.size(), nb = tb.begin.size(), nt = na + nb;
+  std::vector<uint64_t> host_u64;
+  host_u64.insert(host_u64.end(), a->h_seg.begin(), a->h_seg.end());
+  host_u64.insert(host_u64.end(), b->h_seg.begin(), b->h_seg.end());
+  host_u64.insert(host_u64.end(), ta.begin.begin(), ta.begin.end());
+  host_u64.insert(host_u64.end(), tb.begin.begin(), tb.begin.end());
+  host_u64.insert(host_u64.end(), ta.end.begin(), ta.end.end());
+  host_u64.insert(host_u64.end(), tb.end.begin(), tb.end.end());
+  std::vector<uint32_t> segs(ta.seg);
+  segs.insert(segs.end(), tb.seg.begin(), tb.seg.end());
+  const size_t ou = host_u64.size() * 8, os = align256(ou), oacc = os + align256(std::max<size_t>(segs.size(), 1) * 4);
+  const size_t ocnt = oacc + align256((size_t)n * 16), total = ocnt + align256((size_t)n * 8);
+  void* mem = nullptr;
+  if (hipMalloc(&mem, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(a, QIMAX_ENOMEM, "compare: hipMalloc failed");
+  }
+  uint8_t* m = (uint8_t*)mem;
+  const uint64_t* d_aoff = (const uint64_t*)m;
+  const uint64_t* d_boff = d_aoff + (n + 1);
+  const uint64_t* d_beg = d_boff + (n + 1);
+  const uint64_t* d_end = d_beg + nt;
+  const uint32_t* d_seg = (const uint32_t*)(m + os);
+  double* acc = (double*)(m + oacc);
+  unsigned long long* cnt = (unsigned long long*)(m + ocnt);
+  hipStream_t st = a->stream;
+  hipError_t e = hipMemcpyAsync(m, host_u64.data(), ou, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !segs.empty()) e = hipMemcpyAsync(m + os, segs.data(), segs.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(acc, 0, total - oacc, st);
+  // pass 0 over a's terms (searched in b), pass 1 over b's (the reference) searched in a
+  if (e == hipSuccess)
+    e = launch_compare(a->KC, a->WP, b->WP, a->keys.p, a->w.p, b->keys.p, b->w.p, d_boff, d_beg, d_end, d_seg,
+                       (uint32_t)na, 0, tau, acc, cnt, st);
+  if (e == hipSuccess)
+    e = launch_compare(a->KC, b->WP, a->WP, b->keys.p, b->w.p, a->keys.p, a->w.p, d_aoff, d_beg + na, d_end + na,
+                       d_seg + na, (uint32_t)nb, 1, tau, acc, cnt, st);
+  std::vector<double> h_acc(2 * (size_t)n);
+  std::vector<unsigned long long> h_cnt(n);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_acc.data(), acc, (size_t)n * 16, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_cnt.data(), cnt, (size_t)n * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(mem);
+  if (e != hipSuccess) return hip_fail(a, e, "compare");
+  for (uint32_t j = 0; j < n; ++j) {
+    diff_norm[j] = std::sqrt(h_acc[2 * j]);
+    ref_norm[j] = std::sqrt(h_acc[2 * j + 1]);
+    n_tau_diff[j] = h_cnt[j];
+  }
+  return QIMAX_OK;
 }
 
 qimax_status qimax_get_stats(const qimax_ctx* c, qimax_stats* out) {
@@ -2026,7 +2263,7 @@ qimax_status plan_circuit(qimax_batch* b, const qimax_circuit* q, double eps, Ba
                        nullptr, nullptr));
     std::vector<const HostOp*> all = pending;
     for (auto& op : ops) {
-      op.group += (int)(l * 1000000);
+      op.group += (int64_t)l << 32;  // layers in order (a layer has fewer than 2^32 groups)
       bc.ops.push_back(std::move(op));
       all.push_back(&bc.ops.back());
     }
@@ -2040,6 +2277,7 @@ qimax_status plan_circuit(qimax_batch* b, const qimax_circuit* q, double eps, Ba
   if (!pending.empty()) {  // trailing Clifford operators: one permutation-only pass
     Pass p;
     p.A = pending;
+    count_clifford_groups(p, {});
     bc.passes.push_back(p);
     bc.thr.push_back(0.0);
   }

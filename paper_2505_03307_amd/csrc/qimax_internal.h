@@ -318,4 +318,28 @@ hipError_t launch_compose_ptm(const uint8_t* gate, const double* theta, const ui
                               const uint32_t* chain_off, uint32_t n_chains, double* ptm_out,
                               hipStream_t s, Prof* prof = nullptr);
 
+// ------------------------------------------------------------- readout (readout.hip)
+// Keys as x / z bit words (bit q: qubit q), one word each (n <= 64).
+hipError_t launch_keys_to_xz(int KC, const void* keys, uint64_t T, uint32_t n, uint64_t* x, uint64_t* z,
+                             hipStream_t s);
+// Per-generator comparison of side a with side b (see k_compare); tiles of at most
+// compare_tile() elements of side a, each inside one segment; acc[2s] / acc[2s+1] and cnt[s]
+// accumulate (zeroed by the caller).
+size_t compare_tile();
+hipError_t launch_compare(int KC, int WPa, int WPb, const void* ka, const void* wa, const void* kb, const void* wb,
+                          const uint64_t* b_off, const uint64_t* t_begin, const uint64_t* t_end, const uint32_t* t_seg,
+                          uint32_t n_tiles, int count_ref, double tau, double* acc, unsigned long long* cnt,
+                          hipStream_t s);
+// Statevector readout: 2^n complex amplitudes (double2).
+hipError_t launch_sv_terms(int KC, int WP, const void* keys, const void* w, uint64_t T, uint32_t n, uint64_t* xm,
+                           uint64_t* zm, void* cf, hipStream_t s);
+hipError_t launch_sv_random(void* v, uint64_t D, uint64_t seed, hipStream_t s);
+// v <- (v + G v) / 2 for the generator given by T terms (masks and coefficients); tmp: D amplitudes.
+hipError_t launch_sv_project(void* v, void* tmp, uint64_t D, const uint64_t* xm, const uint64_t* zm, const void* cf,
+                             uint64_t T, hipStream_t s);
+// acc[0] += |v|^2; zall = 0: acc[1] + i acc[2] += <v|c P|v> for the string (xm, zm, c);
+// zall = 1: acc[1 + q] += sum_i |v_i|^2 (1 - 2 bit_q(i)) for every qubit q < n (n <= 32).
+hipError_t launch_sv_reduce(const void* v, uint64_t D, uint32_t n, uint64_t xm, uint64_t zm, double c_re,
+                            double c_im, int zall, double* acc, hipStream_t s);
+
 }  // namespace qimax

@@ -6,11 +6,12 @@ plain copy kernel of known size (`qimax_copy_probe`), and writes, per kernel, th
 HBM bytes per launch: (FETCH_SIZE x f_fetch + WRITE_SIZE x f_write) x 1024, where the
 factors f scale each counter so that the copy kernel reads and writes exactly its bytes.
 
-    python -m paper_2505_03307_amd.hbm_traffic --fetch DIR --write DIR \
+    python -m paper_2505_03307_amd.hbm_traffic --workload c2 --fetch DIR --write DIR \
         --copy-fetch DIR --copy-write DIR --copy-bytes B -o profiles/traffic.json
 
-The output is keyed by the kernel names the library's profiler uses and carries a hash of
-the kernel sources: a reader ignores an entry whose kernels have changed since.
+The output holds one object per workload (merged into an existing file), keyed by the kernel
+names the library's profiler uses; every entry carries a hash of the kernel sources: a
+reader ignores an entry whose kernels have changed since.
 """
 from __future__ import annotations
 
@@ -75,6 +76,7 @@ def main(argv=None):
     ap.add_argument("--copy-write", required=True)
     ap.add_argument("--copy-bytes", type=float, required=True, help="bytes one copy launch reads (and writes)")
     ap.add_argument("-o", "--out", required=True)
+    ap.add_argument("--workload", required=True, help="name of the profiled workload (e.g. c2, hea-fp64)")
     a = ap.parse_args(argv)
     fetch, write = read_counter(a.fetch, "FETCH_SIZE"), read_counter(a.write, "WRITE_SIZE")
     cf = per_kernel(read_counter(a.copy_fetch, "FETCH_SIZE"), KERNELS["copy"])
@@ -97,8 +99,15 @@ def main(argv=None):
         wb = sum(wv) / len(wv) * 1024.0 * f_write
         out[name] = {"launches": len(fv), "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
                      "bytes_per_launch": round(fb + wb), "source_hash": src}
+    allw = {}
+    if os.path.exists(a.out):
+        with open(a.out) as fh:
+            allw = json.load(fh)
+        if "_calibration" in allw:  # an older single-workload file
+            allw = {}
+    allw[a.workload] = out
     with open(a.out, "w") as fh:
-        json.dump(out, fh, indent=1, sort_keys=True)
+        json.dump(allw, fh, indent=1, sort_keys=True)
         fh.write("\n")
     print(json.dumps(out, indent=1, sort_keys=True))
 

@@ -39,7 +39,8 @@ class Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("terms", "passes", "term_updates", "images", "sort_elems", "peak_bytes", "alloc_bytes")] + \
                [("host_wait_ms", ctypes.c_double), ("host_busy_ms", ctypes.c_double), ("syncs", ctypes.c_uint64),
-                ("sort_redos", ctypes.c_uint64), ("tuned_classes", ctypes.c_uint64)]
+                ("sort_redos", ctypes.c_uint64), ("tuned_classes", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("alg_bytes", ctypes.c_double)]
 
 
 class CircuitC(ctypes.Structure):
@@ -63,7 +64,8 @@ EXPORTS = ["qimax_batch_create", "qimax_batch_submit", "qimax_batch_step", "qima
            "qimax_batch_fetch", "qimax_batch_info", "qimax_batch_circuit_updates", "qimax_batch_context",
            "qimax_batch_last_error", "qimax_batch_destroy",
            "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
-           "qimax_num_terms", "qimax_get_generators", "qimax_expect", "qimax_get_stats", "qimax_sync",
+           "qimax_num_terms", "qimax_get_generators", "qimax_get_generators_xz", "qimax_expect",
+           "qimax_expect_many", "qimax_prob_zero_all", "qimax_compare", "qimax_get_stats", "qimax_sync",
            "qimax_profile", "qimax_profile_only", "qimax_profile_read", "qimax_copy_probe", "qimax_last_error", "qimax_destroy"]
 
 _lib = None
@@ -96,6 +98,10 @@ def load():
     lib.qimax_num_terms.argtypes = [P, u64p]
     lib.qimax_get_generators.argtypes = [P, u64p, u64p, dp, ctypes.c_size_t, szp]
     lib.qimax_expect.argtypes = [P, ctypes.c_char_p, dp]
+    lib.qimax_get_generators_xz.argtypes = [P, u64p, u64p, u64p, dp, ctypes.c_size_t, szp]
+    lib.qimax_expect_many.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t, dp]
+    lib.qimax_prob_zero_all.argtypes = [P, dp]
+    lib.qimax_compare.argtypes = [P, P, ctypes.c_double, dp, dp, u64p]
     lib.qimax_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.qimax_sync.argtypes = [P]
     lib.qimax_profile.argtypes = [P, ctypes.c_int]
@@ -258,10 +264,47 @@ class Simulator:
                                              _p(w, ctypes.c_double), T.value, ctypes.byref(T)))
         return off, keys[:T.value], w[:T.value]
 
+    def generators_xz(self):
+        """(gen_off [n+1], x [T], z [T] uint64 bit words (bit q: qubit q), weights [T] float64)."""
+        lib = load()
+        T = ctypes.c_size_t()
+        off = np.zeros(self.n + 1, dtype=np.uint64)
+        self._check(lib.qimax_get_generators_xz(self._h, _p(off, ctypes.c_uint64), None, None, None, 0,
+                                                ctypes.byref(T)))
+        x = np.zeros(max(T.value, 1), dtype=np.uint64)
+        z = np.zeros(max(T.value, 1), dtype=np.uint64)
+        w = np.zeros(max(T.value, 1), dtype=np.float64)
+        self._check(lib.qimax_get_generators_xz(self._h, _p(off, ctypes.c_uint64), _p(x, ctypes.c_uint64),
+                                                _p(z, ctypes.c_uint64), _p(w, ctypes.c_double), T.value,
+                                                ctypes.byref(T)))
+        return off, x[:T.value], z[:T.value], w[:T.value]
+
     def expect(self, pauli: str) -> float:
         out = ctypes.c_double()
         self._check(load().qimax_expect(self._h, pauli.encode(), ctypes.byref(out)))
         return out.value
+
+    def expect_many(self, paulis) -> np.ndarray:
+        paulis = list(paulis)
+        out = np.zeros(max(len(paulis), 1), dtype=np.float64)
+        buf = "".join(paulis).encode()
+        self._check(load().qimax_expect_many(self._h, buf, len(paulis), _p(out, ctypes.c_double)))
+        return out[:len(paulis)]
+
+    def prob_zero_all(self) -> np.ndarray:
+        """p_{k,0} = (1 + <Z_k>)/2 for every qubit k."""
+        out = np.zeros(self.n, dtype=np.float64)
+        self._check(load().qimax_prob_zero_all(self._h, _p(out, ctypes.c_double)))
+        return out
+
+    def compare(self, ref: "Simulator", tau: float = 1e-6):
+        """Per generator (||w_self - w_ref||_2, ||w_ref||_2, keys with |w| > tau on one side only)."""
+        d = np.zeros(self.n, dtype=np.float64)
+        r = np.zeros(self.n, dtype=np.float64)
+        k = np.zeros(self.n, dtype=np.uint64)
+        self._check(load().qimax_compare(self._h, ref._h, float(tau), _p(d, ctypes.c_double), _p(r, ctypes.c_double),
+                                         _p(k, ctypes.c_uint64)))
+        return d, r, k
 
     def stats(self) -> dict:
         s = Stats()

@@ -77,3 +77,34 @@ def fp32_relative_errors(g32, g64):
         if allk.shape[0]:
             mx = max(mx, float(np.max(np.abs(va - vb))))
     return np.array(rel), mx
+
+
+def fp32_contract(g32, g64, eps, rel_tol=5e-6, tau_min=1e-6, delta=1e-9):
+    """The FP32-vs-FP64 contract, per generator: ||w32 - w64||_2 / ||w64||_2 <= rel_tol over the
+    union of keys; on K_tau = {|w| > tau}, tau = max(eps, tau_min), the key sets are equal
+    except for straddlers, keys on one side only whose FP64 weight lies within delta of tau
+    (rounding decides them). Returns (per-generator rel errors, straddlers, max |dw|)."""
+    rel, mx = fp32_relative_errors(g32, g64)
+    tau = max(eps, tau_min)
+    o32, k32, w32 = g32
+    o64, k64, w64 = g64
+    straddlers = 0
+    for j in range(len(o64) - 1):
+        a32, b32 = int(o32[j]), int(o32[j + 1])
+        a64, b64 = int(o64[j]), int(o64[j + 1])
+        s32 = _key_rows(k32[a32:b32][np.abs(w32[a32:b32]) > tau])
+        m64 = np.abs(w64[a64:b64]) > tau
+        s64 = _key_rows(k64[a64:b64][m64])
+        only = np.setxor1d(s32, s64, assume_unique=True)
+        if only.size:
+            allk = _key_rows(k64[a64:b64])
+            w_at = np.zeros(only.size)  # FP64 weight of each such key (0 when FP64 has no such key)
+            if allk.size:
+                pos = np.minimum(np.searchsorted(allk, only), allk.size - 1)
+                hit = allk[pos] == only
+                w_at[hit] = w64[a64:b64][pos[hit]]
+            off = np.abs(np.abs(w_at) - tau)
+            assert np.all(off <= delta), f"gen {j}: {int(np.sum(off > delta))} keys differ on K_tau beyond rounding"
+            straddlers += int(only.size)
+    assert float(rel.max(initial=0.0)) <= rel_tol, f"FP32 rel err {float(rel.max()):.3e} > {rel_tol}"
+    return rel, straddlers, mx

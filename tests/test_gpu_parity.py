@@ -111,24 +111,26 @@ def test_c2_full_size_seed0():
     say("c2 full residues", info)
 
 
-def test_hea_full_size_sampled():
-    """n=16, two layers, eps=1e-9 at full size (129M terms before pruning): every
-    generator's count against the closed form minus pruned terms is not available, so
-    the small generators are compared term by term with the oracle and the norm
-    invariant is checked on all of them."""
+def test_hea_full_size_every_generator():
+    """n=16, two layers, eps=0 at full size (129,140,286 terms): every generator's count
+    against the closed form, and every term of every generator against the oracle (raw key
+    sets identical, weights within 1e-12), plus the norm invariant."""
     c = W.c3_hea(seed=0, n=16, layers=2, eps=0.0)
-    say("hea full n=16 L=2")
+    say("hea full n=16 L=2, all generators")
+    t0 = time.time()
     s = run_gpu(c)
     g = s.generators()
+    s.close()
     counts = np.diff(g[0].astype(np.int64)).tolist()
     want = [3 ** 16 + 3] + [3 ** (16 - j) + 3 ** (17 - j) + 9 for j in range(1, 15)] + [12]
-    assert counts == want
+    assert counts == want and sum(counts) == 129_140_286
     for j in range(16):
         w = g[2][int(g[0][j]):int(g[0][j + 1])]
         assert abs(float(np.sum(w * w)) - 1.0) < 1e-10
-    gens = list(range(8, 16))
-    o = oracle.propagate(c, gens=gens, threads=8)
-    compare_fp64(g, oracle_arrays(o, 16), gens=gens, raw_exact=True, label="hea n=16 sampled")
+    o = oracle.propagate(c, threads=16)
+    say("hea full: oracle done", round(time.time() - t0, 1), "s")
+    info = compare_fp64(g, oracle_arrays(o, 16), raw_exact=True, label="hea n=16 full")
+    say("hea full: compared", info, round(time.time() - t0, 1), "s")
 
 
 def test_clifford_only_is_exact():
@@ -307,6 +309,51 @@ def test_grouping_matches_the_paper_partition():
 
 
 # --------------------------------------------------------------------------- precision
+
+@pytest.fixture(scope="module")
+def hea16_fp64():
+    """The n=16 two-layer ansatz at its stated precision setting (eps = 1e-9), FP64 on the GPU."""
+    c = W.c3_hea(seed=0, n=16, layers=2, eps=1e-9)
+    s = run_gpu(c)
+    yield c, s
+    s.close()
+
+
+@pytest.mark.parametrize("merge", [0, 1])
+def test_hea_full_size_fp32_contract(hea16_fp64, merge):
+    """The ansatz at full size in FP32 (compensated FP32 sums, or FP64 accumulation), eps =
+    1e-9, against FP64 on the GPU: per generator ||w32 - w64|| / ||w64|| <= 5e-6, keys on
+    K_tau (tau = 1e-6) identical up to counted straddlers; the library's own per-generator
+    error (qimax_compare) agrees with the host's."""
+    c, s64 = hea16_fp64
+    say("hea fp32 merge", merge)
+    s32 = run_gpu(c, precision=32, fp32_merge=merge)
+    d, r, kdiff = s32.compare(s64, tau=1e-6)
+    rel_lib = d / np.where(r > 0, r, 1.0)
+    rel, strad, mx = fp32_contract(s32.generators(), s64.generators(), eps=1e-9)
+    say("hea fp32 merge", merge, "rel max", float(rel.max()), "lib", float(rel_lib.max()), "straddlers", strad,
+        "max |dw|", mx)
+    assert np.allclose(rel_lib, rel, rtol=1e-6, atol=1e-12)
+    assert int(kdiff.sum()) == strad
+    assert float(rel_lib.max()) <= 5e-6
+    s32.close()
+
+
+@pytest.mark.parametrize("merge", [0, 1])
+def test_c2_full_size_fp32_contract(merge):
+    """The n=32 Clifford+Rz workload at full size in FP32 against FP64 (eps = 0)."""
+    c = W.c2_clifford_rz(seed=0)
+    say("c2 fp32 merge", merge)
+    s64 = run_gpu(c)
+    s32 = run_gpu(c, precision=32, fp32_merge=merge)
+    d, r, kdiff = s32.compare(s64, tau=1e-6)
+    rel, strad, mx = fp32_contract(s32.generators(), s64.generators(), eps=0.0)
+    say("c2 fp32 merge", merge, "rel max", float(rel.max()), "straddlers", strad, "max |dw|", mx)
+    assert np.allclose(d / r, rel, rtol=1e-6, atol=1e-12)
+    assert int(kdiff.sum()) == strad
+    s32.close()
+    s64.close()
+
 
 @pytest.mark.parametrize("merge", [0, 1])
 def test_fp32_within_5e6_of_fp64(merge):
