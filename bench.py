@@ -176,6 +176,45 @@ def bench_serve(log, count: int = 200, budget_gb: float = 200.0, one_batch: bool
     return out
 
 
+def bench_families(log, reps: int = 3):
+    """The paper's families (Sec. V): GHZ, graph state and |XYZ + chain> at #Repeats from 10^2
+    to 10^5. Per case: instructions m, grouped runs K + K', the grouping alone (median ms), a
+    whole step (reset, grouping, propagation; median ms) and the average stabilizer rank
+    (terms per generator). The paper's claim: cost follows K + K' and the rank, not m."""
+    from paper_2505_03307_amd import workloads as W
+    from paper_2505_03307_amd.qimax import Simulator
+
+    cases = [("ghz", 64, r, 1) for r in (100, 1000, 10000)] + [("graph", 48, r, 1) for r in (100, 1000)] + \
+            [("xyz_chain", 12, r, 2) for r in (100, 1000, 10000, 100000)]
+    out = []
+    for fam, n, r, L in cases:
+        c = (W.ghz(n, repeats=r, layers=L) if fam == "ghz" else
+             W.graph_state(0, n, repeats=r, layers=L) if fam == "graph" else W.xyz_chain(0, n, repeats=r, layers=L))
+        with Simulator(n, device=0) as s:
+            s.run(c)  # warm-up (buffers)
+            s.sync()
+            tg, ts = [], []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                n_ops, K, Kp = s.group_counts(c)
+                tg.append(time.perf_counter() - t0)
+            for _ in range(reps):
+                s.sync()
+                t0 = time.perf_counter()
+                s.reset()
+                s.run(c)
+                s.flush()
+                s.sync()
+                ts.append(time.perf_counter() - t0)
+            terms = s.num_terms()
+        ent = {"family": fam, "n": n, "repeats": r, "layers": L, "m": c.m, "runs_K_plus_Kp": K + Kp, "operators": n_ops,
+               "grouping_ms": round(float(np.median(tg)) * 1e3, 3), "step_ms": round(float(np.median(ts)) * 1e3, 3),
+               "avg_rank": round(terms / n, 2)}
+        log("families", ent)
+        out.append(ent)
+    return out
+
+
 def run_workload(circ, precision: int, steps: int, warmup: int, fp32_merge: int = 0, label: str = ""):
     """Time `steps` propagation steps of one workload on one context. A step resets the
     generators to Z_j, runs every layer (grouping and passes) and ends with the final
@@ -187,6 +226,7 @@ def run_workload(circ, precision: int, steps: int, warmup: int, fp32_merge: int 
     def step():
         sim.reset()
         sim.run(circ)
+        sim.flush()  # a trailing Clifford run too: the final generators are in HBM
 
     # warm-up with every kernel timed: finds the kernel with the largest device time
     sim.profile(True)
@@ -248,9 +288,10 @@ def run_workload(circ, precision: int, steps: int, warmup: int, fp32_merge: int 
     return sim, out
 
 
-def cpu_oracle_baseline(circ, gen_updates: np.ndarray, reps: int = 3):
-    """The CPU oracle (as it stands) on the host cores: all generators with the box's thread
-    share, and a sample of generators on one thread; medians of `reps` runs."""
+def cpu_oracle_baseline(circ, gen_updates: np.ndarray, reps: int = 3, gens=None):
+    """The CPU oracle (as it stands) on the host cores: the generators `gens` (all by default)
+    with the box's thread share, and a sample of generators on one thread; medians of `reps`
+    runs."""
     import oracle
 
     def timed(gens, threads):
@@ -263,13 +304,13 @@ def cpu_oracle_baseline(circ, gen_updates: np.ndarray, reps: int = 3):
         return float(np.median(ts)), float(np.mean(ts))
 
     threads = min(16, os.cpu_count() or 1)
-    allg = list(range(circ.n))
+    allg = list(range(circ.n)) if gens is None else list(gens)
     med, mean = timed(allg, threads)
-    upd = float(gen_updates.sum())
+    upd = float(gen_updates[allg].sum())
     res = {"value": round(upd / med, 1), "unit": "term-updates/s", "cores": threads, "kind": "oracle",
            "seconds_median": round(med, 3), "seconds_mean": round(mean, 3), "runs": reps,
-           "sample": f"all {circ.n} generators of the workload, gate by gate in FP64, {threads} threads "
-                     f"(generators in parallel); median of {reps} runs"}
+           "sample": f"generators {allg[0]}..{allg[-1]} of {circ.n} of the workload, gate by gate in FP64, "
+                     f"{threads} threads (generators in parallel); median of {reps} runs"}
     # one thread: the generators with the fewest updates that together hold about 1/16 of them
     order = np.argsort(gen_updates)
     pick, acc = [], 0.0
@@ -300,7 +341,12 @@ def main():
     ap.add_argument("--precision", type=int, default=64, choices=(32, 64))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu", type=int, default=1, help="time the CPU oracle baseline (0: skip)")
-    ap.add_argument("--hea", type=int, default=1, help="the n=16 two-layer ansatz section (0: skip)")
+    ap.add_argument("--workload", choices=("c2", "hea"), default="c2",
+                    help="headline: the n=32 Clifford+Rz circuit (c2) or the n=16 two-layer ansatz (hea)")
+    ap.add_argument("--c2", type=int, default=1, help="the n=32 Clifford+Rz section when it is not the headline")
+    ap.add_argument("--c2-fp32", type=int, default=1, help="the FP32 run of the n=32 Clifford+Rz circuit (0: skip)")
+    ap.add_argument("--hea", type=int, default=1, help="the n=16 two-layer ansatz section when it is not the headline")
+    ap.add_argument("--families", type=int, default=1, help="the paper's circuit families section (0: skip)")
     ap.add_argument("--batch", type=int, default=256, help="circuits in the batched-vs-plain section (0: skip)")
     ap.add_argument("--serve", type=int, default=200, help="requests in the serving section (0: skip)")
     ap.add_argument("--serve-one-batch", action="store_true", help="also serve the trace with a single batch")
@@ -312,42 +358,68 @@ def main():
 
     from paper_2505_03307_amd import workloads as W
 
-    # ---- headline: the n=32 Clifford+Rz circuit
-    circ = W.c2_clifford_rz(seed=args.seed)
-    log("workload", circ.name, "instructions", circ.m)
-    sim, head = run_workload(circ, args.precision, args.steps, args.warmup, label="c2")
-    gen_updates = sim.generator_updates()
-    runs = max(args.warmup, 1) + 2 * args.steps  # generator_updates accumulates over every step
-    gen_updates = gen_updates / runs
-    # FP32 on the same circuit (compensated merge), with the library's stated error per generator
-    sim32, c2_32 = run_workload(circ, 32, args.steps, 2, label="c2-fp32")
-    dn, rn, kd = sim32.compare(sim, tau=1e-6)
-    c2_32["fp32_rel_err_vs_fp64_per_generator_max"] = float(np.max(dn / np.where(rn > 0, rn, 1.0)))
-    c2_32["keys_differing_on_K_1e-6"] = int(kd.sum())
-    sim32.close()
-    sim.close()
-    cpu = cpu_oracle_baseline(circ, gen_updates) if args.cpu else None
+    # ---- the n=32 Clifford+Rz circuit, FP64 (and FP32)
+    c2 = None
+    cpu = None
+    if args.workload == "c2" or args.c2:
+        circ = W.c2_clifford_rz(seed=args.seed)
+        log("workload", circ.name, "instructions", circ.m)
+        sim, c2 = run_workload(circ, args.precision, args.steps, args.warmup, label="c2")
+        gen_updates = sim.generator_updates()
+        runs = max(args.warmup, 1) + 2 * args.steps  # generator_updates accumulates over every step
+        gen_updates = gen_updates / runs
+        if args.c2_fp32:
+            # FP32 on the same circuit (compensated merge), with the library's stated error per generator
+            sim32, c2_32 = run_workload(circ, 32, args.steps, 2, label="c2-fp32")
+            dn, rn, kd = sim32.compare(sim, tau=1e-6)
+            c2_32["fp32_rel_err_vs_fp64_per_generator_max"] = float(np.max(dn / np.where(rn > 0, rn, 1.0)))
+            c2_32["keys_differing_on_K_1e-6"] = int(kd.sum())
+            c2["fp32"] = c2_32
+            sim32.close()
+        sim.close()
+        c2["workload"] = (f"random Clifford+Rz circuit, n=32, 200 moments, 40 Rz, seed {args.seed}, eps=0, "
+                          f"final terms {c2['final_terms']}")
+        c2["note"] = ("each grouped operator counted once; no two images of this circuit ever share a key, so its "
+                      "merges sum nothing; most updates are Clifford relabellings done by table lookup")
+        if args.cpu and args.workload == "c2":
+            cpu = cpu_oracle_baseline(circ, gen_updates)
 
-    # ---- the n=16 two-layer ansatz (the configuration with merging), FP64 and FP32
+    # ---- the n=16 two-layer ansatz (the configuration whose images merge), FP32 (and FP64)
     hea = None
-    if args.hea:
+    if args.workload == "hea" or args.hea:
         c3 = W.c3_hea(seed=0, n=16, layers=2, eps=1e-9)
         log("workload", c3.name)
-        hsteps = max(3, args.steps)
+        hsteps = args.steps if args.workload == "hea" else max(3, args.steps)
+        s32, h32 = run_workload(c3, 32, hsteps, args.warmup if args.workload == "hea" else 3, label="hea-fp32")
         s64, h64 = run_workload(c3, 64, hsteps, 3, label="hea-fp64")
-        s32, h32 = run_workload(c3, 32, hsteps, 3, label="hea-fp32")
         dn, rn, kd = s32.compare(s64, tau=1e-6)
         rel = dn / np.where(rn > 0, rn, 1.0)
         h32["fp32_rel_err_vs_fp64_per_generator"] = [float(f"{x:.3e}") for x in rel]
+        h32["fp32_rel_err_vs_fp64_max"] = float(rel.max())
         h32["keys_differing_on_K_1e-6"] = int(kd.sum())
+        gen_updates = s32.generator_updates() / (max(args.warmup if args.workload == "hea" else 3, 1) + 2 * hsteps)
         s32.close()
         s64.close()
         hea = {"workload": "hardware-efficient ansatz n=16, 2 layers (Rx,Ry,Rz per qubit + CX ladder), "
-                           "eps=1e-9, seed 0", "fp64": h64, "fp32": h32,
+                           "eps=1e-9, seed 0", "fp32": h32, "fp64": h64,
                "note": "two layers reach 1.29e8 terms; a third would exceed 288 GB"}
+        if args.cpu and args.workload == "hea":
+            # generators 0..3 hold 95% of the terms: the multi-thread sample leaves them out
+            cpu = cpu_oracle_baseline(c3, gen_updates, gens=list(range(4, 16)))
 
+    families = bench_families(log) if args.families else None
     batch = bench_batch(log, args.batch) if args.batch else None
     serving = bench_serve(log, args.serve, one_batch=args.serve_one_batch) if args.serve else None
+    if args.workload == "c2":
+        head, dtype, wl = c2, ("f64" if args.precision == 64 else "f32"), c2["workload"]
+        cfg = {"workload": wl, "n_qubits": 32, "instructions": int(circ.m), "final_terms": c2["final_terms"],
+               "term_updates_per_step": c2["term_updates_per_step"], "note": c2["note"]}
+    else:
+        head, dtype = hea["fp32"], "f32"
+        cfg = {"workload": hea["workload"] + ", FP32 weights with compensated (TwoSum) merge",
+               "n_qubits": 16, "layers": 2, "final_terms": head["final_terms"],
+               "term_updates_per_step": head["term_updates_per_step"],
+               "fp32_rel_err_vs_fp64_max": head["fp32_rel_err_vs_fp64_max"]}
     out = {
         "metric": "Pauli-term updates/sec + HBM GB/s fraction; batched vs plain at 5e-6 rel err",
         "value": head["value"],
@@ -359,22 +431,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 64 else "f32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"random Clifford+Rz circuit, n=32, 200 moments, 40 Rz, seed {args.seed}, "
-                               f"eps=0, final terms {head['final_terms']}",
-                   "n_qubits": circ.n, "instructions": circ.m, "final_terms": head["final_terms"],
-                   "term_updates_per_step": head["term_updates_per_step"],
-                   "note": "each grouped operator counted once; no two images of this circuit ever share a "
-                           "key, so its merges sum nothing (the ansatz section is the workload that merges); "
-                           "most updates are Clifford relabellings done by table lookup"},
+        "config": cfg,
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "loop": head["loop"],
         "kernels": head["kernels"],
         "host": head["host"],
-        "c2_fp32": c2_32,
+        "c2_clifford_rz_n32": c2,
         "hea_n16": hea,
+        "families": families,
         "batched_vs_plain": batch,
         "serving": serving,
     }

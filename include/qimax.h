@@ -112,7 +112,15 @@ qimax_status qimax_group_circuit(qimax_ctx* ctx, const uint8_t* gate, const uint
                                  qimax_op* ops, double* ptm_buf, size_t cap, size_t* n_ops,
                                  size_t* n_u, size_t* n_v);
 
-/* Total number of terms held (all generators). Cheap; synchronises the stream. */
+/* Applies the operators a call kept back: a trailing run of Clifford operators (signed
+ * permutations of the terms, Sec. III-C-2) is held for the next call, where it joins that
+ * call's first pass, or for readout, which applies it first. After qimax_flush the device
+ * holds the generators of every operator applied so far (the end of the paper's timing
+ * window, Sec. V). On failure the generators are unchanged. */
+qimax_status qimax_flush(qimax_ctx* ctx);
+
+/* Total number of terms held (all generators). Cheap; synchronises the stream. Operators
+ * kept back by the last call (see qimax_flush) do not change the count. */
 qimax_status qimax_num_terms(qimax_ctx* ctx, uint64_t* T);
 
 /* Copies the generators to host memory (the paper's Lambda and index tensor, Alg. 2):

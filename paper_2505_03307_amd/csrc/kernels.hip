@@ -1058,9 +1058,8 @@ constexpr int kChunkBlock = 512;  // threads of a chunk-local sort (8 waves)
 template <typename K, typename W>
 __global__ void __launch_bounds__(kChunkBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __restrict__ keys_out, W* __restrict__ w_out,
-             Tiling tc, uint32_t n_pass, uint32_t m, const PassArgs* __restrict__ pas,
-             const uint32_t* __restrict__ seg_entry, int fp64_acc, uint32_t* __restrict__ chunk_cnt,
-             uint64_t* __restrict__ chunk_start, uint32_t* err) {
+             uint64_t out_cap, Tiling tc, uint32_t n_pass, uint32_t m, const PassArgs* __restrict__ pas,
+             const uint32_t* __restrict__ seg_entry, int fp64_acc, ChunkOut co, uint32_t* err) {
   constexpr int kItems = kChunkCap / kChunkBlock, kWaves = kChunkBlock / 64;
   __shared__ K sk[kChunkCap];
   __shared__ uint16_t sidx[kChunkCap];
@@ -1072,13 +1071,83 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   __shared__ uint64_t cb[2];
   __shared__ uint32_t nb_sh, fallback_sh;
   __shared__ __align__(16) uint8_t vary_sh[kWaves * sizeof(K)];
-  const uint32_t blk = blockIdx.x;
-  if (tc.n_dev && blk >= *tc.n_dev) return;
-  auto none = [&]() {  // this chunk keeps nothing (empty, or handed to the fallback)
+  __shared__ uint32_t blk_sh, last_sh;
+  __shared__ uint64_t base_sh;
+  // chunks are claimed in order, so every chunk a look-back waits for is running or done
+  if (threadIdx.x == 0) blk_sh = atomicAdd(co.ticket, 1u);
+  __syncthreads();
+  const uint32_t blk = blk_sh;
+  const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
+  if (blk >= nc) return;
+  // The chunk's output offset: publish its kept count, look back over the earlier chunks for
+  // their prefix (decoupled look-back; status words [epoch:16][flag:2][value:46]).
+  auto lookback = [&](uint64_t tot) -> uint64_t {
     if (threadIdx.x == 0) {
-      chunk_cnt[blk] = 0;
-      chunk_start[blk] = 0;
+      const uint64_t ep = co.epoch << 48;
+      st_store(co.status + blk, ep | (blk == 0 ? kStPre : kStAgg) | tot);
+      uint64_t excl = 0;
+      if (blk > 0) {
+        uint32_t t = blk - 1;
+        uint32_t spins = 0;
+        while (true) {
+          const uint64_t v = st_load(co.status + t);
+          const bool ready = (v >> 48) == co.epoch && (v & (kStAgg | kStPre));
+          if (!ready) {
+            if (++spins > kSpinLimit) { atomicOr(err, kErrSpin); break; }
+            continue;
+          }
+          excl += v & kStValMask;
+          if ((v & kStPre) || t == 0) break;
+          --t;
+        }
+        st_store(co.status + blk, ep | kStPre | (excl + tot));
+      }
+      st_store(co.chunk_off + blk, excl);
+      if (blk + 1 == nc) st_store(co.chunk_off + nc, excl + tot);
+      base_sh = excl;
     }
+    __syncthreads();
+    return base_sh;
+  };
+  // The last chunk to finish publishes the round: segment output offsets, the packed
+  // readback area (image offsets, error word) and, last, its sequence word.
+  auto finish = [&]() {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last_sh = atomicAdd(co.done, 1u) + 1 == nc;
+    __syncthreads();
+    if (!last_sh) return;
+    __threadfence();
+    const uint32_t S = tc.n_segs;
+    const uint64_t total = st_load(co.chunk_off + nc);
+    for (uint32_t q = threadIdx.x; q <= S; q += kChunkBlock) {
+      const uint32_t f = min(tc.seg_blk[q], nc);
+      const uint64_t v = f == nc ? total : st_load(co.chunk_off + f);
+      co.seg_off_out[q] = v;
+      co.fin.result[q] = v;
+      if (!co.img_cnt) co.fin.result[S + 1 + q] = co.fin.img_seg[q];
+    }
+    if (co.img_cnt) {  // image offsets of the segments from their counts (serial runs, one block scan)
+      const uint32_t ps = (S + kChunkBlock - 1) / kChunkBlock;
+      const uint32_t q0 = min(threadIdx.x * ps, S), q1 = min(q0 + ps, S);
+      uint64_t isum = 0;
+      for (uint32_t q = q0; q < q1; ++q) isum += co.img_cnt[q];
+      uint64_t itot;
+      uint64_t irun = block_excl_scan<kChunkBlock>(isum, scan_sh, &itot);
+      for (uint32_t q = q0; q < q1; ++q) {
+        co.fin.result[S + 1 + q] = irun;
+        irun += co.img_cnt[q];
+      }
+      if (threadIdx.x == 0) co.fin.result[2 * (uint64_t)S + 1] = itot;
+    }
+    if (threadIdx.x == 0)
+      co.fin.result[2 * (uint64_t)S + 2] =
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | (total > out_cap ? kErrIndex | kErrMerge : 0u);
+    publish_seq(co.fin, S);
+  };
+  auto none = [&]() {  // this chunk keeps nothing (empty, or handed to the fallback)
+    lookback(0);
+    finish();
   };
   const uint64_t a = tc.blk_begin[blk], b = tc.blk_end[blk];
   if (a >= b) {
@@ -1173,7 +1242,8 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   // One stable LDS radix pass: the digit of an element comes from dig(key, bucket); key,
   // original index and bucket move together.
   uint32_t pass_no = 0;
-  auto radix_pass = [&](auto&& dig) {
+  // nbits: digits are below 2^nbits (a bit no lane sets leaves the ballot masks unchanged)
+  auto radix_pass = [&](auto&& dig, uint32_t nbits) {
     const int pb = pass_no++ & 1;
     K key[kItems];
     uint16_t ix[kItems], bk[kItems];
@@ -1195,6 +1265,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
       uint32_t dlo = ~(uint32_t)vm, dhi = ~(uint32_t)(vm >> 32);
 #pragma unroll
       for (int bit = 0; bit < kRadixBits; ++bit) {
+        if ((uint32_t)bit >= nbits) break;
         const int spread = __builtin_amdgcn_sbfe((int)d, bit, 1);  // 0 or all ones
         const uint64_t bb = __builtin_amdgcn_ballot_w64(spread != 0);
         dlo |= (uint32_t)bb ^ (uint32_t)spread;
@@ -1255,8 +1326,8 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   const uint32_t g_shift = two_pass ? top_shift - 8u : top_shift;
   auto gkey = [&](K key) -> K { return (two_pass || m > 0) ? (K)(key >> g_shift) : (K)0; };
   if (two_pass) {
-    radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> g_shift); });
-    if (nb > 1) radix_pass([&](K, uint32_t bkt) { return bkt; });
+    radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> g_shift); }, kRadixBits);
+    if (nb > 1) radix_pass([&](K, uint32_t bkt) { return bkt; }, 32u - (uint32_t)__clz((int)(nb - 1)));
   }
   if (threadIdx.x == 0) fallback_sh = 0;
   __syncthreads();
@@ -1280,7 +1351,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
     for (uint32_t j = threadIdx.x; j < n; j += kChunkBlock) vary |= sk[j] ^ sk[0];
     vary = block_or<kChunkBlock>(vary, (K*)vary_sh);
     for (uint32_t p = 0; p < n_pass; ++p)
-      if ((uint32_t)(vary >> (8u * p)) & 255u) radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> (8u * p)); });
+      if ((uint32_t)(vary >> (8u * p)) & 255u) radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> (8u * p)); }, kRadixBits);
   } else {
     for (uint32_t j = threadIdx.x; j < n; j += kChunkBlock) {
       const uint32_t e = j + sbk[j];
@@ -1334,125 +1405,22 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
     }
   }
   uint64_t tot;
-  uint64_t o = c0 + block_excl_scan<kChunkBlock>(keep, scan_sh, &tot);
+  const uint64_t pre = block_excl_scan<kChunkBlock>(keep, scan_sh, &tot);
+  const uint64_t base = lookback(tot);
+  // every kept run straight to its output position
+  if (base + tot <= out_cap) {
+    uint64_t o = base + pre;
 #pragma unroll
-  for (int t = 0; t < kItems; ++t) {
-    if (!(keep_mask & (1u << t))) continue;
-    keys_out[o] = sk[j0 + t];
-    w_out[o] = sums[t];
-    ++o;
-  }
-  if (threadIdx.x == 0) {
-    chunk_cnt[blk] = (uint32_t)tot;
-    chunk_start[blk] = c0;
-  }
-}
-
-// After the chunk-local sort and merge (one block): chunk_off = exclusive scan of the kept
-// counts of the n_chunks chunks (n_dev or n_blocks of tc), the segment output offsets
-// seg_off_out[s] = chunk_off[seg_blk[s]], and the packed readback area (see MergeFin), whose
-// image offsets are fin.img_seg, or the scan of img_cnt when set; a total above out_cap is
-// reported in the error word there (the compaction then writes nothing).
-constexpr int kPublishBlock = 1024;
-__global__ void __launch_bounds__(kPublishBlock) k_chunk_publish(Tiling tc, const uint32_t* __restrict__ chunk_cnt,
-                                                                 uint64_t* __restrict__ chunk_off,
-                                                                 uint64_t* __restrict__ seg_off_out, MergeFin fin,
-                                                                 const uint32_t* __restrict__ img_cnt, uint64_t out_cap,
-                                                                 const uint32_t* __restrict__ err) {
-  __shared__ uint64_t sh[kPublishBlock / 64];
-  __shared__ uint64_t total_sh;
-  const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
-  // thread t scans the run [t*per, (t+1)*per) serially: one block scan for all the runs
-  const uint32_t per = (nc + kPublishBlock - 1) / kPublishBlock;
-  const uint32_t r0 = min(threadIdx.x * per, nc), r1 = min(r0 + per, nc);
-  // (eight loads in flight at a time: the run is read twice)
-  constexpr uint32_t kBatch = 8;
-  uint64_t sum = 0;
-  for (uint32_t i0 = r0; i0 < r1; i0 += kBatch) {
-    uint32_t v[kBatch];
-#pragma unroll
-    for (uint32_t u = 0; u < kBatch; ++u) v[u] = i0 + u < r1 ? chunk_cnt[i0 + u] : 0u;
-#pragma unroll
-    for (uint32_t u = 0; u < kBatch; ++u) sum += v[u];
-  }
-  uint64_t tot;
-  uint64_t run = block_excl_scan<kPublishBlock>(sum, sh, &tot);
-  for (uint32_t i0 = r0; i0 < r1; i0 += kBatch) {
-    uint32_t v[kBatch];
-#pragma unroll
-    for (uint32_t u = 0; u < kBatch; ++u) v[u] = i0 + u < r1 ? chunk_cnt[i0 + u] : 0u;
-#pragma unroll
-    for (uint32_t u = 0; u < kBatch; ++u) {
-      if (i0 + u < r1) chunk_off[i0 + u] = run;
-      run += v[u];
+    for (int t = 0; t < kItems; ++t) {
+      if (!(keep_mask & (1u << t))) continue;
+      keys_out[o] = sk[j0 + t];
+      w_out[o] = sums[t];
+      ++o;
     }
+  } else if (threadIdx.x == 0 && tot) {
+    atomicOr(err, kErrIndex | kErrMerge);
   }
-  if (threadIdx.x == 0) {
-    chunk_off[nc] = tot;
-    total_sh = tot;
-  }
-  __syncthreads();
-  const uint32_t S = tc.n_segs;
-  for (uint32_t s = threadIdx.x; s <= S; s += kPublishBlock) {
-    const uint64_t v = chunk_off[min(tc.seg_blk[s], nc)];
-    seg_off_out[s] = v;
-    fin.result[s] = v;
-    if (!img_cnt) fin.result[S + 1 + s] = fin.img_seg[s];
-  }
-  if (img_cnt) {  // image offsets of the segments from their counts (same serial-run scan)
-    const uint32_t ps = (S + kPublishBlock - 1) / kPublishBlock;
-    const uint32_t q0 = min(threadIdx.x * ps, S), q1 = min(q0 + ps, S);
-    uint64_t isum = 0;
-    for (uint32_t q = q0; q < q1; ++q) isum += img_cnt[q];
-    uint64_t itot;
-    uint64_t irun = block_excl_scan<kPublishBlock>(isum, sh, &itot);
-    for (uint32_t q = q0; q < q1; ++q) {
-      fin.result[S + 1 + q] = irun;
-      irun += img_cnt[q];
-    }
-    if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 1] = itot;
-  }
-  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (total_sh > out_cap ? kErrIndex | kErrMerge : 0u);
-  publish_seq(fin, S);
-}
-
-// Moves every chunk's kept runs from the front of its range to their output offset.
-template <typename K, typename W>
-__global__ void __launch_bounds__(256) k_chunk_compact(const K* __restrict__ keys_in, const W* __restrict__ w_in,
-                                                       K* __restrict__ keys_out, W* __restrict__ w_out, Tiling tc,
-                                                       const uint32_t* __restrict__ chunk_cnt,
-                                                       const uint64_t* __restrict__ chunk_start,
-                                                       const uint64_t* __restrict__ chunk_off, uint64_t out_cap,
-                                                       uint32_t* err) {
-  const uint32_t blk = blockIdx.x;
-  if (tc.n_dev && blk >= *tc.n_dev) return;
-  const uint32_t cnt = chunk_cnt[blk];
-  const uint64_t src = chunk_start[blk], dst = chunk_off[blk];
-  if (dst + cnt > out_cap || cnt > (uint32_t)kChunkCap) {
-    if (threadIdx.x == 0 && cnt) atomicOr(err, kErrIndex | kErrMerge);
-    return;
-  }
-  // every load of a thread's share in flight before its stores (a chunk keeps at most
-  // kChunkCap terms: kChunkCap / 256 per thread)
-  constexpr int kPer = kChunkCap / 256;
-  K kv[kPer];
-  W wv[kPer];
-#pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const uint32_t i = r * 256 + threadIdx.x;
-    if (i < cnt) {
-      kv[r] = keys_in[src + i];
-      wv[r] = w_in[src + i];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const uint32_t i = r * 256 + threadIdx.x;
-    if (i < cnt) {
-      keys_out[dst + i] = kv[r];
-      w_out[dst + i] = wv[r];
-    }
-  }
+  finish();
 }
 
 // Digit histograms of the radix passes p_begin .. n_pass-1 at once, per segment:
@@ -1727,29 +1695,56 @@ __device__ void gate_ptm(uint32_t code, double th, double R[4][4]) {
   }
 }
 
-__global__ void k_compose_ptm(const uint8_t* __restrict__ gate, const double* __restrict__ theta,
-                              const uint32_t* __restrict__ idx, const uint32_t* __restrict__ chain_off,
-                              uint32_t n_chains, double* __restrict__ out) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_chains) return;
+// One wave per chain (Alg. 1 composes the gates of one wire of a U_k, in gate order): lane l
+// multiplies the gates of its contiguous slice of the chain in order, then the 64 partial
+// products are combined by a tree in LDS, the later slice always on the left (matrix products
+// are associative; only the rounding order differs from a serial product). A chain of
+// #Repeats x 3 rotations (the |XYZ + chain> workload at 10^5 repeats) thus takes about
+// len / 64 serial steps instead of len.
+constexpr int kComposeWaves = 4;
+__global__ void __launch_bounds__(64 * kComposeWaves)
+k_compose_ptm(const uint8_t* __restrict__ gate, const double* __restrict__ theta, const uint32_t* __restrict__ idx,
+              const uint32_t* __restrict__ chain_off, uint32_t n_chains, double* __restrict__ out) {
+  __shared__ double part[kComposeWaves][64][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t c = blockIdx.x * kComposeWaves + wid;
+  const bool valid = c < n_chains;  // a wave past the last chain still takes part in the barriers
+  const uint32_t a = valid ? chain_off[c] : 0u, len = valid ? chain_off[c + 1] - a : 0u;
+  const uint32_t k0 = a + (uint32_t)(((uint64_t)len * lane) / 64), k1 = a + (uint32_t)(((uint64_t)len * (lane + 1)) / 64);
   double R[4][4], G[4][4], P[4][4];
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) R[a][b] = (a == b) ? 1.0 : 0.0;
-  for (uint32_t k = chain_off[c]; k < chain_off[c + 1]; ++k) {
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) R[i][j] = (i == j) ? 1.0 : 0.0;
+  for (uint32_t k = k0; k < k1; ++k) {
     const uint32_t gi = idx[k];
     gate_ptm(gate[gi], theta[gi], G);
-    // later gate acts on the images of the earlier ones: R <- G R
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) {
-        double s = 0.0;
-        for (int t = 0; t < 4; ++t) s += G[a][t] * R[t][b];
-        P[a][b] = s;
+    // a later gate acts on the images of the earlier ones: R <- G R
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double sum = 0.0;
+        for (int t = 0; t < 4; ++t) sum += G[i][t] * R[t][j];
+        P[i][j] = sum;
       }
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) R[a][b] = P[a][b];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) R[i][j] = P[i][j];
   }
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) out[(uint64_t)c * 16 + a * 4 + b] = R[a][b];
+  for (int i = 0; i < 16; ++i) part[wid][lane][i] = R[i >> 2][i & 3];
+  for (int step = 1; step < 64; step <<= 1) {
+    __syncthreads();
+    if ((lane & (2 * step - 1)) == 0) {
+      const double* L = part[wid][lane + step];  // the later slice
+      const double* Rr = part[wid][lane];
+      double Q[16];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          double sum = 0.0;
+          for (int t = 0; t < 4; ++t) sum += L[i * 4 + t] * Rr[t * 4 + j];
+          Q[i * 4 + j] = sum;
+        }
+      for (int i = 0; i < 16; ++i) part[wid][lane][i] = Q[i];
+    }
+  }
+  __syncthreads();
+  if (valid && lane < 16) out[(uint64_t)c * 16 + lane] = part[wid][0][lane];
 }
 
 inline uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)((n + block - 1) / block); }
@@ -2011,44 +2006,29 @@ hipError_t launch_sort_sweep(int KC, int WP, void* const keys[2], void* const w[
   return hipGetLastError();
 }
 
-hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* tmp_keys,
-                                   void* tmp_w, void* keys_out, void* w_out, uint64_t T, const Tiling& tc,
-                                   uint32_t n_pass, uint32_t m, const PassArgs* pas, const uint32_t* seg_entry,
-                                   uint32_t* chunk_cnt, uint64_t* chunk_start, uint64_t* chunk_off,
-                                   uint64_t* seg_off_out, const MergeFin& fin, const uint32_t* img_cnt, uint32_t* err,
+hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* keys_out,
+                                   void* w_out, uint64_t T, const Tiling& tc, uint32_t n_pass, uint32_t m,
+                                   const PassArgs* pas, const uint32_t* seg_entry, const ChunkOut& co, uint32_t* err,
                                    hipStream_t s, Prof* prof) {
   if (tc.n_blocks == 0) {
-    if (img_cnt) return hipErrorInvalidValue;  // chunks are the segments: S is 0 too
-    k_merge_publish<<<1, 256, 0, s>>>(tc, nullptr, seg_off_out, fin, err, 1);
+    if (co.img_cnt) return hipErrorInvalidValue;  // chunks are the segments: S is 0 too
+    k_merge_publish<<<1, 256, 0, s>>>(tc, nullptr, co.seg_off_out, co.fin, err, 1);
     return hipGetLastError();
   }
   const double kb = 4 << KC, wb = WP == 64 ? 8 : 4;
   hipEvent_t ev = prof_begin(prof, s, kKChunkSort);
   QIMAX_DISPATCH_K(KC, {
     if (WP == 64)
-      k_chunk_sort<K, double><<<tc.n_blocks, kChunkBlock, 0, s>>>(
-          (const K*)keys_in, (const double*)w_in, (K*)tmp_keys, (double*)tmp_w, tc, n_pass, m, pas, seg_entry,
-          fp64_acc, chunk_cnt, chunk_start, err);
+      k_chunk_sort<K, double><<<tc.n_blocks, kChunkBlock, 0, s>>>((const K*)keys_in, (const double*)w_in,
+                                                                  (K*)keys_out, (double*)w_out, T, tc, n_pass, m, pas,
+                                                                  seg_entry, fp64_acc, co, err);
     else
-      k_chunk_sort<K, float><<<tc.n_blocks, kChunkBlock, 0, s>>>(
-          (const K*)keys_in, (const float*)w_in, (K*)tmp_keys, (float*)tmp_w, tc, n_pass, m, pas, seg_entry,
-          fp64_acc, chunk_cnt, chunk_start, err);
+      k_chunk_sort<K, float><<<tc.n_blocks, kChunkBlock, 0, s>>>((const K*)keys_in, (const float*)w_in, (K*)keys_out,
+                                                                 (float*)w_out, T, tc, n_pass, m, pas, seg_entry,
+                                                                 fp64_acc, co, err);
   });
   // bytes: every image read; the kept terms' bytes are added by the caller once known
   prof_end(prof, s, ev, kKChunkSort, (kb + wb) * (double)T);
-  k_chunk_publish<<<1, kPublishBlock, 0, s>>>(tc, chunk_cnt, chunk_off, seg_off_out, fin, img_cnt, T, err);
-  ev = prof_begin(prof, s, kKMergeWrite);
-  QIMAX_DISPATCH_K(KC, {
-    if (WP == 64)
-      k_chunk_compact<K, double><<<tc.n_blocks, 256, 0, s>>>((const K*)tmp_keys, (const double*)tmp_w, (K*)keys_out,
-                                                             (double*)w_out, tc, chunk_cnt, chunk_start, chunk_off, T,
-                                                             err);
-    else
-      k_chunk_compact<K, float><<<tc.n_blocks, 256, 0, s>>>((const K*)tmp_keys, (const float*)tmp_w, (K*)keys_out,
-                                                            (float*)w_out, tc, chunk_cnt, chunk_start, chunk_off, T,
-                                                            err);
-  });
-  prof_end(prof, s, ev, kKMergeWrite, 0.0);
   return hipGetLastError();
 }
 
@@ -2344,7 +2324,8 @@ hipError_t launch_compose_ptm(const uint8_t* gate, const double* theta, const ui
                               Prof* prof) {
   if (n_chains == 0) return hipSuccess;
   hipEvent_t ev = prof_begin(prof, s, kKCompose);
-  k_compose_ptm<<<grid_for(n_chains, 64), 64, 0, s>>>(gate, theta, idx, chain_off, n_chains, ptm_out);
+  k_compose_ptm<<<grid_for(n_chains, kComposeWaves), 64 * kComposeWaves, 0, s>>>(gate, theta, idx, chain_off,
+                                                                                    n_chains, ptm_out);
   prof_end(prof, s, ev, kKCompose, 0.0);
   return hipGetLastError();
 }

@@ -245,7 +245,7 @@ bool is_conjugation(const std::vector<double>& R, int dim) {
 constexpr int kMaxE1 = 64;
 constexpr int kBoundPathMaxFanout = 16;  // rounds with a larger fan-out bound read back their image count
 // tile counters of a round (after the per-pass, per-XCD sort counters)
-constexpr int kCtrCount = 252, kCtrMerge = 253;
+constexpr int kCtrCount = 252, kCtrMerge = 253, kCtrChunk = 254, kCtrChunkDone = 255;
 constexpr int kMaxE2 = 8;
 constexpr double kMaxFanout = 2147483647.0;
 
@@ -279,7 +279,7 @@ struct qimax_ctx {
   DevBuf desc, desc2, err, f64tmp;
   DevBuf ptab;  // chain tables of a whole call, compiled in one launch
   DevBuf akeys, asign;  // input terms after their pass's A chain, and the signs (count -> expand)
-  DevBuf chunk_cnt, chunk_start, chunk_off;  // chunk-local merge: kept runs per chunk
+  DevBuf chunk_off;  // chunk-local merge: output offset of every chunk
   DevBuf img_cnt;                            // small rounds: image count per segment
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
@@ -752,7 +752,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   const uint32_t key_bits = 2u * max_n;
   const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
   // ---- round prep: error word, tile counters, digit histograms (one launch)
-  // tile_ctr: [0, n_pass*kXcds) sort passes, [kCtrCount] count tiles, [kCtrMerge] merge tiles
+  // tile_ctr: [0, n_pass*kXcds) sort passes, [kCtrCount] count tiles, [kCtrMerge] merge tiles,
+  // [kCtrChunk] chunk tickets, [kCtrChunkDone] finished chunks
   const uint64_t nh = sweep ? (uint64_t)S * n_pass * kRadix : 0;
   if (sweep) QCHK(ensure(c, c->ghist, std::max<uint64_t>(nh, 1) * 4));
   QCHK(ensure(c, c->tile_ctr, 256 * 4));
@@ -975,15 +976,15 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     if (chunk_path) {
       const size_t nc = std::max<uint32_t>(tc_chunk.n_blocks, 1);
-      QCHK(ensure(c, c->chunk_cnt, nc * 4));
-      QCHK(ensure(c, c->chunk_start, nc * 8));
       QCHK(ensure(c, c->chunk_off, (nc + 1) * 8));
-      HIPCHK(c, launch_chunk_sort_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, c->ik[cur ^ 1].p,
-                                        c->iw[cur ^ 1].p, c->pk[slot].p, c->pw[slot].p, T_img, tc_chunk, n_pass, m_top,
-                                        pas, sent, (uint32_t*)c->chunk_cnt.p, (uint64_t*)c->chunk_start.p,
-                                        (uint64_t*)c->chunk_off.p, (uint64_t*)c->pseg[slot].p, fin,
-                                        small ? (const uint32_t*)c->img_cnt.p : nullptr, (uint32_t*)c->err.p,
-                                        c->stream, &c->prof), "chunk sort");
+      QCHK(status_words(nc));
+      c->mepoch += 1;
+      const ChunkOut co{ctr + kCtrChunk, ctr + kCtrChunkDone, (uint64_t*)c->mstatus.p, c->mepoch,
+                        (uint64_t*)c->chunk_off.p, (uint64_t*)c->pseg[slot].p, fin,
+                        small ? (const uint32_t*)c->img_cnt.p : nullptr};
+      HIPCHK(c, launch_chunk_sort_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, c->pk[slot].p,
+                                        c->pw[slot].p, T_img, tc_chunk, n_pass, m_top, pas, sent, co,
+                                        (uint32_t*)c->err.p, c->stream, &c->prof), "chunk sort");
     } else {
       uint64_t* mstatus = nullptr;
       if (sweep) {
@@ -1075,7 +1076,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   }
   if (c->prof.on) {  // the kept terms' bytes, known now
     const double kept = (double)T_out * (double)(eb + wbt);
-    if ((c->prof.mask >> kKMergeWrite) & 1u) c->prof.bytes[kKMergeWrite] += chunk_path ? 2.0 * kept : kept;
+    if (!chunk_path && ((c->prof.mask >> kKMergeWrite) & 1u)) c->prof.bytes[kKMergeWrite] += kept;
     if (chunk_path && ((c->prof.mask >> kKChunkSort) & 1u)) c->prof.bytes[kKChunkSort] += kept;
   }
   // ---- bookkeeping: one update per output image of every operator (a Clifford operator
@@ -1861,6 +1862,12 @@ qimax_status qimax_reset(qimax_ctx* c) {
   return QIMAX_OK;
 }
 
+qimax_status qimax_flush(qimax_ctx* c) {
+  if (!c) return QIMAX_EINVAL;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  return flush_pending(c);
+}
+
 qimax_status qimax_apply_layer(qimax_ctx* c, const qimax_op* ops, size_t n_ops) {
   if (!c) return QIMAX_EINVAL;
   if (n_ops && !ops) return fail(c, QIMAX_EINVAL, "ops is NULL");
@@ -2183,7 +2190,7 @@ void qimax_destroy(qimax_ctx* c) {
   DevBuf* bufs[] = {&c->keys, &c->w, &c->seg, &c->pk[0], &c->pk[1], &c->pw[0], &c->pw[1], &c->pseg[0],
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
-                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->chunk_cnt, &c->chunk_start, &c->img_cnt,
+                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->img_cnt,
                     &c->chunk_off};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);

@@ -240,18 +240,28 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
 
 // Chunk-local sort and merge after the top m digit passes (see k_chunk_sort): nominal chunks
 // are the tiles of tc (at most kChunkCap/2 images, segment-aligned). Each chunk is sorted in
-// LDS, its runs of equal keys summed and pruned (|sum| > its pass's thr) and compacted into
-// tmp at the chunk's range; a one-block scan of the kept counts gives the output offsets,
-// seg_off_out and the packed readback area (fin); the kept runs then move to keys_out/w_out.
-// chunk_cnt / chunk_start: tc.n_blocks words; chunk_off: tc.n_blocks + 1. Sets kErrRedo when
-// a bucket does not fit a chunk (the outputs are then not valid). With m = 0 every chunk must
-// be a whole segment (at most kChunkCap elements). img_cnt (S words, or null): the image
-// counts of the segments, scanned into the readback area instead of fin.img_seg.
-hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* tmp_keys,
-                                   void* tmp_w, void* keys_out, void* w_out, uint64_t T, const Tiling& tc,
-                                   uint32_t n_pass, uint32_t m, const PassArgs* pas, const uint32_t* seg_entry,
-                                   uint32_t* chunk_cnt, uint64_t* chunk_start, uint64_t* chunk_off,
-                                   uint64_t* seg_off_out, const MergeFin& fin, const uint32_t* img_cnt, uint32_t* err,
+// LDS and its runs of equal keys summed and pruned (|sum| > its pass's thr); chunks are claimed
+// in order (co.ticket) and each writes its kept runs straight to its output offset, found by
+// a decoupled look-back over the earlier chunks' kept counts (co.status, tagged co.epoch;
+// co.chunk_off receives every chunk's offset, tc.n_blocks + 1 words). The last chunk to
+// finish (co.done) writes seg_off_out and the packed readback area (co.fin). Sets kErrRedo
+// when a bucket does not fit a chunk (the outputs are then not valid). With m = 0 every chunk
+// must be a whole segment (at most kChunkCap elements). co.img_cnt (S words, or null): the
+// image counts of the segments, scanned into the readback area instead of fin.img_seg.
+// co.ticket and co.done must be zero at launch.
+struct ChunkOut {
+  uint32_t* ticket;
+  uint32_t* done;
+  uint64_t* status;
+  uint64_t epoch;
+  uint64_t* chunk_off;
+  uint64_t* seg_off_out;
+  MergeFin fin;
+  const uint32_t* img_cnt;
+};
+hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* keys_out,
+                                   void* w_out, uint64_t T, const Tiling& tc, uint32_t n_pass, uint32_t m,
+                                   const PassArgs* pas, const uint32_t* seg_entry, const ChunkOut& co, uint32_t* err,
                                    hipStream_t s, Prof* prof = nullptr);
 
 // Compile chains of permutation ops into ChainTables, one job per chain (jobs in device memory).

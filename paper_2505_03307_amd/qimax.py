@@ -63,7 +63,7 @@ class KernelTime(ctypes.Structure):
 EXPORTS = ["qimax_batch_create", "qimax_batch_submit", "qimax_batch_step", "qimax_batch_run", "qimax_batch_poll",
            "qimax_batch_fetch", "qimax_batch_info", "qimax_batch_circuit_updates", "qimax_batch_context",
            "qimax_batch_last_error", "qimax_batch_destroy",
-           "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
+           "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_flush", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
            "qimax_num_terms", "qimax_get_generators", "qimax_get_generators_xz", "qimax_expect",
            "qimax_expect_many", "qimax_prob_zero_all", "qimax_compare", "qimax_get_stats", "qimax_sync",
            "qimax_profile", "qimax_profile_only", "qimax_profile_read", "qimax_copy_probe", "qimax_last_error", "qimax_destroy"]
@@ -90,6 +90,7 @@ def load():
     lib.qimax_default_opts.restype = None
     lib.qimax_create.argtypes = [ctypes.c_uint32, ctypes.POINTER(Opts), ctypes.POINTER(P)]
     lib.qimax_reset.argtypes = [P]
+    lib.qimax_flush.argtypes = [P]
     lib.qimax_get_generator_updates.argtypes = [P, u64p, ctypes.c_size_t]
     lib.qimax_apply_layer.argtypes = [P, ctypes.POINTER(Op), ctypes.c_size_t]
     lib.qimax_apply_circuit.argtypes = [P, u8p, u32p, u32p, dp, ctypes.c_size_t]
@@ -195,6 +196,11 @@ class Simulator:
         self._check(load().qimax_reset(self._h))
         return self
 
+    def flush(self):
+        """Apply the operators the last call kept back (a trailing Clifford run)."""
+        self._check(load().qimax_flush(self._h))
+        return self
+
     def apply_circuit(self, circuit_or_arrays):
         g, a, b, t = _instr(circuit_or_arrays)
         self._check(load().qimax_apply_circuit(self._h, _p(g, ctypes.c_uint8), _p(a, ctypes.c_uint32),
@@ -221,6 +227,16 @@ class Simulator:
             arr[i].ptm = _p(R, ctypes.c_double)
         self._check(load().qimax_apply_layer(self._h, arr, len(ops)))
         return self
+
+    def group_counts(self, circuit_or_arrays):
+        """(number of grouped operators, K, K') of a circuit: the whole grouping pass runs, only
+        the counts come back."""
+        g, a, b, t = _instr(circuit_or_arrays)
+        n_ops, nu, nv = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(load().qimax_group_circuit(self._h, _p(g, ctypes.c_uint8), _p(a, ctypes.c_uint32),
+                                               _p(b, ctypes.c_uint32), _p(t, ctypes.c_double), g.size, None, None, 0,
+                                               ctypes.byref(n_ops), ctypes.byref(nu), ctypes.byref(nv)))
+        return n_ops.value, nu.value, nv.value
 
     def group(self, circuit_or_arrays):
         """The grouped operators (qubits, R) and (K, K') of a circuit, without applying it."""

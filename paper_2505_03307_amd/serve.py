@@ -62,8 +62,11 @@ def predict_bytes(c: W.Circuit, precision: int = 32, batch_max_n: int | None = N
     kb = 4 if cls <= 16 else (8 if cls <= 32 else 16)
     wb = 8 if precision == 64 else 4
     img, terms = predict_terms(c)
-    # images live in two ping-pong buffers plus the merged output; count + offset per term
-    return int(img * 3 * (kb + wb) + terms * (kb + wb + 12))
+    # the library's buffers for a round of `img` images (each grown with 25% headroom): two
+    # key/weight image buffers for the sort, and three term arrays sized by the images (the
+    # generators and the two output slots a call alternates between); per input term its A-chain
+    # key, sign byte and 8-byte image offset
+    return int(1.25 * (5 * img * (kb + wb) + terms * (kb + 9)))
 
 
 @dataclasses.dataclass

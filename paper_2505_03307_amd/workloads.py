@@ -296,3 +296,70 @@ def random_layered(seed: int, n: int, layers: int, gates_per_layer: int, eps: fl
     ends[-1] = m
     ends = np.unique(ends)
     return Circuit(n, c.gate, c.q0, c.q1, c.theta, ends, eps, f"layered(seed={seed},n={n},L={layers})")
+
+
+# ------------------------------------------------------------------------------------------
+# The paper's benchmark families (Sec. V): GHZ, graph state and |XYZ + chain>. The paper's
+# circuits came from a generator that is not available here; these are built from the
+# paper's description of their structure: L layers, each with its component repeated
+# #Repeats times (the gate count grows linearly with #Repeats and with n).
+
+def _from_arrays(n: int, gate, q0, q1, theta, layer_end, eps: float, name: str) -> Circuit:
+    return Circuit(n, np.asarray(gate, dtype=np.uint8), np.asarray(q0, dtype=np.uint32),
+                   np.asarray(q1, dtype=np.uint32), np.asarray(theta, dtype=np.float64),
+                   np.asarray(layer_end, dtype=np.int64), eps, name)
+
+
+def _repeat_block(n: int, gate, q0, q1, repeats: int, layers: int, name: str) -> Circuit:
+    """A parameter-free block repeated `repeats` times per layer, `layers` layers."""
+    g = np.tile(np.asarray(gate, dtype=np.uint8), repeats * layers)
+    a = np.tile(np.asarray(q0, dtype=np.uint32), repeats * layers)
+    b = np.tile(np.asarray(q1, dtype=np.uint32), repeats * layers)
+    per = len(gate) * repeats
+    ends = np.arange(1, layers + 1, dtype=np.int64) * per
+    return _from_arrays(n, g, a, b, np.zeros(g.shape[0]), ends, 0.0, name)
+
+
+def ghz(n: int, repeats: int = 1, layers: int = 1) -> Circuit:
+    """GHZ preparation (H on qubit 0, then CX(0,1), CX(1,2), ..., CX(n-2, n-1)) as the block,
+    repeated `repeats` times in each of `layers` layers. A Clifford circuit: every generator
+    stays a single Pauli string (stabilizer rank 1)."""
+    gate = [Gate.H] + [Gate.CX] * (n - 1)
+    q0 = [0] + list(range(n - 1))
+    q1 = [0] + list(range(1, n))
+    return _repeat_block(n, gate, q0, q1, repeats, layers, f"ghz(n={n},R={repeats},L={layers})")
+
+
+def graph_state(seed: int, n: int, repeats: int = 1, layers: int = 1, p_edge: float = 0.5) -> Circuit:
+    """Graph-state preparation on a seeded random graph G(n, p_edge): H on every qubit, then
+    CZ on every edge (in lexicographic edge order); the block repeated `repeats` times in each
+    of `layers` layers. Clifford: stabilizer rank 1."""
+    rng = _rng(seed)
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p_edge]
+    gate = [Gate.H] * n + [Gate.CZ] * len(edges)
+    q0 = list(range(n)) + [e[0] for e in edges]
+    q1 = list(range(n)) + [e[1] for e in edges]
+    return _repeat_block(n, gate, q0, q1, repeats, layers, f"graph(seed={seed},n={n},R={repeats},L={layers})")
+
+
+def xyz_chain(seed: int, n: int, repeats: int, layers: int = 1, eps: float = 0.0) -> Circuit:
+    """|XYZ + chain>: per layer, the XYZ component (Rx, Ry, Rz on every qubit, angles
+    U[0, 2pi)) repeated `repeats` times, then the chain CX(0,1), CX(1,2), ..., CX(n-2, n-1).
+    Each layer is one prune point. Built with array operations, so that #Repeats = 10^5
+    (millions of gates) is cheap."""
+    rng = _rng(seed)
+    per_rep = 3 * n
+    g1 = np.tile(np.array([Gate.RX, Gate.RY, Gate.RZ], dtype=np.uint8), n * repeats)
+    w1 = np.tile(np.repeat(np.arange(n, dtype=np.uint32), 3), repeats)
+    gs, qa, qb, th, ends = [], [], [], [], []
+    m = 0
+    for _ in range(layers):
+        angles = rng.uniform(0.0, 2.0 * math.pi, size=per_rep * repeats)
+        gs += [g1, np.full(n - 1, Gate.CX, dtype=np.uint8)]
+        qa += [w1, np.arange(n - 1, dtype=np.uint32)]
+        qb += [w1, np.arange(1, n, dtype=np.uint32)]
+        th += [angles, np.zeros(n - 1)]
+        m += per_rep * repeats + n - 1
+        ends.append(m)
+    return _from_arrays(n, np.concatenate(gs), np.concatenate(qa), np.concatenate(qb), np.concatenate(th),
+                        ends, eps, f"xyz_chain(seed={seed},n={n},R={repeats},L={layers})")

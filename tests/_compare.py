@@ -98,11 +98,13 @@ def fp32_contract(g32, g64, eps, rel_tol=5e-6, tau_min=1e-6, delta=1e-9):
         only = np.setxor1d(s32, s64, assume_unique=True)
         if only.size:
             allk = _key_rows(k64[a64:b64])
+            order = np.argsort(allk)  # byte order of the rows, which numeric order need not be
+            allk, wk = allk[order], w64[a64:b64][order]
             w_at = np.zeros(only.size)  # FP64 weight of each such key (0 when FP64 has no such key)
             if allk.size:
                 pos = np.minimum(np.searchsorted(allk, only), allk.size - 1)
                 hit = allk[pos] == only
-                w_at[hit] = w64[a64:b64][pos[hit]]
+                w_at[hit] = wk[pos[hit]]
             off = np.abs(np.abs(w_at) - tau)
             assert np.all(off <= delta), f"gen {j}: {int(np.sum(off > delta))} keys differ on K_tau beyond rounding"
             straddlers += int(only.size)

@@ -15,7 +15,7 @@ from paper_2505_03307_amd.qimax import QimaxError, Simulator
 from paper_2505_03307_amd.workloads import Gate
 
 import _dense as D
-from _compare import compare_fp64, fp32_relative_errors, oracle_arrays
+from _compare import compare_fp64, fp32_contract, fp32_relative_errors, oracle_arrays
 from _keys import LETTER, string_to_index
 
 pytestmark = pytest.mark.gpu
