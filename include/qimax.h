@@ -38,13 +38,21 @@ typedef enum {
 } qimax_status;
 
 /* Gate codes of the instruction form {gate, wire, theta} (Sec. III-A). Rotations are
- * R_s(theta) = exp(-i theta s / 2); T = R_z(pi/4) and SX = R_x(pi/2) up to a phase. */
+ * R_s(theta) = exp(-i theta s / 2); T = R_z(pi/4) and SX = R_x(pi/2) up to a phase. The
+ * two-qubit gates (codes 12-17) form the V_k runs; consecutive two-qubit gates of a run on
+ * the same pair of wires (no gate of the run touching either wire between them) are fused
+ * into one 16x16 operator. ISWAP is Clifford; RXX / RYY / RZZ expand a term that
+ * anticommutes with the rotation's Pauli pair into two images (Sec. II-C). */
 enum {
   QIMAX_GATE_H = 0, QIMAX_GATE_S = 1, QIMAX_GATE_SDG = 2, QIMAX_GATE_T = 3, QIMAX_GATE_TDG = 4,
   QIMAX_GATE_SX = 5, QIMAX_GATE_X = 6, QIMAX_GATE_Y = 7, QIMAX_GATE_Z = 8,
   QIMAX_GATE_RX = 9, QIMAX_GATE_RY = 10, QIMAX_GATE_RZ = 11,
   QIMAX_GATE_CX = 12, /* q0 = control, q1 = target */
-  QIMAX_GATE_CZ = 13
+  QIMAX_GATE_CZ = 13,
+  QIMAX_GATE_ISWAP = 14, /* exp(i pi/4 (XX + YY)) on (q0, q1) */
+  QIMAX_GATE_RXX = 15,   /* exp(-i theta XX / 2) on (q0, q1); RYY, RZZ likewise */
+  QIMAX_GATE_RYY = 16,
+  QIMAX_GATE_RZZ = 17
 };
 
 typedef struct {
@@ -112,12 +120,30 @@ qimax_status qimax_group_circuit(qimax_ctx* ctx, const uint8_t* gate, const uint
                                  qimax_op* ops, double* ptm_buf, size_t cap, size_t* n_ops,
                                  size_t* n_u, size_t* n_v);
 
-/* Applies the operators a call kept back: a trailing run of Clifford operators (signed
- * permutations of the terms, Sec. III-C-2) is held for the next call, where it joins that
- * call's first pass, or for readout, which applies it first. After qimax_flush the device
- * holds the generators of every operator applied so far (the end of the paper's timing
- * window, Sec. V). On failure the generators are unchanged. */
+/* Applies the operators a call kept back: a call whose operators are all Clifford (signed
+ * permutations of the terms, Sec. III-C-2) only records them; they join the next call's
+ * first pass, or readout applies them first. (A call with an expanding operator applies its
+ * Clifford operators within its own passes.) After qimax_flush the device holds the
+ * generators of every operator applied so far (the end of the paper's timing window, Sec. V).
+ * On failure the generators are unchanged. */
 qimax_status qimax_flush(qimax_ctx* ctx);
+
+/* A recorded step, replayed as one HIP graph (multi-circuit execution and fixed circuits are
+ * the paper's stated next step, Sec. VI): qimax_graph_record runs reset, every layer of the
+ * circuit (layer_end[0..n_layers), NULL for one layer) and qimax_flush once, capturing the
+ * launches between the host's synchronisations; qimax_graph_launch then replays them on the
+ * context's stream with no host work in between, leaving the same generators (bit for bit)
+ * and counting the same statistics. The replay is asynchronous (qimax_sync waits).
+ * Recording never allocates: every buffer the step needs must already be large enough, so run
+ * the step once before recording (QIMAX_ESTATE otherwise; the context is then reset). A graph
+ * refers to its context's buffers: a replay is refused (QIMAX_ESTATE) once any of them has
+ * been reallocated or freed since the recording. Destroy graphs before their context. */
+typedef struct qimax_graph qimax_graph;
+qimax_status qimax_graph_record(qimax_ctx* ctx, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
+                                const double* theta, size_t m, const uint64_t* layer_end, size_t n_layers,
+                                qimax_graph** out);
+qimax_status qimax_graph_launch(qimax_graph* g);
+void qimax_graph_destroy(qimax_graph* g);
 
 /* Total number of terms held (all generators). Cheap; synchronises the stream. Operators
  * kept back by the last call (see qimax_flush) do not change the count. */

@@ -64,6 +64,8 @@ def _load():
     lib.oracle_fanout_sum.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint8),
                                       u64p]
     lib.oracle_fanout_sum.restype = None
+    lib.oracle_fanout_sum2.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8), u64p]
+    lib.oracle_fanout_sum2.restype = None
     lib.oracle_count.restype = ctypes.c_size_t
     lib.oracle_count.argtypes = [P, ctypes.c_int]
     lib.oracle_gen_id.argtypes = [P, ctypes.c_int]
@@ -183,6 +185,14 @@ class Oracle:
         out = np.zeros(self.num_gens, dtype=np.uint64)
         _load().oracle_fanout_sum(self._h, int(w.size), _ptr(w, ctypes.c_int), _ptr(z, ctypes.c_uint8),
                                   _ptr(out, ctypes.c_uint64))
+        return out
+
+    def fanout_sum2(self, a: int, b: int, nnz16) -> np.ndarray:
+        """Per generator: sum over terms of nnz16[4 p_a + p_b] (a two-qubit operator's columns)."""
+        z = np.ascontiguousarray(nnz16, dtype=np.uint8).reshape(-1)
+        assert z.size == 16
+        out = np.zeros(self.num_gens, dtype=np.uint64)
+        _load().oracle_fanout_sum2(self._h, int(a), int(b), _ptr(z, ctypes.c_uint8), _ptr(out, ctypes.c_uint64))
         return out
 
     def count(self, g: int) -> int:

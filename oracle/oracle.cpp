@@ -15,6 +15,11 @@
 //     sum_a R[a][p] sigma_a, where R is the gate's real Pauli transfer matrix
 //     R[a][b] = (1/2) Tr(sigma_a U sigma_b U^dagger); identity stays identity;
 //   * CX and CZ act on the two local Paulis as signed permutations (Sec. III-C-2);
+//   * a two-qubit rotation exp(-i t A / 2), A = P (x) P for P in {X, Y, Z}, keeps a Pauli
+//     string Q that commutes with A and sends one that anticommutes to
+//     cos t Q + sin t (-i A Q) (-i A Q is again a Pauli string, with a real sign);
+//     ISWAP = exp(i pi/4 (XX + YY)) is the two rotations at t = -pi/2 (cos exactly 0),
+//     a signed permutation;
 //   * after a gate that is not a signed permutation, images with equal Pauli
 //     strings are summed ("index-based Pauli accumulation", abstract) and exact
 //     zeros are dropped (only non-zero weights are stored, Sec. III-B);
@@ -50,8 +55,11 @@ struct Term {
 // Gate codes of the instruction arrays (the input format).
 enum GateCode {
   G_H = 0, G_S = 1, G_SDG = 2, G_T = 3, G_TDG = 4, G_SX = 5, G_X = 6, G_Y = 7, G_Z = 8,
-  G_RX = 9, G_RY = 10, G_RZ = 11, G_CX = 12, G_CZ = 13, G_COUNT = 14
+  G_RX = 9, G_RY = 10, G_RZ = 11, G_CX = 12, G_CZ = 13, G_ISWAP = 14, G_RXX = 15, G_RYY = 16,
+  G_RZZ = 17, G_COUNT = 18
 };
+
+inline bool two_qubit(int code) { return code >= G_CX && code <= G_RZZ; }
 
 inline int local_pauli(const Term& t, int q) {
   int xb = (int)((t.x >> q) & 1u), zb = (int)((t.z >> q) & 1u);
@@ -163,6 +171,62 @@ void merge_into(std::vector<Term>& images, std::vector<Term>& out) {
   }
 }
 
+// Phase exponent e of a product of two one-qubit Paulis given by their (x, z) bits:
+// P1 P2 = i^e P3 with P3 = (x1 ^ x2, z1 ^ z2) (Aaronson & Gottesman 2004, function g).
+inline int product_phase(int x1, int z1, int x2, int z2) {
+  if (!x1 && !z1) return 0;
+  if (x1 && z1) return z2 - x2;
+  if (x1) return z2 * (2 * x2 - 1);
+  return x2 * (1 - 2 * z2);
+}
+
+// exp(-i t A / 2), A = P (x) P on wires (a, b), P given by its bits (px, pz); c = cos t and
+// s = sin t are passed in (exact 0 / -1 for ISWAP). A term that anticommutes with A gains
+// the image s * (-i A Q); with c == 0 it is replaced by it.
+void apply_pp_rotation(std::vector<Term>& gen, int a, int b, int px, int pz, double c, double s,
+                       std::vector<Term>& scratch) {
+  scratch.clear();
+  for (const Term& t : gen) {
+    const int xa = (int)((t.x >> a) & 1u), za = (int)((t.z >> a) & 1u);
+    const int xb = (int)((t.x >> b) & 1u), zb = (int)((t.z >> b) & 1u);
+    // symplectic product of Q with A: odd = anticommute
+    const int sym = ((xa & pz) ^ (za & px)) ^ ((xb & pz) ^ (zb & px));
+    if (!sym) {
+      scratch.push_back(t);
+      continue;
+    }
+    if (c != 0.0) scratch.push_back(Term{t.x, t.z, t.w * c});
+    // -i A Q = i^(e - 1) (A Q) with e the phase exponent of A Q; e is odd here
+    const int e = product_phase(px, pz, xa, za) + product_phase(px, pz, xb, zb);
+    const int k = ((e - 1) % 4 + 4) % 4;  // 0 or 2
+    Term u = t;
+    u.x ^= ((uint64_t)px << a) | ((uint64_t)px << b);
+    u.z ^= ((uint64_t)pz << a) | ((uint64_t)pz << b);
+    u.w = t.w * s * (k == 0 ? 1.0 : -1.0);
+    scratch.push_back(u);
+  }
+  if (c == 0.0) {
+    gen.swap(scratch);  // a signed permutation: no two images share a string
+  } else {
+    std::vector<Term> out;
+    merge_into(scratch, out);
+    gen.swap(out);
+  }
+}
+
+void apply_2q_gate(std::vector<Term>& gen, int code, int a, int b, double theta, std::vector<Term>& scratch) {
+  switch (code) {
+    case G_ISWAP:
+      apply_pp_rotation(gen, a, b, 1, 0, 0.0, -1.0, scratch);  // exp(i pi/4 XX)
+      apply_pp_rotation(gen, a, b, 1, 1, 0.0, -1.0, scratch);  // exp(i pi/4 YY)
+      return;
+    case G_RXX: apply_pp_rotation(gen, a, b, 1, 0, std::cos(theta), std::sin(theta), scratch); return;
+    case G_RYY: apply_pp_rotation(gen, a, b, 1, 1, std::cos(theta), std::sin(theta), scratch); return;
+    case G_RZZ: apply_pp_rotation(gen, a, b, 0, 1, std::cos(theta), std::sin(theta), scratch); return;
+    default: return;
+  }
+}
+
 // Generic one-qubit map given by a 4x4 matrix R[out][in].
 void apply_map_1q(std::vector<Term>& gen, int q, const double R[4][4], std::vector<Term>& scratch) {
   double flat[16];
@@ -229,6 +293,10 @@ void apply_gate(std::vector<Term>& gen, int code, int q0, int q1, double theta,
   if (code == G_CZ) {
     for (Term& t : gen)
       if (apply_cz(t, q0, q1)) t.w = -t.w;
+    return;
+  }
+  if (two_qubit(code)) {
+    apply_2q_gate(gen, code, q0, q1, theta, scratch);
     return;
   }
   double R[4][4];
@@ -311,7 +379,7 @@ int oracle_num_gens(const oracle_state* s) { return (int)s->gens.size(); }
 static bool valid_gate(const oracle_state* s, int code, int q0, int q1) {
   if (code < 0 || code >= G_COUNT) return false;
   if (q0 < 0 || q0 >= s->n) return false;
-  if (code == G_CX || code == G_CZ) {
+  if (two_qubit(code)) {
     if (q1 < 0 || q1 >= s->n || q1 == q0) return false;
   }
   return true;
@@ -407,6 +475,16 @@ void oracle_fanout_sum(const oracle_state* s, int k, const int* wires, const uin
   }
 }
 
+// As oracle_fanout_sum for one two-qubit operator on wires (a, b): nnz16[4*p(a) + p(b)] is
+// the number of nonzero entries of that column of its transfer matrix.
+void oracle_fanout_sum2(const oracle_state* s, int a, int b, const uint8_t* nnz16, uint64_t* out) {
+  for (size_t g = 0; g < s->gens.size(); ++g) {
+    uint64_t tot = 0;
+    for (const Term& t : s->gens[g]) tot += nnz16[4 * local_pauli(t, a) + local_pauli(t, b)];
+    out[g] = tot;
+  }
+}
+
 size_t oracle_count(const oracle_state* s, int g) {
   if (g < 0 || g >= (int)s->gens.size()) return 0;
   return s->gens[g].size();
@@ -430,9 +508,22 @@ void oracle_read(const oracle_state* s, int g, uint64_t* x, uint64_t* z, double*
   }
 }
 
-// The transfer matrix the oracle uses for a gate: 4x4 (one-qubit) or 16x16 (CX, CZ)
+// The transfer matrix the oracle uses for a gate: 4x4 (one-qubit) or 16x16 (two-qubit)
 // R[out][in]; the two-qubit index is 4*p(q0) + p(q1). Returns the dimension, or 0.
 int oracle_gate_ptm(int code, double theta, double* R) {
+  if (two_qubit(code) && code != G_CX && code != G_CZ) {
+    std::memset(R, 0, sizeof(double) * 256);
+    std::vector<Term> gen, scratch;
+    for (int in = 0; in < 16; ++in) {
+      Term t{0, 0, 1.0};
+      set_local_pauli(t, 0, in >> 2);
+      set_local_pauli(t, 1, in & 3);
+      gen.assign(1, t);
+      apply_2q_gate(gen, code, 0, 1, theta, scratch);
+      for (const Term& u : gen) R[(4 * local_pauli(u, 0) + local_pauli(u, 1)) * 16 + in] += u.w;
+    }
+    return 16;
+  }
   if (code == G_CX || code == G_CZ) {
     std::memset(R, 0, sizeof(double) * 256);
     for (int in = 0; in < 16; ++in) {

@@ -987,6 +987,164 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
   }
 }
 
+// Count and expansion in one launch, for rounds whose fan-out bound is at most
+// kFuseMaxFanout: tiles of kFuseTile input terms are claimed in order; each applies its terms'
+// A chain and counts their fan-outs, scans them in LDS, looks back over the earlier tiles for
+// its first image (decoupled look-back, as the count), and then writes every image
+// (expansion and B chain) straight to its position, with the digit counts of up to
+// kExpandHistPasses global sort passes. img_seg[s] receives the first image of segment s
+// (written by the tile that starts it, or for segments without terms by the next tile, or the
+// last tile for the trailing ones) and img_seg[S] the image count. The images come out in the
+// same order as from the count and expansion launches.
+constexpr int kFuseBlock = 512, kFuseItems = 4, kFuseTile = kFuseBlock * kFuseItems;
+constexpr int kFuseChunk = 4096;  // images per window of the image -> parent map
+template <typename K, int WP>
+__global__ void __launch_bounds__(kFuseBlock)
+k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__ w, Tiling tl,
+               const PassArgs* __restrict__ pas, const uint32_t* __restrict__ seg_entry, uint64_t* __restrict__ status,
+               uint32_t* __restrict__ ctr, uint64_t epoch, uint64_t* __restrict__ img_seg, K* __restrict__ keys_out,
+               typename WTraits<WP>::W* __restrict__ w_out, uint64_t out_cap, uint32_t* __restrict__ ghist,
+               uint32_t n_pass, uint32_t hp_begin, uint32_t* err) {
+  using W = typename WTraits<WP>::W;
+  constexpr int kTabN = sizeof(K) <= 8 ? (int)sizeof(K) * 256 : 1;  // no tables for 16-byte keys
+  constexpr int kWaves = kFuseBlock / 64;
+  __shared__ K tk[kTabN];
+  __shared__ uint8_t tn[kTabN];
+  __shared__ K akey[kFuseTile];
+  __shared__ uint8_t aneg[kFuseTile];
+  __shared__ uint32_t loff[kFuseTile + 1];
+  __shared__ uint16_t pmap[kFuseChunk];
+  __shared__ uint32_t hh[kExpandHistPasses * kWaves * kRadix];
+  __shared__ uint64_t scan_sh[kWaves];
+  __shared__ uint64_t base_sh;
+  __shared__ uint32_t tile_sh;
+  if (threadIdx.x == 0) tile_sh = atomicAdd(ctr, 1u);
+  __syncthreads();
+  const uint32_t b = tile_sh;  // launched with exactly n_blocks blocks
+  const uint32_t seg = tl.blk_seg[b];
+  const PassArgs pa = pas[seg_entry[seg]];
+  const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
+  const uint32_t n = (uint32_t)min<uint64_t>(end - begin, (uint64_t)kFuseTile);
+  const uint32_t n_hp = ghist ? n_pass - hp_begin : 0u;
+  K kr[kFuseItems];
+#pragma unroll
+  for (int r = 0; r < kFuseItems; ++r) {  // every load in flight before the first use
+    const uint32_t li = r * kFuseBlock + threadIdx.x;
+    kr[r] = keys[n ? begin + min(li, n - 1) : 0];
+  }
+  if (pa.useA && !pa.drop) {
+    stage_table(pa.tA, tk, tn);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kFuseItems; ++r) {
+    const uint32_t li = r * kFuseBlock + threadIdx.x;
+    if (li >= n) break;
+    K key = kr[r];
+    uint32_t neg = 0;
+    uint64_t f = a_chain_and_fanout(key, neg, pa, tk, tn, err);
+    if (f > (uint64_t)kFuseMaxFanout) {  // the caller's bound did not hold
+      atomicOr(err, kErrIndex | kErrFanout);
+      f = 0;
+    }
+    akey[li] = key;
+    aneg[li] = (uint8_t)(neg & 1u);
+    loff[li] = (uint32_t)f;
+  }
+  for (uint32_t i = threadIdx.x; i < n_hp * kWaves * kRadix; i += kFuseBlock) hh[i] = 0u;
+  __syncthreads();
+  // each thread scans a run of kFuseItems consecutive terms
+  const uint32_t l0 = threadIdx.x * kFuseItems;
+  uint32_t fv[kFuseItems];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k2 = 0; k2 < kFuseItems; ++k2) {
+    fv[k2] = l0 + k2 < n ? loff[l0 + k2] : 0u;
+    sum += fv[k2];
+  }
+  uint64_t tot;
+  const uint64_t pre = block_excl_scan<kFuseBlock>(sum, scan_sh, &tot);
+  {
+    uint32_t run = (uint32_t)pre;
+#pragma unroll
+    for (int k2 = 0; k2 < kFuseItems; ++k2) {
+      if (l0 + k2 < n) loff[l0 + k2] = run;
+      run += fv[k2];
+    }
+  }
+  if (threadIdx.x == 0) {
+    loff[n] = (uint32_t)tot;
+    const uint64_t ep = epoch << 48;
+    st_store(status + b, ep | (b == 0 ? kStPre : kStAgg) | tot);
+    uint64_t excl = 0;
+    if (b > 0) {
+      uint32_t t = b - 1;
+      uint32_t spins = 0;
+      while (true) {
+        const uint64_t v = st_load(status + t);
+        const bool ready = (v >> 48) == epoch && (v & (kStAgg | kStPre));
+        if (!ready) {
+          if (++spins > kSpinLimit) { atomicOr(err, kErrSpin); break; }
+          continue;
+        }
+        excl += v & kStValMask;
+        if ((v & kStPre) || t == 0) break;
+        --t;
+      }
+      st_store(status + b, ep | kStPre | (excl + tot));
+    }
+    base_sh = excl;
+    // the segments this tile starts (with any empty ones before it), and after the last tile
+    // the trailing empty segments and the total
+    for (uint32_t q = seg + 1; q-- > 0 && tl.seg_blk[q] == b;) img_seg[q] = excl;
+    if (b + 1 == tl.n_blocks)
+      for (uint32_t q = tl.n_segs; q > seg && tl.seg_blk[q] == tl.n_blocks; --q) img_seg[q] = excl + tot;
+  }
+  if (pa.useB) {
+    __syncthreads();  // the A table is no longer read
+    stage_table(pa.tB, tk, tn);
+  }
+  __syncthreads();
+  const uint64_t base = base_sh;
+  const uint32_t n_img = (uint32_t)tot;
+  if (base + n_img > out_cap) {
+    if (threadIdx.x == 0 && n_img) atomicOr(err, kErrIndex | kErrExpand);
+    return;
+  }
+  uint32_t* hw = hh + (threadIdx.x >> 6) * n_hp * kRadix;
+  for (uint32_t c0 = 0; c0 < n_img; c0 += kFuseChunk) {
+    const uint32_t c1 = min(c0 + (uint32_t)kFuseChunk, n_img);
+    for (uint32_t j = threadIdx.x; j < n; j += kFuseBlock) {
+      const uint32_t a = max(loff[j], c0), e = min(loff[j + 1], c1);
+      for (uint32_t g = a; g < e; ++g) pmap[g - c0] = (uint16_t)j;
+    }
+    __syncthreads();
+    for (uint32_t g = c0 + threadIdx.x; g < c1; g += kFuseBlock) {
+      const uint32_t j = pmap[g - c0];
+      K key = akey[j];
+      W wv = w[begin + j];
+      uint32_t neg = aneg[j];
+      expand_ops<K, WP>(key, wv, g - loff[j], pa, pa.E1, pa.E2, err);
+      if (pa.useB) key = apply_table(key, tk, tn, neg);
+      else for (uint32_t q = 0; q < pa.nB; ++q) key = apply_perm(key, pa.B[q], neg);
+      if (neg) wv = -wv;
+      keys_out[base + g] = key;
+      w_out[base + g] = wv;
+      for (uint32_t p = 0; p < n_hp; ++p) atomicAdd(&hw[p * kRadix + ((uint32_t)(key >> (8u * (hp_begin + p))) & 255u)], 1u);
+    }
+    __syncthreads();  // the map is rebuilt for the next window
+  }
+  if (n_hp) {
+    for (uint32_t i = threadIdx.x; i < n_hp * kRadix; i += kFuseBlock) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int wv = 0; wv < kWaves; ++wv) c += hh[wv * n_hp * kRadix + i];
+      const uint32_t p = hp_begin + i / kRadix, d = i % kRadix;
+      if (c) atomicAdd(&ghist[((uint64_t)seg * n_pass + p) * kRadix + d], c);
+    }
+  }
+}
+
 // --------------------------------------------------------------- run accumulators
 // Equal keys are adjacent inside a segment after the sort. The thread that owns the
 // first element of a run (its head) sums the run in array order (deterministic), then
@@ -1071,7 +1229,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   __shared__ uint64_t cb[2];
   __shared__ uint32_t nb_sh, fallback_sh;
   __shared__ __align__(16) uint8_t vary_sh[kWaves * sizeof(K)];
-  __shared__ uint32_t blk_sh, last_sh;
+  __shared__ uint32_t blk_sh;
   __shared__ uint64_t base_sh;
   // chunks are claimed in order, so every chunk a look-back waits for is running or done
   if (threadIdx.x == 0) blk_sh = atomicAdd(co.ticket, 1u);
@@ -1109,46 +1267,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
     __syncthreads();
     return base_sh;
   };
-  // The last chunk to finish publishes the round: segment output offsets, the packed
-  // readback area (image offsets, error word) and, last, its sequence word.
-  auto finish = [&]() {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last_sh = atomicAdd(co.done, 1u) + 1 == nc;
-    __syncthreads();
-    if (!last_sh) return;
-    __threadfence();
-    const uint32_t S = tc.n_segs;
-    const uint64_t total = st_load(co.chunk_off + nc);
-    for (uint32_t q = threadIdx.x; q <= S; q += kChunkBlock) {
-      const uint32_t f = min(tc.seg_blk[q], nc);
-      const uint64_t v = f == nc ? total : st_load(co.chunk_off + f);
-      co.seg_off_out[q] = v;
-      co.fin.result[q] = v;
-      if (!co.img_cnt) co.fin.result[S + 1 + q] = co.fin.img_seg[q];
-    }
-    if (co.img_cnt) {  // image offsets of the segments from their counts (serial runs, one block scan)
-      const uint32_t ps = (S + kChunkBlock - 1) / kChunkBlock;
-      const uint32_t q0 = min(threadIdx.x * ps, S), q1 = min(q0 + ps, S);
-      uint64_t isum = 0;
-      for (uint32_t q = q0; q < q1; ++q) isum += co.img_cnt[q];
-      uint64_t itot;
-      uint64_t irun = block_excl_scan<kChunkBlock>(isum, scan_sh, &itot);
-      for (uint32_t q = q0; q < q1; ++q) {
-        co.fin.result[S + 1 + q] = irun;
-        irun += co.img_cnt[q];
-      }
-      if (threadIdx.x == 0) co.fin.result[2 * (uint64_t)S + 1] = itot;
-    }
-    if (threadIdx.x == 0)
-      co.fin.result[2 * (uint64_t)S + 2] =
-          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | (total > out_cap ? kErrIndex | kErrMerge : 0u);
-    publish_seq(co.fin, S);
-  };
-  auto none = [&]() {  // this chunk keeps nothing (empty, or handed to the fallback)
-    lookback(0);
-    finish();
-  };
+  auto none = [&]() { lookback(0); };  // this chunk keeps nothing (empty, or handed to the fallback)
   const uint64_t a = tc.blk_begin[blk], b = tc.blk_end[blk];
   if (a >= b) {
     none();
@@ -1420,7 +1539,42 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   } else if (threadIdx.x == 0 && tot) {
     atomicOr(err, kErrIndex | kErrMerge);
   }
-  finish();
+}
+
+// After the chunk-local sort and merge (one block): the segments' output offsets from the
+// chunks' offsets, and the packed readback area in mapped host memory (output offsets, image
+// offsets — fin.img_seg, or the scan of img_cnt when set — and the error word), its sequence
+// word last.
+constexpr int kFinishBlock = 512;
+__global__ void __launch_bounds__(kFinishBlock) k_chunk_finish(Tiling tc, const uint64_t* __restrict__ chunk_off,
+                                                               uint64_t* __restrict__ seg_off_out, MergeFin fin,
+                                                               const uint32_t* __restrict__ img_cnt, uint64_t out_cap,
+                                                               const uint32_t* __restrict__ err) {
+  __shared__ uint64_t sh[kFinishBlock / 64];
+  const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
+  const uint32_t S = tc.n_segs;
+  const uint64_t total = chunk_off[nc];
+  for (uint32_t q = threadIdx.x; q <= S; q += kFinishBlock) {
+    const uint64_t v = chunk_off[min(tc.seg_blk[q], nc)];
+    seg_off_out[q] = v;
+    fin.result[q] = v;
+    if (!img_cnt) fin.result[S + 1 + q] = fin.img_seg[q];
+  }
+  if (img_cnt) {  // image offsets of the segments from their counts (serial runs, one block scan)
+    const uint32_t ps = (S + kFinishBlock - 1) / kFinishBlock;
+    const uint32_t q0 = min(threadIdx.x * ps, S), q1 = min(q0 + ps, S);
+    uint64_t isum = 0;
+    for (uint32_t q = q0; q < q1; ++q) isum += img_cnt[q];
+    uint64_t itot;
+    uint64_t irun = block_excl_scan<kFinishBlock>(isum, sh, &itot);
+    for (uint32_t q = q0; q < q1; ++q) {
+      fin.result[S + 1 + q] = irun;
+      irun += img_cnt[q];
+    }
+    if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 1] = itot;
+  }
+  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (total > out_cap ? kErrIndex | kErrMerge : 0u);
+  publish_seq(fin, S);
 }
 
 // Digit histograms of the radix passes p_begin .. n_pass-1 at once, per segment:
@@ -1755,7 +1909,7 @@ inline uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)((n + bl
 
 const char* kernel_kind_name(int k) {
   static const char* names[kKNum] = {"init", "count", "scan", "expand", "sort_hist", "sort_scatter",
-                                     "merge_count", "merge_write", "compose_ptm", "chunk_sort"};
+                                     "merge_count", "merge_write", "compose_ptm", "chunk_sort", "count_expand"};
   return (k >= 0 && k < kKNum) ? names[k] : "?";
 }
 
@@ -1920,6 +2074,32 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign,
   return hipGetLastError();
 }
 
+size_t fuse_tile() { return (size_t)kFuseTile; }
+
+hipError_t launch_count_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const Tiling& tl,
+                               const PassArgs* pas, const uint32_t* seg_entry, uint64_t* status, uint32_t* ctr,
+                               uint64_t epoch, uint64_t* img_seg, void* keys_out, void* w_out, uint64_t out_cap,
+                               uint32_t* ghist, uint32_t n_pass, uint32_t hp_begin, uint32_t* err, hipStream_t s,
+                               Prof* prof) {
+  if (tl.n_blocks == 0) return hipErrorInvalidValue;  // a round with no input terms takes another path
+  if (ghist && (hp_begin > n_pass || n_pass - hp_begin > kExpandHistPasses)) return hipErrorInvalidValue;
+  hipEvent_t ev = prof_begin(prof, s, kKCountExpand);
+  QIMAX_DISPATCH_K(KC, {
+    if (WP == 64)
+      k_count_expand<K, 64><<<tl.n_blocks, kFuseBlock, 0, s>>>((const K*)keys, (const double*)w, tl, pas, seg_entry,
+                                                               status, ctr, epoch, img_seg, (K*)keys_out,
+                                                               (double*)w_out, out_cap, ghist, n_pass, hp_begin, err);
+    else
+      k_count_expand<K, 32><<<tl.n_blocks, kFuseBlock, 0, s>>>((const K*)keys, (const float*)w, tl, pas, seg_entry,
+                                                               status, ctr, epoch, img_seg, (K*)keys_out,
+                                                               (float*)w_out, out_cap, ghist, n_pass, hp_begin, err);
+  });
+  // bytes: every input term read; the images' bytes are added by the caller once known
+  const double per = (4 << KC) + (WP == 64 ? 8 : 4);
+  prof_end(prof, s, ev, kKCountExpand, per * (double)T_in);
+  return hipGetLastError();
+}
+
 hipError_t launch_expand_small(int KC, int WP, const void* keys, const void* w, const uint64_t* seg_in, uint32_t S,
                                uint64_t T_in, const PassArgs* pas, const uint32_t* seg_entry, void* keys_out,
                                void* w_out, uint32_t* img_cnt, const TileJob2& tiles, uint32_t* err, hipStream_t s,
@@ -2029,6 +2209,7 @@ hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* key
   });
   // bytes: every image read; the kept terms' bytes are added by the caller once known
   prof_end(prof, s, ev, kKChunkSort, (kb + wb) * (double)T);
+  k_chunk_finish<<<1, kFinishBlock, 0, s>>>(tc, co.chunk_off, co.seg_off_out, co.fin, co.img_cnt, T, err);
   return hipGetLastError();
 }
 

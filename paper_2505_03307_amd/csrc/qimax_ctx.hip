@@ -245,7 +245,7 @@ bool is_conjugation(const std::vector<double>& R, int dim) {
 constexpr int kMaxE1 = 64;
 constexpr int kBoundPathMaxFanout = 16;  // rounds with a larger fan-out bound read back their image count
 // tile counters of a round (after the per-pass, per-XCD sort counters)
-constexpr int kCtrCount = 252, kCtrMerge = 253, kCtrChunk = 254, kCtrChunkDone = 255;
+constexpr int kCtrCount = 252, kCtrMerge = 253, kCtrChunk = 254;
 constexpr int kMaxE2 = 8;
 constexpr double kMaxFanout = 2147483647.0;
 
@@ -291,6 +291,7 @@ struct qimax_ctx {
   bool xcd_ranges = true;
   bool local_sort = true;     // top-digit passes + chunk-local sorts instead of all global passes
   bool small_rounds = true;   // rounds of small segments: one block per segment (see run_round)
+  bool fused_expand = true;   // bound-path rounds: count and expansion in one launch
   int local_sort_m = -1;      // >= 0: force the number of top-digit passes
   uint32_t redo_cooldown = 0; // rounds left with global passes only after a chunk overflow
   bool autotune = true;       // choose among sort variants by measured time per size class
@@ -317,6 +318,11 @@ struct qimax_ctx {
   uint64_t* zres_dev = nullptr;
   size_t zres_words = 0;
   uint64_t zseq = 0;  // sequence word of the last results asked for
+  // step recording (qimax_graph_record): the work of a step is captured between the host's
+  // synchronisations and replayed later as one graph
+  struct qimax_graph* rec = nullptr;
+  bool rec_capturing = false;
+  uint64_t buf_gen = 0;  // counts every (re)allocation or release of the context's memory
 };
 
 namespace {
@@ -351,6 +357,7 @@ void dev_free(qimax_ctx* c, DevBuf& b) {
   if (b.p) {
     (void)hipFree(b.p);
     c->alloc_bytes -= b.bytes;
+    c->buf_gen += 1;
   }
   b.p = nullptr;
   b.bytes = 0;
@@ -359,6 +366,8 @@ void dev_free(qimax_ctx* c, DevBuf& b) {
 // Grow-only device buffer with the context's memory cap.
 qimax_status ensure(qimax_ctx* c, DevBuf& b, size_t bytes, bool headroom = true) {
   if (bytes <= b.bytes && b.p) return QIMAX_OK;
+  if (c->rec) return fail(c, QIMAX_ESTATE, "a device buffer must grow while recording: run the step once first");
+  c->buf_gen += 1;
   size_t want = bytes == 0 ? 256 : bytes;
   if (headroom) want = want + want / 4;
   want = (want + 255) & ~(size_t)255;
@@ -389,6 +398,8 @@ qimax_status ensure(qimax_ctx* c, DevBuf& b, size_t bytes, bool headroom = true)
 // Grow a buffer keeping its first `keep` bytes.
 qimax_status ensure_keep(qimax_ctx* c, DevBuf& b, size_t bytes, size_t keep) {
   if (bytes <= b.bytes && b.p) return QIMAX_OK;
+  if (c->rec) return fail(c, QIMAX_ESTATE, "a device buffer must grow while recording: run the step once first");
+  c->buf_gen += 1;
   DevBuf nb;
   size_t want = align256(bytes + bytes / 4 + 256);
   if (c->cap && c->alloc_bytes + want > c->cap) {
@@ -534,6 +545,8 @@ size_t put_tiling(const HostTiling& t, uint8_t* host, uint8_t* dev, size_t off, 
 
 qimax_status ensure_stage(qimax_ctx* c, int i, size_t bytes) {
   if (bytes <= c->stage_bytes[i] && c->stage[i]) return QIMAX_OK;
+  if (c->rec) return fail(c, QIMAX_ESTATE, "a staging buffer must grow while recording: run the step once first");
+  c->buf_gen += 1;
   if (c->stage[i]) {
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     (void)hipHostFree(c->stage[i]);
@@ -550,6 +563,8 @@ qimax_status ensure_stage(qimax_ctx* c, int i, size_t bytes) {
 // Result words written by the device into mapped host memory (read after a synchronisation).
 qimax_status ensure_zres(qimax_ctx* c, size_t words) {
   if (words <= c->zres_words && c->zres) return QIMAX_OK;
+  if (c->rec) return fail(c, QIMAX_ESTATE, "a result buffer must grow while recording: run the step once first");
+  c->buf_gen += 1;
   if (c->zres) {
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     (void)hipHostFree(c->zres);
@@ -565,12 +580,83 @@ qimax_status ensure_zres(qimax_ctx* c, size_t words) {
   return QIMAX_OK;
 }
 
+// ------------------------------------------------------------------ step recording
+// While a step is recorded, the stream is captured between the host's synchronisations: at
+// each one the captured part becomes a graph, which is launched at once (so the recording run
+// computes the step as usual) and kept; the replay launches the parts in order with no host
+// work in between. Data the host stages for a launch (descriptors in mapped memory, rewritten
+// every round) is copied into memory owned by the recording.
+}  // namespace
+
+struct qimax_graph {
+  qimax_ctx* ctx = nullptr;
+  std::vector<hipGraph_t> parts;
+  hipGraph_t whole = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void*> snaps;  // pinned copies of staged data, read by the parts
+  std::vector<hipGraphExec_t> runs;  // the parts as launched while recording
+  uint64_t gen = 0;          // ctx->buf_gen when recorded
+  bool failed = false;
+  // the context's state after the step
+  DevBuf keys, w, seg, pk[2], pw[2], pseg[2];
+  std::vector<uint64_t> h_seg;
+  uint64_t T = 0;
+  qimax_stats st_delta{};
+  std::vector<uint64_t> upd_delta;
+};
+
+namespace {
+
+qimax_status rec_cut(qimax_ctx* c) {
+  if (!c->rec || !c->rec_capturing) return QIMAX_OK;
+  c->rec_capturing = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (e != hipSuccess || !g) {
+    c->rec->failed = true;
+    return hip_fail(c, e == hipSuccess ? hipErrorUnknown : e, "hipStreamEndCapture");
+  }
+  c->rec->parts.push_back(g);
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (x) c->rec->runs.push_back(x);  // destroyed once the recording run has finished
+  if (e == hipSuccess) e = hipGraphLaunch(x, c->stream);
+  if (e != hipSuccess) {
+    c->rec->failed = true;
+    return hip_fail(c, e, "recorded part");
+  }
+  return QIMAX_OK;
+}
+
+qimax_status rec_resume(qimax_ctx* c) {
+  if (!c->rec || c->rec_capturing || c->rec->failed) return QIMAX_OK;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+  c->rec_capturing = true;
+  return QIMAX_OK;
+}
+
+// The device address a launch should read `bytes` of staged host data from: the staging
+// area itself, or while recording a pinned copy of it that lives as long as the recording.
+qimax_status rec_src(qimax_ctx* c, const void* host, const void* dev, size_t bytes, const void** out) {
+  *out = dev;
+  if (!c->rec || bytes == 0) return QIMAX_OK;
+  void* h = nullptr;
+  HIPCHK(c, hipHostMalloc(&h, bytes, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc (recording)");
+  c->rec->snaps.push_back(h);
+  std::memcpy(h, host, bytes);
+  void* d = nullptr;
+  HIPCHK(c, hipHostGetDevicePointer(&d, h, 0), "hipHostGetDevicePointer");
+  *out = d;
+  return QIMAX_OK;
+}
+
 // Wait for the words the device writes into zres (words - 2: the error word, words - 1: the
 // sequence word, stored last). The host polls the sequence word rather than waiting for the
 // stream: launches queued after the publishing one (a compaction) keep running meanwhile.
 // Once a millisecond of polling the stream is queried (a query is not free: it is kept rare),
 // so that a failed or finished stream ends the wait.
 qimax_status wait_zres(qimax_ctx* c, size_t words, uint32_t* err_out) {
+  QCHK(rec_cut(c));
   const auto t0 = std::chrono::steady_clock::now();
   auto t_query = t0;
   volatile const uint64_t* seq = c->zres + words - 1;
@@ -591,14 +677,17 @@ qimax_status wait_zres(qimax_ctx* c, size_t words, uint32_t* err_out) {
   c->st.syncs += 1;
   prof_resolve(&c->prof);
   *err_out = (uint32_t)(c->zres[words - 2] & 0xFFFFFFFFu);
-  return QIMAX_OK;
+  return rec_resume(c);
 }
 
 // Copy `words` uint64 from device to the pinned scratch (plus the error word) and wait.
 // `words` uint64 from the device to the pinned scratch, then the error word: the context's
 // (one more copy) or, with err_packed, the last of the words.
 qimax_status readback(qimax_ctx* c, const void* dev, size_t words, uint32_t* err_out, bool err_packed = false) {
+  QCHK(rec_cut(c));
   if (words + 1 > c->pinned_words) {
+    if (c->rec) return fail(c, QIMAX_ESTATE, "a readback buffer must grow while recording: run the step once first");
+    c->buf_gen += 1;
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
     size_t want = std::max<size_t>(words + 1, 4096);
@@ -615,7 +704,7 @@ qimax_status readback(qimax_ctx* c, const void* dev, size_t words, uint32_t* err
   c->st.syncs += 1;
   prof_resolve(&c->prof);
   *err_out = (uint32_t)(c->pinned[err_packed ? words - 1 : words] & 0xFFFFFFFFu);
-  return QIMAX_OK;
+  return rec_resume(c);
 }
 
 std::string err_text(uint32_t e) {
@@ -753,7 +842,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
   // ---- round prep: error word, tile counters, digit histograms (one launch)
   // tile_ctr: [0, n_pass*kXcds) sort passes, [kCtrCount] count tiles, [kCtrMerge] merge tiles,
-  // [kCtrChunk] chunk tickets, [kCtrChunkDone] finished chunks
+  // [kCtrChunk] chunk tickets
   const uint64_t nh = sweep ? (uint64_t)S * n_pass * kRadix : 0;
   if (sweep) QCHK(ensure(c, c->ghist, std::max<uint64_t>(nh, 1) * 4));
   QCHK(ensure(c, c->tile_ctr, 256 * 4));
@@ -779,20 +868,26 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   // input tiling: segment-aligned tiles of at most kSortTile terms, built on the device from
   // the segment offsets (the tile count is known here exactly) by the round's first launch,
   // which also clears the error word, counters and histograms and pulls the descriptors
+  // Fused round: the count and the expansion in one launch (a small fan-out bound keeps every
+  // tile's images in reach of one block); its input tiles are smaller.
+  const bool fused = bound_path && !small && c->fused_expand && (double)f_round <= (double)kFuseMaxFanout;
+  const uint64_t in_tile = fused ? (uint64_t)fuse_tile() : (uint64_t)kSortTile;
   Tiling tl_in{};
   {
     uint32_t n_tin = 0;
-    for (uint32_t s = 0; s < S; ++s) n_tin += (uint32_t)((so_in[s + 1] - so_in[s] + kSortTile - 1) / kSortTile);
+    for (uint32_t s = 0; s < S; ++s) n_tin += (uint32_t)((so_in[s + 1] - so_in[s] + in_tile - 1) / in_tile);
     const size_t o1 = 0, o2 = align256((size_t)n_tin * 8), o3 = o2 + align256((size_t)n_tin * 8);
     const size_t o4 = o3 + align256((size_t)n_tin * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
     const size_t o6 = o5 + 256;
     QCHK(ensure(c, c->dtile[2], o6 + 256));
     uint8_t* d = (uint8_t*)c->dtile[2].p;
-    const TileJob2 job{(uint64_t)kSortTile, n_tin, 0, (uint64_t*)(d + o1), (uint64_t*)(d + o2), (uint32_t*)(d + o3),
+    const TileJob2 job{in_tile, n_tin, 0, (uint64_t*)(d + o1), (uint64_t*)(d + o2), (uint32_t*)(d + o3),
                        (uint32_t*)(d + o4), (uint32_t*)(d + o5), (uint32_t*)(d + o6)};
     tl_in = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
                    (const uint32_t*)(d + o4), n_tin, S, nullptr, nullptr};
-    HIPCHK(c, launch_round_start(c->stage_dev[0], ds, host_bytes, (uint32_t*)c->err.p, ctr, 256,
+    const void* blob = nullptr;
+    QCHK(rec_src(c, c->stage[0], c->stage_dev[0], host_bytes, &blob));
+    HIPCHK(c, launch_round_start(blob, ds, host_bytes, (uint32_t*)c->err.p, ctr, 256,
                                  (uint32_t*)c->ghist.p, nh, seg_in, S, job, T_in, c->stream), "round start");
   }
   HIPCHK(c, launch_build_tables(c->KC, (const TableJob*)(ds + oJ), (uint32_t)n_jobs, c->stream, &c->prof),
@@ -809,7 +904,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     return QIMAX_OK;
   };
-  if (!small) {
+  if (!small && !fused) {
     QCHK(ensure(c, c->off, (T_in + 1) * 8));
     QCHK(ensure(c, c->akeys, std::max<uint64_t>(T_in, 1) * c->kb));
     QCHK(ensure(c, c->asign, std::max<uint64_t>(T_in, 1)));
@@ -823,13 +918,14 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   uint32_t e = 0;
   uint64_t T_img = 0;
   Tiling tl_exp{}, tl{};
+  TileJob2 img_jobs[2];
   if (bound_path) {
     T_img = (uint64_t)f_round * T_in;  // capacity: an upper bound of the image count
     const uint32_t caps[2] = {(uint32_t)((T_img + kExpandTile - 1) / kExpandTile + S),
                               (uint32_t)((T_img + kSortTile - 1) / kSortTile + S)};
     const uint64_t tiles[2] = {(uint64_t)kExpandTile, (uint64_t)kSortTile};
     Tiling* tls[2] = {&tl_exp, &tl};
-    TileJob2 jobs[2];
+    TileJob2* jobs = img_jobs;
     for (int i = 0; i < 2; ++i) {
       const size_t o1 = 0, o2 = align256((size_t)caps[i] * 8), o3 = o2 + align256((size_t)caps[i] * 8);
       const size_t o4 = o3 + align256((size_t)caps[i] * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
@@ -841,7 +937,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       *tls[i] = Tiling{(const uint64_t*)(d + o1), (const uint64_t*)(d + o2), (const uint32_t*)(d + o3),
                        (const uint32_t*)(d + o4), caps[i], S, (const uint32_t*)(d + o5), (const uint32_t*)(d + o6)};
     }
-    if (!small)
+    if (!small && !fused)  // (a fused round builds them after its launch, from the image offsets it wrote)
       HIPCHK(c, launch_make_tiles2((const uint64_t*)c->off.p, seg_in, S, (uint64_t*)c->img_seg.p, jobs[0], jobs[1],
                                    T_img, (uint32_t*)c->err.p, c->stream), "tiles");
   } else {
@@ -860,7 +956,13 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     QCHK(ensure_stage(c, 1, img_bytes));
     const size_t mid = put_tiling(t_exp, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, 0, tl_exp);
     put_tiling(t_sort, (uint8_t*)c->stage[1], (uint8_t*)c->desc2.p, mid, tl);
-    HIPCHK(c, hipMemcpyAsync(c->desc2.p, c->stage[1], img_bytes, hipMemcpyHostToDevice, c->stream), "upload tiling");
+    if (c->rec) {  // the recording's own copy, pulled by a kernel
+      const void* src = nullptr;
+      QCHK(rec_src(c, c->stage[1], c->stage_dev[1], img_bytes, &src));
+      HIPCHK(c, launch_pull(src, c->desc2.p, img_bytes, c->stream), "upload tiling");
+    } else {
+      HIPCHK(c, hipMemcpyAsync(c->desc2.p, c->stage[1], img_bytes, hipMemcpyHostToDevice, c->stream), "upload tiling");
+    }
   }
   // ---- sort plan (single-sweep sort): global passes over every digit, or over the top m
   // digits only, followed by chunk-local sorts in LDS. m is the fewest top digits that split
@@ -886,10 +988,11 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       if (c->autotune && c->local_sort_m < 0 && m_top < n_pass) {
         tune_key = (uint32_t)c->KC * 4096u + (uint32_t)c->WP * 64u + (uint32_t)std::min(63, ilog2_u64(T_img));
         TuneState& ts = c->tune[tune_key];
-        tune_cand = ts.best >= 0 ? ts.best : ts.tried;
+        // (a recording never explores: its rounds are not timed)
+        tune_cand = ts.best >= 0 ? ts.best : (c->rec ? 0 : ts.tried);
         if (tune_cand == 1) m_top = std::min(m_top + 1, n_pass);
         if (tune_cand == 2) xr = false;
-        if (ts.best < 0) {  // exploring: time this round
+        if (ts.best < 0 && !c->rec) {  // exploring: time this round
           HIPCHK(c, hipEventRecord(c->tune_ev[0], c->stream), "tune event");
           tune_timed = true;
         }
@@ -920,6 +1023,15 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     HIPCHK(c, launch_expand_small(c->KC, c->WP, k_in, w_in, seg_in, S, T_in, pas, sent, c->ik[0].p, c->iw[0].p,
                                   (uint32_t*)c->img_cnt.p, job, (uint32_t*)c->err.p, c->stream, &c->prof),
            "expand");
+  } else if (fused) {
+    QCHK(status_words(tl_in.n_blocks));
+    c->mepoch += 1;
+    HIPCHK(c, launch_count_expand(c->KC, c->WP, k_in, w_in, T_in, tl_in, pas, sent, (uint64_t*)c->mstatus.p,
+                                  ctr + kCtrCount, c->mepoch, (uint64_t*)c->img_seg.p, c->ik[0].p, c->iw[0].p, T_img,
+                                  hist_in_expand ? (uint32_t*)c->ghist.p : nullptr, n_pass, n_pass - m_top,
+                                  (uint32_t*)c->err.p, c->stream, &c->prof), "count and expand");
+    HIPCHK(c, launch_make_tiles2(nullptr, (const uint64_t*)c->img_seg.p, S, nullptr, img_jobs[0], img_jobs[1], T_img,
+                                 (uint32_t*)c->err.p, c->stream), "tiles");
   } else
   HIPCHK(c, launch_expand(c->KC, c->WP, c->akeys.p, (const uint8_t*)c->asign.p, w_in, T_in,
                           (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent, seg_in, any_b_tables, e_bytes,
@@ -979,7 +1091,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       QCHK(ensure(c, c->chunk_off, (nc + 1) * 8));
       QCHK(status_words(nc));
       c->mepoch += 1;
-      const ChunkOut co{ctr + kCtrChunk, ctr + kCtrChunkDone, (uint64_t*)c->mstatus.p, c->mepoch,
+      const ChunkOut co{ctr + kCtrChunk, (uint64_t*)c->mstatus.p, c->mepoch,
                         (uint64_t*)c->chunk_off.p, (uint64_t*)c->pseg[slot].p, fin,
                         small ? (const uint32_t*)c->img_cnt.p : nullptr};
       HIPCHK(c, launch_chunk_sort_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, c->pk[slot].p,
@@ -1065,6 +1177,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       };
       if (small) {  // the images' bytes, known now
         if ((c->prof.mask >> kKExpand) & 1u) c->prof.bytes[kKExpand] += (double)(eb + wbt) * (double)T_img;
+      } else if (fused) {
+        if ((c->prof.mask >> kKCountExpand) & 1u) c->prof.bytes[kKCountExpand] += (double)(eb + wbt) * (double)T_img;
       } else {
         fix(kKExpand, (double)(eb + wbt) * d);
       }
@@ -1147,7 +1261,9 @@ void plan_passes(const std::vector<const HostOp*>& all, std::vector<Pass>& passe
     int n1 = 0, n2 = 0;
     for (auto* e : cur.E) (e->arity == 1 ? n1 : n2)++;
     const bool fits = (op.arity == 1 ? n1 + 1 <= kMaxE1 : n2 + 1 <= kMaxE2) && cur.fanout_bound * f <= kMaxFanout;
-    const bool join = !cur.E.empty() && op.group == cur.egroup && !(op.mask & cur.emask) &&
+    // one-qubit expanding operators of one U_k on disjoint wires share a pass; a two-qubit
+    // expanding operator has a pass of its own (its images are counted operator by operator)
+    const bool join = !cur.E.empty() && op.arity == 1 && op.group == cur.egroup && !(op.mask & cur.emask) &&
                       !(op.mask & cur.bmask) && fits;
     if (!cur.E.empty() && !join) {
       passes.push_back(cur);
@@ -1343,7 +1459,55 @@ qimax_status check_op_input(qimax_ctx* c, const qimax_op& in, int64_t group, Hos
   return QIMAX_OK;
 }
 
-bool is_2q_code(uint8_t g) { return g == QIMAX_GATE_CX || g == QIMAX_GATE_CZ; }
+bool is_2q_code(uint8_t g) { return g >= QIMAX_GATE_CX && g <= QIMAX_GATE_RZZ; }
+
+// One-qubit Pauli products sigma_a sigma_b = i^kMulPhase[a][b] sigma_kMulOut[a][b], Pauli
+// order I, X, Y, Z (X Y = i Z and cyclic; the reverse order gives -i).
+constexpr int kMulOut[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
+constexpr int kMulPhase[4][4] = {{0, 0, 0, 0}, {0, 0, 1, 3}, {0, 3, 0, 1}, {0, 1, 3, 0}};
+
+// Transfer matrix of exp(-i t A / 2), A = sigma_P (x) sigma_P (P in 1..3), from c = cos t and
+// s = sin t: a Pauli pair Q commuting with A is kept; one anticommuting with A goes to
+// c Q + s (-i A Q), -i A Q being a Pauli pair with a real sign.
+void pair_rotation_ptm(int P, double c, double s, double* R) {
+  std::fill(R, R + 256, 0.0);
+  auto anti = [P](int a) { return a != 0 && a != P; };  // a one-qubit Pauli anticommuting with sigma_P
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const int in = 4 * a + b;
+      if (anti(a) == anti(b)) {
+        R[in * 16 + in] = 1.0;
+        continue;
+      }
+      R[in * 16 + in] = c;
+      const int out = 4 * kMulOut[P][a] + kMulOut[P][b];
+      const int k = (kMulPhase[P][a] + kMulPhase[P][b] + 3) & 3;  // -i = i^3
+      R[out * 16 + in] += (k == 0 ? s : -s);                      // k is 0 or 2 here
+    }
+}
+
+// ISWAP = exp(i pi/4 XX) exp(i pi/4 YY) (the factors commute), each a pair rotation at
+// t = -pi/2 taken with its exact cosine 0 and sine -1: a signed permutation.
+void iswap_ptm(double* R) {
+  double xx[256], yy[256];
+  pair_rotation_ptm(1, 0.0, -1.0, xx);
+  pair_rotation_ptm(2, 0.0, -1.0, yy);
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 16; ++k) acc += yy[i * 16 + k] * xx[k * 16 + j];
+      R[i * 16 + j] = acc;
+    }
+}
+
+// The 16x16 R of a 16x16 operator on (q0, q1) written for the wires in the other order.
+void swap_wires_ptm(const double* R, double* out) {
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) {
+      const int i2 = 4 * (i & 3) + (i >> 2), j2 = 4 * (j & 3) + (j >> 2);
+      out[i2 * 16 + j2] = R[i * 16 + j];
+    }
+}
 
 // A 4x4 matrix with one entry of +-1 per column and zeros elsewhere, as a code: per column c,
 // (row | 4 * negative) << 3c; -1 for any other matrix.
@@ -1371,7 +1535,7 @@ constexpr int kIdentityCode4 = 0 | (1 << 3) | (2 << 6) | (3 << 9);
 qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
                            const double* theta, size_t m, std::vector<HostOp>& ops, size_t* n_u, size_t* n_v) {
   for (size_t i = 0; i < m; ++i) {
-    if (gate[i] > QIMAX_GATE_CZ) return fail(c, QIMAX_EINVAL, "unknown gate code at instruction " + std::to_string(i));
+    if (gate[i] > QIMAX_GATE_RZZ) return fail(c, QIMAX_EINVAL, "unknown gate code at instruction " + std::to_string(i));
     if (q0[i] >= n) return fail(c, QIMAX_EINVAL, "qubit out of range at instruction " + std::to_string(i));
     if (is_2q_code(gate[i]) && (q1[i] >= n || q1[i] == q0[i]))
       return fail(c, QIMAX_EINVAL, "bad second qubit at instruction " + std::to_string(i));
@@ -1423,11 +1587,15 @@ qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const 
     std::memcpy(hs + oI, idx.data(), idx.size() * 4);
     std::memcpy(hs + oO, chain_off.data(), chain_off.size() * 4);
     const uint8_t* dg = (const uint8_t*)c->gr_in.p;
-    HIPCHK(c, launch_pull(c->stage_dev[0], c->gr_in.p, up, c->stream), "group upload");
+    const void* gsrc = nullptr;
+    QCHK(rec_src(c, c->stage[0], c->stage_dev[0], up, &gsrc));
+    HIPCHK(c, launch_pull(gsrc, c->gr_in.p, up, c->stream), "group upload");
     HIPCHK(c, launch_compose_ptm(dg + oG, (const double*)(dg + oT), (const uint32_t*)(dg + oI),
                                  (const uint32_t*)(dg + oO), (uint32_t)chains.size(), (double*)c->stage_dev[1],
                                  c->stream, &c->prof), "compose_ptm");
+    QCHK(rec_cut(c));
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    QCHK(rec_resume(c));
     ptm = (const double*)c->stage[1];
   }
   // assemble the operator list in run order
@@ -1445,6 +1613,13 @@ qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const 
     t.assign(R, R + 256);
     return t;
   }();
+  static const Ptm kIswap = [] {
+    double R[256];
+    iswap_ptm(R);
+    Ptm t;
+    t.assign(R, R + 256);
+    return t;
+  }();
   size_t ci = 0;
   ops.clear();
   ops.reserve(m);
@@ -1454,13 +1629,50 @@ qimax_status group_circuit(qimax_ctx* c, uint32_t n, const uint8_t* gate, const 
   std::unordered_map<int, Cls> perm_cache;
   for (size_t r = 0; r < runs.size(); ++r) {
     if (runs[r].two) {
+      // last operator of this run on each wire (index into ops), for fusing same-pair gates
+      std::unordered_map<uint32_t, size_t> last;
       for (size_t i = runs[r].a; i < runs[r].b; ++i) {
+        Ptm R;
+        double buf[256];
+        bool perm = true, conj = true;  // CX, CZ and ISWAP are Clifford
+        switch (gate[i]) {
+          case QIMAX_GATE_CX: R = kCx; break;
+          case QIMAX_GATE_CZ: R = kCz; break;
+          case QIMAX_GATE_ISWAP: R = kIswap; break;
+          default: {  // RXX, RYY, RZZ
+            const double th = theta ? theta[i] : 0.0;
+            pair_rotation_ptm(gate[i] - QIMAX_GATE_RXX + 1, std::cos(th), std::sin(th), buf);
+            R.assign(buf, buf + 256);
+            perm = is_signed_perm(R, 16);
+            conj = perm && is_conjugation(R, 16);
+          }
+        }
+        auto ia = last.find(q0[i]), ib = last.find(q1[i]);
+        if (ia != last.end() && ib != last.end() && ia->second == ib->second) {
+          // the run's previous operator on both wires acts on exactly this pair, and nothing
+          // in between touched them: fuse (this gate acts on that operator's images)
+          HostOp& prev = ops[ia->second];
+          double g[256], f[256];
+          if (prev.q0 == (int)q0[i]) std::copy(R.begin(), R.end(), g);
+          else swap_wires_ptm(R.vec().data(), g);
+          for (int a = 0; a < 16; ++a)
+            for (int b = 0; b < 16; ++b) {
+              double acc = 0.0;
+              for (int k = 0; k < 16; ++k) acc += g[a * 16 + k] * prev.R[k * 16 + b];
+              f[a * 16 + b] = acc;
+            }
+          prev.R.assign(f, f + 256);
+          prev.perm = is_signed_perm(prev.R, 16);
+          prev.conj = prev.perm && is_conjugation(prev.R, 16);
+          continue;
+        }
         HostOp op;
         op.arity = 2; op.dim = 16; op.q0 = (int)q0[i]; op.q1 = (int)q1[i]; op.group = (int)r;
-        op.R = gate[i] == QIMAX_GATE_CX ? kCx : kCz;
+        op.R = R;
         op.mask = (1ull << op.q0) | (1ull << op.q1);
-        op.perm = true;
-        op.conj = true;
+        op.perm = perm;
+        op.conj = conj;
+        last[q0[i]] = last[q1[i]] = ops.size();
         ops.push_back(std::move(op));
       }
     } else {
@@ -1803,6 +2015,8 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     c->xcd_ranges = !(env && env[0] == '0');
     env = std::getenv("QIMAX_SMALL_ROUNDS");  // 0: small rounds take the general path too
     c->small_rounds = !(env && env[0] == '0');
+    env = std::getenv("QIMAX_FUSED_EXPAND");  // 0: separate count and expansion launches
+    c->fused_expand = !(env && env[0] == '0');
     env = std::getenv("QIMAX_LOCAL_SORT");  // 0: every digit by global passes
     c->local_sort = !(env && env[0] == '0');
     env = std::getenv("QIMAX_LOCAL_SORT_M");  // force the number of top-digit passes (tests)
@@ -1892,6 +2106,141 @@ qimax_status qimax_apply_circuit(qimax_ctx* c, const uint8_t* gate, const uint32
     QCHK(group_circuit(c, c->n, gate, q0, q1, theta, m, ops, nullptr, nullptr));
   }
   return apply_ops(c, ops);
+}
+
+// ------------------------------------------------------------------------ step graphs
+
+void qimax_graph_destroy(qimax_graph* g) {
+  if (!g) return;
+  if (g->ctx && g->ctx->stream) (void)hipStreamSynchronize(g->ctx->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  for (hipGraphExec_t x : g->runs) (void)hipGraphExecDestroy(x);
+  if (g->whole) (void)hipGraphDestroy(g->whole);
+  for (hipGraph_t p : g->parts) (void)hipGraphDestroy(p);
+  for (void* h : g->snaps) (void)hipHostFree(h);
+  delete g;
+}
+
+qimax_status qimax_graph_record(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,
+                                const double* theta, size_t m, const uint64_t* layer_end, size_t n_layers,
+                                qimax_graph** out) {
+  if (!c || !out) return QIMAX_EINVAL;
+  *out = nullptr;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  if (c->rec) return fail(c, QIMAX_ESTATE, "a recording is already in progress");
+  if (m && (!gate || !q0 || !q1)) return fail(c, QIMAX_EINVAL, "instruction arrays are NULL");
+  std::vector<uint64_t> ends;
+  if (layer_end && n_layers) ends.assign(layer_end, layer_end + n_layers);
+  else ends.push_back(m);
+  for (size_t l = 0; l < ends.size(); ++l)
+    if (ends[l] > m || (l && ends[l] < ends[l - 1])) return fail(c, QIMAX_EINVAL, "layer ends out of order");
+  if (ends.back() != m) return fail(c, QIMAX_EINVAL, "the last layer must end at m");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  qimax_graph* g = new qimax_graph;
+  g->ctx = c;
+  const qimax_stats st0 = c->st;
+  std::vector<uint64_t> upd0 = c->gen_updates;
+  upd0.resize(c->n, 0);
+  const bool prof_on = c->prof.on;
+  c->prof.on = false;  // no timing events inside a recording
+  const uint64_t gen0 = c->buf_gen;
+  c->rec = g;
+  qimax_status s = rec_resume(c);
+  if (s == QIMAX_OK) s = qimax_reset(c);
+  uint64_t a = 0;
+  for (size_t l = 0; l < ends.size() && s == QIMAX_OK; ++l) {
+    s = qimax_apply_circuit(c, gate + a, q0 + a, q1 + a, theta ? theta + a : nullptr, ends[l] - a);
+    a = ends[l];
+  }
+  if (s == QIMAX_OK) s = flush_pending(c);
+  if (s == QIMAX_OK) s = rec_cut(c);
+  if (c->rec_capturing) {  // a failure inside a captured part: drop it
+    hipGraph_t junk = nullptr;
+    (void)hipStreamEndCapture(c->stream, &junk);
+    if (junk) (void)hipGraphDestroy(junk);
+    c->rec_capturing = false;
+  }
+  c->rec = nullptr;
+  c->prof.on = prof_on;
+  if (s == QIMAX_OK && c->buf_gen != gen0)
+    s = fail(c, QIMAX_ESTATE, "the context's buffers changed while recording: run the step once first");
+  if (hipStreamSynchronize(c->stream) != hipSuccess && s == QIMAX_OK) s = fail(c, QIMAX_EDEVICE, "recorded step failed");
+  for (hipGraphExec_t x : g->runs) (void)hipGraphExecDestroy(x);
+  g->runs.clear();
+  if (s == QIMAX_OK) {
+    hipError_t e = hipGraphCreate(&g->whole, 0);
+    hipGraphNode_t prev = nullptr;
+    for (size_t i = 0; i < g->parts.size() && e == hipSuccess; ++i) {
+      hipGraphNode_t node = nullptr;
+      e = hipGraphAddChildGraphNode(&node, g->whole, prev ? &prev : nullptr, prev ? 1 : 0, g->parts[i]);
+      prev = node;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->whole, nullptr, nullptr, 0);
+    if (e != hipSuccess) s = fail(c, QIMAX_EDEVICE, std::string("building the step graph: ") + hipGetErrorString(e));
+  }
+  if (s != QIMAX_OK) {
+    const std::string msg = c->last_error;
+    g->ctx = nullptr;  // nothing of it is in flight
+    qimax_graph_destroy(g);
+    if (!c->broken) (void)qimax_reset(c);
+    c->last_error = msg;
+    return s;
+  }
+  g->gen = c->buf_gen;
+  g->keys = c->keys; g->w = c->w; g->seg = c->seg;
+  for (int i = 0; i < 2; ++i) { g->pk[i] = c->pk[i]; g->pw[i] = c->pw[i]; g->pseg[i] = c->pseg[i]; }
+  g->h_seg = c->h_seg;
+  g->T = c->T;
+  g->st_delta.passes = c->st.passes - st0.passes;
+  g->st_delta.term_updates = c->st.term_updates - st0.term_updates;
+  g->st_delta.images = c->st.images - st0.images;
+  g->st_delta.sort_elems = c->st.sort_elems - st0.sort_elems;
+  g->st_delta.rounds = c->st.rounds - st0.rounds;
+  g->st_delta.alg_bytes = c->st.alg_bytes - st0.alg_bytes;
+  g->upd_delta.assign(c->n, 0);
+  for (uint32_t j = 0; j < c->n && j < c->gen_updates.size(); ++j) g->upd_delta[j] = c->gen_updates[j] - upd0[j];
+  *out = g;
+  return QIMAX_OK;
+}
+
+qimax_status qimax_graph_launch(qimax_graph* g) {
+  if (!g || !g->ctx) return QIMAX_EINVAL;
+  qimax_ctx* c = g->ctx;
+  if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
+  if (c->rec) return fail(c, QIMAX_ESTATE, "a recording is in progress");
+  if (c->buf_gen != g->gen) return fail(c, QIMAX_ESTATE, "the context's buffers changed since the recording");
+  // the recorded buffers must be the context's (in any of the roles a call swaps them through)
+  auto same = [](std::initializer_list<const DevBuf*> x, std::initializer_list<const DevBuf*> y) {
+    std::vector<void*> a, b;
+    for (auto* d : x) a.push_back(d->p);
+    for (auto* d : y) b.push_back(d->p);
+    std::sort(a.begin(), a.end());
+    std::sort(b.begin(), b.end());
+    return a == b;
+  };
+  if (!same({&c->keys, &c->pk[0], &c->pk[1]}, {&g->keys, &g->pk[0], &g->pk[1]}) ||
+      !same({&c->w, &c->pw[0], &c->pw[1]}, {&g->w, &g->pw[0], &g->pw[1]}) ||
+      !same({&c->seg, &c->pseg[0], &c->pseg[1]}, {&g->seg, &g->pseg[0], &g->pseg[1]}))
+    return fail(c, QIMAX_ESTATE, "the context's term buffers are not the recorded ones");
+  // look-back status words carry the recorded epochs: clear them first
+  if (c->mstatus.p) HIPCHK(c, launch_fill_u64((uint64_t*)c->mstatus.p, c->mstatus.bytes / 8, 0ull, c->stream), "clear status");
+  if (c->sstatus.p) HIPCHK(c, launch_fill_u64((uint64_t*)c->sstatus.p, c->sstatus.bytes / 8, 0ull, c->stream), "clear status");
+  HIPCHK(c, hipGraphLaunch(g->exec, c->stream), "hipGraphLaunch");
+  c->keys = g->keys; c->w = g->w; c->seg = g->seg;
+  for (int i = 0; i < 2; ++i) { c->pk[i] = g->pk[i]; c->pw[i] = g->pw[i]; c->pseg[i] = g->pseg[i]; }
+  c->h_seg = g->h_seg;
+  c->T = g->T;
+  c->st.terms = c->T;
+  c->pending.clear();
+  c->st.passes += g->st_delta.passes;
+  c->st.term_updates += g->st_delta.term_updates;
+  c->st.images += g->st_delta.images;
+  c->st.sort_elems += g->st_delta.sort_elems;
+  c->st.rounds += g->st_delta.rounds;
+  c->st.alg_bytes += g->st_delta.alg_bytes;
+  if (c->gen_updates.size() != c->n) c->gen_updates.assign(c->n, 0);
+  for (uint32_t j = 0; j < c->n; ++j) c->gen_updates[j] += g->upd_delta[j];
+  return QIMAX_OK;
 }
 
 qimax_status qimax_group_circuit(qimax_ctx* c, const uint8_t* gate, const uint32_t* q0, const uint32_t* q1,

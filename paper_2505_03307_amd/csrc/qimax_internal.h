@@ -130,7 +130,7 @@ enum : uint32_t {
 // algorithmic bytes each launch must move (what the roofline is measured against).
 enum KernelKind : int {
   kKInit, kKCount, kKScan, kKExpand, kKSortHist, kKSortScatter, kKMergeCount, kKMergeWrite, kKCompose, kKChunkSort,
-  kKNum
+  kKCountExpand, kKNum
 };
 const char* kernel_kind_name(int k);
 
@@ -243,15 +243,14 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
 // LDS and its runs of equal keys summed and pruned (|sum| > its pass's thr); chunks are claimed
 // in order (co.ticket) and each writes its kept runs straight to its output offset, found by
 // a decoupled look-back over the earlier chunks' kept counts (co.status, tagged co.epoch;
-// co.chunk_off receives every chunk's offset, tc.n_blocks + 1 words). The last chunk to
-// finish (co.done) writes seg_off_out and the packed readback area (co.fin). Sets kErrRedo
-// when a bucket does not fit a chunk (the outputs are then not valid). With m = 0 every chunk
-// must be a whole segment (at most kChunkCap elements). co.img_cnt (S words, or null): the
-// image counts of the segments, scanned into the readback area instead of fin.img_seg.
-// co.ticket and co.done must be zero at launch.
+// co.chunk_off receives every chunk's offset, tc.n_blocks + 1 words). A one-block launch then
+// writes seg_off_out and the packed readback area (co.fin). Sets kErrRedo when a bucket does
+// not fit a chunk (the outputs are then not valid). With m = 0 every chunk must be a whole
+// segment (at most kChunkCap elements). co.img_cnt (S words, or null): the image counts of
+// the segments, scanned into the readback area instead of fin.img_seg. co.ticket must be zero
+// at launch.
 struct ChunkOut {
   uint32_t* ticket;
-  uint32_t* done;
   uint64_t* status;
   uint64_t epoch;
   uint64_t* chunk_off;
@@ -290,6 +289,19 @@ struct TileJob2 {
 // limit sets an error bit.
 hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint32_t S, uint64_t* img_seg,
                               const TileJob2& j0, const TileJob2& j1, uint64_t limit, uint32_t* err, hipStream_t s);
+
+// Count and expansion fused (see k_count_expand), for rounds whose fan-out bound is at most
+// kFuseMaxFanout: tl is the tiling of the input terms into tiles of fuse_tile() terms, claimed
+// in order through *ctr (zero at launch); status / epoch as for the count. img_seg (S + 1
+// words) receives the segments' first images and the image count; images go to keys_out /
+// w_out (out_cap elements), digit counts of passes hp_begin .. n_pass-1 to ghist.
+constexpr int kFuseMaxFanout = 16;
+size_t fuse_tile();
+hipError_t launch_count_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const Tiling& tl,
+                               const PassArgs* pas, const uint32_t* seg_entry, uint64_t* status, uint32_t* ctr,
+                               uint64_t epoch, uint64_t* img_seg, void* keys_out, void* w_out, uint64_t out_cap,
+                               uint32_t* ghist, uint32_t n_pass, uint32_t hp_begin, uint32_t* err, hipStream_t s,
+                               Prof* prof = nullptr);
 
 // A round whose segments each hold at most kChunkCap terms and images, one block per
 // segment: A chain, fan-out, scan and images of segment s, written to its chunk

@@ -50,6 +50,29 @@ class CircuitC(ctypes.Structure):
                 ("prune_eps", ctypes.c_double)]
 
 
+class StepGraph:
+    """A recorded step (qimax_graph): launch() replays it on the simulator's stream."""
+
+    def __init__(self, sim: "Simulator", handle):
+        self.sim = sim
+        self._g = handle
+
+    def launch(self):
+        self.sim._check(load().qimax_graph_launch(self._g))
+        return self
+
+    def close(self):
+        if self._g:
+            load().qimax_graph_destroy(self._g)
+            self._g = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 class BatchInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("queued", "active", "finished", "rounds", "terms", "term_updates", "alloc_bytes", "peak_bytes")]
@@ -63,7 +86,7 @@ class KernelTime(ctypes.Structure):
 EXPORTS = ["qimax_batch_create", "qimax_batch_submit", "qimax_batch_step", "qimax_batch_run", "qimax_batch_poll",
            "qimax_batch_fetch", "qimax_batch_info", "qimax_batch_circuit_updates", "qimax_batch_context",
            "qimax_batch_last_error", "qimax_batch_destroy",
-           "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_flush", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
+           "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_flush", "qimax_graph_record", "qimax_graph_launch", "qimax_graph_destroy", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
            "qimax_num_terms", "qimax_get_generators", "qimax_get_generators_xz", "qimax_expect",
            "qimax_expect_many", "qimax_prob_zero_all", "qimax_compare", "qimax_get_stats", "qimax_sync",
            "qimax_profile", "qimax_profile_only", "qimax_profile_read", "qimax_copy_probe", "qimax_last_error", "qimax_destroy"]
@@ -91,6 +114,13 @@ def load():
     lib.qimax_create.argtypes = [ctypes.c_uint32, ctypes.POINTER(Opts), ctypes.POINTER(P)]
     lib.qimax_reset.argtypes = [P]
     lib.qimax_flush.argtypes = [P]
+    lib.qimax_graph_record.argtypes = [P, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint32),
+                                       ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t,
+                                       ctypes.POINTER(P)]
+    lib.qimax_graph_launch.argtypes = [P]
+    lib.qimax_graph_destroy.argtypes = [P]
+    lib.qimax_graph_destroy.restype = None
     lib.qimax_get_generator_updates.argtypes = [P, u64p, ctypes.c_size_t]
     lib.qimax_apply_layer.argtypes = [P, ctypes.POINTER(Op), ctypes.c_size_t]
     lib.qimax_apply_circuit.argtypes = [P, u8p, u32p, u32p, dp, ctypes.c_size_t]
@@ -197,9 +227,23 @@ class Simulator:
         return self
 
     def flush(self):
-        """Apply the operators the last call kept back (a trailing Clifford run)."""
+        """Apply the operators kept back by calls that held only Clifford operators."""
         self._check(load().qimax_flush(self._h))
         return self
+
+    def record_step(self, circuit) -> "StepGraph":
+        """Record reset + every layer + flush of a workloads.Circuit as a replayable graph (the
+        step runs once while it is recorded). Run the step once before recording."""
+        g = np.ascontiguousarray(circuit.gate, dtype=np.uint8)
+        a = np.ascontiguousarray(circuit.q0, dtype=np.uint32)
+        b = np.ascontiguousarray(circuit.q1, dtype=np.uint32)
+        t = np.ascontiguousarray(circuit.theta, dtype=np.float64)
+        ends = np.ascontiguousarray(circuit.layer_end, dtype=np.uint64)
+        h = ctypes.c_void_p()
+        self._check(load().qimax_graph_record(self._h, _p(g, ctypes.c_uint8), _p(a, ctypes.c_uint32),
+                                              _p(b, ctypes.c_uint32), _p(t, ctypes.c_double), g.size,
+                                              _p(ends, ctypes.c_uint64), ends.size, ctypes.byref(h)))
+        return StepGraph(self, h)
 
     def apply_circuit(self, circuit_or_arrays):
         g, a, b, t = _instr(circuit_or_arrays)

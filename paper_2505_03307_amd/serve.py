@@ -24,7 +24,7 @@ import numpy as np
 from . import workloads as W
 from .qimax import Batch, Simulator
 
-_NON_CLIFFORD = (W.Gate.T, W.Gate.TDG, W.Gate.RX, W.Gate.RY, W.Gate.RZ)
+_NON_CLIFFORD = W.NON_CLIFFORD
 
 
 def _hea_layers(c: W.Circuit):

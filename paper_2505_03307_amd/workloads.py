@@ -13,6 +13,9 @@ one gate per row, stored as four parallel arrays
     q1    : uint32  second wire for two-qubit gates, else equal to q0
     theta : float64 rotation angle; 0 for gates without a parameter
 
+Two-qubit gates: CX (q0 = control), CZ, ISWAP, and the rotations RXX, RYY, RZZ
+(exp(-i theta P P / 2) for P = X, Y, Z on both wires).
+
 ``layer_end`` lists, for every circuit layer, the index one past its last
 instruction. A layer is what one call of the propagation API receives; the
 prune of small weights runs once at the end of each layer.
@@ -42,10 +45,16 @@ class Gate(enum.IntEnum):
     RZ = 11
     CX = 12
     CZ = 13
+    ISWAP = 14
+    RXX = 15
+    RYY = 16
+    RZZ = 17
 
 
-TWO_QUBIT = (Gate.CX, Gate.CZ)
+TWO_QUBIT = (Gate.CX, Gate.CZ, Gate.ISWAP, Gate.RXX, Gate.RYY, Gate.RZZ)
 CLIFFORD_1Q = (Gate.H, Gate.S, Gate.SDG, Gate.SX, Gate.X, Gate.Y, Gate.Z)
+ROTATIONS = (Gate.RX, Gate.RY, Gate.RZ, Gate.RXX, Gate.RYY, Gate.RZZ)
+NON_CLIFFORD = (Gate.T, Gate.TDG) + ROTATIONS
 
 
 @dataclasses.dataclass
@@ -91,20 +100,21 @@ class Circuit:
         inv = {Gate.S: Gate.SDG, Gate.SDG: Gate.S, Gate.T: Gate.TDG, Gate.TDG: Gate.T}
         g = self.gate[::-1].copy()
         th = -self.theta[::-1].copy()
-        sx = []
+        cube = []
         for i in range(g.shape[0]):
             code = Gate(int(g[i]))
-            if code == Gate.SX:
-                sx.append(i)
+            if code in (Gate.SX, Gate.ISWAP):
+                cube.append(i)
             g[i] = int(inv.get(code, code))
-            if code not in (Gate.RX, Gate.RY, Gate.RZ):
+            if code not in ROTATIONS:
                 th[i] = 0.0
         q0 = self.q0[::-1].copy()
         q1 = self.q1[::-1].copy()
-        if sx:  # SX^dagger = SX^3: expand in place
+        if cube:  # SX^dagger = SX^3, ISWAP^dagger = ISWAP^3: expand in place
+            cube = set(cube)
             rows = []
             for i in range(g.shape[0]):
-                reps = 3 if i in sx else 1
+                reps = 3 if i in cube else 1
                 rows.extend([i] * reps)
             rows = np.array(rows)
             g, q0, q1, th = g[rows], q0[rows], q1[rows], th[rows]
@@ -273,16 +283,16 @@ def random_circuit(seed: int, n: int, m: int, p_nonclifford: float = 0.15,
     b = _Builder(n)
     for _ in range(m):
         code = Gate(int(rng.choice([int(g) for g in gates])))
-        if code in (Gate.RX, Gate.RY, Gate.RZ, Gate.T, Gate.TDG) and rng.random() > p_nonclifford * 4:
+        if code in NON_CLIFFORD and rng.random() > p_nonclifford * 4:
             code = Gate(int(rng.choice([int(g) for g in CLIFFORD_1Q if g in gates] or [int(Gate.H)])))
+        th = float(rng.uniform(0, 2 * math.pi)) if code in ROTATIONS else 0.0
         if code in TWO_QUBIT:
             if n < 2:
                 continue
             a, c = rng.choice(n, size=2, replace=False).tolist()
-            b.add(code, a, c)
+            b.add(code, a, c, th)
         else:
             q = int(rng.integers(n))
-            th = float(rng.uniform(0, 2 * math.pi)) if code in (Gate.RX, Gate.RY, Gate.RZ) else 0.0
             b.add(code, q, q, th)
     return b.build(0.0, f"random(seed={seed},n={n},m={m})")
 

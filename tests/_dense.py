@@ -11,7 +11,7 @@ import math
 
 import numpy as np
 
-from paper_2505_03307_amd.workloads import Gate
+from paper_2505_03307_amd.workloads import TWO_QUBIT, Gate
 
 I2 = np.eye(2, dtype=complex)
 PX = np.array([[0, 1], [1, 0]], dtype=complex)
@@ -50,13 +50,18 @@ def unitary_1q(code: int, theta: float = 0.0) -> np.ndarray:
     raise ValueError(code)
 
 
-def unitary_2q(code: int) -> np.ndarray:
+def unitary_2q(code: int, theta: float = 0.0) -> np.ndarray:
     """4x4 unitary on (q0, q1), basis |q0 q1>, q0 the more significant bit."""
     g = Gate(code)
     if g == Gate.CX:
         return np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=complex)
     if g == Gate.CZ:
         return np.diag([1, 1, 1, -1]).astype(complex)
+    if g == Gate.ISWAP:
+        return np.array([[1, 0, 0, 0], [0, 0, 1j, 0], [0, 1j, 0, 0], [0, 0, 0, 1]], dtype=complex)
+    if g in (Gate.RXX, Gate.RYY, Gate.RZZ):
+        P = {Gate.RXX: PX, Gate.RYY: PY, Gate.RZZ: PZ}[g]
+        return math.cos(theta / 2) * np.eye(4) - 1j * math.sin(theta / 2) * np.kron(P, P)
     raise ValueError(code)
 
 
@@ -98,8 +103,8 @@ def apply_circuit_state(circuit, psi: np.ndarray) -> np.ndarray:
     for i in range(circuit.m):
         code = int(circuit.gate[i])
         a, b, th = int(circuit.q0[i]), int(circuit.q1[i]), float(circuit.theta[i])
-        if code in (Gate.CX, Gate.CZ):
-            psi = _apply_2q_state(psi, n, a, b, unitary_2q(code))
+        if Gate(code) in TWO_QUBIT:
+            psi = _apply_2q_state(psi, n, a, b, unitary_2q(code, th))
         else:
             psi = _apply_1q_state(psi, n, a, unitary_1q(code, th))
     return psi

@@ -54,6 +54,9 @@ class Tableau:
             self.cx(a, b)
         elif g == Gate.CZ:
             self.h(b); self.cx(a, b); self.h(b)
+        elif g == Gate.ISWAP:
+            # ISWAP = CX(a,b) CX(b,a) S(b) CX(a,b) in time order, up to a global phase
+            self.cx(a, b); self.s(b); self.cx(b, a); self.cx(a, b)
         else:
             raise ValueError(f"not a Clifford gate: {g!r}")
 

@@ -27,6 +27,10 @@ MUTATIONS = {
                                "if (std::fabs(gen[i].w) >= eps) gen[k++] = gen[i];"),
     "Y and Z codes swapped": ("if (xb && zb) return 2;\n  return 3;", "if (xb && zb) return 3;\n  return 2;"),
     "generators start as X": ("g[0].z = 1ull << j;  // Z on qubit j", "g[0].x = 1ull << j; g[0].z = 0;"),
+    "two-qubit rotation image sign": ("u.w = t.w * s * (k == 0 ? 1.0 : -1.0);", "u.w = t.w * s * (k == 0 ? -1.0 : 1.0);"),
+    "two-qubit rotation commutation test": ("const int sym = ((xa & pz) ^ (za & px)) ^ ((xb & pz) ^ (zb & px));",
+                                            "const int sym = ((xa & pz) ^ (za & px)) | ((xb & pz) ^ (zb & px));"),
+    "ISWAP as XX only": ("      apply_pp_rotation(gen, a, b, 1, 1, 0.0, -1.0, scratch);  // exp(i pi/4 YY)\n", ""),
 }
 
 

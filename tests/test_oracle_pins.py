@@ -73,7 +73,7 @@ def test_cx_propagation_matches_paper_rules():
         assert oracle_generator_dict(o, 0) == {parts[1]: float(parts[2])}
 
 
-@pytest.mark.parametrize("code", [g for g in Gate if g not in (Gate.CX, Gate.CZ)])
+@pytest.mark.parametrize("code", [g for g in Gate if g not in W.TWO_QUBIT])
 @pytest.mark.parametrize("theta", [0.0, 0.3, 1.234, -2.5, math.pi / 2])
 def test_1q_ptm_matches_unitary(code, theta):
     R = oracle.gate_ptm(code, theta)
@@ -81,12 +81,23 @@ def test_1q_ptm_matches_unitary(code, theta):
     assert np.max(np.abs(R - ref)) < 1e-14
 
 
-@pytest.mark.parametrize("code", [Gate.CX, Gate.CZ])
+@pytest.mark.parametrize("code", [Gate.CX, Gate.CZ, Gate.ISWAP])
 def test_2q_ptm_matches_unitary(code):
     R = oracle.gate_ptm(code)
     ref = D.ptm_from_unitary(D.unitary_2q(code))
     assert np.max(np.abs(R - ref)) < 1e-14
     assert set(np.unique(R).tolist()) <= {-1.0, 0.0, 1.0}
+
+
+@pytest.mark.parametrize("code", [Gate.RXX, Gate.RYY, Gate.RZZ])
+@pytest.mark.parametrize("theta", [0.0, 0.3, 1.234, -2.5, math.pi / 2])
+def test_2q_rotation_ptm_matches_unitary(code, theta):
+    """exp(-i theta P P / 2): Paulis commuting with PP stay, the others rotate into -i PP Q."""
+    R = oracle.gate_ptm(code, theta)
+    ref = D.ptm_from_unitary(D.unitary_2q(code, theta))
+    assert np.max(np.abs(R - ref)) < 1e-14
+    # every column has one or two nonzeros (fan-out at most 2)
+    assert set(((R != 0).sum(axis=0)).tolist()) <= {1, 2}
 
 
 def test_sx_maps_z_to_minus_y():
@@ -280,7 +291,9 @@ def test_generic_ptm_ops_vs_dense():
 def test_stabilizer_relation(seed):
     """G_j |psi> = |psi> for every propagated generator (n <= 10)."""
     n = 6 + seed
-    c = W.random_circuit(100 + seed, n, 12 * n, p_nonclifford=0.2)
+    # one-qubit gates with CX and CZ: the two-qubit rotations are covered by the dense pins
+    gates = [g for g in Gate if g not in (Gate.ISWAP, Gate.RXX, Gate.RYY, Gate.RZZ)]
+    c = W.random_circuit(100 + seed, n, 12 * n, p_nonclifford=0.2, gates=gates)
     psi = D.statevector(c)
     o = oracle.propagate(c)
     for j in range(n):
@@ -313,7 +326,7 @@ def test_density_operator_product():
 
 @pytest.mark.parametrize("n", [5, 17, 32, 48])
 def test_clifford_matches_tableau(n):
-    gates = [Gate.H, Gate.S, Gate.SDG, Gate.SX, Gate.X, Gate.Y, Gate.Z, Gate.CX, Gate.CZ]
+    gates = [Gate.H, Gate.S, Gate.SDG, Gate.SX, Gate.X, Gate.Y, Gate.Z, Gate.CX, Gate.CZ, Gate.ISWAP]
     c = W.random_circuit(n, n, 20 * n, gates=gates)
     o = oracle.propagate(c)
     rows = Tableau(n).run(c).rows()

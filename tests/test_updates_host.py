@@ -50,3 +50,21 @@ def test_hand_count_layers_and_ansatz_closed_form():
     c = _circ(n, rows)
     assert definition_updates(c).tolist() == [6] * n
     assert math.isclose(float(definition_updates(c).sum()), 6 * n)
+
+
+def test_hand_count_two_qubit_rotations_and_fusion():
+    # V_0 = RZZ(0,1) then RXX(0,1): one fused operator. Z_0 (ZI) commutes with ZZ and
+    # anticommutes with XX: the fused column of ZI holds 2 nonzeros; Z_1 (IZ) likewise: 2 and 2.
+    # Then U_1 = H(0) (Clifford) sees 2 terms each: 4 and 4.
+    c = _circ(2, [(Gate.RZZ, 0, 1, 0.7), (Gate.RXX, 1, 0, 0.2), (Gate.H, 0)])
+    assert definition_updates(c).tolist() == [4, 4]
+
+
+def test_hand_count_rotations_on_other_pairs_count_one_by_one():
+    # V_0 = RZZ(0,1), ISWAP(1,2), RXX(1,2): the ISWAP and the RXX fuse into one operator on
+    # (1, 2); the group is non-Clifford, so each of its two operators counts its images.
+    # Z_0: RZZ keeps it (1 image), and it holds I on (1, 2) (1 image): 2. Z_1: RZZ keeps it
+    # (1); the ISWAP moves its Z to wire 2, where it anticommutes with XX (2 images): 3.
+    # Z_2: 1, then the ISWAP moves its Z to wire 1 (2 images): 3.
+    c = _circ(3, [(Gate.RZZ, 0, 1, 0.7), (Gate.ISWAP, 1, 2), (Gate.RXX, 1, 2, 0.4)])
+    assert definition_updates(c).tolist() == [2, 3, 3]
