@@ -134,8 +134,10 @@ qimax_status qimax_flush(qimax_ctx* ctx);
  * launches between the host's synchronisations; qimax_graph_launch then replays them on the
  * context's stream with no host work in between, leaving the same generators (bit for bit)
  * and counting the same statistics. The replay is asynchronous (qimax_sync waits).
- * Recording never allocates: every buffer the step needs must already be large enough, so run
- * the step once before recording (QIMAX_ESTATE otherwise; the context is then reset). A graph
+ * The record call runs the step uncaptured until three runs in a row grew no buffer (a step
+ * moves the term buffers through up to three roles), then once captured (recording itself
+ * never allocates; a step that still needs a larger buffer fails with QIMAX_ESTATE and the
+ * context is reset). The autotuner does not explore during these runs. A graph
  * refers to its context's buffers: a replay is refused (QIMAX_ESTATE) once any of them has
  * been reallocated or freed since the recording. Destroy graphs before their context. */
 typedef struct qimax_graph qimax_graph;

@@ -1213,6 +1213,7 @@ __global__ void k_merge_publish(Tiling tl, const uint64_t* __restrict__ blk_off,
 // a chunk raises kErrRedo (not an error: the caller sorts the round again with global passes
 // only).
 constexpr int kChunkBlock = 512;  // threads of a chunk-local sort (8 waves)
+constexpr uint64_t kChunkPlaced = ~0ull;          // chunk_start of a chunk written in place
 template <typename K, typename W>
 __global__ void __launch_bounds__(kChunkBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __restrict__ keys_out, W* __restrict__ w_out,
@@ -1237,13 +1238,18 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   const uint32_t blk = blk_sh;
   const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
   if (blk >= nc) return;
-  // The chunk's output offset: publish its kept count, look back over the earlier chunks for
-  // their prefix (decoupled look-back; status words [epoch:16][flag:2][value:46]).
-  auto lookback = [&](uint64_t tot) -> uint64_t {
+  // The chunk's output offset: publish its kept count and look back over the earlier chunks
+  // for their prefix (decoupled look-back; status words [epoch:16][flag:2][value:46]). The
+  // wait for an earlier chunk that has not published yet is short: past co.defer_spins polls the chunk
+  // is deferred (its runs go to its own range, and a later launch moves them), so that one
+  // slow chunk does not hold every later one on the chip. Returns the offset, or kDeferred.
+  constexpr uint64_t kDeferred = ~0ull;
+  auto lookback = [&](uint64_t tot, uint64_t start) -> uint64_t {
     if (threadIdx.x == 0) {
       const uint64_t ep = co.epoch << 48;
       st_store(co.status + blk, ep | (blk == 0 ? kStPre : kStAgg) | tot);
       uint64_t excl = 0;
+      bool resolved = true;
       if (blk > 0) {
         uint32_t t = blk - 1;
         uint32_t spins = 0;
@@ -1251,23 +1257,23 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
           const uint64_t v = st_load(co.status + t);
           const bool ready = (v >> 48) == co.epoch && (v & (kStAgg | kStPre));
           if (!ready) {
-            if (++spins > kSpinLimit) { atomicOr(err, kErrSpin); break; }
+            if (++spins > co.defer_spins) { resolved = false; break; }
             continue;
           }
           excl += v & kStValMask;
           if ((v & kStPre) || t == 0) break;
           --t;
         }
-        st_store(co.status + blk, ep | kStPre | (excl + tot));
+        if (resolved) st_store(co.status + blk, ep | kStPre | (excl + tot));
       }
-      st_store(co.chunk_off + blk, excl);
-      if (blk + 1 == nc) st_store(co.chunk_off + nc, excl + tot);
-      base_sh = excl;
+      co.chunk_cnt[blk] = (uint32_t)tot;
+      co.chunk_start[blk] = resolved ? kChunkPlaced : start;
+      base_sh = resolved ? excl : kDeferred;
     }
     __syncthreads();
     return base_sh;
   };
-  auto none = [&]() { lookback(0); };  // this chunk keeps nothing (empty, or handed to the fallback)
+  auto none = [&]() { lookback(0, 0); };  // this chunk keeps nothing (empty, or handed to the fallback)
   const uint64_t a = tc.blk_begin[blk], b = tc.blk_end[blk];
   if (a >= b) {
     none();
@@ -1525,53 +1531,259 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   }
   uint64_t tot;
   const uint64_t pre = block_excl_scan<kChunkBlock>(keep, scan_sh, &tot);
-  const uint64_t base = lookback(tot);
-  // every kept run straight to its output position
-  if (base + tot <= out_cap) {
-    uint64_t o = base + pre;
+  const uint64_t base = lookback(tot, c0);
+  // every kept run straight to its output position, or (deferred) to the front of the chunk's
+  // own range of the scratch arrays
+  K* kd = keys_out;
+  W* wd = w_out;
+  uint64_t o = base + pre;
+  if (base == kDeferred) {
+    kd = (K*)co.tmp_keys;
+    wd = (W*)co.tmp_w;
+    o = c0 + pre;
+  } else if (base + tot > out_cap) {
+    if (threadIdx.x == 0 && tot) atomicOr(err, kErrIndex | kErrMerge);
+    return;
+  }
 #pragma unroll
-    for (int t = 0; t < kItems; ++t) {
-      if (!(keep_mask & (1u << t))) continue;
-      keys_out[o] = sk[j0 + t];
-      w_out[o] = sums[t];
-      ++o;
-    }
-  } else if (threadIdx.x == 0 && tot) {
-    atomicOr(err, kErrIndex | kErrMerge);
+  for (int t = 0; t < kItems; ++t) {
+    if (!(keep_mask & (1u << t))) continue;
+    kd[o] = sk[j0 + t];
+    wd[o] = sums[t];
+    ++o;
   }
 }
 
-// After the chunk-local sort and merge (one block): the segments' output offsets from the
-// chunks' offsets, and the packed readback area in mapped host memory (output offsets, image
-// offsets — fin.img_seg, or the scan of img_cnt when set — and the error word), its sequence
-// word last.
-constexpr int kFinishBlock = 512;
-__global__ void __launch_bounds__(kFinishBlock) k_chunk_finish(Tiling tc, const uint64_t* __restrict__ chunk_off,
-                                                               uint64_t* __restrict__ seg_off_out, MergeFin fin,
-                                                               const uint32_t* __restrict__ img_cnt, uint64_t out_cap,
-                                                               const uint32_t* __restrict__ err) {
-  __shared__ uint64_t sh[kFinishBlock / 64];
+// After the chunk-local sort and merge (one block): chunk_off = exclusive scan of the kept
+// counts of the chunks (n_dev or n_blocks of tc), the segment output offsets
+// seg_off_out[s] = chunk_off[seg_blk[s]], and the packed readback area (see MergeFin), whose
+// image offsets are fin.img_seg, or the scan of img_cnt when set; a total above out_cap is
+// reported in the error word there (the compaction then writes nothing).
+constexpr int kPublishBlock = 1024;
+__global__ void __launch_bounds__(kPublishBlock) k_chunk_publish(Tiling tc, const uint32_t* __restrict__ chunk_cnt,
+                                                                 uint64_t* __restrict__ chunk_off,
+                                                                 uint64_t* __restrict__ seg_off_out, MergeFin fin,
+                                                                 const uint32_t* __restrict__ img_cnt, uint64_t out_cap,
+                                                                 const uint32_t* __restrict__ err) {
+  __shared__ uint64_t sh[kPublishBlock / 64];
+  __shared__ uint64_t total_sh;
   const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
+  // thread t scans the run [t*per, (t+1)*per) serially: one block scan for all the runs
+  const uint32_t per = (nc + kPublishBlock - 1) / kPublishBlock;
+  const uint32_t r0 = min(threadIdx.x * per, nc), r1 = min(r0 + per, nc);
+  // (eight loads in flight at a time: the run is read twice)
+  constexpr uint32_t kBatch = 8;
+  uint64_t sum = 0;
+  for (uint32_t i0 = r0; i0 < r1; i0 += kBatch) {
+    uint32_t v[kBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) v[u] = i0 + u < r1 ? chunk_cnt[i0 + u] : 0u;
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) sum += v[u];
+  }
+  uint64_t tot;
+  uint64_t run = block_excl_scan<kPublishBlock>(sum, sh, &tot);
+  for (uint32_t i0 = r0; i0 < r1; i0 += kBatch) {
+    uint32_t v[kBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) v[u] = i0 + u < r1 ? chunk_cnt[i0 + u] : 0u;
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) {
+      if (i0 + u < r1) chunk_off[i0 + u] = run;
+      run += v[u];
+    }
+  }
+  if (threadIdx.x == 0) {
+    chunk_off[nc] = tot;
+    total_sh = tot;
+  }
+  __syncthreads();
   const uint32_t S = tc.n_segs;
-  const uint64_t total = chunk_off[nc];
-  for (uint32_t q = threadIdx.x; q <= S; q += kFinishBlock) {
+  for (uint32_t q = threadIdx.x; q <= S; q += kPublishBlock) {
     const uint64_t v = chunk_off[min(tc.seg_blk[q], nc)];
     seg_off_out[q] = v;
     fin.result[q] = v;
     if (!img_cnt) fin.result[S + 1 + q] = fin.img_seg[q];
   }
-  if (img_cnt) {  // image offsets of the segments from their counts (serial runs, one block scan)
-    const uint32_t ps = (S + kFinishBlock - 1) / kFinishBlock;
+  if (img_cnt) {  // image offsets of the segments from their counts (same serial-run scan)
+    const uint32_t ps = (S + kPublishBlock - 1) / kPublishBlock;
     const uint32_t q0 = min(threadIdx.x * ps, S), q1 = min(q0 + ps, S);
     uint64_t isum = 0;
     for (uint32_t q = q0; q < q1; ++q) isum += img_cnt[q];
     uint64_t itot;
-    uint64_t irun = block_excl_scan<kFinishBlock>(isum, sh, &itot);
+    uint64_t irun = block_excl_scan<kPublishBlock>(isum, sh, &itot);
     for (uint32_t q = q0; q < q1; ++q) {
       fin.result[S + 1 + q] = irun;
       irun += img_cnt[q];
     }
     if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 1] = itot;
+  }
+  if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (total_sh > out_cap ? kErrIndex | kErrMerge : 0u);
+  publish_seq(fin, S);
+}
+
+// Moves the kept runs of every deferred chunk from the front of its range (in the scratch
+// arrays) to its output offset; the other chunks wrote theirs in place already.
+template <typename K, typename W>
+__global__ void __launch_bounds__(256) k_chunk_compact(const K* __restrict__ keys_in, const W* __restrict__ w_in,
+                                                       K* __restrict__ keys_out, W* __restrict__ w_out, Tiling tc,
+                                                       const uint32_t* __restrict__ chunk_cnt,
+                                                       const uint64_t* __restrict__ chunk_start,
+                                                       const uint64_t* __restrict__ chunk_off, uint64_t out_cap,
+                                                       uint32_t* err) {
+  const uint32_t blk = blockIdx.x;
+  if (tc.n_dev && blk >= *tc.n_dev) return;
+  const uint64_t src = chunk_start[blk];
+  if (src == kChunkPlaced) return;
+  const uint32_t cnt = chunk_cnt[blk];
+  const uint64_t dst = chunk_off[blk];
+  if (dst + cnt > out_cap || cnt > (uint32_t)kChunkCap) {
+    if (threadIdx.x == 0 && cnt) atomicOr(err, kErrIndex | kErrMerge);
+    return;
+  }
+  // every load of a thread's share in flight before its stores (a chunk keeps at most
+  // kChunkCap terms: kChunkCap / 256 per thread)
+  constexpr int kPer = kChunkCap / 256;
+  K kv[kPer];
+  W wv[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const uint32_t i = r * 256 + threadIdx.x;
+    if (i < cnt) {
+      kv[r] = keys_in[src + i];
+      wv[r] = w_in[src + i];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const uint32_t i = r * 256 + threadIdx.x;
+    if (i < cnt) {
+      keys_out[dst + i] = kv[r];
+      w_out[dst + i] = wv[r];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ dense accumulation
+// The dense alternative to sorting (the paper's fixed-size weight tensor of its v2 mode,
+// Sec. V): for a round whose keys index a small space (4^n per generator), every image adds
+// its weight into the slot of its key in a dense array per segment, and a scan of the array in
+// index order (which is key order) keeps the nonzero sums. The sums are taken in 64-bit fixed
+// point (2^-kDenseFracBits units): integer additions commute, so the result does not depend
+// on the order in which images arrive, and each image is rounded once by at most 2^-57.
+constexpr int kDenseFracBits = 56;   // |partial sum| < 2^(63-56) = 128
+constexpr int kDenseTile = 4096;     // dense slots per compaction tile
+
+template <typename K, typename W>
+__global__ void __launch_bounds__(256) k_dense_scatter(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl,
+                                                       unsigned long long* __restrict__ acc, uint64_t per_seg,
+                                                       uint32_t* err) {
+  const uint32_t b = blockIdx.x;
+  if (tl.n_dev && b >= *tl.n_dev) return;
+  const uint64_t a0 = tl.blk_begin[b], a1 = tl.blk_end[b];
+  unsigned long long* base = acc + (uint64_t)tl.blk_seg[b] * per_seg;
+  for (uint64_t i = a0 + threadIdx.x; i < a1; i += 256) {
+    const uint64_t k = (uint64_t)keys[i];
+    const double v = (double)w[i];
+    if (k >= per_seg || !(fabs(v) < 64.0)) {  // outside the dense space, or too large for it
+      atomicOr(err, kErrIndex | kErrMerge);
+      continue;
+    }
+    const long long q = __double2ll_rn(ldexp(v, kDenseFracBits));
+    atomicAdd(base + k, (unsigned long long)q);
+  }
+}
+
+// Tiles of kDenseTile slots, tiles_per_seg per segment, claimed in order: each keeps the slots
+// whose sum exceeds thr in magnitude (and is nonzero), finds its output offset by look-back
+// over the earlier tiles, and writes its kept terms (key = slot index) in key order.
+template <typename K, typename W>
+__global__ void __launch_bounds__(256) k_dense_compact(const unsigned long long* __restrict__ acc, uint64_t per_seg,
+                                                       uint32_t tiles_per_seg, uint32_t n_tiles, double thr,
+                                                       uint32_t* __restrict__ ticket, uint64_t* __restrict__ status,
+                                                       uint64_t epoch, uint64_t* __restrict__ tile_off,
+                                                       K* __restrict__ keys_out, W* __restrict__ w_out,
+                                                       uint64_t out_cap, uint32_t* err) {
+  constexpr int kItems = kDenseTile / 256;
+  __shared__ uint64_t scan_sh[4];
+  __shared__ uint64_t base_sh;
+  __shared__ uint32_t tile_sh;
+  if (threadIdx.x == 0) tile_sh = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const uint32_t t = tile_sh;
+  if (t >= n_tiles) return;
+  const uint32_t s = t / tiles_per_seg;
+  const uint64_t lo = (uint64_t)(t - s * tiles_per_seg) * kDenseTile;
+  const uint64_t n = min<uint64_t>(kDenseTile, per_seg - lo);
+  const unsigned long long* src = acc + (uint64_t)s * per_seg + lo;
+  // each thread a run of kItems consecutive slots
+  const uint32_t j0 = threadIdx.x * kItems;
+  W vals[kItems];
+  uint32_t keep_mask = 0, keep = 0;
+#pragma unroll
+  for (int k2 = 0; k2 < kItems; ++k2) {
+    const uint32_t j = j0 + k2;
+    double v = 0.0;
+    if (j < n) v = ldexp((double)(long long)src[j], -kDenseFracBits);
+    vals[k2] = (W)v;
+    if (v != 0.0 && fabs(v) > thr) {
+      keep_mask |= 1u << k2;
+      ++keep;
+    }
+  }
+  uint64_t tot;
+  const uint64_t pre = block_excl_scan<256>(keep, scan_sh, &tot);
+  if (threadIdx.x == 0) {
+    const uint64_t ep = epoch << 48;
+    st_store(status + t, ep | (t == 0 ? kStPre : kStAgg) | tot);
+    uint64_t excl = 0;
+    if (t > 0) {
+      uint32_t u = t - 1;
+      uint32_t spins = 0;
+      while (true) {
+        const uint64_t v = st_load(status + u);
+        const bool ready = (v >> 48) == epoch && (v & (kStAgg | kStPre));
+        if (!ready) {
+          if (++spins > kSpinLimit) { atomicOr(err, kErrSpin); break; }
+          continue;
+        }
+        excl += v & kStValMask;
+        if ((v & kStPre) || u == 0) break;
+        --u;
+      }
+      st_store(status + t, ep | kStPre | (excl + tot));
+    }
+    tile_off[t] = excl;
+    if (t + 1 == n_tiles) tile_off[n_tiles] = excl + tot;
+    base_sh = excl;
+  }
+  __syncthreads();
+  const uint64_t base = base_sh;
+  if (base + tot > out_cap) {
+    if (threadIdx.x == 0 && tot) atomicOr(err, kErrIndex | kErrMerge);
+    return;
+  }
+  uint64_t o = base + pre;
+#pragma unroll
+  for (int k2 = 0; k2 < kItems; ++k2) {
+    if (!(keep_mask & (1u << k2))) continue;
+    keys_out[o] = (K)(lo + j0 + k2);
+    w_out[o] = vals[k2];
+    ++o;
+  }
+}
+
+// One block after the compaction: segment s's output starts at the offset of its first tile;
+// the packed readback area as after the chunk-local merge.
+__global__ void __launch_bounds__(256) k_dense_finish(const uint64_t* __restrict__ tile_off, uint32_t tiles_per_seg,
+                                                      uint32_t S, uint64_t* __restrict__ seg_off_out, MergeFin fin,
+                                                      uint64_t out_cap, const uint32_t* __restrict__ err) {
+  const uint64_t total = tile_off[(uint64_t)S * tiles_per_seg];
+  for (uint32_t q = threadIdx.x; q <= S; q += 256) {
+    const uint64_t v = tile_off[(uint64_t)q * tiles_per_seg];
+    seg_off_out[q] = v;
+    fin.result[q] = v;
+    fin.result[S + 1 + q] = fin.img_seg[q];
   }
   if (threadIdx.x == 0) fin.result[2 * (uint64_t)S + 2] = *err | (total > out_cap ? kErrIndex | kErrMerge : 0u);
   publish_seq(fin, S);
@@ -1909,7 +2121,8 @@ inline uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)((n + bl
 
 const char* kernel_kind_name(int k) {
   static const char* names[kKNum] = {"init", "count", "scan", "expand", "sort_hist", "sort_scatter",
-                                     "merge_count", "merge_write", "compose_ptm", "chunk_sort", "count_expand"};
+                                     "merge_count", "merge_write", "compose_ptm", "chunk_sort", "count_expand",
+                                     "dense_merge"};
   return (k >= 0 && k < kKNum) ? names[k] : "?";
 }
 
@@ -2209,7 +2422,53 @@ hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* key
   });
   // bytes: every image read; the kept terms' bytes are added by the caller once known
   prof_end(prof, s, ev, kKChunkSort, (kb + wb) * (double)T);
-  k_chunk_finish<<<1, kFinishBlock, 0, s>>>(tc, co.chunk_off, co.seg_off_out, co.fin, co.img_cnt, T, err);
+  k_chunk_publish<<<1, kPublishBlock, 0, s>>>(tc, co.chunk_cnt, co.chunk_off, co.seg_off_out, co.fin, co.img_cnt, T,
+                                              err);
+  QIMAX_DISPATCH_K(KC, {
+    if (WP == 64)
+      k_chunk_compact<K, double><<<tc.n_blocks, 256, 0, s>>>((const K*)co.tmp_keys, (const double*)co.tmp_w,
+                                                             (K*)keys_out, (double*)w_out, tc, co.chunk_cnt,
+                                                             co.chunk_start, co.chunk_off, T, err);
+    else
+      k_chunk_compact<K, float><<<tc.n_blocks, 256, 0, s>>>((const K*)co.tmp_keys, (const float*)co.tmp_w,
+                                                            (K*)keys_out, (float*)w_out, tc, co.chunk_cnt,
+                                                            co.chunk_start, co.chunk_off, T, err);
+  });
+  return hipGetLastError();
+}
+
+size_t dense_tile() { return (size_t)kDenseTile; }
+
+hipError_t launch_dense_merge(int KC, int WP, const void* keys_in, const void* w_in, uint64_t T_img, const Tiling& tl,
+                              uint64_t per_seg, uint32_t S, void* acc, double thr, uint32_t* ticket, uint64_t* status,
+                              uint64_t epoch, uint64_t* tile_off, void* keys_out, void* w_out, uint64_t out_cap,
+                              uint64_t* seg_off_out, const MergeFin& fin, uint32_t* err, hipStream_t s, Prof* prof) {
+  if (KC != 0 || S == 0 || per_seg == 0) return hipErrorInvalidValue;  // 32-bit keys only (n <= 16)
+  const uint64_t slots = (uint64_t)S * per_seg;
+  const uint32_t tps = (uint32_t)((per_seg + kDenseTile - 1) / kDenseTile);
+  const uint32_t n_tiles = tps * S;
+  hipEvent_t ev = prof_begin(prof, s, kKDense);
+  k_fill_u64<<<grid_for(slots, 256), 256, 0, s>>>((uint64_t*)acc, slots, 0ull);
+  if (tl.n_blocks) {
+    if (WP == 64)
+      k_dense_scatter<uint32_t, double><<<tl.n_blocks, 256, 0, s>>>((const uint32_t*)keys_in, (const double*)w_in, tl,
+                                                                    (unsigned long long*)acc, per_seg, err);
+    else
+      k_dense_scatter<uint32_t, float><<<tl.n_blocks, 256, 0, s>>>((const uint32_t*)keys_in, (const float*)w_in, tl,
+                                                                   (unsigned long long*)acc, per_seg, err);
+  }
+  if (WP == 64)
+    k_dense_compact<uint32_t, double><<<n_tiles, 256, 0, s>>>((const unsigned long long*)acc, per_seg, tps, n_tiles,
+                                                              thr, ticket, status, epoch, tile_off, (uint32_t*)keys_out,
+                                                              (double*)w_out, out_cap, err);
+  else
+    k_dense_compact<uint32_t, float><<<n_tiles, 256, 0, s>>>((const unsigned long long*)acc, per_seg, tps, n_tiles, thr,
+                                                             ticket, status, epoch, tile_off, (uint32_t*)keys_out,
+                                                             (float*)w_out, out_cap, err);
+  // bytes: images read, every slot written (cleared), read back; the kept terms added later
+  const double wb = WP == 64 ? 8 : 4;
+  prof_end(prof, s, ev, kKDense, (4.0 + wb) * (double)T_img + 16.0 * (double)slots);
+  k_dense_finish<<<1, 256, 0, s>>>(tile_off, tps, S, seg_off_out, fin, out_cap, err);
   return hipGetLastError();
 }
 

@@ -86,10 +86,11 @@ struct HostOp {
 };
 
 // Autotuner state of one size class of rounds: the sort variants tried (0: heuristic number
-// of top-digit passes, 1: one more, 2: heuristic without per-XCD tile ranges), their measured
+// of top-digit passes, 1: one more, 2: heuristic without per-XCD tile ranges, 3: dense
+// accumulation instead of the sort, where it applies and is enabled), their measured
 // device times, and the winner once every candidate has run once.
 struct TuneState {
-  static constexpr int kCand = 3;
+  static constexpr int kCand = 4;  // 3: dense accumulation (classes where it applies)
   int tried = 0;
   int best = -1;
   float ms[kCand] = {};
@@ -246,6 +247,9 @@ constexpr int kMaxE1 = 64;
 constexpr int kBoundPathMaxFanout = 16;  // rounds with a larger fan-out bound read back their image count
 // tile counters of a round (after the per-pass, per-XCD sort counters)
 constexpr int kCtrCount = 252, kCtrMerge = 253, kCtrChunk = 254;
+constexpr uint32_t kDenseMaxN = 12;           // dense accumulation: at most 4^12 slots per generator
+constexpr double kDenseMaxBytes = 4.0e9;      // and at most this many bytes of slots in all
+constexpr double kDenseRatio = 8.0;           // tuned only where slots <= 8 x images
 constexpr int kMaxE2 = 8;
 constexpr double kMaxFanout = 2147483647.0;
 
@@ -279,7 +283,7 @@ struct qimax_ctx {
   DevBuf desc, desc2, err, f64tmp;
   DevBuf ptab;  // chain tables of a whole call, compiled in one launch
   DevBuf akeys, asign;  // input terms after their pass's A chain, and the signs (count -> expand)
-  DevBuf chunk_off;  // chunk-local merge: output offset of every chunk
+  DevBuf chunk_off, chunk_cnt, chunk_start;  // chunk-local merge: offset, kept terms, deferred runs per chunk
   DevBuf img_cnt;                            // small rounds: image count per segment
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
@@ -292,9 +296,13 @@ struct qimax_ctx {
   bool local_sort = true;     // top-digit passes + chunk-local sorts instead of all global passes
   bool small_rounds = true;   // rounds of small segments: one block per segment (see run_round)
   bool fused_expand = true;   // bound-path rounds: count and expansion in one launch
+  uint32_t defer_spins = 0;   // chunk-local merge: look-back polls before a chunk is deferred (0: one look)
+  int dense_mode = 0;         // dense accumulation: 0 off, 1 wherever it applies, 2 a tuner candidate
+  DevBuf dense_acc;           // its fixed-point slots
   int local_sort_m = -1;      // >= 0: force the number of top-digit passes
   uint32_t redo_cooldown = 0; // rounds left with global passes only after a chunk overflow
   bool autotune = true;       // choose among sort variants by measured time per size class
+  bool tune_frozen = false;   // no exploration: settled variants, else the heuristic (recording)
   std::map<uint32_t, TuneState> tune;
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   DevBuf gr_in, gr_out;  // grouping pass inputs; batch admission lists
@@ -596,6 +604,7 @@ struct qimax_graph {
   std::vector<void*> snaps;  // pinned copies of staged data, read by the parts
   std::vector<hipGraphExec_t> runs;  // the parts as launched while recording
   uint64_t gen = 0;          // ctx->buf_gen when recorded
+  uint64_t epoch_end = 0, mepoch_end = 0;  // the last look-back epochs the parts use
   bool failed = false;
   // the context's state after the step
   DevBuf keys, w, seg, pk[2], pw[2], pseg[2];
@@ -975,6 +984,14 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   int tune_cand = 0;
   bool tune_timed = false;
   bool xr = c->xcd_ranges;
+  // Dense accumulation instead of the sort: one circuit, 32-bit keys, a dense space of 4^n
+  // slots per generator that stays small next to the images, bounded weights (orthogonal
+  // transfer matrices). Forced (QIMAX_DENSE=1) or a tuner candidate (QIMAX_DENSE=auto).
+  const uint64_t per_seg = (c->KC == 0 && max_n <= kDenseMaxN) ? (1ull << (2 * max_n)) : 0;
+  const bool dense_ok = c->dense_mode && sweep && !small && E == 1 && per_seg && c->validate &&
+                        !entries[0].drop && (double)S * (double)per_seg * 8.0 <= kDenseMaxBytes &&
+                        (c->dense_mode == 1 || (double)S * (double)per_seg <= kDenseRatio * (double)T_img);
+  bool dense = dense_ok && c->dense_mode == 1;
   if (small) m_top = 0;  // whole segments sorted in LDS
   if (sweep && !small) {
     if (c->local_sort && c->redo_cooldown == 0) {
@@ -985,14 +1002,16 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       uint32_t mm = 0;
       for (double cap_b = 512.0; mm < n_pass && (double)seg_max > cap_b; cap_b *= 256.0) ++mm;
       m_top = c->local_sort_m >= 0 ? std::min<uint32_t>((uint32_t)c->local_sort_m, n_pass) : mm;
-      if (c->autotune && c->local_sort_m < 0 && m_top < n_pass) {
-        tune_key = (uint32_t)c->KC * 4096u + (uint32_t)c->WP * 64u + (uint32_t)std::min(63, ilog2_u64(T_img));
+      if (c->autotune && c->local_sort_m < 0 && (m_top < n_pass || dense_ok)) {
+        tune_key = (uint32_t)c->KC * 4096u + (uint32_t)c->WP * 64u + (uint32_t)std::min(63, ilog2_u64(T_img)) +
+                   (dense_ok ? (1u << 20) : 0u);
         TuneState& ts = c->tune[tune_key];
         // (a recording never explores: its rounds are not timed)
-        tune_cand = ts.best >= 0 ? ts.best : (c->rec ? 0 : ts.tried);
+        tune_cand = ts.best >= 0 ? ts.best : (c->tune_frozen ? 0 : ts.tried);
         if (tune_cand == 1) m_top = std::min(m_top + 1, n_pass);
         if (tune_cand == 2) xr = false;
-        if (ts.best < 0 && !c->rec) {  // exploring: time this round
+        if (tune_cand == 3) dense = true;
+        if (ts.best < 0 && !c->tune_frozen) {  // exploring: time this round
           HIPCHK(c, hipEventRecord(c->tune_ev[0], c->stream), "tune event");
           tune_timed = true;
         }
@@ -1000,7 +1019,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     if (c->redo_cooldown > 0) --c->redo_cooldown;
   }
-  const bool hist_in_expand = sweep && m_top <= kExpandHistPasses;
+  const bool hist_in_expand = sweep && !dense && m_top <= kExpandHistPasses;
   // ---- expand into images
   const size_t eb = c->kb, wbt = c->wb;
   // image buffers: the capacity, or for a small round S chunks of kChunkCap
@@ -1043,6 +1062,8 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   int pre_chunk = -1;       // slot holding the images before the chunk-local sort
   if (small) {
     pre_chunk = 0;
+  } else if (dense) {
+    // no sort: the images are added into the dense slots by the merge below
   } else if (!sweep) {
     QCHK(ensure(c, c->scan_tmp, scan_tmp_words(std::max<uint64_t>(hsize, T_in)) * 8));
     QCHK(ensure(c, c->hist, hsize * 8));
@@ -1086,14 +1107,29 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       fin.seq = ++c->zseq;
       c->zres[2 * (size_t)S + 3] = 0;
     }
-    if (chunk_path) {
+    if (dense) {
+      const uint64_t tps = (per_seg + dense_tile() - 1) / dense_tile();
+      const uint64_t n_tiles = tps * S;
+      QCHK(ensure(c, c->dense_acc, (size_t)(S * per_seg) * 8));
+      QCHK(ensure(c, c->chunk_off, (size_t)(n_tiles + 1) * 8));
+      QCHK(status_words(n_tiles));
+      c->mepoch += 1;
+      HIPCHK(c, launch_dense_merge(c->KC, c->WP, c->ik[0].p, c->iw[0].p, T_img, tl, per_seg, S, c->dense_acc.p,
+                                   entries[0].thr, ctr + kCtrChunk, (uint64_t*)c->mstatus.p, c->mepoch,
+                                   (uint64_t*)c->chunk_off.p, c->pk[slot].p, c->pw[slot].p, T_img,
+                                   (uint64_t*)c->pseg[slot].p, fin, (uint32_t*)c->err.p, c->stream, &c->prof),
+             "dense merge");
+    } else if (chunk_path) {
       const size_t nc = std::max<uint32_t>(tc_chunk.n_blocks, 1);
       QCHK(ensure(c, c->chunk_off, (nc + 1) * 8));
+      QCHK(ensure(c, c->chunk_cnt, nc * 4));
+      QCHK(ensure(c, c->chunk_start, nc * 8));
       QCHK(status_words(nc));
       c->mepoch += 1;
-      const ChunkOut co{ctr + kCtrChunk, (uint64_t*)c->mstatus.p, c->mepoch,
-                        (uint64_t*)c->chunk_off.p, (uint64_t*)c->pseg[slot].p, fin,
-                        small ? (const uint32_t*)c->img_cnt.p : nullptr};
+      const ChunkOut co{ctr + kCtrChunk, (uint64_t*)c->mstatus.p, c->mepoch, (uint32_t*)c->chunk_cnt.p,
+                        (uint64_t*)c->chunk_start.p, (uint64_t*)c->chunk_off.p, c->ik[cur ^ 1].p, c->iw[cur ^ 1].p,
+                        (uint64_t*)c->pseg[slot].p, fin, small ? (const uint32_t*)c->img_cnt.p : nullptr,
+                        c->defer_spins};
       HIPCHK(c, launch_chunk_sort_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, c->pk[slot].p,
                                         c->pw[slot].p, T_img, tc_chunk, n_pass, m_top, pas, sent, co,
                                         (uint32_t*)c->err.p, c->stream, &c->prof), "chunk sort");
@@ -1149,9 +1185,10 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     if (hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]) != hipSuccess) ms = 1e30f;
     if (sorted_again) ms = 1e30f;  // a candidate that overflows chunks is never chosen
     ts.ms[tune_cand] = ms;
-    if (++ts.tried >= TuneState::kCand) {
+    const int n_cand = (tune_key >> 20) & 1u ? TuneState::kCand : TuneState::kCand - 1;
+    if (++ts.tried >= n_cand) {
       ts.best = 0;
-      for (int i = 1; i < TuneState::kCand; ++i)
+      for (int i = 1; i < n_cand; ++i)
         if (ts.ms[i] < ts.ms[ts.best]) ts.best = i;
       c->st.tuned_classes += 1;
     }
@@ -1182,15 +1219,23 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       } else {
         fix(kKExpand, (double)(eb + wbt) * d);
       }
-      if (!small) fix(kKSortHist, (double)eb * d * ((hist_in_expand ? 0 : 1) + (sorted_again ? 1 : 0)));  // upsweeps run
-      if (!small) fix(kKSortScatter, 2.0 * (double)(eb + wbt) * (sorted_again ? n_pass + m_top : m_top) * d);
-      if (m_top < n_pass) fix(kKChunkSort, (double)(eb + wbt) * d);
-      if (!chunk_path) fix(kKMergeWrite, (double)(eb + wbt) * d);
+      if (dense) {
+        fix(kKDense, (4.0 + (double)wbt) * d);
+      } else {
+        if (!small) fix(kKSortHist, (double)eb * d * ((hist_in_expand ? 0 : 1) + (sorted_again ? 1 : 0)));  // upsweeps run
+        if (!small) fix(kKSortScatter, 2.0 * (double)(eb + wbt) * (sorted_again ? n_pass + m_top : m_top) * d);
+        if (m_top < n_pass) fix(kKChunkSort, (double)(eb + wbt) * d);
+        if (!chunk_path) fix(kKMergeWrite, (double)(eb + wbt) * d);
+      }
     }
   }
   if (c->prof.on) {  // the kept terms' bytes, known now
     const double kept = (double)T_out * (double)(eb + wbt);
-    if (!chunk_path && ((c->prof.mask >> kKMergeWrite) & 1u)) c->prof.bytes[kKMergeWrite] += kept;
+    if (dense) {
+      if ((c->prof.mask >> kKDense) & 1u) c->prof.bytes[kKDense] += kept;
+    } else if (!chunk_path && ((c->prof.mask >> kKMergeWrite) & 1u)) {
+      c->prof.bytes[kKMergeWrite] += kept;
+    }
     if (chunk_path && ((c->prof.mask >> kKChunkSort) & 1u)) c->prof.bytes[kKChunkSort] += kept;
   }
   // ---- bookkeeping: one update per output image of every operator (a Clifford operator
@@ -1347,7 +1392,9 @@ qimax_status prebuild_tables(qimax_ctx* c, std::vector<Pass>& passes) {
     jobs[j] = TableJob{(const PermDesc*)(ds + oP) + first, (uint32_t)v.size(), 0, tk, tn};
     p.pre[ab] = ChainTable{tk, tn};
   }
-  HIPCHK(c, launch_pull(c->stage_dev[1], ds, host_bytes, c->stream), "upload chains");
+  const void* src = nullptr;  // (a recording reads its own copy: the staging area is rewritten later)
+  QCHK(rec_src(c, c->stage[1], c->stage_dev[1], host_bytes, &src));
+  HIPCHK(c, launch_pull(src, ds, host_bytes, c->stream), "upload chains");
   HIPCHK(c, launch_build_tables(c->KC, (const TableJob*)(ds + oJ), (uint32_t)chains.size(), c->stream, &c->prof),
          "chain tables");
   return QIMAX_OK;
@@ -2017,10 +2064,14 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     c->small_rounds = !(env && env[0] == '0');
     env = std::getenv("QIMAX_FUSED_EXPAND");  // 0: separate count and expansion launches
     c->fused_expand = !(env && env[0] == '0');
+    env = std::getenv("QIMAX_DENSE");  // 1: dense accumulation wherever it applies; auto: tuned
+    c->dense_mode = (env && env[0] == '1') ? 1 : (env && std::strcmp(env, "auto") == 0) ? 2 : 0;
     env = std::getenv("QIMAX_LOCAL_SORT");  // 0: every digit by global passes
     c->local_sort = !(env && env[0] == '0');
     env = std::getenv("QIMAX_LOCAL_SORT_M");  // force the number of top-digit passes (tests)
     if (env && env[0]) c->local_sort_m = std::atoi(env);
+    env = std::getenv("QIMAX_DEFER_SPINS");  // chunk-local merge: polls before deferring a chunk
+    if (env && env[0]) c->defer_spins = (uint32_t)std::strtoul(env, nullptr, 10);
     env = std::getenv("QIMAX_AUTOTUNE");  // 0: always the heuristic's sort variant
     c->autotune = !(env && env[0] == '0');
   }
@@ -2136,6 +2187,31 @@ qimax_status qimax_graph_record(qimax_ctx* c, const uint8_t* gate, const uint32_
     if (ends[l] > m || (l && ends[l] < ends[l - 1])) return fail(c, QIMAX_EINVAL, "layer ends out of order");
   if (ends.back() != m) return fail(c, QIMAX_EINVAL, "the last layer must end at m");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  // The step runs before it is recorded, with the same sort variants as the recording (no
+  // exploration), until every buffer is large enough for the recording. A step moves the term
+  // buffers between their roles (the current terms and the two pass outputs: a cycle of at
+  // most three), so a buffer can meet a larger role only after up to three runs: the warm-up
+  // ends after three runs in a row that grew nothing.
+  c->tune_frozen = true;
+  auto run_step = [&]() -> qimax_status {
+    QCHK(qimax_reset(c));
+    uint64_t a0 = 0;
+    for (size_t l = 0; l < ends.size(); ++l) {
+      QCHK(qimax_apply_circuit(c, gate + a0, q0 + a0, q1 + a0, theta ? theta + a0 : nullptr, ends[l] - a0));
+      a0 = ends[l];
+    }
+    return flush_pending(c);
+  };
+  for (int runs = 0, quiet = 0; quiet < 3 && runs < 9; ++runs) {
+    const uint64_t gen = c->buf_gen;
+    const qimax_status s0 = run_step();
+    if (s0 != QIMAX_OK) {
+      c->tune_frozen = false;
+      return s0;
+    }
+    quiet = c->buf_gen == gen ? quiet + 1 : 0;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   qimax_graph* g = new qimax_graph;
   g->ctx = c;
   const qimax_stats st0 = c->st;
@@ -2146,13 +2222,7 @@ qimax_status qimax_graph_record(qimax_ctx* c, const uint8_t* gate, const uint32_
   const uint64_t gen0 = c->buf_gen;
   c->rec = g;
   qimax_status s = rec_resume(c);
-  if (s == QIMAX_OK) s = qimax_reset(c);
-  uint64_t a = 0;
-  for (size_t l = 0; l < ends.size() && s == QIMAX_OK; ++l) {
-    s = qimax_apply_circuit(c, gate + a, q0 + a, q1 + a, theta ? theta + a : nullptr, ends[l] - a);
-    a = ends[l];
-  }
-  if (s == QIMAX_OK) s = flush_pending(c);
+  if (s == QIMAX_OK) s = run_step();
   if (s == QIMAX_OK) s = rec_cut(c);
   if (c->rec_capturing) {  // a failure inside a captured part: drop it
     hipGraph_t junk = nullptr;
@@ -2162,6 +2232,7 @@ qimax_status qimax_graph_record(qimax_ctx* c, const uint8_t* gate, const uint32_
   }
   c->rec = nullptr;
   c->prof.on = prof_on;
+  c->tune_frozen = false;
   if (s == QIMAX_OK && c->buf_gen != gen0)
     s = fail(c, QIMAX_ESTATE, "the context's buffers changed while recording: run the step once first");
   if (hipStreamSynchronize(c->stream) != hipSuccess && s == QIMAX_OK) s = fail(c, QIMAX_EDEVICE, "recorded step failed");
@@ -2187,6 +2258,8 @@ qimax_status qimax_graph_record(qimax_ctx* c, const uint8_t* gate, const uint32_
     return s;
   }
   g->gen = c->buf_gen;
+  g->epoch_end = c->epoch;
+  g->mepoch_end = c->mepoch;
   g->keys = c->keys; g->w = c->w; g->seg = c->seg;
   for (int i = 0; i < 2; ++i) { g->pk[i] = c->pk[i]; g->pw[i] = c->pw[i]; g->pseg[i] = c->pseg[i]; }
   g->h_seg = c->h_seg;
@@ -2232,6 +2305,10 @@ qimax_status qimax_graph_launch(qimax_graph* g) {
   c->T = g->T;
   c->st.terms = c->T;
   c->pending.clear();
+  // the replay leaves status words tagged with the recorded epochs: later rounds count on
+  // from above them
+  c->epoch = std::max(c->epoch, g->epoch_end);
+  c->mepoch = std::max(c->mepoch, g->mepoch_end);
   c->st.passes += g->st_delta.passes;
   c->st.term_updates += g->st_delta.term_updates;
   c->st.images += g->st_delta.images;
@@ -2415,7 +2492,8 @@ qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_
   hipStream_t st = a->stream;
   hipError_t e = hipMemcpyAsync(m, host_u64.data(), ou, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !segs.empty()) e = hipMemcpyAsync(m + os, segs.data(), segs.size() * 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemsetAsync(acc, 0, total - oacc, st);
+  // the sums and counters start at zero (a fill kernel: no memset node if the stream is captured)
+  if (e == hipSuccess) e = launch_fill_u64((uint64_t*)acc, (total - oacc) / 8, 0ull, st);
   // pass 0 over a's terms (searched in b), pass 1 over b's (the reference) searched in a
   if (e == hipSuccess)
     e = launch_compare(a->KC, a->WP, b->WP, a->keys.p, a->w.p, b->keys.p, b->w.p, d_boff, d_beg, d_end, d_seg,
@@ -2539,7 +2617,7 @@ void qimax_destroy(qimax_ctx* c) {
   DevBuf* bufs[] = {&c->keys, &c->w, &c->seg, &c->pk[0], &c->pk[1], &c->pw[0], &c->pw[1], &c->pseg[0],
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
-                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->img_cnt,
+                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->img_cnt, &c->dense_acc, &c->chunk_cnt, &c->chunk_start,
                     &c->chunk_off};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);

@@ -130,7 +130,7 @@ enum : uint32_t {
 // algorithmic bytes each launch must move (what the roofline is measured against).
 enum KernelKind : int {
   kKInit, kKCount, kKScan, kKExpand, kKSortHist, kKSortScatter, kKMergeCount, kKMergeWrite, kKCompose, kKChunkSort,
-  kKCountExpand, kKNum
+  kKCountExpand, kKDense, kKNum
 };
 const char* kernel_kind_name(int k);
 
@@ -242,9 +242,11 @@ hipError_t launch_merge(int KC, int WP, int fp64_acc, const void* keys_in, const
 // are the tiles of tc (at most kChunkCap/2 images, segment-aligned). Each chunk is sorted in
 // LDS and its runs of equal keys summed and pruned (|sum| > its pass's thr); chunks are claimed
 // in order (co.ticket) and each writes its kept runs straight to its output offset, found by
-// a decoupled look-back over the earlier chunks' kept counts (co.status, tagged co.epoch;
-// co.chunk_off receives every chunk's offset, tc.n_blocks + 1 words). A one-block launch then
-// writes seg_off_out and the packed readback area (co.fin). Sets kErrRedo when a bucket does
+// a decoupled look-back over the earlier chunks' kept counts (co.status, tagged co.epoch); a
+// chunk whose earlier chunks are slow to publish is deferred instead: it leaves its runs at
+// the front of its own range of co.tmp_keys / co.tmp_w. A one-block launch then scans the
+// counts into co.chunk_off and writes seg_off_out and the packed readback area (co.fin), and a
+// last launch moves the deferred chunks' runs. Sets kErrRedo when a bucket does
 // not fit a chunk (the outputs are then not valid). With m = 0 every chunk must be a whole
 // segment (at most kChunkCap elements). co.img_cnt (S words, or null): the image counts of
 // the segments, scanned into the readback area instead of fin.img_seg. co.ticket must be zero
@@ -253,15 +255,33 @@ struct ChunkOut {
   uint32_t* ticket;
   uint64_t* status;
   uint64_t epoch;
-  uint64_t* chunk_off;
+  uint32_t* chunk_cnt;     // kept terms per chunk
+  uint64_t* chunk_start;   // where a deferred chunk left its runs in tmp (~0: written in place)
+  uint64_t* chunk_off;     // output offset per chunk (tc.n_blocks + 1)
+  void* tmp_keys;          // scratch arrays of the image length
+  void* tmp_w;
   uint64_t* seg_off_out;
   MergeFin fin;
   const uint32_t* img_cnt;
+  uint32_t defer_spins;    // look-back polls before a chunk is deferred
 };
 hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* keys_out,
                                    void* w_out, uint64_t T, const Tiling& tc, uint32_t n_pass, uint32_t m,
                                    const PassArgs* pas, const uint32_t* seg_entry, const ChunkOut& co, uint32_t* err,
                                    hipStream_t s, Prof* prof = nullptr);
+
+// Dense accumulation instead of the sort and merge (see k_dense_scatter): the T_img images
+// (32-bit keys, every key < per_seg) of segments tiled by tl are added into acc (S * per_seg
+// 64-bit fixed-point slots, cleared here), the slots are compacted in key order into
+// keys_out / w_out (|sum| > thr, nonzero), tiles claimed through *ticket (zero at launch) with
+// look-back on status (tagged epoch; dense_tile() slots per tile, S * ceil(per_seg /
+// dense_tile()) tiles, tile_off one word more), and one block writes seg_off_out and fin.
+size_t dense_tile();
+hipError_t launch_dense_merge(int KC, int WP, const void* keys_in, const void* w_in, uint64_t T_img, const Tiling& tl,
+                              uint64_t per_seg, uint32_t S, void* acc, double thr, uint32_t* ticket, uint64_t* status,
+                              uint64_t epoch, uint64_t* tile_off, void* keys_out, void* w_out, uint64_t out_cap,
+                              uint64_t* seg_off_out, const MergeFin& fin, uint32_t* err, hipStream_t s,
+                              Prof* prof = nullptr);
 
 // Compile chains of permutation ops into ChainTables, one job per chain (jobs in device memory).
 hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hipStream_t s, Prof* prof = nullptr);

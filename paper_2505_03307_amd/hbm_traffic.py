@@ -27,15 +27,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 # library profiler name -> pattern of the kernel symbol(s) it covers
 KERNELS = {
-    "count": r"k_count",
-    "scan": r"k_scan_",
-    "expand": r"k_expand",
-    "sort_hist": r"k_sort_(upsweep|hist)",
-    "sort_scatter": r"k_sort_scatter",
-    "chunk_sort": r"k_chunk_sort",
-    "merge_count": r"k_merge<[^,]+, [^,]+, 0>",
-    "merge_write": r"k_merge<[^,]+, [^,]+, [12]>|k_chunk_compact",
-    "copy": r"k_copy_u64",
+    "count": r"\bk_count_scan",
+    "count_expand": r"\bk_count_expand",
+    "expand": r"\bk_expand",
+    "sort_hist": r"\bk_sort_(upsweep|hist)",
+    "sort_scatter": r"\bk_sort_scatter",
+    "chunk_sort": r"\bk_chunk_sort",
+    "dense_merge": r"\bk_dense_(scatter|compact)",
+    "merge_count": r"\bk_merge<[^,]+, [^,]+, 0>",
+    "merge_write": r"\bk_merge<[^,]+, [^,]+, [12]>|\bk_chunk_compact",
+    "copy": r"\bk_copy_u64",
 }
 
 

@@ -63,17 +63,24 @@ def test_replay_refused_after_buffers_change():
     small = W.c2_clifford_rz(seed=1, n=16, depth=40, n_rz=6)
     big = W.c2_clifford_rz(seed=2, n=16, depth=120, n_rz=30)
     with Simulator(16) as s:
-        _eager(s, small)
+        want = _eager(s, small)
         g = s.record_step(small)
         try:
+            g.launch()
+            assert _same(s.generators(), want)
             _eager(s, big)  # grows the buffers
             with pytest.raises(QimaxError, match="ESTATE"):
                 g.launch()
         finally:
             g.close()
-        # a context whose buffers are too small for the step refuses to record it
-        with Simulator(16) as s2:
-            with pytest.raises(QimaxError, match="ESTATE"):
-                s2.record_step(big)
-            assert s2.num_terms() == 16  # reset after the failed recording
-            assert _same(_eager(s2, small), _eager(s, small))
+    # a fresh context: the record call sizes its buffers with a first run of the step
+    with Simulator(16) as ref:
+        want_big = _eager(ref, big)
+    with Simulator(16) as s2:
+        g2 = s2.record_step(big)
+        try:
+            assert _same(s2.generators(), want_big)
+            g2.launch()
+            assert _same(s2.generators(), want_big)
+        finally:
+            g2.close()
