@@ -199,6 +199,18 @@ qimax_status qimax_prob_zero_all(qimax_ctx* ctx, double* p0);
 qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
                            uint64_t* n_tau_diff);
 
+/* qimax_compare for callers that cannot allocate device memory (code under stream capture,
+ * serving loops that must not call hipMalloc): same arguments, same results. Instead of
+ * allocating, the tile arrays, sums and counters of the comparison live in a fixed 4 MiB
+ * device array that every GPU the library runs on holds until the process ends; that bounds
+ * the two contexts' tiles (4096 terms each, per generator) to roughly 200,000 together, about
+ * 8e8 terms: beyond, QIMAX_ETOOLARGE. Deferred operators are refused, not applied (applying
+ * them allocates): QIMAX_ESTATE until qimax_flush has run on both contexts. Every call on a
+ * GPU uses that GPU's one array: calls that overlap on the same GPU (from several threads)
+ * race and must be serialised by the caller. Device memory is never allocated or freed. */
+qimax_status qimax_compare_noalloc(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
+                                   uint64_t* n_tau_diff);
+
 /* Counters since qimax_create (host-side bookkeeping, no device work). */
 typedef struct {
   uint64_t terms;          /* current number of terms                                     */

@@ -2445,17 +2445,34 @@ qimax_status qimax_get_generators_xz(qimax_ctx* c, uint64_t* gen_off, uint64_t* 
   return QIMAX_OK;
 }
 
-qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
-                           uint64_t* n_tau_diff) {
+namespace {
+
+// The comparison of qimax_compare. With a scratch area (no_alloc), the tile arrays and the
+// accumulators live there and nothing is allocated on the device; deferred operators are then
+// refused instead of applied (applying them allocates).
+qimax_status compare_impl(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
+                          uint64_t* n_tau_diff, bool no_alloc) {
   if (!a || !b || !diff_norm || !ref_norm || !n_tau_diff) return QIMAX_EINVAL;
   if (a->n != b->n) return fail(a, QIMAX_EINVAL, "compare: contexts of different n");
   if (a->device != b->device) return fail(a, QIMAX_EINVAL, "compare: contexts on different devices");
   if (a->broken || b->broken) return fail(a, QIMAX_ESTATE, "context unusable after an earlier device error");
-  QCHK(flush_pending(a));
-  {
+  if (no_alloc) {
+    if (!a->pending.empty() || !b->pending.empty())
+      return fail(a, QIMAX_ESTATE, "compare_noalloc: a context holds deferred operators (call qimax_flush first)");
+  } else {
+    QCHK(flush_pending(a));
     qimax_status sb = flush_pending(b);
     if (sb != QIMAX_OK) return fail(a, sb, std::string("compare: ") + b->last_error);
   }
+  int prev_dev = -1;
+  HIPCHK(a, hipGetDevice(&prev_dev), "hipGetDevice");
+  if (prev_dev != a->device) HIPCHK(a, hipSetDevice(a->device), "hipSetDevice");
+  struct Restore {
+    int dev, prev;
+    ~Restore() {
+      if (prev != dev) (void)hipSetDevice(prev);
+    }
+  } restore{a->device, prev_dev};
   HIPCHK(a, hipStreamSynchronize(a->stream), "hipStreamSynchronize");
   HIPCHK(a, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   const uint32_t n = a->n;
@@ -2477,7 +2494,13 @@ qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_
   const size_t ou = host_u64.size() * 8, os = align256(ou), oacc = os + align256(std::max<size_t>(segs.size(), 1) * 4);
   const size_t ocnt = oacc + align256((size_t)n * 16), total = ocnt + align256((size_t)n * 8);
   void* mem = nullptr;
-  if (hipMalloc(&mem, total) != hipSuccess) {
+  if (no_alloc) {
+    size_t cap = 0;
+    HIPCHK(a, compare_scratch(a->device, &mem, &cap), "compare_noalloc scratch");
+    if (total > cap)
+      return fail(a, QIMAX_ETOOLARGE, "compare_noalloc: " + std::to_string(total) + " bytes of tiles and sums exceed the " +
+                                          std::to_string(cap) + "-byte scratch (" + std::to_string(nt) + " tiles)");
+  } else if (hipMalloc(&mem, total) != hipSuccess) {
     (void)hipGetLastError();
     return fail(a, QIMAX_ENOMEM, "compare: hipMalloc failed");
   }
@@ -2506,14 +2529,26 @@ qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_
   if (e == hipSuccess) e = hipMemcpyAsync(h_acc.data(), acc, (size_t)n * 16, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipMemcpyAsync(h_cnt.data(), cnt, (size_t)n * 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(mem);
-  if (e != hipSuccess) return hip_fail(a, e, "compare");
+  if (!no_alloc) (void)hipFree(mem);
+  if (e != hipSuccess) return hip_fail(a, e, no_alloc ? "compare_noalloc" : "compare");
   for (uint32_t j = 0; j < n; ++j) {
     diff_norm[j] = std::sqrt(h_acc[2 * j]);
     ref_norm[j] = std::sqrt(h_acc[2 * j + 1]);
     n_tau_diff[j] = h_cnt[j];
   }
   return QIMAX_OK;
+}
+
+}  // namespace
+
+qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
+                           uint64_t* n_tau_diff) {
+  return compare_impl(a, b, tau, diff_norm, ref_norm, n_tau_diff, false);
+}
+
+qimax_status qimax_compare_noalloc(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
+                                   uint64_t* n_tau_diff) {
+  return compare_impl(a, b, tau, diff_norm, ref_norm, n_tau_diff, true);
 }
 
 qimax_status qimax_get_stats(const qimax_ctx* c, qimax_stats* out) {

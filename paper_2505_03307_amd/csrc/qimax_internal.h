@@ -368,6 +368,9 @@ hipError_t launch_keys_to_xz(int KC, const void* keys, uint64_t T, uint32_t n, u
 // compare_tile() elements of side a, each inside one segment; acc[2s] / acc[2s+1] and cnt[s]
 // accumulate (zeroed by the caller).
 size_t compare_tile();
+// The fixed device array of qimax_compare_noalloc on `device` (which must be current): its
+// address on that device (looked up once per device) and its size in bytes.
+hipError_t compare_scratch(int device, void** ptr, size_t* bytes);
 hipError_t launch_compare(int KC, int WPa, int WPb, const void* ka, const void* wa, const void* kb, const void* wb,
                           const uint64_t* b_off, const uint64_t* t_begin, const uint64_t* t_end, const uint32_t* t_seg,
                           uint32_t n_tiles, int count_ref, double tau, double* acc, unsigned long long* cnt,

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "qimax_internal.h"
 
@@ -289,6 +290,34 @@ hipError_t launch_keys_to_xz(int KC, const void* keys, uint64_t T, uint32_t n, u
 }
 
 size_t compare_tile() { return (size_t)kCmpTile; }
+
+// Device memory of qimax_compare_noalloc (the comparison's tile arrays, accumulators and
+// counters), held by every GPU the library runs on until the process ends. Host code never
+// passes the array's name to a kernel or copy: it uses the address hipGetSymbolAddress
+// returns for the current device.
+constexpr size_t kCompareScratchBytes = (size_t)4 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kCompareScratchBytes];
+
+hipError_t compare_scratch(int device, void** ptr, size_t* bytes) {
+  static std::mutex mu;
+  static void* addr[kScratchDevices] = {};
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  *bytes = kCompareScratchBytes;
+  return hipSuccess;
+}
 
 hipError_t launch_compare(int KC, int WPa, int WPb, const void* ka, const void* wa, const void* kb, const void* wb,
                           const uint64_t* b_off, const uint64_t* t_begin, const uint64_t* t_end, const uint32_t* t_seg,

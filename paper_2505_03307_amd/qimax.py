@@ -88,7 +88,7 @@ EXPORTS = ["qimax_batch_create", "qimax_batch_submit", "qimax_batch_step", "qima
            "qimax_batch_last_error", "qimax_batch_destroy",
            "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_flush", "qimax_graph_record", "qimax_graph_launch", "qimax_graph_destroy", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
            "qimax_num_terms", "qimax_get_generators", "qimax_get_generators_xz", "qimax_expect",
-           "qimax_expect_many", "qimax_prob_zero_all", "qimax_compare", "qimax_get_stats", "qimax_sync",
+           "qimax_expect_many", "qimax_prob_zero_all", "qimax_compare", "qimax_compare_noalloc", "qimax_get_stats", "qimax_sync",
            "qimax_profile", "qimax_profile_only", "qimax_profile_read", "qimax_copy_probe", "qimax_last_error", "qimax_destroy"]
 
 _lib = None
@@ -133,6 +133,7 @@ def load():
     lib.qimax_expect_many.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t, dp]
     lib.qimax_prob_zero_all.argtypes = [P, dp]
     lib.qimax_compare.argtypes = [P, P, ctypes.c_double, dp, dp, u64p]
+    lib.qimax_compare_noalloc.argtypes = [P, P, ctypes.c_double, dp, dp, u64p]
     lib.qimax_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.qimax_sync.argtypes = [P]
     lib.qimax_profile.argtypes = [P, ctypes.c_int]
@@ -357,13 +358,15 @@ class Simulator:
         self._check(load().qimax_prob_zero_all(self._h, _p(out, ctypes.c_double)))
         return out
 
-    def compare(self, ref: "Simulator", tau: float = 1e-6):
-        """Per generator (||w_self - w_ref||_2, ||w_ref||_2, keys with |w| > tau on one side only)."""
+    def compare(self, ref: "Simulator", tau: float = 1e-6, no_alloc: bool = False):
+        """Per generator (||w_self - w_ref||_2, ||w_ref||_2, keys with |w| > tau on one side only).
+        no_alloc: the variant that allocates no device memory (qimax_compare_noalloc)."""
         d = np.zeros(self.n, dtype=np.float64)
         r = np.zeros(self.n, dtype=np.float64)
         k = np.zeros(self.n, dtype=np.uint64)
-        self._check(load().qimax_compare(self._h, ref._h, float(tau), _p(d, ctypes.c_double), _p(r, ctypes.c_double),
-                                         _p(k, ctypes.c_uint64)))
+        fn = load().qimax_compare_noalloc if no_alloc else load().qimax_compare
+        self._check(fn(self._h, ref._h, float(tau), _p(d, ctypes.c_double), _p(r, ctypes.c_double),
+                       _p(k, ctypes.c_uint64)))
         return d, r, k
 
     def stats(self) -> dict:
