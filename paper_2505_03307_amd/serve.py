@@ -9,7 +9,8 @@ same trace one circuit at a time on a single-circuit context.
 
 The footprint predictor follows the paper's feasibility bound (Sec. IV: the number of
 Pauli strings a run can hold is limited by memory / (bytes per string)): predicted bytes =
-peak images in flight x bytes per image + terms x bytes per term, with the peak image
+peak images in flight x bytes per image + terms x bytes per term + 1 MiB of buffers of
+fixed size, with the peak image
 count taken from the closed form of the hardware-efficient ansatz when the circuit is of
 that family (3n terms after one layer; 3^(n+1) + 9n - 21 after two, from 4*3^n + 9n - 12
 images), and otherwise from the bound min(4^n - 1, 2^(#non-Clifford gates)) per generator.
@@ -57,6 +58,9 @@ def key_class(n: int) -> int:
     return 16 if n <= 16 else (32 if n <= 32 else 64)
 
 
+_FIXED_BYTES = 1 << 20
+
+
 def predict_bytes(c: W.Circuit, precision: int = 32, batch_max_n: int | None = None) -> int:
     cls = batch_max_n or key_class(c.n)
     kb = 4 if cls <= 16 else (8 if cls <= 32 else 16)
@@ -65,8 +69,9 @@ def predict_bytes(c: W.Circuit, precision: int = 32, batch_max_n: int | None = N
     # the library's buffers for a round of `img` images (each grown with 25% headroom): two
     # key/weight image buffers for the sort, and three term arrays sized by the images (the
     # generators and the two output slots a call alternates between); per input term its A-chain
-    # key, sign byte and 8-byte image offset
-    return int(1.25 * (5 * img * (kb + wb) + terms * (kb + 9)))
+    # key, sign byte and 8-byte image offset; plus a round's buffers of fixed size (tilings,
+    # look-back status words, chain tables, staging: 0.1-0.2 MB for the small ansatz circuits)
+    return int(1.25 * (5 * img * (kb + wb) + terms * (kb + 9))) + _FIXED_BYTES
 
 
 @dataclasses.dataclass

@@ -227,3 +227,25 @@ def test_batch_with_more_segments_than_a_tiling_block_holds():
             ref = alone(c)
             for x, y in zip(got, ref):
                 assert np.array_equal(x, y), c.name
+
+
+@pytest.mark.parametrize("case", ["hea12_1", "hea12_2", "hea16_1", "hea14_2", "c2_24"])
+def test_predicted_footprint_covers_device_memory(case):
+    """The server admits a request by serve.predict_bytes: for circuits of the served family
+    (and one Clifford+Rz circuit), the device memory a batch grows by while it runs that one
+    request alone stays below the prediction."""
+    from paper_2505_03307_amd import serve
+    c = {"hea12_1": lambda: W.c3_hea(seed=11, n=12, layers=1),
+         "hea12_2": lambda: W.c3_hea(seed=12, n=12, layers=2),
+         "hea16_1": lambda: W.c3_hea(seed=13, n=16, layers=1),
+         "hea14_2": lambda: W.c3_hea(seed=14, n=14, layers=2),
+         "c2_24": lambda: W.c2_clifford_rz(seed=15, n=24, depth=120, n_rz=14)}[case]()
+    cls = serve.key_class(c.n)
+    with Batch(precision=32, max_n=cls) as b:
+        a0 = b.info()["alloc_bytes"]
+        b.submit(c)
+        b.run()
+        peak = b.info()["peak_bytes"]
+    need = serve.predict_bytes(c, 32, cls)
+    say("footprint", case, "grew", peak - a0, "predicted", need)
+    assert peak - a0 <= need
