@@ -40,8 +40,7 @@ __device__ __forceinline__ K apply_perm(K key, const PermDesc& p, uint32_t& neg)
   return key;
 }
 
-// Phase exponent (mod 4) of the product a*b of two Pauli strings given as digit keys:
-// per qubit XY = iZ, YZ = iX, ZX = iY (+1) and the reverse orders (-1).
+// Mask of the low bit of every 2-bit digit.
 template <typename K>
 __device__ __forceinline__ K even_bits() {
   if constexpr (sizeof(K) > 8) return ((K)0x5555555555555555ull << 64) | (K)0x5555555555555555ull;
@@ -55,34 +54,37 @@ __device__ __forceinline__ int popc_k(K x) {
   else return __popc(x);
 }
 
+// Number of Y digits of a key (hi bit set, lo bit clear).
 template <typename K>
-__device__ __forceinline__ uint32_t product_phase(K a, K b) {
-  const K kEven = even_bits<K>();
-  const K al = a & kEven, ah = (a >> 1) & kEven;
-  const K bl = b & kEven, bh = (b >> 1) & kEven;
-  const K xa = al & ~ah, ya = ah & ~al, za = ah & al;
-  const K xb = bl & ~bh, yb = bh & ~bl, zb = bh & bl;
-  const K plus = (xa & yb) | (ya & zb) | (za & xb);
-  const K minus = (xa & zb) | (ya & xb) | (za & yb);
-  return (uint32_t)(popc_k(plus) - popc_k(minus)) & 3u;
+__device__ __forceinline__ uint32_t y_count(K key) {
+  return (uint32_t)popc_k((key >> 1) & ~key & even_bits<K>());
 }
 
-// Image of a key under a compiled Clifford chain (tables staged in LDS by the caller).
+// Image of a key under a compiled Clifford chain (tables staged in LDS by the caller): the
+// product of the images of its bytes. Entry b of byte k holds the image key and, in tn, its
+// sign (bit 0) and its number of Y digits mod 4 (bits 1-2). With x = lo ^ hi and z = hi the
+// planes of a digit key and P = i^(x.z) X^x Z^z, an ordered product of images P_j is
+// i^e P(xor of the keys) with e = sum_j y_j + 2 sum_{i<j} z_i.x_j - y(product) (mod 4); the
+// images commute, so e is 0 or 2. The cross term only matters mod 2: the z plane of the
+// product so far ANDed with each image's x plane, accumulated by XOR, counted once.
 template <typename K>
 __device__ __forceinline__ K apply_table(K key, const K* __restrict__ tk, const uint8_t* __restrict__ tn,
                                          uint32_t& neg) {
-  K acc = 0;
-  uint32_t ph = 0;
+  K acc = 0, cross = 0;
+  uint32_t e = 0;
 #pragma unroll
   for (int k = 0; k < (int)sizeof(K); ++k) {
     const uint32_t b = (uint32_t)(key >> (8 * k)) & 0xFFu;
     if (b == 0) continue;  // four identities map to identity
     const K img = tk[k * 256 + b];
-    neg ^= tn[k * 256 + b];
-    ph += product_phase(acc, img);
+    const uint32_t t = tn[k * 256 + b];
+    neg ^= t & 1u;
+    e += t >> 1;
+    cross ^= (acc >> 1) & (img ^ (img >> 1));
     acc ^= img;
   }
-  neg ^= (ph >> 1) & 1u;  // images commute: the product's phase is +1 or -1
+  e += 2u * ((uint32_t)popc_k(cross & even_bits<K>()) & 1u) - y_count(acc);
+  neg ^= (e >> 1) & 1u;
   return acc;
 }
 
@@ -315,6 +317,24 @@ __device__ __forceinline__ uint64_t wave_upper_bound(const uint64_t* __restrict_
   return wave_first_true(lo, hi, [&](uint64_t i) { return a[i] > x; });
 }
 
+// q = r / c and rem = r - q c for an image count 1 <= c <= 16, with m = ceil(2^32 / c): the
+// high word of r m exceeds r / c by r (m - 2^32 / c) / 2^32 < 1, so it is the quotient or one
+// more, which one correction step settles (integer division has no instruction on the chip).
+__device__ __forceinline__ uint32_t div_count(uint32_t r, uint32_t c, uint32_t m, uint32_t& rem) {
+  if (c == 1) {
+    rem = 0;
+    return r;
+  }
+  uint32_t q = __umulhi(r, m);
+  int32_t k = (int32_t)(r - q * c);
+  if (k < 0) {
+    --q;
+    k += (int32_t)c;
+  }
+  rem = (uint32_t)k;
+  return q;
+}
+
 // Image number r (mixed radix over the operators' column counts, first operator fastest) of
 // a term under the expanding operators: key and weight updated in place.
 template <typename K, int WP>
@@ -325,9 +345,8 @@ __device__ __forceinline__ void expand_ops(K& key, typename WTraits<WP>::W& wv, 
     const uint32_t d = get_d(key, E.pos);
     const uint32_t c = E.cnt[d];
     if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
-    const uint32_t q = r / c;
-    const uint32_t k = r - q * c;
-    r = q;
+    uint32_t k;
+    r = div_count(r, c, E.rcp[d], k);
     key = set_d(key, E.pos, E.out[d][k]);
     if constexpr (WP == 64) wv *= E.val[d][k]; else wv *= E.valf[d][k];
   }
@@ -336,9 +355,8 @@ __device__ __forceinline__ void expand_ops(K& key, typename WTraits<WP>::W& wv, 
     const uint32_t in = local2(key, E.pa, E.pb);
     const uint32_t c = E.cnt[in];
     if (c == 0) { atomicOr(err, kErrIndex | kErrExpand); break; }
-    const uint32_t q = r / c;
-    const uint32_t k = r - q * c;
-    r = q;
+    uint32_t k;
+    r = div_count(r, c, E.rcp[in], k);
     const uint32_t o = E.out[in][k];
     key = set_d(key, E.pa, o >> 2);
     key = set_d(key, E.pb, o & 3u);
@@ -1209,7 +1227,8 @@ __global__ void k_merge_publish(Tiling tl, const uint64_t* __restrict__ blk_off,
 // start of nominal tile c (the segment start for its first tile), so chunks are runs of whole
 // buckets; each chunk (at most kChunkCap elements) is sorted in LDS, stably, which completes a
 // stable sort of the segment: stable 8-bit passes bring equal top m+1 digits together within
-// each bucket, and the resulting small groups are sorted by insertion. A bucket too large for
+// each bucket, and each element of the resulting small groups moves to its rank in its group.
+// A bucket too large for
 // a chunk raises kErrRedo (not an error: the caller sorts the round again with global passes
 // only).
 constexpr int kChunkBlock = 512;  // threads of a chunk-local sort (8 waves)
@@ -1229,13 +1248,18 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   __shared__ uint64_t scan_sh[kWaves];
   __shared__ uint64_t cb[2];
   __shared__ uint32_t nb_sh, fallback_sh;
+  __shared__ uint32_t gmax_sh[kWaves], gmin_sh[kWaves];
   __shared__ __align__(16) uint8_t vary_sh[kWaves * sizeof(K)];
   __shared__ uint32_t blk_sh;
   __shared__ uint64_t base_sh;
-  // chunks are claimed in order, so every chunk a look-back waits for is running or done
-  if (threadIdx.x == 0) blk_sh = atomicAdd(co.ticket, 1u);
-  __syncthreads();
-  const uint32_t blk = blk_sh;
+  // a look-back that waits claims chunks in order (so that every chunk it waits for is
+  // running or done); one that only looks once takes the block's own index
+  uint32_t blk = blockIdx.x;
+  if (co.defer_spins) {
+    if (threadIdx.x == 0) blk_sh = atomicAdd(co.ticket, 1u);
+    __syncthreads();
+    blk = blk_sh;
+  }
   const uint32_t nc = tc.n_dev ? *tc.n_dev : tc.n_blocks;
   if (blk >= nc) return;
   // The chunk's output offset: publish its kept count and look back over the earlier chunks
@@ -1444,8 +1468,8 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   // Few buckets: one pass by the digit just below the bucket digits, one by the bucket number
   // (skipped for a single bucket), which leaves groups of equal top m+1 digits in order.
   // Many buckets (fewer than 16 elements each on average): the buckets are the groups. The
-  // groups are then sorted by insertion (stable); a group above kMaxGroup elements sends the
-  // chunk through stable passes over every digit instead (same order from here).
+  // groups are then sorted by ranking inside each group (stable); a group above kMaxGroup
+  // elements sends the chunk through stable passes over every digit instead (same order).
   constexpr uint32_t kMaxGroup = 32;
   const bool two_pass = nb <= (uint32_t)kRadix && m > 0 && m < n_pass;
   const uint32_t g_shift = two_pass ? top_shift - 8u : top_shift;
@@ -1454,21 +1478,97 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
     radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> g_shift); }, kRadixBits);
     if (nb > 1) radix_pass([&](K, uint32_t bkt) { return bkt; }, 32u - (uint32_t)__clz((int)(nb - 1)));
   }
-  if (threadIdx.x == 0) fallback_sh = 0;
-  __syncthreads();
-  // group lengths at their heads (sbk is free now), all found before any group is sorted
-  for (uint32_t j = threadIdx.x; j < n; j += kChunkBlock) {
-    uint32_t len = 0;
-    if (j == 0 || gkey(sk[j]) != gkey(sk[j - 1])) {
-      const K g = gkey(sk[j]);
-      uint32_t e = j + 1;
-      while (e < n && e - j <= kMaxGroup && gkey(sk[e]) == g) ++e;
-      len = e - j;
-      if (len > kMaxGroup) fallback_sh = 1;
+  // Groups of equal gkey: thread t holds the sorted positions [t*kItems, (t+1)*kItems). Every
+  // element finds its group [gs, ge) from a block max-scan of the group heads before it and a
+  // min-scan of the heads after it (positions past n count as heads); with every group at most
+  // kMaxGroup long, it counts the smaller keys of its group (equal keys by position: stable) and
+  // moves to gs + that rank. A longer group sends the chunk to the fallback.
+  {
+    const uint32_t j0 = threadIdx.x * kItems;
+    K kk[kItems];
+    uint16_t ii[kItems];
+    bool hd[kItems];
+    const K prevk = (j0 > 0 && j0 - 1 < n) ? sk[j0 - 1] : (K)0;
+#pragma unroll
+    for (int t = 0; t < kItems; ++t) {
+      const uint32_t j = j0 + t;
+      const bool valid = j < n;
+      kk[t] = valid ? sk[j] : (K)0;
+      ii[t] = valid ? sidx[j] : (uint16_t)0;
+      hd[t] = !valid || j == 0 || gkey(kk[t]) != gkey(t ? kk[t - 1] : prevk);
     }
-    sbk[j] = (uint16_t)len;
+    uint32_t last_head = 0, first_head = kChunkCap;
+#pragma unroll
+    for (int t = 0; t < kItems; ++t)
+      if (hd[t]) last_head = j0 + t;
+#pragma unroll
+    for (int t = kItems - 1; t >= 0; --t)
+      if (hd[t]) first_head = j0 + t;
+    // wave scans: the last head in earlier lanes (max), the first head in later lanes (min)
+    uint32_t lo_max = last_head, hi_min = first_head;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t u = __shfl_up(lo_max, d, 64);
+      const uint32_t v = __shfl_down(hi_min, d, 64);
+      if (lane >= d) lo_max = max(lo_max, u);
+      if (lane + d < 64) hi_min = min(hi_min, v);
+    }
+    if (lane == 63) gmax_sh[wid] = lo_max;
+    if (lane == 0) gmin_sh[wid] = hi_min;
+    if (threadIdx.x == 0) fallback_sh = 0;
+    uint32_t before = __shfl_up(lo_max, 1, 64), after = __shfl_down(hi_min, 1, 64);
+    if (lane == 0) before = 0;
+    if (lane == 63) after = kChunkCap;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      if (w < wid) before = max(before, gmax_sh[w]);
+      if (w > wid) after = min(after, gmin_sh[w]);
+    }
+    // group bounds packed per item: start | end << 16 (positions below 2^13)
+    uint32_t gb[kItems];
+    uint32_t run = before;
+#pragma unroll
+    for (int t = 0; t < kItems; ++t) {
+      if (hd[t]) run = j0 + t;
+      gb[t] = run;
+    }
+    run = after;
+#pragma unroll
+    for (int t = kItems - 1; t >= 0; --t) {
+      gb[t] |= min(run, n) << 16;
+      if (hd[t]) run = j0 + t;
+    }
+    bool big = false;
+#pragma unroll
+    for (int t = 0; t < kItems; ++t)
+      if (j0 + t < n && (gb[t] >> 16) - (gb[t] & 0xFFFFu) > kMaxGroup) big = true;
+    if (big) fallback_sh = 1;
+    __syncthreads();
+    if (!fallback_sh) {
+      uint32_t dst[kItems];
+#pragma unroll
+      for (int t = 0; t < kItems; ++t) {
+        const uint32_t j = j0 + t, gs = gb[t] & 0xFFFFu, ge = gb[t] >> 16;
+        uint32_t r = 0;
+        if (j < n && ge - gs > 1)
+          for (uint32_t i = gs; i < ge; ++i) {
+            const K v = sk[i];
+            r += (v < kk[t] || (v == kk[t] && i < j)) ? 1u : 0u;
+          }
+        dst[t] = gs + r;
+      }
+      __syncthreads();  // every rank counted before any element moves
+#pragma unroll
+      for (int t = 0; t < kItems; ++t) {
+        if (j0 + t < n && dst[t] != j0 + t) {
+          sk[dst[t]] = kk[t];
+          sidx[dst[t]] = ii[t];
+        }
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
   if (fallback_sh) {
     // stable passes over the digits that vary inside the chunk (a constant digit leaves a
     // stable pass's order unchanged)
@@ -1477,58 +1577,56 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
     vary = block_or<kChunkBlock>(vary, (K*)vary_sh);
     for (uint32_t p = 0; p < n_pass; ++p)
       if ((uint32_t)(vary >> (8u * p)) & 255u) radix_pass([&](K key, uint32_t) { return (uint32_t)(key >> (8u * p)); }, kRadixBits);
-  } else {
-    for (uint32_t j = threadIdx.x; j < n; j += kChunkBlock) {
-      const uint32_t e = j + sbk[j];
-      for (uint32_t i = j + 1; i < e; ++i) {  // insertion sort of the group [j, e), stable
-        const K kv = sk[i];
-        const uint16_t iv = sidx[i];
-        uint32_t t = i;
-        while (t > j && sk[t - 1] > kv) {
-          sk[t] = sk[t - 1];
-          sidx[t] = sidx[t - 1];
-          --t;
-        }
-        sk[t] = kv;
-        sidx[t] = iv;
-      }
-    }
-    __syncthreads();
   }
   // Merge in place: runs of equal keys lie in one chunk (equal keys share their top digits).
-  // The thread owning a run's head sums it in array order, keeps it when |sum| > thr; the kept
-  // runs are compacted to the front of the chunk's range and counted for the publishing scan.
+  // The thread owning a run's head sums it in array order and keeps it when |sum| > thr; the
+  // kept runs are counted for the chunk's offset and written in order.
   const double thr = pas[seg_entry[s]].thr;
   const uint32_t j0 = threadIdx.x * kItems;  // this thread's run of sorted positions
   W wr[kItems], sums[kItems];
+  K kt[kItems];
 #pragma unroll
   for (int t = 0; t < kItems; ++t) wr[t] = w_in[c0 + sidx[min(j0 + t, n - 1)]];  // every gather in flight
+#pragma unroll
+  for (int t = 0; t < kItems; ++t) kt[t] = sk[min(j0 + t, n - 1)];
+  const K k_before = (j0 > 0 && j0 <= n) ? sk[j0 - 1] : (K)0;
+  const K k_after = j0 + kItems < n ? sk[j0 + kItems] : (K)0;
+  // Each run is summed left to right by the thread holding its head (its tail past this
+  // thread's items read from global memory) and its sum kept at its last item in this thread
+  // (static register indices only).
   uint32_t keep_mask = 0, keep = 0;
-  auto run_sum = [&](auto acc, int t) {
-    const uint32_t j = j0 + t;
-    acc.add(wr[t]);
+  auto sum_runs = [&](auto proto) {
+    auto acc = proto;
+    bool active = false;
 #pragma unroll
-    for (int u = t + 1; u < kItems; ++u) {
-      if (j0 + u >= n || sk[j0 + u] != sk[j]) return acc.value();
-      acc.add(wr[u]);
+    for (int t = 0; t < kItems; ++t) {
+      const uint32_t j = j0 + t;
+      const bool valid = j < n;
+      const bool head = valid && (j == 0 || kt[t] != (t ? kt[t - 1] : k_before));
+      const bool cont = j + 1 < n && (t + 1 < kItems ? kt[t + 1] : k_after) == kt[t];
+      if (head) {
+        acc = proto;
+        active = true;
+      }
+      if (active && valid) {
+        acc.add(wr[t]);
+        if (t + 1 == kItems && cont)
+          for (uint32_t i = j0 + kItems; i < n && sk[i] == kt[t]; ++i) acc.add(w_in[c0 + sidx[i]]);
+        if (!cont || t + 1 == kItems) {
+          const W v = acc.value();
+          sums[t] = v;
+          if (fabs((double)v) > thr) {
+            keep_mask |= 1u << t;
+            ++keep;
+          }
+          active = false;
+        }
+      }
     }
-    for (uint32_t i = j0 + kItems; i < n && sk[i] == sk[j]; ++i) acc.add(w_in[c0 + sidx[i]]);
-    return acc.value();
   };
-#pragma unroll
-  for (int t = 0; t < kItems; ++t) {
-    const uint32_t j = j0 + t;
-    sums[t] = 0;
-    if (j >= n || (j > 0 && sk[j] == sk[j - 1])) continue;
-    W v;
-    if constexpr (sizeof(W) == 8) v = run_sum(PlainSum<W>{}, t);
-    else v = fp64_acc ? run_sum(F64Sum{}, t) : run_sum(RunSum<float>{}, t);
-    if (fabs((double)v) > thr) {
-      sums[t] = v;
-      keep_mask |= 1u << t;
-      ++keep;
-    }
-  }
+  if constexpr (sizeof(W) == 8) sum_runs(PlainSum<W>{});
+  else if (fp64_acc) sum_runs(F64Sum{});
+  else sum_runs(RunSum<float>{});
   uint64_t tot;
   const uint64_t pre = block_excl_scan<kChunkBlock>(keep, scan_sh, &tot);
   const uint64_t base = lookback(tot, c0);
@@ -1548,7 +1646,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
 #pragma unroll
   for (int t = 0; t < kItems; ++t) {
     if (!(keep_mask & (1u << t))) continue;
-    kd[o] = sk[j0 + t];
+    kd[o] = kt[t];
     wd[o] = sums[t];
     ++o;
   }
@@ -2001,7 +2099,7 @@ __global__ void k_build_tables(const TableJob* __restrict__ jobs) {
   uint32_t neg = 0;
   for (uint32_t o = 0; o < jb.n_ops; ++o) key = apply_perm(key, jb.ops[o], neg);
   ((K*)jb.tab_key)[i] = key;
-  jb.tab_neg[i] = (uint8_t)neg;
+  jb.tab_neg[i] = (uint8_t)(neg | ((y_count(key) & 3u) << 1));  // see apply_table
 }
 
 // Z_j of freshly admitted circuits, written at the end of the term array: for entry c,

@@ -459,6 +459,11 @@ PermDesc make_perm(uint32_t n, const HostOp& op) {
   return d;
 }
 
+// ceil(2^32 / k) for an image count k >= 2 (0 otherwise): see the expansion's division.
+uint32_t count_reciprocal(int k) {
+  return k >= 2 ? (uint32_t)(((1ull << 32) + (uint64_t)k - 1) / (uint64_t)k) : 0u;
+}
+
 Exp1Desc make_exp1(uint32_t n, const HostOp& op) {
   Exp1Desc d{};
   d.pos = bitpos(n, op.q0);
@@ -473,6 +478,7 @@ Exp1Desc make_exp1(uint32_t n, const HostOp& op) {
       ++k;
     }
     d.cnt[in] = (uint8_t)k;
+    d.rcp[in] = count_reciprocal(k);
   }
   return d;
 }
@@ -492,6 +498,7 @@ Exp2Desc make_exp2(uint32_t n, const HostOp& op) {
       ++k;
     }
     d.cnt[in] = (uint8_t)k;
+    d.rcp[in] = count_reciprocal(k);
   }
   return d;
 }

@@ -31,6 +31,7 @@ struct Exp1Desc {
   uint32_t pos;
   uint8_t cnt[4];
   uint8_t out[4][4];
+  uint32_t rcp[4];  // ceil(2^32 / cnt) for cnt >= 2 (division by the count without a divide)
   double val[4][4];
   float valf[4][4];
 };
@@ -40,6 +41,7 @@ struct Exp2Desc {
   uint32_t pa, pb;
   uint8_t cnt[16];
   uint8_t out[16][16];
+  uint32_t rcp[16];
   double val[16][16];
   float valf[16][16];
 };
@@ -47,8 +49,9 @@ struct Exp2Desc {
 // One pass: terms -> [A perms] -> [E expanding ops] -> [B perms] -> images.
 // A Clifford chain compiled into per-byte tables: byte k of a key holds the digits of four
 // qubits; tab_key[k*256 + b] is the image key of that 4-qubit Pauli string under the chain
-// and tab_neg[k*256 + b] its sign bit. Conjugation is multiplicative, so the image of a
-// whole key is the product of its bytes' images (they commute) with the product's phase.
+// and tab_neg[k*256 + b] its sign bit (bit 0) and number of Y digits mod 4 (bits 1-2).
+// Conjugation is multiplicative, so the image of a whole key is the product of its bytes'
+// images (they commute) with the product's phase.
 struct ChainTable {
   const void* tab_key;     // K[nbytes * 256]
   const uint8_t* tab_neg;  // [nbytes * 256]
