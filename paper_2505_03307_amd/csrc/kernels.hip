@@ -2220,7 +2220,7 @@ inline uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)((n + bl
 const char* kernel_kind_name(int k) {
   static const char* names[kKNum] = {"init", "count", "scan", "expand", "sort_hist", "sort_scatter",
                                      "merge_count", "merge_write", "compose_ptm", "chunk_sort", "count_expand",
-                                     "dense_merge"};
+                                     "dense_merge", "chunk_finish"};
   return (k >= 0 && k < kKNum) ? names[k] : "?";
 }
 
@@ -2520,6 +2520,7 @@ hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* key
   });
   // bytes: every image read; the kept terms' bytes are added by the caller once known
   prof_end(prof, s, ev, kKChunkSort, (kb + wb) * (double)T);
+  ev = prof_begin(prof, s, kKChunkFinish);
   k_chunk_publish<<<1, kPublishBlock, 0, s>>>(tc, co.chunk_cnt, co.chunk_off, co.seg_off_out, co.fin, co.img_cnt, T,
                                               err);
   QIMAX_DISPATCH_K(KC, {
@@ -2532,6 +2533,8 @@ hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* key
                                                             (K*)keys_out, (float*)w_out, tc, co.chunk_cnt,
                                                             co.chunk_start, co.chunk_off, T, err);
   });
+  // bytes: the chunk counts and offsets (the moved runs are not known here)
+  prof_end(prof, s, ev, kKChunkFinish, 12.0 * (double)tc.n_blocks);
   return hipGetLastError();
 }
 

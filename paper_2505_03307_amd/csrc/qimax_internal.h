@@ -133,7 +133,7 @@ enum : uint32_t {
 // algorithmic bytes each launch must move (what the roofline is measured against).
 enum KernelKind : int {
   kKInit, kKCount, kKScan, kKExpand, kKSortHist, kKSortScatter, kKMergeCount, kKMergeWrite, kKCompose, kKChunkSort,
-  kKCountExpand, kKDense, kKNum
+  kKCountExpand, kKDense, kKChunkFinish, kKNum
 };
 const char* kernel_kind_name(int k);
 

@@ -34,8 +34,11 @@ KERNELS = {
     "sort_scatter": r"\bk_sort_scatter",
     "chunk_sort": r"\bk_chunk_sort",
     "dense_merge": r"\bk_dense_(scatter|compact)",
+    "chunk_finish": r"\bk_chunk_(publish|compact)\b",
+    # with truncated kernel names (rocprofv3 -T) k_merge counts as the writing merge, the one
+    # the benchmark runs
     "merge_count": r"\bk_merge<[^,]+, [^,]+, 0>",
-    "merge_write": r"\bk_merge<[^,]+, [^,]+, [12]>|\bk_chunk_compact",
+    "merge_write": r"\bk_merge<[^,]+, [^,]+, [12]>|\bk_merge$",
     "copy": r"\bk_copy_u64",
 }
 
