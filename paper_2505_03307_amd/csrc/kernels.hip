@@ -1252,6 +1252,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   __shared__ __align__(16) uint8_t vary_sh[kWaves * sizeof(K)];
   __shared__ uint32_t blk_sh;
   __shared__ uint64_t base_sh;
+  __shared__ K prev_sh;
   // a look-back that waits claims chunks in order (so that every chunk it waits for is
   // running or done); one that only looks once takes the block's own index
   uint32_t blk = blockIdx.x;
@@ -1307,18 +1308,39 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   const uint64_t seg_lo = tc.blk_begin[tc.seg_blk[s]], seg_hi = tc.blk_end[tc.seg_blk[s + 1] - 1];
   const uint32_t top_shift = 8u * (n_pass - m);
   auto top = [&](K key) -> K { return m == 0 ? (K)0 : (K)(key >> top_shift); };
-  // chunk bounds: wave 0 for the tile start, wave 1 for the tile end
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // The window [a, a + kChunkCap) of the segment goes to LDS first (with the key before it);
+  // the chunk bounds are found there (wave 0 from the tile start, wave 1 from the tile end),
+  // in global memory only where a bucket reaches past the window.
+  const uint64_t wend = min(seg_hi, a + (uint64_t)kChunkCap);
+  const uint32_t wn = (uint32_t)(wend - a);  // >= b - a >= 1
+  {
+    K kr[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) kr[r] = keys_in[a + min((uint32_t)(r * kChunkBlock + threadIdx.x), wn - 1)];
+    const K before = (threadIdx.x == 0 && a != seg_lo) ? keys_in[a - 1] : (K)0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t j = r * kChunkBlock + threadIdx.x;
+      if (j < wn) sk[j] = kr[r];
+    }
+    if (threadIdx.x == 0) prev_sh = before;
+  }
+  __syncthreads();
   if (threadIdx.x < 128) {
-    const uint64_t x = threadIdx.x < 64 ? a : b;
+    const bool at_end = threadIdx.x >= 64;
+    const uint64_t x = at_end ? b : a;
     uint64_t r = x;
     if (x != seg_lo && x != seg_hi) {
-      const K t = top(keys_in[x - 1]);
+      // (b - 1 - a < b - a <= the nominal tile, inside the window)
+      const K t = top(at_end ? sk[b - 1 - a] : prev_sh);
       // a bucket holding x-1 ends before x + kChunkCap unless it is too large for a chunk
-      const uint64_t lim = min(seg_hi, x + (uint64_t)kChunkCap);
-      r = wave_first_true(x, lim, [&](uint64_t i) { return top(keys_in[i]) != t; });
-      if (r == lim && lim < seg_hi && (threadIdx.x & 63) == 0) atomicOr(err, kErrRedo);
+      const uint64_t lim = min(seg_hi, x + (uint64_t)kChunkCap), lim_w = min(lim, wend);
+      r = wave_first_true(x, lim_w, [&](uint64_t i) { return top(sk[i - a]) != t; });
+      if (r == lim_w && lim_w < lim) r = wave_first_true(lim_w, lim, [&](uint64_t i) { return top(keys_in[i]) != t; });
+      if (r == lim && lim < seg_hi && lane == 0) atomicOr(err, kErrRedo);
     }
-    if ((threadIdx.x & 63) == 0) cb[threadIdx.x >> 6] = r;
+    if (lane == 0) cb[threadIdx.x >> 6] = r;
   }
   __syncthreads();
   const uint64_t c0 = cb[0], c1 = cb[1];
@@ -1332,11 +1354,17 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
     return;
   }
   const uint32_t n = (uint32_t)(c1 - c0);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   {
+    // the chunk's keys to the front of sk: from the window, or from global memory where the
+    // chunk reaches past it
+    const bool in_win = c1 <= wend;
     K kr[kItems];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) kr[r] = keys_in[c0 + min((uint32_t)(r * kChunkBlock + threadIdx.x), n - 1)];
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t j = min((uint32_t)(r * kChunkBlock + threadIdx.x), n - 1);
+      kr[r] = in_win ? sk[(uint32_t)(c0 - a) + j] : keys_in[c0 + j];
+    }
+    __syncthreads();  // every window read before the first write
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t j = r * kChunkBlock + threadIdx.x;

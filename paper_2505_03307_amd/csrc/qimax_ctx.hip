@@ -937,9 +937,12 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   TileJob2 img_jobs[2];
   if (bound_path) {
     T_img = (uint64_t)f_round * T_in;  // capacity: an upper bound of the image count
-    const uint32_t caps[2] = {(uint32_t)((T_img + kExpandTile - 1) / kExpandTile + S),
+    // (a fused round has no separate expansion: its first tiling only sets the chunk-local
+    // sort's nominal chunks, which are then larger)
+    const uint64_t t0 = fused ? (uint64_t)kChunkTile : (uint64_t)kExpandTile;
+    const uint32_t caps[2] = {(uint32_t)((T_img + t0 - 1) / t0 + S),
                               (uint32_t)((T_img + kSortTile - 1) / kSortTile + S)};
-    const uint64_t tiles[2] = {(uint64_t)kExpandTile, (uint64_t)kSortTile};
+    const uint64_t tiles[2] = {t0, (uint64_t)kSortTile};
     Tiling* tls[2] = {&tl_exp, &tl};
     TileJob2* jobs = img_jobs;
     for (int i = 0; i < 2; ++i) {
@@ -1108,7 +1111,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   QCHK(ensure_zres(c, 2 * (size_t)S + 4));
   MergeFin fin{(const uint64_t*)c->img_seg.p, c->zres_dev, 0};
   bool chunk_path = pre_chunk >= 0;  // chunk-local sort fused with the merge
-  const Tiling& tc_chunk = small ? tc_small : tl_exp;  // the chunks' nominal tiles
+  const Tiling& tc_chunk = small ? tc_small : tl_exp;  // the chunks' nominal tiles (see the tilings)
   auto merge_and_read = [&]() -> qimax_status {
     if (sweep) {  // a fresh sequence word for these results
       fin.seq = ++c->zseq;
