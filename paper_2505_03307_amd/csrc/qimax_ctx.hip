@@ -297,6 +297,7 @@ struct qimax_ctx {
   bool small_rounds = true;   // rounds of small segments: one block per segment (see run_round)
   bool fused_expand = true;   // bound-path rounds: count and expansion in one launch
   uint32_t defer_spins = 0;   // chunk-local merge: look-back polls before a chunk is deferred (0: one look)
+  uint32_t chunk_tile = 0;    // nominal chunk of a fused round (0: from the expected bucket size)
   int dense_mode = 0;         // dense accumulation: 0 off, 1 wherever it applies, 2 a tuner candidate
   DevBuf dense_acc;           // its fixed-point slots
   int local_sort_m = -1;      // >= 0: force the number of top-digit passes
@@ -937,12 +938,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   TileJob2 img_jobs[2];
   if (bound_path) {
     T_img = (uint64_t)f_round * T_in;  // capacity: an upper bound of the image count
-    // (a fused round has no separate expansion: its first tiling only sets the chunk-local
-    // sort's nominal chunks, which are then larger)
-    const uint64_t t0 = fused ? (uint64_t)kChunkTile : (uint64_t)kExpandTile;
-    const uint32_t caps[2] = {(uint32_t)((T_img + t0 - 1) / t0 + S),
+    const uint32_t caps[2] = {(uint32_t)((T_img + kExpandTile - 1) / kExpandTile + S),
                               (uint32_t)((T_img + kSortTile - 1) / kSortTile + S)};
-    const uint64_t tiles[2] = {t0, (uint64_t)kSortTile};
+    const uint64_t tiles[2] = {(uint64_t)kExpandTile, (uint64_t)kSortTile};
     Tiling* tls[2] = {&tl_exp, &tl};
     TileJob2* jobs = img_jobs;
     for (int i = 0; i < 2; ++i) {
@@ -1003,9 +1001,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
                         (c->dense_mode == 1 || (double)S * (double)per_seg <= kDenseRatio * (double)T_img);
   bool dense = dense_ok && c->dense_mode == 1;
   if (small) m_top = 0;  // whole segments sorted in LDS
+  uint64_t seg_max = 0;     // the largest segment's image count (or its bound)
   if (sweep && !small) {
     if (c->local_sort && c->redo_cooldown == 0) {
-      uint64_t seg_max = 0;
       for (uint32_t s = 0; s < S; ++s)
         seg_max = std::max<uint64_t>(seg_max, bound_path ? (uint64_t)(f_round * (double)(so_in[s + 1] - so_in[s]))
                                                          : so_img[s + 1] - so_img[s]);
@@ -1059,6 +1057,17 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
                                   ctr + kCtrCount, c->mepoch, (uint64_t*)c->img_seg.p, c->ik[0].p, c->iw[0].p, T_img,
                                   hist_in_expand ? (uint32_t*)c->ghist.p : nullptr, n_pass, n_pass - m_top,
                                   (uint32_t*)c->err.p, c->stream, &c->prof), "count and expand");
+    // A fused round has no separate expansion: its first tiling only sets the chunk-local
+    // sort's nominal chunks, as large as the buckets straddling their ends leave room for in
+    // a chunk (kChunkCap): 4096 less four times the largest segment's average bucket, within
+    // [kExpandTile, kChunkTile] (the capacity was sized for kExpandTile).
+    if (c->chunk_tile) {
+      img_jobs[0].tile = c->chunk_tile;
+    } else if (m_top < n_pass) {
+      const double bucket = (double)seg_max / std::ldexp(1.0, 8 * (int)m_top);
+      const double t = std::min((double)kChunkTile, std::max((double)kExpandTile, (double)kChunkCap - 4.0 * bucket));
+      img_jobs[0].tile = (uint64_t)t / 256 * 256;
+    }
     HIPCHK(c, launch_make_tiles2(nullptr, (const uint64_t*)c->img_seg.p, S, nullptr, img_jobs[0], img_jobs[1], T_img,
                                  (uint32_t*)c->err.p, c->stream), "tiles");
   } else
@@ -2082,6 +2091,10 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     if (env && env[0]) c->local_sort_m = std::atoi(env);
     env = std::getenv("QIMAX_DEFER_SPINS");  // chunk-local merge: polls before deferring a chunk
     if (env && env[0]) c->defer_spins = (uint32_t)std::strtoul(env, nullptr, 10);
+    env = std::getenv("QIMAX_CHUNK_TILE");  // fixed nominal chunk of a fused round (2048 .. 4096)
+    if (env && env[0])
+      c->chunk_tile = std::min<uint32_t>(std::max<uint32_t>((uint32_t)std::strtoul(env, nullptr, 10), kExpandTile),
+                                         (uint32_t)kChunkCap);
     env = std::getenv("QIMAX_AUTOTUNE");  // 0: always the heuristic's sort variant
     c->autotune = !(env && env[0] == '0');
   }

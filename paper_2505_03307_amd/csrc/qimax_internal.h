@@ -104,10 +104,10 @@ constexpr int kSortTile = kSortBlock * kSortItems;  // elements per tile (4096)
 constexpr int kRadixBits = 8;
 constexpr uint32_t kSmallMaxSegs = 8192;  // segments of a small round (one block each)
 constexpr int kChunkCap = 4096;  // elements a chunk-local sort holds in LDS
-// nominal chunk of a fused round (other rounds: the expansion tiles, kExpandTile); a chunk
-// extends to whole buckets at both ends, so the slack below kChunkCap takes the straddling
-// buckets (about 512 images on average by the choice of the top-digit passes)
-constexpr int kChunkTile = 3072;
+// largest nominal chunk of a fused round (other rounds: the expansion tiles, kExpandTile); a
+// chunk extends to whole buckets at both ends, so the slack below kChunkCap takes the
+// straddling buckets
+constexpr int kChunkTile = 3584;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kExpandBlock = 256;
 constexpr int kExpandItems = 8;

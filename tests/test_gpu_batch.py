@@ -144,15 +144,18 @@ def test_served_results_equal_alone():
 @pytest.mark.parametrize("variant", [("QIMAX_HOST_TILING", "1"), ("QIMAX_SORT_CLASSIC", "1"),
                                      ("QIMAX_LOCAL_SORT", "0"), ("QIMAX_LOCAL_SORT_M", "0"),
                                      ("QIMAX_LOCAL_SORT_M", "1"), ("QIMAX_XCD_RANGES", "0"),
-                                     ("QIMAX_SMALL_ROUNDS", "0"), ("QIMAX_FUSED_EXPAND", "0")])
+                                     ("QIMAX_SMALL_ROUNDS", "0"), ("QIMAX_FUSED_EXPAND", "0"),
+                                     ("QIMAX_CHUNK_TILE", "2048"), ("QIMAX_CHUNK_TILE", "4096"),
+                                     ("QIMAX_DEFER_SPINS", "100000")])
 def test_tiling_and_sort_variants_bit_identical(variant, monkeypatch):
     """Image tilings built on the device from the fan-out bound (the default for rounds whose
     bound is small) or on the host after reading the image count back; the classic
     multi-launch sort; every digit by global passes, or the top 0 / 1 digits followed by
     chunk-local sorts (0 makes every segment above a chunk fall back to global passes); small
     rounds (one block per segment) or the general path for them; the count and the expansion
-    in one launch or in two: all are stable sorts of the same images, hence identical sums, so
-    the results must agree bit for bit, alone and batched."""
+    in one launch or in two; fixed nominal chunks of 2048 or 4096 images; chunks that wait for
+    their predecessors' offsets instead of deferring: all are stable sorts of the same images,
+    hence identical sums, so the results must agree bit for bit, alone and batched."""
     name, value = variant
     cs = mixed_circuits()
     with Batch(precision=64) as b:
