@@ -237,6 +237,26 @@ typedef struct {
 
 qimax_status qimax_get_stats(const qimax_ctx* ctx, qimax_stats* out);
 
+/* The autotuner's state (multi-circuit execution, Sec. VI: tile and bucket choices made per
+ * size class of rounds). A size class is the key size, the weight precision, floor(log2) of
+ * the round's image capacity and whether dense accumulation applies. The candidates are the
+ * same sort with: 0 the heuristic number of top-digit passes, 1 one pass more, 2 sort tiles
+ * claimed in one global order instead of per XCD, 3 and 4 as 0 and 1 with multi-launch
+ * global passes (histogram, scan, scatter) instead of single-sweep ones, 5 dense
+ * accumulation (classes where it applies). Writes min(cap, classes) entries to out (out may
+ * be NULL when cap is 0) and the number of classes to *n. Host bookkeeping, no device work. */
+typedef struct {
+  uint32_t key_bytes;        /* 4, 8 or 16                                                 */
+  uint32_t weight_bits;      /* 32 or 64                                                   */
+  uint32_t log2_images;      /* floor(log2) of the round's image capacity                  */
+  uint32_t dense_candidate;  /* 1 when dense accumulation is a candidate                   */
+  int32_t best;              /* the chosen candidate, -1 while candidates are still timed  */
+  uint32_t tried;            /* rounds timed so far (each candidate twice, in turns)       */
+  float ms[6];               /* each candidate's least round time on the device (ms; 1e30
+                                for a candidate whose buckets overflowed a chunk)           */
+} qimax_tune_entry;
+qimax_status qimax_get_tuning(const qimax_ctx* ctx, qimax_tune_entry* out, size_t cap, size_t* n);
+
 /* The term_updates counter split by generator: out[j] for j < n (host bookkeeping). */
 qimax_status qimax_get_generator_updates(const qimax_ctx* ctx, uint64_t* out, size_t n);
 

@@ -388,7 +388,7 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
          uint64_t T_in, const uint64_t* __restrict__ off, uint64_t T_img, Tiling tl, const PassArgs* __restrict__ pas,
          const uint32_t* __restrict__ seg_entry, const uint64_t* __restrict__ seg_in, K* __restrict__ keys_out,
          typename WTraits<WP>::W* __restrict__ w_out, uint32_t* __restrict__ ghist, uint32_t n_pass, uint32_t hp_begin,
-         uint32_t* err) {
+         uint32_t* err, uint64_t narrow_lim) {
   using W = typename WTraits<WP>::W;
   constexpr int kWaves = kExpandBlock / 64;
   constexpr int kWin = kExpandTile + 1;
@@ -436,8 +436,9 @@ k_expand(const K* __restrict__ keys, const uint8_t* __restrict__ asign, const ty
   __syncthreads();
   const uint64_t plo = bounds[0], phi = bounds[1];
   const uint64_t nwin = phi - plo + 2;  // off[plo .. phi+1]
-  // (offsets below 2^31 keep every window entry minus g0 within 32 bits)
-  const bool in_lds = nwin <= (uint64_t)kWin && T_img < (1ull << 31);
+  // (offsets below 2^31 keep every window entry minus g0 within 32 bits; narrow_lim = 2^31,
+  // 0 forces the search in global memory, for tests)
+  const bool in_lds = nwin <= (uint64_t)kWin && T_img < narrow_lim;
   if (in_lds) {
     for (uint64_t k = threadIdx.x; k < nwin; k += kExpandBlock) win[k] = (int32_t)((int64_t)off[plo + k] - (int64_t)g0);
     __syncthreads();
@@ -638,6 +639,7 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_hist(const K* __restrict__ 
                                                           uint64_t hist_size, uint32_t* err) {
   __shared__ uint32_t h[kSortBlock / 64][kRadix];
   const uint32_t b = blockIdx.x;
+  if (tl.n_dev && b >= *tl.n_dev) return;  // launched for a bound on the tile count
   const int wid = threadIdx.x >> 6;
   for (int k = threadIdx.x; k < (kSortBlock / 64) * kRadix; k += kSortBlock) (&h[0][0])[k] = 0;
   __syncthreads();
@@ -903,7 +905,8 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
                                                     const uint32_t* __restrict__ seg_entry, uint64_t* __restrict__ off,
                                                     uint64_t T_in, uint64_t* __restrict__ status,
                                                     uint32_t* __restrict__ ctr, uint64_t epoch, uint32_t* err,
-                                                    K* __restrict__ akeys, uint8_t* __restrict__ asign) {
+                                                    K* __restrict__ akeys, uint8_t* __restrict__ asign,
+                                                    uint64_t narrow_lim) {
   constexpr int kItems = kSortTile / 256;  // input tiles hold at most kSortTile terms
   constexpr int kTabN = sizeof(K) <= 8 ? (int)sizeof(K) * 256 : 1;  // no tables for 16-byte keys
   __shared__ K tk[kTabN];
@@ -975,8 +978,9 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
   }
   __syncthreads();
   const uint64_t base = base_sh;
-  if (tot < (1ull << 32)) {
-    // offsets within the tile fit 32 bits: they go back through LDS for coalesced stores
+  if (tot < narrow_lim) {
+    // offsets within the tile fit 32 bits (narrow_lim = 2^32; 0 forces the other branch, for
+    // tests): they go back through LDS for coalesced stores
     uint32_t run = (uint32_t)pre;
 #pragma unroll
     for (int k2 = 0; k2 < kItems; ++k2) {
@@ -1015,7 +1019,7 @@ __global__ void __launch_bounds__(256) k_count_scan(const K* __restrict__ keys, 
 // last tile for the trailing ones) and img_seg[S] the image count. The images come out in the
 // same order as from the count and expansion launches.
 constexpr int kFuseBlock = 512, kFuseItems = 4, kFuseTile = kFuseBlock * kFuseItems;
-constexpr int kFuseChunk = 4096;  // images per window of the image -> parent map
+constexpr int kFuseChunk = 2048;  // images per window of the image -> parent map
 template <typename K, int WP>
 __global__ void __launch_bounds__(kFuseBlock)
 k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __restrict__ w, Tiling tl,
@@ -1032,7 +1036,7 @@ k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __rest
   __shared__ uint8_t aneg[kFuseTile];
   __shared__ uint32_t loff[kFuseTile + 1];
   __shared__ uint16_t pmap[kFuseChunk];
-  __shared__ uint32_t hh[kExpandHistPasses * kWaves * kRadix];
+  __shared__ uint32_t hh[kExpandHistPasses * kRadix];  // one copy per block (LDS for 3 blocks per CU)
   __shared__ uint64_t scan_sh[kWaves];
   __shared__ uint64_t base_sh;
   __shared__ uint32_t tile_sh;
@@ -1069,7 +1073,7 @@ k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __rest
     aneg[li] = (uint8_t)(neg & 1u);
     loff[li] = (uint32_t)f;
   }
-  for (uint32_t i = threadIdx.x; i < n_hp * kWaves * kRadix; i += kFuseBlock) hh[i] = 0u;
+  for (uint32_t i = threadIdx.x; i < n_hp * kRadix; i += kFuseBlock) hh[i] = 0u;
   __syncthreads();
   // each thread scans a run of kFuseItems consecutive terms
   const uint32_t l0 = threadIdx.x * kFuseItems;
@@ -1129,7 +1133,7 @@ k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __rest
     if (threadIdx.x == 0 && n_img) atomicOr(err, kErrIndex | kErrExpand);
     return;
   }
-  uint32_t* hw = hh + (threadIdx.x >> 6) * n_hp * kRadix;
+  uint32_t* hw = hh;
   for (uint32_t c0 = 0; c0 < n_img; c0 += kFuseChunk) {
     const uint32_t c1 = min(c0 + (uint32_t)kFuseChunk, n_img);
     for (uint32_t j = threadIdx.x; j < n; j += kFuseBlock) {
@@ -1154,9 +1158,7 @@ k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __rest
   }
   if (n_hp) {
     for (uint32_t i = threadIdx.x; i < n_hp * kRadix; i += kFuseBlock) {
-      uint32_t c = 0;
-#pragma unroll
-      for (int wv = 0; wv < kWaves; ++wv) c += hh[wv * n_hp * kRadix + i];
+      const uint32_t c = hh[i];
       const uint32_t p = hp_begin + i / kRadix, d = i % kRadix;
       if (c) atomicAdd(&ghist[((uint64_t)seg * n_pass + p) * kRadix + d], c);
     }
@@ -2338,7 +2340,7 @@ hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, u
 
 hipError_t launch_count_scan(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
                              const uint32_t* seg_entry, uint64_t* off, uint64_t* status, uint32_t* ctr, uint64_t epoch,
-                             uint32_t* err, void* akeys, uint8_t* asign, hipStream_t s, Prof* prof) {
+                             uint32_t* err, void* akeys, uint8_t* asign, hipStream_t s, Prof* prof, bool wide) {
   if (T == 0 || tl.n_blocks == 0) {
     k_zero_one<<<1, 1, 0, s>>>(off);
     return hipGetLastError();
@@ -2346,7 +2348,7 @@ hipError_t launch_count_scan(int KC, const void* keys, uint64_t T, const Tiling&
   hipEvent_t ev = prof_begin(prof, s, kKCount);
   QIMAX_DISPATCH_K(KC, {
     k_count_scan<K><<<tl.n_blocks, 256, 0, s>>>((const K*)keys, tl, pas, seg_entry, off, T, status, ctr, epoch, err,
-                                                 (K*)akeys, asign);
+                                                 (K*)akeys, asign, wide ? 0ull : (1ull << 32));
   });
   prof_end(prof, s, ev, kKCount, (double)T * (2 * (4 << KC) + 9));
   return hipGetLastError();
@@ -2390,8 +2392,9 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
                          const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
                          uint32_t* ghist, uint32_t n_pass, uint32_t hp_begin, uint32_t* err, hipStream_t s,
-                         Prof* prof) {
+                         Prof* prof, bool wide) {
   if (T_img == 0 || tl.n_blocks == 0) return hipSuccess;
+  const uint64_t narrow = wide ? 0ull : (1ull << 31);
   if (ghist && (hp_begin > n_pass || n_pass - hp_begin > kExpandHistPasses)) return hipErrorInvalidValue;
   const size_t hist = ghist ? (size_t)(n_pass - hp_begin) * (kExpandBlock / 64) * kRadix * 4 : 0;
   hipEvent_t ev = prof_begin(prof, s, kKExpand);
@@ -2402,11 +2405,11 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign,
     if (WP == 64)
       k_expand<K, 64><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, asign, (const double*)w, T_in, off, T_img, tl,
                                                               pas, seg_entry, seg_in, (K*)keys_out, (double*)w_out,
-                                                              ghist, n_pass, hp_begin, err);
+                                                              ghist, n_pass, hp_begin, err, narrow);
     else
       k_expand<K, 32><<<tl.n_blocks, kExpandBlock, lds, s>>>((const K*)keys, asign, (const float*)w, T_in, off, T_img, tl,
                                                               pas, seg_entry, seg_in, (K*)keys_out, (float*)w_out,
-                                                              ghist, n_pass, hp_begin, err);
+                                                              ghist, n_pass, hp_begin, err, narrow);
   });
   const double per = (4 << KC) + (WP == 64 ? 8 : 4);
   prof_end(prof, s, ev, kKExpand, per * (double)(T_in + T_img) + 8.0 * (double)T_in);

@@ -85,12 +85,15 @@ struct HostOp {
   Ptm R;              // dim*dim
 };
 
-// Autotuner state of one size class of rounds: the sort variants tried (0: heuristic number
-// of top-digit passes, 1: one more, 2: heuristic without per-XCD tile ranges, 3: dense
-// accumulation instead of the sort, where it applies and is enabled), their measured
-// device times, and the winner once every candidate has run once.
+// Autotuner state of one size class of rounds: the rounds timed so far, each candidate's
+// least device time, and the winner once every candidate has been timed kTuneSamples times.
+// Candidates: 0 the heuristic number of top-digit passes, 1 one more, 2 one global tile
+// order instead of per-XCD ranges, 3 / 4 as 0 / 1 with multi-launch global passes, 5 dense
+// accumulation (classes where it applies and is enabled).
+constexpr int kTuneSamples = 2;
+
 struct TuneState {
-  static constexpr int kCand = 4;  // 3: dense accumulation (classes where it applies)
+  static constexpr int kCand = 6;
   int tried = 0;
   int best = -1;
   float ms[kCand] = {};
@@ -298,6 +301,8 @@ struct qimax_ctx {
   bool fused_expand = true;   // bound-path rounds: count and expansion in one launch
   uint32_t defer_spins = 0;   // chunk-local merge: look-back polls before a chunk is deferred (0: one look)
   uint32_t chunk_tile = 0;    // nominal chunk of a fused round (0: from the expected bucket size)
+  bool wide_offsets = false;  // count and expansion take their paths for 2^32 / 2^31 images (tests)
+  bool classic_passes = false;  // multi-launch global sort passes in every round (tests)
   int dense_mode = 0;         // dense accumulation: 0 off, 1 wherever it applies, 2 a tuner candidate
   DevBuf dense_acc;           // its fixed-point slots
   int local_sort_m = -1;      // >= 0: force the number of top-digit passes
@@ -929,7 +934,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     c->mepoch += 1;
     HIPCHK(c, launch_count_scan(c->KC, k_in, T_in, tl_in, pas, sent, (uint64_t*)c->off.p, (uint64_t*)c->mstatus.p,
                                 ctr + kCtrCount, c->mepoch, (uint32_t*)c->err.p, c->akeys.p, (uint8_t*)c->asign.p,
-                                c->stream, &c->prof), "count");
+                                c->stream, &c->prof, c->wide_offsets), "count");
   }
   QCHK(ensure(c, c->img_seg, (S + 1) * 8));
   uint32_t e = 0;
@@ -992,6 +997,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   int tune_cand = 0;
   bool tune_timed = false;
   bool xr = c->xcd_ranges;
+  // the global passes as multi-launch passes (histogram, scan, scatter per digit) instead of
+  // single-sweep ones: no look-back chain over a segment's tiles, at one more read per pass
+  bool classic_passes = c->classic_passes;
   // Dense accumulation instead of the sort: one circuit, 32-bit keys, a dense space of 4^n
   // slots per generator that stays small next to the images, bounded weights (orthogonal
   // transfer matrices). Forced (QIMAX_DENSE=1) or a tuner candidate (QIMAX_DENSE=auto).
@@ -1011,14 +1019,18 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       for (double cap_b = 512.0; mm < n_pass && (double)seg_max > cap_b; cap_b *= 256.0) ++mm;
       m_top = c->local_sort_m >= 0 ? std::min<uint32_t>((uint32_t)c->local_sort_m, n_pass) : mm;
       if (c->autotune && c->local_sort_m < 0 && (m_top < n_pass || dense_ok)) {
-        tune_key = (uint32_t)c->KC * 4096u + (uint32_t)c->WP * 64u + (uint32_t)std::min(63, ilog2_u64(T_img)) +
+        // size class: key class << 8 | FP64 weights << 6 | log2 of the image capacity (| 2^20 with dense)
+        tune_key = ((uint32_t)c->KC << 8) + (c->WP == 64 ? 64u : 0u) + (uint32_t)std::min(63, ilog2_u64(T_img)) +
                    (dense_ok ? (1u << 20) : 0u);
         TuneState& ts = c->tune[tune_key];
         // (a recording never explores: its rounds are not timed)
-        tune_cand = ts.best >= 0 ? ts.best : (c->tune_frozen ? 0 : ts.tried);
-        if (tune_cand == 1) m_top = std::min(m_top + 1, n_pass);
+        // (each candidate is timed kTuneSamples times, in turns; its time is the least)
+        const int n_cand = dense_ok ? TuneState::kCand : TuneState::kCand - 1;
+        tune_cand = ts.best >= 0 ? ts.best : (c->tune_frozen ? 0 : ts.tried % n_cand);
+        if (tune_cand == 1 || tune_cand == 4) m_top = std::min(m_top + 1, n_pass);
         if (tune_cand == 2) xr = false;
-        if (tune_cand == 3) dense = true;
+        if (tune_cand == 3 || tune_cand == 4) classic_passes = true;
+        if (tune_cand == 5) dense = true;
         if (ts.best < 0 && !c->tune_frozen) {  // exploring: time this round
           HIPCHK(c, hipEventRecord(c->tune_ev[0], c->stream), "tune event");
           tune_timed = true;
@@ -1027,7 +1039,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     }
     if (c->redo_cooldown > 0) --c->redo_cooldown;
   }
-  const bool hist_in_expand = sweep && !dense && m_top <= kExpandHistPasses;
+  const bool hist_in_expand = sweep && !dense && !classic_passes && m_top <= kExpandHistPasses;
   // ---- expand into images
   const size_t eb = c->kb, wbt = c->wb;
   // image buffers: the capacity, or for a small round S chunks of kChunkCap
@@ -1074,7 +1086,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
   HIPCHK(c, launch_expand(c->KC, c->WP, c->akeys.p, (const uint8_t*)c->asign.p, w_in, T_in,
                           (const uint64_t*)c->off.p, T_img, tl_exp, pas, sent, seg_in, any_b_tables, e_bytes,
                           c->ik[0].p, c->iw[0].p, hist_in_expand ? (uint32_t*)c->ghist.p : nullptr, n_pass,
-                          n_pass - m_top, (uint32_t*)c->err.p, c->stream, &c->prof), "expand");
+                          n_pass - m_top, (uint32_t*)c->err.p, c->stream, &c->prof, c->wide_offsets), "expand");
   // ---- segment-local LSD radix sort of the images
   const uint64_t hsize = (uint64_t)kRadix * std::max<uint32_t>(tl.n_blocks, 1);
   int cur = 0;
@@ -1106,9 +1118,22 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     void* const kk[2] = {c->ik[0].p, c->ik[1].p};
     void* const ww[2] = {c->iw[0].p, c->iw[1].p};
     if (!xr) tl.xrange = nullptr;
-    HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, n_pass - m_top, !hist_in_expand, tl,
-                                (const uint64_t*)c->img_seg.p, (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr,
-                                &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof), "sort");
+    if (classic_passes) {
+      QCHK(ensure(c, c->scan_tmp, scan_tmp_words(hsize) * 8));
+      QCHK(ensure(c, c->hist, hsize * 8));
+      QCHK(ensure(c, c->hist_off, (hsize + 1) * 8));
+      cur = 0;
+      for (uint32_t p = n_pass - m_top; p < n_pass; ++p) {
+        HIPCHK(c, launch_sort_pass(c->KC, c->WP, kk[cur], ww[cur], kk[cur ^ 1], ww[cur ^ 1], T_img, p * kRadixBits,
+                                   tl, (uint64_t*)c->hist.p, (uint64_t*)c->hist_off.p, (uint64_t*)c->scan_tmp.p,
+                                   (uint32_t*)c->err.p, c->stream, &c->prof), "sort");
+        cur ^= 1;
+      }
+    } else {
+      HIPCHK(c, launch_sort_sweep(c->KC, c->WP, kk, ww, T_img, key_bits, n_pass - m_top, !hist_in_expand, tl,
+                                  (const uint64_t*)c->img_seg.p, (uint32_t*)c->ghist.p, (uint64_t*)c->sstatus.p, ctr,
+                                  &c->epoch, (uint32_t*)c->err.p, &cur, c->stream, &c->prof), "sort");
+    }
     if (m_top < n_pass) pre_chunk = cur;  // the chunk-local sort runs with the merge
   }
   // ---- segmented reduce + prune + compaction into the pass output slot
@@ -1203,9 +1228,9 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]) != hipSuccess) ms = 1e30f;
     if (sorted_again) ms = 1e30f;  // a candidate that overflows chunks is never chosen
-    ts.ms[tune_cand] = ms;
-    const int n_cand = (tune_key >> 20) & 1u ? TuneState::kCand : TuneState::kCand - 1;
-    if (++ts.tried >= n_cand) {
+    const int n_cand = (tune_key >> 20) & 1u ? TuneState::kCand : TuneState::kCand - 1;  // dense: the last
+    ts.ms[tune_cand] = ts.tried < n_cand ? ms : std::min(ts.ms[tune_cand], ms);
+    if (++ts.tried >= kTuneSamples * n_cand) {
       ts.best = 0;
       for (int i = 1; i < n_cand; ++i)
         if (ts.ms[i] < ts.ms[ts.best]) ts.best = i;
@@ -2095,6 +2120,10 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     if (env && env[0])
       c->chunk_tile = std::min<uint32_t>(std::max<uint32_t>((uint32_t)std::strtoul(env, nullptr, 10), kExpandTile),
                                          (uint32_t)kChunkCap);
+    env = std::getenv("QIMAX_CLASSIC_PASSES");  // 1: multi-launch global passes in the single-sweep rounds
+    c->classic_passes = env && env[0] == '1';
+    env = std::getenv("QIMAX_WIDE_OFFSETS");  // 1: the count's and expansion's paths for huge rounds
+    c->wide_offsets = env && env[0] == '1';
     env = std::getenv("QIMAX_AUTOTUNE");  // 0: always the heuristic's sort variant
     c->autotune = !(env && env[0] == '0');
   }
@@ -2572,6 +2601,27 @@ qimax_status qimax_compare(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_
 qimax_status qimax_compare_noalloc(qimax_ctx* a, qimax_ctx* b, double tau, double* diff_norm, double* ref_norm,
                                    uint64_t* n_tau_diff) {
   return compare_impl(a, b, tau, diff_norm, ref_norm, n_tau_diff, true);
+}
+
+qimax_status qimax_get_tuning(const qimax_ctx* c, qimax_tune_entry* out, size_t cap, size_t* n) {
+  if (!c || !n || (cap && !out)) return QIMAX_EINVAL;
+  size_t i = 0;
+  for (const auto& kv : c->tune) {
+    if (i < cap) {
+      const uint32_t k = kv.first;  // see the size class of a round in run_round
+      qimax_tune_entry& e = out[i];
+      e.key_bytes = 4u << ((k >> 8) & 3u);
+      e.weight_bits = (k & 64u) ? 64u : 32u;
+      e.log2_images = k & 63u;
+      e.dense_candidate = (k >> 20) & 1u;
+      e.best = kv.second.best;
+      e.tried = (uint32_t)kv.second.tried;
+      for (int j = 0; j < 6; ++j) e.ms[j] = j < TuneState::kCand ? kv.second.ms[j] : 0.f;
+    }
+    ++i;
+  }
+  *n = i;
+  return QIMAX_OK;
 }
 
 qimax_status qimax_get_stats(const qimax_ctx* c, qimax_stats* out) {

@@ -176,7 +176,8 @@ hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, u
 // `epoch`.
 hipError_t launch_count_scan(int KC, const void* keys, uint64_t T, const Tiling& tl, const PassArgs* pas,
                              const uint32_t* seg_entry, uint64_t* off, uint64_t* status, uint32_t* ctr, uint64_t epoch,
-                             uint32_t* err, void* akeys, uint8_t* asign, hipStream_t s, Prof* prof = nullptr);
+                             uint32_t* err, void* akeys, uint8_t* asign, hipStream_t s, Prof* prof = nullptr,
+                             bool wide = false);  // wide: 64-bit in-tile offsets always (tests)
 
 // out[i] = exclusive prefix sum of in[0..i-1] for i in [0, N]; out has N+1 entries.
 // tmp must hold scan_tmp_words(N) uint64 words.
@@ -200,7 +201,7 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign,
                          uint64_t T_img, const Tiling& tl, const PassArgs* pas, const uint32_t* seg_entry,
                          const uint64_t* seg_in, bool any_tables, size_t e_bytes, void* keys_out, void* w_out,
                          uint32_t* ghist, uint32_t n_pass, uint32_t hp_begin, uint32_t* err, hipStream_t s,
-                         Prof* prof = nullptr);
+                         Prof* prof = nullptr, bool wide = false);  // wide: parents found in global memory (tests)
 
 // One LSD radix pass over digit `shift` of every segment, stable, segment-local.
 // hist must hold kRadix * n_blocks uint64 words; tmp scan_tmp_words(kRadix * n_blocks).

@@ -43,6 +43,11 @@ class Stats(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint32) for k in ("key_bytes", "weight_bits", "log2_images", "dense_candidate")] + \
+               [("best", ctypes.c_int32), ("tried", ctypes.c_uint32), ("ms", ctypes.c_float * 6)]
+
+
 class CircuitC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("gate", ctypes.POINTER(ctypes.c_uint8)), ("q0", ctypes.POINTER(ctypes.c_uint32)),
                 ("q1", ctypes.POINTER(ctypes.c_uint32)), ("theta", ctypes.POINTER(ctypes.c_double)),
@@ -88,7 +93,7 @@ EXPORTS = ["qimax_batch_create", "qimax_batch_submit", "qimax_batch_step", "qima
            "qimax_batch_last_error", "qimax_batch_destroy",
            "qimax_default_opts", "qimax_create", "qimax_reset", "qimax_flush", "qimax_graph_record", "qimax_graph_launch", "qimax_graph_destroy", "qimax_get_generator_updates", "qimax_apply_layer", "qimax_apply_circuit", "qimax_group_circuit",
            "qimax_num_terms", "qimax_get_generators", "qimax_get_generators_xz", "qimax_expect",
-           "qimax_expect_many", "qimax_prob_zero_all", "qimax_compare", "qimax_compare_noalloc", "qimax_get_stats", "qimax_sync",
+           "qimax_expect_many", "qimax_prob_zero_all", "qimax_compare", "qimax_compare_noalloc", "qimax_get_stats", "qimax_get_tuning", "qimax_sync",
            "qimax_profile", "qimax_profile_only", "qimax_profile_read", "qimax_copy_probe", "qimax_last_error", "qimax_destroy"]
 
 _lib = None
@@ -135,6 +140,7 @@ def load():
     lib.qimax_compare.argtypes = [P, P, ctypes.c_double, dp, dp, u64p]
     lib.qimax_compare_noalloc.argtypes = [P, P, ctypes.c_double, dp, dp, u64p]
     lib.qimax_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.qimax_get_tuning.argtypes = [P, ctypes.POINTER(TuneEntry), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     lib.qimax_sync.argtypes = [P]
     lib.qimax_profile.argtypes = [P, ctypes.c_int]
     lib.qimax_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_size_t, szp]
@@ -368,6 +374,17 @@ class Simulator:
         self._check(fn(self._h, ref._h, float(tau), _p(d, ctypes.c_double), _p(r, ctypes.c_double),
                        _p(k, ctypes.c_uint64)))
         return d, r, k
+
+    def tuning(self) -> list:
+        """The autotuner's size classes and chosen candidates (qimax_get_tuning)."""
+        lib = load()
+        n = ctypes.c_size_t()
+        self._check(lib.qimax_get_tuning(self._h, None, 0, ctypes.byref(n)))
+        arr = (TuneEntry * max(n.value, 1))()
+        self._check(lib.qimax_get_tuning(self._h, arr, n.value, ctypes.byref(n)))
+        return [{"key_bytes": e.key_bytes, "weight_bits": e.weight_bits, "log2_images": e.log2_images,
+                 "dense_candidate": bool(e.dense_candidate), "best": e.best, "tried": e.tried,
+                 "ms": [round(float(x), 4) for x in e.ms[:5 + e.dense_candidate]]} for e in arr[:n.value]]
 
     def stats(self) -> dict:
         s = Stats()

@@ -160,8 +160,9 @@ def serve_trace(circuits, arrivals, budget_bytes: int, precision: int = 32, keep
     return results, srv
 
 
-def serve_sequential(circuits, arrivals, precision: int = 32, keep_results: bool = False):
-    """The plain path on the same trace: one circuit at a time, FIFO, in real time."""
+def serve_sequential(circuits, arrivals, precision: int = 32, keep_results: bool = False, progress=None):
+    """The plain path on the same trace: one circuit at a time, FIFO, in real time.
+    progress(n), if given, is called after each result with the number of results so far."""
     order = np.argsort(arrivals, kind="stable")
     t0 = time.perf_counter()
     results, outputs = [], {}
@@ -185,6 +186,8 @@ def serve_sequential(circuits, arrivals, precision: int = 32, keep_results: bool
             outputs[int(i)] = res
         results.append(Result(int(i), float(arrivals[i]), start, done, int(res[0][-1]),
                               s.stats()["term_updates"] - u0))
+        if progress:
+            progress(len(results))
     for s in sims.values():
         s.close()
     return results, outputs
@@ -221,14 +224,15 @@ class _Budget:
 
 
 def serve_trace_lanes(circuits, arrivals, budget_bytes: int, precision: int = 32, split_bytes: int = 256 << 20,
-                      large_in_flight: int = 1, keep_results: bool = False, batch_factory=None):
+                      large_in_flight: int = 1, keep_results: bool = False, batch_factory=None, progress=None):
     """Continuous batching with two lanes: requests predicted to need less than split_bytes
     go to one batch, the others to a second; each batch runs on its own HIP stream, driven by
     its own host thread, so small requests do not wait behind the rounds of large ones. The
     large lane keeps at most large_in_flight requests in flight (large requests already fill
     the device, so sharing rounds among them only delays each one). Admission in arrival
     order per lane, against one shared memory budget (a lane with nothing in flight may always
-    admit its next request). Returns (results, outputs)."""
+    admit its next request). progress(n), if given, is called with the number of
+    requests the trace has handed to the lanes (every 100). Returns (results, outputs)."""
     import collections
     import threading
 
@@ -289,10 +293,12 @@ def serve_trace_lanes(circuits, arrivals, budget_bytes: int, precision: int = 32
     threads = [threading.Thread(target=work, args=(ln,), daemon=True) for ln in lanes]
     for t in threads:
         t.start()
-    for i in order:
+    for n_handed, i in enumerate(order, 1):
         wait = arrivals[i] - clock()
         if wait > 0:
             time.sleep(wait)
+        if progress and n_handed % 100 == 0:
+            progress(n_handed)
         need = predict_bytes(circuits[i], precision, max_n)
         if need > budget.total:
             raise ValueError(f"request {i} needs {need} bytes, more than the whole budget")

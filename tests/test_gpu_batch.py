@@ -146,7 +146,7 @@ def test_served_results_equal_alone():
                                      ("QIMAX_LOCAL_SORT_M", "1"), ("QIMAX_XCD_RANGES", "0"),
                                      ("QIMAX_SMALL_ROUNDS", "0"), ("QIMAX_FUSED_EXPAND", "0"),
                                      ("QIMAX_CHUNK_TILE", "2048"), ("QIMAX_CHUNK_TILE", "4096"),
-                                     ("QIMAX_DEFER_SPINS", "100000")])
+                                     ("QIMAX_DEFER_SPINS", "100000"), ("QIMAX_CLASSIC_PASSES", "1")])
 def test_tiling_and_sort_variants_bit_identical(variant, monkeypatch):
     """Image tilings built on the device from the fan-out bound (the default for rounds whose
     bound is small) or on the host after reading the image count back; the classic
@@ -203,13 +203,20 @@ def test_autotuner_settles_and_keeps_results(monkeypatch):
     c = W.c2_clifford_rz(seed=1, n=24, depth=100, n_rz=20)
     with Simulator(c.n, prune_eps=c.eps) as s:
         runs = []
-        for _ in range(4):
+        for _ in range(11):
             s.reset()
             s.run(c)
             runs.append(s.generators())
         st = s.stats()
-    say("tuned classes", st["tuned_classes"])
+        tun = s.tuning()
+    say("tuned classes", st["tuned_classes"], tun)
     assert st["tuned_classes"] > 0
+    # qimax_get_tuning: one entry per class; a fixed class chose its fastest candidate
+    fixed = [t for t in tun if t["best"] >= 0]
+    assert len(fixed) == st["tuned_classes"]
+    for t in fixed:
+        assert t["key_bytes"] == 8 and t["weight_bits"] == 64 and t["tried"] >= 3
+        assert t["ms"][t["best"]] == min(t["ms"])
     for r in runs[1:]:
         for x, y in zip(r, runs[0]):
             assert np.array_equal(x, y)
@@ -252,3 +259,18 @@ def test_predicted_footprint_covers_device_memory(case):
     need = serve.predict_bytes(c, 32, cls)
     say("footprint", case, "grew", peak - a0, "predicted", need)
     assert peak - a0 <= need
+
+
+def test_wide_offset_paths_bit_identical(monkeypatch):
+    """The count's 64-bit in-tile image offsets (taken by a tile of 2^32 images or more) and
+    the expansion's parent search in global memory (taken by a round of 2^31 images or more),
+    forced at small sizes with the count and the expansion as separate launches: the same
+    images in the same order, hence bit-identical results."""
+    cs = mixed_circuits()
+    ref = [alone(c) for c in cs]
+    monkeypatch.setenv("QIMAX_FUSED_EXPAND", "0")
+    monkeypatch.setenv("QIMAX_WIDE_OFFSETS", "1")
+    for c, r in zip(cs, ref):
+        say("wide offsets", c.name)
+        for x, y in zip(alone(c), r):
+            assert np.array_equal(x, y), c.name

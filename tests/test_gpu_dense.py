@@ -68,7 +68,7 @@ def test_autotuner_chooses_between_dense_and_sort(monkeypatch):
     monkeypatch.setenv("QIMAX_SMALL_ROUNDS", "0")
     with Simulator(c.n) as s:
         outs = []
-        for _ in range(6):
+        for _ in range(13):
             s.reset()
             s.run(c)
             outs.append(s.generators())

@@ -415,3 +415,23 @@ def test_wide_keys_initial_and_expect():
             assert v == 3 << (2 * (n - 1 - j))
         assert s.expect("Z" + "I" * (n - 1)) == 1.0
         assert s.expect("X" + "I" * (n - 1)) == 0.0
+
+
+def test_dense_two_qubit_operators_at_n12():
+    """Dense non-Clifford two-qubit operators (15 images per non-identity local Pauli) on
+    twelve qubits after a Clifford spread, against the oracle: 16x16 expansions on the general
+    path with many images per term."""
+    rng = np.random.default_rng(11)
+    n = 12
+    c = W.random_circuit(17, n, 60, gates=[W.Gate.H, W.Gate.S, W.Gate.CX])
+    s = Simulator(n)
+    o = oracle.Oracle(n)
+    s.run(c)
+    o.gates(c.gate, c.q0, c.q1, c.theta)
+    for k in range(4):
+        a, b = rng.choice(n, 2, replace=False).tolist()
+        R = D.ptm_from_unitary(_rand_unitary(rng, 4))
+        s.apply_layer([((a, b), R)])
+        o.ptm2(a, b, R)
+    say("dense 2q n12 terms", s.num_terms())
+    compare_fp64(s.generators(), oracle_arrays(o, n), tol=1e-11, label="dense 2q n12")
