@@ -1141,18 +1141,34 @@ k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __rest
       for (uint32_t g = a; g < e; ++g) pmap[g - c0] = (uint16_t)j;
     }
     __syncthreads();
-    for (uint32_t g = c0 + threadIdx.x; g < c1; g += kFuseBlock) {
-      const uint32_t j = pmap[g - c0];
-      K key = akey[j];
-      W wv = w[begin + j];
-      uint32_t neg = aneg[j];
-      expand_ops<K, WP>(key, wv, g - loff[j], pa, pa.E1, pa.E2, err);
-      if (pa.useB) key = apply_table(key, tk, tn, neg);
-      else for (uint32_t q = 0; q < pa.nB; ++q) key = apply_perm(key, pa.B[q], neg);
-      if (neg) wv = -wv;
-      keys_out[base + g] = key;
-      w_out[base + g] = wv;
-      for (uint32_t p = 0; p < n_hp; ++p) atomicAdd(&hw[p * kRadix + ((uint32_t)(key >> (8u * (hp_begin + p))) & 255u)], 1u);
+    // kFuseUnroll images per thread at a time: their parents' weight loads all in flight
+    // before the first is used
+    constexpr int kFuseUnroll = 4;
+    for (uint32_t g0 = c0 + threadIdx.x; g0 < c1; g0 += kFuseUnroll * kFuseBlock) {
+      uint32_t jj[kFuseUnroll];
+      W wp[kFuseUnroll];
+#pragma unroll
+      for (int u = 0; u < kFuseUnroll; ++u) {
+        const uint32_t g = min(g0 + (uint32_t)u * kFuseBlock, c1 - 1);
+        jj[u] = pmap[g - c0];
+        wp[u] = w[begin + jj[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kFuseUnroll; ++u) {
+        const uint32_t g = g0 + (uint32_t)u * kFuseBlock;
+        if (g >= c1) break;
+        const uint32_t j = jj[u];
+        K key = akey[j];
+        W wv = wp[u];
+        uint32_t neg = aneg[j];
+        expand_ops<K, WP>(key, wv, g - loff[j], pa, pa.E1, pa.E2, err);
+        if (pa.useB) key = apply_table(key, tk, tn, neg);
+        else for (uint32_t q = 0; q < pa.nB; ++q) key = apply_perm(key, pa.B[q], neg);
+        if (neg) wv = -wv;
+        keys_out[base + g] = key;
+        w_out[base + g] = wv;
+        for (uint32_t p = 0; p < n_hp; ++p) atomicAdd(&hw[p * kRadix + ((uint32_t)(key >> (8u * (hp_begin + p))) & 255u)], 1u);
+      }
     }
     __syncthreads();  // the map is rebuilt for the next window
   }
@@ -1306,21 +1322,25 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
     none();
     return;
   }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // The window [a, a + kChunkCap) of the segment goes to LDS first (with the key before it);
+  // the chunk bounds are found there (wave 0 from the tile start, wave 1 from the tile end),
+  // in global memory only where a bucket reaches past the window. Its loads (clamped to the
+  // image arrays, co.in_len elements) are issued before the segment bounds are looked up.
+  K kr[kItems];
+  {
+    const uint32_t ln = (uint32_t)(min(co.in_len, a + (uint64_t)kChunkCap) - a);  // >= b - a >= 1
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) kr[r] = keys_in[a + min((uint32_t)(r * kChunkBlock + threadIdx.x), ln - 1)];
+  }
+  const K before = (threadIdx.x == 0 && a > 0) ? keys_in[a - 1] : (K)0;
   const uint32_t s = tc.blk_seg[blk];
   const uint64_t seg_lo = tc.blk_begin[tc.seg_blk[s]], seg_hi = tc.blk_end[tc.seg_blk[s + 1] - 1];
   const uint32_t top_shift = 8u * (n_pass - m);
   auto top = [&](K key) -> K { return m == 0 ? (K)0 : (K)(key >> top_shift); };
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // The window [a, a + kChunkCap) of the segment goes to LDS first (with the key before it);
-  // the chunk bounds are found there (wave 0 from the tile start, wave 1 from the tile end),
-  // in global memory only where a bucket reaches past the window.
   const uint64_t wend = min(seg_hi, a + (uint64_t)kChunkCap);
   const uint32_t wn = (uint32_t)(wend - a);  // >= b - a >= 1
   {
-    K kr[kItems];
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) kr[r] = keys_in[a + min((uint32_t)(r * kChunkBlock + threadIdx.x), wn - 1)];
-    const K before = (threadIdx.x == 0 && a != seg_lo) ? keys_in[a - 1] : (K)0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t j = r * kChunkBlock + threadIdx.x;

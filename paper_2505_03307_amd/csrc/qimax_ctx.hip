@@ -1173,7 +1173,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
       const ChunkOut co{ctr + kCtrChunk, (uint64_t*)c->mstatus.p, c->mepoch, (uint32_t*)c->chunk_cnt.p,
                         (uint64_t*)c->chunk_start.p, (uint64_t*)c->chunk_off.p, c->ik[cur ^ 1].p, c->iw[cur ^ 1].p,
                         (uint64_t*)c->pseg[slot].p, fin, small ? (const uint32_t*)c->img_cnt.p : nullptr,
-                        c->defer_spins};
+                        c->defer_spins, n_work};
       HIPCHK(c, launch_chunk_sort_merge(c->KC, c->WP, c->fp64_acc, c->ik[cur].p, c->iw[cur].p, c->pk[slot].p,
                                         c->pw[slot].p, T_img, tc_chunk, n_pass, m_top, pas, sent, co,
                                         (uint32_t*)c->err.p, c->stream, &c->prof), "chunk sort");

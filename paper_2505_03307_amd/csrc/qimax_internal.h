@@ -272,6 +272,7 @@ struct ChunkOut {
   MergeFin fin;
   const uint32_t* img_cnt;
   uint32_t defer_spins;    // look-back polls before a chunk is deferred
+  uint64_t in_len;         // elements of the image arrays (keys_in / w_in) that may be read
 };
 hipError_t launch_chunk_sort_merge(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in, void* keys_out,
                                    void* w_out, uint64_t T, const Tiling& tc, uint32_t n_pass, uint32_t m,
