@@ -1812,6 +1812,292 @@ __global__ void __launch_bounds__(256) k_chunk_compact(const K* __restrict__ key
   }
 }
 
+// ------------------------------------------------------------ persistent small passes
+// Consecutive passes of one circuit whose segments stay small (at most kChunkCap terms and
+// images each, by the host's fan-out bound) in one launch: one block per segment keeps its
+// terms in a slot of kChunkCap in global memory (L2-resident at these sizes) and, pass after
+// pass, applies the A chain and counts the fan-outs, scans them in LDS, forms the images
+// (expansion and B chain: keys to LDS, weights to a scratch slot), sorts the keys stably in
+// LDS (LSD passes over the digits that vary), sums each run of equal keys in array order,
+// prunes, and writes the kept terms to the other slot. These are the images, the order and
+// the sums of the round-by-round small path, so the results agree bit for bit; only the
+// launches and the host's waits between the passes are gone. cnt[(p*S + s)*3 + {0,1,2}]
+// receives segment s's input terms, images and kept terms in pass p.
+constexpr int kGroupBlock = 512;
+template <typename K, int WP>
+__global__ void __launch_bounds__(kGroupBlock) k_small_passes(
+    const K* __restrict__ keys_in, const typename WTraits<WP>::W* __restrict__ w_in,
+    const uint64_t* __restrict__ seg_in, uint32_t S, const PassArgs* __restrict__ pas, uint32_t n_grp,
+    K* __restrict__ kslot0, typename WTraits<WP>::W* __restrict__ wslot0, K* __restrict__ kslot1,
+    typename WTraits<WP>::W* __restrict__ wslot1, typename WTraits<WP>::W* __restrict__ wimg,
+    uint32_t* __restrict__ cnt, int fp64_acc, uint32_t* err) {
+  using W = typename WTraits<WP>::W;
+  constexpr int kTabN = (int)sizeof(K) * 256;
+  constexpr int kItems = kChunkCap / kGroupBlock, kWaves = kGroupBlock / 64;
+  __shared__ K tk[kTabN];
+  __shared__ uint8_t tn[kTabN];
+  __shared__ K akey[kChunkCap];
+  __shared__ uint8_t negs[kChunkCap];
+  __shared__ uint32_t off[kChunkCap + 1];
+  __shared__ uint16_t pmap[kChunkCap];
+  __shared__ K sk[kChunkCap];
+  __shared__ uint16_t sidx[kChunkCap];
+  __shared__ __align__(16) uint32_t wrun[kWaves][kRadix];
+  __shared__ __align__(16) uint32_t dbase[kWaves][kRadix];
+  __shared__ uint32_t wdummy[kWaves][64];
+  __shared__ uint64_t scan_sh[kWaves];
+  __shared__ uint32_t nimg_sh;
+  __shared__ __align__(16) uint8_t vary_sh[kWaves * sizeof(K)];
+  const uint32_t s = blockIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t slot0 = (uint64_t)s * kChunkCap;
+  const K* kin = keys_in + seg_in[s];
+  const W* win = w_in + seg_in[s];
+  uint64_t n64 = seg_in[s + 1] - seg_in[s];
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  for (uint32_t p = 0; p < n_grp; ++p) {
+    const PassArgs pa = pas[p];
+    K* kout = ((p & 1u) ? kslot1 : kslot0) + slot0;
+    W* wout = ((p & 1u) ? wslot1 : wslot0) + slot0;
+    uint32_t* cp = cnt + ((uint64_t)p * S + s) * 3;
+    if (n64 > (uint64_t)kChunkCap || pa.drop) {  // the caller's bound did not hold
+      if (threadIdx.x == 0) {
+        atomicOr(err, kErrIndex | kErrFanout);
+        cp[0] = cp[1] = cp[2] = 0;
+      }
+      n64 = 0;
+      kin = kout;
+      win = wout;
+      continue;
+    }
+    const uint32_t n = (uint32_t)n64;
+    // ---- A chain and fan-out of every term, their scan (as the round's count)
+    if (pa.useA) stage_table(pa.tA, tk, tn);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kGroupBlock) {
+      K key = kin[i];
+      uint32_t neg = 0;
+      const uint64_t f = a_chain_and_fanout(key, neg, pa, tk, tn, err);
+      akey[i] = key;
+      negs[i] = (uint8_t)(neg & 1u);
+      off[i] = (uint32_t)min<uint64_t>(f, kChunkCap + 1);  // larger: flagged by the total below
+    }
+    __syncthreads();
+    {
+      const uint32_t r0 = min(threadIdx.x * (uint32_t)kItems, n), r1 = min(r0 + (uint32_t)kItems, n);
+      uint64_t sum = 0;
+      for (uint32_t i = r0; i < r1; ++i) sum += off[i];
+      uint64_t tot;
+      uint64_t run = block_excl_scan<kGroupBlock>(sum, scan_sh, &tot);
+      for (uint32_t i = r0; i < r1; ++i) {  // (each thread rewrites only its own run)
+        const uint32_t f = off[i];
+        off[i] = (uint32_t)min<uint64_t>(run, kChunkCap);
+        run += f;
+      }
+      if (threadIdx.x == 0) {
+        if (tot > (uint64_t)kChunkCap) atomicOr(err, kErrIndex | kErrFanout);
+        nimg_sh = tot > (uint64_t)kChunkCap ? 0u : (uint32_t)tot;
+        off[n] = nimg_sh;
+      }
+    }
+    __syncthreads();
+    const uint32_t n_img = nimg_sh;
+    for (uint32_t j = threadIdx.x; j < n; j += kGroupBlock) {
+      const uint32_t e = min(off[j + 1], n_img);
+      for (uint32_t g = off[j]; g < e; ++g) pmap[g] = (uint16_t)j;
+    }
+    __syncthreads();  // (the A table is no longer read)
+    if (pa.useB) {
+      stage_table(pa.tB, tk, tn);
+      __syncthreads();
+    }
+    // ---- the images (as the expansion): keys to LDS with their positions, weights to wimg
+    for (uint32_t g = threadIdx.x; g < n_img; g += kGroupBlock) {
+      const uint32_t j = pmap[g];
+      K key = akey[j];
+      W wv = win[j];
+      uint32_t neg = negs[j];
+      expand_ops<K, WP>(key, wv, g - off[j], pa, pa.E1, pa.E2, err);
+      if (pa.useB) key = apply_table(key, tk, tn, neg);
+      else for (uint32_t q = 0; q < pa.nB; ++q) key = apply_perm(key, pa.B[q], neg);
+      if (neg) wv = -wv;
+      sk[g] = key;
+      sidx[g] = (uint16_t)g;
+      wimg[slot0 + g] = wv;
+    }
+    for (int i = threadIdx.x; i < kWaves * kRadix; i += kGroupBlock) (&wrun[0][0])[i] = 0;
+    __syncthreads();
+    // ---- stable LSD passes in LDS over the digits that vary (a constant digit leaves a
+    // stable pass's order unchanged); elements in equal wave spans of whole 64-element rounds
+    if (n_img > 1) {
+      K vary = 0;
+      for (uint32_t j = threadIdx.x; j < n_img; j += kGroupBlock) vary |= sk[j] ^ sk[0];
+      vary = block_or<kGroupBlock>(vary, (K*)vary_sh);
+      const uint32_t span = (n_img + kWaves * 64 - 1) / (kWaves * 64) * 64, nr = span / 64;
+      for (uint32_t dp = 0; dp < (uint32_t)sizeof(K); ++dp) {
+        if (!((uint32_t)(vary >> (8u * dp)) & 255u)) continue;
+        K key[kItems];
+        uint16_t ix[kItems];
+        uint32_t rank[kItems], pk[kItems];
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+          const uint32_t li = min(wid * span + r * 64 + lane, n_img - 1);
+          key[r] = sk[li];
+          ix[r] = sidx[li];
+        }
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+          const uint32_t li = wid * span + r * 64 + lane;  // stable order: wave span, round, lane
+          const bool valid = (uint32_t)r < nr && li < n_img;
+          const uint32_t d = (uint32_t)(key[r] >> (8u * dp)) & (kRadix - 1);
+          // lanes with this lane's digit: no bit of the digit differs
+          const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
+          uint32_t dlo = ~(uint32_t)vm, dhi = ~(uint32_t)(vm >> 32);
+#pragma unroll
+          for (int bit = 0; bit < kRadixBits; ++bit) {
+            const int spread = __builtin_amdgcn_sbfe((int)d, bit, 1);
+            const uint64_t bb = __builtin_amdgcn_ballot_w64(spread != 0);
+            dlo |= (uint32_t)bb ^ (uint32_t)spread;
+            dhi |= (uint32_t)(bb >> 32) ^ (uint32_t)spread;
+          }
+          const uint64_t mk = ~(((uint64_t)dhi << 32) | dlo);
+          const int leader = __ffsll((long long)mk) - 1;
+          const bool lead_me = valid && lane == leader;
+          rank[r] = atomicAdd(lead_me ? &wrun[wid][d] : &wdummy[wid][lane], lead_me ? (uint32_t)__popcll(mk) : 0u);
+          pk[r] = d | ((uint32_t)(leader < 0 ? 0 : leader) << 8) | ((uint32_t)__popcll(mk & lt) << 16);
+        }
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) rank[r] = __shfl(rank[r], (pk[r] >> 8) & 63u, 64) + (pk[r] >> 16);
+        __syncthreads();
+        {
+          // every wave scans all 256 digit totals (lane l: digits 4l..4l+3) for its bases
+          uint32_t tot[4] = {0, 0, 0, 0}, pre[4] = {0, 0, 0, 0};
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) {
+            const uint4 cw4 = *(const uint4*)&wrun[w][4 * lane];
+            const uint32_t cw[4] = {cw4.x, cw4.y, cw4.z, cw4.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (w < wid) pre[j] += cw[j];
+              tot[j] += cw[j];
+            }
+          }
+          const uint32_t lane_sum = tot[0] + tot[1] + tot[2] + tot[3];
+          uint32_t run = (uint32_t)(wave_incl_scan((uint64_t)lane_sum) - lane_sum);
+          uint4 base;
+          base.x = run + pre[0]; run += tot[0];
+          base.y = run + pre[1]; run += tot[1];
+          base.z = run + pre[2]; run += tot[2];
+          base.w = run + pre[3];
+          *(uint4*)&dbase[wid][4 * lane] = base;
+        }
+        __syncthreads();  // every count read before the counters are cleared and keys move
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+          if ((uint32_t)r < nr && wid * span + r * 64 + lane < n_img) {
+            const uint32_t dst = dbase[wid][pk[r] & 255u] + rank[r];
+            sk[dst] = key[r];
+            sidx[dst] = ix[r];
+          }
+        }
+        for (int i = threadIdx.x; i < kWaves * kRadix; i += kGroupBlock) (&wrun[0][0])[i] = 0;
+        __syncthreads();
+      }
+    }
+    // ---- runs of equal keys summed in array order by the thread holding their head, pruned
+    // (thread t holds sorted positions [t*kItems, (t+1)*kItems); a run's sum is kept at its last
+    // item in the thread), then written in order to the other slot
+    const double thr = pa.thr;
+    const uint32_t j0 = threadIdx.x * kItems;
+    W wr[kItems], sums[kItems];
+    K kt[kItems];
+#pragma unroll
+    for (int t = 0; t < kItems; ++t) {
+      const uint32_t j = min(j0 + t, n_img ? n_img - 1 : 0u);
+      kt[t] = sk[j];
+      wr[t] = n_img ? wimg[slot0 + sidx[j]] : (W)0;
+    }
+    const K k_before = (j0 > 0 && j0 <= n_img) ? sk[j0 - 1] : (K)0;
+    const K k_after = j0 + kItems < n_img ? sk[j0 + kItems] : (K)0;
+    uint32_t keep_mask = 0, keep = 0;
+    auto sum_runs = [&](auto proto) {
+      auto acc = proto;
+      bool active = false;
+#pragma unroll
+      for (int t = 0; t < kItems; ++t) {
+        const uint32_t j = j0 + t;
+        const bool valid = j < n_img;
+        const bool head = valid && (j == 0 || kt[t] != (t ? kt[t - 1] : k_before));
+        const bool cont = j + 1 < n_img && (t + 1 < kItems ? kt[t + 1] : k_after) == kt[t];
+        if (head) {
+          acc = proto;
+          active = true;
+        }
+        if (active && valid) {
+          acc.add(wr[t]);
+          if (t + 1 == kItems && cont)
+            for (uint32_t i = j0 + kItems; i < n_img && sk[i] == kt[t]; ++i) acc.add(wimg[slot0 + sidx[i]]);
+          if (!cont || t + 1 == kItems) {
+            const W v = acc.value();
+            sums[t] = v;
+            if (fabs((double)v) > thr) {
+              keep_mask |= 1u << t;
+              ++keep;
+            }
+            active = false;
+          }
+        }
+      }
+    };
+    if constexpr (sizeof(W) == 8) sum_runs(PlainSum<W>{});
+    else if (fp64_acc) sum_runs(F64Sum{});
+    else sum_runs(RunSum<float>{});
+    uint64_t tot;
+    uint32_t o = (uint32_t)block_excl_scan<kGroupBlock>(keep, scan_sh, &tot);
+#pragma unroll
+    for (int t = 0; t < kItems; ++t) {
+      if (!(keep_mask & (1u << t))) continue;
+      kout[o] = kt[t];
+      wout[o] = sums[t];
+      ++o;
+    }
+    if (threadIdx.x == 0) {
+      cp[0] = n;
+      cp[1] = n_img;
+      cp[2] = (uint32_t)tot;
+    }
+    __syncthreads();  // the kept terms (global, this block's) before the next pass reads them
+    kin = kout;
+    win = wout;
+    n64 = tot;
+  }
+}
+
+// After k_small_passes: segment s's kept terms (its slot, cnt_last[s*3 + 2] of them) copied to
+// the pass output at the sum of the earlier segments' counts; seg_off receives the offsets.
+template <typename K, typename W>
+__global__ void __launch_bounds__(256) k_small_gather(const K* __restrict__ kslot, const W* __restrict__ wslot,
+                                                      const uint32_t* __restrict__ cnt_last, uint32_t S,
+                                                      K* __restrict__ keys_out, W* __restrict__ w_out,
+                                                      uint64_t* __restrict__ seg_off) {
+  __shared__ uint64_t base_sh;
+  const uint32_t s = blockIdx.x;
+  if (threadIdx.x == 0) {
+    uint64_t b = 0;
+    for (uint32_t q = 0; q < s; ++q) b += cnt_last[q * 3 + 2];
+    base_sh = b;
+    seg_off[s] = b;
+    if (s + 1 == S) seg_off[S] = b + cnt_last[s * 3 + 2];
+  }
+  __syncthreads();
+  const uint64_t base = base_sh, src = (uint64_t)s * kChunkCap;
+  const uint32_t m = min(cnt_last[s * 3 + 2], (uint32_t)kChunkCap);
+  for (uint32_t i = threadIdx.x; i < m; i += 256) {
+    keys_out[base + i] = kslot[src + i];
+    w_out[base + i] = wslot[src + i];
+  }
+}
+
 // ------------------------------------------------------------------ dense accumulation
 // The dense alternative to sorting (the paper's fixed-size weight tensor of its v2 mode,
 // Sec. V): for a round whose keys index a small space (4^n per generator), every image adds
@@ -2270,7 +2556,7 @@ inline uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)((n + bl
 const char* kernel_kind_name(int k) {
   static const char* names[kKNum] = {"init", "count", "scan", "expand", "sort_hist", "sort_scatter",
                                      "merge_count", "merge_write", "compose_ptm", "chunk_sort", "count_expand",
-                                     "dense_merge", "chunk_finish"};
+                                     "dense_merge", "chunk_finish", "small_passes"};
   return (k >= 0 && k < kKNum) ? names[k] : "?";
 }
 
@@ -2437,6 +2723,35 @@ hipError_t launch_expand(int KC, int WP, const void* keys, const uint8_t* asign,
 }
 
 size_t fuse_tile() { return (size_t)kFuseTile; }
+
+hipError_t launch_small_passes(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in,
+                               const uint64_t* seg_in, uint32_t S, const PassArgs* pas, uint32_t n_grp,
+                               void* const kslot[2], void* const wslot[2], void* wimg, uint32_t* cnt,
+                               void* keys_out, void* w_out, uint64_t* seg_off_out, uint32_t* err, hipStream_t s,
+                               Prof* prof) {
+  if (S == 0 || n_grp == 0 || KC > 1) return hipErrorInvalidValue;  // keys of 4 or 8 bytes
+  hipEvent_t ev = prof_begin(prof, s, kKSmallPasses);
+  const int last = (int)((n_grp - 1) & 1u);
+  const uint32_t* cnt_last = cnt + (uint64_t)(n_grp - 1) * S * 3;
+#define QIMAX_SMALL_PASSES(K)                                                                                     \
+  if (WP == 64) {                                                                                                 \
+    k_small_passes<K, 64><<<S, kGroupBlock, 0, s>>>((const K*)keys_in, (const double*)w_in, seg_in, S, pas, n_grp, \
+                                                    (K*)kslot[0], (double*)wslot[0], (K*)kslot[1], (double*)wslot[1], \
+                                                    (double*)wimg, cnt, fp64_acc, err);                           \
+    k_small_gather<K, double><<<S, 256, 0, s>>>((const K*)kslot[last], (const double*)wslot[last], cnt_last, S,    \
+                                                (K*)keys_out, (double*)w_out, seg_off_out);                       \
+  } else {                                                                                                        \
+    k_small_passes<K, 32><<<S, kGroupBlock, 0, s>>>((const K*)keys_in, (const float*)w_in, seg_in, S, pas, n_grp,  \
+                                                    (K*)kslot[0], (float*)wslot[0], (K*)kslot[1], (float*)wslot[1], \
+                                                    (float*)wimg, cnt, fp64_acc, err);                            \
+    k_small_gather<K, float><<<S, 256, 0, s>>>((const K*)kslot[last], (const float*)wslot[last], cnt_last, S,      \
+                                               (K*)keys_out, (float*)w_out, seg_off_out);                         \
+  }
+  if (KC == 0) { QIMAX_SMALL_PASSES(uint32_t) } else { QIMAX_SMALL_PASSES(uint64_t) }
+#undef QIMAX_SMALL_PASSES
+  prof_end(prof, s, ev, kKSmallPasses, 0.0);  // bytes: added by the caller once the counts are back
+  return hipGetLastError();
+}
 
 hipError_t launch_count_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const Tiling& tl,
                                const PassArgs* pas, const uint32_t* seg_entry, uint64_t* status, uint32_t* ctr,

@@ -287,6 +287,7 @@ struct qimax_ctx {
   DevBuf ptab;  // chain tables of a whole call, compiled in one launch
   DevBuf akeys, asign;  // input terms after their pass's A chain, and the signs (count -> expand)
   DevBuf chunk_off, chunk_cnt, chunk_start;  // chunk-local merge: offset, kept terms, deferred runs per chunk
+  DevBuf grp_cnt;  // persistent small passes: counts per pass and segment
   DevBuf img_cnt;                            // small rounds: image count per segment
   DevBuf ghist, sbase, sstatus, tile_ctr;  // single-sweep sort state
   uint64_t epoch = 0;
@@ -303,6 +304,7 @@ struct qimax_ctx {
   uint32_t chunk_tile = 0;    // nominal chunk of a fused round (0: from the expected bucket size)
   bool wide_offsets = false;  // count and expansion take their paths for 2^32 / 2^31 images (tests)
   bool classic_passes = false;  // multi-launch global sort passes in every round (tests)
+  bool small_groups = true;  // consecutive small passes in one launch (k_small_passes)
   int dense_mode = 0;         // dense accumulation: 0 off, 1 wherever it applies, 2 a tuner candidate
   DevBuf dense_acc;           // its fixed-point slots
   int local_sort_m = -1;      // >= 0: force the number of top-digit passes
@@ -756,18 +758,24 @@ inline uint64_t pass_updates(const Pass& p, uint64_t t_in, uint64_t t_img, uint6
   return p.ng_in * t_in + (p.E.empty() ? 0 : t_img) + p.ng_out * t_out;
 }
 
-// Runs one round: every segment s of the input (k_in, w_in; device offsets seg_in, host
-// offsets so_in) is processed with the pass of entries[seg_entry[s]], in one set of
-// launches for all segments. The merged result goes to pass slot `slot`; so_out / so_img
-// receive the output and image segment offsets. upd[e] receives entry e's term updates.
-qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, const std::vector<uint32_t>& seg_entry,
-                       const void* k_in, const void* w_in, const uint64_t* seg_in, const std::vector<uint64_t>& so_in,
-                       int slot, std::vector<uint64_t>& so_out, std::vector<uint64_t>& so_img,
-                       std::vector<uint64_t>* upd) {
+// A round's descriptors staged for upload (in c->stage[0]; their device copy, c->desc, is
+// pulled by the round's first launch): the entries' permutations and expanding-operator
+// descriptors, one PassArgs per entry, the segments' entry numbers and the chain-table jobs.
+struct RoundDesc {
+  const PassArgs* pas = nullptr;   // device addresses
+  const uint32_t* sent = nullptr;
+  const TableJob* jobs = nullptr;
+  size_t n_jobs = 0;
+  size_t host_bytes = 0;
+  size_t e_bytes = 0;              // largest expanding-operator descriptor set of an entry
+  bool any_b_tables = false;
+  uint32_t max_n = 1;
+};
+
+qimax_status build_round_desc(qimax_ctx* c, const std::vector<RoundEntry>& entries,
+                              const std::vector<uint32_t>& seg_entry, RoundDesc& rd) {
   const uint32_t S = (uint32_t)seg_entry.size();
-  const uint64_t T_in = so_in[S];
   const size_t E = entries.size();
-  // ---- descriptors of every entry
   std::vector<PermDesc> perms;
   std::vector<Exp1Desc> e1;
   std::vector<Exp2Desc> e2;
@@ -857,8 +865,36 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     pas_h[e] = pa;
   }
   std::memcpy(hs + oS, seg_entry.data(), S * 4);
-  const PassArgs* pas = (const PassArgs*)(ds + oA);
-  const uint32_t* sent = (const uint32_t*)(ds + oS);
+  rd.pas = (const PassArgs*)(ds + oA);
+  rd.sent = (const uint32_t*)(ds + oS);
+  rd.jobs = (const TableJob*)(ds + oJ);
+  rd.n_jobs = n_jobs;
+  rd.host_bytes = host_bytes;
+  rd.e_bytes = e_bytes;
+  rd.any_b_tables = any_b_tables;
+  rd.max_n = max_n;
+  return QIMAX_OK;
+}
+
+// Runs one round: every segment s of the input (k_in, w_in; device offsets seg_in, host
+// offsets so_in) is processed with the pass of entries[seg_entry[s]], in one set of
+// launches for all segments. The merged result goes to pass slot `slot`; so_out / so_img
+// receive the output and image segment offsets. upd[e] receives entry e's term updates.
+qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, const std::vector<uint32_t>& seg_entry,
+                       const void* k_in, const void* w_in, const uint64_t* seg_in, const std::vector<uint64_t>& so_in,
+                       int slot, std::vector<uint64_t>& so_out, std::vector<uint64_t>& so_img,
+                       std::vector<uint64_t>* upd) {
+  const uint32_t S = (uint32_t)seg_entry.size();
+  const uint64_t T_in = so_in[S];
+  const size_t E = entries.size();
+  RoundDesc rd;
+  QCHK(build_round_desc(c, entries, seg_entry, rd));
+  uint8_t* ds = (uint8_t*)c->desc.p;
+  const PassArgs* pas = rd.pas;
+  const uint32_t* sent = rd.sent;
+  const size_t host_bytes = rd.host_bytes, n_jobs = rd.n_jobs, e_bytes = rd.e_bytes;
+  const bool any_b_tables = rd.any_b_tables;
+  const uint32_t max_n = rd.max_n;
   const bool sweep = !c->classic_sort;
   const uint32_t key_bits = 2u * max_n;
   const uint32_t n_pass = (key_bits + kRadixBits - 1) / kRadixBits;
@@ -912,8 +948,7 @@ qimax_status run_round(qimax_ctx* c, const std::vector<RoundEntry>& entries, con
     HIPCHK(c, launch_round_start(blob, ds, host_bytes, (uint32_t*)c->err.p, ctr, 256,
                                  (uint32_t*)c->ghist.p, nh, seg_in, S, job, T_in, c->stream), "round start");
   }
-  HIPCHK(c, launch_build_tables(c->KC, (const TableJob*)(ds + oJ), (uint32_t)n_jobs, c->stream, &c->prof),
-         "chain tables");
+  HIPCHK(c, launch_build_tables(c->KC, rd.jobs, (uint32_t)n_jobs, c->stream, &c->prof), "chain tables");
   // ---- fan-out count fused with its scan -> image offsets of every input term
   // mstatus: one word per tile, shared by the count and merge sweeps (distinct epochs)
   auto status_words = [&](uint64_t tiles) -> qimax_status {
@@ -1444,6 +1479,121 @@ qimax_status prebuild_tables(qimax_ctx* c, std::vector<Pass>& passes) {
   return QIMAX_OK;
 }
 
+// How many passes from i0 on (at most kMaxGroupPasses) one launch of k_small_passes can run:
+// every segment's terms, multiplied by each pass's fan-out bound in turn, stay within a chunk
+// (so do its images). 0 or 1: run the passes as rounds.
+constexpr size_t kMaxGroupPasses = 64;
+size_t small_group_len(const qimax_ctx* c, const std::vector<Pass>& passes, size_t i0,
+                       const std::vector<uint64_t>& so_in) {
+  if (!c->small_groups || !c->small_rounds || c->classic_sort || c->host_tiling || c->KC > 1 || c->n > kSmallMaxSegs)
+    return 0;
+  std::vector<double> len(c->n);
+  for (uint32_t s = 0; s < c->n; ++s) len[s] = (double)(so_in[s + 1] - so_in[s]);
+  size_t k = 0;
+  while (i0 + k < passes.size() && k < kMaxGroupPasses) {
+    const double f = std::max(1.0, passes[i0 + k].fanout_bound);
+    bool fits = true;
+    for (uint32_t s = 0; s < c->n && fits; ++s) fits = f * len[s] <= (double)kChunkCap;
+    if (!fits) break;
+    for (uint32_t s = 0; s < c->n; ++s) len[s] *= f;
+    ++k;
+  }
+  return k;
+}
+
+// Passes i0 .. i0+k-1 of the context's circuit in one launch of k_small_passes (one block per
+// generator, the terms in LDS-sized slots between the passes); so_ins / so_imgs / so_outs
+// receive each pass's segment offsets of its input terms, images and kept terms, and the
+// last pass's terms go to pass slot `slot`. Counters as for k rounds.
+qimax_status run_small_group(qimax_ctx* c, std::vector<Pass>& passes, size_t i0, size_t k, const void* k_in,
+                             const void* w_in, const uint64_t* s_in, const std::vector<uint64_t>& so_in, int slot,
+                             std::vector<std::vector<uint64_t>>& so_ins, std::vector<std::vector<uint64_t>>& so_imgs,
+                             std::vector<std::vector<uint64_t>>& so_outs) {
+  const uint32_t S = c->n;
+  std::vector<RoundEntry> en(k);
+  for (size_t p = 0; p < k; ++p) {
+    en[p].pass = &passes[i0 + p];
+    en[p].n = c->n;
+    en[p].thr = (i0 + p + 1 == passes.size()) ? c->eps : 0.0;
+  }
+  const std::vector<uint32_t> seg_entry(S, 0);
+  RoundDesc rd;
+  QCHK(build_round_desc(c, en, seg_entry, rd));
+  const uint64_t T_in = so_in[S];
+  QCHK(ensure(c, c->tile_ctr, 256 * 4));
+  {
+    // the round's first launch clears the error word and counters and pulls the descriptors
+    // (the input tiling it also builds is not used by the group)
+    uint32_t n_tin = 0;
+    for (uint32_t s = 0; s < S; ++s) n_tin += (uint32_t)((so_in[s + 1] - so_in[s] + kSortTile - 1) / kSortTile);
+    const size_t o1 = 0, o2 = align256((size_t)n_tin * 8), o3 = o2 + align256((size_t)n_tin * 8);
+    const size_t o4 = o3 + align256((size_t)n_tin * 4), o5 = o4 + align256((size_t)(S + 1) * 4);
+    const size_t o6 = o5 + 256;
+    QCHK(ensure(c, c->dtile[2], o6 + 256));
+    uint8_t* d = (uint8_t*)c->dtile[2].p;
+    const TileJob2 job{(uint64_t)kSortTile, n_tin, 0, (uint64_t*)(d + o1), (uint64_t*)(d + o2), (uint32_t*)(d + o3),
+                       (uint32_t*)(d + o4), (uint32_t*)(d + o5), (uint32_t*)(d + o6)};
+    const void* blob = nullptr;
+    QCHK(rec_src(c, c->stage[0], c->stage_dev[0], rd.host_bytes, &blob));
+    HIPCHK(c, launch_round_start(blob, c->desc.p, rd.host_bytes, (uint32_t*)c->err.p, (uint32_t*)c->tile_ctr.p, 256,
+                                 (uint32_t*)c->ghist.p, 0, s_in, S, job, T_in, c->stream), "round start");
+  }
+  HIPCHK(c, launch_build_tables(c->KC, rd.jobs, (uint32_t)rd.n_jobs, c->stream, &c->prof), "chain tables");
+  const size_t eb = c->kb, wbt = c->wb;
+  const uint64_t n_work = (uint64_t)S * kChunkCap;
+  for (int i = 0; i < 2; ++i) {
+    QCHK(ensure(c, c->ik[i], n_work * eb));
+    QCHK(ensure(c, c->iw[i], n_work * wbt));
+  }
+  QCHK(ensure(c, c->pk[slot], n_work * eb));
+  QCHK(ensure(c, c->pw[slot], n_work * wbt));  // (also the images' weights during the passes)
+  QCHK(ensure(c, c->pseg[slot], (S + 1) * 8));
+  const size_t cnt_words = (k * S * 3 + 1) / 2;
+  QCHK(ensure(c, c->grp_cnt, cnt_words * 8));
+  void* const ks[2] = {c->ik[0].p, c->ik[1].p};
+  void* const ws[2] = {c->iw[0].p, c->iw[1].p};
+  HIPCHK(c, launch_small_passes(c->KC, c->WP, c->fp64_acc, k_in, w_in, s_in, S, rd.pas, (uint32_t)k, ks, ws,
+                                c->pw[slot].p, (uint32_t*)c->grp_cnt.p, c->pk[slot].p, c->pw[slot].p,
+                                (uint64_t*)c->pseg[slot].p, (uint32_t*)c->err.p, c->stream, &c->prof),
+         "small passes");
+  uint32_t e = 0;
+  QCHK(readback(c, c->grp_cnt.p, cnt_words, &e));
+  if (e) return fail(c, (e & kErrFanout) ? QIMAX_ETOOLARGE : QIMAX_EDEVICE, "small passes:" + err_text(e));
+  const uint32_t* h = (const uint32_t*)c->pinned;
+  so_ins.assign(k, {});
+  so_imgs.assign(k, {});
+  so_outs.assign(k, {});
+  const uint32_t n_digits = (2u * c->n + kRadixBits - 1) / kRadixBits;
+  double prof_bytes = 0.0;
+  for (size_t p = 0; p < k; ++p) {
+    auto& si = so_ins[p];
+    auto& sg = so_imgs[p];
+    auto& so = so_outs[p];
+    si.assign(S + 1, 0);
+    sg.assign(S + 1, 0);
+    so.assign(S + 1, 0);
+    for (uint32_t s = 0; s < S; ++s) {
+      const uint32_t* q = h + (p * S + s) * 3;
+      si[s + 1] = si[s] + q[0];
+      sg[s + 1] = sg[s] + q[1];
+      so[s + 1] = so[s] + q[2];
+    }
+    if (si != (p ? so_outs[p - 1] : so_in))
+      return fail(c, QIMAX_EDEVICE, "small passes: a pass's input counts do not match the previous output");
+    uint64_t upd = 0;
+    for (uint32_t s = 0; s < S; ++s)
+      upd += pass_updates(*en[p].pass, si[s + 1] - si[s], sg[s + 1] - sg[s], so[s + 1] - so[s]);
+    c->st.term_updates += upd;
+    c->st.alg_bytes += (double)(si[S] + so[S]) * (double)(eb + wbt);
+    c->st.rounds += 1;
+    c->st.images += sg[S];
+    c->st.sort_elems += sg[S] * n_digits;
+    prof_bytes += (double)(si[S] + sg[S] + so[S]) * (double)(eb + wbt);
+  }
+  if (c->prof.on && ((c->prof.mask >> kKSmallPasses) & 1u)) c->prof.bytes[kKSmallPasses] += prof_bytes;
+  return QIMAX_OK;
+}
+
 qimax_status apply_ops(qimax_ctx* c, std::vector<HostOp>& ops) {
   if (c->broken) return fail(c, QIMAX_ESTATE, "context unusable after an earlier device error");
   BusyTimer bt(c);
@@ -1475,6 +1625,26 @@ qimax_status apply_ops(qimax_ctx* c, std::vector<HostOp>& ops) {
   std::vector<uint32_t> seg_entry(c->n, 0);
   int slot = 0;
   for (size_t i = 0; i < passes.size(); ++i) {
+    const size_t kg = small_group_len(c, passes, i, so_in);
+    if (kg >= 2) {  // consecutive small passes: one launch
+      std::vector<std::vector<uint64_t>> gi, gg, go;
+      qimax_status s = run_small_group(c, passes, i, kg, k_in, w_in, s_in, so_in, slot, gi, gg, go);
+      if (s != QIMAX_OK) return s;  // committed state untouched
+      if (c->gen_updates.size() != c->n) c->gen_updates.assign(c->n, 0);
+      for (size_t p = 0; p < kg; ++p) {
+        for (uint32_t j = 0; j < c->n; ++j)
+          c->gen_updates[j] += pass_updates(passes[i + p], gi[p][j + 1] - gi[p][j], gg[p][j + 1] - gg[p][j],
+                                            go[p][j + 1] - go[p][j]);
+        if (!passes[i + p].E.empty()) c->st.passes += 1;
+      }
+      k_in = c->pk[slot].p;
+      w_in = c->pw[slot].p;
+      s_in = (const uint64_t*)c->pseg[slot].p;
+      so_in = go.back();
+      slot ^= 1;
+      i += kg - 1;
+      continue;
+    }
     RoundEntry en;
     en.pass = &passes[i];
     en.n = c->n;
@@ -2120,6 +2290,8 @@ qimax_status qimax_create(uint32_t n, const qimax_opts* opts, qimax_ctx** out) {
     if (env && env[0])
       c->chunk_tile = std::min<uint32_t>(std::max<uint32_t>((uint32_t)std::strtoul(env, nullptr, 10), kExpandTile),
                                          (uint32_t)kChunkCap);
+    env = std::getenv("QIMAX_SMALL_GROUPS");  // 0: every small pass as a round of its own
+    c->small_groups = !(env && env[0] == '0');
     env = std::getenv("QIMAX_CLASSIC_PASSES");  // 1: multi-launch global passes in the single-sweep rounds
     c->classic_passes = env && env[0] == '1';
     env = std::getenv("QIMAX_WIDE_OFFSETS");  // 1: the count's and expansion's paths for huge rounds
@@ -2725,7 +2897,7 @@ void qimax_destroy(qimax_ctx* c) {
   DevBuf* bufs[] = {&c->keys, &c->w, &c->seg, &c->pk[0], &c->pk[1], &c->pw[0], &c->pw[1], &c->pseg[0],
                     &c->pseg[1], &c->ik[0], &c->ik[1], &c->iw[0], &c->iw[1], &c->cnt, &c->off, &c->scan_tmp,
                     &c->hist, &c->hist_off, &c->blk_begin, &c->blk_end, &c->blk_seg, &c->seg_blk, &c->blk_cnt,
-                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->img_cnt, &c->dense_acc, &c->chunk_cnt, &c->chunk_start,
+                    &c->blk_off, &c->img_seg, &c->desc, &c->desc2, &c->err, &c->f64tmp, &c->gr_in, &c->gr_out, &c->ghist, &c->sbase, &c->sstatus, &c->tile_ctr, &c->mstatus, &c->dtile[0], &c->dtile[1], &c->dtile[2], &c->ptab, &c->akeys, &c->asign, &c->img_cnt, &c->dense_acc, &c->chunk_cnt, &c->chunk_start, &c->grp_cnt,
                     &c->chunk_off};
   for (DevBuf* b : bufs) dev_free(c, *b);
   if (c->pinned) (void)hipHostFree(c->pinned);

@@ -137,7 +137,7 @@ enum : uint32_t {
 // algorithmic bytes each launch must move (what the roofline is measured against).
 enum KernelKind : int {
   kKInit, kKCount, kKScan, kKExpand, kKSortHist, kKSortScatter, kKMergeCount, kKMergeWrite, kKCompose, kKChunkSort,
-  kKCountExpand, kKDense, kKChunkFinish, kKNum
+  kKCountExpand, kKDense, kKChunkFinish, kKSmallPasses, kKNum
 };
 const char* kernel_kind_name(int k);
 
@@ -326,6 +326,18 @@ hipError_t launch_make_tiles2(const uint64_t* off, const uint64_t* seg_in, uint3
 // w_out (out_cap elements), digit counts of passes hp_begin .. n_pass-1 to ghist.
 constexpr int kFuseMaxFanout = 16;
 size_t fuse_tile();
+
+// Several consecutive passes of one circuit in one launch (k_small_passes), for passes whose
+// segments stay within kChunkCap terms and images (the caller's fan-out bound): pas holds
+// n_grp PassArgs (pass p of the group), kslot / wslot two slot buffers and wimg one scratch
+// of S * kChunkCap elements each; cnt (n_grp * S * 3 words) receives every pass's input,
+// image and kept counts per segment; the last pass's terms go to keys_out / w_out with the
+// segment offsets in seg_off_out (S + 1). Keys of 4 or 8 bytes.
+hipError_t launch_small_passes(int KC, int WP, int fp64_acc, const void* keys_in, const void* w_in,
+                               const uint64_t* seg_in, uint32_t S, const PassArgs* pas, uint32_t n_grp,
+                               void* const kslot[2], void* const wslot[2], void* wimg, uint32_t* cnt,
+                               void* keys_out, void* w_out, uint64_t* seg_off_out, uint32_t* err, hipStream_t s,
+                               Prof* prof = nullptr);
 hipError_t launch_count_expand(int KC, int WP, const void* keys, const void* w, uint64_t T_in, const Tiling& tl,
                                const PassArgs* pas, const uint32_t* seg_entry, uint64_t* status, uint32_t* ctr,
                                uint64_t epoch, uint64_t* img_seg, void* keys_out, void* w_out, uint64_t out_cap,

@@ -146,7 +146,8 @@ def test_served_results_equal_alone():
                                      ("QIMAX_LOCAL_SORT_M", "1"), ("QIMAX_XCD_RANGES", "0"),
                                      ("QIMAX_SMALL_ROUNDS", "0"), ("QIMAX_FUSED_EXPAND", "0"),
                                      ("QIMAX_CHUNK_TILE", "2048"), ("QIMAX_CHUNK_TILE", "4096"),
-                                     ("QIMAX_DEFER_SPINS", "100000"), ("QIMAX_CLASSIC_PASSES", "1")])
+                                     ("QIMAX_DEFER_SPINS", "100000"), ("QIMAX_CLASSIC_PASSES", "1"),
+                                     ("QIMAX_SMALL_GROUPS", "0")])
 def test_tiling_and_sort_variants_bit_identical(variant, monkeypatch):
     """Image tilings built on the device from the fan-out bound (the default for rounds whose
     bound is small) or on the host after reading the image count back; the classic
