@@ -687,7 +687,7 @@ __device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
 // earlier tiles of its segment for their prefix (decoupled look-back), and the digit's base
 // within the segment comes from the upfront histogram (base).
 template <typename K, typename W, bool kSweep>
-__global__ void __launch_bounds__(kSortBlock)
+__global__ void __launch_bounds__(kSortBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __restrict__ keys_out,
                W* __restrict__ w_out, uint64_t T, uint32_t shift, Tiling tl,
                const uint64_t* __restrict__ hist_off, const uint32_t* __restrict__ ghist_p, uint32_t gstride,
@@ -696,11 +696,16 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   constexpr int kWaves = kSortBlock / 64;
   constexpr int kRounds = kSortItems;                 // rounds per wave
   constexpr int kWaveSpan = 64 * kRounds;             // tile elements per wave
+  constexpr int kWords = sizeof(K) > 8 ? 2 : 1;
+  // Four blocks per CU: under 40 KB of LDS and 128 VGPRs per thread. The digit of a sorted
+  // slot is read back from the staged key word (one-word keys) and kept in registers for the
+  // weights; two-word keys keep it in LDS, since the digit may lie in either word.
+  constexpr bool kDigLds = kWords > 1;
+  static_assert(kSortBlock == kRadix && kRounds % 4 == 0, "one thread per digit; four digits a word");
   __shared__ uint64_t stage[kSortTile];               // key words, then weights (as raw 64-bit)
-  __shared__ uint8_t sdig[kSortTile];                  // digit of each sorted slot
-  __shared__ uint32_t wrun[kWaves][kRadix];            // per-wave running digit counts
-  __shared__ uint32_t dstart[kRadix];                  // tile-local start of each digit
-  __shared__ uint64_t gbase[kRadix];                   // global destination of each digit
+  __shared__ uint8_t sdig[kDigLds ? kSortTile : 1];   // digit of each sorted slot (two-word keys)
+  __shared__ uint32_t wrun[kWaves][kRadix];            // per-wave running digit counts, then slot bases
+  __shared__ uint64_t gdst[kRadix];                    // destination of tile slot j of digit d: gdst[d] + j
   __shared__ uint64_t scan_sh[kSortBlock / 64];
   __shared__ uint32_t tile_sh;
 
@@ -752,17 +757,20 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   __syncthreads();
 
   K key[kRounds];
-  W wv[kRounds];
-  uint32_t rank[kRounds];
+  // the wave-local rank of each tile element waits in the (not yet used) staging area, so
+  // that it holds no registers across the look-back and the scan
+  uint16_t* const rk = reinterpret_cast<uint16_t*>(stage);
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  // all loads first, with no branch (slots past the tile re-read its last element), so that
-  // every load of the thread is in flight at once
+  // the tile's elements from a block-uniform base with 32-bit indexes (no 64-bit address
+  // per load); slots past the tile re-read its last element
+  const uint64_t ld_base = n_tile ? begin : 0;
+  const uint32_t ld_last = n_tile ? n_tile - 1 : 0;
+  const K* __restrict__ kb = keys_in + ld_base;
+  // all key loads first, with no branch, so that every load of the thread is in flight at once
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t li = wid * kWaveSpan + r * 64 + lane;
-    const uint64_t gi = n_tile ? begin + min(li, n_tile - 1) : 0;
-    key[r] = keys_in[gi];
-    wv[r] = w_in[gi];
+    key[r] = kb[min(li, ld_last)];
   }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -780,18 +788,19 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
     const int leader = __ffsll((long long)m) - 1;  // lowest lane with this digit
     if (valid && lane == leader) bs = atomicAdd(&wrun[wid][d], (uint32_t)__popcll(m));
     bs = __shfl(bs, leader < 0 ? 0 : leader, 64);
-    rank[r] = valid ? bs + (uint32_t)__popcll(m & lt) : 0u;
+    if (valid) rk[li] = (uint16_t)(bs + (uint32_t)__popcll(m & lt));
   }
   __syncthreads();
-  // per-digit totals of the tile, wave prefixes, digit starts
+  // per-digit totals of the tile and wave prefixes
   uint32_t tile_cnt = 0;
   const int d = threadIdx.x;  // kSortBlock == kRadix
+  uint32_t wpre[kWaves];
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) {
-    const uint32_t c = wrun[w][d];
-    wrun[w][d] = tile_cnt;  // becomes the wave prefix
-    tile_cnt += c;
+    wpre[w] = tile_cnt;
+    tile_cnt += wrun[w][d];
   }
+  uint64_t gbase = 0;
   if constexpr (kSweep) {
     // publish this tile's count, then collect the prefix of the earlier tiles of the segment
     uint64_t* my = status + (uint64_t)b * kRadix + d;
@@ -816,38 +825,58 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
       }
       st_store(my, ep | kStPre | (excl + tile_cnt));
     }
-    gbase[d] = excl;
+    gbase = excl;
   }
   // one scan gives the tile-local digit starts (low 16 bits: a tile holds at most 4096 < 2^16
   // elements) and, in a sweep, the segment-wide start of every digit (high bits)
   uint64_t tot;
   const uint64_t ds2 = block_excl_scan<kSortBlock>((seg_cnt << 16) | tile_cnt, scan_sh, &tot);
-  const uint64_t ds = ds2 & 0xFFFFu;
-  if constexpr (kSweep) gbase[d] += seg_begin + (ds2 >> 16);
-  dstart[d] = (uint32_t)ds;
-  if constexpr (!kSweep) gbase[d] = tile_cnt ? hist_off[hist_pos(tl, b, d)] : 0;
+  const uint32_t ds = (uint32_t)(ds2 & 0xFFFFu);
+  if constexpr (kSweep) gbase += seg_begin + (ds2 >> 16);
+  else gbase = tile_cnt ? hist_off[hist_pos(tl, b, d)] : 0;
+  // slot j of digit d (ds <= j < ds + tile_cnt) goes to gbase + (j - ds); modular arithmetic
+  // keeps the difference exact for the digits that occur
+  gdst[d] = gbase - ds;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) wrun[w][d] = ds + wpre[w];  // slot base of (wave, digit)
   __syncthreads();
-  // stage keys at their tile-local sorted positions (one 64-bit word of the key per round)
+  // tile-local sorted position of every element of the thread
   uint32_t pos[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t li = wid * kWaveSpan + r * 64 + lane;
-    if (li < n_tile) {
+    const uint32_t dd = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+    pos[r] = li < n_tile ? wrun[wid][dd] + rk[li] : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  // stage keys at those positions (one 64-bit word of the key per round)
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    if (pos[r] != 0xFFFFFFFFu) {
       const uint32_t dd = (uint32_t)(key[r] >> shift) & (kRadix - 1);
-      pos[r] = dstart[dd] + wrun[wid][dd] + rank[r];
       if (pos[r] < (uint32_t)kSortTile) {
         stage[pos[r]] = (uint64_t)key[r];
-        sdig[pos[r]] = (uint8_t)dd;
+        if constexpr (kDigLds) sdig[pos[r]] = (uint8_t)dd;
       } else {
         atomicOr(err, kErrIndex | kErrSort);
       }
-    } else {
-      pos[r] = 0xFFFFFFFFu;
     }
   }
+  // the weights are needed only once the keys are out: their loads fly during the key
+  // stores (loaded this late, they do not share registers with the keys)
+  W wv[kRounds];
+  const W* __restrict__ wb = w_in + ld_base;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t li = wid * kWaveSpan + r * 64 + lane;
+    wv[r] = wb[min(li, ld_last)];
+  }
   __syncthreads();
-  // write keys out in sorted tile order (coalesced within each digit run)
-  constexpr int kWords = sizeof(K) > 8 ? 2 : 1;
+  // write keys out in sorted tile order (coalesced within each digit run); the digits of this
+  // thread's slots are kept, four to a register, for the weights
+  uint32_t dpk[kRounds / 4];
+#pragma unroll
+  for (int q = 0; q < kRounds / 4; ++q) dpk[q] = 0;
 #pragma unroll
   for (int word = 0; word < kWords; ++word) {
     if (word) {
@@ -861,8 +890,11 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
     for (int r = 0; r < kRounds; ++r) {
       const uint32_t j = r * kSortBlock + threadIdx.x;
       if (j < n_tile) {
-        const uint32_t dd = sdig[j];
-        const uint64_t dst = gbase[dd] + (j - dstart[dd]);
+        uint32_t dd;
+        if constexpr (kDigLds) dd = sdig[j];
+        else dd = (uint32_t)(stage[j] >> shift) & (kRadix - 1);
+        if (word == 0) dpk[r >> 2] |= dd << (8 * (r & 3));
+        const uint64_t dst = gdst[dd] + j;
         if (dst < T) {
           if constexpr (kWords == 1) keys_out[dst] = (K)stage[j];
           else ((uint64_t*)keys_out)[2 * dst + word] = stage[j];
@@ -885,8 +917,8 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t j = r * kSortBlock + threadIdx.x;
     if (j < n_tile) {
-      const uint32_t dd = sdig[j];
-      const uint64_t dst = gbase[dd] + (j - dstart[dd]);
+      const uint32_t dd = (dpk[r >> 2] >> (8 * (r & 3))) & (kRadix - 1);
+      const uint64_t dst = gdst[dd] + j;
       W v;
       if constexpr (sizeof(W) == 8) v = __longlong_as_double((long long)stage[j]);
       else v = __uint_as_float((uint32_t)stage[j]);
