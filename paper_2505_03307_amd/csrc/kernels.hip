@@ -105,6 +105,15 @@ __device__ __forceinline__ uint32_t xcd_id() {
   return x & (kXcds - 1);
 }
 
+// Block index -> tile for launches of independent tiles: blocks are dealt to the XCDs in turn,
+// so block i of XCD x takes tile x * q + min(x, r) + i (q, r: n / kXcds, n % kXcds) and
+// neighbouring tiles run on one XCD at about the same time; the partial cache lines where
+// their outputs meet then merge in that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  const uint32_t x = b & (kXcds - 1), i = b / kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + min(x, r) + i;
+}
+
 // First tile b >= target with b a segment's first tile (seg_blk[0..S] is non-decreasing and
 // ends with the tile count).
 __device__ __forceinline__ uint32_t seg_boundary_at_or_after(const uint32_t* seg_blk, uint32_t S, uint32_t target) {
@@ -638,7 +647,8 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_hist(const K* __restrict__ 
                                                           Tiling tl, uint64_t* __restrict__ hist,
                                                           uint64_t hist_size, uint32_t* err) {
   __shared__ uint32_t h[kSortBlock / 64][kRadix];
-  const uint32_t b = blockIdx.x;
+  // consecutive tiles on one XCD: their counts of a digit are neighbouring words of hist
+  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
   if (tl.n_dev && b >= *tl.n_dev) return;  // launched for a bound on the tile count
   const int wid = threadIdx.x >> 6;
   for (int k = threadIdx.x; k < (kSortBlock / 64) * kRadix; k += kSortBlock) (&h[0][0])[k] = 0;
@@ -737,10 +747,8 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
     b = tile_sh;
     if (b == 0xFFFFFFFFu) return;  // every tile was claimed already
   } else {
-    // independent tiles: consecutive tiles on one XCD (blocks are dealt to the XCDs in turn),
-    // so the partial cache lines where neighbouring tiles' digit runs meet merge in one L2
-    const uint32_t n = gridDim.x, x = b & (kXcds - 1), i = b / kXcds, q = n / kXcds, r = n % kXcds;
-    b = x * q + min(x, r) + i;
+    // independent tiles: consecutive tiles on one XCD, where neighbouring tiles' digit runs meet
+    b = xcd_tile(b, gridDim.x);
   }
   if (tl.n_dev && b >= *tl.n_dev) return;  // past the tiles that exist
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
