@@ -1080,11 +1080,20 @@ k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __rest
   __shared__ uint64_t scan_sh[kWaves];
   __shared__ uint64_t base_sh;
   __shared__ uint32_t tile_sh;
+  // the expanding single-qubit operators' descriptors, read for every image, in LDS (a fan-out
+  // bound of 16 leaves at most four operators that expand; more, with columns of one entry,
+  // are read from global memory)
+  constexpr int kE1Lds = 4, kE1Words = (int)(sizeof(Exp1Desc) / 8);
+  __shared__ uint64_t e1sh[kE1Lds * kE1Words];
   if (threadIdx.x == 0) tile_sh = atomicAdd(ctr, 1u);
   __syncthreads();
   const uint32_t b = tile_sh;  // launched with exactly n_blocks blocks
   const uint32_t seg = tl.blk_seg[b];
   const PassArgs pa = pas[seg_entry[seg]];
+  const bool e1lds = pa.nE1 <= (uint32_t)kE1Lds;
+  if (e1lds)
+    for (uint32_t i = threadIdx.x; i < pa.nE1 * (uint32_t)kE1Words; i += kFuseBlock)
+      e1sh[i] = ((const uint64_t*)pa.E1)[i];
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
   const uint32_t n = (uint32_t)min<uint64_t>(end - begin, (uint64_t)kFuseTile);
   const uint32_t n_hp = ghist ? n_pass - hp_begin : 0u;
@@ -1201,7 +1210,8 @@ k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __rest
         K key = akey[j];
         W wv = wp[u];
         uint32_t neg = aneg[j];
-        expand_ops<K, WP>(key, wv, g - loff[j], pa, pa.E1, pa.E2, err);
+        if (e1lds) expand_ops<K, WP>(key, wv, g - loff[j], pa, (const Exp1Desc*)e1sh, pa.E2, err);
+        else expand_ops<K, WP>(key, wv, g - loff[j], pa, pa.E1, pa.E2, err);
         if (pa.useB) key = apply_table(key, tk, tn, neg);
         else for (uint32_t q = 0; q < pa.nB; ++q) key = apply_perm(key, pa.B[q], neg);
         if (neg) wv = -wv;
