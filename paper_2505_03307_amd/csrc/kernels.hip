@@ -377,12 +377,14 @@ __device__ __forceinline__ void expand_ops(K& key, typename WTraits<WP>::W& wv, 
 // expanding operators' column counts (0 for a dropped entry; errors as in the count).
 template <typename K>
 __device__ __forceinline__ uint64_t a_chain_and_fanout(K& key, uint32_t& neg, const PassArgs& pa, const K* tk,
-                                                        const uint8_t* tn, uint32_t* err) {
+                                                        const uint8_t* tn, uint32_t* err,
+                                                        const Exp1Desc* E1s = nullptr) {
   if (pa.drop) return 0;
   if (pa.useA) key = apply_table(key, tk, tn, neg);
   else for (uint32_t a = 0; a < pa.nA; ++a) key = apply_perm(key, pa.A[a], neg);
+  if (!E1s) E1s = pa.E1;
   uint64_t f = 1;
-  for (uint32_t e = 0; e < pa.nE1 && f <= 0xFFFFFFFFull; ++e) f *= pa.E1[e].cnt[get_d(key, pa.E1[e].pos)];
+  for (uint32_t e = 0; e < pa.nE1 && f <= 0xFFFFFFFFull; ++e) f *= E1s[e].cnt[get_d(key, E1s[e].pos)];
   for (uint32_t e = 0; e < pa.nE2 && f <= 0xFFFFFFFFull; ++e) f *= pa.E2[e].cnt[local2(key, pa.E2[e].pa, pa.E2[e].pb)];
   if (f > 0xFFFFFFFFull) {
     atomicOr(err, kErrFanout);
@@ -715,6 +717,7 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   __shared__ uint64_t stage[kSortTile];               // key words, then weights (as raw 64-bit)
   __shared__ uint8_t sdig[kDigLds ? kSortTile : 1];   // digit of each sorted slot (two-word keys)
   __shared__ uint32_t wrun[kWaves][kRadix];            // per-wave running digit counts, then slot bases
+  __shared__ uint32_t wdummy[kWaves][64];              // target of the lanes that lead no digit
   __shared__ uint64_t gdst[kRadix];                    // destination of tile slot j of digit d: gdst[d] + j
   __shared__ uint64_t scan_sh[kSortBlock / 64];
   __shared__ uint32_t tile_sh;
@@ -780,23 +783,30 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
     const uint32_t li = wid * kWaveSpan + r * 64 + lane;
     key[r] = kb[min(li, ld_last)];
   }
+  // Ranking: the lanes of a round that share this lane's digit are those where no bit of the
+  // digit differs (a ballot per bit, folded with the bit spread over the word); the lowest of
+  // them adds their number to the wave's digit counter (the others add nothing to a dummy
+  // word, so no branch) and passes the counter's old value on.
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t li = wid * kWaveSpan + r * 64 + lane;  // tile-local index, stable order
     const bool valid = li < n_tile;
     const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
-    uint64_t m = __ballot(valid);
+    const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
+    uint32_t dlo = ~(uint32_t)vm, dhi = ~(uint32_t)(vm >> 32);
 #pragma unroll
     for (int bit = 0; bit < kRadixBits; ++bit) {
-      const bool on = (d >> bit) & 1u;
-      const uint64_t bb = __ballot(on);
-      m &= on ? bb : ~bb;
+      const int spread = __builtin_amdgcn_sbfe((int)d, bit, 1);
+      const uint64_t bb = __builtin_amdgcn_ballot_w64(spread != 0);
+      dlo |= (uint32_t)bb ^ (uint32_t)spread;
+      dhi |= (uint32_t)(bb >> 32) ^ (uint32_t)spread;
     }
-    uint32_t bs = 0;
-    const int leader = __ffsll((long long)m) - 1;  // lowest lane with this digit
-    if (valid && lane == leader) bs = atomicAdd(&wrun[wid][d], (uint32_t)__popcll(m));
-    bs = __shfl(bs, leader < 0 ? 0 : leader, 64);
-    if (valid) rk[li] = (uint16_t)(bs + (uint32_t)__popcll(m & lt));
+    const uint64_t mk = ~(((uint64_t)dhi << 32) | dlo);
+    const int leader = __ffsll((long long)mk) - 1;  // lowest lane with this digit
+    const bool lead_me = valid && lane == leader;
+    const uint32_t bs = atomicAdd(lead_me ? &wrun[wid][d] : &wdummy[wid][lane], lead_me ? (uint32_t)__popcll(mk) : 0u);
+    const uint32_t v = __shfl(bs, leader < 0 ? 0 : leader, 64) + (uint32_t)__popcll(mk & lt);
+    if (valid) rk[li] = (uint16_t)v;
   }
   __syncthreads();
   // per-digit totals of the tile and wave prefixes
@@ -1103,17 +1113,16 @@ k_count_expand(const K* __restrict__ keys, const typename WTraits<WP>::W* __rest
     const uint32_t li = r * kFuseBlock + threadIdx.x;
     kr[r] = keys[n ? begin + min(li, n - 1) : 0];
   }
-  if (pa.useA && !pa.drop) {
-    stage_table(pa.tA, tk, tn);
-    __syncthreads();
-  }
+  if (pa.useA && !pa.drop) stage_table(pa.tA, tk, tn);
+  __syncthreads();  // A table and descriptors staged
 #pragma unroll
   for (int r = 0; r < kFuseItems; ++r) {
     const uint32_t li = r * kFuseBlock + threadIdx.x;
     if (li >= n) break;
     K key = kr[r];
     uint32_t neg = 0;
-    uint64_t f = a_chain_and_fanout(key, neg, pa, tk, tn, err);
+    uint64_t f = e1lds ? a_chain_and_fanout(key, neg, pa, tk, tn, err, (const Exp1Desc*)e1sh)
+                       : a_chain_and_fanout(key, neg, pa, tk, tn, err);
     if (f > (uint64_t)kFuseMaxFanout) {  // the caller's bound did not hold
       atomicOr(err, kErrIndex | kErrFanout);
       f = 0;
