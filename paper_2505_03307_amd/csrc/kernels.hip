@@ -648,12 +648,16 @@ template <typename K>
 __global__ void __launch_bounds__(kSortBlock) k_sort_hist(const K* __restrict__ keys, uint32_t shift,
                                                           Tiling tl, uint64_t* __restrict__ hist,
                                                           uint64_t hist_size, uint32_t* err) {
-  __shared__ uint32_t h[kSortBlock / 64][kRadix];
+  // One counter copy per quarter wave, rows one word longer than the radix: lanes of different
+  // quarters that count the same digit hit different LDS banks, so a skewed digit (many lanes
+  // on one counter) serializes at most the 16 lanes of a quarter.
+  constexpr int kCopies = 4 * (kSortBlock / 64), kRow = kRadix + 1;
+  __shared__ uint32_t h[kCopies * kRow];
   // consecutive tiles on one XCD: their counts of a digit are neighbouring words of hist
   const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
   if (tl.n_dev && b >= *tl.n_dev) return;  // launched for a bound on the tile count
-  const int wid = threadIdx.x >> 6;
-  for (int k = threadIdx.x; k < (kSortBlock / 64) * kRadix; k += kSortBlock) (&h[0][0])[k] = 0;
+  uint32_t* const hq = h + (threadIdx.x >> 4) * kRow;
+  for (int k = threadIdx.x; k < kCopies * kRow; k += kSortBlock) h[k] = 0;
   __syncthreads();
   const uint64_t begin = tl.blk_begin[b], end = tl.blk_end[b];
   const uint32_t n = (uint32_t)(end - begin);  // at most kSortTile
@@ -664,15 +668,13 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_hist(const K* __restrict__ 
     kr[r] = keys[n ? begin + min(li, n - 1) : 0];
   }
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
-    if (r * kSortBlock + threadIdx.x >= n) break;
-    atomicAdd(&h[wid][(uint32_t)(kr[r] >> shift) & (kRadix - 1)], 1u);
-  }
+  for (int r = 0; r < kSortItems; ++r)  // no early exit: the loads above stay in flight together
+    if (r * kSortBlock + threadIdx.x < n) atomicAdd(&hq[(uint32_t)(kr[r] >> shift) & (kRadix - 1)], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kSortBlock) {
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < kSortBlock / 64; ++w) c += h[w][d];
+    for (int q = 0; q < kCopies; ++q) c += h[q * kRow + d];
     const uint64_t pos = hist_pos(tl, b, d);
     if (pos < hist_size) hist[pos] = c; else atomicOr(err, kErrIndex | kErrSort);
   }
@@ -2303,9 +2305,9 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_upsweep(const K* __restrict
     kr[r] = keys[n ? begin + min(li, n - 1) : 0];
   }
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
-    if (r * kSortBlock + threadIdx.x >= n) break;
-    for (uint32_t p = p_begin; p < n_pass; ++p) atomicAdd(&h[wid][p][(uint32_t)(kr[r] >> (8 * p)) & 255u], 1u);
+  for (int r = 0; r < kSortItems; ++r) {  // no early exit: the loads above stay in flight together
+    if (r * kSortBlock + threadIdx.x < n)
+      for (uint32_t p = p_begin; p < n_pass; ++p) atomicAdd(&h[wid][p][(uint32_t)(kr[r] >> (8 * p)) & 255u], 1u);
   }
   __syncthreads();
   const uint32_t s = tl.blk_seg[b];
