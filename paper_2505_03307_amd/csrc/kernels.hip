@@ -2334,14 +2334,14 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
 // Sum of a run starting at tile-local index li: from the staged tile (key_at / sw) while the
 // run stays inside the tile, then from global memory up to the segment end: the elements are
 // added in array order whatever the tiling, so results do not depend on it.
-template <typename Acc, typename W, typename K, typename KeyAt>
-__device__ __forceinline__ W run_sum_tile(const KeyAt& key_at, const W* sw, uint32_t li, uint32_t n_tile,
+template <typename Acc, typename W, typename K, typename KeyAt, typename WAt>
+__device__ __forceinline__ W run_sum_tile(const KeyAt& key_at, const WAt& w_at, uint32_t li, uint32_t n_tile,
                                           const K* __restrict__ keys, const W* __restrict__ w, uint64_t begin,
                                           uint64_t seg_end, K key) {
   Acc a;
-  a.add(sw[li]);
+  a.add(w_at(li));
   uint32_t j = li + 1;
-  for (; j < n_tile && key_at(1 + j) == key; ++j) a.add(sw[j]);
+  for (; j < n_tile && key_at(1 + j) == key; ++j) a.add(w_at(j));
   if (j == n_tile)
     for (uint64_t g = begin + j; g < seg_end && keys[g] == key; ++g) a.add(w[g]);
   return a.value();
@@ -2354,8 +2354,12 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
         uint64_t* __restrict__ blk_off, K* __restrict__ keys_out, W* __restrict__ w_out, uint64_t out_cap,
         uint64_t* __restrict__ status, uint32_t* __restrict__ tile_ctr, uint64_t epoch, uint32_t* err) {
   constexpr bool kLds = sizeof(K) <= 8;  // 16-byte keys are read from global memory
-  __shared__ K sk[kLds ? kSortTile + 1 : 1];
-  __shared__ W sw[kSortTile];
+  // A thread takes kSortItems consecutive elements, so a wave reads LDS with a stride of
+  // kSortItems elements: one pad element after every 16 spreads those reads over the banks.
+  auto pad = [](uint32_t i) -> uint32_t { return i + (i >> 4); };
+  constexpr int kPadded = kSortTile + kSortTile / 16 + 1;
+  __shared__ K sk[kLds ? kPadded : 1];
+  __shared__ W sw[kPadded];
   __shared__ uint64_t scan_sh[kSortBlock / 64];
   __shared__ uint64_t base_sh;
   uint32_t b = blockIdx.x;
@@ -2399,8 +2403,8 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
     for (int r = 0; r < kSortItems; ++r) {
       const uint32_t li = r * kSortBlock + threadIdx.x;
       if (li < n_tile) {
-        if constexpr (kLds) sk[1 + li] = kr[r];
-        sw[li] = wr[r];
+        if constexpr (kLds) sk[pad(1 + li)] = kr[r];
+        sw[pad(li)] = wr[r];
       }
     }
     if constexpr (kLds) {
@@ -2409,9 +2413,10 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
     __syncthreads();
   }
   auto key_at = [&](uint32_t i1) -> K {  // i1 = tile-local index + 1
-    if constexpr (kLds) return sk[i1];
+    if constexpr (kLds) return sk[pad(i1)];
     else return keys[begin + i1 - 1];
   };
+  auto w_at = [&](uint32_t i) -> W { return sw[pad(i)]; };
   const uint32_t i0 = threadIdx.x * kSortItems;
   uint32_t keep = 0;
   uint32_t keep_mask = 0;
@@ -2427,10 +2432,10 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
     if (!head) continue;
     W v;
     if constexpr (sizeof(W) == 8) {
-      v = run_sum_tile<PlainSum<W>>(key_at, sw, li, n_tile, keys, w, begin, seg_end, key);
+      v = run_sum_tile<PlainSum<W>>(key_at, w_at, li, n_tile, keys, w, begin, seg_end, key);
     } else {
-      if (fp64_acc) v = run_sum_tile<F64Sum>(key_at, sw, li, n_tile, keys, w, begin, seg_end, key);
-      else v = run_sum_tile<RunSum<float>>(key_at, sw, li, n_tile, keys, w, begin, seg_end, key);
+      if (fp64_acc) v = run_sum_tile<F64Sum>(key_at, w_at, li, n_tile, keys, w, begin, seg_end, key);
+      else v = run_sum_tile<RunSum<float>>(key_at, w_at, li, n_tile, keys, w, begin, seg_end, key);
     }
     if (fabs((double)v) > thr) {
       sums[k] = v;
