@@ -172,8 +172,9 @@ def bench_serve(log, count: int = 200, budget_gb: float = 200.0, one_batch: bool
     out = {"requests": count, "arrival_rate_per_s": round(lam, 2), "sequential_capacity_per_s": round(cap, 2),
            "budget_GB": budget_gb, "served": serve.summarize(srv_res, t_srv),
            "sequential": serve.summarize(seq, t_seq),
-           "server": "continuous batching, two lanes split at 256 MB predicted footprint, one HIP stream each, "
-                     "one large request in flight"}
+           "server": "two lanes split at 256 MB predicted footprint, one HIP stream and host thread each: "
+                     "small requests continuously batched, large ones one at a time through the "
+                     "single-circuit API"}
     if one_batch:
         t0 = time.perf_counter()
         one, srv = serve.serve_trace(circuits, arrivals, int(budget_gb * 1e9), precision=32)

@@ -3095,6 +3095,37 @@ hipError_t launch_build_tables(int KC, const TableJob* jobs, uint32_t n_jobs, hi
   return hipGetLastError();
 }
 
+// Terms as the C-ABI hands them out: each key as n_words little-endian 64-bit words (the
+// second word of a key of at most 8 bytes is 0), each weight as FP64.
+template <typename K, typename W>
+__global__ void __launch_bounds__(256) k_export(const K* __restrict__ keys, const W* __restrict__ w, uint64_t T,
+                                                uint32_t n_words, uint64_t* __restrict__ words,
+                                                double* __restrict__ wd) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= T) return;
+  const K k = keys[i];
+  if (n_words == 2) {
+    words[2 * i] = (uint64_t)k;
+    if constexpr (sizeof(K) > 8) words[2 * i + 1] = (uint64_t)(k >> 64);
+    else words[2 * i + 1] = 0;
+  } else {
+    words[i] = (uint64_t)k;
+  }
+  wd[i] = (double)w[i];
+}
+
+hipError_t launch_export(int KC, int WP, const void* keys, const void* w, uint64_t T, uint32_t n_words,
+                         uint64_t* words, double* wd, hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  const uint64_t nb = (T + 255) / 256;
+  if (nb > 0x7FFFFFFFull || (n_words != 1 && n_words != 2)) return hipErrorInvalidValue;
+  QIMAX_DISPATCH_K(KC, {
+    if (WP == 64) k_export<K, double><<<(uint32_t)nb, 256, 0, s>>>((const K*)keys, (const double*)w, T, n_words, words, wd);
+    else k_export<K, float><<<(uint32_t)nb, 256, 0, s>>>((const K*)keys, (const float*)w, T, n_words, words, wd);
+  });
+  return hipGetLastError();
+}
+
 hipError_t launch_init_many(int KC, int WP, void* keys, void* w, const uint32_t* nq, const uint64_t* dst,
                             uint32_t n_circ, hipStream_t s) {
   if (n_circ == 0) return hipSuccess;

@@ -2022,6 +2022,37 @@ qimax_status fetch(qimax_ctx* c, HostGens& g) {
   return QIMAX_OK;
 }
 
+// Terms [a, a + T) of the committed term arrays to host memory as the C-ABI returns them
+// (n_words uint64 words per key, FP64 weights): converted on the device and copied in chunks
+// through the image buffers, which are idle between calls and between rounds. *done stays
+// false (nothing written) where those buffers cannot hold a chunk of 64 Ki terms or a graph
+// is being recorded; the caller then converts on the host.
+qimax_status export_terms(qimax_ctx* c, uint64_t a, uint64_t T, uint32_t n_words, uint64_t* words, double* w,
+                          bool* done) {
+  *done = false;
+  if (c->rec) return QIMAX_OK;
+  if (T == 0) {
+    *done = true;
+    return QIMAX_OK;
+  }
+  if (!c->ik[0].p || !c->iw[0].p) return QIMAX_OK;
+  const uint64_t cap = std::min<uint64_t>(c->ik[0].bytes / (8ull * n_words), c->iw[0].bytes / 8);
+  if (cap < (1ull << 16)) return QIMAX_OK;
+  const uint8_t* kb = (const uint8_t*)c->keys.p + a * c->kb;
+  const uint8_t* wb = (const uint8_t*)c->w.p + a * c->wb;
+  for (uint64_t i = 0; i < T; i += cap) {
+    const uint64_t m = std::min(cap, T - i);
+    HIPCHK(c, launch_export(c->KC, c->WP, kb + i * c->kb, wb + i * c->wb, m, n_words, (uint64_t*)c->ik[0].p,
+                            (double*)c->iw[0].p, c->stream), "export");
+    HIPCHK(c, hipMemcpyAsync(words + i * n_words, c->ik[0].p, m * n_words * 8, hipMemcpyDeviceToHost, c->stream),
+           "export D2H");
+    HIPCHK(c, hipMemcpyAsync(w + i, c->iw[0].p, m * 8, hipMemcpyDeviceToHost, c->stream), "export D2H");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  }
+  *done = true;
+  return QIMAX_OK;
+}
+
 int digit_of(u128 key, uint32_t n, uint32_t q) { return (int)((key >> (2 * (n - 1 - q))) & 3u); }
 
 
@@ -2586,6 +2617,12 @@ qimax_status qimax_get_generators(qimax_ctx* c, uint64_t* gen_off, uint64_t* key
     return QIMAX_OK;
   }
   if (!gen_off || (c->T && (!keys || !w))) return fail(c, QIMAX_EINVAL, "output buffers are NULL");
+  bool done = false;
+  QCHK(export_terms(c, 0, c->T, c->n <= 32 ? 1u : 2u, keys, w, &done));
+  if (done) {
+    std::copy(c->h_seg.begin(), c->h_seg.end(), gen_off);
+    return QIMAX_OK;
+  }
   HostGens g;
   QCHK(fetch(c, g));
   std::copy(g.off.begin(), g.off.end(), gen_off);
@@ -3052,9 +3089,13 @@ qimax_status take_result(qimax_batch* b, BatchCirc& bc, size_t s0) {
   bc.res_off.resize(bc.n + 1);
   for (uint32_t j = 0; j <= bc.n; ++j) bc.res_off[j] = b->so[s0 + j] - a;
   bc.res_w.resize(e - a);
+  const uint32_t n_words = bc.n <= 32 ? 1u : 2u;
+  bc.res_key.resize((e - a) * n_words);
+  bool done = false;
+  QCHK(export_terms(c, a, e - a, n_words, bc.res_key.data(), bc.res_w.data(), &done));
+  if (done) return QIMAX_OK;
   std::vector<u128> k;
   HIPCHK(c, keys_to_host(c, (const uint8_t*)c->keys.p + a * c->kb, e - a, k), "result");
-  bc.res_key.resize((e - a) * (bc.n <= 32 ? 1 : 2));
   keys_to_words(k, bc.n, bc.res_key.data());
   if (e == a) return QIMAX_OK;
   if (c->WP == 64) {

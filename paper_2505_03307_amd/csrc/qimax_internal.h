@@ -169,6 +169,10 @@ void prof_destroy(Prof* p);
 hipError_t launch_init(int KC, int WP, void* keys, void* w, uint64_t* seg_off, uint32_t n,
                        hipStream_t s, Prof* prof = nullptr);
 
+// T terms converted for the host: keys to n_words (1 or 2) uint64 words each, weights to FP64.
+hipError_t launch_export(int KC, int WP, const void* keys, const void* w, uint64_t T, uint32_t n_words,
+                         uint64_t* words, double* wd, hipStream_t s);
+
 // Fan-out count fused with its scan (single sweep with decoupled look-back over the tiles of
 // tl, claimed through *ctr): off[i] = first image of input term i, off[T] = image count;
 // akeys[i] / asign[i] = the term's image under its pass's A chain and that image's sign (the

@@ -223,18 +223,51 @@ class _Budget:
             self.used -= need
 
 
+class SimRunner:
+    """Runs one circuit at a time through the single-circuit API, one warm context per
+    (n, eps) kept for later requests: the large lane's executor."""
+
+    def __init__(self, precision: int = 32):
+        self.precision = precision
+        self.sims = {}
+
+    def run(self, c: W.Circuit):
+        """(generators, term updates) of circuit c."""
+        key = (c.n, float(c.eps))
+        if key not in self.sims:
+            self.sims[key] = Simulator(c.n, precision=self.precision, prune_eps=c.eps)
+        s = self.sims[key]
+        s.reset()
+        u0 = s.stats()["term_updates"]
+        s.run(c)
+        res = s.generators()
+        return res, s.stats()["term_updates"] - u0
+
+    def close(self):
+        for s in self.sims.values():
+            s.close()
+        self.sims = {}
+
+
 def serve_trace_lanes(circuits, arrivals, budget_bytes: int, precision: int = 32, split_bytes: int = 256 << 20,
-                      large_in_flight: int = 1, keep_results: bool = False, batch_factory=None, progress=None):
-    """Continuous batching with two lanes: requests predicted to need less than split_bytes
-    go to one batch, the others to a second; each batch runs on its own HIP stream, driven by
-    its own host thread, so small requests do not wait behind the rounds of large ones. The
-    large lane keeps at most large_in_flight requests in flight (large requests already fill
-    the device, so sharing rounds among them only delays each one). Admission in arrival
-    order per lane, against one shared memory budget (a lane with nothing in flight may always
-    admit its next request). progress(n), if given, is called with the number of
-    requests the trace has handed to the lanes (every 100). Returns (results, outputs)."""
+                      large_in_flight: int = 1, keep_results: bool = False, batch_factory=None, progress=None,
+                      large_runner=None):
+    """Two lanes, each driven by its own host thread on its own HIP stream: requests predicted
+    to need less than split_bytes are continuously batched in one lane, so small requests do
+    not wait behind the rounds of large ones. The large lane runs its requests one at a time
+    through large_runner (an object with run(circuit) -> (generators, updates) and close();
+    by default a SimRunner: large requests already fill the device, and the single-circuit API
+    plans all of a circuit's rounds in one call) or, when large_runner is None and a
+    batch_factory is given, as a second batch with at most large_in_flight requests in
+    flight. Admission in arrival order per lane, against one shared memory budget (a lane
+    with nothing in flight may always admit its next request). progress(n), if given, is
+    called with the number of requests the trace has handed to the lanes (every 100).
+    Returns (results, outputs)."""
     import collections
     import threading
+
+    if large_runner is None and batch_factory is None:
+        large_runner = SimRunner(precision)
 
     order = np.argsort(arrivals, kind="stable")
     max_n = key_class(max(c.n for c in circuits))
@@ -243,9 +276,10 @@ def serve_trace_lanes(circuits, arrivals, budget_bytes: int, precision: int = 32
     clock = lambda: time.perf_counter() - t0  # noqa: E731
 
     class Lane:
-        def __init__(self, cap):
+        def __init__(self, cap, runner=None):
             self.cap = cap
-            self.batch = batch_factory() if batch_factory else Batch(precision=precision, max_n=max_n)
+            self.runner = runner
+            self.batch = None if runner else (batch_factory() if batch_factory else Batch(precision=precision, max_n=max_n))
             self.queue = collections.deque()
             self.cv = threading.Condition()
             self.closed = False
@@ -254,10 +288,30 @@ def serve_trace_lanes(circuits, arrivals, budget_bytes: int, precision: int = 32
             self.outputs = {}
             self.error = None
 
-    lanes = [Lane(None), Lane(large_in_flight)]
+    lanes = [Lane(None), Lane(large_in_flight, large_runner)]
+
+    def run_single(lane):
+        # one request at a time: wait for the next, reserve its footprint, run it to the end
+        while True:
+            with lane.cv:
+                while not lane.queue and not lane.closed:
+                    lane.cv.wait(timeout=0.01)
+                if not lane.queue:
+                    return
+                rid, need = lane.queue.popleft()
+            budget.try_reserve(need, force=True)
+            adm = clock()
+            res, upd = lane.runner.run(circuits[rid])
+            budget.release(need)
+            if keep_results:
+                lane.outputs[rid] = res
+            lane.results.append(Result(rid, float(arrivals[rid]), adm, clock(), int(res[0][-1]), upd))
 
     def work(lane):
         try:
+            if lane.runner is not None:
+                run_single(lane)
+                return
             while True:
                 with lane.cv:
                     while not lane.queue and not lane.in_flight and not lane.closed:
@@ -318,5 +372,8 @@ def serve_trace_lanes(circuits, arrivals, budget_bytes: int, precision: int = 32
             raise ln.error
         results += ln.results
         outputs.update(ln.outputs)
-        ln.batch.close()
+        if ln.runner is not None:
+            ln.runner.close()
+        else:
+            ln.batch.close()
     return results, outputs

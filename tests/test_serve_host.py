@@ -109,3 +109,43 @@ def test_two_lane_server_with_fake_executors():
         want = oracle_arrays(oracle.propagate(circuits[r.rid]), circuits[r.rid].n)
         for a, b in zip(outputs[r.rid], want):
             assert np.array_equal(a, b)
+
+
+class FakeRunner:
+    """Stands in for the large lane's single-circuit executor: results from the oracle."""
+
+    def __init__(self):
+        self.ran = []
+        self.closed = False
+
+    def run(self, c):
+        self.ran.append(c.name)
+        return oracle_arrays(oracle.propagate(c), c.n), 1
+
+    def close(self):
+        self.closed = True
+
+
+def test_two_lane_server_with_a_single_circuit_large_lane():
+    circuits, gaps = W.c5_stream(seed=6, count=16, n_range=(4, 7))
+    arrivals = np.cumsum(gaps) * 1e-4
+    cls = serve.key_class(max(c.n for c in circuits))
+    need = sorted(serve.predict_bytes(c, 32, cls) for c in circuits)
+    split = need[len(need) // 2]  # about half of the requests in each lane
+    runner = FakeRunner()
+    results, outputs = serve.serve_trace_lanes(circuits, arrivals, budget_bytes=10 ** 12, split_bytes=split,
+                                               keep_results=True, batch_factory=FakeBatch, large_runner=runner)
+    assert sorted(r.rid for r in results) == list(range(16))
+    large = [i for i, c in enumerate(circuits) if serve.predict_bytes(c, 32, cls) >= split]
+    assert large and len(large) < 16  # both lanes take part
+    assert sorted(runner.ran) == sorted(circuits[i].name for i in large) and runner.closed
+    for r in results:
+        assert r.finished >= r.admitted >= r.arrival - 1e-9
+        want = oracle_arrays(oracle.propagate(circuits[r.rid]), circuits[r.rid].n)
+        for a, b in zip(outputs[r.rid], want):
+            assert np.array_equal(a, b)
+    # the large lane ran its requests one at a time, in arrival order
+    big = sorted((r for r in results if r.rid in large), key=lambda r: r.admitted)
+    assert [r.rid for r in big] == sorted(large, key=lambda i: (arrivals[i], i))
+    assert all(a.finished <= b.admitted for a, b in zip(big, big[1:]))
+
