@@ -774,8 +774,8 @@ k_sort_scatter(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __r
   // that it holds no registers across the look-back and the scan
   uint16_t* const rk = reinterpret_cast<uint16_t*>(stage);
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  // the tile's elements from a block-uniform base with 32-bit indexes (no 64-bit address
-  // per load); slots past the tile re-read its last element
+  // the tile's elements from a block-uniform base with 32-bit index arithmetic; slots past the
+  // tile re-read its last element
   const uint64_t ld_base = n_tile ? begin : 0;
   const uint32_t ld_last = n_tile ? n_tile - 1 : 0;
   const K* __restrict__ kb = keys_in + ld_base;
