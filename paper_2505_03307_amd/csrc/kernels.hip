@@ -1318,7 +1318,7 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
              uint64_t out_cap, Tiling tc, uint32_t n_pass, uint32_t m, const PassArgs* __restrict__ pas,
              const uint32_t* __restrict__ seg_entry, int fp64_acc, ChunkOut co, uint32_t* err) {
   constexpr int kItems = kChunkCap / kChunkBlock, kWaves = kChunkBlock / 64;
-  __shared__ K sk[kChunkCap];
+  __shared__ __align__(16) K sk[kChunkCap];  // (also the staging area of the output weights)
   __shared__ uint16_t sidx[kChunkCap];
   __shared__ uint16_t sbk[kChunkCap];
   __shared__ __align__(16) uint32_t wrun[2][kWaves][kRadix];
@@ -1745,21 +1745,42 @@ k_chunk_sort(const K* __restrict__ keys_in, const W* __restrict__ w_in, K* __res
   // own range of the scratch arrays
   K* kd = keys_out;
   W* wd = w_out;
-  uint64_t o = base + pre;
+  uint64_t ob = base;  // output position of the chunk's first kept run
   if (base == kDeferred) {
     kd = (K*)co.tmp_keys;
     wd = (W*)co.tmp_w;
-    o = c0 + pre;
+    ob = c0;
   } else if (base + tot > out_cap) {
     if (threadIdx.x == 0 && tot) atomicOr(err, kErrIndex | kErrMerge);
     return;
   }
+  // The kept runs leave through LDS, which the sort no longer needs (the look-back's barrier
+  // follows every read of it): staged at their rank in the chunk, then stored by consecutive
+  // threads, so that a wave's stores fill whole lines instead of touching one element every
+  // kItems slots per lane. Keys first, then the weights in passes of what the key area holds.
+  const uint32_t nt = (uint32_t)tot;
+  {
+    uint32_t q = (uint32_t)pre;
 #pragma unroll
-  for (int t = 0; t < kItems; ++t) {
-    if (!(keep_mask & (1u << t))) continue;
-    kd[o] = kt[t];
-    wd[o] = sums[t];
-    ++o;
+    for (int t = 0; t < kItems; ++t)
+      if (keep_mask & (1u << t)) sk[q++] = kt[t];
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < nt; j += kChunkBlock) kd[ob + j] = sk[j];
+  constexpr uint32_t kWCap = (uint32_t)(sizeof(K) * kChunkCap / sizeof(W));
+  W* const sws = reinterpret_cast<W*>(sk);
+  for (uint32_t p0 = 0; p0 < nt; p0 += kWCap) {
+    __syncthreads();  // every read of the staging area before it is rewritten
+    uint32_t q = (uint32_t)pre;
+#pragma unroll
+    for (int t = 0; t < kItems; ++t)
+      if (keep_mask & (1u << t)) {
+        if (q >= p0 && q - p0 < kWCap) sws[q - p0] = sums[t];
+        ++q;
+      }
+    __syncthreads();
+    const uint32_t pn = min(nt - p0, kWCap);
+    for (uint32_t j = threadIdx.x; j < pn; j += kChunkBlock) wd[ob + p0 + j] = sws[j];
   }
 }
 
