@@ -2496,17 +2496,47 @@ k_merge(const K* __restrict__ keys, const W* __restrict__ w, Tiling tl, const Pa
       }
       __syncthreads();
     }
-    uint64_t o = (kMode == 2 ? base_sh : blk_off[b]) + pre;
+    const uint64_t ob = kMode == 2 ? base_sh : blk_off[b];  // output position of the tile's first kept run
+    if constexpr (kLds) {
+      // The kept runs leave through the tile's LDS arrays (every read of them came before the
+      // scan's barriers): staged at their rank in the tile, then stored by consecutive threads,
+      // so that a wave's stores fill whole lines instead of touching one element every
+      // kSortItems slots per lane.
+      K kk[kSortItems];
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-      if (!(keep_mask & (1u << k))) continue;
-      if (o < out_cap) {
-        keys_out[o] = key_at(1 + i0 + k);
-        w_out[o] = sums[k];
-      } else {
-        atomicOr(err, kErrIndex | kErrMerge);
+      for (int k = 0; k < kSortItems; ++k) kk[k] = key_at(1 + i0 + k);
+      __syncthreads();
+      uint32_t q = (uint32_t)pre;
+#pragma unroll
+      for (int k = 0; k < kSortItems; ++k)
+        if (keep_mask & (1u << k)) {
+          sk[pad(q)] = kk[k];
+          sw[pad(q)] = sums[k];
+          ++q;
+        }
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < (uint32_t)tot; j += kSortBlock) {
+        const uint64_t o = ob + j;
+        if (o < out_cap) {
+          keys_out[o] = sk[pad(j)];
+          w_out[o] = sw[pad(j)];
+        } else {
+          atomicOr(err, kErrIndex | kErrMerge);
+        }
       }
-      ++o;
+    } else {
+      uint64_t o = ob + pre;
+#pragma unroll
+      for (int k = 0; k < kSortItems; ++k) {
+        if (!(keep_mask & (1u << k))) continue;
+        if (o < out_cap) {
+          keys_out[o] = key_at(1 + i0 + k);
+          w_out[o] = sums[k];
+        } else {
+          atomicOr(err, kErrIndex | kErrMerge);
+        }
+        ++o;
+      }
     }
   }
 }
