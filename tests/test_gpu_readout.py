@@ -36,6 +36,34 @@ def test_generators_xz_matches_index_words():
         assert np.array_equal(w, w2)
 
 
+@pytest.mark.parametrize("which", ["hea12_fp32", "random24", "random40"])
+def test_exported_generators_at_size(which):
+    """Results large enough to leave through the device-side export (64 Ki terms or more;
+    the ansatz in more than one chunk through the image buffers), with 32-, 64- and 128-bit
+    keys: the index words and FP64 weights agree with the separate x/z readout, and the
+    ansatz count with its closed form."""
+    c, prec = {"hea12_fp32": lambda: (W.c3_hea(seed=3, n=12, layers=2, eps=0.0), 32),
+               "random24": lambda: (W.c2_clifford_rz(seed=4, n=24, depth=60, n_rz=24), 64),
+               "random40": lambda: (W.c2_clifford_rz(seed=3, n=40, depth=60, n_rz=30), 64)}[which]()
+    say("export", c.name)
+    with Simulator(c.n, precision=prec) as s:
+        s.run(c)
+        off, keys, w = s.generators()
+        off2, x, z, w2 = s.generators_xz()
+    assert keys.shape[0] >= 1 << 16
+    if which == "hea12_fp32":
+        assert keys.shape[0] == 3 ** 13 + 9 * 12 - 21
+    assert np.array_equal(off, off2)
+    assert np.array_equal(xz_to_index(x, z, c.n), keys)
+    assert np.array_equal(w, w2)
+    for j in range(c.n):  # ascending keys within every generator
+        kj = keys[int(off[j]):int(off[j + 1])]
+        if c.n > 32:
+            assert np.all((kj[1:, 1] > kj[:-1, 1]) | ((kj[1:, 1] == kj[:-1, 1]) & (kj[1:, 0] > kj[:-1, 0])))
+        else:
+            assert np.all(kj[1:, 0] > kj[:-1, 0])
+
+
 def _want(psi, n, p):
     return float(np.real(np.vdot(psi, D.apply_pauli_state(psi.copy(), n, [LETTER.index(ch) for ch in p]))))
 
